@@ -1,0 +1,129 @@
+"""Batch driver of the FP64 oracle.  TEST INFRASTRUCTURE ONLY.
+
+Subdomains and specification rows are independent (Sec. 3.4 batches them only
+for throughput), so the batch result is the concatenation of per-subdomain
+results of `beta_crown`.  This module also converts between the library's
+documented variable layouts and the oracle's per-layer dense arrays:
+
+  * alpha: per subdomain b, an [m, U_p] block where U_p counts the root-unstable
+    neurons (l < 0 < u) of b's property p in layer-major, index order; blocks are
+    concatenated in subdomain order;
+  * beta: [nnz, m] in CSR split order;
+  * bounds: [B, m].
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import beta_crown as bc
+
+
+def root_bounds_all(net64, x_lo, x_hi):
+    """Per-property root bounds, float64 [P, sum d_i] each (layer-major)."""
+    los, ups = [], []
+    for p in range(x_lo.shape[0]):
+        lo, up = bc.root_bounds(net64, np.asarray(x_lo[p], np.float64), np.asarray(x_hi[p], np.float64))
+        los.append(np.concatenate(lo))
+        ups.append(np.concatenate(up))
+    return np.stack(los), np.stack(ups)
+
+
+class OracleProblem:
+    """The batched problem as the library sees it, evaluated in float64."""
+
+    def __init__(self, layers, x_lo, x_hi, C, lo, up, dom_prop, split_ptr, split_layer, split_neuron, split_side,
+                 net64=None):
+        self.net64 = net64 if net64 is not None else bc.dense_net(layers)
+        self.dims = [self.net64[0][0].shape[1]] + [W.shape[0] for W, _ in self.net64]
+        self.relu_dims = self.dims[1:-1]
+        self.offs = np.concatenate([[0], np.cumsum(self.relu_dims)]).astype(np.int64)
+        self.x_lo = np.asarray(x_lo, np.float64)
+        self.x_hi = np.asarray(x_hi, np.float64)
+        self.C = np.asarray(C, np.float64)
+        self.lo = np.asarray(lo, np.float64)
+        self.up = np.asarray(up, np.float64)
+        self.dom_prop = np.asarray(dom_prop)
+        self.ptr = np.asarray(split_ptr, np.int64)
+        self.s_layer = np.asarray(split_layer)
+        self.s_neuron = np.asarray(split_neuron)
+        self.s_side = np.asarray(split_side)
+        self.m = self.C.shape[1]
+        self.B = self.dom_prop.shape[0]
+        # compact alpha layout
+        self.unstable = [np.nonzero((self.lo[p] < 0) & (self.up[p] > 0))[0] for p in range(self.lo.shape[0])]
+        sizes = np.array([self.m * self.unstable[int(p)].shape[0] for p in self.dom_prop], np.int64)
+        self.alpha_off = np.concatenate([[0], np.cumsum(sizes)])
+
+    @property
+    def n_alpha(self):
+        return int(self.alpha_off[-1])
+
+    @property
+    def nnz(self):
+        return int(self.ptr[-1])
+
+    def _layers(self, vec):
+        return [vec[self.offs[i]:self.offs[i + 1]] for i in range(len(self.relu_dims))]
+
+    def domain(self, b):
+        p = int(self.dom_prop[b])
+        split = [np.zeros(d, np.int8) for d in self.relu_dims]
+        for t in range(self.ptr[b], self.ptr[b + 1]):
+            split[int(self.s_layer[t]) - 1][int(self.s_neuron[t])] = int(self.s_side[t])
+        return p, self._layers(self.lo[p]), self._layers(self.up[p]), split
+
+    # ---- layout conversion -------------------------------------------------
+    def alpha_to_layers(self, b, alpha_flat):
+        p = int(self.dom_prop[b])
+        u = self.unstable[p]
+        blk = np.asarray(alpha_flat[self.alpha_off[b]:self.alpha_off[b + 1]], np.float64).reshape(self.m, u.shape[0])
+        dense = np.zeros((self.m, self.offs[-1]))
+        dense[:, u] = blk
+        return [dense[:, self.offs[i]:self.offs[i + 1]] for i in range(len(self.relu_dims))]
+
+    def alpha_from_layers(self, b, alpha_layers):
+        p = int(self.dom_prop[b])
+        dense = np.concatenate(alpha_layers, axis=1)
+        return dense[:, self.unstable[p]].reshape(-1)
+
+    def beta_to_layers(self, b, beta_flat):
+        beta = [np.zeros((self.m, d)) for d in self.relu_dims]
+        bf = np.asarray(beta_flat, np.float64).reshape(-1, self.m)
+        for t in range(self.ptr[b], self.ptr[b + 1]):
+            beta[int(self.s_layer[t]) - 1][:, int(self.s_neuron[t])] = bf[t]
+        return beta
+
+    def beta_from_layers(self, b, beta_layers):
+        out = np.zeros((int(self.ptr[b + 1] - self.ptr[b]), self.m))
+        for k, t in enumerate(range(self.ptr[b], self.ptr[b + 1])):
+            out[k] = beta_layers[int(self.s_layer[t]) - 1][:, int(self.s_neuron[t])]
+        return out
+
+    # ---- evaluation --------------------------------------------------------
+    def default_alpha_flat(self):
+        out = np.zeros(self.n_alpha)
+        for b in range(self.B):
+            p = int(self.dom_prop[b])
+            u = self.unstable[p]
+            a = bc.default_alpha(self.lo[p][u], self.up[p][u])
+            out[self.alpha_off[b]:self.alpha_off[b + 1]] = np.tile(a, self.m)
+        return out
+
+    def eval(self, b, alpha_flat, beta_flat):
+        p, lo, up, split = self.domain(b)
+        return bc.bound(self.net64, self.x_lo[p], self.x_hi[p], self.C[p], lo, up, split,
+                        self.alpha_to_layers(b, alpha_flat), self.beta_to_layers(b, beta_flat))
+
+    def grad(self, b, alpha_flat, beta_flat):
+        """(g [m], dalpha in the compact block of b, dbeta [depth_b, m])."""
+        p, lo, up, split = self.domain(b)
+        g, ga, gb = bc.bound_and_grad(self.net64, self.x_lo[p], self.x_hi[p], self.C[p], lo, up, split,
+                                      self.alpha_to_layers(b, alpha_flat), self.beta_to_layers(b, beta_flat))
+        return g, self.alpha_from_layers(b, ga), self.beta_from_layers(b, gb)
+
+    def optimize(self, b, alpha_flat, beta_flat, cfg=None):
+        """(best g [m], final alpha block, final beta [depth_b, m], final g)."""
+        p, lo, up, split = self.domain(b)
+        best, a, bt, g = bc.optimize(self.net64, self.x_lo[p], self.x_hi[p], self.C[p], lo, up, split,
+                                     self.alpha_to_layers(b, alpha_flat), self.beta_to_layers(b, beta_flat), cfg)
+        return best, self.alpha_from_layers(b, a), self.beta_from_layers(b, bt), g

@@ -1,0 +1,323 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+No GPU.  Every test below would fail on a plausible slip in the oracle: a
+dropped constant term, a wrong sign of S, a swapped relaxation branch, a
+transposed weight or a wrong box minimiser.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import beta_crown as bc
+from tests import pinlib
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def tiny_case(seed, widths=(2, 6, 5, 2), eps=0.6, m=2):
+    rng = np.random.default_rng(seed)
+    net = pinlib.random_net(rng, list(widths))
+    x0 = rng.uniform(-0.5, 0.5, size=widths[0])
+    x_lo, x_hi = x0 - eps, x0 + eps
+    lo, up = bc.root_bounds(net, x_lo, x_hi)
+    C = rng.standard_normal((m, widths[-1]))
+    return rng, net, x0, eps, x_lo, x_hi, lo, up, C
+
+
+def unstable_list(lo, up):
+    return [(i, j) for i in range(len(lo)) for j in range(lo[i].shape[0]) if lo[i][j] < 0 < up[i][j]]
+
+
+def random_vars(rng, lo, m, split=None, beta_scale=1.0):
+    alpha = [rng.uniform(0, 1, size=(m, l.shape[0])) for l in lo]
+    beta = [rng.uniform(0, beta_scale, size=(m, l.shape[0])) * (0 if split is None else (split[i] != 0))
+            for i, l in enumerate(lo)]
+    return alpha, beta
+
+
+def random_split(rng, lo, up, k):
+    split = [np.zeros(l.shape[0], np.int8) for l in lo]
+    uns = unstable_list(lo, up)
+    if not uns:
+        return split
+    for t in rng.choice(len(uns), size=min(k, len(uns)), replace=False):
+        i, j = uns[t]
+        split[i][j] = rng.choice([-1, 1])
+    return split
+
+
+# ---------------------------------------------------------------------------
+# network plumbing
+
+
+@pytest.mark.parametrize("cfg", [((3, 8, 8), 5, 4, 2, 1), ((8, 16, 16), 7, 4, 2, 1), ((8, 16, 16), 8, 3, 1, 1),
+                                 ((3, 9, 9), 4, 4, 2, 0), ((2, 5, 7), 3, 3, 2, 1)])
+def test_conv_matrix_matches_library_conv(cfg):
+    torch = pytest.importorskip("torch")
+    (ci, h, w), co, k, s, p = cfg
+    rng = np.random.default_rng(0)
+    wt = rng.standard_normal((co, ci, k, k))
+    ho, wo = (h + 2 * p - k) // s + 1, (w + 2 * p - k) // s + 1
+    M = bc.conv_as_matrix(wt, (ci, h, w), (co, ho, wo), s, p)
+    x = rng.standard_normal((ci, h, w))
+    ref = torch.nn.functional.conv2d(torch.from_numpy(x)[None], torch.from_numpy(wt), stride=s, padding=p)[0]
+    assert np.allclose(M @ x.ravel(), ref.numpy().ravel(), atol=1e-12)
+
+
+def test_first_layer_bounds_are_exact_interval_bounds():
+    _, net, _, _, x_lo, x_hi, lo, up, _ = tiny_case(1, widths=(3, 7, 4, 2))
+    W, b = net[0]
+    ctr, rad = (x_lo + x_hi) / 2, (x_hi - x_lo) / 2
+    assert np.allclose(lo[0], W @ ctr - np.abs(W) @ rad + b, atol=1e-12)
+    assert np.allclose(up[0], W @ ctr + np.abs(W) @ rad + b, atol=1e-12)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_root_bounds_enclose_grid(seed):
+    _, net, _, _, x_lo, x_hi, lo, up, _ = tiny_case(seed, widths=(2, 7, 6, 5, 2))
+    zs, _ = pinlib.forward_all(net, pinlib.grid(x_lo, x_hi, 401))
+    for i, z in enumerate(zs):
+        assert np.all(z.min(0) >= lo[i] - 1e-9) and np.all(z.max(0) <= up[i] + 1e-9)
+    # the relaxations actually bite (otherwise the other pins are vacuous)
+    assert len(unstable_list(lo, up)) >= 3
+
+
+# ---------------------------------------------------------------------------
+# T1: soundness against brute force, any alpha in [0,1], beta >= 0
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_sound_against_grid(seed):
+    rng, net, _, _, x_lo, x_hi, lo, up, C = tiny_case(seed, widths=(2, 6, 6, 2), m=2)
+    for trial in range(4):
+        split = random_split(rng, lo, up, k=trial)
+        alpha, beta = random_vars(rng, lo, C.shape[0], split, beta_scale=2.0)
+        g = bc.bound(net, x_lo, x_hi, C, lo, up, split, alpha, beta)
+        gm = pinlib.grid_min(net, C, x_lo, x_hi, split, n=601)
+        assert np.all(g <= gm + 1e-9), (g, gm)
+
+
+def test_sound_against_dense_grid_2001():
+    rng, net, _, _, x_lo, x_hi, lo, up, C = tiny_case(7, widths=(2, 8, 6, 2), m=2)
+    split = random_split(rng, lo, up, k=2)
+    cfg = bc.AdamConfig(iters=60, lr_alpha=0.1, lr_beta=0.1)
+    best, *_ = bc.optimize(net, x_lo, x_hi, C, lo, up, split, [bc.default_alpha(l, u) * np.ones((2, 1)) for l, u in
+                                                                 zip(lo, up)], [np.zeros((2, l.shape[0])) for l in lo], cfg)
+    gm = pinlib.grid_min(net, C, x_lo, x_hi, split, n=2001)
+    assert np.all(best <= gm + 1e-9)
+
+
+# ---------------------------------------------------------------------------
+# T4 / Cor. 3.2.1: weak duality against the LP, and the LP duals attain it
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_weak_duality_and_dual_attainment(seed):
+    rng, net, _, _, x_lo, x_hi, lo, up, C = tiny_case(seed + 20, widths=(2, 6, 5, 2), m=1)
+    split = random_split(rng, lo, up, k=2)
+    p_lp, res, tags = pinlib.lp_verify_split(net, x_lo, x_hi, C[0], lo, up, split)
+    assert res.status == 0
+    for _ in range(5):
+        alpha, beta = random_vars(rng, lo, 1, split, beta_scale=3.0)
+        g = bc.bound(net, x_lo, x_hi, C, lo, up, split, alpha, beta)[0]
+        assert g <= p_lp + 1e-8
+    a_star, b_star = pinlib.duals_to_alpha_beta(res, tags, [l.shape[0] for l in lo])
+    g_star = bc.bound(net, x_lo, x_hi, C, lo, up, split, [a[None] for a in a_star], [b[None] for b in b_star])[0]
+    assert abs(g_star - p_lp) <= 1e-7 * max(1.0, abs(p_lp)), (g_star, p_lp)
+
+
+# ---------------------------------------------------------------------------
+# T6: exactness when every unstable neuron is split
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_exact_when_fully_split(seed):
+    rng, net, _, _, x_lo, x_hi, lo, up, C = tiny_case(seed + 40, widths=(2, 5, 4, 2), m=1)
+    uns = unstable_list(lo, up)
+    if len(uns) > 9:
+        pytest.skip("too many unstable neurons for the enumeration")
+    split = [np.zeros(l.shape[0], np.int8) for l in lo]
+    for (i, j) in uns:
+        split[i][j] = rng.choice([-1, 1])
+    exact = pinlib.vertex_min_2d(net, C, x_lo, x_hi, lo, up, split)[0]
+    p_lp, res, _ = pinlib.lp_verify_split(net, x_lo, x_hi, C[0], lo, up, split)
+    alpha0 = [np.zeros((1, l.shape[0])) for l in lo]
+    slots = [(i, j) for i in range(len(lo)) for j in np.nonzero(split[i])[0]]
+
+    def affine(bvec):
+        beta = [np.zeros((1, l.shape[0])) for l in lo]
+        for v, (i, j) in zip(bvec, slots):
+            beta[i][0, j] = v
+        g, A0, _ = bc.bound(net, x_lo, x_hi, C, lo, up, split, alpha0, beta, keep=True)
+        return A0[0], g[0] - np.minimum(A0[0] * x_lo, A0[0] * x_hi).sum()
+
+    g_max = pinlib.max_over_beta_lp(affine, len(slots), x_lo, x_hi)
+    if np.isinf(exact):
+        # T7: an infeasible split pattern has an unbounded dual
+        assert res.status == 2 and np.isinf(g_max)
+    else:
+        assert abs(exact - p_lp) <= 1e-7 * max(1, abs(exact))
+        assert abs(g_max - exact) <= 1e-7 * max(1, abs(exact)), (g_max, exact)
+        # and the concave beta problem is reachable by the projected ascent
+        cfg = bc.AdamConfig(iters=400, lr_alpha=0.0, lr_beta=0.05, decay=0.995)
+        best, *_ = bc.optimize(net, x_lo, x_hi, C, lo, up, split, alpha0, [np.zeros((1, l.shape[0])) for l in lo], cfg)
+        assert best[0] <= exact + 1e-9 and best[0] >= exact - 2e-2 * max(1, abs(exact))
+
+
+# ---------------------------------------------------------------------------
+# T2: three formulas for g agree
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_dual_nu_form_matches(seed):
+    rng, net, x0, eps, x_lo, x_hi, lo, up, C = tiny_case(seed + 60, widths=(3, 6, 5, 4, 2), m=2)
+    split = random_split(rng, lo, up, k=3)
+    alpha, beta = random_vars(rng, lo, 2, split, beta_scale=2.0)
+    g = bc.bound(net, x_lo, x_hi, C, lo, up, split, alpha, beta)
+    for r in range(2):
+        gd, _ = pinlib.dual_nu_bound(net, x0, eps, C[r], lo, up, split, [a[r] for a in alpha], [b[r] for b in beta])
+        assert abs(gd - g[r]) <= 1e-10 * max(1, abs(g[r]))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_explicit_theorem_form_matches(seed):
+    rng, net, x0, eps, x_lo, x_hi, lo, up, C = tiny_case(seed + 80, widths=(3, 6, 5, 4, 2), m=2)
+    split = random_split(rng, lo, up, k=3)
+    alpha, beta = random_vars(rng, lo, 2, split, beta_scale=2.0)
+    g = bc.bound(net, x_lo, x_hi, C, lo, up, split, alpha, beta)
+    for r in range(2):
+        _, nuhats = pinlib.dual_nu_bound(net, x0, eps, C[r], lo, up, split, [a[r] for a in alpha],
+                                         [b[r] for b in beta])
+        Ds, lbs = [], []
+        for i, nh in enumerate(nuhats):  # A(i) = -nu-hat(i); D, lowerb by Eq. definition_D/lowerb
+            A = -nh
+            l, u, s = lo[i], up[i], split[i]
+            D = np.zeros_like(A)
+            lb = np.zeros_like(A)
+            for j in range(A.shape[0]):
+                if s[j] > 0 or (s[j] == 0 and l[j] >= 0):
+                    D[j] = 1.0
+                elif s[j] < 0 or u[j] <= 0:
+                    D[j] = 0.0
+                elif A[j] >= 0:
+                    D[j] = alpha[i][r, j]
+                else:
+                    D[j] = u[j] / (u[j] - l[j])
+                    lb[j] = -u[j] * l[j] / (u[j] - l[j])
+            Ds.append(D)
+            lbs.append(lb)
+        ge = pinlib.explicit_bound(net, x_lo, x_hi, C[r], Ds, lbs, split, [b[r] for b in beta])
+        assert abs(ge - g[r]) <= 1e-10 * max(1, abs(g[r]))
+
+
+# ---------------------------------------------------------------------------
+# T3: beta = 0 reproduces alpha-CROWN with splits as modified bounds
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_beta_zero_is_alpha_crown(seed):
+    rng, net, _, _, x_lo, x_hi, lo, up, C = tiny_case(seed + 100, widths=(4, 8, 7, 6, 3), m=3)
+    split = random_split(rng, lo, up, k=4)
+    alpha, _ = random_vars(rng, lo, 3)
+    beta0 = [np.zeros((3, l.shape[0])) for l in lo]
+    g = bc.bound(net, x_lo, x_hi, C, lo, up, split, alpha, beta0)
+    for r in range(3):
+        ref = pinlib.alpha_crown_modified_bounds(net, x_lo, x_hi, C[r], lo, up, split, [a[r] for a in alpha])
+        assert abs(ref - g[r]) <= 1e-11 * max(1, abs(g[r]))
+
+
+# ---------------------------------------------------------------------------
+# T8: gradient against central finite differences
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_gradient_matches_central_differences(seed):
+    rng, net, _, _, x_lo, x_hi, lo, up, C = tiny_case(seed + 120, widths=(5, 8, 7, 6, 3), m=2)
+    split = random_split(rng, lo, up, k=3)
+    alpha, beta = random_vars(rng, lo, 2, split, beta_scale=0.5)
+    alpha = [np.clip(a, 0.05, 0.95) for a in alpha]
+    beta = [np.where(s != 0, b + 0.1, 0.0) for b, s in zip(beta, split)]
+    g, ga, gb = bc.bound_and_grad(net, x_lo, x_hi, C, lo, up, split, alpha, beta)
+    h = 1e-3
+
+    def pattern(a, b):
+        _, A0, tr = bc.bound(net, x_lo, x_hi, C, lo, up, split, a, b, keep=True)
+        return [np.sign(A0)] + [np.sign(t[0]) for t in tr]
+
+    base = pattern(alpha, beta)
+    checked = 0
+    for which, vars_, grads in (("a", alpha, ga), ("b", beta, gb)):
+        for i in range(len(vars_)):
+            for r in range(2):
+                for j in range(vars_[i].shape[1]):
+                    uns = lo[i][j] < 0 < up[i][j] and split[i][j] == 0
+                    if (which == "a" and not uns) or (which == "b" and split[i][j] == 0):
+                        assert grads[i][r, j] == 0.0
+                        continue
+                    p, q = [v.copy() for v in vars_], [v.copy() for v in vars_]
+                    p[i][r, j] += h
+                    q[i][r, j] -= h
+                    args_p = (p, beta) if which == "a" else (alpha, p)
+                    args_q = (q, beta) if which == "a" else (alpha, q)
+                    if any((np.any(x != y) or np.any(x != z)) for x, y, z in
+                           zip(base, pattern(*args_p), pattern(*args_q))):
+                        continue
+                    fd = (bc.bound(net, x_lo, x_hi, C, lo, up, split, *args_p)[r] -
+                          bc.bound(net, x_lo, x_hi, C, lo, up, split, *args_q)[r]) / (2 * h)
+                    assert abs(fd - grads[i][r, j]) <= 1e-7 + 1e-6 * abs(fd), (which, i, r, j, fd, grads[i][r, j])
+                    checked += 1
+    assert checked >= 10
+
+
+# ---------------------------------------------------------------------------
+# hand-derived values (tests/golden/hand_example.json holds the derivations)
+
+
+def test_hand_derived_example():
+    with open(os.path.join(HERE, "golden", "hand_example.json")) as f:
+        fx = json.load(f)
+    for case in fx["cases"]:
+        net = [(np.array(W, float), np.array(b, float)) for W, b in case["net"]]
+        lo = [np.array(v, float) for v in case["l"]]
+        up = [np.array(v, float) for v in case["u"]]
+        split = [np.array(v, np.int8) for v in case["split"]]
+        C = np.array(case["C"], float)
+        alpha = [np.array(v, float)[None] for v in case["alpha"]]
+        beta = [np.array(v, float)[None] for v in case["beta"]]
+        x_lo, x_hi = np.array(case["x_lo"], float), np.array(case["x_hi"], float)
+        g, ga, gb = bc.bound_and_grad(net, x_lo, x_hi, C, lo, up, split, alpha, beta)
+        assert abs(g[0] - case["g"]) <= 1e-12, (case["name"], g[0], case["g"])
+        if "dg_dalpha" in case:
+            assert np.allclose(ga[0][0], case["dg_dalpha"], atol=1e-12), case["name"]
+            assert np.allclose(gb[0][0], case["dg_dbeta"], atol=1e-12), case["name"]
+
+
+# ---------------------------------------------------------------------------
+# optimiser
+
+
+def test_adam_first_step_is_normalised_sign():
+    cfg = bc.AdamConfig()
+    th, m, v = bc.adam_ascent_step(np.array([0.5, 0.5, 0.5]), np.array([3.0, -0.02, 0.0]), np.zeros(3), np.zeros(3), 1,
+                                   0.01, cfg)
+    assert np.allclose(th, [0.51, 0.49, 0.5], atol=1e-7)
+
+
+def test_default_alpha_rule():
+    assert list(bc.default_alpha(np.array([-1.0, -2.0, -1.0]), np.array([2.0, 1.0, 1.0]))) == [1.0, 0.0, 1.0]
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_optimise_monotone_and_below_lp(seed):
+    rng, net, _, _, x_lo, x_hi, lo, up, C = tiny_case(seed + 140, widths=(2, 6, 5, 2), m=1)
+    split = random_split(rng, lo, up, k=2)
+    a0 = [bc.default_alpha(l, u)[None] for l, u in zip(lo, up)]
+    b0 = [np.zeros((1, l.shape[0])) for l in lo]
+    g0 = bc.bound(net, x_lo, x_hi, C, lo, up, split, a0, b0)
+    best, a, b, gf = bc.optimize(net, x_lo, x_hi, C, lo, up, split, a0, b0, bc.AdamConfig(lr_alpha=0.1))
+    p_lp, res, _ = pinlib.lp_verify_split(net, x_lo, x_hi, C[0], lo, up, split)
+    assert best[0] >= g0[0] - 1e-12 and best[0] >= gf[0]
+    assert best[0] <= p_lp + 1e-8
+    assert all(np.all((x >= 0) & (x <= 1)) for x in a) and all(np.all(x >= 0) for x in b)
