@@ -1,0 +1,175 @@
+/*
+ * cvbound: batched beta-CROWN bound propagation on one MI355X (gfx950).
+ *
+ * The library computes, for a batch of branch-and-bound subdomains, the
+ * beta-CROWN lower bound of each row of C f(x) over an input box (Wang et al.,
+ * "Beta-CROWN", NeurIPS 2021, Theorem 3.1 with the recursive form of
+ * Eq. definition_A), its gradient with respect to the per-subdomain
+ * variables alpha and beta, and a projected-Adam ascent on them
+ * (Eq. opt_alpha_beta; 20 Adam iterations with a 0.98 learning-rate decay in
+ * the paper's setup, App. C.1).
+ *
+ * Notation (Sec. 2.1): layer i computes z(i) = W(i) zhat(i-1) + b(i) and
+ * zhat(i) = ReLU(z(i)) for i = 1..L-1; layer L is linear; zhat(0) = x.
+ * l(i) <= z(i) <= u(i) are intermediate bounds.  A subdomain adds split
+ * constraints z(i)_j >= 0 (set Z+) or z(i)_j < 0 (set Z-) (Sec. 2.3).
+ *
+ * Conventions for every entry point:
+ *   - return value 0 on success, a negative CV_E* code on failure; on
+ *     failure cv_last_error() gives a message (thread-local), and no output
+ *     has been written;
+ *   - `stream` is a hipStream_t (NULL = the null stream);
+ *   - "host" pointers are read during the call and may be freed afterwards;
+ *     "device" pointers are caller-owned device memory, accessed in stream
+ *     order after the call returns (asynchronous), float32 and contiguous;
+ *   - a handle is not thread-safe: one thread, one stream at a time.
+ *
+ * Variable layouts (device, float32):
+ *   alpha:  for subdomain b with property p, an [m, U_p] block, where U_p is
+ *           the number of root-unstable neurons (l < 0 < u) of property p,
+ *           listed layer by layer in neuron order; blocks concatenated in
+ *           subdomain order (cv_bound_sizes gives the total,
+ *           cv_bound_alpha_offset one entry).  Entries of neurons that the
+ *           subdomain splits are ignored (gradient 0).
+ *   beta:   [nnz, m] in CSR split order (one multiplier per split per spec
+ *           row).
+ *   bounds: [B, m].
+ */
+#ifndef CVBOUND_H
+#define CVBOUND_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  CV_OK = 0,
+  CV_EINVAL = -1,  /* null pointer, bad count or non-finite input           */
+  CV_ESHAPE = -2,  /* layer shapes do not chain or are unsupported           */
+  CV_ESPLIT = -3,  /* invalid split set (see cv_bound_init)                  */
+  CV_ENOMEM = -4,  /* device allocation failed                               */
+  CV_EDEVICE = -5  /* a HIP runtime call failed                              */
+};
+
+enum { CV_LAYER_DENSE = 0, CV_LAYER_CONV2D = 1 };
+
+/* One affine layer (Sec. 2.1).  Dense: in = (in_c,1,1), out = (out_c,1,1),
+ * weight [out_c][in_c] row-major.  Conv2d (cross-correlation, zero padding):
+ * weight OIHW [out_c][in_c][k][k], out_h = (in_h + 2 pad - k)/stride + 1.
+ * Activations are flattened C,H,W row-major.  bias [out_c].  Host pointers. */
+typedef struct cv_layer {
+  int32_t type;
+  int32_t in_c, in_h, in_w;
+  int32_t out_c, out_h, out_w;
+  int32_t kernel, stride, pad;
+  const float *weight;
+  const float *bias;
+} cv_layer;
+
+typedef struct cv_bound cv_bound;
+
+/* Root intermediate bounds by per-layer CROWN (the bound of this library with
+ * beta = 0, no splits, default alpha and specification [I; -I] on each ReLU
+ * layer in turn), computed once per property as in App. B.1.
+ *   layers[n_layers], ReLU after all but the last layer;
+ *   x_lo, x_hi: host [n_props][d0] box;
+ *   l_out, u_out: host [n_props][sum_{i<L} d_i], layer-major.
+ * Synchronous.  Float32 arithmetic: the result is not outward-rounded. */
+int cv_bound_root_bounds(const cv_layer *layers, int32_t n_layers, int32_t n_props,
+                         const float *x_lo, const float *x_hi,
+                         float *l_out, float *u_out, void *stream);
+
+/* Build a handle for one batch of subdomains (Theorem 3.1 inputs).
+ *   layers[n_layers]: the network; the last layer must be dense.
+ *   x_lo, x_hi: host [n_props][d0] input box of each property (the L-inf ball
+ *     of Sec. 2.1, possibly clipped).
+ *   m, C: host [n_props][m][d_L] specification rows, merged into the last
+ *     layer (Sec. 2.1).
+ *   l, u: host [n_props][sum_{i<L} d_i] intermediate bounds, layer-major.
+ *   n_dom, dom_prop: host [n_dom] property of each subdomain.
+ *   split_ptr: host [n_dom+1] CSR offsets; split_layer (1..L-1),
+ *     split_neuron, split_side (+1: z >= 0, i.e. Z+, S = -1; -1: z < 0,
+ *     i.e. Z-, S = +1), each host [nnz] (Eq. S).
+ * CV_ESPLIT when a split names a layer or neuron out of range, a neuron that
+ * is not root-unstable for its property, the same neuron twice in one
+ * subdomain, a side other than +-1, or more than 8191 splits in one
+ * subdomain.  CV_ESHAPE when shapes do not chain, the last layer is a
+ * convolution, or a convolution has an output plane with a multiple-of-64
+ * count of positions violated (H*W % 64 != 0), or stride > 2.
+ * Synchronous; copies everything it needs to the device. */
+int cv_bound_init(cv_bound **out, const cv_layer *layers, int32_t n_layers,
+                  int32_t n_props, const float *x_lo, const float *x_hi,
+                  int32_t m, const float *C, const float *l, const float *u,
+                  int32_t n_dom, const int32_t *dom_prop, const int64_t *split_ptr,
+                  const int32_t *split_layer, const int32_t *split_neuron,
+                  const int8_t *split_side, void *stream);
+
+/* Sizes of the caller-owned arrays: alpha entries, beta entries (nnz*m),
+ * bound rows (n_dom*m).  Any output pointer may be NULL. */
+int cv_bound_sizes(const cv_bound *h, int64_t *n_alpha, int64_t *n_beta, int64_t *n_rows);
+
+/* Index of alpha for (subdomain, spec row, ReLU layer 1..L-1, neuron) in the
+ * alpha layout, or -1 when that neuron is not root-unstable. Host only. */
+int64_t cv_bound_alpha_offset(const cv_bound *h, int32_t dom, int32_t row, int32_t layer,
+                              int32_t neuron);
+
+/* CROWN's default lower slope (alpha = 1 where u >= -l, else 0) into every
+ * alpha entry.  alpha: device [n_alpha]. */
+int cv_bound_alpha_init(cv_bound *h, float *alpha, void *stream);
+
+/* Bound g(alpha, beta) of Eq. beta_crown_lp (box form) for every row.
+ * alpha: device [n_alpha] in [0,1]; beta: device [nnz*m] >= 0 (values are
+ * used as given); lb: device [n_rows] output. */
+int cv_bound_eval(cv_bound *h, const float *alpha, const float *beta, float *lb, void *stream);
+
+/* Bound and its supergradient with respect to alpha and beta (reverse sweep
+ * from the box minimiser x*; per-row, so d(sum lb)/d(var) = d(own row)/d(var)).
+ * lb [n_rows], g_alpha [n_alpha], g_beta [nnz*m]: device outputs. */
+int cv_bound_grad(cv_bound *h, const float *alpha, const float *beta, float *lb,
+                  float *g_alpha, float *g_beta, void *stream);
+
+/* Projected Adam ascent (Kingma & Ba; beta1 0.9, beta2 0.999, eps 1e-8) on
+ * alpha in [0,1] and beta >= 0 for `iters` steps; step t (0-based, counted
+ * from step0) uses learning rate lr * lr_decay^t and bias corrections of step
+ * t+1.  Iterate k is evaluated before its step; the final iterate once more.
+ *   alpha, beta: device in/out (start point in, final iterate out);
+ *   adam_state: device [2*n_alpha + 2*n_beta] (first moments of alpha, second
+ *     of alpha, first of beta, second of beta), in/out, or NULL for zero
+ *     moments kept internally; step0: steps already taken (0 for a fresh run);
+ *   lb_best: device [n_rows] out, max over the iters+1 evaluated bounds;
+ *   lb_last: device [n_rows] out (may be NULL), bound of the final iterate.
+ * The whole loop is captured once in a HIP graph and replayed on later calls
+ * with the same arguments. */
+int cv_bound_optimize(cv_bound *h, int32_t iters, float lr_alpha, float lr_beta, float lr_decay,
+                      float *alpha, float *beta, float *adam_state, int32_t step0,
+                      float *lb_best, float *lb_last, void *stream);
+
+/* Time the candidate tile shapes of every layer's kernels on this handle's
+ * shapes and keep the fastest (process-wide cache keyed by shape).
+ * Synchronous.  Results do not depend on the choice beyond float32 rounding
+ * of the summation order. */
+int cv_bound_autotune(cv_bound *h, void *stream);
+
+/* Per-kernel timing of one gradient pass plus one plain evaluation, each
+ * kernel launch bracketed by HIP events on `stream`, repeated `reps` times.
+ * Fills up to max_out records; *n_out gets the number of distinct kernels.
+ * flops / bytes are the algorithmic counts per launch (see design notes). */
+typedef struct cv_kernel_stat {
+  char name[64];
+  int32_t launches;     /* launches per pass                              */
+  double total_ms;      /* summed over all launches and reps              */
+  double flops;         /* algorithmic flops, summed over launches per rep */
+  double bytes;         /* algorithmic HBM bytes, summed likewise          */
+} cv_kernel_stat;
+int cv_bound_profile(cv_bound *h, const float *alpha, const float *beta, int32_t reps,
+                     cv_kernel_stat *out, int32_t max_out, int32_t *n_out, void *stream);
+
+void cv_bound_destroy(cv_bound *h);
+const char *cv_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CVBOUND_H */

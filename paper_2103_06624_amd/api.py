@@ -1,0 +1,184 @@
+"""Torch-facing wrapper of libcvbound (device memory and streams only).
+
+`BoundProblem` owns a library handle; its methods pass torch tensors' device
+pointers and the current HIP stream to the C ABI.  `BetaCrownBound` is a
+torch.autograd.Function whose forward is cv_bound_eval and whose backward is
+cv_bound_grad scaled by the incoming per-row gradient.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import binding as B
+
+
+def _ptr(a):
+    return ctypes.c_void_p(a.ctypes.data) if a is not None else None
+
+
+def _dptr(t):
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous() and t.dtype == torch.float32, "expected contiguous float32 device tensor"
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def make_layers(layers):
+    """cv_layer array (+ host arrays kept alive) from synth.Layer-like objects."""
+    keep = []
+    arr = (B.cv_layer * len(layers))()
+    for i, ly in enumerate(layers):
+        w = np.ascontiguousarray(ly.weight, dtype=np.float32)
+        b = np.ascontiguousarray(ly.bias, dtype=np.float32)
+        keep += [w, b]
+        ci, hi, wi = ly.in_shape
+        co, ho, wo = ly.out_shape
+        arr[i] = B.cv_layer(B.CV_LAYER_DENSE if ly.kind == 0 else B.CV_LAYER_CONV2D, ci, hi, wi, co, ho, wo,
+                            ly.kernel, ly.stride, ly.pad, w.ctypes.data, b.ctypes.data)
+    return arr, keep
+
+
+def root_bounds(layers, x_lo, x_hi):
+    """Per-layer CROWN intermediate bounds on the GPU: (l, u) float32 [P, sum d_i]."""
+    arr, keep = make_layers(layers)
+    x_lo = np.ascontiguousarray(x_lo, np.float32)
+    x_hi = np.ascontiguousarray(x_hi, np.float32)
+    P = x_lo.shape[0]
+    nd = sum(ly.d_out for ly in layers[:-1])
+    lo = np.zeros((P, nd), np.float32)
+    up = np.zeros((P, nd), np.float32)
+    B.check(B.cv_bound_root_bounds(arr, len(layers), P, _ptr(x_lo), _ptr(x_hi), _ptr(lo), _ptr(up), _stream()))
+    return lo, up
+
+
+class BoundProblem:
+    def __init__(self, layers, x_lo, x_hi, C, lo, up, dom_prop, split_ptr, split_layer, split_neuron, split_side):
+        arr, keep = make_layers(layers)
+        self._keep = keep
+        x_lo = np.ascontiguousarray(x_lo, np.float32)
+        x_hi = np.ascontiguousarray(x_hi, np.float32)
+        C = np.ascontiguousarray(C, np.float32)
+        lo = np.ascontiguousarray(lo, np.float32)
+        up = np.ascontiguousarray(up, np.float32)
+        dom_prop = np.ascontiguousarray(dom_prop, np.int32)
+        split_ptr = np.ascontiguousarray(split_ptr, np.int64)
+        split_layer = np.ascontiguousarray(split_layer, np.int32)
+        split_neuron = np.ascontiguousarray(split_neuron, np.int32)
+        split_side = np.ascontiguousarray(split_side, np.int8)
+        self.P, self.m = C.shape[0], C.shape[1]
+        self.B = dom_prop.shape[0]
+        self._ucount = ((lo < 0) & (up > 0)).sum(axis=1).astype(np.int64)
+        self._dom_prop = dom_prop
+        self._split_ptr = split_ptr
+        self._maps = None
+        h = ctypes.c_void_p()
+        B.check(B.cv_bound_init(ctypes.byref(h), arr, len(layers), self.P, _ptr(x_lo), _ptr(x_hi), self.m, _ptr(C),
+                                _ptr(lo), _ptr(up), self.B, _ptr(dom_prop), _ptr(split_ptr), _ptr(split_layer),
+                                _ptr(split_neuron), _ptr(split_side), _stream()))
+        self.h = h
+        na, nb, nr = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        B.check(B.cv_bound_sizes(h, ctypes.byref(na), ctypes.byref(nb), ctypes.byref(nr)))
+        self.n_alpha, self.n_beta, self.n_rows = na.value, nb.value, nr.value
+
+    @classmethod
+    def from_workload(cls, wl, lo, up, splits=None):
+        sp = splits if splits is not None else wl.splits
+        return cls(wl.net.layers, wl.x_lo, wl.x_hi, wl.C, lo, up, sp.dom_prop, sp.split_ptr, sp.layer, sp.neuron,
+                   sp.side)
+
+    def close(self):
+        if getattr(self, "h", None):
+            B.cv_bound_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _f(self, n):
+        return torch.empty(max(n, 1), dtype=torch.float32, device="cuda")[:n]
+
+    def alpha_offset(self, dom, row, layer, neuron):
+        return B.cv_bound_alpha_offset(self.h, dom, row, layer, neuron)
+
+    def alpha_init(self):
+        a = self._f(self.n_alpha)
+        B.check(B.cv_bound_alpha_init(self.h, _dptr(a), _stream()))
+        return a
+
+    def zeros_beta(self):
+        return torch.zeros(self.n_beta, dtype=torch.float32, device="cuda")
+
+    def eval(self, alpha, beta, out=None):
+        lb = out if out is not None else self._f(self.n_rows)
+        B.check(B.cv_bound_eval(self.h, _dptr(alpha), _dptr(beta), _dptr(lb), _stream()))
+        return lb.view(self.B, self.m)
+
+    def grad(self, alpha, beta):
+        lb = self._f(self.n_rows)
+        ga = self._f(self.n_alpha)
+        gb = self._f(self.n_beta)
+        B.check(B.cv_bound_grad(self.h, _dptr(alpha), _dptr(beta), _dptr(lb), _dptr(ga), _dptr(gb), _stream()))
+        return lb.view(self.B, self.m), ga, gb
+
+    def optimize(self, alpha, beta, iters=20, lr_alpha=0.01, lr_beta=0.05, decay=0.98, adam_state=None, step0=0,
+                 lb_best=None, lb_last=None):
+        """In-place projected Adam on alpha, beta; returns (best, last) bounds [B, m]."""
+        best = lb_best if lb_best is not None else self._f(self.n_rows)
+        last = lb_last if lb_last is not None else self._f(self.n_rows)
+        B.check(B.cv_bound_optimize(self.h, iters, lr_alpha, lr_beta, decay, _dptr(alpha), _dptr(beta),
+                                    _dptr(adam_state), step0, _dptr(best), _dptr(last), _stream()))
+        return best.view(self.B, self.m), last.view(self.B, self.m)
+
+    def row_maps(self):
+        """(row of each alpha entry, row of each beta entry) as device index tensors."""
+        if self._maps is None:
+            rows = np.arange(self.B * self.m)
+            ra = np.repeat(rows, np.repeat(self._ucount[self._dom_prop], self.m))
+            dom = np.repeat(np.arange(self.B), np.diff(self._split_ptr))
+            rb = (dom[:, None] * self.m + np.arange(self.m)[None, :]).reshape(-1)
+            self._maps = (torch.from_numpy(ra).cuda(), torch.from_numpy(rb).cuda())
+        return self._maps
+
+    def autotune(self):
+        B.check(B.cv_bound_autotune(self.h, _stream()))
+
+    def profile(self, alpha, beta, reps=5):
+        out = (B.cv_kernel_stat * 64)()
+        n = ctypes.c_int32()
+        B.check(B.cv_bound_profile(self.h, _dptr(alpha), _dptr(beta), reps, out, 64, ctypes.byref(n), _stream()))
+        res = []
+        for i in range(min(n.value, 64)):
+            s = out[i]
+            res.append(dict(name=s.name.decode(), launches=s.launches, total_ms=s.total_ms, reps=reps, flops=s.flops,
+                            bytes=s.bytes))
+        return res
+
+
+class BetaCrownBound(torch.autograd.Function):
+    """lb = g(alpha, beta) per row [B, m]; backward returns the grad_lb-weighted
+    d lb / d(alpha, beta) (each variable belongs to exactly one row)."""
+
+    @staticmethod
+    def forward(ctx, alpha, beta, problem):
+        lb, ga, gb = problem.grad(alpha.detach().contiguous(), beta.detach().contiguous())
+        ctx.problem = problem
+        ctx.save_for_backward(ga, gb)
+        return lb.clone()
+
+    @staticmethod
+    def backward(ctx, grad_lb):
+        ga, gb = ctx.saved_tensors
+        pb = ctx.problem
+        g = grad_lb.reshape(-1).contiguous()
+        ra, rb = pb.row_maps()
+        return ga * g[ra], gb * g[rb], None

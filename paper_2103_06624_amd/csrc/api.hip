@@ -1,0 +1,964 @@
+// The C ABI of libcvbound: validation, device set-up, pass orchestration,
+// HIP-graph capture of the optimisation loop, tile autotuning and profiling.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/cvbound.h"
+#include "common.h"
+#include "internal.h"
+
+using namespace cvb;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                 \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess) return fail(CV_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+inline int r4(int d) { return (d + 3) & ~3; }
+
+// ---------------------------------------------------------------------------
+// device memory owned by a handle
+
+struct DevMem {
+  std::vector<void*> ptrs;
+  ~DevMem() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+  template <typename T>
+  int alloc(T** out, size_t count) {
+    *out = nullptr;
+    if (count == 0) count = 1;
+    void* p = nullptr;
+    if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(CV_ENOMEM, "device allocation of %zu bytes failed", count * sizeof(T));
+    }
+    ptrs.push_back(p);
+    *out = static_cast<T*>(p);
+    return CV_OK;
+  }
+  template <typename T>
+  int upload(T** out, const T* host, size_t count, hipStream_t s) {
+    int rc = alloc(out, count);
+    if (rc) return rc;
+    (void)s;  // blocking copy: the host buffer may be a temporary
+    if (count && host) HIPCHK(hipMemcpy(*out, host, count * sizeof(T), hipMemcpyHostToDevice));
+    return CV_OK;
+  }
+};
+
+struct DevLayer {
+  int type;
+  int din, dout;
+  ConvGeom g;
+  int ld_in, ld_out;       // padded row lengths of W and Wt (dense)
+  float* W = nullptr;      // dense [dout, ld_in]; conv OIHW
+  float* Wt = nullptr;     // dense [din, ld_out]
+  float* bias = nullptr;   // [dout], per neuron
+  int uniform = 0;         // conv: stride-parity classes hold whole waves
+};
+
+struct KStat {
+  std::string name;
+  double flops = 0, bytes = 0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+};
+
+struct Profiler {
+  std::vector<KStat> recs;
+  hipStream_t s;
+  void begin(const std::string& name, double flops, double bytes) {
+    KStat k;
+    k.name = name;
+    k.flops = flops;
+    k.bytes = bytes;
+    (void)hipEventCreate(&k.e0);
+    (void)hipEventCreate(&k.e1);
+    (void)hipEventRecord(k.e0, s);
+    recs.push_back(k);
+  }
+  void end() { (void)hipEventRecord(recs.back().e1, s); }
+};
+
+struct GraphKey {
+  std::vector<uintptr_t> v;
+  bool operator==(const GraphKey& o) const { return v == o.v; }
+};
+
+}  // namespace
+
+struct cv_bound {
+  DevMem mem;
+  int L = 0;  // layers (ReLU after 1..L-1)
+  std::vector<DevLayer> layers;
+  std::vector<int> dims;  // d_0..d_L
+  std::vector<int> offs;  // ReLU layer offsets in the nd axis
+  int P = 0, m = 0, B = 0, R = 0, nd = 0, d0 = 0, w64 = 0;
+  int64_t nnz = 0, n_alpha = 0;
+  int ldact = 4;
+  int n_slots = 1;
+  // host copies for queries
+  std::vector<int> h_prop;
+  std::vector<int64_t> h_aoff;
+  std::vector<int> h_cidx;  // [P, nd]
+  std::vector<int> h_ucount;
+  std::vector<double> unst_rows_per_layer;  // sum over rows of unstable neurons per ReLU layer
+  // device arrays
+  Batch bt{};
+  float* CW = nullptr;
+  int64_t cw_pstride = 0, cb_pstride = 0;
+  int ldcw = 4;
+  float* Cb = nullptr;
+  float* act[2] = {nullptr, nullptr};
+  float* part = nullptr;
+  int* ulist = nullptr;
+  int64_t* uoff = nullptr;
+  // gradient / optimisation buffers (allocated on first use)
+  float* acomp = nullptr;
+  uint64_t* xpos = nullptr;
+  uint64_t* xneg = nullptr;
+  float* g_alpha = nullptr;
+  float* g_beta = nullptr;
+  float* adam = nullptr;  // [2 n_alpha + 2 n_beta]
+  // tile choice per ReLU-layer kernel: [0..L-1] back-substitution of layer i+1,
+  // [L..2L-1] adjoint forward of layer i+1
+  std::vector<int> cfg;
+  // optimisation graph
+  hipStream_t cap = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  GraphKey gkey;
+  Profiler* prof = nullptr;
+};
+
+namespace {
+
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int>, int> g_tune;  // (mode, M, N, K) -> cfg
+
+int gemm_default_cfg(int M, int N) {
+  (void)M;
+  if (N <= 32) return 5;   // 32x32
+  if (N <= 64) return 2;   // 32x64
+  return 0;                // 64x64
+}
+
+int cfg_for(const cv_bound* h, int mode, int M, int N, int K, int fallback) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find({mode, M, N, K});
+  return it == g_tune.end() ? fallback : it->second;
+  (void)h;
+}
+
+// ---------------------------------------------------------------------------
+// validation
+
+int check_layers(const cv_layer* layers, int n, std::vector<int>& dims, bool allow_conv_last = false) {
+  if (!layers || n < 1) return fail(CV_EINVAL, "need at least one layer");
+  dims.assign(n + 1, 0);
+  for (int i = 0; i < n; ++i) {
+    const cv_layer& ly = layers[i];
+    if (!ly.weight || !ly.bias) return fail(CV_EINVAL, "layer %d: null weight or bias", i + 1);
+    const int64_t din = (int64_t)ly.in_c * ly.in_h * ly.in_w;
+    const int64_t dout = (int64_t)ly.out_c * ly.out_h * ly.out_w;
+    if (ly.in_c <= 0 || ly.in_h <= 0 || ly.in_w <= 0 || ly.out_c <= 0 || ly.out_h <= 0 || ly.out_w <= 0 ||
+        din > (1 << 24) || dout > (1 << 24))
+      return fail(CV_ESHAPE, "layer %d: bad sizes", i + 1);
+    if (ly.type == CV_LAYER_CONV2D) {
+      if (ly.kernel <= 0 || ly.stride <= 0 || ly.pad < 0) return fail(CV_ESHAPE, "layer %d: bad conv geometry", i + 1);
+      if ((ly.in_h + 2 * ly.pad - ly.kernel) / ly.stride + 1 != ly.out_h ||
+          (ly.in_w + 2 * ly.pad - ly.kernel) / ly.stride + 1 != ly.out_w)
+        return fail(CV_ESHAPE, "layer %d: conv output size does not match", i + 1);
+      if (ly.stride > 2 || ly.in_h % ly.stride || ly.in_w % ly.stride)
+        return fail(CV_ESHAPE, "layer %d: stride must be 1 or 2 and divide the input plane", i + 1);
+      if ((ly.in_h * ly.in_w) % 64 || (ly.out_h * ly.out_w) % 64)
+        return fail(CV_ESHAPE, "layer %d: conv planes must hold a multiple of 64 positions", i + 1);
+      if (!conv_channels_supported(ly.in_c) || !(conv_channels_supported(ly.out_c) || ly.out_c == 64))
+        return fail(CV_ESHAPE, "layer %d: unsupported channel count", i + 1);
+      if (i == n - 1 && !allow_conv_last) return fail(CV_ESHAPE, "the last layer must be dense");
+    } else if (ly.type != CV_LAYER_DENSE) {
+      return fail(CV_ESHAPE, "layer %d: unknown type %d", i + 1, ly.type);
+    }
+    if (i == 0) dims[0] = (int)din;
+    else if (din != dims[i]) return fail(CV_ESHAPE, "layer %d: input size %lld does not match %d", i + 1, (long long)din, dims[i]);
+    dims[i + 1] = (int)dout;
+  }
+  return CV_OK;
+}
+
+bool finite_all(const float* p, int64_t n) {
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+// Build the layer copies on the device.
+int upload_layers(cv_bound* h, const cv_layer* layers, int n, hipStream_t s) {
+  h->layers.resize(n);
+  for (int i = 0; i < n; ++i) {
+    const cv_layer& ly = layers[i];
+    DevLayer& d = h->layers[i];
+    d.type = ly.type;
+    d.din = h->dims[i];
+    d.dout = h->dims[i + 1];
+    d.g = ConvGeom{ly.in_c, ly.in_h, ly.in_w, ly.out_c, ly.out_h, ly.out_w, ly.kernel, ly.stride, ly.pad};
+    std::vector<float> bias_full(d.dout);
+    if (ly.type == CV_LAYER_DENSE) {
+      d.ld_in = r4(d.din);
+      d.ld_out = r4(d.dout);
+      std::vector<float> W((size_t)d.dout * d.ld_in, 0.f), Wt((size_t)d.din * d.ld_out, 0.f);
+      for (int o = 0; o < d.dout; ++o)
+        for (int j = 0; j < d.din; ++j) {
+          const float w = ly.weight[(size_t)o * d.din + j];
+          W[(size_t)o * d.ld_in + j] = w;
+          Wt[(size_t)j * d.ld_out + o] = w;
+        }
+      int rc = h->mem.upload(&d.W, W.data(), W.size(), s);
+      if (rc) return rc;
+      rc = h->mem.upload(&d.Wt, Wt.data(), Wt.size(), s);
+      if (rc) return rc;
+      for (int o = 0; o < d.dout; ++o) bias_full[o] = ly.bias[o];
+    } else {
+      const size_t nw = (size_t)ly.out_c * ly.in_c * ly.kernel * ly.kernel;
+      int rc = h->mem.upload(&d.W, ly.weight, nw, s);
+      if (rc) return rc;
+      const int pos = ly.out_h * ly.out_w;
+      for (int o = 0; o < d.dout; ++o) bias_full[o] = ly.bias[o / pos];
+      d.uniform = ((ly.in_h / ly.stride) * (ly.in_w / ly.stride)) % 64 == 0;
+      if (!finite_all(ly.weight, (int64_t)nw)) return fail(CV_EINVAL, "layer %d: non-finite weight", i + 1);
+    }
+    if (ly.type == CV_LAYER_DENSE && !finite_all(ly.weight, (int64_t)d.dout * d.din))
+      return fail(CV_EINVAL, "layer %d: non-finite weight", i + 1);
+    if (!finite_all(ly.bias, ly.out_c)) return fail(CV_EINVAL, "layer %d: non-finite bias", i + 1);
+    int rc = h->mem.upload(&d.bias, bias_full.data(), bias_full.size(), s);
+    if (rc) return rc;
+  }
+  return CV_OK;
+}
+
+// Spec source for build(): host C, or the identity [I; -I] on the last layer.
+struct Spec {
+  const float* C = nullptr;  // [P, m, dL] host
+  bool identity = false;
+};
+
+int build(cv_bound* h, const cv_layer* layers, int n_layers, int P, const float* x_lo, const float* x_hi, int m,
+          Spec spec, const float* l, const float* u, int B, const int32_t* dom_prop, const int64_t* split_ptr,
+          const int32_t* split_layer, const int32_t* split_neuron, const int8_t* split_side, hipStream_t s) {
+  if (P <= 0 || B < 0 || m <= 0) return fail(CV_EINVAL, "n_props, n_dom and m must be positive");
+  if (!x_lo || !x_hi || (!spec.C && !spec.identity) || (!dom_prop && B > 0) || !split_ptr)
+    return fail(CV_EINVAL, "null input pointer");
+  int rc = check_layers(layers, n_layers, h->dims, spec.identity);
+  if (rc) return rc;
+  h->L = n_layers;
+  h->P = P;
+  h->m = m;
+  h->B = B;
+  const int64_t R = (int64_t)B * m;
+  if (R > (1ll << 30)) return fail(CV_EINVAL, "too many rows (%lld)", (long long)R);
+  h->R = (int)R;
+  h->d0 = h->dims[0];
+  h->w64 = (h->d0 + 63) / 64;
+  h->offs.assign(std::max(1, n_layers), 0);
+  int nd = 0;
+  for (int i = 1; i < n_layers; ++i) {
+    h->offs[i - 1] = nd;
+    nd += h->dims[i];
+  }
+  h->nd = nd;
+  if (nd > 0 && (!l || !u)) return fail(CV_EINVAL, "null intermediate bounds");
+  if (!finite_all(x_lo, (int64_t)P * h->d0) || !finite_all(x_hi, (int64_t)P * h->d0))
+    return fail(CV_EINVAL, "non-finite input box");
+  for (int64_t i = 0; i < (int64_t)P * h->d0; ++i)
+    if (x_lo[i] > x_hi[i]) return fail(CV_EINVAL, "input box has x_lo > x_hi at %lld", (long long)i);
+  if (nd > 0 && (!finite_all(l, (int64_t)P * nd) || !finite_all(u, (int64_t)P * nd)))
+    return fail(CV_EINVAL, "non-finite intermediate bounds");
+  if (spec.C && !finite_all(spec.C, (int64_t)P * m * h->dims[n_layers])) return fail(CV_EINVAL, "non-finite C");
+
+  // ---- per-property neuron classes (Eq. definition_D: l >= 0 active, u <= 0 inactive)
+  std::vector<uint16_t> kind((size_t)P * nd);
+  h->h_cidx.assign((size_t)P * nd, -1);
+  h->h_ucount.assign(P, 0);
+  std::vector<int> ulist;
+  std::vector<int64_t> uoff(P + 1, 0);
+  std::vector<std::vector<int>> ucount_layer(P, std::vector<int>(std::max(1, n_layers - 1), 0));
+  for (int p = 0; p < P; ++p) {
+    uoff[p] = (int64_t)ulist.size();
+    for (int j = 0; j < nd; ++j) {
+      const float lo = l[(size_t)p * nd + j], up = u[(size_t)p * nd + j];
+      uint16_t k = lo >= 0.f ? kActive : (up <= 0.f ? kInactive : kUnstable);
+      kind[(size_t)p * nd + j] = k;
+      if (k == kUnstable) {
+        h->h_cidx[(size_t)p * nd + j] = h->h_ucount[p]++;
+        ulist.push_back(j);
+        int li = (int)(std::upper_bound(h->offs.begin(), h->offs.begin() + (n_layers - 1), j) - h->offs.begin()) - 1;
+        ucount_layer[p][li]++;
+      }
+    }
+  }
+  uoff[P] = (int64_t)ulist.size();
+
+  // ---- subdomains and splits
+  if (split_ptr[0] != 0) return fail(CV_ESPLIT, "split_ptr[0] must be 0");
+  h->nnz = B > 0 ? split_ptr[B] : 0;
+  std::vector<int> split_dom(h->nnz), split_col(h->nnz);
+  h->h_prop.assign(dom_prop, dom_prop + B);
+  h->h_aoff.assign(B + 1, 0);
+  h->unst_rows_per_layer.assign(std::max(1, n_layers - 1), 0.0);
+  std::vector<int> seen(nd, -1);
+  for (int b = 0; b < B; ++b) {
+    const int p = dom_prop[b];
+    if (p < 0 || p >= P) return fail(CV_EINVAL, "subdomain %d: property %d out of range", b, p);
+    h->h_aoff[b + 1] = h->h_aoff[b] + (int64_t)m * h->h_ucount[p];
+    for (int li = 0; li + 1 < n_layers; ++li) h->unst_rows_per_layer[li] += (double)m * ucount_layer[p][li];
+    const int64_t s0 = split_ptr[b], s1 = split_ptr[b + 1];
+    if (s1 < s0) return fail(CV_ESPLIT, "subdomain %d: split_ptr decreases", b);
+    if (s1 - s0 > kMaxDepth) return fail(CV_ESPLIT, "subdomain %d: more than %d splits", b, kMaxDepth);
+    for (int64_t t = s0; t < s1; ++t) {
+      const int ly = split_layer[t], nr = split_neuron[t];
+      if (ly < 1 || ly >= n_layers) return fail(CV_ESPLIT, "split %lld: layer %d out of range", (long long)t, ly);
+      if (nr < 0 || nr >= h->dims[ly]) return fail(CV_ESPLIT, "split %lld: neuron %d out of range", (long long)t, nr);
+      if (split_side[t] != 1 && split_side[t] != -1)
+        return fail(CV_ESPLIT, "split %lld: side must be +1 or -1", (long long)t);
+      const int col = h->offs[ly - 1] + nr;
+      if (kind[(size_t)p * nd + col] != kUnstable)
+        return fail(CV_ESPLIT, "split %lld: neuron (%d,%d) is not root-unstable", (long long)t, ly, nr);
+      if (seen[col] == b) return fail(CV_ESPLIT, "subdomain %d splits neuron (%d,%d) twice", b, ly, nr);
+      seen[col] = b;
+      split_dom[t] = b;
+      split_col[t] = col;
+    }
+  }
+  h->n_alpha = h->h_aoff[B];
+
+  // ---- device copies
+  rc = upload_layers(h, layers, n_layers, s);
+  if (rc) return rc;
+  DevMem& M = h->mem;
+  int *d_prop, *d_ucount, *d_cidx, *d_split_dom, *d_split_col;
+  int64_t *d_aoff, *d_sptr;
+  uint16_t *d_kind, *d_status;
+  int8_t* d_side;
+  float *d_l, *d_u, *d_xlo, *d_xhi, *d_adef;
+  float2* d_chord;
+  if ((rc = M.upload(&d_prop, h->h_prop.data(), B, s)) || (rc = M.upload(&d_aoff, h->h_aoff.data(), B + 1, s)) ||
+      (rc = M.upload(&d_ucount, h->h_ucount.data(), P, s)) || (rc = M.upload(&d_sptr, split_ptr, B + 1, s)) ||
+      (rc = M.upload(&d_cidx, h->h_cidx.data(), (size_t)P * nd, s)) ||
+      (rc = M.upload(&d_kind, kind.data(), (size_t)P * nd, s)) ||
+      (rc = M.upload(&d_split_dom, split_dom.data(), h->nnz, s)) ||
+      (rc = M.upload(&d_split_col, split_col.data(), h->nnz, s)) ||
+      (rc = M.upload(&d_side, split_side ? split_side : (const int8_t*)nullptr, split_side ? h->nnz : 0, s)) ||
+      (rc = M.upload(&d_l, l, l ? (size_t)P * nd : 0, s)) || (rc = M.upload(&d_u, u, u ? (size_t)P * nd : 0, s)) ||
+      (rc = M.upload(&d_xlo, x_lo, (size_t)P * h->d0, s)) || (rc = M.upload(&d_xhi, x_hi, (size_t)P * h->d0, s)) ||
+      (rc = M.alloc(&d_adef, (size_t)P * nd)) || (rc = M.alloc(&d_chord, (size_t)P * nd)) ||
+      (rc = M.alloc(&d_status, (size_t)B * nd)) || (rc = M.upload(&h->ulist, ulist.data(), ulist.size(), s)) ||
+      (rc = M.upload(&h->uoff, uoff.data(), P + 1, s)))
+    return rc;
+  launch_prep_chord(d_l, d_u, d_chord, d_adef, (int64_t)P * nd, s);
+  launch_status_fill(d_status, d_kind, d_prop, B, nd, s);
+  launch_status_split(d_status, d_split_dom, d_sptr, d_split_col, d_side, h->nnz, nd, s);
+  HIPCHK(hipGetLastError());
+
+  Batch& bt = h->bt;
+  bt.m = m;
+  bt.n_rows = h->R;
+  bt.nd = nd;
+  bt.d0 = h->d0;
+  bt.w64 = h->w64;
+  bt.prop = d_prop;
+  bt.aoff = d_aoff;
+  bt.ucount = d_ucount;
+  bt.sptr = d_sptr;
+  bt.status = d_status;
+  bt.cidx = d_cidx;
+  bt.chord = d_chord;
+  bt.adef = d_adef;
+  bt.xlo = d_xlo;
+  bt.xhi = d_xhi;
+
+  // ---- specification merged into the last layer: A(L-1) = C W(L), c = C b(L)
+  const DevLayer& last = h->layers[n_layers - 1];
+  const int dprev = h->dims[n_layers - 1];
+  h->ldcw = r4(dprev);
+  if (spec.identity) {
+    const int d = last.dout;
+    if (m != 2 * d) return fail(CV_EINVAL, "identity spec needs m = 2 d");
+    if ((rc = M.alloc(&h->CW, (size_t)m * h->ldcw)) || (rc = M.alloc(&h->Cb, m))) return rc;
+    launch_spec_identity(last.type == CV_LAYER_DENSE ? last.W : nullptr, last.ld_in,
+                         last.type == CV_LAYER_CONV2D ? last.W : nullptr,
+                         last.type == CV_LAYER_CONV2D ? &last.g : nullptr, last.bias, d, dprev, h->CW, h->ldcw, h->Cb,
+                         s);
+    h->cw_pstride = 0;
+    h->cb_pstride = 0;
+  } else {
+    float* dC;
+    if ((rc = M.upload(&dC, spec.C, (size_t)P * m * last.dout, s)) ||
+        (rc = M.alloc(&h->CW, (size_t)P * m * h->ldcw)) || (rc = M.alloc(&h->Cb, (size_t)P * m)))
+      return rc;
+    launch_spec_merge(dC, last.W, last.ld_in, last.bias, P, m, last.dout, dprev, h->CW, h->ldcw, h->Cb, s);
+    h->cw_pstride = (int64_t)m * h->ldcw;
+    h->cb_pstride = m;
+  }
+  HIPCHK(hipGetLastError());
+
+  // ---- workspace
+  int maxd = 4;
+  for (int i = 1; i < n_layers; ++i) maxd = std::max(maxd, h->dims[i]);
+  h->ldact = r4(maxd);
+  h->n_slots = 1;
+  for (int i = n_layers - 1; i >= 1; --i) {  // back-substitution through layer i
+    const DevLayer& ly = h->layers[i - 1];
+    h->n_slots += ly.type == CV_LAYER_DENSE ? (h->dims[i - 1] + 31) / 32 : 1;
+  }
+  if (n_layers >= 2) {
+    if ((rc = M.alloc(&h->act[0], (size_t)h->R * h->ldact)) || (rc = M.alloc(&h->act[1], (size_t)h->R * h->ldact)))
+      return rc;
+  }
+  if ((rc = M.alloc(&h->part, (size_t)std::max(1, h->R) * h->n_slots))) return rc;
+  h->cfg.assign(2 * n_layers, -1);
+  for (int i = 1; i < n_layers; ++i) {
+    if (h->layers[i - 1].type != CV_LAYER_DENSE) continue;
+    const int N_b = h->dims[i - 1], K_b = h->dims[i];
+    h->cfg[i - 1] = cfg_for(h, i - 1 >= 1 ? kBwdRelax : kBwdConc, h->R, N_b, K_b, gemm_default_cfg(h->R, N_b));
+    h->cfg[n_layers + i - 1] = cfg_for(h, i == 1 ? kFwdX : kFwd, h->R, K_b, N_b, gemm_default_cfg(h->R, K_b));
+  }
+  // conv kernels' LDS needs
+  for (int i = 0; i + 1 < n_layers; ++i) {
+    const DevLayer& ly = h->layers[i];
+    if (ly.type != CV_LAYER_CONV2D) continue;
+    if (convt_smem_bytes(ly.g, h->w64, i == 0) > 65536 || conv_smem_bytes(ly.g) > 65536)
+      return fail(CV_ESHAPE, "layer %d: conv rows do not fit in LDS", i + 1);
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  return CV_OK;
+}
+
+int ensure_grad(cv_bound* h) {
+  if (h->acomp) return CV_OK;
+  int rc;
+  if ((rc = h->mem.alloc(&h->acomp, h->n_alpha)) || (rc = h->mem.alloc(&h->xpos, (size_t)h->R * h->w64)) ||
+      (rc = h->mem.alloc(&h->xneg, (size_t)h->R * h->w64)))
+    return rc;
+  return CV_OK;
+}
+
+int ensure_opt(cv_bound* h) {
+  int rc = ensure_grad(h);
+  if (rc) return rc;
+  if (h->g_alpha) return CV_OK;
+  const int64_t nb = h->nnz * h->m;
+  if ((rc = h->mem.alloc(&h->g_alpha, h->n_alpha)) || (rc = h->mem.alloc(&h->g_beta, nb)) ||
+      (rc = h->mem.alloc(&h->adam, 2 * h->n_alpha + 2 * nb)))
+    return rc;
+  return CV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// passes
+
+std::string cfg_name(int cfg) {
+  return std::to_string(kGemmCfgs[cfg].bm) + "x" + std::to_string(kGemmCfgs[cfg].bn);
+}
+
+Epi make_epi(const cv_bound* h) {
+  Epi e{};
+  e.part = h->part;
+  e.n_slots = h->n_slots;
+  e.ldo = h->ldact;
+  return e;
+}
+
+// conv MACs of one row (taps inside the input only)
+double conv_macs(const ConvGeom& g) {
+  double taps = 0;
+  for (int oy = 0; oy < g.ho; ++oy)
+    for (int ky = 0; ky < g.k; ++ky) {
+      const int iy = oy * g.s - g.p + ky;
+      if (iy < 0 || iy >= g.hi) continue;
+      for (int ox = 0; ox < g.wo; ++ox)
+        for (int kx = 0; kx < g.k; ++kx) {
+          const int ix = ox * g.s - g.p + kx;
+          if (ix >= 0 && ix < g.wi) taps += 1;
+        }
+    }
+  return taps * g.ci * g.co;
+}
+
+// Back-substitution of every layer plus concretisation; lb / best per row.
+int enqueue_bwd(cv_bound* h, const float* alpha, const float* beta, bool grad, float* lb, float* best, int first,
+                hipStream_t s) {
+  const int L = h->L;
+  Vars v{};
+  v.alpha = alpha;
+  v.beta = beta;
+  v.acomp = grad ? h->acomp : nullptr;
+  v.xpos = grad ? h->xpos : nullptr;
+  v.xneg = grad ? h->xneg : nullptr;
+  Profiler* pf = h->prof;
+  if (h->R == 0) return CV_OK;
+  {
+    TopArgs ta{};
+    ta.CW = h->CW;
+    ta.cw_pstride = h->cw_pstride;
+    ta.ldcw = h->ldcw;
+    ta.Cb = h->Cb;
+    ta.cb_pstride = h->cb_pstride;
+    ta.n = h->dims[L - 1];
+    ta.conc = L == 1;
+    ta.bt = h->bt;
+    ta.v = v;
+    ta.e = make_epi(h);
+    ta.e.slot0 = 0;
+    if (L >= 2) {
+      ta.e.layer_off = h->offs[L - 2];
+      ta.e.bias = h->layers[L - 2].bias;
+      ta.e.out = h->act[0];
+    }
+    if (pf) pf->begin(L == 1 ? "top_conc" : "top_relax", 0, (double)h->R * ta.n * 8);
+    launch_top(ta, s);
+    if (pf) pf->end();
+  }
+  int cur = 0, slot = 1;
+  for (int i = L - 1; i >= 1; --i) {
+    const DevLayer& ly = h->layers[i - 1];
+    const int mode = i - 1 >= 1 ? kBwdRelax : kBwdConc;
+    Epi e = make_epi(h);
+    e.slot0 = slot;
+    e.n = h->dims[i - 1];
+    if (mode == kBwdRelax) {
+      e.layer_off = h->offs[i - 2];
+      e.bias = h->layers[i - 2].bias;
+      e.out = h->act[cur ^ 1];
+    }
+    const double rows = h->R;
+    const int N = h->dims[i - 1], K = h->dims[i];
+    const double io = rows * K * 4.0 + (mode == kBwdRelax ? rows * N * 4.0 : rows * N / 4.0) +
+                      (double)h->B * N * 2.0 +
+                      (mode == kBwdRelax ? h->unst_rows_per_layer[i - 2] * 4.0 * (grad ? 2 : 1) : 0.0);
+    if (ly.type == CV_LAYER_DENSE) {
+      const int c = h->cfg[i - 1] >= 0 ? h->cfg[i - 1] : 0;
+      GemmArgs g{h->act[cur], h->ldact, ly.Wt, ly.ld_out, h->R, N, K, 0, h->bt, v, e};
+      if (pf) pf->begin(std::string(mode == kBwdRelax ? "gemm_bwd_relax_" : "gemm_bwd_conc_") + cfg_name(c),
+                        2.0 * rows * N * K, io + (double)N * K * 4.0);
+      launch_gemm(c, mode, g, s);
+      if (pf) pf->end();
+      slot += (N + kGemmCfgs[c].bn - 1) / kGemmCfgs[c].bn;
+    } else {
+      ConvArgs a{h->act[cur], h->ldact, ly.W, ly.g, h->R, 0, ly.uniform, h->bt, v, e};
+      if (pf) pf->begin(std::string(mode == kBwdRelax ? "convt_bwd_relax_ci" : "convt_bwd_conc_ci") +
+                            std::to_string(ly.g.ci),
+                        2.0 * rows * conv_macs(ly.g), io);
+      if (launch_convt_bwd(mode, a, s)) return fail(CV_ESHAPE, "unsupported conv channels");
+      if (pf) pf->end();
+      slot += 1;
+    }
+    cur ^= 1;
+  }
+  if (pf) pf->begin("finalize", 0, (double)h->R * (slot + 2) * 4.0);
+  launch_finalize(h->part, h->n_slots, slot, h->R, lb, best, first, s);
+  if (pf) pf->end();
+  HIPCHK(hipGetLastError());
+  return CV_OK;
+}
+
+// Adjoint forward sweep: zbar(i) = W(i) zhat(i-1) + b(i) from zhat(0) = x*,
+// gradients of alpha and beta in the epilogues.
+int enqueue_fwd(cv_bound* h, const float* alpha, const float* beta, float* ga, float* gb, hipStream_t s) {
+  const int L = h->L;
+  Vars v{};
+  v.alpha = alpha;
+  v.beta = beta;
+  v.acomp = h->acomp;
+  v.galpha = ga;
+  v.gbeta = gb;
+  v.xpos = h->xpos;
+  v.xneg = h->xneg;
+  Profiler* pf = h->prof;
+  if (h->R == 0) return CV_OK;
+  for (int i = 1; i <= L - 1; ++i) {
+    const DevLayer& ly = h->layers[i - 1];
+    const int mode = i == 1 ? kFwdX : kFwd;
+    const int last = i == L - 1;
+    Epi e = make_epi(h);
+    e.layer_off = h->offs[i - 1];
+    e.bias = ly.bias;
+    e.n = h->dims[i];
+    e.out = h->act[i & 1];
+    const float* in = i == 1 ? nullptr : h->act[(i - 1) & 1];
+    const double rows = h->R;
+    const int N = h->dims[i], K = h->dims[i - 1];
+    const double io = (i == 1 ? rows * K / 4.0 : rows * K * 4.0) + (last ? 0.0 : rows * N * 4.0) +
+                      (double)h->B * N * 2.0 + h->unst_rows_per_layer[i - 1] * 4.0 * 3;
+    if (ly.type == CV_LAYER_DENSE) {
+      const int c = h->cfg[L + i - 1] >= 0 ? h->cfg[L + i - 1] : 0;
+      GemmArgs g{in, h->ldact, ly.W, ly.ld_in, h->R, N, K, last, h->bt, v, e};
+      if (pf) pf->begin(std::string(mode == kFwdX ? "gemm_fwd_x_" : "gemm_fwd_") + cfg_name(c), 2.0 * rows * N * K,
+                        io + (double)N * K * 4.0);
+      launch_gemm(c, mode, g, s);
+      if (pf) pf->end();
+    } else {
+      ConvArgs a{in, h->ldact, ly.W, ly.g, h->R, last, ly.uniform, h->bt, v, e};
+      if (pf) pf->begin(std::string(mode == kFwdX ? "conv_fwd_x_co" : "conv_fwd_co") + std::to_string(ly.g.co),
+                        2.0 * rows * conv_macs(ly.g), io);
+      if (launch_conv_fwd(mode, a, s)) return fail(CV_ESHAPE, "unsupported conv channels");
+      if (pf) pf->end();
+    }
+  }
+  HIPCHK(hipGetLastError());
+  return CV_OK;
+}
+
+int enqueue_opt(cv_bound* h, int iters, float lr_a, float lr_b, float decay, float* alpha, float* beta,
+                float* adam_state, int step0, float* lb_best, float* lb_last, hipStream_t s) {
+  const int64_t nb = h->nnz * h->m;
+  float* st = adam_state ? adam_state : h->adam;
+  float *ma = st, *va = st + h->n_alpha, *mb = st + 2 * h->n_alpha, *vb = st + 2 * h->n_alpha + nb;
+  if (!adam_state) launch_fill(h->adam, 0.f, 2 * h->n_alpha + 2 * nb, s);
+  int rc;
+  for (int t = 0; t < iters; ++t) {
+    if ((rc = enqueue_bwd(h, alpha, beta, true, nullptr, lb_best, t == 0, s))) return rc;
+    if ((rc = enqueue_fwd(h, alpha, beta, h->g_alpha, h->g_beta, s))) return rc;
+    const int tt = step0 + t;
+    const double bc1 = 1.0 - std::pow(0.9, tt + 1), bc2 = 1.0 - std::pow(0.999, tt + 1);
+    const double sc = std::pow((double)decay, tt);
+    if (h->prof) h->prof->begin("adam", 0, (h->n_alpha + nb) * 28.0);
+    launch_adam(alpha, h->g_alpha, ma, va, h->n_alpha, (float)(lr_a * sc), (float)bc1, (float)bc2, 0.f, 1.f, s);
+    launch_adam(beta, h->g_beta, mb, vb, nb, (float)(lr_b * sc), (float)bc1, (float)bc2, 0.f, INFINITY, s);
+    if (h->prof) h->prof->end();
+  }
+  if ((rc = enqueue_bwd(h, alpha, beta, false, lb_last, lb_best, iters == 0, s))) return rc;
+  HIPCHK(hipGetLastError());
+  return CV_OK;
+}
+
+void drop_graph(cv_bound* h) {
+  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+  h->gexec = nullptr;
+  h->gkey.v.clear();
+}
+
+}  // namespace
+
+// ===========================================================================
+// ABI
+
+extern "C" {
+
+const char* cv_last_error(void) { return g_err.c_str(); }
+
+int cv_bound_init(cv_bound** out, const cv_layer* layers, int32_t n_layers, int32_t n_props, const float* x_lo,
+                  const float* x_hi, int32_t m, const float* C, const float* l, const float* u, int32_t n_dom,
+                  const int32_t* dom_prop, const int64_t* split_ptr, const int32_t* split_layer,
+                  const int32_t* split_neuron, const int8_t* split_side, void* stream) {
+  if (!out) return fail(CV_EINVAL, "null handle pointer");
+  *out = nullptr;
+  if (!C) return fail(CV_EINVAL, "null specification");
+  if (split_ptr && n_dom > 0 && split_ptr[n_dom] > 0 && (!split_layer || !split_neuron || !split_side))
+    return fail(CV_EINVAL, "null split arrays");
+  std::unique_ptr<cv_bound> h(new cv_bound());
+  Spec sp;
+  sp.C = C;
+  int rc = build(h.get(), layers, n_layers, n_props, x_lo, x_hi, m, sp, l, u, n_dom, dom_prop, split_ptr,
+                 split_layer, split_neuron, split_side, (hipStream_t)stream);
+  if (rc) return rc;
+  *out = h.release();
+  return CV_OK;
+}
+
+int cv_bound_sizes(const cv_bound* h, int64_t* n_alpha, int64_t* n_beta, int64_t* n_rows) {
+  if (!h) return fail(CV_EINVAL, "null handle");
+  if (n_alpha) *n_alpha = h->n_alpha;
+  if (n_beta) *n_beta = h->nnz * h->m;
+  if (n_rows) *n_rows = h->R;
+  return CV_OK;
+}
+
+int64_t cv_bound_alpha_offset(const cv_bound* h, int32_t dom, int32_t row, int32_t layer, int32_t neuron) {
+  if (!h || dom < 0 || dom >= h->B || row < 0 || row >= h->m || layer < 1 || layer >= h->L || neuron < 0 ||
+      neuron >= h->dims[layer])
+    return -1;
+  const int p = h->h_prop[dom];
+  const int c = h->h_cidx[(size_t)p * h->nd + h->offs[layer - 1] + neuron];
+  if (c < 0) return -1;
+  return h->h_aoff[dom] + (int64_t)row * h->h_ucount[p] + c;
+}
+
+int cv_bound_alpha_init(cv_bound* h, float* alpha, void* stream) {
+  if (!h || (!alpha && h->n_alpha > 0)) return fail(CV_EINVAL, "null argument");
+  launch_alpha_default(alpha, h->ulist, h->uoff, h->bt, (hipStream_t)stream);
+  HIPCHK(hipGetLastError());
+  return CV_OK;
+}
+
+int cv_bound_eval(cv_bound* h, const float* alpha, const float* beta, float* lb, void* stream) {
+  if (!h || !lb || (!alpha && h->n_alpha > 0) || (!beta && h->nnz > 0)) return fail(CV_EINVAL, "null argument");
+  return enqueue_bwd(h, alpha, beta, false, lb, nullptr, 0, (hipStream_t)stream);
+}
+
+int cv_bound_grad(cv_bound* h, const float* alpha, const float* beta, float* lb, float* g_alpha, float* g_beta,
+                  void* stream) {
+  if (!h || !lb || (!alpha && h->n_alpha > 0) || (!beta && h->nnz > 0) || (!g_alpha && h->n_alpha > 0) ||
+      (!g_beta && h->nnz > 0))
+    return fail(CV_EINVAL, "null argument");
+  int rc = ensure_grad(h);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  if ((rc = enqueue_bwd(h, alpha, beta, true, lb, nullptr, 0, s))) return rc;
+  return enqueue_fwd(h, alpha, beta, g_alpha, g_beta, s);
+}
+
+int cv_bound_optimize(cv_bound* h, int32_t iters, float lr_alpha, float lr_beta, float lr_decay, float* alpha,
+                      float* beta, float* adam_state, int32_t step0, float* lb_best, float* lb_last, void* stream) {
+  if (!h || !lb_best || (!alpha && h->n_alpha > 0) || (!beta && h->nnz > 0)) return fail(CV_EINVAL, "null argument");
+  if (iters < 0 || step0 < 0 || !std::isfinite(lr_alpha) || !std::isfinite(lr_beta) || !std::isfinite(lr_decay))
+    return fail(CV_EINVAL, "bad optimiser settings");
+  int rc = ensure_opt(h);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  if (h->R == 0) return CV_OK;
+  GraphKey key;
+  float fl[3] = {lr_alpha, lr_beta, lr_decay};
+  uint32_t fb[3];
+  std::memcpy(fb, fl, sizeof(fb));
+  key.v = {(uintptr_t)alpha, (uintptr_t)beta, (uintptr_t)adam_state, (uintptr_t)lb_best, (uintptr_t)lb_last,
+           (uintptr_t)iters, (uintptr_t)step0, fb[0], fb[1], fb[2]};
+  if (!h->gexec || !(h->gkey == key)) {
+    drop_graph(h);
+    if (!h->cap) HIPCHK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+    HIPCHK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+    rc = enqueue_opt(h, iters, lr_alpha, lr_beta, lr_decay, alpha, beta, adam_state, step0, lb_best, lb_last, h->cap);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(h->cap, &graph);
+    if (rc) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    if (e != hipSuccess) return fail(CV_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&h->gexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      h->gexec = nullptr;
+      return fail(CV_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
+    }
+    h->gkey = key;
+  }
+  HIPCHK(hipGraphLaunch(h->gexec, s));
+  return CV_OK;
+}
+
+int cv_bound_autotune(cv_bound* h, void* stream) {
+  if (!h) return fail(CV_EINVAL, "null handle");
+  hipStream_t s = (hipStream_t)stream;
+  int rc = ensure_opt(h);
+  if (rc) return rc;
+  if (h->R == 0) return CV_OK;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  const int L = h->L;
+  for (int dir = 0; dir < 2; ++dir) {
+    for (int i = 1; i < L; ++i) {
+      const DevLayer& ly = h->layers[i - 1];
+      if (ly.type != CV_LAYER_DENSE) continue;
+      int mode, N, K;
+      const float* A;
+      const float* Bt;
+      int ldb;
+      Epi e = make_epi(h);
+      Vars v{};
+      v.alpha = nullptr;
+      v.beta = h->g_beta;  // any valid memory: only timing matters here
+      v.acomp = h->acomp;
+      v.galpha = h->g_alpha;
+      v.gbeta = h->g_beta;
+      v.xpos = h->xpos;
+      v.xneg = h->xneg;
+      if (dir == 0) {
+        mode = i - 1 >= 1 ? kBwdRelax : kBwdConc;
+        N = h->dims[i - 1];
+        K = h->dims[i];
+        A = h->act[0];
+        Bt = ly.Wt;
+        ldb = ly.ld_out;
+        if (mode == kBwdRelax) {
+          e.layer_off = h->offs[i - 2];
+          e.bias = h->layers[i - 2].bias;
+          e.out = h->act[1];
+        }
+        e.slot0 = 1;
+      } else {
+        mode = i == 1 ? kFwdX : kFwd;
+        N = h->dims[i];
+        K = h->dims[i - 1];
+        A = h->act[0];
+        Bt = ly.W;
+        ldb = ly.ld_in;
+        e.layer_off = h->offs[i - 1];
+        e.bias = ly.bias;
+        e.out = h->act[1];
+      }
+      // the candidates need the same slot room as the worst case (BN = 32)
+      float best_ms = 1e30f;
+      int best = -1;
+      for (int c = 0; c < kNumGemmCfgs; ++c) {
+        GemmArgs g{A, h->ldact, Bt, ldb, h->R, N, K, dir == 1 && i == L - 1, h->bt, v, e};
+        for (int w = 0; w < 2; ++w) launch_gemm(c, mode, g, s);
+        HIPCHK(hipEventRecord(e0, s));
+        const int reps = 10;
+        for (int w = 0; w < reps; ++w) launch_gemm(c, mode, g, s);
+        HIPCHK(hipEventRecord(e1, s));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = c;
+        }
+      }
+      h->cfg[(dir == 0 ? 0 : L) + i - 1] = best;
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      g_tune[{mode, h->R, N, K}] = best;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  drop_graph(h);
+  HIPCHK(hipStreamSynchronize(s));
+  return CV_OK;
+}
+
+int cv_bound_profile(cv_bound* h, const float* alpha, const float* beta, int32_t reps, cv_kernel_stat* out,
+                     int32_t max_out, int32_t* n_out, void* stream) {
+  if (!h || !out || !n_out || reps <= 0) return fail(CV_EINVAL, "bad argument");
+  int rc = ensure_opt(h);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  Profiler pf;
+  pf.s = s;
+  h->prof = &pf;
+  std::vector<std::string> order;
+  std::map<std::string, cv_kernel_stat> acc;
+  for (int r = 0; r < reps && rc == CV_OK; ++r) {
+    pf.recs.clear();
+    rc = enqueue_bwd(h, alpha, beta, true, nullptr, nullptr, 0, s);
+    if (!rc) rc = enqueue_fwd(h, alpha, beta, h->g_alpha, h->g_beta, s);
+    if (!rc) rc = enqueue_bwd(h, alpha, beta, false, nullptr, nullptr, 0, s);
+    if (hipStreamSynchronize(s) != hipSuccess) rc = fail(CV_EDEVICE, "profile pass failed");
+    std::map<std::string, int> per_rep;
+    for (KStat& k : pf.recs) {
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, k.e0, k.e1);
+      (void)hipEventDestroy(k.e0);
+      (void)hipEventDestroy(k.e1);
+      if (!acc.count(k.name)) {
+        cv_kernel_stat z{};
+        std::snprintf(z.name, sizeof(z.name), "%s", k.name.c_str());
+        acc[k.name] = z;
+        order.push_back(k.name);
+      }
+      cv_kernel_stat& st = acc[k.name];
+      st.total_ms += ms;
+      if (r == 0) {
+        st.launches += 1;
+        st.flops += k.flops;
+        st.bytes += k.bytes;
+      }
+    }
+  }
+  h->prof = nullptr;
+  if (rc) return rc;
+  int n = 0;
+  for (const std::string& nm : order) {
+    if (n < max_out) out[n] = acc[nm];
+    ++n;
+  }
+  *n_out = n;
+  return CV_OK;
+}
+
+void cv_bound_destroy(cv_bound* h) {
+  if (!h) return;
+  drop_graph(h);
+  if (h->cap) (void)hipStreamDestroy(h->cap);
+  delete h;
+}
+
+int cv_bound_root_bounds(const cv_layer* layers, int32_t n_layers, int32_t n_props, const float* x_lo,
+                         const float* x_hi, float* l_out, float* u_out, void* stream) {
+  std::vector<int> dims;
+  int rc = check_layers(layers, n_layers, dims);
+  if (rc) return rc;
+  if (n_props <= 0 || !x_lo || !x_hi) return fail(CV_EINVAL, "bad arguments");
+  int nd = 0;
+  for (int i = 1; i < n_layers; ++i) nd += dims[i];
+  if (nd > 0 && (!l_out || !u_out)) return fail(CV_EINVAL, "null outputs");
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<float> lo((size_t)n_props * nd, 0.f), up((size_t)n_props * nd, 0.f);
+  std::vector<int32_t> prop(n_props);
+  std::vector<int64_t> sptr(n_props + 1, 0);
+  for (int p = 0; p < n_props; ++p) prop[p] = p;
+  int off = 0;
+  for (int i = 1; i < n_layers; ++i) {
+    // sub-network of layers 1..i with specification [I; -I] on layer i
+    const int d = dims[i];
+    std::vector<cv_layer> sub(layers, layers + i);
+    int ndp = off;  // bounds of layers 1..i-1
+    std::vector<float> lsub((size_t)n_props * std::max(1, ndp)), usub((size_t)n_props * std::max(1, ndp));
+    for (int p = 0; p < n_props; ++p)
+      for (int j = 0; j < ndp; ++j) {
+        lsub[(size_t)p * ndp + j] = lo[(size_t)p * nd + j];
+        usub[(size_t)p * ndp + j] = up[(size_t)p * nd + j];
+      }
+    cv_bound hb;
+    Spec sp;
+    sp.identity = true;
+    rc = build(&hb, sub.data(), i, n_props, x_lo, x_hi, 2 * d, sp, lsub.data(), usub.data(), n_props, prop.data(),
+               sptr.data(), nullptr, nullptr, nullptr, s);
+    if (rc) return rc;
+    float* dlb;
+    if ((rc = hb.mem.alloc(&dlb, (size_t)hb.R))) return rc;
+    if ((rc = enqueue_bwd(&hb, nullptr, nullptr, false, dlb, nullptr, 0, s))) return rc;
+    std::vector<float> lb(hb.R);
+    HIPCHK(hipMemcpyAsync(lb.data(), dlb, (size_t)hb.R * sizeof(float), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int p = 0; p < n_props; ++p)
+      for (int j = 0; j < d; ++j) {
+        lo[(size_t)p * nd + off + j] = lb[(size_t)p * 2 * d + j];
+        up[(size_t)p * nd + off + j] = -lb[(size_t)p * 2 * d + d + j];
+      }
+    drop_graph(&hb);
+    off += d;
+  }
+  for (size_t t = 0; t < lo.size(); ++t) {
+    l_out[t] = lo[t];
+    u_out[t] = up[t];
+  }
+  return CV_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,89 @@
+// Host-side interfaces between the ABI layer and the kernels of libcvbound.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace cvb {
+
+// Epilogue / prologue variants of the layer kernels.
+enum Mode {
+  kBwdRelax = 0,  // back-substitution, then the next ReLU layer's relaxation
+  kBwdConc = 1,   // back-substitution into the input, then box concretisation
+  kFwdX = 2,      // adjoint forward step from x* (first layer)
+  kFwd = 3        // adjoint forward step from zhat(i-1)
+};
+
+struct GemmCfg {
+  int bm, bn;
+};
+constexpr int kNumGemmCfgs = 6;
+extern const GemmCfg kGemmCfgs[kNumGemmCfgs];
+
+struct GemmArgs {
+  const float* A;
+  int lda;
+  const float* Bt;
+  int ldb;
+  int M, N, K;
+  int last;  // adjoint: do not write zhat (the top ReLU layer)
+  Batch bt;
+  Vars v;
+  Epi e;
+};
+void launch_gemm(int cfg, int mode, const GemmArgs& g, hipStream_t s);
+
+struct ConvGeom {
+  int ci, hi, wi, co, ho, wo, k, s, p;
+};
+struct ConvArgs {
+  const float* in;
+  int ldi;
+  const float* w;  // OIHW
+  ConvGeom g;
+  int M;
+  int last;
+  int uniform;  // stride-parity classes hold whole waves
+  Batch bt;
+  Vars v;
+  Epi e;
+};
+bool conv_channels_supported(int c);
+size_t convt_smem_bytes(const ConvGeom& g, int w64, bool conc);
+size_t conv_smem_bytes(const ConvGeom& g);
+int launch_convt_bwd(int mode, const ConvArgs& a, hipStream_t s);
+int launch_conv_fwd(int mode, const ConvArgs& a, hipStream_t s);
+
+// misc.hip
+void launch_prep_chord(const float* l, const float* u, float2* chord, float* adef, int64_t n, hipStream_t s);
+void launch_status_fill(uint16_t* status, const uint16_t* root_kind, const int* prop, int B, int nd,
+                        hipStream_t s);
+void launch_status_split(uint16_t* status, const int* split_dom, const int64_t* sptr, const int* split_col,
+                         const int8_t* side, int64_t nnz, int nd, hipStream_t s);
+void launch_spec_merge(const float* C, const float* W, int ldw, const float* b, int P, int m, int dL, int dprev,
+                       float* CW, int ldcw, float* Cb, hipStream_t s);
+void launch_spec_identity(const float* Wdense, int ldw, const float* wconv, const ConvGeom* g,
+                          const float* bias_full, int d, int dprev, float* CW, int ldcw, float* Cb, hipStream_t s);
+struct TopArgs {
+  const float* CW;
+  int64_t cw_pstride;  // floats between properties (0: shared by all)
+  int ldcw;
+  const float* Cb;
+  int64_t cb_pstride;
+  int n;       // width of layer L-1
+  int conc;    // 1 when there is no ReLU layer: concretise directly
+  Batch bt;
+  Vars v;
+  Epi e;
+};
+void launch_top(const TopArgs& a, hipStream_t s);
+void launch_finalize(const float* part, int n_slots, int n_used, int n_rows, float* lb, float* best, int first,
+                     hipStream_t s);
+void launch_adam(float* x, const float* g, float* m1, float* m2, int64_t n, float lr, float bc1, float bc2,
+                 float lo, float hi, hipStream_t s);
+void launch_fill(float* p, float v, int64_t n, hipStream_t s);
+void launch_alpha_default(float* alpha, const int* ulist, const int64_t* uoff, const Batch& bt, hipStream_t s);
+
+}  // namespace cvb

@@ -1,0 +1,194 @@
+// Small kernels of libcvbound: set-up (relaxation chords, subdomain status,
+// specification merge), the top ReLU layer, bound assembly and projected Adam.
+#include "common.h"
+#include "internal.h"
+
+namespace cvb {
+
+namespace {
+
+__global__ void prep_chord_k(const float* __restrict__ l, const float* __restrict__ u, float2* chord, float* adef,
+                             int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float lo = l[i], up = u[i];
+  float2 c = make_float2(0.f, 0.f);
+  if (lo < 0.f && up > 0.f) {
+    // upper chord of ReLU on [l, u]: zhat <= u/(u-l) (z - l)  (Lemma 2.1)
+    const float den = up - lo;
+    c.x = up / den;
+    c.y = -up * lo / den;
+  }
+  chord[i] = c;
+  adef[i] = (up >= -lo) ? 1.f : 0.f;  // CROWN's adaptive lower slope
+}
+
+__global__ void status_fill_k(uint16_t* status, const uint16_t* __restrict__ root_kind, const int* __restrict__ prop,
+                              int B, int nd) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)B * nd) return;
+  const int b = (int)(i / nd);
+  const int j = (int)(i - (int64_t)b * nd);
+  status[i] = root_kind[(int64_t)prop[b] * nd + j];
+}
+
+__global__ void status_split_k(uint16_t* status, const int* __restrict__ split_dom, const int64_t* __restrict__ sptr,
+                               const int* __restrict__ split_col, const int8_t* __restrict__ side, int64_t nnz,
+                               int nd) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nnz) return;
+  const int b = split_dom[s];
+  const uint16_t slot = (uint16_t)(s - sptr[b]);
+  status[(int64_t)b * nd + split_col[s]] = kSplit | (side[s] > 0 ? kSidePos : 0) | slot;
+}
+
+// A(L-1) = C_p W(L) and c = C_p b(L) for every property and spec row
+// (the specification merged into the last layer, Sec. 2.1).
+__global__ void spec_merge_k(const float* __restrict__ C, const float* __restrict__ W, int ldw,
+                             const float* __restrict__ b, int m, int dL, int dprev, float* CW, int ldcw, float* Cb) {
+  const int pk = blockIdx.x;  // p * m + k
+  const float* c = C + (int64_t)pk * dL;
+  for (int j = threadIdx.x; j < dprev; j += blockDim.x) {
+    float s = 0.f;
+    for (int o = 0; o < dL; ++o) s = fmaf(c[o], W[(int64_t)o * ldw + j], s);
+    CW[(int64_t)pk * ldcw + j] = s;
+  }
+  if (threadIdx.x == 0) {
+    float s = 0.f;
+    for (int o = 0; o < dL; ++o) s = fmaf(c[o], b[o], s);
+    Cb[pk] = s;
+  }
+}
+
+// Specification [I; -I] on layer i (row k < d: +e_k, else -e_{k-d}): A = +-W(i) row.
+__global__ void spec_identity_k(const float* __restrict__ Wd, int ldw, const float* __restrict__ wc, ConvGeom g,
+                                int use_conv, const float* __restrict__ bias_full, int d, int dprev, float* CW,
+                                int ldcw, float* Cb) {
+  const int k = blockIdx.x;
+  const int o = k < d ? k : k - d;
+  const float sg = k < d ? 1.f : -1.f;
+  float* out = CW + (int64_t)k * ldcw;
+  if (!use_conv) {
+    for (int j = threadIdx.x; j < dprev; j += blockDim.x) out[j] = sg * Wd[(int64_t)o * ldw + j];
+  } else {
+    const int pos = g.ho * g.wo;
+    const int co = o / pos, q = o - co * pos;
+    const int oy = q / g.wo, ox = q - oy * g.wo;
+    for (int j = threadIdx.x; j < dprev; j += blockDim.x) {
+      const int ci = j / (g.hi * g.wi), r = j - ci * g.hi * g.wi;
+      const int iy = r / g.wi, ix = r - iy * g.wi;
+      const int ky = iy - oy * g.s + g.p, kx = ix - ox * g.s + g.p;
+      float val = 0.f;
+      if (ky >= 0 && ky < g.k && kx >= 0 && kx < g.k) val = wc[(((int64_t)co * g.ci + ci) * g.k + ky) * g.k + kx];
+      out[j] = sg * val;
+    }
+  }
+  if (threadIdx.x == 0) Cb[k] = sg * bias_full[o];
+}
+
+// The top ReLU layer: relax A(L-1) = C_p W(L) row by row (or concretise it
+// directly when the network has no ReLU layer).  One wave per row.
+__global__ __launch_bounds__(256) void top_k(TopArgs a) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= a.bt.n_rows) return;
+  const RowInfo ri = row_info(a.bt, row);
+  const float* cw = a.CW + ri.p * a.cw_pstride + (int64_t)ri.k * a.ldcw;
+  float cst = 0.f;
+  for (int j = lane; j < a.n; j += 64) {
+    const float v = cw[j];
+    if (a.conc) {
+      const int64_t pb = (int64_t)ri.p * a.bt.d0 + j;
+      cst += conc_term(v, a.bt.xlo[pb], a.bt.xhi[pb]);
+    } else {
+      a.e.out[(int64_t)row * a.e.ldo + j] = relax_bwd(a.bt, a.v, ri, a.e.layer_off, j, v, a.e.bias[j], &cst);
+    }
+  }
+  cst = wave_sum(cst);
+  if (lane == 0) a.e.part[(int64_t)row * a.e.n_slots + a.e.slot0] = cst + a.Cb[ri.p * a.cb_pstride + ri.k];
+}
+
+// lb = sum of the partial constants of a row, in slot order (deterministic).
+__global__ void finalize_k(const float* __restrict__ part, int n_slots, int n_used, int n_rows, float* lb,
+                           float* best, int first) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_rows) return;
+  const float* p = part + (int64_t)r * n_slots;
+  float s = 0.f;
+  for (int t = 0; t < n_used; ++t) s += p[t];
+  if (lb) lb[r] = s;
+  if (best) best[r] = first ? s : fmaxf(best[r], s);
+}
+
+// Projected Adam ascent step (Kingma & Ba, beta1 0.9, beta2 0.999, eps 1e-8).
+__global__ void adam_k(float* x, const float* __restrict__ g, float* m1, float* m2, int64_t n, float lr, float bc1,
+                       float bc2, float lo, float hi) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float a = 0.9f * m1[i] + 0.1f * gi;
+  const float b = 0.999f * m2[i] + 0.001f * gi * gi;
+  m1[i] = a;
+  m2[i] = b;
+  const float step = lr * (a / bc1) / (sqrtf(b / bc2) + 1e-8f);
+  x[i] = fminf(fmaxf(x[i] + step, lo), hi);
+}
+
+__global__ void fill_k(float* p, float v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// alpha <- default slope of each entry's neuron; one block per row.  ulist
+// holds each property's unstable neurons (nd-axis index), uoff its offsets.
+__global__ void alpha_default_k(float* alpha, const int* __restrict__ ulist, const int64_t* __restrict__ uoff,
+                                Batch bt) {
+  const int row = blockIdx.x;
+  const RowInfo ri = row_info(bt, row);
+  const int U = bt.ucount[ri.p];
+  const int* src = ulist + uoff[ri.p];
+  const float* ad = bt.adef + (int64_t)ri.p * bt.nd;
+  for (int t = threadIdx.x; t < U; t += blockDim.x) alpha[ri.abase + t] = ad[src[t]];
+}
+
+inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+void launch_prep_chord(const float* l, const float* u, float2* chord, float* adef, int64_t n, hipStream_t s) {
+  if (n > 0) prep_chord_k<<<nblk(n, 256), 256, 0, s>>>(l, u, chord, adef, n);
+}
+void launch_status_fill(uint16_t* status, const uint16_t* root_kind, const int* prop, int B, int nd, hipStream_t s) {
+  const int64_t n = (int64_t)B * nd;
+  if (n > 0) status_fill_k<<<nblk(n, 256), 256, 0, s>>>(status, root_kind, prop, B, nd);
+}
+void launch_status_split(uint16_t* status, const int* split_dom, const int64_t* sptr, const int* split_col,
+                         const int8_t* side, int64_t nnz, int nd, hipStream_t s) {
+  if (nnz > 0) status_split_k<<<nblk(nnz, 256), 256, 0, s>>>(status, split_dom, sptr, split_col, side, nnz, nd);
+}
+void launch_spec_merge(const float* C, const float* W, int ldw, const float* b, int P, int m, int dL, int dprev,
+                       float* CW, int ldcw, float* Cb, hipStream_t s) {
+  spec_merge_k<<<P * m, 256, 0, s>>>(C, W, ldw, b, m, dL, dprev, CW, ldcw, Cb);
+}
+void launch_spec_identity(const float* Wdense, int ldw, const float* wconv, const ConvGeom* g, const float* bias_full,
+                          int d, int dprev, float* CW, int ldcw, float* Cb, hipStream_t s) {
+  ConvGeom gg = g ? *g : ConvGeom{};
+  spec_identity_k<<<2 * d, 256, 0, s>>>(Wdense, ldw, wconv, gg, g ? 1 : 0, bias_full, d, dprev, CW, ldcw, Cb);
+}
+void launch_top(const TopArgs& a, hipStream_t s) { top_k<<<nblk(a.bt.n_rows, 4), 256, 0, s>>>(a); }
+void launch_finalize(const float* part, int n_slots, int n_used, int n_rows, float* lb, float* best, int first,
+                     hipStream_t s) {
+  finalize_k<<<nblk(n_rows, 256), 256, 0, s>>>(part, n_slots, n_used, n_rows, lb, best, first);
+}
+void launch_adam(float* x, const float* g, float* m1, float* m2, int64_t n, float lr, float bc1, float bc2, float lo,
+                 float hi, hipStream_t s) {
+  if (n > 0) adam_k<<<nblk(n, 256), 256, 0, s>>>(x, g, m1, m2, n, lr, bc1, bc2, lo, hi);
+}
+void launch_fill(float* p, float v, int64_t n, hipStream_t s) {
+  if (n > 0) fill_k<<<nblk(n, 256), 256, 0, s>>>(p, v, n);
+}
+void launch_alpha_default(float* alpha, const int* ulist, const int64_t* uoff, const Batch& bt, hipStream_t s) {
+  if (bt.n_rows > 0) alpha_default_k<<<bt.n_rows, 256, 0, s>>>(alpha, ulist, uoff, bt);
+}
+
+}  // namespace cvb

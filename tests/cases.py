@@ -1,0 +1,53 @@
+"""Seeded parity cases: synthetic workloads with oracle root bounds.
+
+Inputs come from the generator; intermediate bounds come from the FP64
+oracle, rounded outward to float32, and are fed to both the oracle and the
+library so both see the same unstable sets.
+"""
+from __future__ import annotations
+
+import functools
+
+import numpy as np
+
+from oracle import batch as ob
+from oracle import beta_crown as bc
+from paper_2103_06624_amd import synth
+
+# reduced sizes: several row tiles and a ragged tail, oracle in seconds
+SMALL = {
+    "mlp_small": dict(),
+    "mlp_deep": dict(n_dom=48),
+    "cnn_base": dict(n_dom=24),
+    "cnn_wide": dict(n_props=2, n_dom=22),
+    "cnn_deep": dict(n_props=3, n_dom=21),
+}
+
+
+@functools.lru_cache(maxsize=None)
+def case(name, n_props=None, n_dom=None):
+    wl = synth.make(name, n_props=n_props, n_dom=n_dom)
+    net64 = bc.dense_net(wl.net.layers)
+    lo64, up64 = ob.root_bounds_all(net64, wl.x_lo, wl.x_hi)
+    lo, up = bc.outward_f32(lo64, up64)
+    sp = synth.attach_splits(wl, lo, up)
+    orc = ob.OracleProblem(wl.net.layers, wl.x_lo, wl.x_hi, wl.C, lo, up, sp.dom_prop, sp.split_ptr, sp.layer,
+                           sp.neuron, sp.side, net64=net64)
+    return wl, lo, up, lo64, up64, orc
+
+
+def small_case(name):
+    return case(name, **SMALL[name])
+
+
+def random_vars(orc, seed, beta_hi=0.5):
+    rng = np.random.default_rng(seed)
+    alpha = rng.uniform(0, 1, size=orc.n_alpha).astype(np.float32)
+    beta = rng.uniform(0, beta_hi, size=orc.nnz * orc.m).astype(np.float32)
+    return alpha, beta
+
+
+def guarded_rel(a, ref):
+    a = np.asarray(a, np.float64)
+    ref = np.asarray(ref, np.float64)
+    return np.abs(a - ref) / np.maximum(np.abs(ref), 1.0)
