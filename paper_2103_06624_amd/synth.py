@@ -106,7 +106,7 @@ class Workload:
     C: np.ndarray  # float32 [P, m, dL]
     n_dom_per_prop: np.ndarray  # int64 [P]
     depth_range: tuple
-    split_rng: np.random.Generator
+    split_seed: int
     splits: Optional[Splits] = None
 
     @property
@@ -238,40 +238,49 @@ def margin_spec(y: int, n_cls: int) -> np.ndarray:
 # split sets
 
 
-def sample_splits(rng: np.random.Generator, dims: Sequence[int], lo_root, up_root, dom_prop: np.ndarray,
+def sample_splits(seed: int, dims: Sequence[int], lo_root, up_root, dom_prop: np.ndarray,
                   depth_range: tuple) -> Splits:
     """Draw split sets given per-property root bounds.
 
     lo_root / up_root: float arrays [P, sum(d_1..d_{L-1})] (ReLU layers only,
-    layer-major).  A neuron is root-unstable when lo < 0 < up.
+    layer-major).  A neuron is root-unstable when lo < 0 < up.  Subdomain b
+    draws from its own stream (seed, b): a depth, then one key and one side
+    per neuron; it splits the `depth` root-unstable neurons with the smallest
+    keys.  A neuron whose stability differs between two sets of root bounds
+    therefore only changes the subdomains that would have picked it.
     """
     relu_dims = list(dims[1:-1])
+    nd = int(sum(relu_dims))
     offs = np.concatenate([[0], np.cumsum(relu_dims)])
     ptr = [0]
     lay, neu, side = [], [], []
+    unstable = [np.nonzero((lo_root[p] < 0) & (up_root[p] > 0))[0] for p in range(lo_root.shape[0])]
     for b in range(dom_prop.shape[0]):
-        p = int(dom_prop[b])
-        unst = np.nonzero((lo_root[p] < 0) & (up_root[p] > 0))[0]
+        rng = np.random.default_rng([seed, b])
         depth = int(rng.integers(depth_range[0], depth_range[1] + 1))
+        keys = rng.random(nd)
+        sides = rng.integers(0, 2, size=nd) * 2 - 1
+        unst = unstable[int(dom_prop[b])]
         depth = min(depth, unst.shape[0])
-        pick = np.sort(rng.choice(unst, size=depth, replace=False)) if depth > 0 else np.zeros(0, np.int64)
-        sides = rng.integers(0, 2, size=depth) * 2 - 1
-        for flat, sd in zip(pick, sides):
+        pick = np.sort(unst[np.argsort(keys[unst], kind="stable")[:depth]])
+        for flat in pick:
             i = int(np.searchsorted(offs, flat, side="right"))  # 1-based layer
             lay.append(i)
             neu.append(int(flat - offs[i - 1]))
-            side.append(int(sd))
+            side.append(int(sides[flat]))
         ptr.append(len(lay))
     return Splits(dom_prop.astype(np.int32), np.asarray(ptr, np.int64), np.asarray(lay, np.int32),
                   np.asarray(neu, np.int32), np.asarray(side, np.int8))
 
 
 def attach_splits(wl: Workload, lo_root, up_root) -> Splits:
-    """Draw the workload's subdomains (random order across properties)."""
-    rng = wl.split_rng
+    """Draw the workload's subdomains (random order across properties).
+
+    Deterministic for a workload: repeated calls give the same subdomains."""
+    rng = np.random.default_rng(wl.split_seed)
     dom_prop = np.repeat(np.arange(wl.n_props, dtype=np.int32), wl.n_dom_per_prop)
     rng.shuffle(dom_prop)
-    wl.splits = sample_splits(rng, wl.net.dims, lo_root, up_root, dom_prop, wl.depth_range)
+    wl.splits = sample_splits(wl.split_seed, wl.net.dims, lo_root, up_root, dom_prop, wl.depth_range)
     return wl.splits
 
 
@@ -353,7 +362,8 @@ def make(name: str, n_props: Optional[int] = None, n_dom: Optional[int] = None) 
         counts = np.asarray((per * P)[:P] if n_props is not None else per, np.int64)
     if n_dom is not None:
         counts = np.maximum(1, np.round(counts * n_dom / counts.sum())).astype(np.int64)
-    return Workload(name, net, lo, hi, x0, float(eps), C, counts, depth, sr)
+    split_seed = int(sr.integers(0, 2**31 - 1))
+    return Workload(name, net, lo, hi, x0, float(eps), C, counts, depth, split_seed)
 
 
 WORKLOADS = ("mlp_small", "mlp_deep", "cnn_base", "cnn_wide", "cnn_deep")
