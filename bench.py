@@ -127,6 +127,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--plan", default=None, help="chain rows bwd,fwd (e.g. 16,16 or 0,0); overrides the autotuner")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -152,6 +153,9 @@ def main():
     B, m = pb.B, pb.m
     if not args.no_autotune:
         pb.autotune()
+    if args.plan:
+        cb, cf = (int(x) for x in args.plan.split(","))
+        pb.set_plan(cb, cf)
     a0 = pb.alpha_init()
     b0 = pb.zeros_beta()
     alpha, beta = a0.clone(), b0.clone()

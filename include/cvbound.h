@@ -94,10 +94,13 @@ int cv_bound_root_bounds(const cv_layer *layers, int32_t n_layers, int32_t n_pro
  *     i.e. Z-, S = +1), each host [nnz] (Eq. S).
  * CV_ESPLIT when a split names a layer or neuron out of range, a neuron that
  * is not root-unstable for its property, the same neuron twice in one
- * subdomain, a side other than +-1, or more than 8191 splits in one
- * subdomain.  CV_ESHAPE when shapes do not chain, the last layer is a
- * convolution, or a convolution has an output plane with a multiple-of-64
- * count of positions violated (H*W % 64 != 0), or stride > 2.
+ * subdomain, a side other than +-1, or when nnz reaches 2^29.  CV_ESHAPE when
+ * shapes do not chain, the last layer is a convolution, or a convolution has
+ * a stride other than 1 or 2 (dividing its input plane), an input or output
+ * plane whose position count H*W is not a multiple of 64, a channel count
+ * outside {1, 2, 3, 4, 8, 16, 32}, or rows too large for the on-chip tiles.
+ * CV_EINVAL for non-finite inputs, x_lo > x_hi or a property index out of
+ * range.  Validation happens before any device call.
  * Synchronous; copies everything it needs to the device. */
 int cv_bound_init(cv_bound **out, const cv_layer *layers, int32_t n_layers,
                   int32_t n_props, const float *x_lo, const float *x_hi,
@@ -151,6 +154,15 @@ int cv_bound_optimize(cv_bound *h, int32_t iters, float lr_alpha, float lr_beta,
  * Synchronous.  Results do not depend on the choice beyond float32 rounding
  * of the summation order. */
 int cv_bound_autotune(cv_bound *h, void *stream);
+
+/* Execution plan of the dense layers at the top of the network: rows per
+ * workgroup of the fused chain kernels for the back-substitution (chain_bwd)
+ * and the adjoint (chain_fwd): 16 or 32, or 0 for one kernel per layer.
+ * cv_bound_init picks a default and cv_bound_autotune a measured choice; this
+ * call overrides both.  CV_EINVAL when a chain is requested where the network
+ * has none (its dense tail is missing or too wide for the on-chip tiles).
+ * Results agree across plans up to float32 summation order. */
+int cv_bound_set_plan(cv_bound *h, int32_t chain_bwd, int32_t chain_fwd);
 
 /* Per-kernel timing of one gradient pass plus one plain evaluation, each
  * kernel launch bracketed by HIP events on `stream`, repeated `reps` times.

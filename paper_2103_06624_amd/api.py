@@ -152,6 +152,10 @@ class BoundProblem:
     def autotune(self):
         B.check(B.cv_bound_autotune(self.h, _stream()))
 
+    def set_plan(self, chain_bwd, chain_fwd):
+        """Rows per workgroup of the fused dense chains (0: one kernel per layer)."""
+        B.check(B.cv_bound_set_plan(self.h, chain_bwd, chain_fwd))
+
     def profile(self, alpha, beta, reps=5):
         out = (B.cv_kernel_stat * 64)()
         n = ctypes.c_int32()

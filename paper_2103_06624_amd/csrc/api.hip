@@ -41,6 +41,8 @@ int fail(int code, const char* fmt, ...) {
   } while (0)
 
 inline int r4(int d) { return (d + 3) & ~3; }
+inline int r16(int d) { return (d + 15) & ~15; }
+inline int r32(int d) { return (d + 31) & ~31; }
 
 // ---------------------------------------------------------------------------
 // device memory owned by a handle
@@ -149,6 +151,11 @@ struct cv_bound {
   // tile choice per ReLU-layer kernel: [0..L-1] back-substitution of layer i+1,
   // [L..2L-1] adjoint forward of layer i+1
   std::vector<int> cfg;
+  // runs of dense layers fused by the chain kernels: the back-substitution
+  // chain covers layers L-1 .. chain_lo (with the top ReLU layer), the adjoint
+  // chain layers chain_lo .. L-1; 0 rows per tile = per-layer kernels
+  int chain_lo = 0;
+  int chain_bT = 0, chain_fT = 0;
   // optimisation graph
   hipStream_t cap = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -175,6 +182,17 @@ int cfg_for(const cv_bound* h, int mode, int M, int N, int K, int fallback) {
   (void)h;
 }
 
+int chain_ldk(int kmax) { return ((kmax + 31) & ~31) + 4; }
+
+// LDS stride of a handle's chain: the widest LDS-resident operand
+int chain_ldk_of(const cv_bound* h) {
+  int kmax = 4;
+  for (int i = h->chain_lo; i <= h->L - 1; ++i) kmax = std::max(kmax, h->dims[i]);
+  return chain_ldk(kmax);
+}
+
+bool chain_fits(const cv_bound* h, int T) { return chain_smem_bytes(T, chain_ldk_of(h)) <= 65536; }
+
 // ---------------------------------------------------------------------------
 // validation
 
@@ -198,7 +216,7 @@ int check_layers(const cv_layer* layers, int n, std::vector<int>& dims, bool all
         return fail(CV_ESHAPE, "layer %d: stride must be 1 or 2 and divide the input plane", i + 1);
       if ((ly.in_h * ly.in_w) % 64 || (ly.out_h * ly.out_w) % 64)
         return fail(CV_ESHAPE, "layer %d: conv planes must hold a multiple of 64 positions", i + 1);
-      if (!conv_channels_supported(ly.in_c) || !(conv_channels_supported(ly.out_c) || ly.out_c == 64))
+      if (!conv_channels_supported(ly.in_c) || !conv_channels_supported(ly.out_c))
         return fail(CV_ESHAPE, "layer %d: unsupported channel count", i + 1);
       if (i == n - 1 && !allow_conv_last) return fail(CV_ESHAPE, "the last layer must be dense");
     } else if (ly.type != CV_LAYER_DENSE) {
@@ -229,9 +247,12 @@ int upload_layers(cv_bound* h, const cv_layer* layers, int n, hipStream_t s) {
     d.g = ConvGeom{ly.in_c, ly.in_h, ly.in_w, ly.out_c, ly.out_h, ly.out_w, ly.kernel, ly.stride, ly.pad};
     std::vector<float> bias_full(d.dout);
     if (ly.type == CV_LAYER_DENSE) {
-      d.ld_in = r4(d.din);
-      d.ld_out = r4(d.dout);
-      std::vector<float> W((size_t)d.dout * d.ld_in, 0.f), Wt((size_t)d.din * d.ld_out, 0.f);
+      // zero padding: rows to multiples of 16 and the K (contiguous) axis to
+      // multiples of 32, so MFMA tiles read whole blocks (and k-chunk pairs)
+      // without masks
+      d.ld_in = r32(d.din);
+      d.ld_out = r32(d.dout);
+      std::vector<float> W((size_t)r16(d.dout) * d.ld_in, 0.f), Wt((size_t)r16(d.din) * d.ld_out, 0.f);
       for (int o = 0; o < d.dout; ++o)
         for (int j = 0; j < d.din; ++j) {
           const float w = ly.weight[(size_t)o * d.din + j];
@@ -301,7 +322,7 @@ int build(cv_bound* h, const cv_layer* layers, int n_layers, int P, const float*
   if (spec.C && !finite_all(spec.C, (int64_t)P * m * h->dims[n_layers])) return fail(CV_EINVAL, "non-finite C");
 
   // ---- per-property neuron classes (Eq. definition_D: l >= 0 active, u <= 0 inactive)
-  std::vector<uint16_t> kind((size_t)P * nd);
+  std::vector<uint32_t> kind((size_t)P * nd);
   h->h_cidx.assign((size_t)P * nd, -1);
   h->h_ucount.assign(P, 0);
   std::vector<int> ulist;
@@ -311,14 +332,15 @@ int build(cv_bound* h, const cv_layer* layers, int n_layers, int P, const float*
     uoff[p] = (int64_t)ulist.size();
     for (int j = 0; j < nd; ++j) {
       const float lo = l[(size_t)p * nd + j], up = u[(size_t)p * nd + j];
-      uint16_t k = lo >= 0.f ? kActive : (up <= 0.f ? kInactive : kUnstable);
-      kind[(size_t)p * nd + j] = k;
+      uint32_t k = lo >= 0.f ? kActive : (up <= 0.f ? kInactive : kUnstable);
       if (k == kUnstable) {
+        k |= (uint32_t)h->h_ucount[p];  // index in the property's unstable list
         h->h_cidx[(size_t)p * nd + j] = h->h_ucount[p]++;
         ulist.push_back(j);
         int li = (int)(std::upper_bound(h->offs.begin(), h->offs.begin() + (n_layers - 1), j) - h->offs.begin()) - 1;
         ucount_layer[p][li]++;
       }
+      kind[(size_t)p * nd + j] = k;
     }
   }
   uoff[P] = (int64_t)ulist.size();
@@ -338,7 +360,7 @@ int build(cv_bound* h, const cv_layer* layers, int n_layers, int P, const float*
     for (int li = 0; li + 1 < n_layers; ++li) h->unst_rows_per_layer[li] += (double)m * ucount_layer[p][li];
     const int64_t s0 = split_ptr[b], s1 = split_ptr[b + 1];
     if (s1 < s0) return fail(CV_ESPLIT, "subdomain %d: split_ptr decreases", b);
-    if (s1 - s0 > kMaxDepth) return fail(CV_ESPLIT, "subdomain %d: more than %d splits", b, kMaxDepth);
+    if (s1 >= kMaxSplits) return fail(CV_ESPLIT, "more than %lld splits in total", (long long)kMaxSplits - 1);
     for (int64_t t = s0; t < s1; ++t) {
       const int ly = split_layer[t], nr = split_neuron[t];
       if (ly < 1 || ly >= n_layers) return fail(CV_ESPLIT, "split %lld: layer %d out of range", (long long)t, ly);
@@ -346,7 +368,7 @@ int build(cv_bound* h, const cv_layer* layers, int n_layers, int P, const float*
       if (split_side[t] != 1 && split_side[t] != -1)
         return fail(CV_ESPLIT, "split %lld: side must be +1 or -1", (long long)t);
       const int col = h->offs[ly - 1] + nr;
-      if (kind[(size_t)p * nd + col] != kUnstable)
+      if ((kind[(size_t)p * nd + col] & kKindMask) != kUnstable)
         return fail(CV_ESPLIT, "split %lld: neuron (%d,%d) is not root-unstable", (long long)t, ly, nr);
       if (seen[col] == b) return fail(CV_ESPLIT, "subdomain %d splits neuron (%d,%d) twice", b, ly, nr);
       seen[col] = b;
@@ -362,7 +384,7 @@ int build(cv_bound* h, const cv_layer* layers, int n_layers, int P, const float*
   DevMem& M = h->mem;
   int *d_prop, *d_ucount, *d_cidx, *d_split_dom, *d_split_col;
   int64_t *d_aoff, *d_sptr;
-  uint16_t *d_kind, *d_status;
+  uint32_t *d_kind, *d_status;
   int8_t* d_side;
   float *d_l, *d_u, *d_xlo, *d_xhi, *d_adef;
   float2* d_chord;
@@ -381,7 +403,7 @@ int build(cv_bound* h, const cv_layer* layers, int n_layers, int P, const float*
     return rc;
   launch_prep_chord(d_l, d_u, d_chord, d_adef, (int64_t)P * nd, s);
   launch_status_fill(d_status, d_kind, d_prop, B, nd, s);
-  launch_status_split(d_status, d_split_dom, d_sptr, d_split_col, d_side, h->nnz, nd, s);
+  launch_status_split(d_status, d_split_dom, d_split_col, d_side, h->nnz, nd, s);
   HIPCHK(hipGetLastError());
 
   Batch& bt = h->bt;
@@ -393,7 +415,6 @@ int build(cv_bound* h, const cv_layer* layers, int n_layers, int P, const float*
   bt.prop = d_prop;
   bt.aoff = d_aoff;
   bt.ucount = d_ucount;
-  bt.sptr = d_sptr;
   bt.status = d_status;
   bt.cidx = d_cidx;
   bt.chord = d_chord;
@@ -447,6 +468,25 @@ int build(cv_bound* h, const cv_layer* layers, int n_layers, int P, const float*
     h->cfg[i - 1] = cfg_for(h, i - 1 >= 1 ? kBwdRelax : kBwdConc, h->R, N_b, K_b, gemm_default_cfg(h->R, N_b));
     h->cfg[n_layers + i - 1] = cfg_for(h, i == 1 ? kFwdX : kFwd, h->R, K_b, N_b, gemm_default_cfg(h->R, K_b));
   }
+  // dense layers fused by the chain kernels (widths must fit two LDS tiles)
+  h->chain_lo = 0;
+  h->chain_bT = h->chain_fT = 0;
+  auto chain_ok = [&](int i) {  // layer i dense with a K-dim (d_i) that fits
+    return i >= 1 && h->layers[i - 1].type == CV_LAYER_DENSE && h->dims[i] % 4 == 0 &&
+           chain_smem_bytes(16, chain_ldk(h->dims[i])) <= 65536;
+  };
+  if (n_layers >= 2 && chain_ok(n_layers - 1)) {
+    int lo = n_layers - 1;
+    while (lo - 1 >= 1 && chain_ok(lo - 1) && h->layers[lo - 2].type == CV_LAYER_DENSE && (n_layers - lo) < kChainMax)
+      --lo;
+    // the first adjoint step reads x* (lo = 1) or the conv output with float4 loads
+    if (h->dims[lo - 1] % 4 == 0) {
+      h->chain_lo = lo;
+      const int T = chain_fits(h, 32) ? 32 : 16;
+      h->chain_bT = T;
+      h->chain_fT = lo + 1 <= n_layers - 1 ? T : 0;
+    }
+  }
   // conv kernels' LDS needs
   for (int i = 0; i + 1 < n_layers; ++i) {
     const DevLayer& ly = h->layers[i];
@@ -482,7 +522,8 @@ int ensure_opt(cv_bound* h) {
 // passes
 
 std::string cfg_name(int cfg) {
-  return std::to_string(kGemmCfgs[cfg].bm) + "x" + std::to_string(kGemmCfgs[cfg].bn);
+  return std::to_string(kGemmCfgs[cfg].bm) + "x" + std::to_string(kGemmCfgs[cfg].bn) + "x" +
+         std::to_string(kGemmCfgs[cfg].bk);
 }
 
 Epi make_epi(const cv_bound* h) {
@@ -509,6 +550,17 @@ double conv_macs(const ConvGeom& g) {
   return taps * g.ci * g.co;
 }
 
+struct AdamStep {
+  float lr_a, lr_b, bc1, bc2;
+  float *ma, *va, *mb, *vb;
+};
+
+double chain_flops(const cv_bound* h) {
+  double f = 0;
+  for (int i = h->chain_lo; i <= h->L - 1; ++i) f += 2.0 * h->R * h->dims[i] * h->dims[i - 1];
+  return f;
+}
+
 // Back-substitution of every layer plus concretisation; lb / best per row.
 int enqueue_bwd(cv_bound* h, const float* alpha, const float* beta, bool grad, float* lb, float* best, int first,
                 hipStream_t s) {
@@ -521,7 +573,49 @@ int enqueue_bwd(cv_bound* h, const float* alpha, const float* beta, bool grad, f
   v.xneg = grad ? h->xneg : nullptr;
   Profiler* pf = h->prof;
   if (h->R == 0) return CV_OK;
-  {
+  int cur = 0, slot = 1, i_next = L - 1;
+  if (h->chain_bT) {
+    const int lo = h->chain_lo;
+    ChainArgs ca{};
+    ca.nl = L - lo;
+    for (int i = L - 1, t = 0; i >= lo; --i, ++t) {
+      const DevLayer& ly = h->layers[i - 1];
+      ca.ly[t] = ChainLayer{ly.Wt, ly.ld_out, h->dims[i], h->dims[i - 1], i - 1 >= 1 ? h->layers[i - 2].bias : nullptr,
+                            i - 1 >= 1 ? h->offs[i - 2] : 0};
+    }
+    ca.ldk = chain_ldk_of(h);
+    ca.CW = h->CW;
+    ca.cw_pstride = h->cw_pstride;
+    ca.ldcw = h->ldcw;
+    ca.Cb = h->Cb;
+    ca.cb_pstride = h->cb_pstride;
+    ca.n_top = h->dims[L - 1];
+    ca.top_off = h->offs[L - 2];
+    ca.top_bias = h->layers[L - 2].bias;
+    ca.conc = lo == 1;
+    ca.out = h->act[0];
+    ca.ldo = h->ldact;
+    ca.part = h->part;
+    ca.n_slots = h->n_slots;
+    ca.slot = 0;
+    ca.lb = lb;
+    ca.best = best;
+    ca.first = first;
+    ca.final = lo == 1;
+    ca.bt = h->bt;
+    ca.v = v;
+    const double rows = h->R;
+    if (pf) pf->begin("chain_bwd_T" + std::to_string(h->chain_bT), chain_flops(h),
+                      rows * h->dims[L - 1] * 4.0 + (lo == 1 ? rows * h->d0 / 4.0 : rows * h->dims[lo - 1] * 4.0) +
+                          (double)h->B * (h->nd - (lo >= 2 ? h->offs[lo - 2] : 0)) * 2.0);
+    launch_chain_bwd(h->chain_bT, ca, s);
+    if (pf) pf->end();
+    if (lo == 1) {
+      HIPCHK(hipGetLastError());
+      return CV_OK;
+    }
+    i_next = lo - 1;
+  } else {
     TopArgs ta{};
     ta.CW = h->CW;
     ta.cw_pstride = h->cw_pstride;
@@ -543,8 +637,7 @@ int enqueue_bwd(cv_bound* h, const float* alpha, const float* beta, bool grad, f
     launch_top(ta, s);
     if (pf) pf->end();
   }
-  int cur = 0, slot = 1;
-  for (int i = L - 1; i >= 1; --i) {
+  for (int i = i_next; i >= 1; --i) {
     const DevLayer& ly = h->layers[i - 1];
     const int mode = i - 1 >= 1 ? kBwdRelax : kBwdConc;
     Epi e = make_epi(h);
@@ -587,8 +680,10 @@ int enqueue_bwd(cv_bound* h, const float* alpha, const float* beta, bool grad, f
 }
 
 // Adjoint forward sweep: zbar(i) = W(i) zhat(i-1) + b(i) from zhat(0) = x*,
-// gradients of alpha and beta in the epilogues.
-int enqueue_fwd(cv_bound* h, const float* alpha, const float* beta, float* ga, float* gb, hipStream_t s) {
+// gradients of alpha and beta in the epilogues (or, with `ad`, the projected
+// Adam step applied in place).
+int enqueue_fwd(cv_bound* h, const float* alpha, const float* beta, float* ga, float* gb, const AdamStep* ad,
+                hipStream_t s) {
   const int L = h->L;
   Vars v{};
   v.alpha = alpha;
@@ -598,9 +693,25 @@ int enqueue_fwd(cv_bound* h, const float* alpha, const float* beta, float* ga, f
   v.gbeta = gb;
   v.xpos = h->xpos;
   v.xneg = h->xneg;
+  if (ad) {
+    v.adam = 1;
+    v.lr_a = ad->lr_a;
+    v.lr_b = ad->lr_b;
+    v.bc1 = ad->bc1;
+    v.bc2 = ad->bc2;
+    v.alpha_w = const_cast<float*>(alpha);
+    v.beta_w = const_cast<float*>(beta);
+    v.ma = ad->ma;
+    v.va = ad->va;
+    v.mb = ad->mb;
+    v.vb = ad->vb;
+  }
   Profiler* pf = h->prof;
   if (h->R == 0) return CV_OK;
-  for (int i = 1; i <= L - 1; ++i) {
+  // the adjoint chain starts one layer above the lowest chained layer, whose
+  // input (x* or a wide conv output) goes through the per-layer kernel
+  const int i_chain = h->chain_fT ? h->chain_lo + 1 : L;
+  for (int i = 1; i <= L - 1 && i < i_chain; ++i) {
     const DevLayer& ly = h->layers[i - 1];
     const int mode = i == 1 ? kFwdX : kFwd;
     const int last = i == L - 1;
@@ -629,6 +740,30 @@ int enqueue_fwd(cv_bound* h, const float* alpha, const float* beta, float* ga, f
       if (pf) pf->end();
     }
   }
+  if (i_chain <= L - 1) {
+    const int lo = i_chain;
+    ChainArgs ca{};
+    ca.nl = L - lo;
+    double fl = 0, unst = 0;
+    for (int i = lo, t = 0; i <= L - 1; ++i, ++t) {
+      const DevLayer& ly = h->layers[i - 1];
+      ca.ly[t] = ChainLayer{ly.W, ly.ld_in, h->dims[i - 1], h->dims[i], ly.bias, h->offs[i - 1]};
+      fl += 2.0 * h->R * h->dims[i] * h->dims[i - 1];
+      unst += h->unst_rows_per_layer[i - 1];
+    }
+    ca.ldk = chain_ldk_of(h);
+    ca.from_x = 0;
+    ca.in = h->act[(lo - 1) & 1];
+    ca.ldi = h->ldact;
+    ca.bt = h->bt;
+    ca.v = v;
+    const double rows = h->R;
+    if (pf) pf->begin("chain_fwd_T" + std::to_string(h->chain_fT), fl,
+                      rows * h->dims[lo - 1] * 4.0 + (double)h->B * (h->nd - h->offs[lo - 1]) * 2.0 +
+                          unst * 4.0 * (ad ? 7 : 3));
+    launch_chain_fwd(h->chain_fT, ca, s);
+    if (pf) pf->end();
+  }
   HIPCHK(hipGetLastError());
   return CV_OK;
 }
@@ -637,19 +772,22 @@ int enqueue_opt(cv_bound* h, int iters, float lr_a, float lr_b, float decay, flo
                 float* adam_state, int step0, float* lb_best, float* lb_last, hipStream_t s) {
   const int64_t nb = h->nnz * h->m;
   float* st = adam_state ? adam_state : h->adam;
-  float *ma = st, *va = st + h->n_alpha, *mb = st + 2 * h->n_alpha, *vb = st + 2 * h->n_alpha + nb;
   if (!adam_state) launch_fill(h->adam, 0.f, 2 * h->n_alpha + 2 * nb, s);
   int rc;
   for (int t = 0; t < iters; ++t) {
     if ((rc = enqueue_bwd(h, alpha, beta, true, nullptr, lb_best, t == 0, s))) return rc;
-    if ((rc = enqueue_fwd(h, alpha, beta, h->g_alpha, h->g_beta, s))) return rc;
     const int tt = step0 + t;
-    const double bc1 = 1.0 - std::pow(0.9, tt + 1), bc2 = 1.0 - std::pow(0.999, tt + 1);
+    AdamStep ad;
+    ad.bc1 = (float)(1.0 - std::pow(0.9, tt + 1));
+    ad.bc2 = (float)(1.0 - std::pow(0.999, tt + 1));
     const double sc = std::pow((double)decay, tt);
-    if (h->prof) h->prof->begin("adam", 0, (h->n_alpha + nb) * 28.0);
-    launch_adam(alpha, h->g_alpha, ma, va, h->n_alpha, (float)(lr_a * sc), (float)bc1, (float)bc2, 0.f, 1.f, s);
-    launch_adam(beta, h->g_beta, mb, vb, nb, (float)(lr_b * sc), (float)bc1, (float)bc2, 0.f, INFINITY, s);
-    if (h->prof) h->prof->end();
+    ad.lr_a = (float)(lr_a * sc);
+    ad.lr_b = (float)(lr_b * sc);
+    ad.ma = st;
+    ad.va = st + h->n_alpha;
+    ad.mb = st + 2 * h->n_alpha;
+    ad.vb = st + 2 * h->n_alpha + nb;
+    if ((rc = enqueue_fwd(h, alpha, beta, nullptr, nullptr, &ad, s))) return rc;
   }
   if ((rc = enqueue_bwd(h, alpha, beta, false, lb_last, lb_best, iters == 0, s))) return rc;
   HIPCHK(hipGetLastError());
@@ -729,7 +867,7 @@ int cv_bound_grad(cv_bound* h, const float* alpha, const float* beta, float* lb,
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
   if ((rc = enqueue_bwd(h, alpha, beta, true, lb, nullptr, 0, s))) return rc;
-  return enqueue_fwd(h, alpha, beta, g_alpha, g_beta, s);
+  return enqueue_fwd(h, alpha, beta, g_alpha, g_beta, nullptr, s);
 }
 
 int cv_bound_optimize(cv_bound* h, int32_t iters, float lr_alpha, float lr_beta, float lr_decay, float* alpha,
@@ -845,10 +983,53 @@ int cv_bound_autotune(cv_bound* h, void* stream) {
       g_tune[{mode, h->R, N, K}] = best;
     }
   }
+  // whole passes: fused dense chain with 16 or 32 rows per tile, or per-layer kernels
+  if (h->chain_lo) {
+    const int saved_b = h->chain_bT, saved_f = h->chain_fT;
+    std::vector<int> cands = {0, 16};
+    if (chain_fits(h, 32)) cands.push_back(32);
+    for (int dir = 0; dir < 2; ++dir) {
+      if (dir == 1 && h->chain_lo + 1 > L - 1) continue;  // no adjoint chain
+      float best_ms = 1e30f;
+      int best = dir == 0 ? saved_b : saved_f;
+      for (int T : cands) {
+        (dir == 0 ? h->chain_bT : h->chain_fT) = T;
+        auto pass = [&]() {
+          return dir == 0 ? enqueue_bwd(h, h->g_alpha, h->g_beta, true, nullptr, nullptr, 0, s)
+                          : enqueue_fwd(h, h->g_alpha, h->g_beta, h->g_alpha, h->g_beta, nullptr, s);
+        };
+        for (int w = 0; w < 2; ++w)
+          if ((rc = pass())) return rc;
+        HIPCHK(hipEventRecord(e0, s));
+        for (int w = 0; w < 5; ++w)
+          if ((rc = pass())) return rc;
+        HIPCHK(hipEventRecord(e1, s));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = T;
+        }
+      }
+      (dir == 0 ? h->chain_bT : h->chain_fT) = best;
+    }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   drop_graph(h);
   HIPCHK(hipStreamSynchronize(s));
+  return CV_OK;
+}
+
+int cv_bound_set_plan(cv_bound* h, int32_t chain_bwd, int32_t chain_fwd) {
+  if (!h) return fail(CV_EINVAL, "null handle");
+  auto ok = [&](int T) { return T == 0 || ((T == 16 || T == 32) && h->chain_lo && chain_fits(h, T)); };
+  if (!ok(chain_bwd) || !ok(chain_fwd)) return fail(CV_EINVAL, "chain rows must be 0, 16 or 32 where a chain exists");
+  if (chain_fwd && h->chain_lo + 1 > h->L - 1) return fail(CV_EINVAL, "this network has no adjoint chain");
+  h->chain_bT = chain_bwd;
+  h->chain_fT = chain_fwd;
+  drop_graph(h);
   return CV_OK;
 }
 
@@ -866,7 +1047,7 @@ int cv_bound_profile(cv_bound* h, const float* alpha, const float* beta, int32_t
   for (int r = 0; r < reps && rc == CV_OK; ++r) {
     pf.recs.clear();
     rc = enqueue_bwd(h, alpha, beta, true, nullptr, nullptr, 0, s);
-    if (!rc) rc = enqueue_fwd(h, alpha, beta, h->g_alpha, h->g_beta, s);
+    if (!rc) rc = enqueue_fwd(h, alpha, beta, h->g_alpha, h->g_beta, nullptr, s);
     if (!rc) rc = enqueue_bwd(h, alpha, beta, false, nullptr, nullptr, 0, s);
     if (hipStreamSynchronize(s) != hipSuccess) rc = fail(CV_EDEVICE, "profile pass failed");
     std::map<std::string, int> per_rep;

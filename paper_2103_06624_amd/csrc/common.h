@@ -8,18 +8,21 @@ namespace cvb {
 
 constexpr int kWave = 64;
 
-// Per (subdomain, neuron) status word.  Bits 15..14: kind.  For SPLIT, bit 13
-// is the side (1: z >= 0, set Z+) and bits 12..0 the split's position in the
-// subdomain's CSR list.  Root kinds follow the cases of Eq. definition_D:
-// l >= 0 active, u <= 0 inactive, otherwise unstable.
-constexpr uint16_t kInactive = 0u << 14;
-constexpr uint16_t kActive = 1u << 14;
-constexpr uint16_t kUnstable = 2u << 14;
-constexpr uint16_t kSplit = 3u << 14;
-constexpr uint16_t kKindMask = 3u << 14;
-constexpr uint16_t kSidePos = 1u << 13;
-constexpr uint16_t kSlotMask = (1u << 13) - 1;
-constexpr int kMaxDepth = (1 << 13) - 1;
+// Per (subdomain, neuron) status record, 32 bits.  Bits 31..30: kind, the
+// cases of Eq. definition_D (l >= 0 active, u <= 0 inactive, otherwise
+// unstable) with split neurons as a fourth kind.  UNSTABLE: bits 29..0 hold
+// the neuron's index in its property's unstable list (its alpha entry is
+// row base + that index).  SPLIT: bit 29 is the side (1: z >= 0, set Z+) and
+// bits 28..0 the split's index in the CSR split arrays (its beta row).
+constexpr uint32_t kInactive = 0u << 30;
+constexpr uint32_t kActive = 1u << 30;
+constexpr uint32_t kUnstable = 2u << 30;
+constexpr uint32_t kSplit = 3u << 30;
+constexpr uint32_t kKindMask = 3u << 30;
+constexpr uint32_t kCidxMask = (1u << 30) - 1;
+constexpr uint32_t kSidePos = 1u << 29;
+constexpr uint32_t kSplitMask = (1u << 29) - 1;
+constexpr int64_t kMaxSplits = (int64_t)1 << 29;
 
 // Everything a kernel needs to know about the batch, by value.
 struct Batch {
@@ -31,8 +34,7 @@ struct Batch {
   const int* prop;          // [B] property of each subdomain
   const int64_t* aoff;      // [B] first alpha entry of each subdomain
   const int* ucount;        // [P] root-unstable neurons per property
-  const int64_t* sptr;      // [B+1] CSR split offsets
-  const uint16_t* status;   // [B, nd]
+  const uint32_t* status;   // [B, nd] status records
   const int* cidx;          // [P, nd] index in the property's unstable list or -1
   const float2* chord;      // [P, nd] (u/(u-l), -u l/(u-l)) for unstable neurons
   const float* adef;        // [P, nd] default alpha (used when a pass has no alpha array)
@@ -49,7 +51,31 @@ struct Vars {
   float* gbeta;        // [nnz, m]
   uint64_t* xpos;      // [n_rows, w64] bit set where A(0) > 0
   uint64_t* xneg;      // [n_rows, w64] bit set where A(0) < 0
+  // Projected Adam fused into the adjoint (optimisation passes): when adam is
+  // set, each gradient entry is applied in place by its owning (row, neuron)
+  // instead of being written to galpha / gbeta.  alpha_w / beta_w alias alpha /
+  // beta; every entry has exactly one owner, which reads it before writing it.
+  int adam;
+  float lr_a, lr_b, bc1, bc2;
+  float* alpha_w;
+  float* beta_w;
+  float* ma;
+  float* va;
+  float* mb;
+  float* vb;
 };
+
+// One projected Adam ascent step on entry i (Kingma & Ba: beta1 0.9, beta2
+// 0.999, eps 1e-8; bc1 = 1 - 0.9^t, bc2 = 1 - 0.999^t), clamped to [lo, hi].
+__device__ __forceinline__ void adam_apply(float* x, float* m1, float* m2, int64_t i, float g, float lr, float bc1,
+                                           float bc2, float lo, float hi) {
+  const float a = 0.9f * m1[i] + 0.1f * g;
+  const float b = 0.999f * m2[i] + 0.001f * g * g;
+  m1[i] = a;
+  m2[i] = b;
+  const float step = lr * (a / bc1) / (sqrtf(b / bc2) + 1e-8f);
+  x[i] = fminf(fmaxf(x[i] + step, lo), hi);
+}
 
 // Per-launch epilogue parameters (one layer).
 struct Epi {
@@ -58,7 +84,7 @@ struct Epi {
   const float* bias;   // [n] bias of that layer (fwd: added to z; bwd: b of the relaxed layer)
   float* out;          // [n_rows, ldo] next operand
   int ldo;
-  float* part;         // [n_rows, n_slots] partial constants
+  float* part;         // [n_slots, n_rows] partial constants (slot-major)
   int n_slots;
   int slot0;           // first slot of this launch
 };
@@ -66,7 +92,6 @@ struct Epi {
 struct RowInfo {
   int b, k, p;
   int64_t abase;  // alpha index of (b, k, unstable #0)
-  int64_t sbase;  // first split of b
 };
 
 __device__ __forceinline__ RowInfo row_info(const Batch& bt, int r) {
@@ -75,7 +100,6 @@ __device__ __forceinline__ RowInfo row_info(const Batch& bt, int r) {
   ri.k = r - ri.b * bt.m;
   ri.p = bt.prop[ri.b];
   ri.abase = bt.aoff[ri.b] + (int64_t)ri.k * bt.ucount[ri.p];
-  ri.sbase = bt.sptr[ri.b];
   return ri;
 }
 
@@ -84,34 +108,49 @@ __device__ __forceinline__ RowInfo row_info(const Batch& bt, int r) {
 // beta^T S of Eq. definition_A).  a = A(i)_j.  Returns Lambda(i)_j and adds
 // A lowerb + Lambda b to *cst.  Stores a into acomp at unstable neurons when
 // acomp is set (the adjoint needs the branch and the value).
-__device__ __forceinline__ float relax_bwd(const Batch& bt, const Vars& v, const RowInfo& ri, int layer_off,
-                                          int j, float a, float bias, float* cst) {
-  const int col = layer_off + j;
-  const uint16_t st = bt.status[(int64_t)ri.b * bt.nd + col];
-  const uint16_t kind = st & kKindMask;
+__device__ __forceinline__ float relax_value(const Batch& bt, const Vars& v, const RowInfo& ri, uint32_t rec,
+                                             float2 ch, float coef, float a, float bias, float* cst) {
+  const uint32_t kind = rec & kKindMask;
   float lam;
   if (kind == kActive) {
     lam = a;
   } else if (kind == kInactive) {
     lam = 0.f;
   } else if (kind == kUnstable) {
-    const int64_t pc = (int64_t)ri.p * bt.nd + col;
-    const int64_t ai = ri.abase + bt.cidx[pc];
-    if (v.acomp) v.acomp[ai] = a;
     if (a >= 0.f) {
-      lam = (v.alpha ? v.alpha[ai] : bt.adef[pc]) * a;
+      lam = coef * a;  // coef = alpha
     } else {
-      const float2 ch = bt.chord[pc];
       lam = a * ch.x;
       *cst = fmaf(a, ch.y, *cst);
     }
   } else {
-    const bool pos = (st & kSidePos) != 0;
-    const float be = v.beta[(ri.sbase + (st & kSlotMask)) * bt.m + ri.k];
-    lam = pos ? a - be : be;  // D = 1, S = -1 for z >= 0; D = 0, S = +1 for z < 0
+    lam = (rec & kSidePos) ? a - coef : coef;  // coef = beta; D = 1, S = -1 / D = 0, S = +1
   }
   *cst = fmaf(lam, bias, *cst);
   return lam;
+}
+
+// The variable that multiplies neuron (row, col): alpha for an unstable
+// neuron, beta for a split one (0 otherwise).
+__device__ __forceinline__ float relax_coef(const Batch& bt, const Vars& v, const RowInfo& ri, uint32_t rec,
+                                            int64_t pc) {
+  const uint32_t kind = rec & kKindMask;
+  if (kind == kUnstable) {
+    const int64_t ai = ri.abase + (rec & kCidxMask);
+    return v.alpha ? v.alpha[ai] : bt.adef[pc];
+  }
+  if (kind == kSplit) return v.beta[(int64_t)(rec & kSplitMask) * bt.m + ri.k];
+  return 0.f;
+}
+
+__device__ __forceinline__ float relax_bwd(const Batch& bt, const Vars& v, const RowInfo& ri, int layer_off,
+                                          int j, float a, float bias, float* cst) {
+  const int col = layer_off + j;
+  const uint32_t rec = bt.status[(int64_t)ri.b * bt.nd + col];
+  const int64_t pc = (int64_t)ri.p * bt.nd + col;
+  const float2 ch = bt.chord[pc];
+  if (v.acomp && (rec & kKindMask) == kUnstable) v.acomp[ri.abase + (rec & kCidxMask)] = a;
+  return relax_value(bt, v, ri, rec, ch, relax_coef(bt, v, ri, rec, pc), a, bias, cst);
 }
 
 // Box minimiser contribution min(a xl, a xu) (Eq. beta_crown_lp for a box).
@@ -126,32 +165,56 @@ __device__ __forceinline__ float xstar(bool pos, bool neg, float xl, float xu) {
 
 // Adjoint at one neuron of ReLU layer i during the forward sweep: zb =
 // zbar(i)_j (bias included).  Writes the gradient of alpha / beta owned by
-// this (row, neuron) and returns zhat(i)_j = D zbar + lowerb.
-__device__ __forceinline__ float relax_fwd(const Batch& bt, const Vars& v, const RowInfo& ri, int layer_off,
-                                          int j, float zb) {
-  const int col = layer_off + j;
-  const uint16_t st = bt.status[(int64_t)ri.b * bt.nd + col];
-  const uint16_t kind = st & kKindMask;
+// this (row, neuron) -- or applies the fused Adam step -- and returns
+// zhat(i)_j = D zbar + lowerb.  a_st is the stored A(i)_j and al the alpha of
+// an unstable neuron; be is the beta of a split neuron.
+__device__ __forceinline__ float relax_fwd_value(const Batch& bt, const Vars& v, const RowInfo& ri, uint32_t rec,
+                                                 float2 ch, float a_st, float al, int64_t pc, float zb) {
+  const uint32_t kind = rec & kKindMask;
   if (kind == kActive) return zb;
   if (kind == kInactive) return 0.f;
   if (kind == kUnstable) {
-    const int64_t pc = (int64_t)ri.p * bt.nd + col;
-    const int64_t ai = ri.abase + bt.cidx[pc];
-    const float a = v.acomp[ai];
-    if (a >= 0.f) {
-      v.galpha[ai] = zb * a;
-      return (v.alpha ? v.alpha[ai] : bt.adef[pc]) * zb;
+    const int64_t ai = ri.abase + (rec & kCidxMask);
+    float zh, g;
+    if (a_st >= 0.f) {
+      g = zb * a_st;
+      zh = al * zb;
+    } else {
+      g = 0.f;
+      zh = fmaf(ch.x, zb, ch.y);
     }
-    v.galpha[ai] = 0.f;
-    const float2 ch = bt.chord[pc];
-    return fmaf(ch.x, zb, ch.y);
+    if (v.adam) adam_apply(v.alpha_w, v.ma, v.va, ai, g, v.lr_a, v.bc1, v.bc2, 0.f, 1.f);
+    else v.galpha[ai] = g;
+    return zh;
   }
-  const bool pos = (st & kSidePos) != 0;
-  v.gbeta[(ri.sbase + (st & kSlotMask)) * bt.m + ri.k] = pos ? -zb : zb;
+  const bool pos = (rec & kSidePos) != 0;
+  const int64_t bi = (int64_t)(rec & kSplitMask) * bt.m + ri.k;
   // a split neuron is root-unstable, so it owns an alpha entry: its gradient is 0
-  const int64_t pc = (int64_t)ri.p * bt.nd + col;
-  v.galpha[ri.abase + bt.cidx[pc]] = 0.f;
+  const int64_t ai = ri.abase + bt.cidx[pc];
+  const float gb = pos ? -zb : zb;
+  if (v.adam) {
+    adam_apply(v.beta_w, v.mb, v.vb, bi, gb, v.lr_b, v.bc1, v.bc2, 0.f, INFINITY);
+    adam_apply(v.alpha_w, v.ma, v.va, ai, 0.f, v.lr_a, v.bc1, v.bc2, 0.f, 1.f);
+  } else {
+    v.gbeta[bi] = gb;
+    v.galpha[ai] = 0.f;
+  }
   return pos ? zb : 0.f;
+}
+
+__device__ __forceinline__ float relax_fwd(const Batch& bt, const Vars& v, const RowInfo& ri, int layer_off,
+                                          int j, float zb) {
+  const int col = layer_off + j;
+  const uint32_t rec = bt.status[(int64_t)ri.b * bt.nd + col];
+  const int64_t pc = (int64_t)ri.p * bt.nd + col;
+  const float2 ch = bt.chord[pc];
+  float a_st = 0.f, al = 0.f;
+  if ((rec & kKindMask) == kUnstable) {
+    const int64_t ai = ri.abase + (rec & kCidxMask);
+    a_st = v.acomp[ai];
+    al = v.alpha ? v.alpha[ai] : bt.adef[pc];
+  }
+  return relax_fwd_value(bt, v, ri, rec, ch, a_st, al, pc, zb);
 }
 
 __device__ __forceinline__ float wave_sum16(float x) {

@@ -133,7 +133,7 @@ __global__ __launch_bounds__(256) void convt_bwd(const float* __restrict__ lam, 
   const float tot = row_sum(cst, pos, red);
   if (threadIdx.x < sl.rb) {
     const int r2 = sl.row0 + threadIdx.x;
-    if (r2 < M) e.part[(int64_t)r2 * e.n_slots + e.slot0] = tot;
+    if (r2 < M) e.part[(int64_t)e.slot0 * M + r2] = tot;
   }
   if (MODE == kBwdConc && v.xpos) {
     __syncthreads();
@@ -239,7 +239,7 @@ int conv_dispatch(const ConvArgs& a, hipStream_t st) {
     conv_fwd<CO, MODE><<<grid, block, sm, st>>>(a.in, a.ldi, a.w, a.g, a.M, a.last, a.bt, a.v, a.e); \
     return 0;
   switch (a.g.co) {
-    CVB_CF(1) CVB_CF(2) CVB_CF(3) CVB_CF(4) CVB_CF(8) CVB_CF(16) CVB_CF(32) CVB_CF(64)
+    CVB_CF(1) CVB_CF(2) CVB_CF(3) CVB_CF(4) CVB_CF(8) CVB_CF(16) CVB_CF(32)
     default:
       return -1;
   }

@@ -19,9 +19,6 @@ namespace cvb {
 
 namespace {
 
-constexpr int BK = 16;
-constexpr int LDK = BK + 4;  // padded LDS row (floats): conflict-free b128 reads
-
 template <int MODE>
 __device__ __forceinline__ float4 load_a4(const float* __restrict__ A, int lda, int row, int k, int M, int K,
                                           const Batch& bt, const Vars& v) {
@@ -30,17 +27,22 @@ __device__ __forceinline__ float4 load_a4(const float* __restrict__ A, int lda, 
   if (MODE == kFwdX) {
     // zhat(0) = x*, rebuilt from the sign planes of A(0) and the box
     const int p = bt.prop[row / bt.m];
-    const uint64_t wp = v.xpos[(int64_t)row * bt.w64 + (k >> 6)];
-    const uint64_t wn = v.xneg[(int64_t)row * bt.w64 + (k >> 6)];
-    const float* xl = bt.xlo + (int64_t)p * bt.d0;
-    const float* xu = bt.xhi + (int64_t)p * bt.d0;
+    const uint64_t wp = v.xpos[(int64_t)row * bt.w64 + (k >> 6)] >> (k & 63);
+    const uint64_t wn = v.xneg[(int64_t)row * bt.w64 + (k >> 6)] >> (k & 63);
+    const float* xl = bt.xlo + (int64_t)p * bt.d0 + k;
+    const float* xu = bt.xhi + (int64_t)p * bt.d0 + k;
+    if (k + 3 < K && (bt.d0 & 3) == 0) {
+      const float4 l4 = *reinterpret_cast<const float4*>(xl);
+      const float4 u4 = *reinterpret_cast<const float4*>(xu);
+      r.x = xstar(wp & 1, wn & 1, l4.x, u4.x);
+      r.y = xstar((wp >> 1) & 1, (wn >> 1) & 1, l4.y, u4.y);
+      r.z = xstar((wp >> 2) & 1, (wn >> 2) & 1, l4.z, u4.z);
+      r.w = xstar((wp >> 3) & 1, (wn >> 3) & 1, l4.w, u4.w);
+      return r;
+    }
     float t[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int kk = k + q;
-      const int bit = kk & 63;
-      t[q] = kk < K ? xstar((wp >> bit) & 1, (wn >> bit) & 1, xl[kk], xu[kk]) : 0.f;
-    }
+    for (int q = 0; q < 4; ++q) t[q] = k + q < K ? xstar((wp >> q) & 1, (wn >> q) & 1, xl[q], xu[q]) : 0.f;
     return make_float4(t[0], t[1], t[2], t[3]);
   }
   const float* src = A + (int64_t)row * lda + k;
@@ -63,17 +65,21 @@ __device__ __forceinline__ float4 load_b4(const float* __restrict__ Bt, int ldb,
 }
 
 // 256 threads = 4 waves in a 2x2 arrangement; each wave owns (BM/2)x(BN/2)
-// made of 16x16 MFMA blocks.  K advances 16 at a time through double-buffered
-// LDS tiles; each lane reads 4 consecutive k of one row with one b128 read and
-// feeds them to 4 MFMAs (k slot g of MFMA t holds k = 4g + t, identically for
-// both operands, so the products pair up correctly).
-template <int BM, int BN, int MODE>
+// made of 16x16 MFMA blocks.  K advances BK at a time through double-buffered
+// LDS tiles (the next slab's global loads are in flight while this one's
+// MFMAs run, so a larger BK covers more latency); each lane reads 4
+// consecutive k of one row with one b128 read and feeds them to 4 MFMAs (k
+// slot g of MFMA t holds k = 4g + t, identically for both operands, so the
+// products pair up correctly).
+template <int BM, int BN, int BK, int MODE>
 __global__ __launch_bounds__(256) void gemm_nt(const float* __restrict__ A, int lda, const float* __restrict__ Bt,
                                                int ldb, int M, int N, int K, int last, Batch bt, Vars v, Epi e) {
+  constexpr int LDK = BK + 4;  // padded LDS row: LDK/4 odd, conflict-free b128 reads
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int FM = WM / 16, FN = WN / 16;
-  constexpr int A_LD = BM * 4 / 256 > 0 ? BM * 4 / 256 : 1;  // float4 loads per thread
-  constexpr int B_LD = BN * 4 / 256 > 0 ? BN * 4 / 256 : 1;
+  constexpr int QK = BK / 4;  // float4 per row of a slab
+  constexpr int A_LD = (BM * QK + 255) / 256;  // float4 loads per thread
+  constexpr int B_LD = (BN * QK + 255) / 256;
   __shared__ __attribute__((aligned(16))) float As[2][BM][LDK];
   __shared__ __attribute__((aligned(16))) float Bs[2][BN][LDK];
   __shared__ float red[2][BM];
@@ -103,26 +109,26 @@ __global__ __launch_bounds__(256) void gemm_nt(const float* __restrict__ A, int 
 #pragma unroll
     for (int t = 0; t < A_LD; ++t) {
       const int idx = tid + t * 256;
-      ra[t] = (idx < BM * 4) ? load_a4<MODE>(A, lda, m0 + (idx >> 2), k0 + (idx & 3) * 4, M, K, bt, v)
-                             : make_float4(0.f, 0.f, 0.f, 0.f);
+      ra[t] = (idx < BM * QK) ? load_a4<MODE>(A, lda, m0 + idx / QK, k0 + (idx % QK) * 4, M, K, bt, v)
+                              : make_float4(0.f, 0.f, 0.f, 0.f);
     }
 #pragma unroll
     for (int t = 0; t < B_LD; ++t) {
       const int idx = tid + t * 256;
-      rb[t] = (idx < BN * 4) ? load_b4(Bt, ldb, n0 + (idx >> 2), k0 + (idx & 3) * 4, N, K)
-                             : make_float4(0.f, 0.f, 0.f, 0.f);
+      rb[t] = (idx < BN * QK) ? load_b4(Bt, ldb, n0 + idx / QK, k0 + (idx % QK) * 4, N, K)
+                              : make_float4(0.f, 0.f, 0.f, 0.f);
     }
   };
   auto sstore = [&](int buf) {
 #pragma unroll
     for (int t = 0; t < A_LD; ++t) {
       const int idx = tid + t * 256;
-      if (idx < BM * 4) *reinterpret_cast<float4*>(&As[buf][idx >> 2][(idx & 3) * 4]) = ra[t];
+      if (idx < BM * QK) *reinterpret_cast<float4*>(&As[buf][idx / QK][(idx % QK) * 4]) = ra[t];
     }
 #pragma unroll
     for (int t = 0; t < B_LD; ++t) {
       const int idx = tid + t * 256;
-      if (idx < BN * 4) *reinterpret_cast<float4*>(&Bs[buf][idx >> 2][(idx & 3) * 4]) = rb[t];
+      if (idx < BN * QK) *reinterpret_cast<float4*>(&Bs[buf][idx / QK][(idx % QK) * 4]) = rb[t];
     }
   };
 
@@ -133,22 +139,25 @@ __global__ __launch_bounds__(256) void gemm_nt(const float* __restrict__ A, int 
   for (int kt = 0; kt < nk; ++kt) {
     const int buf = kt & 1;
     if (kt + 1 < nk) gload((kt + 1) * BK);
-    float4 fa[FM], fb[FN];
 #pragma unroll
-    for (int i = 0; i < FM; ++i)
-      fa[i] = *reinterpret_cast<const float4*>(&As[buf][wm * WM + i * 16 + (lane & 15)][4 * (lane >> 4)]);
+    for (int ks = 0; ks < BK; ks += 16) {
+      float4 fa[FM], fb[FN];
 #pragma unroll
-    for (int j = 0; j < FN; ++j)
-      fb[j] = *reinterpret_cast<const float4*>(&Bs[buf][wn * WN + j * 16 + (lane & 15)][4 * (lane >> 4)]);
+      for (int i = 0; i < FM; ++i)
+        fa[i] = *reinterpret_cast<const float4*>(&As[buf][wm * WM + i * 16 + (lane & 15)][ks + 4 * (lane >> 4)]);
 #pragma unroll
-    for (int i = 0; i < FM; ++i)
+      for (int j = 0; j < FN; ++j)
+        fb[j] = *reinterpret_cast<const float4*>(&Bs[buf][wn * WN + j * 16 + (lane & 15)][ks + 4 * (lane >> 4)]);
 #pragma unroll
-      for (int j = 0; j < FN; ++j) {
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i].x, fb[j].x, acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i].y, fb[j].y, acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i].z, fb[j].z, acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i].w, fb[j].w, acc[i][j], 0, 0, 0);
-      }
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i].x, fb[j].x, acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i].y, fb[j].y, acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i].z, fb[j].z, acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i].w, fb[j].w, acc[i][j], 0, 0, 0);
+        }
+    }
     if (kt + 1 < nk) sstore(buf ^ 1);
     __syncthreads();
   }
@@ -207,7 +216,7 @@ __global__ __launch_bounds__(256) void gemm_nt(const float* __restrict__ A, int 
     __syncthreads();
     for (int t = tid; t < BM; t += 256) {
       const int row = m0 + t;
-      if (row < M) e.part[(int64_t)row * e.n_slots + e.slot0 + tn] = red[0][t] + red[1][t];
+      if (row < M) e.part[(int64_t)(e.slot0 + tn) * M + row] = red[0][t] + red[1][t];
     }
   } else {
 #pragma unroll
@@ -230,38 +239,49 @@ __global__ __launch_bounds__(256) void gemm_nt(const float* __restrict__ A, int 
   }
 }
 
-template <int BM, int BN>
+template <int BM, int BN, int BK>
 void launch_cfg(int mode, const GemmArgs& g, hipStream_t s) {
   const int tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
   dim3 grid(tiles), block(256);
   switch (mode) {
     case kBwdRelax:
-      gemm_nt<BM, BN, kBwdRelax><<<grid, block, 0, s>>>(g.A, g.lda, g.Bt, g.ldb, g.M, g.N, g.K, g.last, g.bt, g.v, g.e);
+      gemm_nt<BM, BN, BK, kBwdRelax><<<grid, block, 0, s>>>(g.A, g.lda, g.Bt, g.ldb, g.M, g.N, g.K, g.last, g.bt, g.v,
+                                                            g.e);
       break;
     case kBwdConc:
-      gemm_nt<BM, BN, kBwdConc><<<grid, block, 0, s>>>(g.A, g.lda, g.Bt, g.ldb, g.M, g.N, g.K, g.last, g.bt, g.v, g.e);
+      gemm_nt<BM, BN, BK, kBwdConc><<<grid, block, 0, s>>>(g.A, g.lda, g.Bt, g.ldb, g.M, g.N, g.K, g.last, g.bt, g.v,
+                                                           g.e);
       break;
     case kFwdX:
-      gemm_nt<BM, BN, kFwdX><<<grid, block, 0, s>>>(g.A, g.lda, g.Bt, g.ldb, g.M, g.N, g.K, g.last, g.bt, g.v, g.e);
+      gemm_nt<BM, BN, BK, kFwdX><<<grid, block, 0, s>>>(g.A, g.lda, g.Bt, g.ldb, g.M, g.N, g.K, g.last, g.bt, g.v, g.e);
       break;
     default:
-      gemm_nt<BM, BN, kFwd><<<grid, block, 0, s>>>(g.A, g.lda, g.Bt, g.ldb, g.M, g.N, g.K, g.last, g.bt, g.v, g.e);
+      gemm_nt<BM, BN, BK, kFwd><<<grid, block, 0, s>>>(g.A, g.lda, g.Bt, g.ldb, g.M, g.N, g.K, g.last, g.bt, g.v, g.e);
       break;
   }
 }
 
 }  // namespace
 
-const GemmCfg kGemmCfgs[kNumGemmCfgs] = {{64, 64}, {64, 32}, {32, 64}, {128, 64}, {128, 32}, {32, 32}};
+const GemmCfg kGemmCfgs[kNumGemmCfgs] = {{64, 64, 16}, {64, 32, 16}, {32, 64, 16}, {128, 64, 16}, {128, 32, 16},
+                                         {32, 32, 16}, {32, 32, 32}, {32, 32, 64}, {64, 32, 32}, {32, 64, 32},
+                                         {64, 64, 32}, {64, 32, 64}, {32, 64, 64}};
 
 void launch_gemm(int cfg, int mode, const GemmArgs& g, hipStream_t s) {
   switch (cfg) {
-    case 0: launch_cfg<64, 64>(mode, g, s); break;
-    case 1: launch_cfg<64, 32>(mode, g, s); break;
-    case 2: launch_cfg<32, 64>(mode, g, s); break;
-    case 3: launch_cfg<128, 64>(mode, g, s); break;
-    case 4: launch_cfg<128, 32>(mode, g, s); break;
-    default: launch_cfg<32, 32>(mode, g, s); break;
+    case 0: launch_cfg<64, 64, 16>(mode, g, s); break;
+    case 1: launch_cfg<64, 32, 16>(mode, g, s); break;
+    case 2: launch_cfg<32, 64, 16>(mode, g, s); break;
+    case 3: launch_cfg<128, 64, 16>(mode, g, s); break;
+    case 4: launch_cfg<128, 32, 16>(mode, g, s); break;
+    case 5: launch_cfg<32, 32, 16>(mode, g, s); break;
+    case 6: launch_cfg<32, 32, 32>(mode, g, s); break;
+    case 7: launch_cfg<32, 32, 64>(mode, g, s); break;
+    case 8: launch_cfg<64, 32, 32>(mode, g, s); break;
+    case 9: launch_cfg<32, 64, 32>(mode, g, s); break;
+    case 10: launch_cfg<64, 64, 32>(mode, g, s); break;
+    case 11: launch_cfg<64, 32, 64>(mode, g, s); break;
+    default: launch_cfg<32, 64, 64>(mode, g, s); break;
   }
 }
 

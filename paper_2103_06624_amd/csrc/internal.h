@@ -17,9 +17,9 @@ enum Mode {
 };
 
 struct GemmCfg {
-  int bm, bn;
+  int bm, bn, bk;
 };
-constexpr int kNumGemmCfgs = 6;
+constexpr int kNumGemmCfgs = 13;
 extern const GemmCfg kGemmCfgs[kNumGemmCfgs];
 
 struct GemmArgs {
@@ -56,12 +56,55 @@ size_t conv_smem_bytes(const ConvGeom& g);
 int launch_convt_bwd(int mode, const ConvArgs& a, hipStream_t s);
 int launch_conv_fwd(int mode, const ConvArgs& a, hipStream_t s);
 
+// chain.hip: runs of dense layers fused per row tile
+struct ChainLayer {
+  const float* Bt;     // K-contiguous operand [N, ldb] (back-substitution: W^T; adjoint: W)
+  int ldb;
+  int K, N;
+  const float* bias;   // bias of the output layer (per neuron)
+  int out_off;         // nd offset of the output ReLU layer (unused when concretising)
+};
+constexpr int kChainMax = 12;
+struct ChainArgs {
+  int nl;
+  ChainLayer ly[kChainMax];
+  int ldk;  // LDS row stride (floats): 16-multiple + 4
+  // back-substitution start: the top ReLU layer from C W(L)
+  const float* CW;
+  int64_t cw_pstride;
+  int ldcw;
+  const float* Cb;
+  int64_t cb_pstride;
+  int n_top;
+  int top_off;
+  const float* top_bias;
+  int conc;  // 1: the last step concretises into the input; 0: write relaxed Lambda to out
+  // adjoint start: 1 = x* from the sign planes, 0 = read `in`
+  int from_x;
+  const float* in;
+  int ldi;
+  float* out;
+  int ldo;
+  float* part;
+  int n_slots;
+  int slot;
+  float* lb;
+  float* best;
+  int first;
+  int final;  // 1: the chain completes the pass: write lb / best instead of a slot
+  Batch bt;
+  Vars v;
+};
+size_t chain_smem_bytes(int T, int ldk);
+void launch_chain_bwd(int T, const ChainArgs& a, hipStream_t s);
+void launch_chain_fwd(int T, const ChainArgs& a, hipStream_t s);
+
 // misc.hip
 void launch_prep_chord(const float* l, const float* u, float2* chord, float* adef, int64_t n, hipStream_t s);
-void launch_status_fill(uint16_t* status, const uint16_t* root_kind, const int* prop, int B, int nd,
+void launch_status_fill(uint32_t* status, const uint32_t* root_kind, const int* prop, int B, int nd,
                         hipStream_t s);
-void launch_status_split(uint16_t* status, const int* split_dom, const int64_t* sptr, const int* split_col,
-                         const int8_t* side, int64_t nnz, int nd, hipStream_t s);
+void launch_status_split(uint32_t* status, const int* split_dom, const int* split_col, const int8_t* side,
+                         int64_t nnz, int nd, hipStream_t s);
 void launch_spec_merge(const float* C, const float* W, int ldw, const float* b, int P, int m, int dL, int dprev,
                        float* CW, int ldcw, float* Cb, hipStream_t s);
 void launch_spec_identity(const float* Wdense, int ldw, const float* wconv, const ConvGeom* g,

@@ -23,7 +23,7 @@ __global__ void prep_chord_k(const float* __restrict__ l, const float* __restric
   adef[i] = (up >= -lo) ? 1.f : 0.f;  // CROWN's adaptive lower slope
 }
 
-__global__ void status_fill_k(uint16_t* status, const uint16_t* __restrict__ root_kind, const int* __restrict__ prop,
+__global__ void status_fill_k(uint32_t* status, const uint32_t* __restrict__ root_kind, const int* __restrict__ prop,
                               int B, int nd) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (int64_t)B * nd) return;
@@ -32,14 +32,12 @@ __global__ void status_fill_k(uint16_t* status, const uint16_t* __restrict__ roo
   status[i] = root_kind[(int64_t)prop[b] * nd + j];
 }
 
-__global__ void status_split_k(uint16_t* status, const int* __restrict__ split_dom, const int64_t* __restrict__ sptr,
-                               const int* __restrict__ split_col, const int8_t* __restrict__ side, int64_t nnz,
-                               int nd) {
+__global__ void status_split_k(uint32_t* status, const int* __restrict__ split_dom, const int* __restrict__ split_col,
+                               const int8_t* __restrict__ side, int64_t nnz, int nd) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= nnz) return;
   const int b = split_dom[s];
-  const uint16_t slot = (uint16_t)(s - sptr[b]);
-  status[(int64_t)b * nd + split_col[s]] = kSplit | (side[s] > 0 ? kSidePos : 0) | slot;
+  status[(int64_t)b * nd + split_col[s]] = kSplit | (side[s] > 0 ? kSidePos : 0u) | (uint32_t)s;
 }
 
 // A(L-1) = C_p W(L) and c = C_p b(L) for every property and spec row
@@ -105,17 +103,17 @@ __global__ __launch_bounds__(256) void top_k(TopArgs a) {
     }
   }
   cst = wave_sum(cst);
-  if (lane == 0) a.e.part[(int64_t)row * a.e.n_slots + a.e.slot0] = cst + a.Cb[ri.p * a.cb_pstride + ri.k];
+  if (lane == 0) a.e.part[(int64_t)a.e.slot0 * a.bt.n_rows + row] = cst + a.Cb[ri.p * a.cb_pstride + ri.k];
 }
 
 // lb = sum of the partial constants of a row, in slot order (deterministic).
+// Partials are slot-major [slot][row], so each slot's reads are coalesced.
 __global__ void finalize_k(const float* __restrict__ part, int n_slots, int n_used, int n_rows, float* lb,
                            float* best, int first) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n_rows) return;
-  const float* p = part + (int64_t)r * n_slots;
   float s = 0.f;
-  for (int t = 0; t < n_used; ++t) s += p[t];
+  for (int t = 0; t < n_used; ++t) s += part[(int64_t)t * n_rows + r];
   if (lb) lb[r] = s;
   if (best) best[r] = first ? s : fmaxf(best[r], s);
 }
@@ -125,13 +123,7 @@ __global__ void adam_k(float* x, const float* __restrict__ g, float* m1, float* 
                        float bc2, float lo, float hi) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const float gi = g[i];
-  const float a = 0.9f * m1[i] + 0.1f * gi;
-  const float b = 0.999f * m2[i] + 0.001f * gi * gi;
-  m1[i] = a;
-  m2[i] = b;
-  const float step = lr * (a / bc1) / (sqrtf(b / bc2) + 1e-8f);
-  x[i] = fminf(fmaxf(x[i] + step, lo), hi);
+  adam_apply(x, m1, m2, i, g[i], lr, bc1, bc2, lo, hi);
 }
 
 __global__ void fill_k(float* p, float v, int64_t n) {
@@ -158,13 +150,13 @@ inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); 
 void launch_prep_chord(const float* l, const float* u, float2* chord, float* adef, int64_t n, hipStream_t s) {
   if (n > 0) prep_chord_k<<<nblk(n, 256), 256, 0, s>>>(l, u, chord, adef, n);
 }
-void launch_status_fill(uint16_t* status, const uint16_t* root_kind, const int* prop, int B, int nd, hipStream_t s) {
+void launch_status_fill(uint32_t* status, const uint32_t* root_kind, const int* prop, int B, int nd, hipStream_t s) {
   const int64_t n = (int64_t)B * nd;
   if (n > 0) status_fill_k<<<nblk(n, 256), 256, 0, s>>>(status, root_kind, prop, B, nd);
 }
-void launch_status_split(uint16_t* status, const int* split_dom, const int64_t* sptr, const int* split_col,
-                         const int8_t* side, int64_t nnz, int nd, hipStream_t s) {
-  if (nnz > 0) status_split_k<<<nblk(nnz, 256), 256, 0, s>>>(status, split_dom, sptr, split_col, side, nnz, nd);
+void launch_status_split(uint32_t* status, const int* split_dom, const int* split_col, const int8_t* side, int64_t nnz,
+                         int nd, hipStream_t s) {
+  if (nnz > 0) status_split_k<<<nblk(nnz, 256), 256, 0, s>>>(status, split_dom, split_col, side, nnz, nd);
 }
 void launch_spec_merge(const float* C, const float* W, int ldw, const float* b, int P, int m, int dL, int dprev,
                        float* CW, int ldcw, float* Cb, hipStream_t s) {
