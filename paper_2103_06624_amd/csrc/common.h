@@ -33,6 +33,7 @@ struct Batch {
   int w64;        // 64-bit words per row of the x* sign planes
   const int* prop;          // [B] property of each subdomain
   const int64_t* aoff;      // [B] first alpha entry of each subdomain
+  const int64_t* rbase;     // [n_rows] first alpha entry of each row
   const int* ucount;        // [P] root-unstable neurons per property
   const uint32_t* status;   // [B, nd] status records
   const int* cidx;          // [P, nd] index in the property's unstable list or -1
@@ -99,7 +100,7 @@ __device__ __forceinline__ RowInfo row_info(const Batch& bt, int r) {
   ri.b = r / bt.m;
   ri.k = r - ri.b * bt.m;
   ri.p = bt.prop[ri.b];
-  ri.abase = bt.aoff[ri.b] + (int64_t)ri.k * bt.ucount[ri.p];
+  ri.abase = bt.rbase[r];
   return ri;
 }
 

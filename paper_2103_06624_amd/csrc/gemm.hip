@@ -132,8 +132,73 @@ __global__ __launch_bounds__(256) void gemm_nt(const float* __restrict__ A, int 
     }
   };
 
+  // ---- epilogue operands, gathered before the K loop so that they land
+  // while the MFMAs run: row info and status records first, then what
+  // depends on them (chord and alpha / beta, the stored A for the adjoint, or
+  // the box for concretisation).  Element (i, r, j) of a lane is row
+  // m0 + wm*WM + 16i + 4(lane/16) + r, column n0 + wn*WN + 16j + lane%16.
+  constexpr int NE = FM * 4 * FN;
+  const int rsub = 4 * (lane >> 4);
+  const int csub = lane & 15;
+  RowInfo eri[FM][4];
+  uint32_t rec[NE];
+  float2 ech[NE];
+  float ecf[NE], east[NE], ebias[FN];
+#pragma unroll
+  for (int j = 0; j < FN; ++j) {
+    const int col = n0 + wn * WN + j * 16 + csub;
+    ebias[j] = (MODE != kBwdConc && col < N) ? e.bias[col] : 0.f;
+  }
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = m0 + wm * WM + i * 16 + rsub + r;
+      eri[i][r] = row_info(bt, min(row, M - 1));
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const int col = n0 + wn * WN + j * 16 + csub;
+        const int q = (i * 4 + r) * FN + j;
+        rec[q] = kInactive;
+        if (MODE != kBwdConc && row < M && col < N)
+          rec[q] = bt.status[(int64_t)eri[i][r].b * bt.nd + e.layer_off + col];
+      }
+    }
+
   const int nk = (K + BK - 1) / BK;
   gload(0);
+
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const int row = m0 + wm * WM + i * 16 + rsub + r;
+        const int col = n0 + wn * WN + j * 16 + csub;
+        const int q = (i * 4 + r) * FN + j;
+        const RowInfo& ri = eri[i][r];
+        ech[q] = make_float2(0.f, 0.f);
+        ecf[q] = 0.f;
+        east[q] = 0.f;
+        if (row >= M || col >= N) continue;
+        if (MODE == kBwdConc) {
+          const int64_t pb = (int64_t)ri.p * bt.d0 + col;
+          ech[q] = make_float2(bt.xlo[pb], bt.xhi[pb]);
+          continue;
+        }
+        const int64_t pc = (int64_t)ri.p * bt.nd + e.layer_off + col;
+        const bool uns = (rec[q] & kKindMask) == kUnstable;
+        if (uns) ech[q] = bt.chord[pc];
+        if (MODE == kBwdRelax) {
+          ecf[q] = relax_coef(bt, v, ri, rec[q], pc);
+        } else if (uns) {
+          const int64_t ai = ri.abase + (rec[q] & kCidxMask);
+          east[q] = v.acomp[ai];
+          ecf[q] = v.alpha ? v.alpha[ai] : bt.adef[pc];
+        }
+      }
+
   sstore(0);
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
@@ -163,8 +228,6 @@ __global__ __launch_bounds__(256) void gemm_nt(const float* __restrict__ A, int 
   }
 
   // ---- epilogue: lane holds rows 4*(lane/16)+r of each 16x16 block, column lane%16
-  const int rsub = 4 * (lane >> 4);
-  const int csub = lane & 15;
   if (MODE == kBwdRelax || MODE == kBwdConc) {
     float cst[FM][4];
 #pragma unroll
@@ -174,23 +237,20 @@ __global__ __launch_bounds__(256) void gemm_nt(const float* __restrict__ A, int 
         cst[i][r] = 0.f;
         const int row = m0 + wm * WM + i * 16 + rsub + r;
         const bool rok = row < M;
-        RowInfo ri;
-        if (rok) ri = row_info(bt, rok ? row : 0);
+        const RowInfo& ri = eri[i][r];
 #pragma unroll
         for (int j = 0; j < FN; ++j) {
           const int col = n0 + wn * WN + j * 16 + csub;
+          const int q = (i * 4 + r) * FN + j;
           const float a = acc[i][j][r];
           const bool ok = rok && col < N;
           if (MODE == kBwdRelax) {
             if (ok) {
-              const float lam = relax_bwd(bt, v, ri, e.layer_off, col, a, e.bias[col], &cst[i][r]);
-              e.out[(int64_t)row * e.ldo + col] = lam;
+              if (v.acomp && (rec[q] & kKindMask) == kUnstable) v.acomp[ri.abase + (rec[q] & kCidxMask)] = a;
+              e.out[(int64_t)row * e.ldo + col] = relax_value(bt, v, ri, rec[q], ech[q], ecf[q], a, ebias[j], &cst[i][r]);
             }
           } else {
-            if (ok) {
-              const int64_t pb = (int64_t)ri.p * bt.d0 + col;
-              cst[i][r] += conc_term(a, bt.xlo[pb], bt.xhi[pb]);
-            }
+            if (ok) cst[i][r] += conc_term(a, ech[q].x, ech[q].y);
             if (v.xpos) {
               const uint64_t mp = __ballot(ok && a > 0.f);
               const uint64_t mn = __ballot(ok && a < 0.f);
@@ -225,13 +285,15 @@ __global__ __launch_bounds__(256) void gemm_nt(const float* __restrict__ A, int 
       for (int r = 0; r < 4; ++r) {
         const int row = m0 + wm * WM + i * 16 + rsub + r;
         if (row >= M) continue;
-        const RowInfo ri = row_info(bt, row);
+        const RowInfo& ri = eri[i][r];
 #pragma unroll
         for (int j = 0; j < FN; ++j) {
           const int col = n0 + wn * WN + j * 16 + csub;
           if (col >= N) continue;
-          const float zb = acc[i][j][r] + e.bias[col];
-          const float zh = relax_fwd(bt, v, ri, e.layer_off, col, zb);
+          const int q = (i * 4 + r) * FN + j;
+          const float zb = acc[i][j][r] + ebias[j];
+          const int64_t pc = (int64_t)ri.p * bt.nd + e.layer_off + col;
+          const float zh = relax_fwd_value(bt, v, ri, rec[q], ech[q], east[q], ecf[q], pc, zb);
           if (!last) e.out[(int64_t)row * e.ldo + col] = zh;
         }
       }

@@ -85,37 +85,94 @@ __global__ void spec_identity_k(const float* __restrict__ Wd, int ldw, const flo
 }
 
 // The top ReLU layer: relax A(L-1) = C_p W(L) row by row (or concretise it
-// directly when the network has no ReLU layer).  One wave per row.
+// directly when the network has no ReLU layer).  One wave per row; each lane
+// takes E neurons at a time and issues their loads together (row operand,
+// status, bias, then the chord and variable that depend on the status).
 __global__ __launch_bounds__(256) void top_k(TopArgs a) {
+  constexpr int E = 4;
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (row >= a.bt.n_rows) return;
   const RowInfo ri = row_info(a.bt, row);
   const float* cw = a.CW + ri.p * a.cw_pstride + (int64_t)ri.k * a.ldcw;
+  const uint32_t* st = a.bt.status + (int64_t)ri.b * a.bt.nd + a.e.layer_off;
   float cst = 0.f;
-  for (int j = lane; j < a.n; j += 64) {
-    const float v = cw[j];
+  for (int j0 = lane; j0 < a.n; j0 += 64 * E) {
+    float av[E], b1[E], b2[E];
+    uint32_t rec[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int j = j0 + 64 * e;
+      const bool ok = j < a.n;
+      av[e] = ok ? cw[j] : 0.f;
+      rec[e] = kInactive;
+      b1[e] = 0.f;
+      b2[e] = 0.f;
+      if (a.conc) {
+        const int64_t pb = (int64_t)ri.p * a.bt.d0 + j;
+        if (ok) {
+          b1[e] = a.bt.xlo[pb];
+          b2[e] = a.bt.xhi[pb];
+        }
+      } else if (ok) {
+        rec[e] = st[j];
+        b1[e] = a.e.bias[j];
+      }
+    }
     if (a.conc) {
-      const int64_t pb = (int64_t)ri.p * a.bt.d0 + j;
-      cst += conc_term(v, a.bt.xlo[pb], a.bt.xhi[pb]);
-    } else {
-      a.e.out[(int64_t)row * a.e.ldo + j] = relax_bwd(a.bt, a.v, ri, a.e.layer_off, j, v, a.e.bias[j], &cst);
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+        if (j0 + 64 * e < a.n) cst += conc_term(av[e], b1[e], b2[e]);
+      continue;
+    }
+    float2 ch[E];
+    float cf[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int64_t pc = (int64_t)ri.p * a.bt.nd + a.e.layer_off + j0 + 64 * e;
+      ch[e] = (rec[e] & kKindMask) == kUnstable ? a.bt.chord[pc] : make_float2(0.f, 0.f);
+      cf[e] = relax_coef(a.bt, a.v, ri, rec[e], pc);
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int j = j0 + 64 * e;
+      if (j >= a.n) continue;
+      if (a.v.acomp && (rec[e] & kKindMask) == kUnstable) a.v.acomp[ri.abase + (rec[e] & kCidxMask)] = av[e];
+      a.e.out[(int64_t)row * a.e.ldo + j] = relax_value(a.bt, a.v, ri, rec[e], ch[e], cf[e], av[e], b1[e], &cst);
     }
   }
   cst = wave_sum(cst);
   if (lane == 0) a.e.part[(int64_t)a.e.slot0 * a.bt.n_rows + row] = cst + a.Cb[ri.p * a.cb_pstride + ri.k];
 }
 
-// lb = sum of the partial constants of a row, in slot order (deterministic).
-// Partials are slot-major [slot][row], so each slot's reads are coalesced.
-__global__ void finalize_k(const float* __restrict__ part, int n_slots, int n_used, int n_rows, float* lb,
-                           float* best, int first) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n_rows) return;
+// lb = sum of the partial constants of a row, in a fixed order
+// (deterministic).  Partials are slot-major [slot][row].  Wave g of a block
+// sums slots g, g+4, g+8, ... of 64 rows with 8 loads in flight per lane; the
+// four sums are then added in wave order.
+__global__ __launch_bounds__(256) void finalize_k(const float* __restrict__ part, int n_used, int n_rows, float* lb,
+                                                  float* best, int first) {
+  __shared__ float red[4][64];
+  const int rl = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int r = blockIdx.x * 64 + rl;
   float s = 0.f;
-  for (int t = 0; t < n_used; ++t) s += part[(int64_t)t * n_rows + r];
-  if (lb) lb[r] = s;
-  if (best) best[r] = first ? s : fmaxf(best[r], s);
+  if (r < n_rows) {
+    int t = g;
+    for (; t + 28 < n_used; t += 32) {
+      float x[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) x[q] = part[(int64_t)(t + 4 * q) * n_rows + r];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) s += x[q];
+    }
+    for (; t < n_used; t += 4) s += part[(int64_t)t * n_rows + r];
+  }
+  red[g][rl] = s;
+  __syncthreads();
+  if (g == 0 && r < n_rows) {
+    const float tot = ((red[0][rl] + red[1][rl]) + red[2][rl]) + red[3][rl];
+    if (lb) lb[r] = tot;
+    if (best) best[r] = first ? tot : fmaxf(best[r], tot);
+  }
 }
 
 // Projected Adam ascent step (Kingma & Ba, beta1 0.9, beta2 0.999, eps 1e-8).
@@ -170,7 +227,8 @@ void launch_spec_identity(const float* Wdense, int ldw, const float* wconv, cons
 void launch_top(const TopArgs& a, hipStream_t s) { top_k<<<nblk(a.bt.n_rows, 4), 256, 0, s>>>(a); }
 void launch_finalize(const float* part, int n_slots, int n_used, int n_rows, float* lb, float* best, int first,
                      hipStream_t s) {
-  finalize_k<<<nblk(n_rows, 256), 256, 0, s>>>(part, n_slots, n_used, n_rows, lb, best, first);
+  (void)n_slots;
+  finalize_k<<<nblk(n_rows, 64), 256, 0, s>>>(part, n_used, n_rows, lb, best, first);
 }
 void launch_adam(float* x, const float* g, float* m1, float* m2, int64_t n, float lr, float bc1, float bc2, float lo,
                  float hi, hipStream_t s) {
