@@ -127,7 +127,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--plan", default=None, help="chain rows bwd,fwd (e.g. 16,16 or 0,0); overrides the autotuner")
+    ap.add_argument("--plan", default=None, help="dense-chain plan bwd,fwd (1,1 fused chains, 0,0 per-layer kernels); overrides the autotuner")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()

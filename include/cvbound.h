@@ -155,13 +155,15 @@ int cv_bound_optimize(cv_bound *h, int32_t iters, float lr_alpha, float lr_beta,
  * of the summation order. */
 int cv_bound_autotune(cv_bound *h, void *stream);
 
-/* Execution plan of the dense layers at the top of the network: rows per
- * workgroup of the fused chain kernels for the back-substitution (chain_bwd)
- * and the adjoint (chain_fwd): 16 or 32, or 0 for one kernel per layer.
- * cv_bound_init picks a default and cv_bound_autotune a measured choice; this
- * call overrides both.  CV_EINVAL when a chain is requested where the network
- * has none (its dense tail is missing or too wide for the on-chip tiles).
- * Results agree across plans up to float32 summation order. */
+/* Execution plan of the dense layers at the top of the network, for the
+ * back-substitution (chain_bwd) and the adjoint (chain_fwd): 1 runs the run of
+ * dense layers as one fused kernel (each workgroup keeps its rows on chip
+ * through all of them), 0 one kernel per layer.  cv_bound_init starts with
+ * per-layer kernels, cv_bound_autotune makes a measured choice; this call
+ * overrides both.  CV_EINVAL for other values, or for 1
+ * where the network has no chain (its dense tail is missing, wider than 256
+ * neurons, or does not fit the on-chip memory).  Results agree across plans
+ * up to float32 summation order. */
 int cv_bound_set_plan(cv_bound *h, int32_t chain_bwd, int32_t chain_fwd);
 
 /* Per-kernel timing of one gradient pass plus one plain evaluation, each

@@ -153,7 +153,7 @@ class BoundProblem:
         B.check(B.cv_bound_autotune(self.h, _stream()))
 
     def set_plan(self, chain_bwd, chain_fwd):
-        """Rows per workgroup of the fused dense chains (0: one kernel per layer)."""
+        """Fused dense chain (1) or one kernel per layer (0), per direction."""
         B.check(B.cv_bound_set_plan(self.h, chain_bwd, chain_fwd))
 
     def profile(self, alpha, beta, reps=5):

@@ -153,9 +153,11 @@ struct cv_bound {
   std::vector<int> cfg;
   // runs of dense layers fused by the chain kernels: the back-substitution
   // chain covers layers L-1 .. chain_lo (with the top ReLU layer), the adjoint
-  // chain layers chain_lo .. L-1; 0 rows per tile = per-layer kernels
+  // chain layers chain_lo+1 .. L-1; chain_b / chain_f select the chain (1) or
+  // per-layer kernels (0) for each direction
   int chain_lo = 0;
-  int chain_bT = 0, chain_fT = 0;
+  int chain_b = 0, chain_f = 0;
+  int chain_np = 0, chain_ncw = 0, chain_rb = 0, chain_uw = 0, chain_grid = 0;  // chain geometry (plan_chain)
   // optimisation graph
   hipStream_t cap = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -184,16 +186,42 @@ int cfg_for(const cv_bound* h, int mode, int M, int N, int K, int fallback) {
   (void)h;
 }
 
-int chain_ldk(int kmax) { return ((kmax + 31) & ~31) + 4; }
+constexpr int kChainWidth = 256;         // widest LDS-resident layer of a chain
+constexpr int kLdsBytes = 160 * 1024;    // LDS per workgroup on gfx950
+constexpr int kChainStaticLds = 64 * 32; // row-info table of the chain kernels (upper bound)
 
-// LDS stride of a handle's chain: the widest LDS-resident operand
-int chain_ldk_of(const cv_bound* h) {
-  int kmax = 4;
-  for (int i = h->chain_lo; i <= h->L - 1; ++i) kmax = std::max(kmax, h->dims[i]);
-  return chain_ldk(kmax);
+// Chain geometry: np = widest chained operand rounded to 32 (LDS pitch) and
+// ncw rounded to 16 (output chunk); the rows divided
+// evenly over one workgroup per compute unit, each padded to rb 16-row blocks
+// (at most kChainRowBlocks, else more workgroups than CUs).  Returns false when it does not
+// fit the LDS or the per-wave unit registers.
+bool plan_chain(cv_bound* h) {
+  int wmax = 4;
+  for (int i = h->chain_lo; i <= h->L - 1; ++i) wmax = std::max(wmax, h->dims[i]);
+  const int np = (wmax + 31) & ~31, ncw = (wmax + 15) & ~15;
+  int dev = 0, ncu = 0, lds = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
+    ncu = 256;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || lds <= 0)
+    lds = 64 * 1024;
+  lds = std::min(lds, kLdsBytes);
+  const int R = std::max(1, h->R);
+  int grid = std::min(ncu, R);
+  int rb = ((R + grid - 1) / grid + 15) / 16;
+  if (rb > kChainRowBlocks) {
+    rb = kChainRowBlocks;
+    grid = (R + 16 * rb - 1) / (16 * rb);
+  }
+  if (!chain_units_fit(rb, np, ncw) || chain_smem_bytes(rb, np) + kChainStaticLds > (size_t)lds) return false;
+  chain_prepare(lds - kChainStaticLds);
+  h->chain_np = np;
+  h->chain_rb = rb;
+  h->chain_ncw = ncw;
+  h->chain_uw = chain_units_per_wave(rb, ncw);
+  h->chain_grid = grid;
+  return true;
 }
-
-bool chain_fits(const cv_bound* h, int T) { return chain_smem_bytes(T, chain_ldk_of(h)) <= 65536; }
 
 // ---------------------------------------------------------------------------
 // validation
@@ -475,24 +503,19 @@ int build(cv_bound* h, const cv_layer* layers, int n_layers, int P, const float*
     h->cfg[i - 1] = cfg_for(h, i - 1 >= 1 ? kBwdRelax : kBwdConc, h->R, N_b, K_b, gemm_default_cfg(h->R, N_b));
     h->cfg[n_layers + i - 1] = cfg_for(h, i == 1 ? kFwdX : kFwd, h->R, K_b, N_b, gemm_default_cfg(h->R, K_b));
   }
-  // dense layers fused by the chain kernels (widths must fit two LDS tiles)
+  // dense layers fused by the chain kernels (LDS-resident widths up to kChainWidth)
   h->chain_lo = 0;
-  h->chain_bT = h->chain_fT = 0;
+  h->chain_b = h->chain_f = 0;
   auto chain_ok = [&](int i) {  // layer i dense with a K-dim (d_i) that fits
-    return i >= 1 && h->layers[i - 1].type == CV_LAYER_DENSE && h->dims[i] % 4 == 0 &&
-           chain_smem_bytes(16, chain_ldk(h->dims[i])) <= 65536;
+    return i >= 1 && h->layers[i - 1].type == CV_LAYER_DENSE && h->dims[i] <= kChainWidth;
   };
   if (n_layers >= 2 && chain_ok(n_layers - 1)) {
     int lo = n_layers - 1;
-    while (lo - 1 >= 1 && chain_ok(lo - 1) && h->layers[lo - 2].type == CV_LAYER_DENSE && (n_layers - lo) < kChainMax)
-      --lo;
-    // the first adjoint step reads x* (lo = 1) or the conv output with float4 loads
-    if (h->dims[lo - 1] % 4 == 0) {
-      h->chain_lo = lo;
-      const int T = chain_fits(h, 32) ? 32 : 16;
-      h->chain_bT = T;
-      h->chain_fT = lo + 1 <= n_layers - 1 ? T : 0;
-    }
+    while (lo - 1 >= 1 && chain_ok(lo - 1) && (n_layers - lo) < kChainMax) --lo;
+    h->chain_lo = lo;
+    // the chain is available; per-layer kernels stay the default (measured
+    // faster at ~10^4 rows), cv_bound_autotune / cv_bound_set_plan choose
+    if (!plan_chain(h)) h->chain_lo = 0;
   }
   // conv kernels' LDS needs
   for (int i = 0; i + 1 < n_layers; ++i) {
@@ -581,7 +604,7 @@ int enqueue_bwd(cv_bound* h, const float* alpha, const float* beta, bool grad, f
   Profiler* pf = h->prof;
   if (h->R == 0) return CV_OK;
   int cur = 0, slot = 1, i_next = L - 1;
-  if (h->chain_bT) {
+  if (h->chain_b) {
     const int lo = h->chain_lo;
     ChainArgs ca{};
     ca.nl = L - lo;
@@ -590,7 +613,12 @@ int enqueue_bwd(cv_bound* h, const float* alpha, const float* beta, bool grad, f
       ca.ly[t] = ChainLayer{ly.Wt, ly.ld_out, h->dims[i], h->dims[i - 1], i - 1 >= 1 ? h->layers[i - 2].bias : nullptr,
                             i - 1 >= 1 ? h->offs[i - 2] : 0};
     }
-    ca.ldk = chain_ldk_of(h);
+    ca.np = h->chain_np;
+    ca.ncw = h->chain_ncw;
+    ca.ldk = h->chain_np + 4;
+    ca.rb = h->chain_rb;
+    ca.uw = h->chain_uw;
+    ca.grid = h->chain_grid;
     ca.CW = h->CW;
     ca.cw_pstride = h->cw_pstride;
     ca.ldcw = h->ldcw;
@@ -612,10 +640,10 @@ int enqueue_bwd(cv_bound* h, const float* alpha, const float* beta, bool grad, f
     ca.bt = h->bt;
     ca.v = v;
     const double rows = h->R;
-    if (pf) pf->begin("chain_bwd_T" + std::to_string(h->chain_bT), chain_flops(h),
+    if (pf) pf->begin("chain_bwd", chain_flops(h),
                       rows * h->dims[L - 1] * 4.0 + (lo == 1 ? rows * h->d0 / 4.0 : rows * h->dims[lo - 1] * 4.0) +
                           (double)h->B * (h->nd - (lo >= 2 ? h->offs[lo - 2] : 0)) * 2.0);
-    launch_chain_bwd(h->chain_bT, ca, s);
+    launch_chain_bwd(ca, s);
     if (pf) pf->end();
     if (lo == 1) {
       HIPCHK(hipGetLastError());
@@ -717,7 +745,7 @@ int enqueue_fwd(cv_bound* h, const float* alpha, const float* beta, float* ga, f
   if (h->R == 0) return CV_OK;
   // the adjoint chain starts one layer above the lowest chained layer, whose
   // input (x* or a wide conv output) goes through the per-layer kernel
-  const int i_chain = h->chain_fT ? h->chain_lo + 1 : L;
+  const int i_chain = h->chain_f ? h->chain_lo + 1 : L;
   for (int i = 1; i <= L - 1 && i < i_chain; ++i) {
     const DevLayer& ly = h->layers[i - 1];
     const int mode = i == 1 ? kFwdX : kFwd;
@@ -758,17 +786,22 @@ int enqueue_fwd(cv_bound* h, const float* alpha, const float* beta, float* ga, f
       fl += 2.0 * h->R * h->dims[i] * h->dims[i - 1];
       unst += h->unst_rows_per_layer[i - 1];
     }
-    ca.ldk = chain_ldk_of(h);
+    ca.np = h->chain_np;
+    ca.ncw = h->chain_ncw;
+    ca.ldk = h->chain_np + 4;
+    ca.rb = h->chain_rb;
+    ca.uw = h->chain_uw;
+    ca.grid = h->chain_grid;
     ca.from_x = 0;
     ca.in = h->act[(lo - 1) & 1];
     ca.ldi = h->ldact;
     ca.bt = h->bt;
     ca.v = v;
     const double rows = h->R;
-    if (pf) pf->begin("chain_fwd_T" + std::to_string(h->chain_fT), fl,
+    if (pf) pf->begin("chain_fwd", fl,
                       rows * h->dims[lo - 1] * 4.0 + (double)h->B * (h->nd - h->offs[lo - 1]) * 2.0 +
                           unst * 4.0 * (ad ? 7 : 3));
-    launch_chain_fwd(h->chain_fT, ca, s);
+    launch_chain_fwd(ca, s);
     if (pf) pf->end();
   }
   HIPCHK(hipGetLastError());
@@ -990,17 +1023,16 @@ int cv_bound_autotune(cv_bound* h, void* stream) {
       g_tune[{mode, h->R, N, K}] = best;
     }
   }
-  // whole passes: fused dense chain with 16 or 32 rows per tile, or per-layer kernels
+  // whole passes: fused dense chain or per-layer kernels
   if (h->chain_lo) {
-    const int saved_b = h->chain_bT, saved_f = h->chain_fT;
-    std::vector<int> cands = {0, 16};
-    if (chain_fits(h, 32)) cands.push_back(32);
+    const int saved_b = h->chain_b, saved_f = h->chain_f;
+    const std::vector<int> cands = {0, 1};
     for (int dir = 0; dir < 2; ++dir) {
       if (dir == 1 && h->chain_lo + 1 > L - 1) continue;  // no adjoint chain
       float best_ms = 1e30f;
       int best = dir == 0 ? saved_b : saved_f;
       for (int T : cands) {
-        (dir == 0 ? h->chain_bT : h->chain_fT) = T;
+        (dir == 0 ? h->chain_b : h->chain_f) = T;
         auto pass = [&]() {
           return dir == 0 ? enqueue_bwd(h, h->g_alpha, h->g_beta, true, nullptr, nullptr, 0, s)
                           : enqueue_fwd(h, h->g_alpha, h->g_beta, h->g_alpha, h->g_beta, nullptr, s);
@@ -1019,7 +1051,7 @@ int cv_bound_autotune(cv_bound* h, void* stream) {
           best = T;
         }
       }
-      (dir == 0 ? h->chain_bT : h->chain_fT) = best;
+      (dir == 0 ? h->chain_b : h->chain_f) = best;
     }
   }
   (void)hipEventDestroy(e0);
@@ -1031,11 +1063,11 @@ int cv_bound_autotune(cv_bound* h, void* stream) {
 
 int cv_bound_set_plan(cv_bound* h, int32_t chain_bwd, int32_t chain_fwd) {
   if (!h) return fail(CV_EINVAL, "null handle");
-  auto ok = [&](int T) { return T == 0 || ((T == 16 || T == 32) && h->chain_lo && chain_fits(h, T)); };
-  if (!ok(chain_bwd) || !ok(chain_fwd)) return fail(CV_EINVAL, "chain rows must be 0, 16 or 32 where a chain exists");
+  auto ok = [&](int c) { return c == 0 || (c == 1 && h->chain_lo); };
+  if (!ok(chain_bwd) || !ok(chain_fwd)) return fail(CV_EINVAL, "plan entries must be 0 or 1 (1 only where a chain exists)");
   if (chain_fwd && h->chain_lo + 1 > h->L - 1) return fail(CV_EINVAL, "this network has no adjoint chain");
-  h->chain_bT = chain_bwd;
-  h->chain_fT = chain_fwd;
+  h->chain_b = chain_bwd;
+  h->chain_f = chain_fwd;
   drop_graph(h);
   return CV_OK;
 }

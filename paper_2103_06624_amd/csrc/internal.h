@@ -68,7 +68,12 @@ constexpr int kChainMax = 12;
 struct ChainArgs {
   int nl;
   ChainLayer ly[kChainMax];
-  int ldk;  // LDS row stride (floats): 16-multiple + 4
+  int np;    // LDS pitch basis: widest LDS-resident operand rounded to 32
+  int ncw;   // output columns per chunk: that width rounded to 16
+  int ldk;   // LDS row stride of the resident rows (np + 4 floats)
+  int rb;    // 16-row MFMA blocks per workgroup (1..kChainRowBlocks)
+  int uw;    // 16x16 output units per wave: ceil(rb * ncw/16 / 8)
+  int grid;  // workgroups; rows divided evenly over them
   // back-substitution start: the top ReLU layer from C W(L)
   const float* CW;
   int64_t cw_pstride;
@@ -95,9 +100,13 @@ struct ChainArgs {
   Batch bt;
   Vars v;
 };
-size_t chain_smem_bytes(int T, int ldk);
-void launch_chain_bwd(int T, const ChainArgs& a, hipStream_t s);
-void launch_chain_fwd(int T, const ChainArgs& a, hipStream_t s);
+constexpr int kChainRowBlocks = 3;  // 16-row MFMA blocks per chain workgroup, at most
+size_t chain_smem_bytes(int rb, int np);
+bool chain_units_fit(int rb, int np, int ncw);
+int chain_units_per_wave(int rb, int ncw);
+void chain_prepare(int lds_bytes);
+void launch_chain_bwd(const ChainArgs& a, hipStream_t s);
+void launch_chain_fwd(const ChainArgs& a, hipStream_t s);
 
 // misc.hip
 void launch_prep_chord(const float* l, const float* u, float2* chord, float* adef, int64_t n, hipStream_t s);

@@ -105,11 +105,9 @@ def kink_free_rows(orc, b, alpha, beta, ulps=100.0):
     return ok
 
 
-@pytest.mark.parametrize("name", NAMES)
-def test_grad_parity(name):
-    say("grad parity", name)
-    wl, orc, pb = problem(name)
-    alpha, beta = cases.random_vars(orc, seed=2)
+def check_grad(name, orc, pb, alpha, beta):
+    """Bound and gradient of every subdomain against the oracle; gradient rows
+    are compared where no sign decision is within float32 reach of a kink."""
     lb, ga, gb = pb.grad(dev(alpha), dev(beta))
     lb, ga, gb = lb.cpu().numpy(), ga.cpu().numpy(), gb.cpu().numpy().reshape(-1, orc.m)
     checked = 0
@@ -133,10 +131,47 @@ def test_grad_parity(name):
     assert worst <= TOL
 
 
-@pytest.mark.parametrize("name", ["mlp_small", "mlp_deep", "cnn_base", "cnn_deep"])
-def test_optimize_parity(name):
-    say("optimize parity", name)
+@pytest.mark.parametrize("name", NAMES)
+def test_grad_parity(name):
+    say("grad parity", name)
     wl, orc, pb = problem(name)
+    alpha, beta = cases.random_vars(orc, seed=2)
+    check_grad(name, orc, pb, alpha, beta)
+
+
+@pytest.mark.parametrize("name,plan", [("mlp_deep", (0, 0)), ("mlp_deep", (1, 1)), ("mlp_deep", (1, 0)),
+                                       ("mlp_deep", (0, 1)), ("cnn_deep", (0, 0)), ("cnn_deep", (1, 0))])
+def test_plan_parity(name, plan):
+    """Fused dense chains and per-layer kernels, each direction on its own
+    (cnn_deep's dense tail is one layer deep: a back-substitution chain only)."""
+    say("plan parity", name, plan)
+    wl, orc, pb = problem(name)
+    pb.set_plan(*plan)
+    alpha, beta = cases.random_vars(orc, seed=6)
+    lb = pb.eval(dev(alpha), dev(beta)).cpu().numpy()
+    ref = np.stack([orc.eval(b, alpha, beta) for b in range(orc.B)])
+    assert guarded_rel(lb, ref).max() <= TOL
+    check_grad(name, orc, pb, alpha, beta)
+
+
+def test_plan_rejects_bad_values():
+    from paper_2103_06624_amd.binding import CvError
+    wl, orc, pb = problem("mlp_small")
+    for bad in [(2, 0), (0, -1), (16, 16)]:
+        with pytest.raises(CvError):
+            pb.set_plan(*bad)
+    wl, orc, pb = problem("cnn_deep")
+    with pytest.raises(CvError):
+        pb.set_plan(1, 1)  # no adjoint chain above a single dense layer
+
+
+@pytest.mark.parametrize("name,plan", [("mlp_small", None), ("mlp_deep", None), ("cnn_base", None),
+                                       ("cnn_deep", None), ("mlp_deep", (0, 0)), ("cnn_deep", (0, 0))])
+def test_optimize_parity(name, plan):
+    say("optimize parity", name, plan)
+    wl, orc, pb = problem(name)
+    if plan is not None:
+        pb.set_plan(*plan)
     a = pb.alpha_init()
     b = pb.zeros_beta()
     best, last = pb.optimize(a, b, iters=20, lr_alpha=0.01, lr_beta=0.05, decay=0.98)
@@ -280,3 +315,30 @@ def test_full_size_sampled(name):
         e1.append(guarded_rel(best[d], rbest).max())
     say(name, "full-size eval err", max(e0), "opt err", max(e1))
     assert max(e0) <= TOL and max(e1) <= TOL
+
+
+@pytest.mark.parametrize("n_dom", [600, 1500, 2000])
+def test_chain_row_blocks(n_dom):
+    """Batch sizes that give the fused chain 2 and 3 row blocks per workgroup,
+    the latter with more workgroups than compute units; sampled subdomains
+    checked."""
+    say("chain row blocks", n_dom)
+    from paper_2103_06624_amd.api import BoundProblem
+    wl, lo, up, _, _, orc = cases.case("mlp_deep", n_dom=n_dom)
+    pb = BoundProblem.from_workload(wl, lo, up)
+    pb.set_plan(1, 1)
+    alpha, beta = cases.random_vars(orc, seed=9)
+    lb = pb.eval(dev(alpha), dev(beta)).cpu().numpy()
+    lbg, ga, gb = pb.grad(dev(alpha), dev(beta))
+    lbg, ga = lbg.cpu().numpy(), ga.cpu().numpy()
+    for d in sample_doms(orc, 6, seed=n_dom):
+        g, ra, _ = orc.grad(d, alpha, beta)
+        assert guarded_rel(lb[d], g).max() <= TOL
+        assert guarded_rel(lbg[d], g).max() <= TOL
+        ok = kink_free_rows(orc, d, alpha, beta)
+        U = ra.shape[0] // orc.m
+        a_gpu = ga[orc.alpha_off[d]:orc.alpha_off[d + 1]].reshape(orc.m, U)
+        a_ref = ra.reshape(orc.m, U)
+        for k in np.nonzero(ok)[0]:
+            scale = max(1.0, np.abs(a_ref[k]).max(initial=0))
+            assert np.abs(a_gpu[k] - a_ref[k]).max(initial=0) / scale <= TOL
