@@ -342,3 +342,47 @@ def test_chain_row_blocks(n_dom):
         for k in np.nonzero(ok)[0]:
             scale = max(1.0, np.abs(a_ref[k]).max(initial=0))
             assert np.abs(a_gpu[k] - a_ref[k]).max(initial=0) / scale <= TOL
+
+
+def test_grad_matches_central_fd_of_oracle():
+    """GPU gradient entries against central finite differences (h = 1e-3) of
+    the FP64 oracle's bound, on 8 subdomains of the deep MLP.  A coordinate
+    is compared where the bound is smooth across the step (the h and h/2
+    differences agree), i.e. no sign decision flips inside [x - h, x + h]."""
+    say("grad vs central FD")
+    wl, orc, pb = problem("mlp_deep")
+    alpha, beta = cases.random_vars(orc, seed=11)
+    alpha = alpha.astype(np.float64)
+    beta = beta.astype(np.float64)
+    _, ga, gb = pb.grad(dev(alpha), dev(beta))
+    ga, gb = ga.cpu().numpy().astype(np.float64), gb.cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(12)
+    compared = tried = 0
+    worst = 0.0
+    for d in sample_doms(orc, 8, seed=13):
+        U = (orc.alpha_off[d + 1] - orc.alpha_off[d]) // orc.m
+        coords = [("a", int(orc.alpha_off[d] + rng.integers(orc.alpha_off[d + 1] - orc.alpha_off[d])))
+                  for _ in range(6)]
+        nb = int(orc.ptr[d + 1] - orc.ptr[d])
+        coords += [("b", int((orc.ptr[d] + rng.integers(nb)) * orc.m + rng.integers(orc.m))) for _ in range(3)]
+        for kind, i in coords:
+            x = alpha if kind == "a" else beta
+            row = (i - orc.alpha_off[d]) // U if kind == "a" else i % orc.m
+
+            def f(delta):
+                y = x.copy()
+                y[i] += delta
+                return (orc.eval(d, y, beta) if kind == "a" else orc.eval(d, alpha, y))[row]
+
+            h = 1e-3
+            fd1 = (f(h) - f(-h)) / (2 * h)
+            fd2 = (f(h / 2) - f(-h / 2)) / h
+            tried += 1
+            if abs(fd1 - fd2) > 1e-6 * max(1.0, abs(fd1)):
+                continue  # a kink inside the step
+            g = (ga if kind == "a" else gb)[i]
+            worst = max(worst, abs(g - fd1) / max(1.0, abs(fd1)))
+            compared += 1
+    say("FD coordinates compared", compared, "of", tried, "worst", worst)
+    assert compared >= tried // 2
+    assert worst <= TOL
