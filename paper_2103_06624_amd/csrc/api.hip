@@ -553,7 +553,8 @@ int ensure_opt(cv_bound* h) {
 
 std::string cfg_name(int cfg) {
   const GemmCfg& c = kGemmCfgs[cfg];
-  return std::to_string(c.bm) + "x" + std::to_string(c.bn) + "x" + std::to_string(c.bk);
+  return std::to_string(c.bm) + "x" + std::to_string(c.bn) + "x" + std::to_string(c.bk) +
+         (c.occ ? "w" + std::to_string(c.occ) : std::string());
 }
 
 Epi make_epi(const cv_bound* h) {

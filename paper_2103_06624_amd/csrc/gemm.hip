@@ -71,8 +71,11 @@ __device__ __forceinline__ float4 load_b4(const float* __restrict__ Bt, int ldb,
 // consecutive k of one row with one b128 read and feeds them to 4 MFMAs (k
 // slot g of MFMA t holds k = 4g + t, identically for both operands, so the
 // products pair up correctly).
-template <int BM, int BN, int BK, int MODE>
-__global__ __launch_bounds__(256) void gemm_nt(const float* __restrict__ A, int lda, const float* __restrict__ Bt,
+// OCC > 0 asks the compiler for at least OCC waves per SIMD (registers capped
+// accordingly): with OCC = 8 a 32x32 tiling of ~10^4 x 200 is resident in one
+// round instead of two.
+template <int BM, int BN, int BK, int MODE, int OCC>
+__global__ __launch_bounds__(256, OCC) void gemm_nt(const float* __restrict__ A, int lda, const float* __restrict__ Bt,
                                                int ldb, int M, int N, int K, int last, Batch bt, Vars v, Epi e) {
   constexpr int LDK = BK + 4;  // padded LDS row: LDK/4 odd, conflict-free b128 reads
   constexpr int WM = BM / 2, WN = BN / 2;
@@ -301,49 +304,56 @@ __global__ __launch_bounds__(256) void gemm_nt(const float* __restrict__ A, int 
   }
 }
 
-template <int BM, int BN, int BK>
+template <int BM, int BN, int BK, int OCC>
 void launch_cfg(int mode, const GemmArgs& g, hipStream_t s) {
   const int tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
   dim3 grid(tiles), block(256);
   switch (mode) {
     case kBwdRelax:
-      gemm_nt<BM, BN, BK, kBwdRelax><<<grid, block, 0, s>>>(g.A, g.lda, g.Bt, g.ldb, g.M, g.N, g.K, g.last, g.bt, g.v,
-                                                            g.e);
+      gemm_nt<BM, BN, BK, kBwdRelax, OCC><<<grid, block, 0, s>>>(g.A, g.lda, g.Bt, g.ldb, g.M, g.N, g.K, g.last, g.bt,
+                                                                 g.v, g.e);
       break;
     case kBwdConc:
-      gemm_nt<BM, BN, BK, kBwdConc><<<grid, block, 0, s>>>(g.A, g.lda, g.Bt, g.ldb, g.M, g.N, g.K, g.last, g.bt, g.v,
-                                                           g.e);
+      gemm_nt<BM, BN, BK, kBwdConc, OCC><<<grid, block, 0, s>>>(g.A, g.lda, g.Bt, g.ldb, g.M, g.N, g.K, g.last, g.bt,
+                                                                g.v, g.e);
       break;
     case kFwdX:
-      gemm_nt<BM, BN, BK, kFwdX><<<grid, block, 0, s>>>(g.A, g.lda, g.Bt, g.ldb, g.M, g.N, g.K, g.last, g.bt, g.v, g.e);
+      gemm_nt<BM, BN, BK, kFwdX, OCC><<<grid, block, 0, s>>>(g.A, g.lda, g.Bt, g.ldb, g.M, g.N, g.K, g.last, g.bt, g.v,
+                                                             g.e);
       break;
     default:
-      gemm_nt<BM, BN, BK, kFwd><<<grid, block, 0, s>>>(g.A, g.lda, g.Bt, g.ldb, g.M, g.N, g.K, g.last, g.bt, g.v, g.e);
+      gemm_nt<BM, BN, BK, kFwd, OCC><<<grid, block, 0, s>>>(g.A, g.lda, g.Bt, g.ldb, g.M, g.N, g.K, g.last, g.bt, g.v,
+                                                            g.e);
       break;
   }
 }
 
 }  // namespace
 
-const GemmCfg kGemmCfgs[kNumGemmCfgs] = {{64, 64, 16}, {64, 32, 16}, {32, 64, 16}, {128, 64, 16}, {128, 32, 16},
-                                         {32, 32, 16}, {32, 32, 32}, {32, 32, 64}, {64, 32, 32}, {32, 64, 32},
-                                         {64, 64, 32}, {64, 32, 64}, {32, 64, 64}};
+const GemmCfg kGemmCfgs[kNumGemmCfgs] = {
+    {64, 64, 16, 0}, {64, 32, 16, 0}, {32, 64, 16, 0}, {128, 64, 16, 0}, {128, 32, 16, 0}, {32, 32, 16, 0},
+    {32, 32, 32, 0}, {32, 32, 64, 0}, {64, 32, 32, 0}, {32, 64, 32, 0},  {64, 64, 32, 0},  {64, 32, 64, 0},
+    {32, 64, 64, 0}, {32, 32, 16, 8}, {32, 32, 32, 8}, {64, 32, 16, 6}, {32, 64, 16, 6}};
 
 void launch_gemm(int cfg, int mode, const GemmArgs& g, hipStream_t s) {
   switch (cfg) {
-    case 0: launch_cfg<64, 64, 16>(mode, g, s); break;
-    case 1: launch_cfg<64, 32, 16>(mode, g, s); break;
-    case 2: launch_cfg<32, 64, 16>(mode, g, s); break;
-    case 3: launch_cfg<128, 64, 16>(mode, g, s); break;
-    case 4: launch_cfg<128, 32, 16>(mode, g, s); break;
-    case 5: launch_cfg<32, 32, 16>(mode, g, s); break;
-    case 6: launch_cfg<32, 32, 32>(mode, g, s); break;
-    case 7: launch_cfg<32, 32, 64>(mode, g, s); break;
-    case 8: launch_cfg<64, 32, 32>(mode, g, s); break;
-    case 9: launch_cfg<32, 64, 32>(mode, g, s); break;
-    case 10: launch_cfg<64, 64, 32>(mode, g, s); break;
-    case 11: launch_cfg<64, 32, 64>(mode, g, s); break;
-    default: launch_cfg<32, 64, 64>(mode, g, s); break;
+    case 0: launch_cfg<64, 64, 16, 0>(mode, g, s); break;
+    case 1: launch_cfg<64, 32, 16, 0>(mode, g, s); break;
+    case 2: launch_cfg<32, 64, 16, 0>(mode, g, s); break;
+    case 3: launch_cfg<128, 64, 16, 0>(mode, g, s); break;
+    case 4: launch_cfg<128, 32, 16, 0>(mode, g, s); break;
+    case 5: launch_cfg<32, 32, 16, 0>(mode, g, s); break;
+    case 6: launch_cfg<32, 32, 32, 0>(mode, g, s); break;
+    case 7: launch_cfg<32, 32, 64, 0>(mode, g, s); break;
+    case 8: launch_cfg<64, 32, 32, 0>(mode, g, s); break;
+    case 9: launch_cfg<32, 64, 32, 0>(mode, g, s); break;
+    case 10: launch_cfg<64, 64, 32, 0>(mode, g, s); break;
+    case 11: launch_cfg<64, 32, 64, 0>(mode, g, s); break;
+    case 12: launch_cfg<32, 64, 64, 0>(mode, g, s); break;
+    case 13: launch_cfg<32, 32, 16, 8>(mode, g, s); break;
+    case 14: launch_cfg<32, 32, 32, 8>(mode, g, s); break;
+    case 15: launch_cfg<64, 32, 16, 6>(mode, g, s); break;
+    default: launch_cfg<32, 64, 16, 6>(mode, g, s); break;
   }
 }
 

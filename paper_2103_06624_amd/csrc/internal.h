@@ -18,8 +18,9 @@ enum Mode {
 
 struct GemmCfg {
   int bm, bn, bk;
+  int occ;  // minimum waves per SIMD requested from the compiler (0: its choice)
 };
-constexpr int kNumGemmCfgs = 13;
+constexpr int kNumGemmCfgs = 17;
 extern const GemmCfg kGemmCfgs[kNumGemmCfgs];
 
 struct GemmArgs {
