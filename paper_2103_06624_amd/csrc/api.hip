@@ -145,6 +145,8 @@ struct cv_bound {
   float* acomp = nullptr;
   uint64_t* xpos = nullptr;
   uint64_t* xneg = nullptr;
+  float* xdense = nullptr;  // x* per row when the first layer is dense
+  int ldx = 0;
   float* g_alpha = nullptr;
   float* g_beta = nullptr;
   float* adam = nullptr;  // [2 n_alpha + 2 n_beta]
@@ -501,7 +503,7 @@ int build(cv_bound* h, const cv_layer* layers, int n_layers, int P, const float*
     if (h->layers[i - 1].type != CV_LAYER_DENSE) continue;
     const int N_b = h->dims[i - 1], K_b = h->dims[i];
     h->cfg[i - 1] = cfg_for(h, i - 1 >= 1 ? kBwdRelax : kBwdConc, h->R, N_b, K_b, gemm_default_cfg(h->R, N_b));
-    h->cfg[n_layers + i - 1] = cfg_for(h, i == 1 ? kFwdX : kFwd, h->R, K_b, N_b, gemm_default_cfg(h->R, K_b));
+    h->cfg[n_layers + i - 1] = cfg_for(h, kFwd, h->R, K_b, N_b, gemm_default_cfg(h->R, K_b));
   }
   // dense layers fused by the chain kernels (LDS-resident widths up to kChainWidth)
   h->chain_lo = 0;
@@ -534,6 +536,11 @@ int ensure_grad(cv_bound* h) {
   if ((rc = h->mem.alloc(&h->acomp, h->n_alpha)) || (rc = h->mem.alloc(&h->xpos, (size_t)h->R * h->w64)) ||
       (rc = h->mem.alloc(&h->xneg, (size_t)h->R * h->w64)))
     return rc;
+  if (h->layers[0].type == CV_LAYER_DENSE) {
+    // the first adjoint step reads x* as a plain GEMM operand
+    h->ldx = r4(h->d0);
+    if ((rc = h->mem.alloc(&h->xdense, (size_t)h->R * h->ldx))) return rc;
+  }
   return CV_OK;
 }
 
@@ -600,8 +607,12 @@ int enqueue_bwd(cv_bound* h, const float* alpha, const float* beta, bool grad, f
   v.alpha = alpha;
   v.beta = beta;
   v.acomp = grad ? h->acomp : nullptr;
-  v.xpos = grad ? h->xpos : nullptr;
-  v.xneg = grad ? h->xneg : nullptr;
+  // x* for the adjoint: dense rows for a dense first layer, sign planes for a convolution
+  const bool dense1 = h->layers[0].type == CV_LAYER_DENSE;
+  v.xpos = grad && !dense1 ? h->xpos : nullptr;
+  v.xneg = grad && !dense1 ? h->xneg : nullptr;
+  v.xdense = grad && dense1 ? h->xdense : nullptr;
+  v.ldx = h->ldx;
   Profiler* pf = h->prof;
   if (h->R == 0) return CV_OK;
   int cur = 0, slot = 1, i_next = L - 1;
@@ -642,7 +653,8 @@ int enqueue_bwd(cv_bound* h, const float* alpha, const float* beta, bool grad, f
     ca.v = v;
     const double rows = h->R;
     if (pf) pf->begin("chain_bwd", chain_flops(h),
-                      rows * h->dims[L - 1] * 4.0 + (lo == 1 ? rows * h->d0 / 4.0 : rows * h->dims[lo - 1] * 4.0) +
+                      rows * h->dims[L - 1] * 4.0 +
+                          (lo == 1 && !v.xdense ? rows * h->d0 / 4.0 : rows * h->dims[lo - 1] * 4.0) +
                           (double)h->B * (h->nd - (lo >= 2 ? h->offs[lo - 2] : 0)) * 2.0);
     launch_chain_bwd(ca, s);
     if (pf) pf->end();
@@ -686,7 +698,7 @@ int enqueue_bwd(cv_bound* h, const float* alpha, const float* beta, bool grad, f
     }
     const double rows = h->R;
     const int N = h->dims[i - 1], K = h->dims[i];
-    const double io = rows * K * 4.0 + (mode == kBwdRelax ? rows * N * 4.0 : rows * N / 4.0) +
+    const double io = rows * K * 4.0 + (mode == kBwdRelax || v.xdense ? rows * N * 4.0 : rows * N / 4.0) +
                       (double)h->B * N * 2.0 +
                       (mode == kBwdRelax ? h->unst_rows_per_layer[i - 2] * 4.0 * (grad ? 2 : 1) : 0.0);
     if (ly.type == CV_LAYER_DENSE) {
@@ -749,22 +761,24 @@ int enqueue_fwd(cv_bound* h, const float* alpha, const float* beta, float* ga, f
   const int i_chain = h->chain_f ? h->chain_lo + 1 : L;
   for (int i = 1; i <= L - 1 && i < i_chain; ++i) {
     const DevLayer& ly = h->layers[i - 1];
-    const int mode = i == 1 ? kFwdX : kFwd;
+    const bool xd = i == 1 && ly.type == CV_LAYER_DENSE;  // x* read as a dense operand
+    const int mode = i == 1 && !xd ? kFwdX : kFwd;
     const int last = i == L - 1;
     Epi e = make_epi(h);
     e.layer_off = h->offs[i - 1];
     e.bias = ly.bias;
     e.n = h->dims[i];
     e.out = h->act[i & 1];
-    const float* in = i == 1 ? nullptr : h->act[(i - 1) & 1];
+    const float* in = i == 1 ? (xd ? h->xdense : nullptr) : h->act[(i - 1) & 1];
+    const int lda = xd ? h->ldx : h->ldact;
     const double rows = h->R;
     const int N = h->dims[i], K = h->dims[i - 1];
-    const double io = (i == 1 ? rows * K / 4.0 : rows * K * 4.0) + (last ? 0.0 : rows * N * 4.0) +
+    const double io = (i == 1 && !xd ? rows * K / 4.0 : rows * K * 4.0) + (last ? 0.0 : rows * N * 4.0) +
                       (double)h->B * N * 2.0 + h->unst_rows_per_layer[i - 1] * 4.0 * 3;
     if (ly.type == CV_LAYER_DENSE) {
       const int c = h->cfg[L + i - 1] >= 0 ? h->cfg[L + i - 1] : 0;
-      GemmArgs g{in, h->ldact, ly.W, ly.ld_in, h->R, N, K, last, h->bt, v, e};
-      if (pf) pf->begin(std::string(mode == kFwdX ? "gemm_fwd_x_" : "gemm_fwd_") + cfg_name(c), 2.0 * rows * N * K,
+      GemmArgs g{in, lda, ly.W, ly.ld_in, h->R, N, K, last, h->bt, v, e};
+      if (pf) pf->begin(std::string(i == 1 ? "gemm_fwd_x_" : "gemm_fwd_") + cfg_name(c), 2.0 * rows * N * K,
                         io + (double)N * K * 4.0);
       launch_gemm(c, mode, g, s);
       if (pf) pf->end();
@@ -975,8 +989,11 @@ int cv_bound_autotune(cv_bound* h, void* stream) {
       v.acomp = h->acomp;
       v.galpha = h->g_alpha;
       v.gbeta = h->g_beta;
-      v.xpos = h->xpos;
-      v.xneg = h->xneg;
+      v.xpos = nullptr;
+      v.xneg = nullptr;
+      v.xdense = h->xdense;
+      v.ldx = h->ldx;
+      int lda = h->ldact;
       if (dir == 0) {
         mode = i - 1 >= 1 ? kBwdRelax : kBwdConc;
         N = h->dims[i - 1];
@@ -991,10 +1008,11 @@ int cv_bound_autotune(cv_bound* h, void* stream) {
         }
         e.slot0 = 1;
       } else {
-        mode = i == 1 ? kFwdX : kFwd;
+        mode = kFwd;  // a dense first layer reads x* as a dense operand
         N = h->dims[i];
         K = h->dims[i - 1];
-        A = h->act[0];
+        A = i == 1 ? h->xdense : h->act[0];
+        if (i == 1) lda = h->ldx;
         Bt = ly.W;
         ldb = ly.ld_in;
         e.layer_off = h->offs[i - 1];
@@ -1005,7 +1023,7 @@ int cv_bound_autotune(cv_bound* h, void* stream) {
       float best_ms = 1e30f;
       int best = -1;
       for (int c = 0; c < kNumGemmCfgs; ++c) {
-        GemmArgs g{A, h->ldact, Bt, ldb, h->R, N, K, dir == 1 && i == L - 1, h->bt, v, e};
+        GemmArgs g{A, lda, Bt, ldb, h->R, N, K, dir == 1 && i == L - 1, h->bt, v, e};
         for (int w = 0; w < 2; ++w) launch_gemm(c, mode, g, s);
         HIPCHK(hipEventRecord(e0, s));
         const int reps = 10;

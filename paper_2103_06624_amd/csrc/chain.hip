@@ -271,6 +271,7 @@ __device__ __forceinline__ void conc_phase(const ChainArgs& a, const RowInfo& ri
           *cst += conc_term(av[t], l8[t], u8[t]);
           bp |= (av[t] > 0.f ? 1u : 0u) << (q + t);
           bn |= (av[t] < 0.f ? 1u : 0u) << (q + t);
+          if (a.v.xdense) a.v.xdense[(int64_t)row * a.v.ldx + c] = xstar(av[t] > 0.f, av[t] < 0.f, l8[t], u8[t]);
         }
       }
     }

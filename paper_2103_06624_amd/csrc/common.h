@@ -50,8 +50,10 @@ struct Vars {
   float* acomp;        // [n_alpha] A at unstable neurons, written in grad passes (or null)
   float* galpha;       // [n_alpha] gradient out (fwd passes)
   float* gbeta;        // [nnz, m]
-  uint64_t* xpos;      // [n_rows, w64] bit set where A(0) > 0
+  uint64_t* xpos;      // [n_rows, w64] bit set where A(0) > 0 (convolution first layer)
   uint64_t* xneg;      // [n_rows, w64] bit set where A(0) < 0
+  float* xdense;       // [n_rows, ldx] the box minimiser x* itself (dense first layer)
+  int ldx;
   // Projected Adam fused into the adjoint (optimisation passes): when adam is
   // set, each gradient entry is applied in place by its owning (row, neuron)
   // instead of being written to galpha / gbeta.  alpha_w / beta_w alias alpha /

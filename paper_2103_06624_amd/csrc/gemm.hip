@@ -254,6 +254,7 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt(const float* __restrict__ A,
             }
           } else {
             if (ok) cst[i][r] += conc_term(a, ech[q].x, ech[q].y);
+            if (ok && v.xdense) v.xdense[(int64_t)row * v.ldx + col] = xstar(a > 0.f, a < 0.f, ech[q].x, ech[q].y);
             if (v.xpos) {
               const uint64_t mp = __ballot(ok && a > 0.f);
               const uint64_t mn = __ballot(ok && a < 0.f);
