@@ -561,7 +561,7 @@ int ensure_opt(cv_bound* h) {
 std::string cfg_name(int cfg) {
   const GemmCfg& c = kGemmCfgs[cfg];
   return std::to_string(c.bm) + "x" + std::to_string(c.bn) + "x" + std::to_string(c.bk) +
-         (c.occ ? "w" + std::to_string(c.occ) : std::string());
+         (c.occ ? "w" + std::to_string(c.occ) : std::string()) + (c.depth > 1 ? "d" + std::to_string(c.depth) : "");
 }
 
 Epi make_epi(const cv_bound* h) {

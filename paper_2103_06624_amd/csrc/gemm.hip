@@ -19,62 +19,34 @@ namespace cvb {
 
 namespace {
 
-template <int MODE>
-__device__ __forceinline__ float4 load_a4(const float* __restrict__ A, int lda, int row, int k, int M, int K,
-                                          const Batch& bt, const Vars& v) {
-  float4 r = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (row >= M || k >= K) return r;
-  if (MODE == kFwdX) {
-    // zhat(0) = x*, rebuilt from the sign planes of A(0) and the box
-    const int p = bt.prop[row / bt.m];
-    const uint64_t wp = v.xpos[(int64_t)row * bt.w64 + (k >> 6)] >> (k & 63);
-    const uint64_t wn = v.xneg[(int64_t)row * bt.w64 + (k >> 6)] >> (k & 63);
-    const float* xl = bt.xlo + (int64_t)p * bt.d0 + k;
-    const float* xu = bt.xhi + (int64_t)p * bt.d0 + k;
-    if (k + 3 < K && (bt.d0 & 3) == 0) {
-      const float4 l4 = *reinterpret_cast<const float4*>(xl);
-      const float4 u4 = *reinterpret_cast<const float4*>(xu);
-      r.x = xstar(wp & 1, wn & 1, l4.x, u4.x);
-      r.y = xstar((wp >> 1) & 1, (wn >> 1) & 1, l4.y, u4.y);
-      r.z = xstar((wp >> 2) & 1, (wn >> 2) & 1, l4.z, u4.z);
-      r.w = xstar((wp >> 3) & 1, (wn >> 3) & 1, l4.w, u4.w);
-      return r;
-    }
-    float t[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) t[q] = k + q < K ? xstar((wp >> q) & 1, (wn >> q) & 1, xl[q], xu[q]) : 0.f;
-    return make_float4(t[0], t[1], t[2], t[3]);
-  }
-  const float* src = A + (int64_t)row * lda + k;
-  if (k + 3 < K) return *reinterpret_cast<const float4*>(src);
-  r.x = src[0];
-  if (k + 1 < K) r.y = src[1];
-  if (k + 2 < K) r.z = src[2];
-  return r;
+// 4 consecutive elements [k, k+4) of row `row` of a K-contiguous matrix
+// (leading dimension ld >= K rounded up to 4, 16-byte aligned rows).  The
+// address is clamped into the matrix, so the load needs no per-lane branch;
+// mask4 zeroes what lies outside [0, nrows) x [0, K).  The two are separate
+// so that the mask (which needs the data) runs when the slab is parked in
+// LDS, not right after the load is issued.
+__device__ __forceinline__ float4 ld4(const float* __restrict__ P, int ld, int row, int nrows, int k, int K) {
+  const int K4 = (K + 3) & ~3;
+  return *reinterpret_cast<const float4*>(P + (int64_t)min(row, nrows - 1) * ld + min(k, K4 - 4));
 }
 
-__device__ __forceinline__ float4 load_b4(const float* __restrict__ Bt, int ldb, int n, int k, int N, int K) {
-  float4 r = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (n >= N || k >= K) return r;
-  const float* src = Bt + (int64_t)n * ldb + k;
-  if (k + 3 < K) return *reinterpret_cast<const float4*>(src);
-  r.x = src[0];
-  if (k + 1 < K) r.y = src[1];
-  if (k + 2 < K) r.z = src[2];
-  return r;
+__device__ __forceinline__ float4 mask4(float4 x, int row, int nrows, int k, int K) {
+  const bool rok = row < nrows;
+  x.x = rok && k < K ? x.x : 0.f;
+  x.y = rok && k + 1 < K ? x.y : 0.f;
+  x.z = rok && k + 2 < K ? x.z : 0.f;
+  x.w = rok && k + 3 < K ? x.w : 0.f;
+  return x;
 }
 
-// 256 threads = 4 waves in a 2x2 arrangement; each wave owns (BM/2)x(BN/2)
-// made of 16x16 MFMA blocks.  K advances BK at a time through double-buffered
-// LDS tiles (the next slab's global loads are in flight while this one's
-// MFMAs run, so a larger BK covers more latency); each lane reads 4
-// consecutive k of one row with one b128 read and feeds them to 4 MFMAs (k
-// slot g of MFMA t holds k = 4g + t, identically for both operands, so the
-// products pair up correctly).
 // OCC > 0 asks the compiler for at least OCC waves per SIMD (registers capped
 // accordingly): with OCC = 8 a 32x32 tiling of ~10^4 x 200 is resident in one
-// round instead of two.
-template <int BM, int BN, int BK, int MODE, int OCC>
+// round instead of two.  DEPTH = 2 keeps two slabs of global loads in flight
+// (two register sets, loads issued two slabs before they are parked in LDS):
+// a slab's MFMA work is far shorter than the load latency at these sizes.
+// Modes: kBwdRelax, kBwdConc, kFwd (the adjoint's first layer reads x* as a
+// dense operand).
+template <int BM, int BN, int BK, int MODE, int OCC, int DEPTH>
 __global__ __launch_bounds__(256, OCC) void gemm_nt(const float* __restrict__ A, int lda, const float* __restrict__ Bt,
                                                int ldb, int M, int N, int K, int last, Batch bt, Vars v, Epi e) {
   constexpr int LDK = BK + 4;  // padded LDS row: LDK/4 odd, conflict-free b128 reads
@@ -107,31 +79,34 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt(const float* __restrict__ A,
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-  float4 ra[A_LD], rb[B_LD];
-  auto gload = [&](int k0) {
+  struct Regs {
+    float4 a[A_LD], b[B_LD];
+  };
+  auto gload = [&](Regs& r, int k0) {
 #pragma unroll
     for (int t = 0; t < A_LD; ++t) {
-      const int idx = tid + t * 256;
-      ra[t] = (idx < BM * QK) ? load_a4<MODE>(A, lda, m0 + idx / QK, k0 + (idx % QK) * 4, M, K, bt, v)
-                              : make_float4(0.f, 0.f, 0.f, 0.f);
+      const int idx = min(tid + t * 256, BM * QK - 1);
+      r.a[t] = ld4(A, lda, m0 + idx / QK, M, k0 + (idx % QK) * 4, K);
     }
 #pragma unroll
     for (int t = 0; t < B_LD; ++t) {
-      const int idx = tid + t * 256;
-      rb[t] = (idx < BN * QK) ? load_b4(Bt, ldb, n0 + idx / QK, k0 + (idx % QK) * 4, N, K)
-                              : make_float4(0.f, 0.f, 0.f, 0.f);
+      const int idx = min(tid + t * 256, BN * QK - 1);
+      r.b[t] = ld4(Bt, ldb, n0 + idx / QK, N, k0 + (idx % QK) * 4, K);
     }
   };
-  auto sstore = [&](int buf) {
+  // threads past the slab repeat its last float4 (same value, same address)
+  auto sstore = [&](const Regs& r, int buf, int k0) {
 #pragma unroll
     for (int t = 0; t < A_LD; ++t) {
-      const int idx = tid + t * 256;
-      if (idx < BM * QK) *reinterpret_cast<float4*>(&As[buf][idx / QK][(idx % QK) * 4]) = ra[t];
+      const int idx = min(tid + t * 256, BM * QK - 1);
+      *reinterpret_cast<float4*>(&As[buf][idx / QK][(idx % QK) * 4]) =
+          mask4(r.a[t], m0 + idx / QK, M, k0 + (idx % QK) * 4, K);
     }
 #pragma unroll
     for (int t = 0; t < B_LD; ++t) {
-      const int idx = tid + t * 256;
-      if (idx < BN * QK) *reinterpret_cast<float4*>(&Bs[buf][idx / QK][(idx % QK) * 4]) = rb[t];
+      const int idx = min(tid + t * 256, BN * QK - 1);
+      *reinterpret_cast<float4*>(&Bs[buf][idx / QK][(idx % QK) * 4]) =
+          mask4(r.b[t], n0 + idx / QK, N, k0 + (idx % QK) * 4, K);
     }
   };
 
@@ -169,7 +144,9 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt(const float* __restrict__ A,
     }
 
   const int nk = (K + BK - 1) / BK;
-  gload(0);
+  Regs r0, r1;
+  gload(r0, 0);
+  if (DEPTH == 2) gload(r1, min(1, nk - 1) * BK);
 
 #pragma unroll
   for (int i = 0; i < FM; ++i)
@@ -202,11 +179,7 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt(const float* __restrict__ A,
         }
       }
 
-  sstore(0);
-  __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    const int buf = kt & 1;
-    if (kt + 1 < nk) gload((kt + 1) * BK);
+  auto compute = [&](int buf) {
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 16) {
       float4 fa[FM], fb[FN];
@@ -226,8 +199,36 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt(const float* __restrict__ A,
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i].w, fb[j].w, acc[i][j], 0, 0, 0);
         }
     }
-    if (kt + 1 < nk) sstore(buf ^ 1);
-    __syncthreads();
+  };
+
+  sstore(r0, 0, 0);
+  __syncthreads();
+  if (DEPTH == 1) {
+    for (int kt = 0; kt < nk; ++kt) {
+      const int buf = kt & 1;
+      if (kt + 1 < nk) gload(r0, (kt + 1) * BK);
+      compute(buf);
+      if (kt + 1 < nk) sstore(r0, buf ^ 1, (kt + 1) * BK);
+      __syncthreads();
+    }
+  } else {
+    // entering a pair of slabs kt, kt+1: slab kt in LDS buffer 0, slab kt+1
+    // in flight in r1.  Loads and stores are unconditional (slab index
+    // clamped: past the end they repeat the last slab into a buffer nobody
+    // reads again), so every load is consumed on every path and no load is
+    // left pending where its registers are reused.
+    for (int kt = 0; kt < nk; kt += 2) {
+      const int k2 = min(kt + 2, nk - 1) * BK, k3 = min(kt + 3, nk - 1) * BK;
+      gload(r0, k2);
+      compute(0);
+      sstore(r1, 1, min(kt + 1, nk - 1) * BK);
+      __syncthreads();
+      if (kt + 1 >= nk) break;
+      gload(r1, k3);
+      compute(1);
+      sstore(r0, 0, k2);
+      __syncthreads();
+    }
   }
 
   // ---- epilogue: lane holds rows 4*(lane/16)+r of each 16x16 block, column lane%16
@@ -305,26 +306,22 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt(const float* __restrict__ A,
   }
 }
 
-template <int BM, int BN, int BK, int OCC>
+template <int BM, int BN, int BK, int OCC, int DEPTH>
 void launch_cfg(int mode, const GemmArgs& g, hipStream_t s) {
   const int tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
   dim3 grid(tiles), block(256);
   switch (mode) {
     case kBwdRelax:
-      gemm_nt<BM, BN, BK, kBwdRelax, OCC><<<grid, block, 0, s>>>(g.A, g.lda, g.Bt, g.ldb, g.M, g.N, g.K, g.last, g.bt,
-                                                                 g.v, g.e);
+      gemm_nt<BM, BN, BK, kBwdRelax, OCC, DEPTH><<<grid, block, 0, s>>>(g.A, g.lda, g.Bt, g.ldb, g.M, g.N, g.K, g.last,
+                                                                        g.bt, g.v, g.e);
       break;
     case kBwdConc:
-      gemm_nt<BM, BN, BK, kBwdConc, OCC><<<grid, block, 0, s>>>(g.A, g.lda, g.Bt, g.ldb, g.M, g.N, g.K, g.last, g.bt,
-                                                                g.v, g.e);
-      break;
-    case kFwdX:
-      gemm_nt<BM, BN, BK, kFwdX, OCC><<<grid, block, 0, s>>>(g.A, g.lda, g.Bt, g.ldb, g.M, g.N, g.K, g.last, g.bt, g.v,
-                                                             g.e);
+      gemm_nt<BM, BN, BK, kBwdConc, OCC, DEPTH><<<grid, block, 0, s>>>(g.A, g.lda, g.Bt, g.ldb, g.M, g.N, g.K, g.last,
+                                                                       g.bt, g.v, g.e);
       break;
     default:
-      gemm_nt<BM, BN, BK, kFwd, OCC><<<grid, block, 0, s>>>(g.A, g.lda, g.Bt, g.ldb, g.M, g.N, g.K, g.last, g.bt, g.v,
-                                                            g.e);
+      gemm_nt<BM, BN, BK, kFwd, OCC, DEPTH><<<grid, block, 0, s>>>(g.A, g.lda, g.Bt, g.ldb, g.M, g.N, g.K, g.last,
+                                                                   g.bt, g.v, g.e);
       break;
   }
 }
@@ -332,29 +329,39 @@ void launch_cfg(int mode, const GemmArgs& g, hipStream_t s) {
 }  // namespace
 
 const GemmCfg kGemmCfgs[kNumGemmCfgs] = {
-    {64, 64, 16, 0}, {64, 32, 16, 0}, {32, 64, 16, 0}, {128, 64, 16, 0}, {128, 32, 16, 0}, {32, 32, 16, 0},
-    {32, 32, 32, 0}, {32, 32, 64, 0}, {64, 32, 32, 0}, {32, 64, 32, 0},  {64, 64, 32, 0},  {64, 32, 64, 0},
-    {32, 64, 64, 0}, {32, 32, 16, 8}, {32, 32, 32, 8}, {64, 32, 16, 6}, {32, 64, 16, 6}};
+    {64, 64, 16, 0, 1}, {64, 32, 16, 0, 1}, {32, 64, 16, 0, 1}, {128, 64, 16, 0, 1}, {128, 32, 16, 0, 1},
+    {32, 32, 16, 0, 1}, {32, 32, 32, 0, 1}, {32, 32, 64, 0, 1}, {64, 32, 32, 0, 1},  {32, 64, 32, 0, 1},
+    {64, 64, 32, 0, 1}, {64, 32, 64, 0, 1}, {32, 64, 64, 0, 1}, {32, 32, 16, 8, 1},  {32, 32, 32, 8, 1},
+    {64, 32, 16, 6, 1}, {32, 64, 16, 6, 1}, {32, 32, 16, 8, 2}, {32, 32, 32, 8, 2},  {32, 32, 32, 0, 2},
+    {64, 32, 32, 0, 2}, {32, 64, 32, 0, 2}, {64, 64, 32, 0, 2}, {64, 32, 16, 6, 2},  {32, 64, 16, 6, 2}};
 
 void launch_gemm(int cfg, int mode, const GemmArgs& g, hipStream_t s) {
   switch (cfg) {
-    case 0: launch_cfg<64, 64, 16, 0>(mode, g, s); break;
-    case 1: launch_cfg<64, 32, 16, 0>(mode, g, s); break;
-    case 2: launch_cfg<32, 64, 16, 0>(mode, g, s); break;
-    case 3: launch_cfg<128, 64, 16, 0>(mode, g, s); break;
-    case 4: launch_cfg<128, 32, 16, 0>(mode, g, s); break;
-    case 5: launch_cfg<32, 32, 16, 0>(mode, g, s); break;
-    case 6: launch_cfg<32, 32, 32, 0>(mode, g, s); break;
-    case 7: launch_cfg<32, 32, 64, 0>(mode, g, s); break;
-    case 8: launch_cfg<64, 32, 32, 0>(mode, g, s); break;
-    case 9: launch_cfg<32, 64, 32, 0>(mode, g, s); break;
-    case 10: launch_cfg<64, 64, 32, 0>(mode, g, s); break;
-    case 11: launch_cfg<64, 32, 64, 0>(mode, g, s); break;
-    case 12: launch_cfg<32, 64, 64, 0>(mode, g, s); break;
-    case 13: launch_cfg<32, 32, 16, 8>(mode, g, s); break;
-    case 14: launch_cfg<32, 32, 32, 8>(mode, g, s); break;
-    case 15: launch_cfg<64, 32, 16, 6>(mode, g, s); break;
-    default: launch_cfg<32, 64, 16, 6>(mode, g, s); break;
+    case 0: launch_cfg<64, 64, 16, 0, 1>(mode, g, s); break;
+    case 1: launch_cfg<64, 32, 16, 0, 1>(mode, g, s); break;
+    case 2: launch_cfg<32, 64, 16, 0, 1>(mode, g, s); break;
+    case 3: launch_cfg<128, 64, 16, 0, 1>(mode, g, s); break;
+    case 4: launch_cfg<128, 32, 16, 0, 1>(mode, g, s); break;
+    case 5: launch_cfg<32, 32, 16, 0, 1>(mode, g, s); break;
+    case 6: launch_cfg<32, 32, 32, 0, 1>(mode, g, s); break;
+    case 7: launch_cfg<32, 32, 64, 0, 1>(mode, g, s); break;
+    case 8: launch_cfg<64, 32, 32, 0, 1>(mode, g, s); break;
+    case 9: launch_cfg<32, 64, 32, 0, 1>(mode, g, s); break;
+    case 10: launch_cfg<64, 64, 32, 0, 1>(mode, g, s); break;
+    case 11: launch_cfg<64, 32, 64, 0, 1>(mode, g, s); break;
+    case 12: launch_cfg<32, 64, 64, 0, 1>(mode, g, s); break;
+    case 13: launch_cfg<32, 32, 16, 8, 1>(mode, g, s); break;
+    case 14: launch_cfg<32, 32, 32, 8, 1>(mode, g, s); break;
+    case 15: launch_cfg<64, 32, 16, 6, 1>(mode, g, s); break;
+    case 16: launch_cfg<32, 64, 16, 6, 1>(mode, g, s); break;
+    case 17: launch_cfg<32, 32, 16, 8, 2>(mode, g, s); break;
+    case 18: launch_cfg<32, 32, 32, 8, 2>(mode, g, s); break;
+    case 19: launch_cfg<32, 32, 32, 0, 2>(mode, g, s); break;
+    case 20: launch_cfg<64, 32, 32, 0, 2>(mode, g, s); break;
+    case 21: launch_cfg<32, 64, 32, 0, 2>(mode, g, s); break;
+    case 22: launch_cfg<64, 64, 32, 0, 2>(mode, g, s); break;
+    case 23: launch_cfg<64, 32, 16, 6, 2>(mode, g, s); break;
+    default: launch_cfg<32, 64, 16, 6, 2>(mode, g, s); break;
   }
 }
 

@@ -18,9 +18,10 @@ enum Mode {
 
 struct GemmCfg {
   int bm, bn, bk;
-  int occ;  // minimum waves per SIMD requested from the compiler (0: its choice)
+  int occ;    // minimum waves per SIMD requested from the compiler (0: its choice)
+  int depth;  // K slabs of global loads in flight (1 or 2)
 };
-constexpr int kNumGemmCfgs = 17;
+constexpr int kNumGemmCfgs = 25;
 extern const GemmCfg kGemmCfgs[kNumGemmCfgs];
 
 struct GemmArgs {
