@@ -166,6 +166,16 @@ int cv_bound_autotune(cv_bound *h, void *stream);
  * up to float32 summation order. */
 int cv_bound_set_plan(cv_bound *h, int32_t chain_bwd, int32_t chain_fwd);
 
+/* Concurrent sub-batches of cv_bound_optimize: the subdomains are split into
+ * nparts contiguous ranges of nearly equal size, each optimised by its own
+ * captured graph on its own stream, forked from and joined back into the
+ * caller's stream (the kernels of one range fill the gaps and tails of the
+ * other's).  Results are those of the same algorithm per subdomain; the
+ * float32 summation order may differ from one range to another.  1 disables
+ * the split.  cv_bound_init chooses 2 for batches of 4096 rows or more, else
+ * 1.  CV_EINVAL outside 1..4; more parts than subdomains are reduced. */
+int cv_bound_set_parts(cv_bound *h, int32_t nparts);
+
 /* Per-kernel timing of one gradient pass plus one plain evaluation, each
  * kernel launch bracketed by HIP events on `stream`, repeated `reps` times.
  * Fills up to max_out records; *n_out gets the number of distinct kernels.

@@ -152,6 +152,10 @@ class BoundProblem:
     def autotune(self):
         B.check(B.cv_bound_autotune(self.h, _stream()))
 
+    def set_parts(self, nparts):
+        """Concurrent sub-batches (streams) of optimize(); 1 disables the split."""
+        B.check(B.cv_bound_set_parts(self.h, nparts))
+
     def set_plan(self, chain_bwd, chain_fwd):
         """Fused dense chain (1) or one kernel per layer (0), per direction."""
         B.check(B.cv_bound_set_plan(self.h, chain_bwd, chain_fwd))

@@ -55,6 +55,7 @@ SIGNATURES = {
                                          _vp, _vp, ctypes.c_int32, _vp, _vp, _vp]),
     "cv_bound_autotune": (ctypes.c_int, [_vp, _vp]),
     "cv_bound_set_plan": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32]),
+    "cv_bound_set_parts": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "cv_bound_profile": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32, ctypes.POINTER(cv_kernel_stat),
                                         ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _vp]),
     "cv_bound_destroy": (None, [_vp]),
@@ -102,6 +103,7 @@ cv_bound_grad = _fn("cv_bound_grad")
 cv_bound_optimize = _fn("cv_bound_optimize")
 cv_bound_autotune = _fn("cv_bound_autotune")
 cv_bound_set_plan = _fn("cv_bound_set_plan")
+cv_bound_set_parts = _fn("cv_bound_set_parts")
 cv_bound_profile = _fn("cv_bound_profile")
 cv_bound_destroy = _fn("cv_bound_destroy")
 cv_last_error = _fn("cv_last_error")

@@ -160,11 +160,30 @@ struct cv_bound {
   int chain_lo = 0;
   int chain_b = 0, chain_f = 0;
   int chain_np = 0, chain_ncw = 0, chain_rb = 0, chain_uw = 0, chain_grid = 0;  // chain geometry (plan_chain)
+  // concurrent sub-batches for the optimiser: the subdomains split into
+  // nparts contiguous ranges, each its own handle, graph and stream
+  struct Inputs;
+  std::unique_ptr<Inputs> in;  // host copy of the init arguments, to build parts
+  std::vector<cv_bound*> parts;
+  std::vector<int> part_dom;  // [nparts + 1] subdomain boundaries
+  std::vector<hipStream_t> pstream;
+  std::vector<hipEvent_t> pev;  // [nparts + 1]
   // optimisation graph
   hipStream_t cap = nullptr;
   hipGraphExec_t gexec = nullptr;
   GraphKey gkey;
   Profiler* prof = nullptr;
+};
+
+struct cv_bound::Inputs {
+  std::vector<cv_layer> layers;
+  std::vector<std::vector<float>> w, b;
+  int P = 0, m = 0;
+  std::vector<float> xlo, xhi, C, l, u;
+  std::vector<int32_t> prop;
+  std::vector<int64_t> sptr;
+  std::vector<int32_t> slayer, sneuron;
+  std::vector<int8_t> sside;
 };
 
 namespace {
@@ -188,6 +207,8 @@ int cfg_for(const cv_bound* h, int mode, int M, int N, int K, int fallback) {
   (void)h;
 }
 
+constexpr int kMaxParts = 4;             // concurrent sub-batches of the optimiser, at most
+constexpr int kPartsMinRows = 4096;      // default: two sub-batches from this many rows on
 constexpr int kChainWidth = 256;         // widest LDS-resident layer of a chain
 constexpr int kLdsBytes = 160 * 1024;    // LDS per workgroup on gfx950
 constexpr int kChainStaticLds = 64 * 32; // row-info table of the chain kernels (upper bound)
@@ -823,11 +844,22 @@ int enqueue_fwd(cv_bound* h, const float* alpha, const float* beta, float* ga, f
   return CV_OK;
 }
 
+// Adam moments: first / second moments of alpha and of beta (all null: the
+// handle's own zeroed state).
+struct AdamPtrs {
+  float *ma = nullptr, *va = nullptr, *mb = nullptr, *vb = nullptr;
+};
+
 int enqueue_opt(cv_bound* h, int iters, float lr_a, float lr_b, float decay, float* alpha, float* beta,
-                float* adam_state, int step0, float* lb_best, float* lb_last, hipStream_t s) {
+                AdamPtrs ap, int step0, float* lb_best, float* lb_last, hipStream_t s) {
   const int64_t nb = h->nnz * h->m;
-  float* st = adam_state ? adam_state : h->adam;
-  if (!adam_state) launch_fill(h->adam, 0.f, 2 * h->n_alpha + 2 * nb, s);
+  if (!ap.ma) {
+    launch_fill(h->adam, 0.f, 2 * h->n_alpha + 2 * nb, s);
+    ap.ma = h->adam;
+    ap.va = h->adam + h->n_alpha;
+    ap.mb = h->adam + 2 * h->n_alpha;
+    ap.vb = h->adam + 2 * h->n_alpha + nb;
+  }
   int rc;
   for (int t = 0; t < iters; ++t) {
     if ((rc = enqueue_bwd(h, alpha, beta, true, nullptr, lb_best, t == 0, s))) return rc;
@@ -838,10 +870,10 @@ int enqueue_opt(cv_bound* h, int iters, float lr_a, float lr_b, float decay, flo
     const double sc = std::pow((double)decay, tt);
     ad.lr_a = (float)(lr_a * sc);
     ad.lr_b = (float)(lr_b * sc);
-    ad.ma = st;
-    ad.va = st + h->n_alpha;
-    ad.mb = st + 2 * h->n_alpha;
-    ad.vb = st + 2 * h->n_alpha + nb;
+    ad.ma = ap.ma;
+    ad.va = ap.va;
+    ad.mb = ap.mb;
+    ad.vb = ap.vb;
     if ((rc = enqueue_fwd(h, alpha, beta, nullptr, nullptr, &ad, s))) return rc;
   }
   if ((rc = enqueue_bwd(h, alpha, beta, false, lb_last, lb_best, iters == 0, s))) return rc;
@@ -853,6 +885,151 @@ void drop_graph(cv_bound* h) {
   if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
   h->gexec = nullptr;
   h->gkey.v.clear();
+}
+
+// The whole optimisation loop of one handle, captured once in a HIP graph
+// (keyed by the arguments) and replayed on `s`.
+int optimize_one(cv_bound* h, int iters, float lr_alpha, float lr_beta, float lr_decay, float* alpha, float* beta,
+                 AdamPtrs ap, int step0, float* lb_best, float* lb_last, hipStream_t s) {
+  int rc = ensure_opt(h);
+  if (rc) return rc;
+  if (h->R == 0) return CV_OK;
+  GraphKey key;
+  float fl[3] = {lr_alpha, lr_beta, lr_decay};
+  uint32_t fb[3];
+  std::memcpy(fb, fl, sizeof(fb));
+  key.v = {(uintptr_t)alpha, (uintptr_t)beta, (uintptr_t)ap.ma, (uintptr_t)ap.va, (uintptr_t)ap.mb, (uintptr_t)ap.vb,
+           (uintptr_t)lb_best, (uintptr_t)lb_last, (uintptr_t)iters, (uintptr_t)step0, fb[0], fb[1], fb[2]};
+  if (!h->gexec || !(h->gkey == key)) {
+    drop_graph(h);
+    if (!h->cap) HIPCHK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+    HIPCHK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+    rc = enqueue_opt(h, iters, lr_alpha, lr_beta, lr_decay, alpha, beta, ap, step0, lb_best, lb_last, h->cap);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(h->cap, &graph);
+    if (rc) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    if (e != hipSuccess) return fail(CV_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&h->gexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      h->gexec = nullptr;
+      return fail(CV_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
+    }
+    h->gkey = key;
+  }
+  HIPCHK(hipGraphLaunch(h->gexec, s));
+  return CV_OK;
+}
+
+void destroy_handle(cv_bound* h);
+
+void free_parts(cv_bound* h) {
+  for (cv_bound* q : h->parts) destroy_handle(q);
+  h->parts.clear();
+  h->part_dom.clear();
+  for (hipStream_t t : h->pstream) (void)hipStreamDestroy(t);
+  h->pstream.clear();
+  for (hipEvent_t e : h->pev) (void)hipEventDestroy(e);
+  h->pev.clear();
+}
+
+// Split the subdomains into n contiguous ranges of (nearly) equal size, each a
+// handle of its own built from the kept init arguments.
+int set_parts(cv_bound* h, int n) {
+  if ((int)h->parts.size() == n || (n == 1 && h->parts.empty())) return CV_OK;
+  free_parts(h);
+  if (n <= 1) return CV_OK;
+  const cv_bound::Inputs& in = *h->in;
+  h->part_dom.resize(n + 1);
+  for (int i = 0; i <= n; ++i) h->part_dom[i] = (int)((int64_t)h->B * i / n);
+  for (int i = 0; i < n; ++i) {
+    const int b0 = h->part_dom[i], b1 = h->part_dom[i + 1];
+    const int64_t s0 = in.sptr[b0], s1 = in.sptr[b1];
+    std::vector<int64_t> ptr(b1 - b0 + 1);
+    for (int b = b0; b <= b1; ++b) ptr[b - b0] = in.sptr[b] - s0;
+    std::unique_ptr<cv_bound> q(new cv_bound());
+    Spec sp;
+    sp.C = in.C.data();
+    int rc = build(q.get(), in.layers.data(), (int)in.layers.size(), in.P, in.xlo.data(), in.xhi.data(), in.m, sp,
+                   in.l.empty() ? nullptr : in.l.data(), in.u.empty() ? nullptr : in.u.data(), b1 - b0,
+                   in.prop.data() + b0, ptr.data(), in.slayer.data() + s0, in.sneuron.data() + s0,
+                   in.sside.data() + s0, nullptr);
+    if (rc) {
+      free_parts(h);
+      return rc;
+    }
+    q->chain_b = h->chain_b ? (q->chain_lo ? 1 : 0) : 0;
+    q->chain_f = h->chain_f ? (q->chain_lo && q->chain_lo + 1 <= q->L - 1 ? 1 : 0) : 0;
+    h->parts.push_back(q.release());
+    hipStream_t t = nullptr;
+    if (hipStreamCreateWithFlags(&t, hipStreamNonBlocking) != hipSuccess) {
+      free_parts(h);
+      return fail(CV_EDEVICE, "stream creation failed");
+    }
+    h->pstream.push_back(t);
+  }
+  for (int i = 0; i <= n; ++i) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      free_parts(h);
+      return fail(CV_EDEVICE, "event creation failed");
+    }
+    h->pev.push_back(e);
+  }
+  return CV_OK;
+}
+
+void destroy_handle(cv_bound* h) {
+  if (!h) return;
+  free_parts(h);
+  drop_graph(h);
+  if (h->cap) (void)hipStreamDestroy(h->cap);
+  delete h;
+}
+
+// Host copy of the init arguments (the caller's buffers may be freed after
+// cv_bound_init returns).
+void keep_inputs(cv_bound* h, const cv_layer* layers, int n_layers, int P, const float* x_lo, const float* x_hi,
+                 int m, const float* C, const float* l, const float* u, int B, const int32_t* dom_prop,
+                 const int64_t* split_ptr, const int32_t* split_layer, const int32_t* split_neuron,
+                 const int8_t* split_side) {
+  std::unique_ptr<cv_bound::Inputs> in(new cv_bound::Inputs());
+  in->layers.assign(layers, layers + n_layers);
+  in->w.resize(n_layers);
+  in->b.resize(n_layers);
+  for (int i = 0; i < n_layers; ++i) {
+    const cv_layer& ly = layers[i];
+    const size_t nw = ly.type == CV_LAYER_DENSE ? (size_t)ly.out_c * ly.in_c
+                                                 : (size_t)ly.out_c * ly.in_c * ly.kernel * ly.kernel;
+    in->w[i].assign(ly.weight, ly.weight + nw);
+    in->b[i].assign(ly.bias, ly.bias + ly.out_c);
+    in->layers[i].weight = in->w[i].data();
+    in->layers[i].bias = in->b[i].data();
+  }
+  const int d0 = h->d0, dL = h->dims[n_layers], nd = h->nd;
+  in->P = P;
+  in->m = m;
+  in->xlo.assign(x_lo, x_lo + (size_t)P * d0);
+  in->xhi.assign(x_hi, x_hi + (size_t)P * d0);
+  in->C.assign(C, C + (size_t)P * m * dL);
+  if (l) in->l.assign(l, l + (size_t)P * nd);
+  if (u) in->u.assign(u, u + (size_t)P * nd);
+  in->prop.assign(dom_prop, dom_prop + B);
+  in->sptr.assign(split_ptr, split_ptr + B + 1);
+  const int64_t nnz = split_ptr[B];
+  if (nnz > 0) {
+    in->slayer.assign(split_layer, split_layer + nnz);
+    in->sneuron.assign(split_neuron, split_neuron + nnz);
+    in->sside.assign(split_side, split_side + nnz);
+  }
+  // sliced pointers must stay valid for empty slices
+  in->slayer.push_back(0);
+  in->sneuron.push_back(0);
+  in->sside.push_back(1);
+  h->in = std::move(in);
 }
 
 }  // namespace
@@ -879,6 +1056,11 @@ int cv_bound_init(cv_bound** out, const cv_layer* layers, int32_t n_layers, int3
   int rc = build(h.get(), layers, n_layers, n_props, x_lo, x_hi, m, sp, l, u, n_dom, dom_prop, split_ptr,
                  split_layer, split_neuron, split_side, (hipStream_t)stream);
   if (rc) return rc;
+  keep_inputs(h.get(), layers, n_layers, n_props, x_lo, x_hi, m, C, l, u, n_dom, dom_prop, split_ptr, split_layer,
+              split_neuron, split_side);
+  // large batches: two concurrent halves in the optimiser (their kernels
+  // overlap each other's tails and launch gaps)
+  if (h->R >= kPartsMinRows && (rc = set_parts(h.get(), 2))) return rc;
   *out = h.release();
   return CV_OK;
 }
@@ -930,38 +1112,39 @@ int cv_bound_optimize(cv_bound* h, int32_t iters, float lr_alpha, float lr_beta,
   if (!h || !lb_best || (!alpha && h->n_alpha > 0) || (!beta && h->nnz > 0)) return fail(CV_EINVAL, "null argument");
   if (iters < 0 || step0 < 0 || !std::isfinite(lr_alpha) || !std::isfinite(lr_beta) || !std::isfinite(lr_decay))
     return fail(CV_EINVAL, "bad optimiser settings");
-  int rc = ensure_opt(h);
-  if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
   if (h->R == 0) return CV_OK;
-  GraphKey key;
-  float fl[3] = {lr_alpha, lr_beta, lr_decay};
-  uint32_t fb[3];
-  std::memcpy(fb, fl, sizeof(fb));
-  key.v = {(uintptr_t)alpha, (uintptr_t)beta, (uintptr_t)adam_state, (uintptr_t)lb_best, (uintptr_t)lb_last,
-           (uintptr_t)iters, (uintptr_t)step0, fb[0], fb[1], fb[2]};
-  if (!h->gexec || !(h->gkey == key)) {
-    drop_graph(h);
-    if (!h->cap) HIPCHK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
-    HIPCHK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
-    rc = enqueue_opt(h, iters, lr_alpha, lr_beta, lr_decay, alpha, beta, adam_state, step0, lb_best, lb_last, h->cap);
-    hipGraph_t graph = nullptr;
-    hipError_t e = hipStreamEndCapture(h->cap, &graph);
-    if (rc) {
-      if (graph) (void)hipGraphDestroy(graph);
-      return rc;
-    }
-    if (e != hipSuccess) return fail(CV_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
-    e = hipGraphInstantiate(&h->gexec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    if (e != hipSuccess) {
-      h->gexec = nullptr;
-      return fail(CV_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
-    }
-    h->gkey = key;
+  AdamPtrs ap;
+  if (adam_state) {
+    const int64_t nb = h->nnz * h->m;
+    ap = {adam_state, adam_state + h->n_alpha, adam_state + 2 * h->n_alpha, adam_state + 2 * h->n_alpha + nb};
   }
-  HIPCHK(hipGraphLaunch(h->gexec, s));
+  const int np = (int)h->parts.size();
+  if (np <= 1) return optimize_one(h, iters, lr_alpha, lr_beta, lr_decay, alpha, beta, ap, step0, lb_best, lb_last, s);
+  // fork: every part waits for the caller's stream, runs on its own stream;
+  // join: the caller's stream waits for every part
+  HIPCHK(hipEventRecord(h->pev[np], s));
+  for (int i = 0; i < np; ++i) {
+    cv_bound* q = h->parts[i];
+    const int b0 = h->part_dom[i];
+    const int64_t a0 = h->h_aoff[b0], s0 = h->in->sptr[b0] * h->m, r0 = (int64_t)b0 * h->m;
+    AdamPtrs pq;
+    if (ap.ma) pq = {ap.ma + a0, ap.va + a0, ap.mb + s0, ap.vb + s0};
+    HIPCHK(hipStreamWaitEvent(h->pstream[i], h->pev[np], 0));
+    int rc = optimize_one(q, iters, lr_alpha, lr_beta, lr_decay, alpha ? alpha + a0 : nullptr,
+                          beta ? beta + s0 : nullptr, pq, step0, lb_best + r0, lb_last ? lb_last + r0 : nullptr,
+                          h->pstream[i]);
+    if (rc) return rc;
+    HIPCHK(hipEventRecord(h->pev[i], h->pstream[i]));
+    HIPCHK(hipStreamWaitEvent(s, h->pev[i], 0));
+  }
   return CV_OK;
+}
+
+int cv_bound_set_parts(cv_bound* h, int32_t nparts) {
+  if (!h) return fail(CV_EINVAL, "null handle");
+  if (nparts < 1 || nparts > kMaxParts) return fail(CV_EINVAL, "nparts must be 1..%d", kMaxParts);
+  return set_parts(h, std::min<int>(nparts, std::max(1, h->B)));
 }
 
 int cv_bound_autotune(cv_bound* h, void* stream) {
@@ -1077,6 +1260,8 @@ int cv_bound_autotune(cv_bound* h, void* stream) {
   (void)hipEventDestroy(e1);
   drop_graph(h);
   HIPCHK(hipStreamSynchronize(s));
+  for (cv_bound* q : h->parts)
+    if ((rc = cv_bound_autotune(q, stream))) return rc;
   return CV_OK;
 }
 
@@ -1088,6 +1273,11 @@ int cv_bound_set_plan(cv_bound* h, int32_t chain_bwd, int32_t chain_fwd) {
   h->chain_b = chain_bwd;
   h->chain_f = chain_fwd;
   drop_graph(h);
+  for (cv_bound* q : h->parts) {
+    q->chain_b = chain_bwd && q->chain_lo ? 1 : 0;
+    q->chain_f = chain_fwd && q->chain_lo && q->chain_lo + 1 <= q->L - 1 ? 1 : 0;
+    drop_graph(q);
+  }
   return CV_OK;
 }
 
@@ -1146,12 +1336,7 @@ int cv_bound_profile(cv_bound* h, const float* alpha, const float* beta, int32_t
   return CV_OK;
 }
 
-void cv_bound_destroy(cv_bound* h) {
-  if (!h) return;
-  drop_graph(h);
-  if (h->cap) (void)hipStreamDestroy(h->cap);
-  delete h;
-}
+void cv_bound_destroy(cv_bound* h) { destroy_handle(h); }
 
 int cv_bound_root_bounds(const cv_layer* layers, int32_t n_layers, int32_t n_props, const float* x_lo,
                          const float* x_hi, float* l_out, float* u_out, void* stream) {

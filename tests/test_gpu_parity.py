@@ -386,3 +386,43 @@ def test_grad_matches_central_fd_of_oracle():
     say("FD coordinates compared", compared, "of", tried, "worst", worst)
     assert compared >= tried // 2
     assert worst <= TOL
+
+
+@pytest.mark.parametrize("nparts", [1, 2, 3])
+def test_optimize_parts_and_resume(nparts):
+    """The optimiser over concurrent sub-batches matches the oracle, and a run
+    resumed from explicit Adam state (10 + 10 steps) equals a 20-step run."""
+    say("optimize parts", nparts)
+    wl, orc, pb = problem("mlp_deep")
+    pb.set_parts(nparts)
+    a0 = pb.alpha_init()
+    b0 = pb.zeros_beta()
+    a, b = a0.clone(), b0.clone()
+    best, _ = pb.optimize(a, b, iters=20)
+    best = best.cpu().numpy()
+    a64 = orc.default_alpha_flat()
+    z = np.zeros(orc.nnz * orc.m)
+    errs = [guarded_rel(best[d], orc.optimize(d, a64, z)[0]).max() for d in sample_doms(orc, 8, seed=nparts)]
+    say("parts", nparts, "opt max rel err", max(errs))
+    assert max(errs) <= TOL
+    # resume: explicit moments, 10 steps then 10 more from step 10
+    st = torch.zeros(2 * pb.n_alpha + 2 * pb.n_beta, device="cuda")
+    a2, b2 = a0.clone(), b0.clone()
+    best1, _ = pb.optimize(a2, b2, iters=10, adam_state=st)
+    best1 = best1.clone()
+    best2, last2 = pb.optimize(a2, b2, iters=10, adam_state=st, step0=10)
+    a3, b3 = a0.clone(), b0.clone()
+    st3 = torch.zeros_like(st)
+    best3, last3 = pb.optimize(a3, b3, iters=20, adam_state=st3)
+    assert torch.allclose(a2, a3, rtol=0, atol=1e-6) and torch.allclose(b2, b3, rtol=0, atol=1e-6)
+    assert torch.allclose(last2, last3, rtol=1e-6, atol=1e-5)
+    assert torch.allclose(torch.maximum(best1, best2), best3, rtol=1e-6, atol=1e-5)
+
+
+def test_parts_rejects_bad_values():
+    from paper_2103_06624_amd.binding import CvError
+    wl, orc, pb = problem("mlp_small")
+    for bad in (0, 5, -1):
+        with pytest.raises(CvError):
+            pb.set_parts(bad)
+    pb.set_parts(4)  # more parts than needed is fine; 16 subdomains
