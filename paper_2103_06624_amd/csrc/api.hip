@@ -982,6 +982,30 @@ int set_parts(cv_bound* h, int n) {
   return CV_OK;
 }
 
+// Offsets of part i's slices in the whole batch's arrays: alpha entries,
+// beta entries (split rows x m), rows.
+struct PartOff {
+  int64_t a0, s0, r0;
+};
+
+// Run f(part, offsets, part stream) for every part, forked from and joined
+// into s.
+template <class F>
+int for_parts(cv_bound* h, hipStream_t s, F f) {
+  const int np = (int)h->parts.size();
+  HIPCHK(hipEventRecord(h->pev[np], s));
+  for (int i = 0; i < np; ++i) {
+    const int b0 = h->part_dom[i];
+    const PartOff o{h->h_aoff[b0], h->in->sptr[b0] * h->m, (int64_t)b0 * h->m};
+    HIPCHK(hipStreamWaitEvent(h->pstream[i], h->pev[np], 0));
+    int rc = f(h->parts[i], o, h->pstream[i]);
+    if (rc) return rc;
+    HIPCHK(hipEventRecord(h->pev[i], h->pstream[i]));
+    HIPCHK(hipStreamWaitEvent(s, h->pev[i], 0));
+  }
+  return CV_OK;
+}
+
 void destroy_handle(cv_bound* h) {
   if (!h) return;
   free_parts(h);
@@ -1092,7 +1116,8 @@ int cv_bound_alpha_init(cv_bound* h, float* alpha, void* stream) {
 
 int cv_bound_eval(cv_bound* h, const float* alpha, const float* beta, float* lb, void* stream) {
   if (!h || !lb || (!alpha && h->n_alpha > 0) || (!beta && h->nnz > 0)) return fail(CV_EINVAL, "null argument");
-  return enqueue_bwd(h, alpha, beta, false, lb, nullptr, 0, (hipStream_t)stream);
+  hipStream_t s = (hipStream_t)stream;
+  return enqueue_bwd(h, alpha, beta, false, lb, nullptr, 0, s);
 }
 
 int cv_bound_grad(cv_bound* h, const float* alpha, const float* beta, float* lb, float* g_alpha, float* g_beta,
@@ -1123,22 +1148,12 @@ int cv_bound_optimize(cv_bound* h, int32_t iters, float lr_alpha, float lr_beta,
   if (np <= 1) return optimize_one(h, iters, lr_alpha, lr_beta, lr_decay, alpha, beta, ap, step0, lb_best, lb_last, s);
   // fork: every part waits for the caller's stream, runs on its own stream;
   // join: the caller's stream waits for every part
-  HIPCHK(hipEventRecord(h->pev[np], s));
-  for (int i = 0; i < np; ++i) {
-    cv_bound* q = h->parts[i];
-    const int b0 = h->part_dom[i];
-    const int64_t a0 = h->h_aoff[b0], s0 = h->in->sptr[b0] * h->m, r0 = (int64_t)b0 * h->m;
+  return for_parts(h, s, [&](cv_bound* q, const PartOff& o, hipStream_t t) {
     AdamPtrs pq;
-    if (ap.ma) pq = {ap.ma + a0, ap.va + a0, ap.mb + s0, ap.vb + s0};
-    HIPCHK(hipStreamWaitEvent(h->pstream[i], h->pev[np], 0));
-    int rc = optimize_one(q, iters, lr_alpha, lr_beta, lr_decay, alpha ? alpha + a0 : nullptr,
-                          beta ? beta + s0 : nullptr, pq, step0, lb_best + r0, lb_last ? lb_last + r0 : nullptr,
-                          h->pstream[i]);
-    if (rc) return rc;
-    HIPCHK(hipEventRecord(h->pev[i], h->pstream[i]));
-    HIPCHK(hipStreamWaitEvent(s, h->pev[i], 0));
-  }
-  return CV_OK;
+    if (ap.ma) pq = {ap.ma + o.a0, ap.va + o.a0, ap.mb + o.s0, ap.vb + o.s0};
+    return optimize_one(q, iters, lr_alpha, lr_beta, lr_decay, alpha ? alpha + o.a0 : nullptr,
+                        beta ? beta + o.s0 : nullptr, pq, step0, lb_best + o.r0, lb_last ? lb_last + o.r0 : nullptr, t);
+  });
 }
 
 int cv_bound_set_parts(cv_bound* h, int32_t nparts) {

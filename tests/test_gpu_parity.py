@@ -426,3 +426,4 @@ def test_parts_rejects_bad_values():
         with pytest.raises(CvError):
             pb.set_parts(bad)
     pb.set_parts(4)  # more parts than needed is fine; 16 subdomains
+
