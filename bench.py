@@ -128,6 +128,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--plan", default=None, help="dense-chain plan bwd,fwd (1,1 fused chains, 0,0 per-layer kernels); overrides the autotuner")
+    ap.add_argument("--parts", type=int, default=0,
+                    help="concurrent sub-batches of the optimiser (0: the library's default)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -151,11 +153,14 @@ def main():
     sp = synth.attach_splits(wl, lo, up)
     pb = api.BoundProblem.from_workload(wl, lo, up)
     B, m = pb.B, pb.m
+    if args.parts:
+        pb.set_parts(args.parts)
     if not args.no_autotune:
         pb.autotune()
     if args.plan:
         cb, cf = (int(x) for x in args.plan.split(","))
         pb.set_plan(cb, cf)
+
     a0 = pb.alpha_init()
     b0 = pb.zeros_beta()
     alpha, beta = a0.clone(), b0.clone()

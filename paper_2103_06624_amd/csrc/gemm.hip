@@ -333,7 +333,8 @@ const GemmCfg kGemmCfgs[kNumGemmCfgs] = {
     {32, 32, 16, 0, 1}, {32, 32, 32, 0, 1}, {32, 32, 64, 0, 1}, {64, 32, 32, 0, 1},  {32, 64, 32, 0, 1},
     {64, 64, 32, 0, 1}, {64, 32, 64, 0, 1}, {32, 64, 64, 0, 1}, {32, 32, 16, 8, 1},  {32, 32, 32, 8, 1},
     {64, 32, 16, 6, 1}, {32, 64, 16, 6, 1}, {32, 32, 16, 8, 2}, {32, 32, 32, 8, 2},  {32, 32, 32, 0, 2},
-    {64, 32, 32, 0, 2}, {32, 64, 32, 0, 2}, {64, 64, 32, 0, 2}, {64, 32, 16, 6, 2},  {32, 64, 16, 6, 2}};
+    {64, 32, 32, 0, 2}, {32, 64, 32, 0, 2}, {64, 64, 32, 0, 2}, {64, 32, 16, 6, 2},  {32, 64, 16, 6, 2},
+    {32, 32, 64, 0, 2}, {64, 32, 64, 0, 2}, {32, 64, 64, 0, 2}, {64, 64, 16, 0, 2}};
 
 void launch_gemm(int cfg, int mode, const GemmArgs& g, hipStream_t s) {
   switch (cfg) {
@@ -361,7 +362,11 @@ void launch_gemm(int cfg, int mode, const GemmArgs& g, hipStream_t s) {
     case 21: launch_cfg<32, 64, 32, 0, 2>(mode, g, s); break;
     case 22: launch_cfg<64, 64, 32, 0, 2>(mode, g, s); break;
     case 23: launch_cfg<64, 32, 16, 6, 2>(mode, g, s); break;
-    default: launch_cfg<32, 64, 16, 6, 2>(mode, g, s); break;
+    case 24: launch_cfg<32, 64, 16, 6, 2>(mode, g, s); break;
+    case 25: launch_cfg<32, 32, 64, 0, 2>(mode, g, s); break;
+    case 26: launch_cfg<64, 32, 64, 0, 2>(mode, g, s); break;
+    case 27: launch_cfg<32, 64, 64, 0, 2>(mode, g, s); break;
+    default: launch_cfg<64, 64, 16, 0, 2>(mode, g, s); break;
   }
 }
 

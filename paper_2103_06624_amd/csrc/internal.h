@@ -21,7 +21,7 @@ struct GemmCfg {
   int occ;    // minimum waves per SIMD requested from the compiler (0: its choice)
   int depth;  // K slabs of global loads in flight (1 or 2)
 };
-constexpr int kNumGemmCfgs = 25;
+constexpr int kNumGemmCfgs = 29;
 extern const GemmCfg kGemmCfgs[kNumGemmCfgs];
 
 struct GemmArgs {
