@@ -176,14 +176,17 @@ int cv_bound_set_plan(cv_bound *h, int32_t chain_bwd, int32_t chain_fwd);
  * 1.  CV_EINVAL outside 1..4; more parts than subdomains are reduced. */
 int cv_bound_set_parts(cv_bound *h, int32_t nparts);
 
-/* Per-kernel timing of one gradient pass plus one plain evaluation, each
- * kernel launch bracketed by HIP events on `stream`, repeated `reps` times.
- * Fills up to max_out records; *n_out gets the number of distinct kernels.
- * flops / bytes are the algorithmic counts per launch (see design notes). */
+/* Per-kernel timing of one gradient pass plus one plain evaluation, issued
+ * eagerly on `stream`, repeated `reps` times.  Each kernel launch of a pass
+ * is issued 8 times back to back (same arguments) between two HIP events on
+ * `stream`; a launch is timed as elapsed / 8.  Fills up to
+ * max_out records; *n_out gets the number of distinct kernels.  flops and
+ * bytes are algorithmic counts: the multiply-adds (x2) of the contraction a
+ * launch performs, and the bytes it must read and write at least once. */
 typedef struct cv_kernel_stat {
   char name[64];
   int32_t launches;     /* launches per pass                              */
-  double total_ms;      /* summed over all launches and reps              */
+  double total_ms;      /* per-launch time, summed over launches and reps */
   double flops;         /* algorithmic flops, summed over launches per rep */
   double bytes;         /* algorithmic HBM bytes, summed likewise          */
 } cv_kernel_stat;

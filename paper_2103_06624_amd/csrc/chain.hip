@@ -457,8 +457,8 @@ void launch_chain(const ChainArgs& a, hipStream_t s) {
   const int key = a.rb * 8 + a.uw;
 #define CVB_CHAIN_CASE(R, U)                                  \
   case R * 8 + U:                                             \
-    if (BWD) chain_bwd<R, U><<<a.grid, kCT, sm, s>>>(a);      \
-    else chain_fwd<R, U><<<a.grid, kCT, sm, s>>>(a);          \
+    if (BWD) launch_k(chain_bwd<R, U>, a.grid, kCT, sm, s, a); \
+    else launch_k(chain_fwd<R, U>, a.grid, kCT, sm, s, a);     \
     break;
   switch (key) {
     CVB_CHAIN_CASE(1, 1)

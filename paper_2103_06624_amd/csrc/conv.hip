@@ -217,7 +217,7 @@ int convt_dispatch(const ConvArgs& a, hipStream_t st) {
   const dim3 grid((a.M + rb - 1) / rb), block(256);
 #define CVB_CT(CI)                                                                                         \
   case CI:                                                                                                 \
-    convt_bwd<CI, MODE><<<grid, block, sm, st>>>(a.in, a.ldi, a.w, a.g, a.M, a.uniform, a.bt, a.v, a.e); \
+    launch_k(convt_bwd<CI, MODE>, grid, block, sm, st, a.in, a.ldi, a.w, a.g, a.M, a.uniform, a.bt, a.v, a.e); \
     return 0;
   switch (a.g.ci) {
     CVB_CT(1) CVB_CT(2) CVB_CT(3) CVB_CT(4) CVB_CT(8) CVB_CT(16) CVB_CT(32)
@@ -236,7 +236,7 @@ int conv_dispatch(const ConvArgs& a, hipStream_t st) {
   const dim3 grid((a.M + rb - 1) / rb), block(256);
 #define CVB_CF(CO)                                                                                      \
   case CO:                                                                                              \
-    conv_fwd<CO, MODE><<<grid, block, sm, st>>>(a.in, a.ldi, a.w, a.g, a.M, a.last, a.bt, a.v, a.e); \
+    launch_k(conv_fwd<CO, MODE>, grid, block, sm, st, a.in, a.ldi, a.w, a.g, a.M, a.last, a.bt, a.v, a.e); \
     return 0;
   switch (a.g.co) {
     CVB_CF(1) CVB_CF(2) CVB_CF(3) CVB_CF(4) CVB_CF(8) CVB_CF(16) CVB_CF(32)

@@ -312,16 +312,16 @@ void launch_cfg(int mode, const GemmArgs& g, hipStream_t s) {
   dim3 grid(tiles), block(256);
   switch (mode) {
     case kBwdRelax:
-      gemm_nt<BM, BN, BK, kBwdRelax, OCC, DEPTH><<<grid, block, 0, s>>>(g.A, g.lda, g.Bt, g.ldb, g.M, g.N, g.K, g.last,
-                                                                        g.bt, g.v, g.e);
+      launch_k(gemm_nt<BM, BN, BK, kBwdRelax, OCC, DEPTH>, grid, block, 0, s, g.A, g.lda, g.Bt, g.ldb, g.M, g.N, g.K,
+               g.last, g.bt, g.v, g.e);
       break;
     case kBwdConc:
-      gemm_nt<BM, BN, BK, kBwdConc, OCC, DEPTH><<<grid, block, 0, s>>>(g.A, g.lda, g.Bt, g.ldb, g.M, g.N, g.K, g.last,
-                                                                       g.bt, g.v, g.e);
+      launch_k(gemm_nt<BM, BN, BK, kBwdConc, OCC, DEPTH>, grid, block, 0, s, g.A, g.lda, g.Bt, g.ldb, g.M, g.N, g.K,
+               g.last, g.bt, g.v, g.e);
       break;
     default:
-      gemm_nt<BM, BN, BK, kFwd, OCC, DEPTH><<<grid, block, 0, s>>>(g.A, g.lda, g.Bt, g.ldb, g.M, g.N, g.K, g.last,
-                                                                   g.bt, g.v, g.e);
+      launch_k(gemm_nt<BM, BN, BK, kFwd, OCC, DEPTH>, grid, block, 0, s, g.A, g.lda, g.Bt, g.ldb, g.M, g.N, g.K,
+               g.last, g.bt, g.v, g.e);
       break;
   }
 }

@@ -8,6 +8,31 @@
 
 namespace cvb {
 
+// Per-kernel timing (the eager timing pass only; never during graph capture):
+// when `start` is set, the next kernel launch on this host thread is issued
+// `reps` times back to back between `start` and `stop` recorded on its stream,
+// then the request is cleared.  Repeats take the same arguments, so they touch
+// exactly the memory of the first launch.
+struct LaunchTiming {
+  hipEvent_t start = nullptr, stop = nullptr;
+  int reps = 1;
+};
+LaunchTiming& launch_timing();
+
+template <typename... P, typename... A>
+inline void launch_k(void (*k)(P...), dim3 grid, dim3 block, uint32_t smem, hipStream_t s, A... args) {
+  LaunchTiming& t = launch_timing();
+  if (t.start) {
+    const LaunchTiming req = t;
+    t = LaunchTiming{};
+    (void)hipEventRecord(req.start, s);
+    for (int r = 0; r < req.reps; ++r) k<<<grid, block, smem, s>>>(args...);
+    (void)hipEventRecord(req.stop, s);
+  } else {
+    k<<<grid, block, smem, s>>>(args...);
+  }
+}
+
 // Epilogue / prologue variants of the layer kernels.
 enum Mode {
   kBwdRelax = 0,  // back-substitution, then the next ReLU layer's relaxation

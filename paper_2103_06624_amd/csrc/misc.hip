@@ -224,11 +224,11 @@ void launch_spec_identity(const float* Wdense, int ldw, const float* wconv, cons
   ConvGeom gg = g ? *g : ConvGeom{};
   spec_identity_k<<<2 * d, 256, 0, s>>>(Wdense, ldw, wconv, gg, g ? 1 : 0, bias_full, d, dprev, CW, ldcw, Cb);
 }
-void launch_top(const TopArgs& a, hipStream_t s) { top_k<<<nblk(a.bt.n_rows, 4), 256, 0, s>>>(a); }
+void launch_top(const TopArgs& a, hipStream_t s) { launch_k(top_k, nblk(a.bt.n_rows, 4), 256, 0, s, a); }
 void launch_finalize(const float* part, int n_slots, int n_used, int n_rows, float* lb, float* best, int first,
                      hipStream_t s) {
   (void)n_slots;
-  finalize_k<<<nblk(n_rows, 64), 256, 0, s>>>(part, n_used, n_rows, lb, best, first);
+  launch_k(finalize_k, nblk(n_rows, 64), 256, 0, s, part, n_used, n_rows, lb, best, first);
 }
 void launch_adam(float* x, const float* g, float* m1, float* m2, int64_t n, float lr, float bc1, float bc2, float lo,
                  float hi, hipStream_t s) {
