@@ -61,6 +61,40 @@ def traffic_for(kernel, workload):
     return ent.get("bytes_per_launch")
 
 
+def library_gemm_context(wl, rows):
+    """torch.mm (the ROCm BLAS library) on [rows, d_i] x [d_i, d_(i-1)] for
+    each distinct dense back-substitution shape: what a plain library GEMM of
+    the same size reaches on this GPU, without the relaxation epilogue."""
+    import torch
+
+    from paper_2103_06624_amd import synth
+    torch.backends.cuda.matmul.allow_tf32 = False
+    shapes = []
+    for ly in wl.net.layers[:-1]:  # the last layer is folded into the spec
+        if ly.kind == synth.DENSE:
+            d_out, d_in = ly.weight.shape
+            if (d_in, d_out) not in shapes and len(shapes) < 4:
+                shapes.append((d_in, d_out))
+    out = []
+    for n, k in shapes:
+        a = torch.randn(rows, k, device="cuda")
+        b = torch.randn(k, n, device="cuda")
+        for _ in range(5):
+            c = a @ b
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(50):
+            c = a @ b
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) / 50 * 1e3
+        out.append({"m": rows, "n": n, "k": k, "us": round(us, 2), "tflops": round(2.0 * rows * n * k / us / 1e6, 2)})
+        del a, b, c
+    return out
+
+
 def cpu_baseline(name, gpu_best, gpu_splits, gpu_lo, gpu_up, seconds, iters, lr_a, lr_b, decay):
     """The FP64 oracle timed on this host on a bounded sample of the same
     workload: per-subdomain 20-iteration optimisation (the same unit as the
@@ -227,6 +261,10 @@ def main():
     gemm_ms = sum(s["total_ms"] / s["reps"] for s in stats if s["flops"] > 0)
     all_ms = sum(s["total_ms"] / s["reps"] for s in stats)
 
+    # ---- context: the vendor library's plain FP32 GEMM (no epilogue) at the
+    # back-substitution shapes of the dense layers, same rows
+    lib = library_gemm_context(wl, pb.n_rows)
+
     # ---- a clean 20-iteration run from the default start (for the error check)
     alpha.copy_(a0)
     beta.copy_(b0)
@@ -263,6 +301,7 @@ def main():
         "mfma_kernels_tflops": round(gemm_fl / (gemm_ms * 1e-3) / 1e12, 3) if gemm_ms else None,
         "mfma_kernels_time_share": round(gemm_ms / all_ms, 4) if all_ms else None,
         "kernels": [{k: (round(v, 3) if isinstance(v, float) else v) for k, v in kk.items()} for kk in kern],
+        "library_fp32_gemm": lib,
         "root_bounds_s": round(t_root, 3),
     }
     if not args.no_cpu_baseline:

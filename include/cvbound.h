@@ -176,6 +176,21 @@ int cv_bound_set_plan(cv_bound *h, int32_t chain_bwd, int32_t chain_fwd);
  * 1.  CV_EINVAL outside 1..4; more parts than subdomains are reduced. */
 int cv_bound_set_parts(cv_bound *h, int32_t nparts);
 
+/* GEMM tilings of the dense-layer kernels (back-substitution, Theorem 3.1's
+ * A(i-1) = Lambda(i) W(i), and the adjoint's forward steps): tile shape, K
+ * slab and how many slabs of global loads are kept in flight.  Every tiling
+ * computes the same result up to float32 summation order.
+ * cv_bound_num_tilings: how many there are (numbered from 0).
+ * cv_bound_set_tiling: force tiling `tiling` on every dense layer of h (and
+ * of its concurrent sub-batches) in both directions, or -1 to return to the
+ * tuned choice per layer shape (cv_bound_autotune's, else a built-in
+ * default).  A tiling that keeps all of K in flight cannot take a layer
+ * deeper than it holds; such a layer runs a two-deep tiling instead.  A later
+ * cv_bound_autotune replaces the forced choice.  CV_EINVAL outside
+ * -1..cv_bound_num_tilings()-1. */
+int32_t cv_bound_num_tilings(void);
+int cv_bound_set_tiling(cv_bound *h, int32_t tiling);
+
 /* Per-kernel timing of one gradient pass plus one plain evaluation, issued
  * eagerly on `stream`, repeated `reps` times.  Each kernel launch of a pass
  * is issued 8 times back to back (same arguments) between two HIP events on

@@ -152,6 +152,14 @@ class BoundProblem:
     def autotune(self):
         B.check(B.cv_bound_autotune(self.h, _stream()))
 
+    @staticmethod
+    def num_tilings():
+        return int(B.cv_bound_num_tilings())
+
+    def set_tiling(self, tiling):
+        """Force one GEMM tiling on every dense layer (-1: the tuned choice)."""
+        B.check(B.cv_bound_set_tiling(self.h, tiling))
+
     def set_parts(self, nparts):
         """Concurrent sub-batches (streams) of optimize(); 1 disables the split."""
         B.check(B.cv_bound_set_parts(self.h, nparts))

@@ -56,6 +56,8 @@ SIGNATURES = {
     "cv_bound_autotune": (ctypes.c_int, [_vp, _vp]),
     "cv_bound_set_plan": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32]),
     "cv_bound_set_parts": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "cv_bound_num_tilings": (ctypes.c_int32, []),
+    "cv_bound_set_tiling": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "cv_bound_profile": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32, ctypes.POINTER(cv_kernel_stat),
                                         ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _vp]),
     "cv_bound_destroy": (None, [_vp]),
@@ -104,6 +106,8 @@ cv_bound_optimize = _fn("cv_bound_optimize")
 cv_bound_autotune = _fn("cv_bound_autotune")
 cv_bound_set_plan = _fn("cv_bound_set_plan")
 cv_bound_set_parts = _fn("cv_bound_set_parts")
+cv_bound_num_tilings = _fn("cv_bound_num_tilings")
+cv_bound_set_tiling = _fn("cv_bound_set_tiling")
 cv_bound_profile = _fn("cv_bound_profile")
 cv_bound_destroy = _fn("cv_bound_destroy")
 cv_last_error = _fn("cv_last_error")

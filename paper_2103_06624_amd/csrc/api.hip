@@ -227,6 +227,20 @@ int cfg_for(const cv_bound* h, int mode, int M, int N, int K, int fallback) {
   (void)h;
 }
 
+// GEMM tiling of every dense layer in both directions: `tiling` >= 0 forces
+// that one, -1 takes the tuned (else built-in) choice for each layer shape.
+void assign_tiles(cv_bound* h, int tiling) {
+  const int n_layers = h->L;
+  h->cfg.assign(2 * n_layers, -1);
+  for (int i = 1; i < n_layers; ++i) {
+    if (h->layers[i - 1].type != CV_LAYER_DENSE) continue;
+    const int N_b = h->dims[i - 1], K_b = h->dims[i];
+    h->cfg[i - 1] =
+        tiling >= 0 ? tiling : cfg_for(h, i - 1 >= 1 ? kBwdRelax : kBwdConc, h->R, N_b, K_b, gemm_default_cfg(h->R, N_b));
+    h->cfg[n_layers + i - 1] = tiling >= 0 ? tiling : cfg_for(h, kFwd, h->R, K_b, N_b, gemm_default_cfg(h->R, K_b));
+  }
+}
+
 constexpr int kMaxParts = 4;             // concurrent sub-batches of the optimiser, at most
 constexpr int kPartsMinRows = 4096;      // default: two sub-batches from this many rows on
 constexpr int kChainWidth = 256;         // widest LDS-resident layer of a chain
@@ -539,13 +553,7 @@ int build(cv_bound* h, const cv_layer* layers, int n_layers, int P, const float*
       return rc;
   }
   if ((rc = M.alloc(&h->part, (size_t)std::max(1, h->R) * h->n_slots))) return rc;
-  h->cfg.assign(2 * n_layers, -1);
-  for (int i = 1; i < n_layers; ++i) {
-    if (h->layers[i - 1].type != CV_LAYER_DENSE) continue;
-    const int N_b = h->dims[i - 1], K_b = h->dims[i];
-    h->cfg[i - 1] = cfg_for(h, i - 1 >= 1 ? kBwdRelax : kBwdConc, h->R, N_b, K_b, gemm_default_cfg(h->R, N_b));
-    h->cfg[n_layers + i - 1] = cfg_for(h, kFwd, h->R, K_b, N_b, gemm_default_cfg(h->R, K_b));
-  }
+  assign_tiles(h, -1);
   // dense layers fused by the chain kernels (LDS-resident widths up to kChainWidth)
   h->chain_lo = 0;
   h->chain_b = h->chain_f = 0;
@@ -1241,6 +1249,7 @@ int cv_bound_autotune(cv_bound* h, void* stream) {
       float best_ms = 1e30f;
       int best = -1;
       for (int c = 0; c < kNumGemmCfgs; ++c) {
+        if (!gemm_cfg_fits(c, K)) continue;
         GemmArgs g{A, lda, Bt, ldb, h->R, N, K, dir == 1 && i == L - 1, h->bt, v, e};
         for (int w = 0; w < 2; ++w) launch_gemm(c, mode, g, s);
         HIPCHK(hipEventRecord(e0, s));
@@ -1311,6 +1320,20 @@ int cv_bound_set_plan(cv_bound* h, int32_t chain_bwd, int32_t chain_fwd) {
   for (cv_bound* q : h->parts) {
     q->chain_b = chain_bwd && q->chain_lo ? 1 : 0;
     q->chain_f = chain_fwd && q->chain_lo && q->chain_lo + 1 <= q->L - 1 ? 1 : 0;
+    drop_graph(q);
+  }
+  return CV_OK;
+}
+
+int32_t cv_bound_num_tilings(void) { return kNumGemmCfgs; }
+
+int cv_bound_set_tiling(cv_bound* h, int32_t tiling) {
+  if (!h) return fail(CV_EINVAL, "null handle");
+  if (tiling < -1 || tiling >= kNumGemmCfgs) return fail(CV_EINVAL, "tiling must be -1 or in [0, %d)", kNumGemmCfgs);
+  assign_tiles(h, tiling);
+  drop_graph(h);
+  for (cv_bound* q : h->parts) {
+    assign_tiles(q, tiling);
     drop_graph(q);
   }
   return CV_OK;

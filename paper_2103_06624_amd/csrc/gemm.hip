@@ -44,6 +44,8 @@ __device__ __forceinline__ float4 mask4(float4 x, int row, int nrows, int k, int
 // round instead of two.  DEPTH = 2 keeps two slabs of global loads in flight
 // (two register sets, loads issued two slabs before they are parked in LDS):
 // a slab's MFMA work is far shorter than the load latency at these sizes.
+// DEPTH >= 3 holds all of K in registers (K <= DEPTH * BK): one load latency
+// per tile instead of one per slab.
 // Modes: kBwdRelax, kBwdConc, kFwd (the adjoint's first layer reads x* as a
 // dense operand).
 template <int BM, int BN, int BK, int MODE, int OCC, int DEPTH>
@@ -144,9 +146,17 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt(const float* __restrict__ A,
     }
 
   const int nk = (K + BK - 1) / BK;
-  Regs r0, r1;
-  gload(r0, 0);
-  if (DEPTH == 2) gload(r1, min(1, nk - 1) * BK);
+  // DEPTH >= 3: every slab of K is loaded up front (the host launches these
+  // tilings only when nk <= DEPTH); the loop then waits on no global load.
+  constexpr int NF = DEPTH >= 3 ? DEPTH : 1;
+  Regs r0, r1, rf[NF];
+  if (DEPTH >= 3) {
+#pragma unroll
+    for (int d = 0; d < NF; ++d) gload(rf[d], min(d, nk - 1) * BK);
+  } else {
+    gload(r0, 0);
+    if (DEPTH == 2) gload(r1, min(1, nk - 1) * BK);
+  }
 
 #pragma unroll
   for (int i = 0; i < FM; ++i)
@@ -201,9 +211,18 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt(const float* __restrict__ A,
     }
   };
 
-  sstore(r0, 0, 0);
+  sstore(DEPTH >= 3 ? rf[0] : r0, 0, 0);
   __syncthreads();
-  if (DEPTH == 1) {
+  if (DEPTH >= 3) {
+    // slab d sits in LDS buffer d & 1; slab d + 1 waits in rf[d + 1]
+#pragma unroll
+    for (int d = 0; d < NF; ++d) {
+      if (d >= nk) break;
+      compute(d & 1);
+      if (d + 1 < NF && d + 1 < nk) sstore(rf[d + 1 < NF ? d + 1 : 0], (d + 1) & 1, (d + 1) * BK);
+      __syncthreads();
+    }
+  } else if (DEPTH == 1) {
     for (int kt = 0; kt < nk; ++kt) {
       const int buf = kt & 1;
       if (kt + 1 < nk) gload(r0, (kt + 1) * BK);
@@ -334,9 +353,17 @@ const GemmCfg kGemmCfgs[kNumGemmCfgs] = {
     {64, 64, 32, 0, 1}, {64, 32, 64, 0, 1}, {32, 64, 64, 0, 1}, {32, 32, 16, 8, 1},  {32, 32, 32, 8, 1},
     {64, 32, 16, 6, 1}, {32, 64, 16, 6, 1}, {32, 32, 16, 8, 2}, {32, 32, 32, 8, 2},  {32, 32, 32, 0, 2},
     {64, 32, 32, 0, 2}, {32, 64, 32, 0, 2}, {64, 64, 32, 0, 2}, {64, 32, 16, 6, 2},  {32, 64, 16, 6, 2},
-    {32, 32, 64, 0, 2}, {64, 32, 64, 0, 2}, {32, 64, 64, 0, 2}, {64, 64, 16, 0, 2}};
+    {32, 32, 64, 0, 2}, {64, 32, 64, 0, 2}, {32, 64, 64, 0, 2}, {64, 64, 16, 0, 2}, {64, 32, 32, 0, 8},
+    {32, 32, 32, 0, 8}, {32, 64, 32, 0, 8}, {64, 64, 32, 0, 8}, {64, 32, 64, 0, 4}, {32, 32, 64, 0, 4},
+    {32, 64, 64, 0, 4}, {64, 32, 32, 4, 2}, {32, 64, 32, 4, 2}, {64, 32, 16, 4, 2}, {64, 32, 32, 4, 1}};
+
+bool gemm_cfg_fits(int cfg, int K) {
+  const GemmCfg& c = kGemmCfgs[cfg];
+  return c.depth <= 2 || (K + c.bk - 1) / c.bk <= c.depth;
+}
 
 void launch_gemm(int cfg, int mode, const GemmArgs& g, hipStream_t s) {
+  if (!gemm_cfg_fits(cfg, g.K)) cfg = 19;  // K too deep for an all-of-K tiling
   switch (cfg) {
     case 0: launch_cfg<64, 64, 16, 0, 1>(mode, g, s); break;
     case 1: launch_cfg<64, 32, 16, 0, 1>(mode, g, s); break;
@@ -366,7 +393,18 @@ void launch_gemm(int cfg, int mode, const GemmArgs& g, hipStream_t s) {
     case 25: launch_cfg<32, 32, 64, 0, 2>(mode, g, s); break;
     case 26: launch_cfg<64, 32, 64, 0, 2>(mode, g, s); break;
     case 27: launch_cfg<32, 64, 64, 0, 2>(mode, g, s); break;
-    default: launch_cfg<64, 64, 16, 0, 2>(mode, g, s); break;
+    case 28: launch_cfg<64, 64, 16, 0, 2>(mode, g, s); break;
+    case 29: launch_cfg<64, 32, 32, 0, 8>(mode, g, s); break;
+    case 30: launch_cfg<32, 32, 32, 0, 8>(mode, g, s); break;
+    case 31: launch_cfg<32, 64, 32, 0, 8>(mode, g, s); break;
+    case 32: launch_cfg<64, 64, 32, 0, 8>(mode, g, s); break;
+    case 33: launch_cfg<64, 32, 64, 0, 4>(mode, g, s); break;
+    case 34: launch_cfg<32, 32, 64, 0, 4>(mode, g, s); break;
+    case 35: launch_cfg<32, 64, 64, 0, 4>(mode, g, s); break;
+    case 36: launch_cfg<64, 32, 32, 4, 2>(mode, g, s); break;
+    case 37: launch_cfg<32, 64, 32, 4, 2>(mode, g, s); break;
+    case 38: launch_cfg<64, 32, 16, 4, 2>(mode, g, s); break;
+    default: launch_cfg<64, 32, 32, 4, 1>(mode, g, s); break;
   }
 }
 

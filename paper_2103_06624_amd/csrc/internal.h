@@ -44,10 +44,13 @@ enum Mode {
 struct GemmCfg {
   int bm, bn, bk;
   int occ;    // minimum waves per SIMD requested from the compiler (0: its choice)
-  int depth;  // K slabs of global loads in flight (1 or 2)
+  int depth;  // K slabs of global loads in flight (1, 2, or all of K when >= 3)
 };
-constexpr int kNumGemmCfgs = 29;
+constexpr int kNumGemmCfgs = 40;
 extern const GemmCfg kGemmCfgs[kNumGemmCfgs];
+// whether tiling `cfg` can run a contraction of depth K (all-of-K tilings
+// hold K <= depth * bk); launch_gemm substitutes a two-deep tiling otherwise
+bool gemm_cfg_fits(int cfg, int K);
 
 struct GemmArgs {
   const float* A;

@@ -105,17 +105,23 @@ def kink_free_rows(orc, b, alpha, beta, ulps=100.0):
     return ok
 
 
-def check_grad(name, orc, pb, alpha, beta):
+def oracle_grads(orc, alpha, beta):
+    """Per subdomain: the oracle's bound and gradients, and which spec rows
+    are clear of kinks."""
+    return [(*orc.grad(b, alpha, beta), kink_free_rows(orc, b, alpha, beta)) for b in range(orc.B)]
+
+
+def check_grad(name, orc, pb, alpha, beta, ref=None):
     """Bound and gradient of every subdomain against the oracle; gradient rows
     are compared where no sign decision is within float32 reach of a kink."""
+    ref = ref or oracle_grads(orc, alpha, beta)
     lb, ga, gb = pb.grad(dev(alpha), dev(beta))
     lb, ga, gb = lb.cpu().numpy(), ga.cpu().numpy(), gb.cpu().numpy().reshape(-1, orc.m)
     checked = 0
     worst = 0.0
     for b in range(orc.B):
-        g, ra, rb = orc.grad(b, alpha, beta)
+        g, ra, rb, ok = ref[b]
         assert guarded_rel(lb[b], g).max() <= TOL
-        ok = kink_free_rows(orc, b, alpha, beta)
         U = ra.shape[0] // orc.m
         a_gpu = ga[orc.alpha_off[b]:orc.alpha_off[b + 1]].reshape(orc.m, U)
         a_ref = ra.reshape(orc.m, U)
@@ -152,6 +158,37 @@ def test_plan_parity(name, plan):
     ref = np.stack([orc.eval(b, alpha, beta) for b in range(orc.B)])
     assert guarded_rel(lb, ref).max() <= TOL
     check_grad(name, orc, pb, alpha, beta)
+
+
+@pytest.mark.parametrize("name", ["mlp_small", "mlp_deep"])
+def test_every_tiling(name):
+    """Every GEMM tiling (tile shape, K slab, loads in flight) on every dense
+    layer: bounds and gradients against the oracle."""
+    from paper_2103_06624_amd.api import BoundProblem
+    wl, orc, pb = problem(name)
+    alpha, beta = cases.random_vars(orc, seed=9)
+    ref = oracle_grads(orc, alpha, beta)
+    lb_ref = np.stack([r[0] for r in ref])
+    n = BoundProblem.num_tilings()
+    assert n >= 30
+    for t in range(n):
+        say("tiling", name, t)
+        pb.set_tiling(t)
+        lb = pb.eval(dev(alpha), dev(beta)).cpu().numpy()
+        assert guarded_rel(lb, lb_ref).max() <= TOL, t
+        check_grad(name, orc, pb, alpha, beta, ref)
+    pb.set_tiling(-1)
+    lb = pb.eval(dev(alpha), dev(beta)).cpu().numpy()
+    assert guarded_rel(lb, lb_ref).max() <= TOL
+
+
+def test_tiling_rejects_bad_values():
+    from paper_2103_06624_amd.api import BoundProblem
+    from paper_2103_06624_amd.binding import CvError
+    wl, orc, pb = problem("mlp_small")
+    for bad in [-2, BoundProblem.num_tilings()]:
+        with pytest.raises(CvError):
+            pb.set_tiling(bad)
 
 
 def test_plan_rejects_bad_values():
