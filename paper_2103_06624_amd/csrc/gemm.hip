@@ -39,6 +39,18 @@ __device__ __forceinline__ float4 mask4(float4 x, int row, int nrows, int k, int
   return x;
 }
 
+// Epilogue operands of one tile, gathered before its K loop so that they land
+// while the MFMAs run.  Element (i, r, j) of a lane is row
+// m0 + wm*WM + 16i + 4(lane/16) + r, column n0 + wn*WN + 16j + lane%16.
+template <int BM, int BN>
+struct TileOps {
+  static constexpr int FM = BM / 32, FN = BN / 32, NE = FM * 4 * FN;
+  RowInfo eri[FM][4];
+  uint32_t rec[NE];
+  float2 ech[NE];
+  float ecf[NE], east[NE], ebias[FN];
+};
+
 // OCC > 0 asks the compiler for at least OCC waves per SIMD (registers capped
 // accordingly): with OCC = 8 a 32x32 tiling of ~10^4 x 200 is resident in one
 // round instead of two.  DEPTH = 2 keeps two slabs of global loads in flight
@@ -57,6 +69,7 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt(const float* __restrict__ A,
   constexpr int QK = BK / 4;  // float4 per row of a slab
   constexpr int A_LD = (BM * QK + 255) / 256;  // float4 loads per thread
   constexpr int B_LD = (BN * QK + 255) / 256;
+  using Ops = TileOps<BM, BN>;
   __shared__ __attribute__((aligned(16))) float As[2][BM][LDK];
   __shared__ __attribute__((aligned(16))) float Bs[2][BN][LDK];
   __shared__ float red[2][BM];
@@ -65,6 +78,8 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt(const float* __restrict__ A,
   const int lane = tid & 63;
   const int wid = tid >> 6;
   const int wm = wid >> 1, wn = wid & 1;
+  const int rsub = 4 * (lane >> 4);
+  const int csub = lane & 15;
 
   // XCD-aware order: consecutive logical tiles (the column tiles of one row
   // tile) land on the same XCD, so they share its L2 copy of the row tile.
@@ -74,12 +89,6 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt(const float* __restrict__ A,
   if ((nblk & 7) == 0) logical = (blockIdx.x & 7) * (nblk >> 3) + (blockIdx.x >> 3);
   const int tm = logical / tiles_n, tn = logical - tm * tiles_n;
   const int m0 = tm * BM, n0 = tn * BN;
-
-  floatx4 acc[FM][FN];
-#pragma unroll
-  for (int i = 0; i < FM; ++i)
-#pragma unroll
-    for (int j = 0; j < FN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
   struct Regs {
     float4 a[A_LD], b[B_LD];
@@ -111,85 +120,7 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt(const float* __restrict__ A,
           mask4(r.b[t], n0 + idx / QK, N, k0 + (idx % QK) * 4, K);
     }
   };
-
-  // ---- epilogue operands, gathered before the K loop so that they land
-  // while the MFMAs run: row info and status records first, then what
-  // depends on them (chord and alpha / beta, the stored A for the adjoint, or
-  // the box for concretisation).  Element (i, r, j) of a lane is row
-  // m0 + wm*WM + 16i + 4(lane/16) + r, column n0 + wn*WN + 16j + lane%16.
-  constexpr int NE = FM * 4 * FN;
-  const int rsub = 4 * (lane >> 4);
-  const int csub = lane & 15;
-  RowInfo eri[FM][4];
-  uint32_t rec[NE];
-  float2 ech[NE];
-  float ecf[NE], east[NE], ebias[FN];
-#pragma unroll
-  for (int j = 0; j < FN; ++j) {
-    const int col = n0 + wn * WN + j * 16 + csub;
-    ebias[j] = (MODE != kBwdConc && col < N) ? e.bias[col] : 0.f;
-  }
-#pragma unroll
-  for (int i = 0; i < FM; ++i)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = m0 + wm * WM + i * 16 + rsub + r;
-      eri[i][r] = row_info(bt, min(row, M - 1));
-#pragma unroll
-      for (int j = 0; j < FN; ++j) {
-        const int col = n0 + wn * WN + j * 16 + csub;
-        const int q = (i * 4 + r) * FN + j;
-        rec[q] = kInactive;
-        if (MODE != kBwdConc && row < M && col < N)
-          rec[q] = bt.status[(int64_t)eri[i][r].b * bt.nd + e.layer_off + col];
-      }
-    }
-
-  const int nk = (K + BK - 1) / BK;
-  // DEPTH >= 3: every slab of K is loaded up front (the host launches these
-  // tilings only when nk <= DEPTH); the loop then waits on no global load.
-  constexpr int NF = DEPTH >= 3 ? DEPTH : 1;
-  Regs r0, r1, rf[NF];
-  if (DEPTH >= 3) {
-#pragma unroll
-    for (int d = 0; d < NF; ++d) gload(rf[d], min(d, nk - 1) * BK);
-  } else {
-    gload(r0, 0);
-    if (DEPTH == 2) gload(r1, min(1, nk - 1) * BK);
-  }
-
-#pragma unroll
-  for (int i = 0; i < FM; ++i)
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-      for (int j = 0; j < FN; ++j) {
-        const int row = m0 + wm * WM + i * 16 + rsub + r;
-        const int col = n0 + wn * WN + j * 16 + csub;
-        const int q = (i * 4 + r) * FN + j;
-        const RowInfo& ri = eri[i][r];
-        ech[q] = make_float2(0.f, 0.f);
-        ecf[q] = 0.f;
-        east[q] = 0.f;
-        if (row >= M || col >= N) continue;
-        if (MODE == kBwdConc) {
-          const int64_t pb = (int64_t)ri.p * bt.d0 + col;
-          ech[q] = make_float2(bt.xlo[pb], bt.xhi[pb]);
-          continue;
-        }
-        const int64_t pc = (int64_t)ri.p * bt.nd + e.layer_off + col;
-        const bool uns = (rec[q] & kKindMask) == kUnstable;
-        if (uns) ech[q] = bt.chord[pc];
-        if (MODE == kBwdRelax) {
-          ecf[q] = relax_coef(bt, v, ri, rec[q], pc);
-        } else if (uns) {
-          const int64_t ai = ri.abase + (rec[q] & kCidxMask);
-          east[q] = v.acomp[ai];
-          ecf[q] = v.alpha ? v.alpha[ai] : bt.adef[pc];
-        }
-      }
-
-  auto compute = [&](int buf) {
+  auto compute = [&](floatx4 (&acc)[FM][FN], int buf) {
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 16) {
       float4 fa[FM], fb[FN];
@@ -211,22 +142,178 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt(const float* __restrict__ A,
     }
   };
 
-  sstore(DEPTH >= 3 ? rf[0] : r0, 0, 0);
-  __syncthreads();
+  // epilogue operands, first level: bias, row info and status records
+  auto gather1 = [&](Ops& o) {
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int col = n0 + wn * WN + j * 16 + csub;
+      o.ebias[j] = (MODE != kBwdConc && col < N) ? e.bias[col] : 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * WM + i * 16 + rsub + r;
+        o.eri[i][r] = row_info(bt, min(row, M - 1));
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          const int col = n0 + wn * WN + j * 16 + csub;
+          const int q = (i * 4 + r) * FN + j;
+          o.rec[q] = kInactive;
+          if (MODE != kBwdConc && row < M && col < N)
+            o.rec[q] = bt.status[(int64_t)o.eri[i][r].b * bt.nd + e.layer_off + col];
+        }
+      }
+  };
+  // second level, which needs the status records: chord and alpha / beta,
+  // the stored A for the adjoint, or the box for concretisation
+  auto gather2 = [&](Ops& o) {
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          const int row = m0 + wm * WM + i * 16 + rsub + r;
+          const int col = n0 + wn * WN + j * 16 + csub;
+          const int q = (i * 4 + r) * FN + j;
+          const RowInfo& ri = o.eri[i][r];
+          o.ech[q] = make_float2(0.f, 0.f);
+          o.ecf[q] = 0.f;
+          o.east[q] = 0.f;
+          if (row >= M || col >= N) continue;
+          if (MODE == kBwdConc) {
+            const int64_t pb = (int64_t)ri.p * bt.d0 + col;
+            o.ech[q] = make_float2(bt.xlo[pb], bt.xhi[pb]);
+            continue;
+          }
+          const int64_t pc = (int64_t)ri.p * bt.nd + e.layer_off + col;
+          const bool uns = (o.rec[q] & kKindMask) == kUnstable;
+          if (uns) o.ech[q] = bt.chord[pc];
+          if (MODE == kBwdRelax) {
+            o.ecf[q] = relax_coef(bt, v, ri, o.rec[q], pc);
+          } else if (uns) {
+            const int64_t ai = ri.abase + (o.rec[q] & kCidxMask);
+            o.east[q] = v.acomp[ai];
+            o.ecf[q] = v.alpha ? v.alpha[ai] : bt.adef[pc];
+          }
+        }
+  };
+
+  // epilogue: lane holds rows 4*(lane/16)+r of each 16x16 block, column lane%16
+  auto epilogue = [&](const Ops& o, floatx4 (&acc)[FM][FN]) {
+    if (MODE == kBwdRelax || MODE == kBwdConc) {
+      float cst[FM][4];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          cst[i][r] = 0.f;
+          const int row = m0 + wm * WM + i * 16 + rsub + r;
+          const bool rok = row < M;
+          const RowInfo& ri = o.eri[i][r];
+#pragma unroll
+          for (int j = 0; j < FN; ++j) {
+            const int col = n0 + wn * WN + j * 16 + csub;
+            const int q = (i * 4 + r) * FN + j;
+            const float a = acc[i][j][r];
+            const bool ok = rok && col < N;
+            if (MODE == kBwdRelax) {
+              if (ok) {
+                if (v.acomp && (o.rec[q] & kKindMask) == kUnstable) v.acomp[ri.abase + (o.rec[q] & kCidxMask)] = a;
+                e.out[(int64_t)row * e.ldo + col] =
+                    relax_value(bt, v, ri, o.rec[q], o.ech[q], o.ecf[q], a, o.ebias[j], &cst[i][r]);
+              }
+            } else {
+              if (ok) cst[i][r] += conc_term(a, o.ech[q].x, o.ech[q].y);
+              if (ok && v.xdense) v.xdense[(int64_t)row * v.ldx + col] = xstar(a > 0.f, a < 0.f, o.ech[q].x, o.ech[q].y);
+              if (v.xpos) {
+                const uint64_t mp = __ballot(ok && a > 0.f);
+                const uint64_t mn = __ballot(ok && a < 0.f);
+                const int cb = n0 + wn * WN + j * 16;
+                if (csub == 0 && rok && cb < N) {
+                  const int g = lane >> 4;
+                  reinterpret_cast<uint16_t*>(v.xpos + (int64_t)row * bt.w64)[cb >> 4] = (uint16_t)(mp >> (16 * g));
+                  reinterpret_cast<uint16_t*>(v.xneg + (int64_t)row * bt.w64)[cb >> 4] = (uint16_t)(mn >> (16 * g));
+                }
+              }
+            }
+          }
+          cst[i][r] = wave_sum16(cst[i][r]);
+        }
+      }
+      // combine the two column halves (wn = 0, 1) of each row, one slot per tile
+      if (csub == 0) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) red[wn][wm * WM + i * 16 + rsub + r] = cst[i][r];
+      }
+      __syncthreads();
+      for (int t = tid; t < BM; t += 256) {
+        const int row = m0 + t;
+        if (row < M) e.part[(int64_t)(e.slot0 + tn) * M + row] = red[0][t] + red[1][t];
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < FM; ++i) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = m0 + wm * WM + i * 16 + rsub + r;
+          if (row >= M) continue;
+          const RowInfo& ri = o.eri[i][r];
+#pragma unroll
+          for (int j = 0; j < FN; ++j) {
+            const int col = n0 + wn * WN + j * 16 + csub;
+            if (col >= N) continue;
+            const int q = (i * 4 + r) * FN + j;
+            const float zb = acc[i][j][r] + o.ebias[j];
+            const int64_t pc = (int64_t)ri.p * bt.nd + e.layer_off + col;
+            const float zh = relax_fwd_value(bt, v, ri, o.rec[q], o.ech[q], o.east[q], o.ecf[q], pc, zb);
+            if (!last) e.out[(int64_t)row * e.ldo + col] = zh;
+          }
+        }
+      }
+    }
+  };
+
+  const int nk = (K + BK - 1) / BK;
+  constexpr int NF = DEPTH >= 3 ? DEPTH : 1;
+  Ops ops;
+  Regs r0, r1, rf[NF];
+  floatx4 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  gather1(ops);
+  if (DEPTH >= 3) {
+#pragma unroll
+    for (int d = 0; d < NF; ++d) gload(rf[d], min(d, nk - 1) * BK);
+  } else {
+    gload(r0, 0);
+    if (DEPTH == 2) gload(r1, min(1, nk - 1) * BK);
+  }
+  gather2(ops);
   if (DEPTH >= 3) {
     // slab d sits in LDS buffer d & 1; slab d + 1 waits in rf[d + 1]
+    sstore(rf[0], 0, 0);
+    __syncthreads();
 #pragma unroll
     for (int d = 0; d < NF; ++d) {
       if (d >= nk) break;
-      compute(d & 1);
+      compute(acc, d & 1);
       if (d + 1 < NF && d + 1 < nk) sstore(rf[d + 1 < NF ? d + 1 : 0], (d + 1) & 1, (d + 1) * BK);
       __syncthreads();
     }
   } else if (DEPTH == 1) {
+    sstore(r0, 0, 0);
+    __syncthreads();
     for (int kt = 0; kt < nk; ++kt) {
       const int buf = kt & 1;
       if (kt + 1 < nk) gload(r0, (kt + 1) * BK);
-      compute(buf);
+      compute(acc, buf);
       if (kt + 1 < nk) sstore(r0, buf ^ 1, (kt + 1) * BK);
       __syncthreads();
     }
@@ -236,93 +323,22 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt(const float* __restrict__ A,
     // clamped: past the end they repeat the last slab into a buffer nobody
     // reads again), so every load is consumed on every path and no load is
     // left pending where its registers are reused.
+    sstore(r0, 0, 0);
+    __syncthreads();
     for (int kt = 0; kt < nk; kt += 2) {
       const int k2 = min(kt + 2, nk - 1) * BK, k3 = min(kt + 3, nk - 1) * BK;
       gload(r0, k2);
-      compute(0);
+      compute(acc, 0);
       sstore(r1, 1, min(kt + 1, nk - 1) * BK);
       __syncthreads();
       if (kt + 1 >= nk) break;
       gload(r1, k3);
-      compute(1);
+      compute(acc, 1);
       sstore(r0, 0, k2);
       __syncthreads();
     }
   }
-
-  // ---- epilogue: lane holds rows 4*(lane/16)+r of each 16x16 block, column lane%16
-  if (MODE == kBwdRelax || MODE == kBwdConc) {
-    float cst[FM][4];
-#pragma unroll
-    for (int i = 0; i < FM; ++i) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        cst[i][r] = 0.f;
-        const int row = m0 + wm * WM + i * 16 + rsub + r;
-        const bool rok = row < M;
-        const RowInfo& ri = eri[i][r];
-#pragma unroll
-        for (int j = 0; j < FN; ++j) {
-          const int col = n0 + wn * WN + j * 16 + csub;
-          const int q = (i * 4 + r) * FN + j;
-          const float a = acc[i][j][r];
-          const bool ok = rok && col < N;
-          if (MODE == kBwdRelax) {
-            if (ok) {
-              if (v.acomp && (rec[q] & kKindMask) == kUnstable) v.acomp[ri.abase + (rec[q] & kCidxMask)] = a;
-              e.out[(int64_t)row * e.ldo + col] = relax_value(bt, v, ri, rec[q], ech[q], ecf[q], a, ebias[j], &cst[i][r]);
-            }
-          } else {
-            if (ok) cst[i][r] += conc_term(a, ech[q].x, ech[q].y);
-            if (ok && v.xdense) v.xdense[(int64_t)row * v.ldx + col] = xstar(a > 0.f, a < 0.f, ech[q].x, ech[q].y);
-            if (v.xpos) {
-              const uint64_t mp = __ballot(ok && a > 0.f);
-              const uint64_t mn = __ballot(ok && a < 0.f);
-              const int cb = n0 + wn * WN + j * 16;
-              if (csub == 0 && rok && cb < N) {
-                const int g = lane >> 4;
-                reinterpret_cast<uint16_t*>(v.xpos + (int64_t)row * bt.w64)[cb >> 4] = (uint16_t)(mp >> (16 * g));
-                reinterpret_cast<uint16_t*>(v.xneg + (int64_t)row * bt.w64)[cb >> 4] = (uint16_t)(mn >> (16 * g));
-              }
-            }
-          }
-        }
-        cst[i][r] = wave_sum16(cst[i][r]);
-      }
-    }
-    // combine the two column halves (wn = 0, 1) of each row, one slot per tile
-    if (csub == 0) {
-#pragma unroll
-      for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) red[wn][wm * WM + i * 16 + rsub + r] = cst[i][r];
-    }
-    __syncthreads();
-    for (int t = tid; t < BM; t += 256) {
-      const int row = m0 + t;
-      if (row < M) e.part[(int64_t)(e.slot0 + tn) * M + row] = red[0][t] + red[1][t];
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < FM; ++i) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm * WM + i * 16 + rsub + r;
-        if (row >= M) continue;
-        const RowInfo& ri = eri[i][r];
-#pragma unroll
-        for (int j = 0; j < FN; ++j) {
-          const int col = n0 + wn * WN + j * 16 + csub;
-          if (col >= N) continue;
-          const int q = (i * 4 + r) * FN + j;
-          const float zb = acc[i][j][r] + ebias[j];
-          const int64_t pc = (int64_t)ri.p * bt.nd + e.layer_off + col;
-          const float zh = relax_fwd_value(bt, v, ri, rec[q], ech[q], east[q], ecf[q], pc, zb);
-          if (!last) e.out[(int64_t)row * e.ldo + col] = zh;
-        }
-      }
-    }
-  }
+  epilogue(ops, acc);
 }
 
 template <int BM, int BN, int BK, int OCC, int DEPTH>
