@@ -218,7 +218,7 @@ __device__ __forceinline__ void relax_phase(const ChainArgs& a, const RowInfo& r
   for (int j0 = sub; j0 < n; j0 += TPR * E) {
     uint32_t rec[E];
     float2 ch[E];
-    float av[E], bs[E], cf[E];
+    float av[E], bs[E], al[E], be[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int j = j0 + TPR * e;
@@ -231,13 +231,13 @@ __device__ __forceinline__ void relax_phase(const ChainArgs& a, const RowInfo& r
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int64_t pc = (int64_t)ri.p * a.bt.nd + off + j0 + TPR * e;
-      cf[e] = relax_coef(a.bt, a.v, ri, rec[e], pc);
+      relax_vars(a.bt, a.v, ri, rec[e], pc, &al[e], &be[e]);
       if (a.v.acomp && (rec[e] & kKindMask) == kUnstable) a.v.acomp[ri.abase + (rec[e] & kCidxMask)] = av[e];
     }
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int j = j0 + TPR * e;
-      if (j < n) dst[j] = relax_value(a.bt, a.v, ri, rec[e], ch[e], cf[e], av[e], bs[e], cst);
+      if (j < n) dst[j] = relax_value(a.bt, a.v, ri, rec[e], ch[e], relax_pick(rec[e], al[e], be[e]), av[e], bs[e], cst);
     }
   }
 }

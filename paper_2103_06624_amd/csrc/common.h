@@ -70,14 +70,23 @@ struct Vars {
 
 // One projected Adam ascent step on entry i (Kingma & Ba: beta1 0.9, beta2
 // 0.999, eps 1e-8; bc1 = 1 - 0.9^t, bc2 = 1 - 0.999^t), clamped to [lo, hi].
-__device__ __forceinline__ void adam_apply(float* x, float* m1, float* m2, int64_t i, float g, float lr, float bc1,
-                                           float bc2, float lo, float hi) {
-  const float a = 0.9f * m1[i] + 0.1f * g;
-  const float b = 0.999f * m2[i] + 0.001f * g * g;
+// adam_step takes the entry's current value and moments as arguments (read
+// ahead by the caller); adam_apply reads them itself.
+__device__ __forceinline__ void adam_step(float* x, float* m1, float* m2, int64_t i, float g, float lr, float bc1,
+                                          float bc2, float lo, float hi, float xv, float m1v, float m2v) {
+  // fmaf keeps the products with the moments next to g: a product of a moment
+  // alone would be hoisted to where the moment is read ahead, stalling there
+  const float a = fmaf(0.9f, m1v, 0.1f * g);
+  const float b = fmaf(0.999f, m2v, 0.001f * g * g);
   m1[i] = a;
   m2[i] = b;
   const float step = lr * (a / bc1) / (sqrtf(b / bc2) + 1e-8f);
-  x[i] = fminf(fmaxf(x[i] + step, lo), hi);
+  x[i] = fminf(fmaxf(xv + step, lo), hi);
+}
+
+__device__ __forceinline__ void adam_apply(float* x, float* m1, float* m2, int64_t i, float g, float lr, float bc1,
+                                           float bc2, float lo, float hi) {
+  adam_step(x, m1, m2, i, g, lr, bc1, bc2, lo, hi, x[i], m1[i], m2[i]);
 }
 
 // Per-launch epilogue parameters (one layer).
@@ -133,17 +142,24 @@ __device__ __forceinline__ float relax_value(const Batch& bt, const Vars& v, con
   return lam;
 }
 
-// The variable that multiplies neuron (row, col): alpha for an unstable
-// neuron, beta for a split one (0 otherwise).
-__device__ __forceinline__ float relax_coef(const Batch& bt, const Vars& v, const RowInfo& ri, uint32_t rec,
-                                            int64_t pc) {
+// The variables that multiply neuron (row, col): alpha for an unstable
+// neuron, beta for a split one, each read into a register of its own (two
+// loads into one register from the two sides of a divergent branch would
+// make the second wait for every load in flight).
+__device__ __forceinline__ void relax_vars(const Batch& bt, const Vars& v, const RowInfo& ri, uint32_t rec, int64_t pc,
+                                           float* al, float* be) {
   const uint32_t kind = rec & kKindMask;
+  *al = 0.f;
+  *be = 0.f;
   if (kind == kUnstable) {
     const int64_t ai = ri.abase + (rec & kCidxMask);
-    return v.alpha ? v.alpha[ai] : bt.adef[pc];
+    *al = v.alpha ? v.alpha[ai] : bt.adef[pc];
   }
-  if (kind == kSplit) return v.beta[(int64_t)(rec & kSplitMask) * bt.m + ri.k];
-  return 0.f;
+  if (kind == kSplit) *be = v.beta[(int64_t)(rec & kSplitMask) * bt.m + ri.k];
+}
+
+__device__ __forceinline__ float relax_pick(uint32_t rec, float al, float be) {
+  return (rec & kKindMask) == kSplit ? be : al;
 }
 
 __device__ __forceinline__ float relax_bwd(const Batch& bt, const Vars& v, const RowInfo& ri, int layer_off,
@@ -153,7 +169,9 @@ __device__ __forceinline__ float relax_bwd(const Batch& bt, const Vars& v, const
   const int64_t pc = (int64_t)ri.p * bt.nd + col;
   const float2 ch = bt.chord[pc];
   if (v.acomp && (rec & kKindMask) == kUnstable) v.acomp[ri.abase + (rec & kCidxMask)] = a;
-  return relax_value(bt, v, ri, rec, ch, relax_coef(bt, v, ri, rec, pc), a, bias, cst);
+  float al, be;
+  relax_vars(bt, v, ri, rec, pc, &al, &be);
+  return relax_value(bt, v, ri, rec, ch, relax_pick(rec, al, be), a, bias, cst);
 }
 
 // Box minimiser contribution min(a xl, a xu) (Eq. beta_crown_lp for a box).
@@ -171,8 +189,11 @@ __device__ __forceinline__ float xstar(bool pos, bool neg, float xl, float xu) {
 // this (row, neuron) -- or applies the fused Adam step -- and returns
 // zhat(i)_j = D zbar + lowerb.  a_st is the stored A(i)_j and al the alpha of
 // an unstable neuron; be is the beta of a split neuron.
+// With mom_ahead, mom holds the Adam moments of an unstable neuron's alpha,
+// read ahead by the caller together with al (its current value).
 __device__ __forceinline__ float relax_fwd_value(const Batch& bt, const Vars& v, const RowInfo& ri, uint32_t rec,
-                                                 float2 ch, float a_st, float al, int64_t pc, float zb) {
+                                                 float2 ch, float a_st, float al, int64_t pc, float zb,
+                                                 bool mom_ahead = false, float2 mom = float2{0.f, 0.f}) {
   const uint32_t kind = rec & kKindMask;
   if (kind == kActive) return zb;
   if (kind == kInactive) return 0.f;
@@ -186,7 +207,8 @@ __device__ __forceinline__ float relax_fwd_value(const Batch& bt, const Vars& v,
       g = 0.f;
       zh = fmaf(ch.x, zb, ch.y);
     }
-    if (v.adam) adam_apply(v.alpha_w, v.ma, v.va, ai, g, v.lr_a, v.bc1, v.bc2, 0.f, 1.f);
+    if (v.adam && mom_ahead) adam_step(v.alpha_w, v.ma, v.va, ai, g, v.lr_a, v.bc1, v.bc2, 0.f, 1.f, al, mom.x, mom.y);
+    else if (v.adam) adam_apply(v.alpha_w, v.ma, v.va, ai, g, v.lr_a, v.bc1, v.bc2, 0.f, 1.f);
     else v.galpha[ai] = g;
     return zh;
   }

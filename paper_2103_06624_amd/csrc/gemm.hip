@@ -49,6 +49,8 @@ struct TileOps {
   uint32_t rec[NE];
   float2 ech[NE];
   float ecf[NE], east[NE], ebias[FN];
+  float ebe[NE];   // relaxation: beta of a split neuron (ecf holds alpha)
+  float2 emo[NE];  // adjoint with Adam: the moments of an unstable neuron's alpha
 };
 
 // OCC > 0 asks the compiler for at least OCC waves per SIMD (registers capped
@@ -181,6 +183,8 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt(const float* __restrict__ A,
           o.ech[q] = make_float2(0.f, 0.f);
           o.ecf[q] = 0.f;
           o.east[q] = 0.f;
+          o.ebe[q] = 0.f;
+          o.emo[q] = make_float2(0.f, 0.f);
           if (row >= M || col >= N) continue;
           if (MODE == kBwdConc) {
             const int64_t pb = (int64_t)ri.p * bt.d0 + col;
@@ -191,11 +195,12 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt(const float* __restrict__ A,
           const bool uns = (o.rec[q] & kKindMask) == kUnstable;
           if (uns) o.ech[q] = bt.chord[pc];
           if (MODE == kBwdRelax) {
-            o.ecf[q] = relax_coef(bt, v, ri, o.rec[q], pc);
+            relax_vars(bt, v, ri, o.rec[q], pc, &o.ecf[q], &o.ebe[q]);
           } else if (uns) {
             const int64_t ai = ri.abase + (o.rec[q] & kCidxMask);
             o.east[q] = v.acomp[ai];
             o.ecf[q] = v.alpha ? v.alpha[ai] : bt.adef[pc];
+            if (v.adam) o.emo[q] = make_float2(v.ma[ai], v.va[ai]);
           }
         }
   };
@@ -221,8 +226,8 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt(const float* __restrict__ A,
             if (MODE == kBwdRelax) {
               if (ok) {
                 if (v.acomp && (o.rec[q] & kKindMask) == kUnstable) v.acomp[ri.abase + (o.rec[q] & kCidxMask)] = a;
-                e.out[(int64_t)row * e.ldo + col] =
-                    relax_value(bt, v, ri, o.rec[q], o.ech[q], o.ecf[q], a, o.ebias[j], &cst[i][r]);
+                e.out[(int64_t)row * e.ldo + col] = relax_value(
+                    bt, v, ri, o.rec[q], o.ech[q], relax_pick(o.rec[q], o.ecf[q], o.ebe[q]), a, o.ebias[j], &cst[i][r]);
               }
             } else {
               if (ok) cst[i][r] += conc_term(a, o.ech[q].x, o.ech[q].y);
@@ -269,7 +274,7 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt(const float* __restrict__ A,
             const int q = (i * 4 + r) * FN + j;
             const float zb = acc[i][j][r] + o.ebias[j];
             const int64_t pc = (int64_t)ri.p * bt.nd + e.layer_off + col;
-            const float zh = relax_fwd_value(bt, v, ri, o.rec[q], o.ech[q], o.east[q], o.ecf[q], pc, zb);
+            const float zh = relax_fwd_value(bt, v, ri, o.rec[q], o.ech[q], o.east[q], o.ecf[q], pc, zb, true, o.emo[q]);
             if (!last) e.out[(int64_t)row * e.ldo + col] = zh;
           }
         }

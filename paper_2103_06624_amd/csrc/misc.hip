@@ -126,19 +126,20 @@ __global__ __launch_bounds__(256) void top_k(TopArgs a) {
       continue;
     }
     float2 ch[E];
-    float cf[E];
+    float al[E], be[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int64_t pc = (int64_t)ri.p * a.bt.nd + a.e.layer_off + j0 + 64 * e;
       ch[e] = (rec[e] & kKindMask) == kUnstable ? a.bt.chord[pc] : make_float2(0.f, 0.f);
-      cf[e] = relax_coef(a.bt, a.v, ri, rec[e], pc);
+      relax_vars(a.bt, a.v, ri, rec[e], pc, &al[e], &be[e]);
     }
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int j = j0 + 64 * e;
       if (j >= a.n) continue;
       if (a.v.acomp && (rec[e] & kKindMask) == kUnstable) a.v.acomp[ri.abase + (rec[e] & kCidxMask)] = av[e];
-      a.e.out[(int64_t)row * a.e.ldo + j] = relax_value(a.bt, a.v, ri, rec[e], ch[e], cf[e], av[e], b1[e], &cst);
+      a.e.out[(int64_t)row * a.e.ldo + j] =
+          relax_value(a.bt, a.v, ri, rec[e], ch[e], relax_pick(rec[e], al[e], be[e]), av[e], b1[e], &cst);
     }
   }
   cst = wave_sum(cst);
