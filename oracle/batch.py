@@ -114,6 +114,12 @@ class OracleProblem:
         return bc.bound(self.net64, self.x_lo[p], self.x_hi[p], self.C[p], lo, up, split,
                         self.alpha_to_layers(b, alpha_flat), self.beta_to_layers(b, beta_flat))
 
+    def upper(self, b, alpha_flat, beta_flat):
+        """(g [m], ub [m], sat [m], margin [m]) of subdomain b (beta_crown.upper_bound)."""
+        p, lo, up, split = self.domain(b)
+        return bc.upper_bound(self.net64, self.x_lo[p], self.x_hi[p], self.C[p], lo, up, split,
+                              self.alpha_to_layers(b, alpha_flat), self.beta_to_layers(b, beta_flat))
+
     def grad(self, b, alpha_flat, beta_flat):
         """(g [m], dalpha in the compact block of b, dbeta [depth_b, m])."""
         p, lo, up, split = self.domain(b)

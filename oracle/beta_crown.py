@@ -203,6 +203,51 @@ def bound_and_grad(net64, x_lo, x_hi, C, lo, up, split, alpha, beta):
 
 
 # ----------------------------------------------------------------------------
+# the primal side: an upper bound from the box minimiser (Alg. 1 and its
+# footnote; infeasibility check of the appendix on infeasible subdomains)
+
+
+def upper_bound(net64, x_lo, x_hi, C, lo, up, split, alpha, beta):
+    """The lower bound g, and for each specification row the network itself
+    evaluated at that row's box minimiser x* (the x that minimises the final
+    linear function A(0) x + c over the box, Eq. beta_crown_linear).
+
+    x* lies in the box, so ub = (C f(x*))_k bounds min over the box of
+    (C f(x))_k from above (Alg. 1 takes f(x*) as the subdomain's upper bound;
+    ub < 0 is a counter-example).  sat_k says whether x* also meets every split
+    of the subdomain -- z(i)_j(x*) >= 0 for a z >= 0 split, <= 0 for a z < 0
+    split (the strict inequality closed, as in the LP) -- in which case ub
+    also bounds the subdomain's own minimum from above, so g <= ub; a
+    subdomain whose optimised g exceeds an upper bound that its minimum must
+    meet is infeasible (the appendix on infeasibility).  margin_k is the
+    smallest |z(i)_j(x*)| over the split neurons (inf without splits): how far
+    sat_k is from a tie.  Returns (g [m], ub [m], sat [m] bool, margin [m]).
+    """
+    L = len(net64)
+    g, A0, _ = bound(net64, x_lo, x_hi, C, lo, up, split, alpha, beta, keep=True)
+    xs = box_minimiser(A0, x_lo, x_hi)
+    m = C.shape[0]
+    ub = np.zeros(m)
+    sat = np.ones(m, bool)
+    margin = np.full(m, np.inf)
+    for k in range(m):
+        h = xs[k]
+        for i in range(1, L):
+            W, b = net64[i - 1]
+            z = W @ h + b
+            sp = split[i - 1]
+            broken = ((sp > 0) & (z < 0)) | ((sp < 0) & (z > 0))
+            if broken.any():
+                sat[k] = False
+            if (sp != 0).any():
+                margin[k] = min(margin[k], np.abs(z[sp != 0]).min())
+            h = np.maximum(z, 0.0)
+        W, b = net64[L - 1]
+        ub[k] = C[k] @ (W @ h + b)
+    return g, ub, sat, margin
+
+
+# ----------------------------------------------------------------------------
 # intermediate bounds at the root (per-layer CROWN, beta = 0, no splits)
 
 

@@ -219,11 +219,13 @@ def max_over_beta_lp(bound_fn, nbeta, x_lo, x_hi):
 # Theorem 3.2 dual propagation form (L-inf ball around x0 with radius eps)
 
 
-def dual_nu_bound(net, x0, eps, c_row, lo, up, split, alpha, beta):
+def dual_nu_bound(net, x0, eps, c_row, lo, up, split, alpha, beta, with_input=False):
     """g from nu(L) = -c, nu-hat(i-1) = W(i)^T nu(i) and the per-neuron rules of
     the dual problem (inactive 0, active nu-hat, unstable
     u/(u-l)[nu-hat]^+ - alpha [nu-hat]^-, z<0 split -beta, z>=0 split beta + nu-hat).
-    Returns (g, list of nu-hat per ReLU layer) ."""
+    Returns (g, list of nu-hat per ReLU layer), and with with_input also
+    nu-hat(0) = W(1)^T nu(1), whose negation is the coefficient of x in the
+    dual objective."""
     L = len(net)
     nu = -np.asarray(c_row, float)
     obj = 0.0
@@ -253,7 +255,8 @@ def dual_nu_bound(net, x0, eps, c_row, lo, up, split, alpha, beta):
                 new[j] = u[j] / (u[j] - l[j]) * pos - alpha[k - 1][j] * neg
                 lterm += l[j] * max(new[j], 0.0)
         nu = new
-    return obj - nh @ x0 - np.abs(nh).sum() * eps + lterm, nuhats
+    g = obj - nh @ x0 - np.abs(nh).sum() * eps + lterm
+    return (g, nuhats, nh) if with_input else (g, nuhats)
 
 
 def explicit_bound(net, x_lo, x_hi, c_row, Ds, lbs, split, beta):

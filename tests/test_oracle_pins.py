@@ -321,3 +321,76 @@ def test_optimise_monotone_and_below_lp(seed):
     assert best[0] >= g0[0] - 1e-12 and best[0] >= gf[0]
     assert best[0] <= p_lp + 1e-8
     assert all(np.all((x >= 0) & (x <= 1)) for x in a) and all(np.all(x >= 0) for x in b)
+
+
+# ---------------------------------------------------------------------------
+# The primal side: ub = C f(x*) at the box minimiser (Alg. 1 and its footnote)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_upper_bound_is_the_network_at_the_dual_minimiser(seed):
+    """x* rebuilt from the Theorem 3.2 dual form (coefficient of x = -nu-hat(0),
+    minimised over the l-inf ball coordinate by coordinate); the network run
+    forward at that point by an independent evaluator gives ub, its split
+    pre-activations give sat and margin."""
+    rng, net, x0, eps, x_lo, x_hi, lo, up, C = tiny_case(seed + 200, widths=(3, 6, 5, 4, 2), m=2)
+    split = random_split(rng, lo, up, k=3)
+    alpha, beta = random_vars(rng, lo, 2, split, beta_scale=2.0)
+    g, ub, sat, margin = bc.upper_bound(net, x_lo, x_hi, C, lo, up, split, alpha, beta)
+    for r in range(2):
+        gd, _, nh0 = pinlib.dual_nu_bound(net, x0, eps, C[r], lo, up, split, [a[r] for a in alpha],
+                                          [b[r] for b in beta], with_input=True)
+        assert abs(gd - g[r]) <= 1e-10 * max(1, abs(g[r]))
+        coef = -nh0
+        xs = np.where(coef > 0, x_lo, np.where(coef < 0, x_hi, x0))
+        zs, logits = pinlib.forward_all(net, xs[None, :])
+        assert abs(ub[r] - C[r] @ logits[0]) <= 1e-10 * max(1, abs(ub[r]))
+        ok = all(np.all(z[0][s > 0] >= 0) and np.all(z[0][s < 0] <= 0) for z, s in zip(zs, split))
+        mg = min([np.abs(z[0][s != 0]).min() for z, s in zip(zs, split) if (s != 0).any()] + [np.inf])
+        assert bool(sat[r]) == ok
+        assert mg == margin[r] or abs(mg - margin[r]) <= 1e-12 * max(1.0, mg)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_upper_bound_meets_lower_bound_where_the_network_is_affine(seed):
+    """Biases large enough that every hidden neuron is active on the box: the
+    network is affine there, the relaxation is exact, and x* is the true
+    minimiser, so g = ub."""
+    rng = np.random.default_rng(seed + 300)
+    net = pinlib.random_net(rng, [3, 5, 4, 2])
+    # hidden layers after the first take |W| so that positive inputs stay positive
+    net = [(W if i == 0 or i == len(net) - 1 else np.abs(W), b + (25.0 if i < len(net) - 1 else 0.0))
+           for i, (W, b) in enumerate(net)]
+    x_lo = rng.uniform(-0.5, 0.0, size=3)
+    x_hi = x_lo + 0.8
+    lo, up = bc.root_bounds(net, x_lo, x_hi)
+    assert all((l > 0).all() for l in lo)
+    C = rng.standard_normal((3, 2))
+    alpha = [rng.uniform(0, 1, size=(3, l.shape[0])) for l in lo]
+    beta = [np.zeros((3, l.shape[0])) for l in lo]
+    split = [np.zeros(l.shape[0], np.int8) for l in lo]
+    g, ub, sat, margin = bc.upper_bound(net, x_lo, x_hi, C, lo, up, split, alpha, beta)
+    assert np.allclose(g, ub, rtol=0, atol=1e-9 * max(1.0, np.abs(g).max()))
+    assert sat.all() and np.isinf(margin).all()
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_upper_bound_brackets_the_minimum(seed):
+    """x* is a point of the box, so ub is at least the unsplit problem's
+    minimum, hence at least any sound lower bound of it (here the brute-force
+    grid minimum minus the grid's reach is not needed: the unsplit bound at any
+    alpha is below the minimum); where x* meets the splits, the subdomain's
+    own lower bound is below ub too."""
+    rng, net, _, _, x_lo, x_hi, lo, up, C = tiny_case(seed + 400, widths=(2, 6, 6, 2), m=2)
+    none = [np.zeros(l.shape[0], np.int8) for l in lo]
+    for trial in range(4):
+        split = random_split(rng, lo, up, k=trial)
+        alpha, beta = random_vars(rng, lo, 2, split, beta_scale=2.0)
+        g, ub, sat, _ = bc.upper_bound(net, x_lo, x_hi, C, lo, up, split, alpha, beta)
+        g_free = bc.bound(net, x_lo, x_hi, C, lo, up, none, alpha, [np.zeros_like(b) for b in beta])
+        gm = pinlib.grid_min(net, C, x_lo, x_hi, none, n=401)
+        assert np.all(ub >= g_free - 1e-12)
+        # the grid holds points no better than the true minimum, which ub cannot beat by more than the
+        # grid's resolution; here checked one-sided: ub is never below a sound lower bound of the minimum
+        assert np.all(g_free <= gm + 1e-9)
+        assert np.all(g[sat] <= ub[sat] + 1e-12)
