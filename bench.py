@@ -230,6 +230,20 @@ def main():
     torch.cuda.synchronize()
     ms_eval = (time.perf_counter() - t0) / n_eval * 1e3
 
+    # ---- the primal side on the same batch: bound, x*, the network at x*
+    # and the split check (cv_bound_upper), at the default start
+    for _ in range(3):
+        _, ub, sat = pb.upper(a0, b0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n_eval):
+        _, ub, sat = pb.upper(a0, b0)
+    torch.cuda.synchronize()
+    ms_upper = (time.perf_counter() - t0) / n_eval * 1e3
+    upper = {"value": round(B / (ms_upper / 1e3), 1), "unit": "subdomain (lower, upper) bound pairs/s",
+             "ms_per_call": round(ms_upper, 4), "rows_meeting_splits": int(sat.sum().item()),
+             "rows_below_zero": int((ub < 0).sum().item())}
+
     # ---- per-kernel durations with HIP events on the launch stream
     log("[bench] per-kernel event timing")
     stats = pb.profile(a0, b0, reps=5)
@@ -301,6 +315,7 @@ def main():
                    "lr_decay": args.decay, "root_bounds": "per-layer CROWN on the GPU"},
         "plain_eval": {"value": round(B / (ms_eval / 1e3), 1), "unit": "subdomain bounds/s",
                        "ms_per_eval": round(ms_eval, 4)},
+        "upper_bound": upper,
         "roofline": roof,
         "mfma_kernels_tflops": round(gemm_fl / (gemm_ms * 1e-3) / 1e12, 3) if gemm_ms else None,
         "mfma_kernels_time_share": round(gemm_ms / all_ms, 4) if all_ms else None,

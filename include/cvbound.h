@@ -133,6 +133,26 @@ int cv_bound_eval(cv_bound *h, const float *alpha, const float *beta, float *lb,
 int cv_bound_grad(cv_bound *h, const float *alpha, const float *beta, float *lb,
                   float *g_alpha, float *g_beta, void *stream);
 
+/* The primal side of the branch-and-bound step (Alg. 1 and its footnote; the
+ * appendix on infeasible subdomains): for each row, the box minimiser x* of
+ * the final linear function of the bound at (alpha, beta) (Eq.
+ * beta_crown_linear over the box: x_lo where A(0) > 0, x_hi where A(0) < 0,
+ * the centre where A(0) = 0), and the network itself evaluated at x*:
+ *   ub[r]  = (C_p f(x*))_k, f with its exact ReLUs.  x* lies in the box, so
+ *            ub bounds min over the box of (C_p f(x))_k from above; ub < 0 is
+ *            a counter-example to that specification row;
+ *   sat[r] = 1 if x* meets every split of the row's subdomain (z >= 0 for a
+ *            z >= 0 split, z <= 0 for a z < 0 split), else 0.  Where 1, ub
+ *            also bounds the subdomain's own minimum from above, so lb <= ub
+ *            up to float32 rounding;
+ *   lb[r]  = the bound itself (as cv_bound_eval), or skipped when lb is null.
+ * alpha, beta as for cv_bound_eval; lb, ub [B*m] float32, sat [B*m] int32,
+ * device buffers owned by the caller, written in stream order on `stream`.
+ * Uses the per-layer kernels (and the back-substitution plan of
+ * cv_bound_set_plan).  CV_EINVAL on a null ub, sat or required variable. */
+int cv_bound_upper(cv_bound *h, const float *alpha, const float *beta, float *lb, float *ub, int32_t *sat,
+                   void *stream);
+
 /* Projected Adam ascent (Kingma & Ba; beta1 0.9, beta2 0.999, eps 1e-8) on
  * alpha in [0,1] and beta >= 0 for `iters` steps; step t (0-based, counted
  * from step0) uses learning rate lr * lr_decay^t and bias corrections of step

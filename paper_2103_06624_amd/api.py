@@ -130,6 +130,16 @@ class BoundProblem:
         B.check(B.cv_bound_grad(self.h, _dptr(alpha), _dptr(beta), _dptr(lb), _dptr(ga), _dptr(gb), _stream()))
         return lb.view(self.B, self.m), ga, gb
 
+    def upper(self, alpha, beta, with_lb=True):
+        """(lb, ub, sat) [B, m]: the bound, the network at each row's box
+        minimiser x*, and whether x* meets the subdomain's splits."""
+        lb = self._f(self.n_rows) if with_lb else None
+        ub = self._f(self.n_rows)
+        sat = torch.empty(self.n_rows, dtype=torch.int32, device="cuda")
+        B.check(B.cv_bound_upper(self.h, _dptr(alpha), _dptr(beta), _dptr(lb), _dptr(ub), ctypes.c_void_p(sat.data_ptr()),
+                                 _stream()))
+        return (lb.view(self.B, self.m) if with_lb else None), ub.view(self.B, self.m), sat.view(self.B, self.m)
+
     def optimize(self, alpha, beta, iters=20, lr_alpha=0.01, lr_beta=0.05, decay=0.98, adam_state=None, step0=0,
                  lb_best=None, lb_last=None):
         """In-place projected Adam on alpha, beta; returns (best, last) bounds [B, m]."""

@@ -1142,6 +1142,49 @@ int cv_bound_alpha_init(cv_bound* h, float* alpha, void* stream) {
   return CV_OK;
 }
 
+// The network's own forward pass at each row's x* (left by a gradient-style
+// back-substitution in xdense or the sign planes): exact ReLU, split checks
+// into sat, then ub = C_p (W(L) zhat(L-1) + b(L)).  Per-layer kernels only.
+int enqueue_true_fwd(cv_bound* h, float* ub, int32_t* sat, hipStream_t s) {
+  const int L = h->L;
+  launch_fill_i32(sat, 1, h->R, s);
+  Vars v{};
+  v.xpos = h->xpos;
+  v.xneg = h->xneg;
+  v.sat = sat;
+  for (int i = 1; i <= L - 1; ++i) {
+    const DevLayer& ly = h->layers[i - 1];
+    const bool xd = i == 1 && ly.type == CV_LAYER_DENSE;
+    const int mode = i == 1 && !xd ? kFwdX : kFwd;
+    Epi e = make_epi(h);
+    e.layer_off = h->offs[i - 1];
+    e.bias = ly.bias;
+    e.n = h->dims[i];
+    e.out = h->act[i & 1];
+    const float* in = i == 1 ? (xd ? h->xdense : nullptr) : h->act[(i - 1) & 1];
+    const int N = h->dims[i], K = h->dims[i - 1];
+    if (ly.type == CV_LAYER_DENSE) {
+      const int c = h->cfg[L + i - 1] >= 0 ? h->cfg[L + i - 1] : 0;
+      GemmArgs g{in, xd ? h->ldx : h->ldact, ly.W, ly.ld_in, h->R, N, K, 0, h->bt, v, e};
+      launch_gemm(c, mode, g, s);
+    } else {
+      ConvArgs a{in, h->ldact, ly.W, ly.g, h->R, 0, ly.uniform, h->bt, v, e};
+      if (launch_conv_fwd(mode, a, s)) return fail(CV_ESHAPE, "unsupported conv channels");
+    }
+  }
+  TopArgs ta{};
+  ta.CW = h->CW;
+  ta.cw_pstride = h->cw_pstride;
+  ta.ldcw = h->ldcw;
+  ta.Cb = h->Cb;
+  ta.cb_pstride = h->cb_pstride;
+  ta.n = h->dims[L - 1];
+  ta.bt = h->bt;
+  launch_top_dot(ta, h->act[(L - 1) & 1], h->ldact, ub, s);
+  HIPCHK(hipGetLastError());
+  return CV_OK;
+}
+
 int cv_bound_eval(cv_bound* h, const float* alpha, const float* beta, float* lb, void* stream) {
   if (!h || !lb || (!alpha && h->n_alpha > 0) || (!beta && h->nnz > 0)) return fail(CV_EINVAL, "null argument");
   hipStream_t s = (hipStream_t)stream;
@@ -1158,6 +1201,24 @@ int cv_bound_grad(cv_bound* h, const float* alpha, const float* beta, float* lb,
   hipStream_t s = (hipStream_t)stream;
   if ((rc = enqueue_bwd(h, alpha, beta, true, lb, nullptr, 0, s))) return rc;
   return enqueue_fwd(h, alpha, beta, g_alpha, g_beta, nullptr, s);
+}
+
+int cv_bound_upper(cv_bound* h, const float* alpha, const float* beta, float* lb, float* ub, int32_t* sat,
+                   void* stream) {
+  if (!h || !ub || !sat || (!alpha && h->n_alpha > 0) || (!beta && h->nnz > 0)) return fail(CV_EINVAL, "null argument");
+  int rc = ensure_grad(h);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  if (h->R == 0) return CV_OK;
+  if (h->L == 1) {  // no ReLU layer: the bound is exact and attained at x*
+    if ((rc = enqueue_bwd(h, alpha, beta, false, ub, nullptr, 0, s))) return rc;
+    if (lb) HIPCHK(hipMemcpyAsync(lb, ub, sizeof(float) * h->R, hipMemcpyDeviceToDevice, s));
+    launch_fill_i32(sat, 1, h->R, s);
+    HIPCHK(hipGetLastError());
+    return CV_OK;
+  }
+  if ((rc = enqueue_bwd(h, alpha, beta, true, lb, nullptr, 0, s))) return rc;
+  return enqueue_true_fwd(h, ub, sat, s);
 }
 
 int cv_bound_optimize(cv_bound* h, int32_t iters, float lr_alpha, float lr_beta, float lr_decay, float* alpha,

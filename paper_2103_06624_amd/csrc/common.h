@@ -54,6 +54,11 @@ struct Vars {
   uint64_t* xneg;      // [n_rows, w64] bit set where A(0) < 0
   float* xdense;       // [n_rows, ldx] the box minimiser x* itself (dense first layer)
   int ldx;
+  // The network's own forward pass at x* (upper bound) instead of the
+  // adjoint's relaxed one: when set, the forward kernels apply the exact ReLU
+  // and clear sat[row] where a pre-activation breaks a split of the row's
+  // subdomain.
+  int* sat;
   // Projected Adam fused into the adjoint (optimisation passes): when adam is
   // set, each gradient entry is applied in place by its owning (row, neuron)
   // instead of being written to galpha / gbeta.  alpha_w / beta_w alias alpha /
@@ -70,6 +75,18 @@ struct Vars {
 
 // One projected Adam ascent step on entry i (Kingma & Ba: beta1 0.9, beta2
 // 0.999, eps 1e-8; bc1 = 1 - 0.9^t, bc2 = 1 - 0.999^t), clamped to [lo, hi].
+// The exact ReLU of the network at x* (the primal side of Alg. 1): clears
+// *sat_row when zb breaks the split of a split neuron (z >= 0 for a z >= 0
+// split, z <= 0 for a z < 0 split: the strict side closed, as in the LP).
+// Several lanes may clear the same flag; they all store the same 0.
+__device__ __forceinline__ float true_relu(uint32_t rec, float zb, int* sat_row) {
+  if ((rec & kKindMask) == kSplit) {
+    const bool pos = (rec & kSidePos) != 0;
+    if (pos ? zb < 0.f : zb > 0.f) *sat_row = 0;
+  }
+  return fmaxf(zb, 0.f);
+}
+
 // adam_step takes the entry's current value and moments as arguments (read
 // ahead by the caller); adam_apply reads them itself.
 __device__ __forceinline__ void adam_step(float* x, float* m1, float* m2, int64_t i, float g, float lr, float bc1,

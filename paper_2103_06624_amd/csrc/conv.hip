@@ -201,6 +201,11 @@ __global__ __launch_bounds__(256) void conv_fwd(const float* __restrict__ zin, i
     for (int c = 0; c < CO; ++c) {
       const int j = c * pos + q;
       const float zb = acc[c] + e.bias[j];
+      if (v.sat) {  // the network itself at x*: every layer's output is kept
+        const uint32_t rec = bt.status[(int64_t)ri.b * bt.nd + e.layer_off + j];
+        e.out[(int64_t)row * e.ldo + j] = true_relu(rec, zb, v.sat + row);
+        continue;
+      }
       const float zh = relax_fwd(bt, v, ri, e.layer_off, j, zb);
       if (!last) e.out[(int64_t)row * e.ldo + j] = zh;
     }

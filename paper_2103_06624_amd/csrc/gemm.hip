@@ -196,7 +196,7 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt(const float* __restrict__ A,
           if (uns) o.ech[q] = bt.chord[pc];
           if (MODE == kBwdRelax) {
             relax_vars(bt, v, ri, o.rec[q], pc, &o.ecf[q], &o.ebe[q]);
-          } else if (uns) {
+          } else if (uns && !v.sat) {
             const int64_t ai = ri.abase + (o.rec[q] & kCidxMask);
             o.east[q] = v.acomp[ai];
             o.ecf[q] = v.alpha ? v.alpha[ai] : bt.adef[pc];
@@ -273,6 +273,10 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt(const float* __restrict__ A,
             if (col >= N) continue;
             const int q = (i * 4 + r) * FN + j;
             const float zb = acc[i][j][r] + o.ebias[j];
+            if (v.sat) {  // the network itself at x*: every layer's output is kept
+              e.out[(int64_t)row * e.ldo + col] = true_relu(o.rec[q], zb, v.sat + row);
+              continue;
+            }
             const int64_t pc = (int64_t)ri.p * bt.nd + e.layer_off + col;
             const float zh = relax_fwd_value(bt, v, ri, o.rec[q], o.ech[q], o.east[q], o.ecf[q], pc, zb, true, o.emo[q]);
             if (!last) e.out[(int64_t)row * e.ldo + col] = zh;

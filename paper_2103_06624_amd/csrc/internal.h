@@ -161,6 +161,9 @@ struct TopArgs {
   Epi e;
 };
 void launch_top(const TopArgs& a, hipStream_t s);
+// ub[row] = C_p W(L) z[row] + C_p b(L), z = zhat(L-1) of the network at x*
+void launch_top_dot(const TopArgs& a, const float* z, int ldz, float* ub, hipStream_t s);
+void launch_fill_i32(int* p, int v, int64_t n, hipStream_t s);
 void launch_finalize(const float* part, int n_slots, int n_used, int n_rows, float* lb, float* best, int first,
                      hipStream_t s);
 void launch_adam(float* x, const float* g, float* m1, float* m2, int64_t n, float lr, float bc1, float bc2,

@@ -146,6 +146,26 @@ __global__ __launch_bounds__(256) void top_k(TopArgs a) {
   if (lane == 0) a.e.part[(int64_t)a.e.slot0 * a.bt.n_rows + row] = cst + a.Cb[ri.p * a.cb_pstride + ri.k];
 }
 
+// ub = C_p W(L) zhat(L-1) + C_p b(L) for each row: the network's output at
+// x* under the row's specification row (one wave per row).
+__global__ __launch_bounds__(256) void top_dot_k(TopArgs a, const float* __restrict__ z, int ldz, float* ub) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= a.bt.n_rows) return;
+  const RowInfo ri = row_info(a.bt, row);
+  const float* cw = a.CW + ri.p * a.cw_pstride + (int64_t)ri.k * a.ldcw;
+  const float* zr = z + (int64_t)row * ldz;
+  float s = 0.f;
+  for (int j = lane; j < a.n; j += 64) s = fmaf(cw[j], zr[j], s);
+  s = wave_sum(s);
+  if (lane == 0) ub[row] = s + a.Cb[ri.p * a.cb_pstride + ri.k];
+}
+
+__global__ __launch_bounds__(256) void fill_i32_k(int* p, int v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
 // lb = sum of the partial constants of a row, in a fixed order
 // (deterministic).  Partials are slot-major [slot][row].  Wave g of a block
 // sums slots g, g+4, g+8, ... of 64 rows with 8 loads in flight per lane; the
@@ -225,6 +245,14 @@ void launch_spec_identity(const float* Wdense, int ldw, const float* wconv, cons
   ConvGeom gg = g ? *g : ConvGeom{};
   spec_identity_k<<<2 * d, 256, 0, s>>>(Wdense, ldw, wconv, gg, g ? 1 : 0, bias_full, d, dprev, CW, ldcw, Cb);
 }
+void launch_top_dot(const TopArgs& a, const float* z, int ldz, float* ub, hipStream_t s) {
+  if (a.bt.n_rows > 0) launch_k(top_dot_k, nblk(a.bt.n_rows, 4), 256, 0, s, a, z, ldz, ub);
+}
+
+void launch_fill_i32(int* p, int v, int64_t n, hipStream_t s) {
+  if (n > 0) fill_i32_k<<<nblk(n, 256), 256, 0, s>>>(p, v, n);
+}
+
 void launch_top(const TopArgs& a, hipStream_t s) { launch_k(top_k, nblk(a.bt.n_rows, 4), 256, 0, s, a); }
 void launch_finalize(const float* part, int n_slots, int n_used, int n_rows, float* lb, float* best, int first,
                      hipStream_t s) {

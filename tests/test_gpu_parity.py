@@ -160,6 +160,40 @@ def test_plan_parity(name, plan):
     check_grad(name, orc, pb, alpha, beta)
 
 
+@pytest.mark.parametrize("name,plan", [(n, None) for n in NAMES] + [("mlp_deep", (1, 0))])
+def test_upper_bound_parity(name, plan):
+    """ub = C f(x*) at each row's box minimiser and the split check, against
+    the oracle.  ub is compared on rows whose A(0) signs are out of float32
+    reach of a tie (x* is then the same point); sat where the smallest split
+    pre-activation at x* is clear of zero.  Rows without splits must have
+    sat = 1, and sat = 1 rows must have lb <= ub."""
+    say("upper bound", name, plan)
+    wl, orc, pb = problem(name)
+    if plan:
+        pb.set_plan(*plan)
+    alpha, beta = cases.random_vars(orc, seed=11)
+    lb, ub, sat = [t.cpu().numpy() for t in pb.upper(dev(alpha), dev(beta))]
+    lb_eval = pb.eval(dev(alpha), dev(beta)).cpu().numpy()
+    assert np.array_equal(lb, lb_eval)
+    n_ub = n_sat = 0
+    for b in range(orc.B):
+        g, u, st, mg = orc.upper(b, alpha, beta)
+        assert guarded_rel(lb[b], g).max() <= TOL
+        ok = kink_free_rows(orc, b, alpha, beta)
+        for k in np.nonzero(ok)[0]:
+            assert guarded_rel(ub[b, k], u[k]) <= TOL, (b, k, ub[b, k], u[k])
+            n_ub += 1
+            if mg[k] > 1e-3:
+                assert bool(sat[b, k]) == bool(st[k]), (b, k, mg[k])
+                n_sat += 1
+        if orc.ptr[b + 1] == orc.ptr[b]:
+            assert (sat[b] == 1).all()
+    assert n_ub >= 0.75 * orc.B * orc.m
+    s1 = sat.astype(bool)
+    assert (lb[s1] <= ub[s1] + TOL * np.maximum(1.0, np.abs(ub[s1]))).all()
+    say(name, "ub rows checked", n_ub, "sat checked", n_sat, "sat=1", int(s1.sum()), "of", sat.size)
+
+
 @pytest.mark.parametrize("name", ["mlp_small", "mlp_deep"])
 def test_every_tiling(name):
     """Every GEMM tiling (tile shape, K slab, loads in flight) on every dense
