@@ -81,6 +81,15 @@ int cv_bound_root_bounds(const cv_layer *layers, int32_t n_layers, int32_t n_pro
                          const float *x_lo, const float *x_hi,
                          float *l_out, float *u_out, void *stream);
 
+/* The same bounds made sound: each is moved outward by a rigorous bound on
+ * its float32 rounding error (the margin of cv_bound_set_sound, with each
+ * layer's bounds built on the previous layers' sound bounds), so l_out and
+ * u_out enclose every pre-activation the network takes on the box.  Same
+ * arguments and behaviour as cv_bound_root_bounds. */
+int cv_bound_root_bounds_sound(const cv_layer *layers, int32_t n_layers, int32_t n_props,
+                               const float *x_lo, const float *x_hi,
+                               float *l_out, float *u_out, void *stream);
+
 /* Build a handle for one batch of subdomains (Theorem 3.1 inputs).
  *   layers[n_layers]: the network; the last layer must be dense.
  *   x_lo, x_hi: host [n_props][d0] input box of each property (the L-inf ball
@@ -210,6 +219,23 @@ int cv_bound_set_parts(cv_bound *h, int32_t nparts);
  * -1..cv_bound_num_tilings()-1. */
 int32_t cv_bound_num_tilings(void);
 int cv_bound_set_tiling(cv_bound *h, int32_t tiling);
+
+/* Sound mode (off by default): every bound this handle reports (eval, grad,
+ * upper, optimize) is lowered by a rigorous bound on its float32 rounding
+ * error, so that it lies below the value the same relaxation (same alpha,
+ * beta and sign decisions) gives in exact arithmetic, hence below the true
+ * minimum (Theorem 3.1's bound is sound for any alpha in [0,1], beta >= 0).
+ * The margin per row is sum over the neurons of the row's Lambda weighted by
+ * per-neuron constants computed once in double from |W|, the root bounds and
+ * the box (matrix-product error g(d_i) sum |Lambda||W| max|input|, the
+ * rounding of Lambda, of the float32 chord and of every addition into the
+ * constant and the concretisation; g(n) = n u'/(1 - n u'), u' = 2^-23), plus
+ * the error of the merged specification C W(L); it is typically 1e-6 of the
+ * bound's magnitude.  Gradients are those of the bound without the margin.
+ * The fused dense chain is not used while sound mode is on (the per-layer
+ * kernels carry the margin).  on: 0 or 1 (else CV_EINVAL).  The first switch
+ * on computes the constants (host work, synchronous on `stream`). */
+int cv_bound_set_sound(cv_bound *h, int32_t on, void *stream);
 
 /* Per-kernel timing of one gradient pass plus one plain evaluation, issued
  * eagerly on `stream`, repeated `reps` times.  Each kernel launch of a pass

@@ -45,8 +45,9 @@ def make_layers(layers):
     return arr, keep
 
 
-def root_bounds(layers, x_lo, x_hi):
-    """Per-layer CROWN intermediate bounds on the GPU: (l, u) float32 [P, sum d_i]."""
+def root_bounds(layers, x_lo, x_hi, sound=False):
+    """Per-layer CROWN intermediate bounds on the GPU: (l, u) float32 [P, sum d_i];
+    sound: moved outward by the rigorous float32 rounding margin."""
     arr, keep = make_layers(layers)
     x_lo = np.ascontiguousarray(x_lo, np.float32)
     x_hi = np.ascontiguousarray(x_hi, np.float32)
@@ -54,7 +55,8 @@ def root_bounds(layers, x_lo, x_hi):
     nd = sum(ly.d_out for ly in layers[:-1])
     lo = np.zeros((P, nd), np.float32)
     up = np.zeros((P, nd), np.float32)
-    B.check(B.cv_bound_root_bounds(arr, len(layers), P, _ptr(x_lo), _ptr(x_hi), _ptr(lo), _ptr(up), _stream()))
+    fn = B.cv_bound_root_bounds_sound if sound else B.cv_bound_root_bounds
+    B.check(fn(arr, len(layers), P, _ptr(x_lo), _ptr(x_hi), _ptr(lo), _ptr(up), _stream()))
     return lo, up
 
 
@@ -169,6 +171,10 @@ class BoundProblem:
     def set_tiling(self, tiling):
         """Force one GEMM tiling on every dense layer (-1: the tuned choice)."""
         B.check(B.cv_bound_set_tiling(self.h, tiling))
+
+    def set_sound(self, on):
+        """Lower every reported bound by a rigorous float32 rounding-error margin."""
+        B.check(B.cv_bound_set_sound(self.h, int(on), _stream()))
 
     def set_parts(self, nparts):
         """Concurrent sub-batches (streams) of optimize(); 1 disables the split."""

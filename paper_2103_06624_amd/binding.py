@@ -42,6 +42,8 @@ _lib = None
 SIGNATURES = {
     "cv_bound_root_bounds": (ctypes.c_int, [ctypes.POINTER(cv_layer), ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp,
                                             _vp, _vp]),
+    "cv_bound_root_bounds_sound": (ctypes.c_int, [ctypes.POINTER(cv_layer), ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp,
+                                            _vp, _vp]),
     "cv_bound_init": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.POINTER(cv_layer), ctypes.c_int32, ctypes.c_int32,
                                      _vp, _vp, ctypes.c_int32, _vp, _vp, _vp, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp,
                                      _vp]),
@@ -59,6 +61,7 @@ SIGNATURES = {
     "cv_bound_set_parts": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "cv_bound_num_tilings": (ctypes.c_int32, []),
     "cv_bound_set_tiling": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "cv_bound_set_sound": (ctypes.c_int, [_vp, ctypes.c_int32, _vp]),
     "cv_bound_profile": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32, ctypes.POINTER(cv_kernel_stat),
                                         ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _vp]),
     "cv_bound_destroy": (None, [_vp]),
@@ -97,6 +100,7 @@ def _fn(name):
 
 
 cv_bound_root_bounds = _fn("cv_bound_root_bounds")
+cv_bound_root_bounds_sound = _fn("cv_bound_root_bounds_sound")
 cv_bound_init = _fn("cv_bound_init")
 cv_bound_sizes = _fn("cv_bound_sizes")
 cv_bound_alpha_offset = _fn("cv_bound_alpha_offset")
@@ -110,6 +114,7 @@ cv_bound_set_plan = _fn("cv_bound_set_plan")
 cv_bound_set_parts = _fn("cv_bound_set_parts")
 cv_bound_num_tilings = _fn("cv_bound_num_tilings")
 cv_bound_set_tiling = _fn("cv_bound_set_tiling")
+cv_bound_set_sound = _fn("cv_bound_set_sound")
 cv_bound_profile = _fn("cv_bound_profile")
 cv_bound_destroy = _fn("cv_bound_destroy")
 cv_last_error = _fn("cv_last_error")

@@ -159,6 +159,13 @@ struct cv_bound {
   float* Cb = nullptr;
   float* act[2] = {nullptr, nullptr};
   float* part = nullptr;
+  // sound mode: per-neuron weights of the rounding-error bound, the bound's
+  // per-row partials and its constant for the merged specification
+  bool sound = false;
+  float* sw = nullptr;    // [P, nd]
+  float* perr = nullptr;  // [n_slots, R]
+  float* err0 = nullptr;  // [P, m]
+  float sound_g = 0.f, sound_scale = 1.f;
   int* ulist = nullptr;
   int64_t* uoff = nullptr;
   // gradient / optimisation buffers (allocated on first use)
@@ -605,6 +612,155 @@ int ensure_opt(cv_bound* h) {
 }
 
 // ---------------------------------------------------------------------------
+// sound mode: a rigorous bound on what float32 rounding can move each bound
+// by, so that the reported value lb - margin lies below the bound computed in
+// exact arithmetic from the same relaxation.  Host double arithmetic, every
+// weight rounded up to float.  Terms, with u' = 2^-23 (twice the unit
+// roundoff, so any rounding mode of the matrix cores is covered) and
+// g(n) = n u' / (1 - n u'):
+//   * the product A(i-1) = Lambda(i) W(i) (K = d_i terms per output for a
+//     dense layer on the matrix cores; at most c_out ceil(k/s)^2 taps for a
+//     transposed convolution, whose FMAs round to nearest: u'/2 there): its
+//     error against the exact product, times any input of layer i (at most
+//     hmax = max(u, 0) of layer i-1, or max(|x_lo|, |x_hi|) at the input), is
+//     at most g(d_i) sum_k |Lambda(i)_k| v_k, v_k = sum_j |W(i)_kj| hmax_j;
+//   * Lambda itself is one rounding away from A D + beta S: u' |Lambda_k| zmax_k;
+//   * the float32 chord of an unstable neuron can sit below the ReLU at the
+//     ends of [l, u] by at most 4u'(s zmax + |t|) (slope s, intercept t);
+//     weighted by |A_k| = |Lambda_k| / s;
+//   * every term added into the constant and the concretisation sum passes
+//     through at most N additions (N bounded from the kernels' reduction
+//     trees and the number of partial slots): G = g(N) + u' times its size,
+//     |Lambda_k b_k| for the bias, |A_k t_k| for the chord intercept;
+//   * the merged specification C W(L), C b(L) (formed once in float32):
+//     g(d_L) (sum_o |C_o| v(L)_o + |C_o b_o|), a per-(property, row) constant.
+// All but the last collapse into one weight per (property, neuron):
+//   sw_k = g(d_i) v_k + u' zmax_k + G |b_k| + [unstable] (4u'(s zmax + |t|) + G |t|) / s,
+// so an epilogue adds |Lambda_k| sw_k per element and G |term| per
+// concretisation term; the final sum scales the margin by (1 + 2 g(N)) for
+// its own rounding and rounds the result down.
+
+float round_up_f(double x) {
+  float f = (float)x;
+  if ((double)f < x) f = std::nextafter(f, INFINITY);
+  return f;
+}
+
+// v_k = sum_j |W_kj| hm_j for one layer (host weights)
+void abs_weighted(const cv_layer& ly, const std::vector<double>& hm, std::vector<double>& v) {
+  if (ly.type == CV_LAYER_DENSE) {
+    for (int k = 0; k < ly.out_c; ++k) {
+      double t = 0.0;
+      const float* w = ly.weight + (size_t)k * ly.in_c;
+      for (int j = 0; j < ly.in_c; ++j) t += std::fabs((double)w[j]) * hm[j];
+      v[k] = t;
+    }
+    return;
+  }
+  for (int c = 0; c < ly.out_c; ++c)
+    for (int oy = 0; oy < ly.out_h; ++oy)
+      for (int ox = 0; ox < ly.out_w; ++ox) {
+        double t = 0.0;
+        for (int ci = 0; ci < ly.in_c; ++ci)
+          for (int ky = 0; ky < ly.kernel; ++ky) {
+            const int iy = oy * ly.stride - ly.pad + ky;
+            if (iy < 0 || iy >= ly.in_h) continue;
+            for (int kx = 0; kx < ly.kernel; ++kx) {
+              const int ix = ox * ly.stride - ly.pad + kx;
+              if (ix < 0 || ix >= ly.in_w) continue;
+              const float w = ly.weight[(((size_t)c * ly.in_c + ci) * ly.kernel + ky) * ly.kernel + kx];
+              t += std::fabs((double)w) * hm[((size_t)ci * ly.in_h + iy) * ly.in_w + ix];
+            }
+          }
+        v[((size_t)c * ly.out_h + oy) * ly.out_w + ox] = t;
+      }
+}
+
+// Weights and constants of the margin for handle h from its host inputs
+// (layers, box [P, d0], root bounds [P, nd], C [P, m, dL] unless identity).
+int prepare_sound(cv_bound* h, const cv_layer* layers, const float* x_lo, const float* x_hi, const float* l,
+                  const float* u, const float* C, bool identity, hipStream_t s) {
+  const int L = h->L, P = h->P, m = h->m, nd = h->nd, d0 = h->d0;
+  const double up = std::ldexp(1.0, -23);
+  auto gam = [&](double n) { return n * up / (1.0 - n * up); };
+  // longest addition chain: final sum over slots (and its four-way merge),
+  // plus the longest in-kernel chain (GEMM tiles: a few; top layer: two per
+  // 64 neurons per lane; transposed convolutions: two per input channel per
+  // position a thread owns) and the reduction trees (at most 64 levels)
+  int chain = 0;
+  if (L >= 2) chain = std::max(chain, 2 * ((h->dims[L - 1] + 63) / 64));
+  for (int i = 1; i < L; ++i) {
+    const cv_layer& ly = layers[i - 1];
+    if (ly.type != CV_LAYER_DENSE)
+      chain = std::max(chain, 2 * ly.in_c * ((ly.in_h * ly.in_w + 255) / 256));
+  }
+  chain += h->n_slots + 64;
+  const double G = gam(chain) + up;
+  std::vector<float> sw((size_t)P * std::max(nd, 1), 0.f), e0((size_t)P * m, 0.f);
+  for (int p = 0; p < P; ++p) {
+    std::vector<double> hm(d0);
+    for (int j = 0; j < d0; ++j)
+      hm[j] = std::max(std::fabs((double)x_lo[(size_t)p * d0 + j]), std::fabs((double)x_hi[(size_t)p * d0 + j]));
+    int off = 0;
+    for (int i = 1; i < L; ++i) {
+      const cv_layer& ly = layers[i - 1];
+      const int d = h->dims[i];
+      const int per = ly.type == CV_LAYER_DENSE ? 1 : ly.out_h * ly.out_w;
+      // terms per output of the back-substitution product: all d_i neurons
+      // for a dense layer (matrix cores: u'); for a transposed convolution
+      // the taps of one stride-parity class, at most c_out ceil(k/s)^2
+      // (vector FMAs, one round-to-nearest each: u = u'/2)
+      const int ks = (ly.kernel + ly.stride - 1) / std::max(1, ly.stride);
+      const double gk = ly.type == CV_LAYER_DENSE ? gam(d) : gam(0.5 * ly.out_c * ks * ks);
+      std::vector<double> v(d, 0.0), hn(d);
+      abs_weighted(ly, hm, v);
+      for (int k = 0; k < d; ++k) {
+        const double lk = l[(size_t)p * nd + off + k], uk = u[(size_t)p * nd + off + k];
+        const double zmax = std::max(std::fabs(lk), std::fabs(uk));
+        const double bk = std::fabs((double)ly.bias[k / per]);
+        double w = gk * v[k] + up * zmax + G * bk;
+        if (lk < 0.0 && uk > 0.0) {
+          const double sl = uk / (uk - lk), t = -uk * lk / (uk - lk);
+          w += (4.0 * up * (sl * zmax + std::fabs(t)) + G * std::fabs(t)) / sl;
+        }
+        sw[(size_t)p * nd + off + k] = round_up_f(w);
+        hn[k] = std::max(uk, 0.0);
+      }
+      hm.swap(hn);
+      off += d;
+    }
+    if (!identity) {
+      const cv_layer& ly = layers[L - 1];
+      const int dL = h->dims[L];
+      std::vector<double> vL(dL, 0.0);
+      abs_weighted(ly, hm, vL);
+      for (int k = 0; k < m; ++k) {
+        double e = 0.0, cb = 0.0;
+        for (int o = 0; o < dL; ++o) {
+          const double c = C[((size_t)p * m + k) * dL + o];
+          e += std::fabs(c) * vL[o] + std::fabs(c * ly.bias[o]);
+          cb += c * ly.bias[o];
+        }
+        // 1e-30: room for any flushed denormal along the way
+        e0[(size_t)p * m + k] = round_up_f(gam(dL) * e + G * std::fabs(cb) + 1e-30);
+      }
+    }
+  }
+  int rc;
+  if (!h->sw) {
+    if ((rc = h->mem.alloc(&h->sw, sw.size())) || (rc = h->mem.alloc(&h->err0, e0.size())) ||
+        (rc = h->mem.alloc(&h->perr, (size_t)std::max(1, h->R) * h->n_slots)))
+      return rc;
+  }
+  HIPCHK(hipMemcpyAsync(h->sw, sw.data(), sw.size() * sizeof(float), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(h->err0, e0.data(), e0.size() * sizeof(float), hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  h->sound_g = round_up_f(G);
+  h->sound_scale = round_up_f(1.0 + 2.0 * gam(chain));
+  return CV_OK;
+}
+
+// ---------------------------------------------------------------------------
 // passes
 
 std::string cfg_name(int cfg) {
@@ -616,6 +772,7 @@ std::string cfg_name(int cfg) {
 Epi make_epi(const cv_bound* h) {
   Epi e{};
   e.part = h->part;
+  e.perr = h->sound ? h->perr : nullptr;
   e.n_slots = h->n_slots;
   e.ldo = h->ldact;
   return e;
@@ -665,7 +822,7 @@ int enqueue_bwd(cv_bound* h, const float* alpha, const float* beta, bool grad, f
   Profiler* pf = h->prof;
   if (h->R == 0) return CV_OK;
   int cur = 0, slot = 1, i_next = L - 1;
-  if (h->chain_b) {
+  if (h->chain_b && !h->sound) {
     const int lo = h->chain_lo;
     ChainArgs ca{};
     ca.nl = L - lo;
@@ -721,6 +878,7 @@ int enqueue_bwd(cv_bound* h, const float* alpha, const float* beta, bool grad, f
     ta.cb_pstride = h->cb_pstride;
     ta.n = h->dims[L - 1];
     ta.conc = L == 1;
+    ta.err0 = h->sound ? h->err0 : nullptr;
     ta.bt = h->bt;
     ta.v = v;
     ta.e = make_epi(h);
@@ -770,7 +928,7 @@ int enqueue_bwd(cv_bound* h, const float* alpha, const float* beta, bool grad, f
     cur ^= 1;
   }
   if (pf) pf->begin("finalize", 0, (double)h->R * (slot + 2) * 4.0);
-  launch_finalize(h->part, h->n_slots, slot, h->R, lb, best, first, s);
+  launch_finalize(h->part, h->sound ? h->perr : nullptr, h->sound_scale, h->n_slots, slot, h->R, lb, best, first, s);
   if (pf) pf->end();
   HIPCHK(hipGetLastError());
   return CV_OK;
@@ -1007,6 +1165,18 @@ int set_parts(cv_bound* h, int n) {
     }
     h->pev.push_back(e);
   }
+  // new sub-batches follow the handle's sound mode
+  if (h->sound) {
+    const cv_bound::Inputs& in = *h->in;
+    for (cv_bound* q : h->parts) {
+      int rc = prepare_sound(q, in.layers.data(), in.xlo.data(), in.xhi.data(), in.l.data(), in.u.data(),
+                             in.C.data(), false, nullptr);
+      if (rc) return rc;
+      q->sound = true;
+      q->bt.sw = q->sw;
+      q->bt.sg = q->sound_g;
+    }
+  }
   return CV_OK;
 }
 
@@ -1088,6 +1258,71 @@ void keep_inputs(cv_bound* h, const cv_layer* layers, int n_layers, int P, const
 
 // ===========================================================================
 // ABI
+
+namespace {
+
+// Root bounds of every ReLU layer, one sub-network at a time (layers 1..i,
+// specification [I; -I] on layer i); sound: with the rigorous float32 margin.
+int root_bounds(const cv_layer* layers, int32_t n_layers, int32_t n_props, const float* x_lo, const float* x_hi,
+                float* l_out, float* u_out, bool sound, void* stream) {
+  std::vector<int> dims;
+  int rc = check_layers(layers, n_layers, dims);
+  if (rc) return rc;
+  if (n_props <= 0 || !x_lo || !x_hi) return fail(CV_EINVAL, "bad arguments");
+  int nd = 0;
+  for (int i = 1; i < n_layers; ++i) nd += dims[i];
+  if (nd > 0 && (!l_out || !u_out)) return fail(CV_EINVAL, "null outputs");
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<float> lo((size_t)n_props * nd, 0.f), up((size_t)n_props * nd, 0.f);
+  std::vector<int32_t> prop(n_props);
+  std::vector<int64_t> sptr(n_props + 1, 0);
+  for (int p = 0; p < n_props; ++p) prop[p] = p;
+  int off = 0;
+  for (int i = 1; i < n_layers; ++i) {
+    // sub-network of layers 1..i with specification [I; -I] on layer i
+    const int d = dims[i];
+    std::vector<cv_layer> sub(layers, layers + i);
+    int ndp = off;  // bounds of layers 1..i-1
+    std::vector<float> lsub((size_t)n_props * std::max(1, ndp)), usub((size_t)n_props * std::max(1, ndp));
+    for (int p = 0; p < n_props; ++p)
+      for (int j = 0; j < ndp; ++j) {
+        lsub[(size_t)p * ndp + j] = lo[(size_t)p * nd + j];
+        usub[(size_t)p * ndp + j] = up[(size_t)p * nd + j];
+      }
+    cv_bound hb;
+    Spec sp;
+    sp.identity = true;
+    rc = build(&hb, sub.data(), i, n_props, x_lo, x_hi, 2 * d, sp, lsub.data(), usub.data(), n_props, prop.data(),
+               sptr.data(), nullptr, nullptr, nullptr, s);
+    if (rc) return rc;
+    if (sound) {  // the bounds are lowered (l) and raised (u) by the rigorous float32 margin
+      if ((rc = prepare_sound(&hb, sub.data(), x_lo, x_hi, lsub.data(), usub.data(), nullptr, true, s))) return rc;
+      hb.sound = true;
+      hb.bt.sw = hb.sw;
+      hb.bt.sg = hb.sound_g;
+    }
+    float* dlb;
+    if ((rc = hb.mem.alloc(&dlb, (size_t)hb.R))) return rc;
+    if ((rc = enqueue_bwd(&hb, nullptr, nullptr, false, dlb, nullptr, 0, s))) return rc;
+    std::vector<float> lb(hb.R);
+    HIPCHK(hipMemcpyAsync(lb.data(), dlb, (size_t)hb.R * sizeof(float), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int p = 0; p < n_props; ++p)
+      for (int j = 0; j < d; ++j) {
+        lo[(size_t)p * nd + off + j] = lb[(size_t)p * 2 * d + j];
+        up[(size_t)p * nd + off + j] = -lb[(size_t)p * 2 * d + d + j];
+      }
+    drop_graph(&hb);
+    off += d;
+  }
+  for (size_t t = 0; t < lo.size(); ++t) {
+    l_out[t] = lo[t];
+    u_out[t] = up[t];
+  }
+  return CV_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -1400,6 +1635,27 @@ int cv_bound_set_tiling(cv_bound* h, int32_t tiling) {
   return CV_OK;
 }
 
+int cv_bound_set_sound(cv_bound* h, int32_t on, void* stream) {
+  if (!h || !h->in) return fail(CV_EINVAL, "null handle");
+  if (on != 0 && on != 1) return fail(CV_EINVAL, "sound must be 0 or 1");
+  // the sub-batch handles share the parent's network, boxes and root bounds
+  const cv_bound::Inputs& in = *h->in;
+  std::vector<cv_bound*> all{h};
+  all.insert(all.end(), h->parts.begin(), h->parts.end());
+  for (cv_bound* q : all) {
+    if (on && !q->sw) {
+      int rc = prepare_sound(q, in.layers.data(), in.xlo.data(), in.xhi.data(), in.l.data(), in.u.data(),
+                             in.C.data(), false, (hipStream_t)stream);
+      if (rc) return rc;
+    }
+    q->sound = on != 0;
+    q->bt.sw = q->sound ? q->sw : nullptr;
+    q->bt.sg = q->sound_g;
+    drop_graph(q);
+  }
+  return CV_OK;
+}
+
 int cv_bound_profile(cv_bound* h, const float* alpha, const float* beta, int32_t reps, cv_kernel_stat* out,
                      int32_t max_out, int32_t* n_out, void* stream) {
   if (!h || !out || !n_out || reps <= 0) return fail(CV_EINVAL, "bad argument");
@@ -1460,55 +1716,12 @@ void cv_bound_destroy(cv_bound* h) { destroy_handle(h); }
 
 int cv_bound_root_bounds(const cv_layer* layers, int32_t n_layers, int32_t n_props, const float* x_lo,
                          const float* x_hi, float* l_out, float* u_out, void* stream) {
-  std::vector<int> dims;
-  int rc = check_layers(layers, n_layers, dims);
-  if (rc) return rc;
-  if (n_props <= 0 || !x_lo || !x_hi) return fail(CV_EINVAL, "bad arguments");
-  int nd = 0;
-  for (int i = 1; i < n_layers; ++i) nd += dims[i];
-  if (nd > 0 && (!l_out || !u_out)) return fail(CV_EINVAL, "null outputs");
-  hipStream_t s = (hipStream_t)stream;
-  std::vector<float> lo((size_t)n_props * nd, 0.f), up((size_t)n_props * nd, 0.f);
-  std::vector<int32_t> prop(n_props);
-  std::vector<int64_t> sptr(n_props + 1, 0);
-  for (int p = 0; p < n_props; ++p) prop[p] = p;
-  int off = 0;
-  for (int i = 1; i < n_layers; ++i) {
-    // sub-network of layers 1..i with specification [I; -I] on layer i
-    const int d = dims[i];
-    std::vector<cv_layer> sub(layers, layers + i);
-    int ndp = off;  // bounds of layers 1..i-1
-    std::vector<float> lsub((size_t)n_props * std::max(1, ndp)), usub((size_t)n_props * std::max(1, ndp));
-    for (int p = 0; p < n_props; ++p)
-      for (int j = 0; j < ndp; ++j) {
-        lsub[(size_t)p * ndp + j] = lo[(size_t)p * nd + j];
-        usub[(size_t)p * ndp + j] = up[(size_t)p * nd + j];
-      }
-    cv_bound hb;
-    Spec sp;
-    sp.identity = true;
-    rc = build(&hb, sub.data(), i, n_props, x_lo, x_hi, 2 * d, sp, lsub.data(), usub.data(), n_props, prop.data(),
-               sptr.data(), nullptr, nullptr, nullptr, s);
-    if (rc) return rc;
-    float* dlb;
-    if ((rc = hb.mem.alloc(&dlb, (size_t)hb.R))) return rc;
-    if ((rc = enqueue_bwd(&hb, nullptr, nullptr, false, dlb, nullptr, 0, s))) return rc;
-    std::vector<float> lb(hb.R);
-    HIPCHK(hipMemcpyAsync(lb.data(), dlb, (size_t)hb.R * sizeof(float), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    for (int p = 0; p < n_props; ++p)
-      for (int j = 0; j < d; ++j) {
-        lo[(size_t)p * nd + off + j] = lb[(size_t)p * 2 * d + j];
-        up[(size_t)p * nd + off + j] = -lb[(size_t)p * 2 * d + d + j];
-      }
-    drop_graph(&hb);
-    off += d;
-  }
-  for (size_t t = 0; t < lo.size(); ++t) {
-    l_out[t] = lo[t];
-    u_out[t] = up[t];
-  }
-  return CV_OK;
+  return root_bounds(layers, n_layers, n_props, x_lo, x_hi, l_out, u_out, false, stream);
+}
+
+int cv_bound_root_bounds_sound(const cv_layer* layers, int32_t n_layers, int32_t n_props, const float* x_lo,
+                               const float* x_hi, float* l_out, float* u_out, void* stream) {
+  return root_bounds(layers, n_layers, n_props, x_lo, x_hi, l_out, u_out, true, stream);
 }
 
 }  // extern "C"

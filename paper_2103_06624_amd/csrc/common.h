@@ -41,6 +41,11 @@ struct Batch {
   const float* adef;        // [P, nd] default alpha (used when a pass has no alpha array)
   const float* xlo;         // [P, d0]
   const float* xhi;         // [P, d0]
+  // sound mode (null sw otherwise): weight of |Lambda_k| in each row's bound
+  // on the float32 rounding error, and the weight sg of every term of the
+  // constant and of the concretisation
+  const float* sw;          // [P, nd]
+  float sg;
 };
 
 // Variables of one pass.
@@ -114,6 +119,7 @@ struct Epi {
   float* out;          // [n_rows, ldo] next operand
   int ldo;
   float* part;         // [n_slots, n_rows] partial constants (slot-major)
+  float* perr;         // [n_slots, n_rows] partial rounding-error bounds (sound mode), or null
   int n_slots;
   int slot0;           // first slot of this launch
 };
@@ -179,8 +185,9 @@ __device__ __forceinline__ float relax_pick(uint32_t rec, float al, float be) {
   return (rec & kKindMask) == kSplit ? be : al;
 }
 
+// (sound mode: also adds |Lambda| sw of the neuron to *err)
 __device__ __forceinline__ float relax_bwd(const Batch& bt, const Vars& v, const RowInfo& ri, int layer_off,
-                                          int j, float a, float bias, float* cst) {
+                                          int j, float a, float bias, float* cst, float* err) {
   const int col = layer_off + j;
   const uint32_t rec = bt.status[(int64_t)ri.b * bt.nd + col];
   const int64_t pc = (int64_t)ri.p * bt.nd + col;
@@ -188,7 +195,9 @@ __device__ __forceinline__ float relax_bwd(const Batch& bt, const Vars& v, const
   if (v.acomp && (rec & kKindMask) == kUnstable) v.acomp[ri.abase + (rec & kCidxMask)] = a;
   float al, be;
   relax_vars(bt, v, ri, rec, pc, &al, &be);
-  return relax_value(bt, v, ri, rec, ch, relax_pick(rec, al, be), a, bias, cst);
+  const float lam = relax_value(bt, v, ri, rec, ch, relax_pick(rec, al, be), a, bias, cst);
+  if (bt.sw) *err = fmaf(fabsf(lam), bt.sw[pc], *err);
+  return lam;
 }
 
 // Box minimiser contribution min(a xl, a xu) (Eq. beta_crown_lp for a box).

@@ -62,7 +62,7 @@ template <int CI, int MODE>
 __global__ __launch_bounds__(256) void convt_bwd(const float* __restrict__ lam, int ldl, const float* __restrict__ w,
                                                  ConvGeom g, int M, int uniform, Batch bt, Vars v, Epi e) {
   extern __shared__ float smem[];
-  __shared__ float red[4];
+  __shared__ float red[4], rede[4];
   const int pos = g.hi * g.wi;             // positions of the output plane
   const int din = g.co * g.ho * g.wo;      // length of a Lambda row
   const Slice sl = slice_of(pos);
@@ -86,7 +86,7 @@ __global__ __launch_bounds__(256) void convt_bwd(const float* __restrict__ lam, 
   const float* L = lrow + sl.rl * din;
   const int s = g.s, k = g.k, pad = g.p;
   const int hs = g.hi / s, ws = g.wi / s, cls_n = hs * ws;
-  float cst = 0.f;
+  float cst = 0.f, cer = 0.f;
   for (int q = sl.q0; q < pos; q += sl.qstep) {
     // position q in parity-class order
     int cls = q / cls_n;
@@ -119,10 +119,12 @@ __global__ __launch_bounds__(256) void convt_bwd(const float* __restrict__ lam, 
       const int j = c * pos + y * g.wi + x;
       const float a = acc[c];
       if (MODE == kBwdRelax) {
-        e.out[(int64_t)row * e.ldo + j] = relax_bwd(bt, v, ri, e.layer_off, j, a, e.bias[j], &cst);
+        e.out[(int64_t)row * e.ldo + j] = relax_bwd(bt, v, ri, e.layer_off, j, a, e.bias[j], &cst, &cer);
       } else {
         const int64_t pb = (int64_t)ri.p * bt.d0 + j;
-        cst += conc_term(a, bt.xlo[pb], bt.xhi[pb]);
+        const float tm = conc_term(a, bt.xlo[pb], bt.xhi[pb]);
+        cst += tm;
+        cer = fmaf(bt.sg, fabsf(tm), cer);
         if (v.xpos) {
           if (a > 0.f) atomicOr(&bits[j >> 5], 1u << (j & 31));
           if (a < 0.f) atomicOr(&bits[w32 + (j >> 5)], 1u << (j & 31));
@@ -134,6 +136,13 @@ __global__ __launch_bounds__(256) void convt_bwd(const float* __restrict__ lam, 
   if (threadIdx.x < sl.rb) {
     const int r2 = sl.row0 + threadIdx.x;
     if (r2 < M) e.part[(int64_t)e.slot0 * M + r2] = tot;
+  }
+  if (e.perr) {
+    const float ter = row_sum(cer, pos, rede);
+    if (threadIdx.x < sl.rb) {
+      const int r2 = sl.row0 + threadIdx.x;
+      if (r2 < M) e.perr[(int64_t)e.slot0 * M + r2] = ter;
+    }
   }
   if (MODE == kBwdConc && v.xpos) {
     __syncthreads();

@@ -50,6 +50,7 @@ struct TileOps {
   float2 ech[NE];
   float ecf[NE], east[NE], ebias[FN];
   float ebe[NE];   // relaxation: beta of a split neuron (ecf holds alpha)
+  float esw[NE];   // relaxation, sound mode: the neuron's rounding-error weight
   float2 emo[NE];  // adjoint with Adam: the moments of an unstable neuron's alpha
 };
 
@@ -75,6 +76,7 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt(const float* __restrict__ A,
   __shared__ __attribute__((aligned(16))) float As[2][BM][LDK];
   __shared__ __attribute__((aligned(16))) float Bs[2][BN][LDK];
   __shared__ float red[2][BM];
+  __shared__ float rede[2][BM];  // sound mode: the rounding-error partials
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -184,6 +186,7 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt(const float* __restrict__ A,
           o.ecf[q] = 0.f;
           o.east[q] = 0.f;
           o.ebe[q] = 0.f;
+          o.esw[q] = 0.f;
           o.emo[q] = make_float2(0.f, 0.f);
           if (row >= M || col >= N) continue;
           if (MODE == kBwdConc) {
@@ -196,6 +199,7 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt(const float* __restrict__ A,
           if (uns) o.ech[q] = bt.chord[pc];
           if (MODE == kBwdRelax) {
             relax_vars(bt, v, ri, o.rec[q], pc, &o.ecf[q], &o.ebe[q]);
+            if (bt.sw) o.esw[q] = bt.sw[pc];
           } else if (uns && !v.sat) {
             const int64_t ai = ri.abase + (o.rec[q] & kCidxMask);
             o.east[q] = v.acomp[ai];
@@ -208,12 +212,13 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt(const float* __restrict__ A,
   // epilogue: lane holds rows 4*(lane/16)+r of each 16x16 block, column lane%16
   auto epilogue = [&](const Ops& o, floatx4 (&acc)[FM][FN]) {
     if (MODE == kBwdRelax || MODE == kBwdConc) {
-      float cst[FM][4];
+      float cst[FM][4], cer[FM][4];
 #pragma unroll
       for (int i = 0; i < FM; ++i) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           cst[i][r] = 0.f;
+          cer[i][r] = 0.f;
           const int row = m0 + wm * WM + i * 16 + rsub + r;
           const bool rok = row < M;
           const RowInfo& ri = o.eri[i][r];
@@ -226,11 +231,17 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt(const float* __restrict__ A,
             if (MODE == kBwdRelax) {
               if (ok) {
                 if (v.acomp && (o.rec[q] & kKindMask) == kUnstable) v.acomp[ri.abase + (o.rec[q] & kCidxMask)] = a;
-                e.out[(int64_t)row * e.ldo + col] = relax_value(
-                    bt, v, ri, o.rec[q], o.ech[q], relax_pick(o.rec[q], o.ecf[q], o.ebe[q]), a, o.ebias[j], &cst[i][r]);
+                const float lam = relax_value(bt, v, ri, o.rec[q], o.ech[q], relax_pick(o.rec[q], o.ecf[q], o.ebe[q]),
+                                              a, o.ebias[j], &cst[i][r]);
+                e.out[(int64_t)row * e.ldo + col] = lam;
+                cer[i][r] = fmaf(fabsf(lam), o.esw[q], cer[i][r]);
               }
             } else {
-              if (ok) cst[i][r] += conc_term(a, o.ech[q].x, o.ech[q].y);
+              if (ok) {
+                const float tm = conc_term(a, o.ech[q].x, o.ech[q].y);
+                cst[i][r] += tm;
+                cer[i][r] = fmaf(bt.sg, fabsf(tm), cer[i][r]);
+              }
               if (ok && v.xdense) v.xdense[(int64_t)row * v.ldx + col] = xstar(a > 0.f, a < 0.f, o.ech[q].x, o.ech[q].y);
               if (v.xpos) {
                 const uint64_t mp = __ballot(ok && a > 0.f);
@@ -245,6 +256,7 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt(const float* __restrict__ A,
             }
           }
           cst[i][r] = wave_sum16(cst[i][r]);
+          if (e.perr) cer[i][r] = wave_sum16(cer[i][r]);
         }
       }
       // combine the two column halves (wn = 0, 1) of each row, one slot per tile
@@ -252,12 +264,18 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt(const float* __restrict__ A,
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) red[wn][wm * WM + i * 16 + rsub + r] = cst[i][r];
+          for (int r = 0; r < 4; ++r) {
+            red[wn][wm * WM + i * 16 + rsub + r] = cst[i][r];
+            if (e.perr) rede[wn][wm * WM + i * 16 + rsub + r] = cer[i][r];
+          }
       }
       __syncthreads();
       for (int t = tid; t < BM; t += 256) {
         const int row = m0 + t;
-        if (row < M) e.part[(int64_t)(e.slot0 + tn) * M + row] = red[0][t] + red[1][t];
+        if (row < M) {
+          e.part[(int64_t)(e.slot0 + tn) * M + row] = red[0][t] + red[1][t];
+          if (e.perr) e.perr[(int64_t)(e.slot0 + tn) * M + row] = rede[0][t] + rede[1][t];
+        }
       }
     } else {
 #pragma unroll

@@ -156,6 +156,7 @@ struct TopArgs {
   int64_t cb_pstride;
   int n;       // width of layer L-1
   int conc;    // 1 when there is no ReLU layer: concretise directly
+  const float* err0;  // sound mode: rounding-error constant of the merged specification [P, m], or null
   Batch bt;
   Vars v;
   Epi e;
@@ -164,8 +165,10 @@ void launch_top(const TopArgs& a, hipStream_t s);
 // ub[row] = C_p W(L) z[row] + C_p b(L), z = zhat(L-1) of the network at x*
 void launch_top_dot(const TopArgs& a, const float* z, int ldz, float* ub, hipStream_t s);
 void launch_fill_i32(int* p, int v, int64_t n, hipStream_t s);
-void launch_finalize(const float* part, int n_slots, int n_used, int n_rows, float* lb, float* best, int first,
-                     hipStream_t s);
+// lb = sum of the used partial slots of each row; with perr (sound mode) minus
+// `scale` times the sum of the rounding-error partials, rounded outward
+void launch_finalize(const float* part, const float* perr, float scale, int n_slots, int n_used, int n_rows,
+                     float* lb, float* best, int first, hipStream_t s);
 void launch_adam(float* x, const float* g, float* m1, float* m2, int64_t n, float lr, float bc1, float bc2,
                  float lo, float hi, hipStream_t s);
 void launch_fill(float* p, float v, int64_t n, hipStream_t s);

@@ -96,7 +96,7 @@ __global__ __launch_bounds__(256) void top_k(TopArgs a) {
   const RowInfo ri = row_info(a.bt, row);
   const float* cw = a.CW + ri.p * a.cw_pstride + (int64_t)ri.k * a.ldcw;
   const uint32_t* st = a.bt.status + (int64_t)ri.b * a.bt.nd + a.e.layer_off;
-  float cst = 0.f;
+  float cst = 0.f, cer = 0.f;
   for (int j0 = lane; j0 < a.n; j0 += 64 * E) {
     float av[E], b1[E], b2[E];
     uint32_t rec[E];
@@ -122,28 +122,40 @@ __global__ __launch_bounds__(256) void top_k(TopArgs a) {
     if (a.conc) {
 #pragma unroll
       for (int e = 0; e < E; ++e)
-        if (j0 + 64 * e < a.n) cst += conc_term(av[e], b1[e], b2[e]);
+        if (j0 + 64 * e < a.n) {
+          const float tm = conc_term(av[e], b1[e], b2[e]);
+          cst += tm;
+          cer = fmaf(a.bt.sg, fabsf(tm), cer);
+        }
       continue;
     }
     float2 ch[E];
-    float al[E], be[E];
+    float al[E], be[E], sw[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const int64_t pc = (int64_t)ri.p * a.bt.nd + a.e.layer_off + j0 + 64 * e;
+      const int j = j0 + 64 * e;
+      const int64_t pc = (int64_t)ri.p * a.bt.nd + a.e.layer_off + j;
       ch[e] = (rec[e] & kKindMask) == kUnstable ? a.bt.chord[pc] : make_float2(0.f, 0.f);
       relax_vars(a.bt, a.v, ri, rec[e], pc, &al[e], &be[e]);
+      sw[e] = a.bt.sw && j < a.n ? a.bt.sw[pc] : 0.f;
     }
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int j = j0 + 64 * e;
       if (j >= a.n) continue;
       if (a.v.acomp && (rec[e] & kKindMask) == kUnstable) a.v.acomp[ri.abase + (rec[e] & kCidxMask)] = av[e];
-      a.e.out[(int64_t)row * a.e.ldo + j] =
+      const float lam =
           relax_value(a.bt, a.v, ri, rec[e], ch[e], relax_pick(rec[e], al[e], be[e]), av[e], b1[e], &cst);
+      a.e.out[(int64_t)row * a.e.ldo + j] = lam;
+      cer = fmaf(fabsf(lam), sw[e], cer);
     }
   }
   cst = wave_sum(cst);
   if (lane == 0) a.e.part[(int64_t)a.e.slot0 * a.bt.n_rows + row] = cst + a.Cb[ri.p * a.cb_pstride + ri.k];
+  if (a.e.perr) {
+    cer = wave_sum(cer);
+    if (lane == 0) a.e.perr[(int64_t)a.e.slot0 * a.bt.n_rows + row] = cer + (a.err0 ? a.err0[ri.p * a.bt.m + ri.k] : 0.f);
+  }
 }
 
 // ub = C_p W(L) zhat(L-1) + C_p b(L) for each row: the network's output at
@@ -170,27 +182,38 @@ __global__ __launch_bounds__(256) void fill_i32_k(int* p, int v, int64_t n) {
 // (deterministic).  Partials are slot-major [slot][row].  Wave g of a block
 // sums slots g, g+4, g+8, ... of 64 rows with 8 loads in flight per lane; the
 // four sums are then added in wave order.
-__global__ __launch_bounds__(256) void finalize_k(const float* __restrict__ part, int n_used, int n_rows, float* lb,
-                                                  float* best, int first) {
-  __shared__ float red[4][64];
+// Sound mode (perr set): the rounding-error partials are summed the same way,
+// scaled by `scale` for their own rounding, and the bound is lowered by them,
+// each step rounded outward.
+__device__ __forceinline__ float slot_sum(const float* __restrict__ part, int n_used, int n_rows, int r, int g) {
+  float s = 0.f;
+  int t = g;
+  for (; t + 28 < n_used; t += 32) {
+    float x[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) x[q] = part[(int64_t)(t + 4 * q) * n_rows + r];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) s += x[q];
+  }
+  for (; t < n_used; t += 4) s += part[(int64_t)t * n_rows + r];
+  return s;
+}
+
+__global__ __launch_bounds__(256) void finalize_k(const float* __restrict__ part, const float* __restrict__ perr,
+                                                  float scale, int n_used, int n_rows, float* lb, float* best,
+                                                  int first) {
+  __shared__ float red[4][64], rede[4][64];
   const int rl = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int r = blockIdx.x * 64 + rl;
-  float s = 0.f;
-  if (r < n_rows) {
-    int t = g;
-    for (; t + 28 < n_used; t += 32) {
-      float x[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) x[q] = part[(int64_t)(t + 4 * q) * n_rows + r];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) s += x[q];
-    }
-    for (; t < n_used; t += 4) s += part[(int64_t)t * n_rows + r];
-  }
-  red[g][rl] = s;
+  red[g][rl] = r < n_rows ? slot_sum(part, n_used, n_rows, r, g) : 0.f;
+  if (perr) rede[g][rl] = r < n_rows ? slot_sum(perr, n_used, n_rows, r, g) : 0.f;
   __syncthreads();
   if (g == 0 && r < n_rows) {
-    const float tot = ((red[0][rl] + red[1][rl]) + red[2][rl]) + red[3][rl];
+    float tot = ((red[0][rl] + red[1][rl]) + red[2][rl]) + red[3][rl];
+    if (perr) {
+      const float err = nextafterf((((rede[0][rl] + rede[1][rl]) + rede[2][rl]) + rede[3][rl]) * scale, INFINITY);
+      tot = nextafterf(tot - err, -INFINITY);
+    }
     if (lb) lb[r] = tot;
     if (best) best[r] = first ? tot : fmaxf(best[r], tot);
   }
@@ -254,10 +277,10 @@ void launch_fill_i32(int* p, int v, int64_t n, hipStream_t s) {
 }
 
 void launch_top(const TopArgs& a, hipStream_t s) { launch_k(top_k, nblk(a.bt.n_rows, 4), 256, 0, s, a); }
-void launch_finalize(const float* part, int n_slots, int n_used, int n_rows, float* lb, float* best, int first,
-                     hipStream_t s) {
+void launch_finalize(const float* part, const float* perr, float scale, int n_slots, int n_used, int n_rows,
+                     float* lb, float* best, int first, hipStream_t s) {
   (void)n_slots;
-  launch_k(finalize_k, nblk(n_rows, 64), 256, 0, s, part, n_used, n_rows, lb, best, first);
+  launch_k(finalize_k, nblk(n_rows, 64), 256, 0, s, part, perr, scale, n_used, n_rows, lb, best, first);
 }
 void launch_adam(float* x, const float* g, float* m1, float* m2, int64_t n, float lr, float bc1, float bc2, float lo,
                  float hi, hipStream_t s) {

@@ -19,6 +19,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-4
+SOUND_TOL = 1e-2  # sound mode: the rigorous float32 margin, relative to max(|bound|, 1)
 NAMES = list(cases.SMALL)
 
 
@@ -192,6 +193,74 @@ def test_upper_bound_parity(name, plan):
     s1 = sat.astype(bool)
     assert (lb[s1] <= ub[s1] + TOL * np.maximum(1.0, np.abs(ub[s1]))).all()
     say(name, "ub rows checked", n_ub, "sat checked", n_sat, "sat=1", int(s1.sum()), "of", sat.size)
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_sound_mode_is_below_the_exact_bound(name):
+    """Sound mode: each bound lies below the FP64 oracle's bound at the same
+    variables (no tolerance, on rows whose sign decisions are clear of float32
+    ties) and below the plain float32 bound; the optimiser's bounds too.  The
+    margin is a worst-case bound on float32 rounding (matrix products weighed
+    by sum |Lambda| |W| max|input|), so it is far wider than the actual
+    rounding error: it is checked against SOUND_TOL, not the parity bar."""
+    wl, orc, pb = problem(name)
+    alpha, beta = cases.random_vars(orc, seed=12)
+    lb_plain = pb.eval(dev(alpha), dev(beta)).cpu().numpy()
+    pb.set_sound(1)
+    lb = pb.eval(dev(alpha), dev(beta)).cpu().numpy()
+    ref = np.stack([orc.eval(b, alpha, beta) for b in range(orc.B)])
+    clear = np.stack([kink_free_rows(orc, b, alpha, beta) for b in range(orc.B)])
+    assert (lb[clear] <= ref[clear]).all()
+    assert (lb <= ref + 1e-7 * np.maximum(1.0, np.abs(ref))).all()
+    assert guarded_rel(lb, ref).max() <= SOUND_TOL
+    assert (lb <= lb_plain).all()
+    margin = (lb_plain - lb) / np.maximum(1.0, np.abs(lb_plain))
+    say(name, "plain excess", float(np.maximum(lb_plain - ref, 0).max()), "sound excess",
+        float(np.maximum(lb - ref, 0).max()), "relative margin max", float(margin.max()), "median", float(np.median(margin)))
+    # the optimiser reports the best sound bound of its iterates; the final
+    # iterate's bound is checked against the oracle at the returned variables
+    a = pb.alpha_init()
+    b = pb.zeros_beta()
+    best, last = pb.optimize(a, b, iters=5)
+    a_h, b_h = a.cpu().numpy(), b.cpu().numpy()
+    ref_last = np.stack([orc.eval(d, a_h, b_h) for d in range(orc.B)])
+    assert (last.cpu().numpy() <= ref_last + 1e-7 * np.maximum(1.0, np.abs(ref_last))).all()
+    pb.set_sound(0)
+    assert np.array_equal(pb.eval(dev(alpha), dev(beta)).cpu().numpy(), lb_plain)
+
+
+def test_sound_root_bounds_enclose_sampled_preactivations():
+    """The library's root bounds are sound: every pre-activation of the
+    float64 network at random points of the box lies inside them."""
+    from paper_2103_06624_amd import api, synth
+    for name in ["mlp_deep", "cnn_base"]:
+        wl = synth.make(name)
+        lo, up = api.root_bounds(wl.net.layers, wl.x_lo, wl.x_hi, sound=True)
+        lo_p, up_p = api.root_bounds(wl.net.layers, wl.x_lo, wl.x_hi)
+        assert (lo <= lo_p).all() and (up >= up_p).all()
+        from oracle import beta_crown as bc
+        net64 = bc.dense_net(wl.net.layers)
+        rng = np.random.default_rng(5)
+        for p in range(min(2, wl.x_lo.shape[0])):
+            xl, xh = wl.x_lo[p].astype(np.float64), wl.x_hi[p].astype(np.float64)
+            X = xl + (xh - xl) * rng.uniform(size=(256, xl.shape[0]))
+            X[:32] = np.where(rng.uniform(size=(32, xl.shape[0])) < 0.5, xl, xh)  # box corners
+            h = X
+            off = 0
+            for W, b in net64[:-1]:
+                z = h @ W.T + b
+                d = z.shape[1]
+                assert (z >= lo[p, off:off + d] - 0.0).all() and (z <= up[p, off:off + d] + 0.0).all(), name
+                h = np.maximum(z, 0.0)
+                off += d
+
+
+def test_sound_rejects_bad_values():
+    from paper_2103_06624_amd.binding import CvError
+    wl, orc, pb = problem("mlp_small")
+    for bad in [-1, 2]:
+        with pytest.raises(CvError):
+            pb.set_sound(bad)
 
 
 @pytest.mark.parametrize("name", ["mlp_small", "mlp_deep"])
