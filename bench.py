@@ -244,6 +244,27 @@ def main():
              "ms_per_call": round(ms_upper, 4), "rows_meeting_splits": int(sat.sum().item()),
              "rows_below_zero": int((ub < 0).sum().item())}
 
+    # ---- sound mode (rigorous float32 rounding margin) on the same batch:
+    # optimiser throughput and the margin against the plain float32 bound
+    pb.set_sound(1)
+    for _ in range(2):
+        alpha.copy_(a0)
+        beta.copy_(b0)
+        pb.optimize(alpha, beta, **opt)
+    torch.cuda.synchronize()
+    n_sound = max(3, args.steps // 4)
+    t0 = time.perf_counter()
+    for _ in range(n_sound):
+        pb.optimize(alpha, beta, **opt)
+    torch.cuda.synchronize()
+    ms_sound = (time.perf_counter() - t0) / n_sound * 1e3
+    lb_s = pb.eval(a0, b0)
+    pb.set_sound(0)
+    lb_p = pb.eval(a0, b0)
+    rel_margin = ((lb_p - lb_s) / lb_p.abs().clamp(min=1.0)).max().item()
+    sound = {"value": round(B / (ms_sound / 1e3), 1), "unit": "subdomain bounds/s", "ms_per_step": round(ms_sound, 4),
+             "max_rel_margin": rel_margin, "min_margin": (lb_p - lb_s).min().item()}
+
     # ---- per-kernel durations with HIP events on the launch stream
     log("[bench] per-kernel event timing")
     stats = pb.profile(a0, b0, reps=5)
@@ -316,6 +337,7 @@ def main():
         "plain_eval": {"value": round(B / (ms_eval / 1e3), 1), "unit": "subdomain bounds/s",
                        "ms_per_eval": round(ms_eval, 4)},
         "upper_bound": upper,
+        "sound_mode": sound,
         "roofline": roof,
         "mfma_kernels_tflops": round(gemm_fl / (gemm_ms * 1e-3) / 1e12, 3) if gemm_ms else None,
         "mfma_kernels_time_share": round(gemm_ms / all_ms, 4) if all_ms else None,
