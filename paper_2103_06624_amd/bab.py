@@ -1,0 +1,129 @@
+"""Batched branch and bound over the library's bound (App. B.1, Alg. 1).
+
+One property at a time.  The objective of a subdomain is min_k (C f(x))_k over
+its specification rows: the property holds when every row is >= 0.  The pool
+of unverified subdomains lives on the host (a subdomain is its list of split
+decisions); every round takes the `batch` subdomains with the lowest lower
+bounds (batch_pick_out), splits each on its next neuron into a z >= 0 and a
+z < 0 child (batch_split) and bounds all children in one batch on the GPU:
+cv_bound_optimize from CROWN's default alpha and beta = 0, then cv_bound_upper
+at the final iterate for the network at the box minimiser x* (the upper
+bound).  Children whose lower bound is >= 0 are dropped (Domain_Filter), the
+rest go back to the pool.  The global lower bound is the pool's smallest, the
+global upper bound the smallest network value seen.  The loop stops when the
+property is proved (empty pool), a counter-example is found (upper bound
+< 0), no pooled subdomain can be split further, the pool reaches `max_pool`,
+or after `max_rounds` rounds.  Intermediate bounds stay those of the root; a
+split neuron's own bounds become l >= 0 or u <= 0 (App. B.1 remark).
+
+Branching rule (the paper cites BaBSR and FSB without defining them, so the
+rule is this project's own): root-unstable neurons in decreasing order of the
+intercept -l u / (u - l) of their upper chord, ties by layer then index; a
+subdomain splits the first neuron of that order it has not split yet.
+
+sound=True runs the bounds in sound mode (cv_bound_set_sound): every lower
+bound is then rigorous in float32, so a 'verified' verdict is a proof.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+from .api import BoundProblem
+
+
+def branch_order(lo, up, relu_dims):
+    """[(layer (1-based), neuron)] of the root-unstable neurons of one property,
+    largest chord intercept first.  lo, up: [sum d_i] (layer-major)."""
+    lo = np.asarray(lo, np.float64)
+    up = np.asarray(up, np.float64)
+    items = []
+    off = 0
+    for i, d in enumerate(relu_dims):
+        l, u = lo[off:off + d], up[off:off + d]
+        for j in np.nonzero((l < 0) & (u > 0))[0]:
+            items.append((l[j] * u[j] / (u[j] - l[j]), i + 1, int(j)))
+        off += d
+    items.sort()
+    return [(i, j) for _, i, j in items]
+
+
+def bab(layers, x_lo, x_hi, C, lo, up, batch=1024, max_rounds=64, max_pool=1 << 20, iters=20, lr_alpha=0.01,
+        lr_beta=0.05, decay=0.98, sound=False):
+    """x_lo, x_hi [d0]; C [m, dL]; lo, up [sum d_i] root bounds of this property.
+    Returns a dict: verdict ('verified' | 'falsified' | 'unknown'), lb (the
+    smallest lower bound over the leaves of the search tree), ub, rounds,
+    domains (subdomains bounded, the root included), seconds."""
+    t_start = time.perf_counter()
+    x_lo = np.asarray(x_lo, np.float32)[None]
+    x_hi = np.asarray(x_hi, np.float32)[None]
+    C = np.asarray(C, np.float32)[None]
+    lo = np.asarray(lo, np.float32)[None]
+    up = np.asarray(up, np.float32)[None]
+    relu_dims = [ly.d_out for ly in layers[:-1]]
+    order = branch_order(lo[0], up[0], relu_dims)
+    opt = dict(iters=iters, lr_alpha=lr_alpha, lr_beta=lr_beta, decay=decay)
+
+    def solve(domains):
+        """(lower, upper) bound per subdomain, each a tuple of (layer, neuron, side)."""
+        ptr = np.zeros(len(domains) + 1, np.int64)
+        lay, neu, side = [], [], []
+        for b, dom in enumerate(domains):
+            for (i, j, s) in dom:
+                lay.append(i)
+                neu.append(j)
+                side.append(s)
+            ptr[b + 1] = len(lay)
+        pb = BoundProblem(layers, x_lo, x_hi, C, lo, up, np.zeros(len(domains), np.int32), ptr, lay, neu, side)
+        try:
+            if sound:
+                pb.set_sound(1)
+            a = pb.alpha_init()
+            bt = pb.zeros_beta()
+            best, _ = pb.optimize(a, bt, **opt)
+            _, ub, _ = pb.upper(a, bt, with_lb=False)
+            return best.min(dim=1).values.cpu().numpy(), ub.min(dim=1).values.cpu().numpy()
+        finally:
+            pb.close()
+
+    def next_neuron(dom):
+        done = {(i, j) for (i, j, _) in dom}
+        for i, j in order:
+            if (i, j) not in done:
+                return i, j
+        return None
+
+    lb0, ub0 = solve([()])
+    pool = [(float(lb0[0]), 0, ())] if lb0[0] < 0 else []
+    f_lb = float(lb0[0]) if pool else np.inf
+    f_ub = float(ub0[0])
+    done_lb = np.inf if pool else float(lb0[0])
+    rounds, domains, seq = 0, 1, 1
+    while f_lb < 0 <= f_ub and pool and len(pool) < max_pool and rounds < max_rounds:
+        pool.sort(key=lambda t: (t[0], t[1]))
+        picked, rest = [], []
+        for t in pool:
+            (picked if len(picked) < batch and next_neuron(t[2]) is not None else rest).append(t)
+        if not picked:
+            break
+        pool = rest
+        children = []
+        for _, _, dom in picked:
+            i, j = next_neuron(dom)
+            children.append(dom + ((i, j, 1),))
+            children.append(dom + ((i, j, -1),))
+        lbs, ubs = solve(children)
+        domains += len(children)
+        f_ub = min(f_ub, float(ubs.min()))
+        for dom, lb_c in zip(children, lbs):
+            if lb_c < 0:
+                pool.append((float(lb_c), seq, dom))
+            else:
+                done_lb = min(done_lb, float(lb_c))
+            seq += 1
+        f_lb = min(t[0] for t in pool) if pool else np.inf
+        rounds += 1
+    verdict = "falsified" if f_ub < 0 else ("verified" if f_lb >= 0 else "unknown")
+    return {"verdict": verdict, "lb": min(f_lb, done_lb), "ub": f_ub, "rounds": rounds, "domains": domains,
+            "seconds": time.perf_counter() - t_start}

@@ -74,3 +74,15 @@ def test_root_already_verified_or_falsified():
     assert r["verdict"] == "verified" and r["rounds"] == 0 and r["domains"] == 1
     r = ob.bab(shifted(net, fstar + 100.0), x_lo, x_hi, C, lo, up)
     assert r["verdict"] == "falsified" and r["rounds"] == 0
+
+
+def test_library_branch_order_matches_oracle():
+    """The library driver's host-side branching order (layers 1-based) is the oracle's."""
+    from oracle import bab as ob
+    from paper_2103_06624_amd import bab as gb
+    rng = np.random.default_rng(1)
+    lo = [rng.uniform(-2, 1, size=7), rng.uniform(-2, 1, size=5)]
+    up = [l + rng.uniform(0.1, 3, size=l.shape) for l in lo]
+    o = ob.branch_order(lo, up)
+    g = gb.branch_order(np.concatenate(lo), np.concatenate(up), [7, 5])
+    assert g == [(i + 1, j) for i, j in o]
