@@ -95,6 +95,38 @@ def library_gemm_context(wl, rows):
     return out
 
 
+def bab_context(wl, lo, up, args):
+    """Throughput of the library's branch and bound on one property of the
+    workload (context for the paper's branches/s figures)."""
+    import dataclasses
+
+    import numpy as np
+    import torch
+
+    from paper_2103_06624_amd import bab as gb
+    from paper_2103_06624_amd import synth
+    from paper_2103_06624_amd.api import BoundProblem
+
+    layers = list(wl.net.layers)
+    p = 0
+    one = BoundProblem(layers, wl.x_lo[p:p + 1], wl.x_hi[p:p + 1], wl.C[p:p + 1], lo[p:p + 1], up[p:p + 1],
+                       np.zeros(1, np.int32), np.zeros(2, np.int64), [], [], [])
+    lb0, ub0, _ = one.upper(one.alpha_init(), one.zeros_beta())
+    t = ((lb0 + ub0) / 2).cpu().numpy().reshape(-1)
+    one.close()
+    last = layers[-1]
+    W = np.vstack([last.weight, np.zeros((1, last.weight.shape[1]), np.float32)])
+    b = np.concatenate([last.bias, np.ones(1, np.float32)])
+    layers[-1] = dataclasses.replace(last, weight=W, bias=b, out_shape=(W.shape[0], 1, 1))
+    C = np.hstack([wl.C[p], -t[:, None]]).astype(np.float32)
+    torch.cuda.synchronize()
+    r = gb.bab(layers, wl.x_lo[p], wl.x_hi[p], C, lo[p], up[p], batch=args.bab_batch, max_rounds=args.bab_rounds,
+               iters=args.iters, lr_alpha=args.lr_alpha, lr_beta=args.lr_beta, decay=args.decay)
+    return {"domains_per_s": round(r["domains"] / r["seconds"], 1), "domains": r["domains"], "rounds": r["rounds"],
+            "batch": args.bab_batch, "seconds": round(r["seconds"], 3), "verdict": r["verdict"],
+            "lb": r["lb"], "ub": r["ub"]}
+
+
 def cpu_baseline(name, gpu_best, gpu_splits, gpu_lo, gpu_up, seconds, iters, lr_a, lr_b, decay):
     """The FP64 oracle timed on this host on a bounded sample of the same
     workload: per-subdomain 20-iteration optimisation (the same unit as the
@@ -161,6 +193,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--bab-rounds", type=int, default=12, help="branch-and-bound rounds timed as context")
+    ap.add_argument("--bab-batch", type=int, default=1024, help="subdomains split per branch-and-bound round")
     ap.add_argument("--plan", default=None, help="dense-chain plan bwd,fwd (1,1 fused chains, 0,0 per-layer kernels); overrides the autotuner")
     ap.add_argument("--parts", type=int, default=0,
                     help="concurrent sub-batches of the optimiser (0: the library's default)")
@@ -265,6 +299,12 @@ def main():
     sound = {"value": round(B / (ms_sound / 1e3), 1), "unit": "subdomain bounds/s", "ms_per_step": round(ms_sound, 4),
              "max_rel_margin": rel_margin, "min_margin": (lb_p - lb_s).min().item()}
 
+    # ---- branch and bound (Alg. 1) on property 0 of the workload, each row's
+    # objective offset to the middle of its root [lower, upper] bound (an
+    # extra constant output carries the offsets), so that the search has to
+    # branch; a fixed number of rounds of `batch` splits each
+    bab_res = bab_context(wl, lo, up, args)
+
     # ---- per-kernel durations with HIP events on the launch stream
     log("[bench] per-kernel event timing")
     stats = pb.profile(a0, b0, reps=5)
@@ -338,6 +378,7 @@ def main():
                        "ms_per_eval": round(ms_eval, 4)},
         "upper_bound": upper,
         "sound_mode": sound,
+        "branch_and_bound": bab_res,
         "roofline": roof,
         "mfma_kernels_tflops": round(gemm_fl / (gemm_ms * 1e-3) / 1e12, 3) if gemm_ms else None,
         "mfma_kernels_time_share": round(gemm_ms / all_ms, 4) if all_ms else None,
