@@ -161,6 +161,9 @@ struct cv_bound {
   float* part = nullptr;
   // sound mode: per-neuron weights of the rounding-error bound, the bound's
   // per-row partials and its constant for the merged specification
+  // the optimiser's fused top layer: where the last adjoint GEMM left
+  // Lambda(L-1) (act buffer) and how many partial slots it filled
+  int ftop_buf = 0, ftop_slots = 1;
   bool sound = false;
   float* sw = nullptr;    // [P, nd]
   float* perr = nullptr;  // [n_slots, R]
@@ -550,7 +553,10 @@ int build(cv_bound* h, const cv_layer* layers, int n_layers, int P, const float*
   int maxd = 4;
   for (int i = 1; i < n_layers; ++i) maxd = std::max(maxd, h->dims[i]);
   h->ldact = r4(maxd);
-  h->n_slots = 1;
+  // the top layer takes one slot, or one per 32-column tile when it is
+  // relaxed inside the optimiser's last adjoint GEMM
+  h->n_slots = n_layers >= 2 && layers[n_layers - 2].type == CV_LAYER_DENSE ? std::max(1, (h->dims[n_layers - 1] + 31) / 32)
+                                                                           : 1;
   for (int i = n_layers - 1; i >= 1; --i) {  // back-substitution through layer i
     const DevLayer& ly = h->layers[i - 1];
     h->n_slots += ly.type == CV_LAYER_DENSE ? (h->dims[i - 1] + 31) / 32 : 1;
@@ -806,8 +812,10 @@ double chain_flops(const cv_bound* h) {
 }
 
 // Back-substitution of every layer plus concretisation; lb / best per row.
+// skip_top: the top layer was relaxed by the previous adjoint pass (fused
+// into its last GEMM): start from its Lambda(L-1) and partial slots.
 int enqueue_bwd(cv_bound* h, const float* alpha, const float* beta, bool grad, float* lb, float* best, int first,
-                hipStream_t s) {
+                hipStream_t s, bool skip_top = false) {
   const int L = h->L;
   Vars v{};
   v.alpha = alpha;
@@ -822,7 +830,10 @@ int enqueue_bwd(cv_bound* h, const float* alpha, const float* beta, bool grad, f
   Profiler* pf = h->prof;
   if (h->R == 0) return CV_OK;
   int cur = 0, slot = 1, i_next = L - 1;
-  if (h->chain_b && !h->sound) {
+  if (skip_top) {
+    cur = h->ftop_buf;
+    slot = h->ftop_slots;
+  } else if (h->chain_b && !h->sound) {
     const int lo = h->chain_lo;
     ChainArgs ca{};
     ca.nl = L - lo;
@@ -937,8 +948,11 @@ int enqueue_bwd(cv_bound* h, const float* alpha, const float* beta, bool grad, f
 // Adjoint forward sweep: zbar(i) = W(i) zhat(i-1) + b(i) from zhat(0) = x*,
 // gradients of alpha and beta in the epilogues (or, with `ad`, the projected
 // Adam step applied in place).
+// fuse_top (optimiser, with Adam): the last adjoint GEMM also relaxes the next
+// iteration's top layer (Epi::top_out); the next back-substitution then
+// starts from its output (enqueue_bwd with skip_top).
 int enqueue_fwd(cv_bound* h, const float* alpha, const float* beta, float* ga, float* gb, const AdamStep* ad,
-                hipStream_t s) {
+                hipStream_t s, bool fuse_top = false) {
   const int L = h->L;
   Vars v{};
   v.alpha = alpha;
@@ -984,10 +998,21 @@ int enqueue_fwd(cv_bound* h, const float* alpha, const float* beta, float* ga, f
                       (double)h->B * N * 2.0 + h->unst_rows_per_layer[i - 1] * 4.0 * 3;
     if (ly.type == CV_LAYER_DENSE) {
       const int c = h->cfg[L + i - 1] >= 0 ? h->cfg[L + i - 1] : 0;
+      if (last && fuse_top) {
+        h->ftop_buf = i & 1;  // not the input buffer act[(i - 1) & 1]
+        h->ftop_slots = (N + kGemmCfgs[c].bn - 1) / kGemmCfgs[c].bn;
+        e.top_out = h->act[h->ftop_buf];
+        e.cw = h->CW;
+        e.cw_pstride = h->cw_pstride;
+        e.ldcw = h->ldcw;
+        e.cb = h->Cb;
+        e.cb_pstride = h->cb_pstride;
+        e.slot0 = 0;
+      }
       GemmArgs g{in, lda, ly.W, ly.ld_in, h->R, N, K, last, h->bt, v, e};
       if (pf) pf->begin(std::string(i == 1 ? "gemm_fwd_x_" : "gemm_fwd_") + cfg_name(c), 2.0 * rows * N * K,
                         io + (double)N * K * 4.0);
-      launch_gemm(c, mode, g, s);
+      launch_gemm(c, e.top_out ? kFwdTop : mode, g, s);
       if (pf) pf->end();
     } else {
       ConvArgs a{in, h->ldact, ly.W, ly.g, h->R, last, ly.uniform, h->bt, v, e};
@@ -1047,8 +1072,12 @@ int enqueue_opt(cv_bound* h, int iters, float lr_a, float lr_b, float decay, flo
     ap.vb = h->adam + 2 * h->n_alpha + nb;
   }
   int rc;
+  // the top layer's relaxation rides on the last adjoint GEMM from the
+  // second iteration on (per-layer kernels, dense top layer, no sound margin)
+  const int L = h->L;
+  const bool fuse = L >= 2 && h->layers[L - 2].type == CV_LAYER_DENSE && !h->chain_b && !h->chain_f && !h->sound;
   for (int t = 0; t < iters; ++t) {
-    if ((rc = enqueue_bwd(h, alpha, beta, true, nullptr, lb_best, t == 0, s))) return rc;
+    if ((rc = enqueue_bwd(h, alpha, beta, true, nullptr, lb_best, t == 0, s, fuse && t > 0))) return rc;
     const int tt = step0 + t;
     AdamStep ad;
     ad.bc1 = (float)(1.0 - std::pow(0.9, tt + 1));
@@ -1060,9 +1089,9 @@ int enqueue_opt(cv_bound* h, int iters, float lr_a, float lr_b, float decay, flo
     ad.va = ap.va;
     ad.mb = ap.mb;
     ad.vb = ap.vb;
-    if ((rc = enqueue_fwd(h, alpha, beta, nullptr, nullptr, &ad, s))) return rc;
+    if ((rc = enqueue_fwd(h, alpha, beta, nullptr, nullptr, &ad, s, fuse))) return rc;
   }
-  if ((rc = enqueue_bwd(h, alpha, beta, false, lb_last, lb_best, iters == 0, s))) return rc;
+  if ((rc = enqueue_bwd(h, alpha, beta, false, lb_last, lb_best, iters == 0, s, fuse && iters > 0))) return rc;
   HIPCHK(hipGetLastError());
   return CV_OK;
 }

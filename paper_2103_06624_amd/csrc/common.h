@@ -94,8 +94,8 @@ __device__ __forceinline__ float true_relu(uint32_t rec, float zb, int* sat_row)
 
 // adam_step takes the entry's current value and moments as arguments (read
 // ahead by the caller); adam_apply reads them itself.
-__device__ __forceinline__ void adam_step(float* x, float* m1, float* m2, int64_t i, float g, float lr, float bc1,
-                                          float bc2, float lo, float hi, float xv, float m1v, float m2v) {
+__device__ __forceinline__ float adam_step(float* x, float* m1, float* m2, int64_t i, float g, float lr, float bc1,
+                                           float bc2, float lo, float hi, float xv, float m1v, float m2v) {
   // fmaf keeps the products with the moments next to g: a product of a moment
   // alone would be hoisted to where the moment is read ahead, stalling there
   const float a = fmaf(0.9f, m1v, 0.1f * g);
@@ -103,12 +103,14 @@ __device__ __forceinline__ void adam_step(float* x, float* m1, float* m2, int64_
   m1[i] = a;
   m2[i] = b;
   const float step = lr * (a / bc1) / (sqrtf(b / bc2) + 1e-8f);
-  x[i] = fminf(fmaxf(xv + step, lo), hi);
+  const float xn = fminf(fmaxf(xv + step, lo), hi);
+  x[i] = xn;
+  return xn;
 }
 
-__device__ __forceinline__ void adam_apply(float* x, float* m1, float* m2, int64_t i, float g, float lr, float bc1,
-                                           float bc2, float lo, float hi) {
-  adam_step(x, m1, m2, i, g, lr, bc1, bc2, lo, hi, x[i], m1[i], m2[i]);
+__device__ __forceinline__ float adam_apply(float* x, float* m1, float* m2, int64_t i, float g, float lr, float bc1,
+                                            float bc2, float lo, float hi) {
+  return adam_step(x, m1, m2, i, g, lr, bc1, bc2, lo, hi, x[i], m1[i], m2[i]);
 }
 
 // Per-launch epilogue parameters (one layer).
@@ -122,6 +124,17 @@ struct Epi {
   float* perr;         // [n_slots, n_rows] partial rounding-error bounds (sound mode), or null
   int n_slots;
   int slot0;           // first slot of this launch
+  // The adjoint's top ReLU layer inside the optimiser (null top_out
+  // otherwise): after the Adam step the epilogue also relaxes the next
+  // iteration's A(L-1) = C_p W(L) with the new variables -- the top layer of
+  // the next back-substitution -- writing Lambda(L-1) to top_out and its
+  // constant into slots slot0 + column tile (tile 0 adds C_p b(L)).
+  float* top_out;
+  const float* cw;     // [P, m, ldcw] C_p W(L)
+  int64_t cw_pstride;
+  int ldcw;
+  const float* cb;     // [P, m] C_p b(L)
+  int64_t cb_pstride;
 };
 
 struct RowInfo {
@@ -216,10 +229,13 @@ __device__ __forceinline__ float xstar(bool pos, bool neg, float xl, float xu) {
 // zhat(i)_j = D zbar + lowerb.  a_st is the stored A(i)_j and al the alpha of
 // an unstable neuron; be is the beta of a split neuron.
 // With mom_ahead, mom holds the Adam moments of an unstable neuron's alpha,
-// read ahead by the caller together with al (its current value).
+// read ahead by the caller together with al (its current value).  var_new,
+// when set, receives the neuron's variable after this step (alpha of an
+// unstable neuron, beta of a split one).
 __device__ __forceinline__ float relax_fwd_value(const Batch& bt, const Vars& v, const RowInfo& ri, uint32_t rec,
                                                  float2 ch, float a_st, float al, int64_t pc, float zb,
-                                                 bool mom_ahead = false, float2 mom = float2{0.f, 0.f}) {
+                                                 bool mom_ahead = false, float2 mom = float2{0.f, 0.f},
+                                                 float* var_new = nullptr) {
   const uint32_t kind = rec & kKindMask;
   if (kind == kActive) return zb;
   if (kind == kInactive) return 0.f;
@@ -233,9 +249,11 @@ __device__ __forceinline__ float relax_fwd_value(const Batch& bt, const Vars& v,
       g = 0.f;
       zh = fmaf(ch.x, zb, ch.y);
     }
-    if (v.adam && mom_ahead) adam_step(v.alpha_w, v.ma, v.va, ai, g, v.lr_a, v.bc1, v.bc2, 0.f, 1.f, al, mom.x, mom.y);
-    else if (v.adam) adam_apply(v.alpha_w, v.ma, v.va, ai, g, v.lr_a, v.bc1, v.bc2, 0.f, 1.f);
+    float an = al;
+    if (v.adam && mom_ahead) an = adam_step(v.alpha_w, v.ma, v.va, ai, g, v.lr_a, v.bc1, v.bc2, 0.f, 1.f, al, mom.x, mom.y);
+    else if (v.adam) an = adam_apply(v.alpha_w, v.ma, v.va, ai, g, v.lr_a, v.bc1, v.bc2, 0.f, 1.f);
     else v.galpha[ai] = g;
+    if (var_new) *var_new = an;
     return zh;
   }
   const bool pos = (rec & kSidePos) != 0;
@@ -244,8 +262,9 @@ __device__ __forceinline__ float relax_fwd_value(const Batch& bt, const Vars& v,
   const int64_t ai = ri.abase + bt.cidx[pc];
   const float gb = pos ? -zb : zb;
   if (v.adam) {
-    adam_apply(v.beta_w, v.mb, v.vb, bi, gb, v.lr_b, v.bc1, v.bc2, 0.f, INFINITY);
+    const float bn = adam_apply(v.beta_w, v.mb, v.vb, bi, gb, v.lr_b, v.bc1, v.bc2, 0.f, INFINITY);
     adam_apply(v.alpha_w, v.ma, v.va, ai, 0.f, v.lr_a, v.bc1, v.bc2, 0.f, 1.f);
+    if (var_new) *var_new = bn;
   } else {
     v.gbeta[bi] = gb;
     v.galpha[ai] = 0.f;

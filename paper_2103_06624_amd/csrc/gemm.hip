@@ -62,7 +62,7 @@ struct TileOps {
 // DEPTH >= 3 holds all of K in registers (K <= DEPTH * BK): one load latency
 // per tile instead of one per slab.
 // Modes: kBwdRelax, kBwdConc, kFwd (the adjoint's first layer reads x* as a
-// dense operand).
+// dense operand), kFwdTop (kFwd plus the next top-layer relaxation).
 template <int BM, int BN, int BK, int MODE, int OCC, int DEPTH>
 __global__ __launch_bounds__(256, OCC) void gemm_nt(const float* __restrict__ A, int lda, const float* __restrict__ Bt,
                                                int ldb, int M, int N, int K, int last, Batch bt, Vars v, Epi e) {
@@ -206,6 +206,8 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt(const float* __restrict__ A,
             o.ecf[q] = v.alpha ? v.alpha[ai] : bt.adef[pc];
             if (v.adam) o.emo[q] = make_float2(v.ma[ai], v.va[ai]);
           }
+          // the fused top layer: ebe holds C_p W(L) at this neuron
+          if (MODE == kFwdTop) o.ebe[q] = e.cw[ri.p * e.cw_pstride + (int64_t)ri.k * e.ldcw + col];
         }
   };
 
@@ -275,6 +277,54 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt(const float* __restrict__ A,
         if (row < M) {
           e.part[(int64_t)(e.slot0 + tn) * M + row] = red[0][t] + red[1][t];
           if (e.perr) e.perr[(int64_t)(e.slot0 + tn) * M + row] = rede[0][t] + rede[1][t];
+        }
+      }
+    } else if (MODE == kFwdTop) {
+      // last adjoint layer inside the optimiser: Adam step, then the next
+      // iteration's top-layer relaxation with the new variables
+      float cst[FM][4];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          cst[i][r] = 0.f;
+          const int row = m0 + wm * WM + i * 16 + rsub + r;
+          const bool rok = row < M;
+          const RowInfo& ri = o.eri[i][r];
+#pragma unroll
+          for (int j = 0; j < FN; ++j) {
+            const int col = n0 + wn * WN + j * 16 + csub;
+            const int q = (i * 4 + r) * FN + j;
+            if (rok && col < N) {
+              const float zb = acc[i][j][r] + o.ebias[j];
+              const int64_t pc = (int64_t)ri.p * bt.nd + e.layer_off + col;
+              float vn = 0.f;
+              relax_fwd_value(bt, v, ri, o.rec[q], o.ech[q], o.east[q], o.ecf[q], pc, zb, true, o.emo[q], &vn);
+              const float a = o.ebe[q];
+              if (v.acomp && (o.rec[q] & kKindMask) == kUnstable) v.acomp[ri.abase + (o.rec[q] & kCidxMask)] = a;
+              e.top_out[(int64_t)row * e.ldo + col] = relax_value(bt, v, ri, o.rec[q], o.ech[q], vn, a, o.ebias[j],
+                                                                  &cst[i][r]);
+            }
+          }
+          cst[i][r] = wave_sum16(cst[i][r]);
+        }
+      }
+      if (csub == 0) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) red[wn][wm * WM + i * 16 + rsub + r] = cst[i][r];
+      }
+      __syncthreads();
+      for (int t = tid; t < BM; t += 256) {
+        const int row = m0 + t;
+        if (row < M) {
+          float c = red[0][t] + red[1][t];
+          if (tn == 0) {
+            const RowInfo ri = row_info(bt, row);
+            c += e.cb[ri.p * e.cb_pstride + ri.k];
+          }
+          e.part[(int64_t)(e.slot0 + tn) * M + row] = c;
         }
       }
     } else {
@@ -379,6 +429,10 @@ void launch_cfg(int mode, const GemmArgs& g, hipStream_t s) {
       break;
     case kBwdConc:
       launch_k(gemm_nt<BM, BN, BK, kBwdConc, OCC, DEPTH>, grid, block, 0, s, g.A, g.lda, g.Bt, g.ldb, g.M, g.N, g.K,
+               g.last, g.bt, g.v, g.e);
+      break;
+    case kFwdTop:
+      launch_k(gemm_nt<BM, BN, BK, kFwdTop, OCC, DEPTH>, grid, block, 0, s, g.A, g.lda, g.Bt, g.ldb, g.M, g.N, g.K,
                g.last, g.bt, g.v, g.e);
       break;
     default:
