@@ -272,6 +272,30 @@ def root_bounds(net64, x_lo, x_hi):
     return lo, up
 
 
+def root_bounds_opt(net64, x_lo, x_hi, cfg=None):
+    """Intermediate bounds with their own optimised variables (Sec. 3.3: each
+    intermediate neuron's bound l(i)_j = max over its own alpha' of the bound
+    of z(i)_j, u(i)_j likewise for -z(i)_j), at the root (no splits, so beta'
+    plays no part).  Layer by layer as `root_bounds`: the specification
+    [I; -I] on layer i gives each of the 2 d_i bounds its own rows, hence its
+    own alpha' for every unstable neuron below (the unshared form), optimised
+    by `optimize` from CROWN's default; later layers use the optimised bounds
+    of earlier ones.  The reported bound is the best iterate."""
+    cfg = cfg or AdamConfig()
+    L = len(net64)
+    lo, up = [], []
+    for i in range(1, L):
+        d = net64[i - 1][0].shape[0]
+        C = np.vstack([np.eye(d), -np.eye(d)])
+        split = [np.zeros(net64[k][0].shape[0], np.int8) for k in range(i - 1)]
+        alpha = [np.tile(default_alpha(lo[k], up[k]), (2 * d, 1)) for k in range(i - 1)]
+        beta = [np.zeros((2 * d, lo[k].shape[0])) for k in range(i - 1)]
+        best, *_ = optimize(net64[:i], x_lo, x_hi, C, lo, up, split, alpha, beta, cfg)
+        lo.append(best[:d].copy())
+        up.append(-best[d:].copy())
+    return lo, up
+
+
 def outward_f32(lo, up):
     """Round bounds to float32 outward (l down, u up) so they stay sound."""
     lo32 = np.asarray(lo, dtype=np.float32)

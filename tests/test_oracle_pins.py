@@ -394,3 +394,33 @@ def test_upper_bound_brackets_the_minimum(seed):
         # grid's resolution; here checked one-sided: ub is never below a sound lower bound of the minimum
         assert np.all(g_free <= gm + 1e-9)
         assert np.all(g[sat] <= ub[sat] + 1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Optimised intermediate bounds (Sec. 3.3, each bound with its own alpha')
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_optimised_root_bounds_tighter_sound_and_below_the_lp(seed):
+    """At least as tight as CROWN's (the ascent keeps its best iterate, which
+    starts at CROWN's default), enclosing the pre-activations on a dense grid
+    of the box, equal to the exact interval bound on the first layer, and
+    never beyond the LP relaxation of the same neuron (weak duality)."""
+    rng, net, _, _, x_lo, x_hi, lo, up, C = tiny_case(seed + 600, widths=(2, 6, 5, 4, 2))
+    lo_o, up_o = bc.root_bounds_opt(net, x_lo, x_hi, bc.AdamConfig(iters=40, lr_alpha=0.1))
+    assert np.array_equal(lo_o[0], lo[0]) and np.array_equal(up_o[0], up[0])
+    for l, u, lc, uc in zip(lo_o, up_o, lo, up):
+        assert (l >= lc - 1e-12).all() and (u <= uc + 1e-12).all()
+    assert any((l > lc + 1e-6).any() or (u < uc - 1e-6).any() for l, u, lc, uc in zip(lo_o, up_o, lo, up))
+    zs, _ = pinlib.forward_all(net, pinlib.grid(x_lo, x_hi, 301))
+    for z, l, u in zip(zs, lo_o, up_o):
+        assert (z >= l - 1e-9).all() and (z <= u + 1e-9).all()
+    # layer 2 neurons against the LP with the optimised layer-1 bounds
+    sub = net[:2]
+    none = [np.zeros(lo_o[0].shape[0], np.int8)]
+    for j in range(lo_o[1].shape[0]):
+        for sgn, val in ((1.0, lo_o[1][j]), (-1.0, -up_o[1][j])):
+            c = np.zeros(lo_o[1].shape[0])
+            c[j] = sgn
+            p_lp, res, _ = pinlib.lp_verify_split(sub, x_lo, x_hi, c, lo_o[:1], up_o[:1], none)
+            assert res.status == 0 and val <= p_lp + 1e-8
