@@ -90,6 +90,21 @@ int cv_bound_root_bounds_sound(const cv_layer *layers, int32_t n_layers, int32_t
                                const float *x_lo, const float *x_hi,
                                float *l_out, float *u_out, void *stream);
 
+/* Optimised intermediate bounds (Sec. 3.3): as cv_bound_root_bounds, but
+ * each of the 2 d_i bounds of layer i is maximised over its own alpha' (one
+ * per unstable neuron of the layers below: the unshared form of Sec. 3.3;
+ * no splits at the root, so no beta') by `iters` projected-Adam steps from
+ * CROWN's default (learning rate lr_alpha, decay lr_decay per step), keeping
+ * the best iterate; each layer is built on the optimised bounds of the layers
+ * below.  Each bound is therefore at least as tight as CROWN's.  sound = 1
+ * applies the rigorous float32 margin (cv_bound_set_sound) to every bound.
+ * iters = 0 is cv_bound_root_bounds (sound = 0) or _sound (sound = 1).
+ * CV_EINVAL on iters < 0, sound outside 0/1 or non-finite rates. */
+int cv_bound_root_bounds_opt(const cv_layer *layers, int32_t n_layers, int32_t n_props,
+                             const float *x_lo, const float *x_hi, int32_t iters,
+                             float lr_alpha, float lr_decay, int32_t sound,
+                             float *l_out, float *u_out, void *stream);
+
 /* Build a handle for one batch of subdomains (Theorem 3.1 inputs).
  *   layers[n_layers]: the network; the last layer must be dense.
  *   x_lo, x_hi: host [n_props][d0] input box of each property (the L-inf ball

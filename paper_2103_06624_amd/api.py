@@ -45,9 +45,10 @@ def make_layers(layers):
     return arr, keep
 
 
-def root_bounds(layers, x_lo, x_hi, sound=False):
+def root_bounds(layers, x_lo, x_hi, sound=False, opt_iters=0, lr_alpha=0.1, decay=0.98):
     """Per-layer CROWN intermediate bounds on the GPU: (l, u) float32 [P, sum d_i];
-    sound: moved outward by the rigorous float32 rounding margin."""
+    sound: moved outward by the rigorous float32 rounding margin; opt_iters > 0:
+    each bound maximised over its own alpha' by that many Adam steps."""
     arr, keep = make_layers(layers)
     x_lo = np.ascontiguousarray(x_lo, np.float32)
     x_hi = np.ascontiguousarray(x_hi, np.float32)
@@ -55,8 +56,12 @@ def root_bounds(layers, x_lo, x_hi, sound=False):
     nd = sum(ly.d_out for ly in layers[:-1])
     lo = np.zeros((P, nd), np.float32)
     up = np.zeros((P, nd), np.float32)
-    fn = B.cv_bound_root_bounds_sound if sound else B.cv_bound_root_bounds
-    B.check(fn(arr, len(layers), P, _ptr(x_lo), _ptr(x_hi), _ptr(lo), _ptr(up), _stream()))
+    if opt_iters > 0:
+        B.check(B.cv_bound_root_bounds_opt(arr, len(layers), P, _ptr(x_lo), _ptr(x_hi), opt_iters, lr_alpha, decay,
+                                           int(sound), _ptr(lo), _ptr(up), _stream()))
+    else:
+        fn = B.cv_bound_root_bounds_sound if sound else B.cv_bound_root_bounds
+        B.check(fn(arr, len(layers), P, _ptr(x_lo), _ptr(x_hi), _ptr(lo), _ptr(up), _stream()))
     return lo, up
 
 

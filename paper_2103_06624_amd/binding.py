@@ -44,6 +44,9 @@ SIGNATURES = {
                                             _vp, _vp]),
     "cv_bound_root_bounds_sound": (ctypes.c_int, [ctypes.POINTER(cv_layer), ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp,
                                             _vp, _vp]),
+    "cv_bound_root_bounds_opt": (ctypes.c_int, [ctypes.POINTER(cv_layer), ctypes.c_int32, ctypes.c_int32, _vp, _vp,
+                                                ctypes.c_int32, ctypes.c_float, ctypes.c_float, ctypes.c_int32, _vp,
+                                                _vp, _vp]),
     "cv_bound_init": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.POINTER(cv_layer), ctypes.c_int32, ctypes.c_int32,
                                      _vp, _vp, ctypes.c_int32, _vp, _vp, _vp, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp,
                                      _vp]),
@@ -101,6 +104,7 @@ def _fn(name):
 
 cv_bound_root_bounds = _fn("cv_bound_root_bounds")
 cv_bound_root_bounds_sound = _fn("cv_bound_root_bounds_sound")
+cv_bound_root_bounds_opt = _fn("cv_bound_root_bounds_opt")
 cv_bound_init = _fn("cv_bound_init")
 cv_bound_sizes = _fn("cv_bound_sizes")
 cv_bound_alpha_offset = _fn("cv_bound_alpha_offset")

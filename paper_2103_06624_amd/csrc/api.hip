@@ -1293,7 +1293,9 @@ namespace {
 // Root bounds of every ReLU layer, one sub-network at a time (layers 1..i,
 // specification [I; -I] on layer i); sound: with the rigorous float32 margin.
 int root_bounds(const cv_layer* layers, int32_t n_layers, int32_t n_props, const float* x_lo, const float* x_hi,
-                float* l_out, float* u_out, bool sound, void* stream) {
+                float* l_out, float* u_out, bool sound, void* stream, int iters = 0, float lr_alpha = 0.f,
+                float decay = 1.f) {
+  if (iters < 0 || !std::isfinite(lr_alpha) || !std::isfinite(decay)) return fail(CV_EINVAL, "bad optimiser settings");
   std::vector<int> dims;
   int rc = check_layers(layers, n_layers, dims);
   if (rc) return rc;
@@ -1332,7 +1334,19 @@ int root_bounds(const cv_layer* layers, int32_t n_layers, int32_t n_props, const
     }
     float* dlb;
     if ((rc = hb.mem.alloc(&dlb, (size_t)hb.R))) return rc;
-    if ((rc = enqueue_bwd(&hb, nullptr, nullptr, false, dlb, nullptr, 0, s))) return rc;
+    if (iters > 0 && hb.n_alpha > 0) {
+      // each of the 2d bounds (rows) has its own alpha' for every unstable
+      // neuron below: projected Adam from CROWN's default, best iterate kept
+      float *alpha, *dlast;
+      if ((rc = ensure_opt(&hb)) || (rc = hb.mem.alloc(&alpha, (size_t)hb.n_alpha)) ||
+          (rc = hb.mem.alloc(&dlast, (size_t)hb.R)))
+        return rc;
+      launch_alpha_default(alpha, hb.ulist, hb.uoff, hb.bt, s);
+      if ((rc = enqueue_opt(&hb, iters, lr_alpha, 0.f, decay, alpha, nullptr, AdamPtrs{}, 0, dlb, dlast, s)))
+        return rc;
+    } else if ((rc = enqueue_bwd(&hb, nullptr, nullptr, false, dlb, nullptr, 0, s))) {
+      return rc;
+    }
     std::vector<float> lb(hb.R);
     HIPCHK(hipMemcpyAsync(lb.data(), dlb, (size_t)hb.R * sizeof(float), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -1751,6 +1765,14 @@ int cv_bound_root_bounds(const cv_layer* layers, int32_t n_layers, int32_t n_pro
 int cv_bound_root_bounds_sound(const cv_layer* layers, int32_t n_layers, int32_t n_props, const float* x_lo,
                                const float* x_hi, float* l_out, float* u_out, void* stream) {
   return root_bounds(layers, n_layers, n_props, x_lo, x_hi, l_out, u_out, true, stream);
+}
+
+int cv_bound_root_bounds_opt(const cv_layer* layers, int32_t n_layers, int32_t n_props, const float* x_lo,
+                             const float* x_hi, int32_t iters, float lr_alpha, float lr_decay, int32_t sound,
+                             float* l_out, float* u_out, void* stream) {
+  if (sound != 0 && sound != 1) return fail(CV_EINVAL, "sound must be 0 or 1");
+  return root_bounds(layers, n_layers, n_props, x_lo, x_hi, l_out, u_out, sound != 0, stream, iters, lr_alpha,
+                     lr_decay);
 }
 
 }  // extern "C"

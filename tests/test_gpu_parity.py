@@ -255,6 +255,38 @@ def test_sound_root_bounds_enclose_sampled_preactivations():
                 off += d
 
 
+@pytest.mark.parametrize("name", ["mlp_small", "cnn_base"])
+def test_optimised_root_bounds_parity(name):
+    """Intermediate bounds each maximised over its own alpha' (10 Adam steps):
+    against the oracle's, at least as tight as the library's CROWN bounds, and
+    (with the sound margin) enclosing sampled pre-activations."""
+    from oracle import beta_crown as bc
+    from paper_2103_06624_amd.api import root_bounds
+    wl, lo32, up32, lo64, up64, orc = cases.small_case(name)
+    lo, up = root_bounds(wl.net.layers, wl.x_lo, wl.x_hi, opt_iters=10, lr_alpha=0.1, decay=0.98)
+    lo_c, up_c = root_bounds(wl.net.layers, wl.x_lo, wl.x_hi)
+    assert (lo >= lo_c - 1e-6 * np.maximum(1, np.abs(lo_c))).all() and (up <= up_c + 1e-6 * np.maximum(1, np.abs(up_c))).all()
+    assert (lo > lo_c + 1e-4).any() or (up < up_c - 1e-4).any()
+    cfg = bc.AdamConfig(iters=10, lr_alpha=0.1, decay=0.98)
+    for p in range(min(2, wl.x_lo.shape[0])):
+        lo_o, up_o = bc.root_bounds_opt(orc.net64, wl.x_lo[p].astype(np.float64), wl.x_hi[p].astype(np.float64), cfg)
+        e = max(guarded_rel(lo[p], np.concatenate(lo_o)).max(), guarded_rel(up[p], np.concatenate(up_o)).max())
+        say(name, "optimised root bounds rel err", e, "property", p)
+        assert e <= TOL
+    lo_s, up_s = root_bounds(wl.net.layers, wl.x_lo, wl.x_hi, sound=True, opt_iters=10, lr_alpha=0.1, decay=0.98)
+    assert (lo_s <= lo).all() and (up_s >= up).all()
+    rng = np.random.default_rng(3)
+    xl, xh = wl.x_lo[0].astype(np.float64), wl.x_hi[0].astype(np.float64)
+    h = xl + (xh - xl) * rng.uniform(size=(128, xl.shape[0]))
+    off = 0
+    for W, b in orc.net64[:-1]:
+        z = h @ W.T + b
+        d = z.shape[1]
+        assert (z >= lo_s[0, off:off + d]).all() and (z <= up_s[0, off:off + d]).all()
+        h = np.maximum(z, 0.0)
+        off += d
+
+
 def test_sound_rejects_bad_values():
     from paper_2103_06624_amd.binding import CvError
     wl, orc, pb = problem("mlp_small")
