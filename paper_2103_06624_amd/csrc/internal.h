@@ -37,7 +37,7 @@ inline void launch_k(void (*k)(P...), dim3 grid, dim3 block, uint32_t smem, hipS
 enum Mode {
   kBwdRelax = 0,  // back-substitution, then the next ReLU layer's relaxation
   kBwdConc = 1,   // back-substitution into the input, then box concretisation
-  kFwdX = 2,      // adjoint forward step from x* (first layer)
+  kFwdX = 2,      // adjoint forward step from x* of a conv first layer (its sign planes)
   kFwd = 3,       // adjoint forward step from zhat(i-1)
   kFwdTop = 4     // kFwd for the top ReLU layer inside the optimiser, plus the
                   // next iteration's top-layer relaxation (Epi::top_out)
