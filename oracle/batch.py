@@ -53,6 +53,15 @@ class OracleProblem:
         self.unstable = [np.nonzero((self.lo[p] < 0) & (self.up[p] > 0))[0] for p in range(self.lo.shape[0])]
         sizes = np.array([self.m * self.unstable[int(p)].shape[0] for p in self.dom_prop], np.int64)
         self.alpha_off = np.concatenate([[0], np.cumsum(sizes)])
+        self.l2 = None  # (x0 [P, d0], eps [P]) when the input set is an l2 ball per property
+
+    def set_l2(self, x0, eps):
+        """Input set of property p: the l2 ball of radius eps[p] around x0[p]
+        (None: back to the box)."""
+        self.l2 = None if x0 is None else (np.asarray(x0, np.float64), np.asarray(eps, np.float64))
+
+    def _ball(self, p):
+        return None if self.l2 is None else (self.l2[0][p], float(self.l2[1][p]))
 
     @property
     def n_alpha(self):
@@ -112,24 +121,26 @@ class OracleProblem:
     def eval(self, b, alpha_flat, beta_flat):
         p, lo, up, split = self.domain(b)
         return bc.bound(self.net64, self.x_lo[p], self.x_hi[p], self.C[p], lo, up, split,
-                        self.alpha_to_layers(b, alpha_flat), self.beta_to_layers(b, beta_flat))
+                        self.alpha_to_layers(b, alpha_flat), self.beta_to_layers(b, beta_flat), ball=self._ball(p))
 
     def upper(self, b, alpha_flat, beta_flat):
         """(g [m], ub [m], sat [m], margin [m]) of subdomain b (beta_crown.upper_bound)."""
         p, lo, up, split = self.domain(b)
         return bc.upper_bound(self.net64, self.x_lo[p], self.x_hi[p], self.C[p], lo, up, split,
-                              self.alpha_to_layers(b, alpha_flat), self.beta_to_layers(b, beta_flat))
+                              self.alpha_to_layers(b, alpha_flat), self.beta_to_layers(b, beta_flat), self._ball(p))
 
     def grad(self, b, alpha_flat, beta_flat):
         """(g [m], dalpha in the compact block of b, dbeta [depth_b, m])."""
         p, lo, up, split = self.domain(b)
         g, ga, gb = bc.bound_and_grad(self.net64, self.x_lo[p], self.x_hi[p], self.C[p], lo, up, split,
-                                      self.alpha_to_layers(b, alpha_flat), self.beta_to_layers(b, beta_flat))
+                                      self.alpha_to_layers(b, alpha_flat), self.beta_to_layers(b, beta_flat),
+                                      self._ball(p))
         return g, self.alpha_from_layers(b, ga), self.beta_from_layers(b, gb)
 
     def optimize(self, b, alpha_flat, beta_flat, cfg=None):
         """(best g [m], final alpha block, final beta [depth_b, m], final g)."""
         p, lo, up, split = self.domain(b)
         best, a, bt, g = bc.optimize(self.net64, self.x_lo[p], self.x_hi[p], self.C[p], lo, up, split,
-                                     self.alpha_to_layers(b, alpha_flat), self.beta_to_layers(b, beta_flat), cfg)
+                                     self.alpha_to_layers(b, alpha_flat), self.beta_to_layers(b, beta_flat), cfg,
+                                     self._ball(p))
         return best, self.alpha_from_layers(b, a), self.beta_from_layers(b, bt), g

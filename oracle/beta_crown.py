@@ -132,7 +132,27 @@ def split_sign(split):
 # the bound at fixed (alpha, beta)
 
 
-def bound(net64, x_lo, x_hi, C, lo, up, split, alpha, beta, keep=False):
+def concretise(A0, x_lo, x_hi, ball=None):
+    """min over the input set of A0 x, row by row (Eq. beta_crown_lp): over
+    the box, sum_j min(A0_j x_lo_j, A0_j x_hi_j); over the l2 ball
+    ball = (x0, eps), A0 x0 - eps ||A0||_2 (Hoelder, q = p = 2)."""
+    if ball is None:
+        return np.minimum(A0 * x_lo, A0 * x_hi).sum(axis=1)
+    x0, eps = ball
+    return A0 @ x0 - eps * np.linalg.norm(A0, axis=1)
+
+
+def minimiser(A0, x_lo, x_hi, ball=None):
+    """x* of min A0 x over the input set, row by row: `box_minimiser`, or on
+    the l2 ball x0 - eps A0 / ||A0||_2 (x0 where A0 = 0)."""
+    if ball is None:
+        return box_minimiser(A0, x_lo, x_hi)
+    x0, eps = ball
+    nrm = np.linalg.norm(A0, axis=1, keepdims=True)
+    return x0[None, :] - eps * np.divide(A0, nrm, out=np.zeros_like(A0), where=nrm > 0)
+
+
+def bound(net64, x_lo, x_hi, C, lo, up, split, alpha, beta, keep=False, ball=None):
     """Lower bounds of C f(x) over the box under split constraints.
 
     net64: [(W(1), b(1)), ..., (W(L), b(L))]; ReLU after layers 1..L-1.
@@ -141,6 +161,7 @@ def bound(net64, x_lo, x_hi, C, lo, up, split, alpha, beta, keep=False):
       lo/up [d_i] pre-activation bounds, split [d_i] in {+1, -1, 0},
       alpha [m, d_i] in [0, 1], beta [m, d_i] >= 0 (read only where split).
     Returns g [m] (and the per-layer trace used by the adjoint when keep).
+    ball = (x0, eps): the input set is the l2 ball instead of the box.
 
     Recursion (Eq. definition_A with the spec merged into the last layer):
       A(L-1) = C W(L),  c = C b(L);
@@ -162,7 +183,7 @@ def bound(net64, x_lo, x_hi, C, lo, up, split, alpha, beta, keep=False):
         if keep:
             trace[i - 1] = (A, D, lowb)
         A = Lam @ W
-    g = np.minimum(A * x_lo, A * x_hi).sum(axis=1) + c
+    g = concretise(A, x_lo, x_hi, ball) + c
     if keep:
         return g, A, trace
     return g
@@ -174,7 +195,7 @@ def box_minimiser(A0, x_lo, x_hi):
     return np.where(A0 > 0, x_lo, np.where(A0 < 0, x_hi, 0.5 * (x_lo + x_hi)))
 
 
-def bound_and_grad(net64, x_lo, x_hi, C, lo, up, split, alpha, beta):
+def bound_and_grad(net64, x_lo, x_hi, C, lo, up, split, alpha, beta, ball=None):
     """g and its (super)gradient with respect to alpha and beta.
 
     Chain rule through the recursion of `bound`: the adjoint of A(0) is the box
@@ -188,8 +209,8 @@ def bound_and_grad(net64, x_lo, x_hi, C, lo, up, split, alpha, beta):
     sign pattern this is the exact gradient.
     """
     L = len(net64)
-    g, A0, trace = bound(net64, x_lo, x_hi, C, lo, up, split, alpha, beta, keep=True)
-    zhat = box_minimiser(A0, x_lo, x_hi)
+    g, A0, trace = bound(net64, x_lo, x_hi, C, lo, up, split, alpha, beta, keep=True, ball=ball)
+    zhat = minimiser(A0, x_lo, x_hi, ball)
     galpha, gbeta = [], []
     for i in range(1, L):
         W, b = net64[i - 1]
@@ -207,7 +228,7 @@ def bound_and_grad(net64, x_lo, x_hi, C, lo, up, split, alpha, beta):
 # footnote; infeasibility check of the appendix on infeasible subdomains)
 
 
-def upper_bound(net64, x_lo, x_hi, C, lo, up, split, alpha, beta):
+def upper_bound(net64, x_lo, x_hi, C, lo, up, split, alpha, beta, ball=None):
     """The lower bound g, and for each specification row the network itself
     evaluated at that row's box minimiser x* (the x that minimises the final
     linear function A(0) x + c over the box, Eq. beta_crown_linear).
@@ -224,8 +245,8 @@ def upper_bound(net64, x_lo, x_hi, C, lo, up, split, alpha, beta):
     sat_k is from a tie.  Returns (g [m], ub [m], sat [m] bool, margin [m]).
     """
     L = len(net64)
-    g, A0, _ = bound(net64, x_lo, x_hi, C, lo, up, split, alpha, beta, keep=True)
-    xs = box_minimiser(A0, x_lo, x_hi)
+    g, A0, _ = bound(net64, x_lo, x_hi, C, lo, up, split, alpha, beta, keep=True, ball=ball)
+    xs = minimiser(A0, x_lo, x_hi, ball)
     m = C.shape[0]
     ub = np.zeros(m)
     sat = np.ones(m, bool)
@@ -324,7 +345,7 @@ def adam_ascent_step(theta, grad, m, v, t, lr, cfg):
     return theta + lr * mhat / (np.sqrt(vhat) + cfg.eps), m, v
 
 
-def optimize(net64, x_lo, x_hi, C, lo, up, split, alpha0, beta0, cfg=None):
+def optimize(net64, x_lo, x_hi, C, lo, up, split, alpha0, beta0, cfg=None, ball=None):
     """Projected Adam ascent; returns (best g over all evaluated iterates,
     final alpha, final beta, g of the final iterate).
 
@@ -343,13 +364,13 @@ def optimize(net64, x_lo, x_hi, C, lo, up, split, alpha0, beta0, cfg=None):
     vb = [np.zeros_like(b) for b in beta]
     best = None
     for t in range(cfg.iters):
-        g, ga, gb = bound_and_grad(net64, x_lo, x_hi, C, lo, up, split, alpha, beta)
+        g, ga, gb = bound_and_grad(net64, x_lo, x_hi, C, lo, up, split, alpha, beta, ball)
         best = g.copy() if best is None else np.maximum(best, g)
         for i in range(len(alpha)):
             a, ma[i], va[i] = adam_ascent_step(alpha[i], ga[i], ma[i], va[i], t + 1, cfg.lr_alpha * cfg.decay ** t, cfg)
             alpha[i] = np.clip(a, 0.0, 1.0)
             bb, mb[i], vb[i] = adam_ascent_step(beta[i], gb[i], mb[i], vb[i], t + 1, cfg.lr_beta * cfg.decay ** t, cfg)
             beta[i] = np.maximum(bb, 0.0)
-    g = bound(net64, x_lo, x_hi, C, lo, up, split, alpha, beta)
+    g = bound(net64, x_lo, x_hi, C, lo, up, split, alpha, beta, ball=ball)
     best = g.copy() if best is None else np.maximum(best, g)
     return best, alpha, beta, g

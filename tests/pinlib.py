@@ -219,7 +219,7 @@ def max_over_beta_lp(bound_fn, nbeta, x_lo, x_hi):
 # Theorem 3.2 dual propagation form (L-inf ball around x0 with radius eps)
 
 
-def dual_nu_bound(net, x0, eps, c_row, lo, up, split, alpha, beta, with_input=False):
+def dual_nu_bound(net, x0, eps, c_row, lo, up, split, alpha, beta, with_input=False, q=1):
     """g from nu(L) = -c, nu-hat(i-1) = W(i)^T nu(i) and the per-neuron rules of
     the dual problem (inactive 0, active nu-hat, unstable
     u/(u-l)[nu-hat]^+ - alpha [nu-hat]^-, z<0 split -beta, z>=0 split beta + nu-hat).
@@ -255,7 +255,8 @@ def dual_nu_bound(net, x0, eps, c_row, lo, up, split, alpha, beta, with_input=Fa
                 new[j] = u[j] / (u[j] - l[j]) * pos - alpha[k - 1][j] * neg
                 lterm += l[j] * max(new[j], 0.0)
         nu = new
-    g = obj - nh @ x0 - np.abs(nh).sum() * eps + lterm
+    # the input set is the l_p ball around x0 with 1/p + 1/q = 1: q = 1 for l_inf, q = 2 for l_2
+    g = obj - nh @ x0 - np.linalg.norm(nh, ord=q) * eps + lterm
     return (g, nuhats, nh) if with_input else (g, nuhats)
 
 

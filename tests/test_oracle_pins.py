@@ -424,3 +424,94 @@ def test_optimised_root_bounds_tighter_sound_and_below_the_lp(seed):
             c[j] = sgn
             p_lp, res, _ = pinlib.lp_verify_split(sub, x_lo, x_hi, c, lo_o[:1], up_o[:1], none)
             assert res.status == 0 and val <= p_lp + 1e-8
+
+
+# ---------------------------------------------------------------------------
+# l2-ball input sets (the q-norm form of Eq. beta_crown_lp, q = p = 2)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_l2_ball_matches_dual_form_and_minimiser(seed):
+    """The bound over the l2 ball equals Theorem 3.2's dual form with the
+    2-norm of nu-hat(0); x* lies on the sphere and attains the linear part's
+    minimum; ub is the network at that x* (independent forward)."""
+    rng, net, x0, eps, x_lo, x_hi, lo, up, C = tiny_case(seed + 700, widths=(3, 6, 5, 4, 2), m=2)
+    split = random_split(rng, lo, up, k=3)
+    alpha, beta = random_vars(rng, lo, 2, split, beta_scale=2.0)
+    ball = (x0, eps)
+    g, A0, _ = bc.bound(net, x_lo, x_hi, C, lo, up, split, alpha, beta, keep=True, ball=ball)
+    _, ub, sat, _ = bc.upper_bound(net, x_lo, x_hi, C, lo, up, split, alpha, beta, ball)
+    xs = bc.minimiser(A0, x_lo, x_hi, ball)
+    for r in range(2):
+        gd, _, nh0 = pinlib.dual_nu_bound(net, x0, eps, C[r], lo, up, split, [a[r] for a in alpha],
+                                          [b[r] for b in beta], with_input=True, q=2)
+        assert abs(gd - g[r]) <= 1e-10 * max(1, abs(g[r]))
+        coef = -nh0
+        assert abs(np.linalg.norm(xs[r] - x0) - eps) <= 1e-12
+        assert abs(coef @ xs[r] - (coef @ x0 - eps * np.linalg.norm(coef))) <= 1e-10 * max(1.0, abs(coef @ x0))
+        _, logits = pinlib.forward_all(net, xs[r][None, :])
+        assert abs(ub[r] - C[r] @ logits[0]) <= 1e-10 * max(1, abs(ub[r]))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_l2_ball_bound_sound_on_the_disk(seed):
+    """Below the network's minimum over a dense sampling of the disk (2-D
+    input) restricted to the split half-spaces, and at least the bound over
+    the enclosing box at the same variables (the ball lies inside the box:
+    A x0 - eps ||A||_2 >= A x0 - eps ||A||_1)."""
+    rng, net, x0, eps, x_lo, x_hi, lo, up, C = tiny_case(seed + 800, widths=(2, 6, 6, 2), m=2)
+    th = np.linspace(0, 2 * np.pi, 721)[:-1]
+    rad = np.sqrt(np.linspace(0, 1, 301))
+    X = (x0[None, None, :] + eps * rad[:, None, None] * np.stack([np.cos(th), np.sin(th)], 1)[None]).reshape(-1, 2)
+    for trial in range(3):
+        split = random_split(rng, lo, up, k=trial)
+        alpha, beta = random_vars(rng, lo, 2, split, beta_scale=2.0)
+        g = bc.bound(net, x_lo, x_hi, C, lo, up, split, alpha, beta, ball=(x0, eps))
+        g_box = bc.bound(net, x_lo, x_hi, C, lo, up, split, alpha, beta)
+        assert np.all(g >= g_box - 1e-12)
+        zs, logits = pinlib.forward_all(net, X)
+        ok = np.ones(X.shape[0], bool)
+        for z, s in zip(zs, split):
+            ok &= np.all((z[:, s > 0] >= 0), axis=1) & np.all((z[:, s < 0] <= 0), axis=1)
+        if ok.any():
+            fmin = (logits[ok] @ C.T).min(axis=0)
+            assert np.all(g <= fmin + 1e-9), (g, fmin)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_l2_ball_gradient_matches_central_differences(seed):
+    rng, net, x0, eps, x_lo, x_hi, lo, up, C = tiny_case(seed + 900, widths=(5, 8, 7, 3), m=2)
+    split = random_split(rng, lo, up, k=2)
+    alpha, beta = random_vars(rng, lo, 2, split, beta_scale=0.5)
+    alpha = [np.clip(a, 0.05, 0.95) for a in alpha]
+    beta = [np.where(s != 0, b + 0.1, 0.0) for b, s in zip(beta, split)]
+    ball = (x0, eps)
+    g, ga, gb = bc.bound_and_grad(net, x_lo, x_hi, C, lo, up, split, alpha, beta, ball)
+    h = 1e-4
+
+    def pattern(a, b):
+        _, A0, tr = bc.bound(net, x_lo, x_hi, C, lo, up, split, a, b, keep=True, ball=ball)
+        return [np.sign(t[0]) for t in tr]
+
+    base = pattern(alpha, beta)
+    checked = 0
+    for which, vars_, grads in (("a", alpha, ga), ("b", beta, gb)):
+        for i in range(len(vars_)):
+            for r in range(2):
+                for j in range(vars_[i].shape[1]):
+                    uns = lo[i][j] < 0 < up[i][j] and split[i][j] == 0
+                    if (which == "a" and not uns) or (which == "b" and split[i][j] == 0):
+                        continue
+                    p, q = [v.copy() for v in vars_], [v.copy() for v in vars_]
+                    p[i][r, j] += h
+                    q[i][r, j] -= h
+                    args_p = (p, beta) if which == "a" else (alpha, p)
+                    args_q = (q, beta) if which == "a" else (alpha, q)
+                    if any(np.any(x != y) or np.any(x != z) for x, y, z in
+                           zip(base, pattern(*args_p), pattern(*args_q))):
+                        continue
+                    fd = (bc.bound(net, x_lo, x_hi, C, lo, up, split, *args_p, ball=ball)[r] -
+                          bc.bound(net, x_lo, x_hi, C, lo, up, split, *args_q, ball=ball)[r]) / (2 * h)
+                    assert abs(fd - grads[i][r, j]) <= 1e-6 + 1e-5 * abs(fd), (which, i, r, j, fd, grads[i][r, j])
+                    checked += 1
+    assert checked >= 10
