@@ -252,6 +252,24 @@ int cv_bound_set_tiling(cv_bound *h, int32_t tiling);
  * on computes the constants (host work, synchronous on `stream`). */
 int cv_bound_set_sound(cv_bound *h, int32_t on, void *stream);
 
+/* l2-ball input sets (Sec. 2.1 allows any l_p ball; Theorem 3.1's last step
+ * then concretises with the dual norm): property p's input set becomes
+ * {x : ||x - x0_p||_2 <= eps_p} in place of its box.  The bound's last step
+ * is then A(0) x0 - eps ||A(0)||_2 (row of A(0) = Lambda(1) W(1)), and the
+ * adjoint and cv_bound_upper use its minimiser x* = x0 - eps A(0)/||A(0)||_2
+ * (x0 where A(0) = 0).  The handle's root bounds must hold over the balls
+ * (the caller's responsibility, as for boxes).
+ *   x0: host [n_props][d0], finite; eps: host [n_props], finite and >= 0;
+ *   x0 = NULL returns every property to its box (eps ignored).
+ * Applies to the handle and its sub-batches, now and when later created.
+ * Not combined with sound mode: CV_EINVAL while sound mode is on (and
+ * cv_bound_set_sound(h, 1) fails while balls are set).  The fused dense
+ * chain and the optimiser's fused top layer are not used over balls.
+ * Copies its arguments (synchronous on `stream`); the first call allocates
+ * per-row buffers (CV_ENOMEM).  W(1) x0 + b(1) is formed on the host in
+ * double and rounded once. */
+int cv_bound_set_input_l2(cv_bound *h, const float *x0, const float *eps, void *stream);
+
 /* Per-kernel timing of one gradient pass plus one plain evaluation, issued
  * eagerly on `stream`, repeated `reps` times.  Each kernel launch of a pass
  * is issued 8 times back to back (same arguments) between two HIP events on

@@ -181,6 +181,16 @@ class BoundProblem:
         """Lower every reported bound by a rigorous float32 rounding-error margin."""
         B.check(B.cv_bound_set_sound(self.h, int(on), _stream()))
 
+    def set_input_l2(self, x0, eps):
+        """Input sets {x : ||x - x0_p||_2 <= eps_p} per property (x0 [P, d0], eps [P],
+        host arrays) in place of the boxes; x0=None returns to the boxes."""
+        if x0 is None:
+            B.check(B.cv_bound_set_input_l2(self.h, None, None, _stream()))
+            return
+        x0 = np.ascontiguousarray(x0, dtype=np.float32)
+        eps = np.ascontiguousarray(np.broadcast_to(np.asarray(eps, np.float32), (x0.shape[0],)))
+        B.check(B.cv_bound_set_input_l2(self.h, _ptr(x0), _ptr(eps), _stream()))
+
     def set_parts(self, nparts):
         """Concurrent sub-batches (streams) of optimize(); 1 disables the split."""
         B.check(B.cv_bound_set_parts(self.h, nparts))

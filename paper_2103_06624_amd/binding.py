@@ -65,6 +65,7 @@ SIGNATURES = {
     "cv_bound_num_tilings": (ctypes.c_int32, []),
     "cv_bound_set_tiling": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "cv_bound_set_sound": (ctypes.c_int, [_vp, ctypes.c_int32, _vp]),
+    "cv_bound_set_input_l2": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "cv_bound_profile": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32, ctypes.POINTER(cv_kernel_stat),
                                         ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _vp]),
     "cv_bound_destroy": (None, [_vp]),
@@ -119,6 +120,7 @@ cv_bound_set_parts = _fn("cv_bound_set_parts")
 cv_bound_num_tilings = _fn("cv_bound_num_tilings")
 cv_bound_set_tiling = _fn("cv_bound_set_tiling")
 cv_bound_set_sound = _fn("cv_bound_set_sound")
+cv_bound_set_input_l2 = _fn("cv_bound_set_input_l2")
 cv_bound_profile = _fn("cv_bound_profile")
 cv_bound_destroy = _fn("cv_bound_destroy")
 cv_last_error = _fn("cv_last_error")

@@ -164,6 +164,10 @@ struct cv_bound {
   // the optimiser's fused top layer: where the last adjoint GEMM left
   // Lambda(L-1) (act buffer) and how many partial slots it filled
   int ftop_buf = 0, ftop_slots = 1;
+  // l2-ball input sets: centre [P, d0], radius [P], W(1) x0 + b(1) [P, d1],
+  // the A(0)^2 partials [n_slots, R] and eps / ||A(0)||_2 per row
+  bool l2 = false;
+  float *l2x0 = nullptr, *l2eps = nullptr, *wx0 = nullptr, *psq = nullptr, *l2s = nullptr;
   bool sound = false;
   float* sw = nullptr;    // [P, nd]
   float* perr = nullptr;  // [n_slots, R]
@@ -598,7 +602,7 @@ int ensure_grad(cv_bound* h) {
   if ((rc = h->mem.alloc(&h->acomp, h->n_alpha)) || (rc = h->mem.alloc(&h->xpos, (size_t)h->R * h->w64)) ||
       (rc = h->mem.alloc(&h->xneg, (size_t)h->R * h->w64)))
     return rc;
-  if (h->layers[0].type == CV_LAYER_DENSE) {
+  if (h->layers[0].type == CV_LAYER_DENSE && !h->xdense) {
     // the first adjoint step reads x* as a plain GEMM operand
     h->ldx = r4(h->d0);
     if ((rc = h->mem.alloc(&h->xdense, (size_t)h->R * h->ldx))) return rc;
@@ -679,6 +683,38 @@ void abs_weighted(const cv_layer& ly, const std::vector<double>& hm, std::vector
             }
           }
         v[((size_t)c * ly.out_h + oy) * ly.out_w + ox] = t;
+      }
+}
+
+// out = W x + b for one affine layer, in double.
+void affine_host(const cv_layer& ly, const float* x, std::vector<double>& out) {
+  if (ly.type == CV_LAYER_DENSE) {
+    out.assign(ly.out_c, 0.0);
+    for (int k = 0; k < ly.out_c; ++k) {
+      double t = ly.bias[k];
+      const float* w = ly.weight + (size_t)k * ly.in_c;
+      for (int j = 0; j < ly.in_c; ++j) t += (double)w[j] * x[j];
+      out[k] = t;
+    }
+    return;
+  }
+  out.assign((size_t)ly.out_c * ly.out_h * ly.out_w, 0.0);
+  for (int c = 0; c < ly.out_c; ++c)
+    for (int oy = 0; oy < ly.out_h; ++oy)
+      for (int ox = 0; ox < ly.out_w; ++ox) {
+        double t = ly.bias[c];
+        for (int ci = 0; ci < ly.in_c; ++ci)
+          for (int ky = 0; ky < ly.kernel; ++ky) {
+            const int iy = oy * ly.stride - ly.pad + ky;
+            if (iy < 0 || iy >= ly.in_h) continue;
+            for (int kx = 0; kx < ly.kernel; ++kx) {
+              const int ix = ox * ly.stride - ly.pad + kx;
+              if (ix < 0 || ix >= ly.in_w) continue;
+              t += (double)ly.weight[(((size_t)c * ly.in_c + ci) * ly.kernel + ky) * ly.kernel + kx] *
+                   x[((size_t)ci * ly.in_h + iy) * ly.in_w + ix];
+            }
+          }
+        out[((size_t)c * ly.out_h + oy) * ly.out_w + ox] = t;
       }
 }
 
@@ -779,6 +815,7 @@ Epi make_epi(const cv_bound* h) {
   Epi e{};
   e.part = h->part;
   e.perr = h->sound ? h->perr : nullptr;
+  e.psq = h->l2 ? h->psq : nullptr;
   e.n_slots = h->n_slots;
   e.ldo = h->ldact;
   return e;
@@ -822,10 +859,11 @@ int enqueue_bwd(cv_bound* h, const float* alpha, const float* beta, bool grad, f
   v.beta = beta;
   v.acomp = grad ? h->acomp : nullptr;
   // x* for the adjoint: dense rows for a dense first layer, sign planes for a convolution
+  // (over an l2 ball: A(0) itself, densely, whatever the first layer)
   const bool dense1 = h->layers[0].type == CV_LAYER_DENSE;
-  v.xpos = grad && !dense1 ? h->xpos : nullptr;
-  v.xneg = grad && !dense1 ? h->xneg : nullptr;
-  v.xdense = grad && dense1 ? h->xdense : nullptr;
+  v.xpos = grad && !dense1 && !h->l2 ? h->xpos : nullptr;
+  v.xneg = grad && !dense1 && !h->l2 ? h->xneg : nullptr;
+  v.xdense = grad && (dense1 || h->l2) ? h->xdense : nullptr;
   v.ldx = h->ldx;
   Profiler* pf = h->prof;
   if (h->R == 0) return CV_OK;
@@ -833,7 +871,7 @@ int enqueue_bwd(cv_bound* h, const float* alpha, const float* beta, bool grad, f
   if (skip_top) {
     cur = h->ftop_buf;
     slot = h->ftop_slots;
-  } else if (h->chain_b && !h->sound) {
+  } else if (h->chain_b && !h->sound && !h->l2) {
     const int lo = h->chain_lo;
     ChainArgs ca{};
     ca.nl = L - lo;
@@ -939,7 +977,9 @@ int enqueue_bwd(cv_bound* h, const float* alpha, const float* beta, bool grad, f
     cur ^= 1;
   }
   if (pf) pf->begin("finalize", 0, (double)h->R * (slot + 2) * 4.0);
-  launch_finalize(h->part, h->sound ? h->perr : nullptr, h->sound_scale, h->n_slots, slot, h->R, lb, best, first, s);
+  const L2Final l2f{h->bt.prop, h->m, h->l2eps, h->l2s};
+  launch_finalize(h->part, h->sound ? h->perr : nullptr, h->sound_scale, h->l2 ? h->psq : nullptr, l2f, h->n_slots,
+                  slot, h->R, lb, best, first, s);
   if (pf) pf->end();
   HIPCHK(hipGetLastError());
   return CV_OK;
@@ -948,6 +988,28 @@ int enqueue_bwd(cv_bound* h, const float* alpha, const float* beta, bool grad, f
 // Adjoint forward sweep: zbar(i) = W(i) zhat(i-1) + b(i) from zhat(0) = x*,
 // gradients of alpha and beta in the epilogues (or, with `ad`, the projected
 // Adam step applied in place).
+// Operand of forward layer i: zhat(i-1) for i > 1; at the first layer x*,
+// read densely (dense first layer), from its sign planes (conv first layer,
+// mode kFwdX), or over an l2 ball as A(0) itself with zbar(1) = W(1) x0 + b(1)
+// - l2s (W(1) A(0)) formed in the epilogue.
+void first_layer_input(cv_bound* h, int i, Vars& v, Epi& e, const float*& in, int& lda, int& mode) {
+  mode = kFwd;
+  lda = h->ldact;
+  in = i == 1 ? nullptr : h->act[(i - 1) & 1];
+  if (i != 1) return;
+  if (h->l2) {
+    in = h->xdense;
+    lda = h->ldx;
+    e.wx0 = h->wx0;
+    v.l2s = h->l2s;
+  } else if (h->layers[0].type == CV_LAYER_DENSE) {
+    in = h->xdense;
+    lda = h->ldx;
+  } else {
+    mode = kFwdX;
+  }
+}
+
 // fuse_top (optimiser, with Adam): the last adjoint GEMM also relaxes the next
 // iteration's top layer (Epi::top_out); the next back-substitution then
 // starts from its output (enqueue_bwd with skip_top).
@@ -982,19 +1044,18 @@ int enqueue_fwd(cv_bound* h, const float* alpha, const float* beta, float* ga, f
   const int i_chain = h->chain_f ? h->chain_lo + 1 : L;
   for (int i = 1; i <= L - 1 && i < i_chain; ++i) {
     const DevLayer& ly = h->layers[i - 1];
-    const bool xd = i == 1 && ly.type == CV_LAYER_DENSE;  // x* read as a dense operand
-    const int mode = i == 1 && !xd ? kFwdX : kFwd;
     const int last = i == L - 1;
     Epi e = make_epi(h);
     e.layer_off = h->offs[i - 1];
     e.bias = ly.bias;
     e.n = h->dims[i];
     e.out = h->act[i & 1];
-    const float* in = i == 1 ? (xd ? h->xdense : nullptr) : h->act[(i - 1) & 1];
-    const int lda = xd ? h->ldx : h->ldact;
+    int mode, lda;
+    const float* in;
+    first_layer_input(h, i, v, e, in, lda, mode);
     const double rows = h->R;
     const int N = h->dims[i], K = h->dims[i - 1];
-    const double io = (i == 1 && !xd ? rows * K / 4.0 : rows * K * 4.0) + (last ? 0.0 : rows * N * 4.0) +
+    const double io = (mode == kFwdX ? rows * K / 4.0 : rows * K * 4.0) + (last ? 0.0 : rows * N * 4.0) +
                       (double)h->B * N * 2.0 + h->unst_rows_per_layer[i - 1] * 4.0 * 3;
     if (ly.type == CV_LAYER_DENSE) {
       const int c = h->cfg[L + i - 1] >= 0 ? h->cfg[L + i - 1] : 0;
@@ -1015,7 +1076,7 @@ int enqueue_fwd(cv_bound* h, const float* alpha, const float* beta, float* ga, f
       launch_gemm(c, e.top_out ? kFwdTop : mode, g, s);
       if (pf) pf->end();
     } else {
-      ConvArgs a{in, h->ldact, ly.W, ly.g, h->R, last, ly.uniform, h->bt, v, e};
+      ConvArgs a{in, lda, ly.W, ly.g, h->R, last, ly.uniform, h->bt, v, e};
       if (pf) pf->begin(std::string(mode == kFwdX ? "conv_fwd_x_co" : "conv_fwd_co") + std::to_string(ly.g.co),
                         2.0 * rows * conv_macs(ly.g), io);
       if (launch_conv_fwd(mode, a, s)) return fail(CV_ESHAPE, "unsupported conv channels");
@@ -1075,7 +1136,8 @@ int enqueue_opt(cv_bound* h, int iters, float lr_a, float lr_b, float decay, flo
   // the top layer's relaxation rides on the last adjoint GEMM from the
   // second iteration on (per-layer kernels, dense top layer, no sound margin)
   const int L = h->L;
-  const bool fuse = L >= 2 && h->layers[L - 2].type == CV_LAYER_DENSE && !h->chain_b && !h->chain_f && !h->sound;
+  const bool fuse =
+      L >= 2 && h->layers[L - 2].type == CV_LAYER_DENSE && !h->chain_b && !h->chain_f && !h->sound && !h->l2;
   for (int t = 0; t < iters; ++t) {
     if ((rc = enqueue_bwd(h, alpha, beta, true, nullptr, lb_best, t == 0, s, fuse && t > 0))) return rc;
     const int tt = step0 + t;
@@ -1194,7 +1256,23 @@ int set_parts(cv_bound* h, int n) {
     }
     h->pev.push_back(e);
   }
-  // new sub-batches follow the handle's sound mode
+  // new sub-batches follow the handle's input set and sound mode
+  if (h->l2) {
+    for (cv_bound* q : h->parts) {
+      int rc;
+      if ((rc = q->mem.alloc(&q->psq, (size_t)q->n_slots * std::max(1, q->R))) ||
+          (rc = q->mem.alloc(&q->l2s, std::max(1, q->R))))
+        return rc;
+      q->ldx = r4(q->d0);
+      if ((rc = q->mem.alloc(&q->xdense, (size_t)std::max(1, q->R) * q->ldx))) return rc;
+      q->l2x0 = h->l2x0;
+      q->l2eps = h->l2eps;
+      q->wx0 = h->wx0;
+      q->l2 = true;
+      q->bt.l2x0 = h->l2x0;
+      q->bt.l2eps = h->l2eps;
+    }
+  }
   if (h->sound) {
     const cv_bound::Inputs& in = *h->in;
     for (cv_bound* q : h->parts) {
@@ -1432,21 +1510,21 @@ int enqueue_true_fwd(cv_bound* h, float* ub, int32_t* sat, hipStream_t s) {
   v.sat = sat;
   for (int i = 1; i <= L - 1; ++i) {
     const DevLayer& ly = h->layers[i - 1];
-    const bool xd = i == 1 && ly.type == CV_LAYER_DENSE;
-    const int mode = i == 1 && !xd ? kFwdX : kFwd;
     Epi e = make_epi(h);
     e.layer_off = h->offs[i - 1];
     e.bias = ly.bias;
     e.n = h->dims[i];
     e.out = h->act[i & 1];
-    const float* in = i == 1 ? (xd ? h->xdense : nullptr) : h->act[(i - 1) & 1];
+    int mode, lda;
+    const float* in;
+    first_layer_input(h, i, v, e, in, lda, mode);
     const int N = h->dims[i], K = h->dims[i - 1];
     if (ly.type == CV_LAYER_DENSE) {
       const int c = h->cfg[L + i - 1] >= 0 ? h->cfg[L + i - 1] : 0;
-      GemmArgs g{in, xd ? h->ldx : h->ldact, ly.W, ly.ld_in, h->R, N, K, 0, h->bt, v, e};
+      GemmArgs g{in, lda, ly.W, ly.ld_in, h->R, N, K, 0, h->bt, v, e};
       launch_gemm(c, mode, g, s);
     } else {
-      ConvArgs a{in, h->ldact, ly.W, ly.g, h->R, 0, ly.uniform, h->bt, v, e};
+      ConvArgs a{in, lda, ly.W, ly.g, h->R, 0, ly.uniform, h->bt, v, e};
       if (launch_conv_fwd(mode, a, s)) return fail(CV_ESHAPE, "unsupported conv channels");
     }
   }
@@ -1681,6 +1759,7 @@ int cv_bound_set_tiling(cv_bound* h, int32_t tiling) {
 int cv_bound_set_sound(cv_bound* h, int32_t on, void* stream) {
   if (!h || !h->in) return fail(CV_EINVAL, "null handle");
   if (on != 0 && on != 1) return fail(CV_EINVAL, "sound must be 0 or 1");
+  if (on && h->l2) return fail(CV_EINVAL, "sound mode covers box input sets only");
   // the sub-batch handles share the parent's network, boxes and root bounds
   const cv_bound::Inputs& in = *h->in;
   std::vector<cv_bound*> all{h};
@@ -1694,6 +1773,64 @@ int cv_bound_set_sound(cv_bound* h, int32_t on, void* stream) {
     q->sound = on != 0;
     q->bt.sw = q->sound ? q->sw : nullptr;
     q->bt.sg = q->sound_g;
+    drop_graph(q);
+  }
+  return CV_OK;
+}
+
+int cv_bound_set_input_l2(cv_bound* h, const float* x0, const float* eps, void* stream) {
+  if (!h || !h->in) return fail(CV_EINVAL, "null handle");
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<cv_bound*> all{h};
+  all.insert(all.end(), h->parts.begin(), h->parts.end());
+  if (!x0) {  // back to the box
+    for (cv_bound* q : all) {
+      q->l2 = false;
+      q->bt.l2x0 = nullptr;
+      q->bt.l2eps = nullptr;
+      drop_graph(q);
+    }
+    return CV_OK;
+  }
+  if (!eps) return fail(CV_EINVAL, "null argument");
+  if (h->sound) return fail(CV_EINVAL, "sound mode covers box input sets only");
+  const int P = h->P, d0 = h->d0, d1 = h->dims[1];
+  for (int64_t i = 0; i < (int64_t)P * d0; ++i)
+    if (!std::isfinite(x0[i])) return fail(CV_EINVAL, "x0 must be finite");
+  for (int p = 0; p < P; ++p)
+    if (!(eps[p] >= 0.f) || !std::isfinite(eps[p])) return fail(CV_EINVAL, "eps must be finite and >= 0");
+  // W(1) x0 + b(1) per property, in double, rounded once
+  const cv_layer& ly1 = h->in->layers[0];
+  std::vector<float> wx0((size_t)P * d1);
+  std::vector<double> t;
+  for (int p = 0; p < P; ++p) {
+    affine_host(ly1, x0 + (size_t)p * d0, t);
+    for (int j = 0; j < d1; ++j) wx0[(size_t)p * d1 + j] = (float)t[j];
+  }
+  int rc;
+  if (!h->l2x0 && ((rc = h->mem.alloc(&h->l2x0, (size_t)P * d0)) || (rc = h->mem.alloc(&h->l2eps, P)) ||
+                   (rc = h->mem.alloc(&h->wx0, (size_t)P * d1))))
+    return rc;
+  HIPCHK(hipMemcpyAsync(h->l2x0, x0, sizeof(float) * P * d0, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(h->l2eps, eps, sizeof(float) * P, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(h->wx0, wx0.data(), sizeof(float) * P * d1, hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  // the sub-batches read the parent's centre, radius and W(1) x0 + b(1); each
+  // handle keeps its own per-row sums and scales, and x* (A(0)) densely
+  for (cv_bound* q : all) {
+    if (!q->psq && ((rc = q->mem.alloc(&q->psq, (size_t)q->n_slots * std::max(1, q->R))) ||
+                    (rc = q->mem.alloc(&q->l2s, std::max(1, q->R)))))
+      return rc;
+    if (!q->xdense) {
+      q->ldx = r4(q->d0);
+      if ((rc = q->mem.alloc(&q->xdense, (size_t)std::max(1, q->R) * q->ldx))) return rc;
+    }
+    q->l2x0 = h->l2x0;
+    q->l2eps = h->l2eps;
+    q->wx0 = h->wx0;
+    q->l2 = true;
+    q->bt.l2x0 = h->l2x0;
+    q->bt.l2eps = h->l2eps;
     drop_graph(q);
   }
   return CV_OK;

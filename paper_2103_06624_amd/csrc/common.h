@@ -46,6 +46,10 @@ struct Batch {
   // constant and of the concretisation
   const float* sw;          // [P, nd]
   float sg;
+  // l2-ball input sets (null l2x0: the box x_lo, x_hi): centre and radius of
+  // each property's ball (the q = 2 form of Eq. beta_crown_lp)
+  const float* l2x0;        // [P, d0]
+  const float* l2eps;       // [P]
 };
 
 // Variables of one pass.
@@ -59,6 +63,8 @@ struct Vars {
   uint64_t* xneg;      // [n_rows, w64] bit set where A(0) < 0
   float* xdense;       // [n_rows, ldx] the box minimiser x* itself (dense first layer)
   int ldx;
+  // l2-ball adjoint: eps / ||A(0)||_2 of each row (x* = x0 - l2s A(0)), or null
+  const float* l2s;
   // The network's own forward pass at x* (upper bound) instead of the
   // adjoint's relaxed one: when set, the forward kernels apply the exact ReLU
   // and clear sat[row] where a pre-activation breaks a split of the row's
@@ -122,6 +128,10 @@ struct Epi {
   int ldo;
   float* part;         // [n_slots, n_rows] partial constants (slot-major)
   float* perr;         // [n_slots, n_rows] partial rounding-error bounds (sound mode), or null
+  float* psq;          // [n_slots, n_rows] partial sums of A(0)^2 (l2 ball), or null
+  // first layer of the l2-ball adjoint: W(1) x0 + b(1) per property [P, n];
+  // zbar(1) = wx0 - l2s[row] (W(1) A(0)) then replaces W(1) x* + b(1)
+  const float* wx0;
   int n_slots;
   int slot0;           // first slot of this launch
   // The adjoint's top ReLU layer inside the optimiser (null top_out

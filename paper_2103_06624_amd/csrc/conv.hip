@@ -120,6 +120,11 @@ __global__ __launch_bounds__(256) void convt_bwd(const float* __restrict__ lam, 
       const float a = acc[c];
       if (MODE == kBwdRelax) {
         e.out[(int64_t)row * e.ldo + j] = relax_bwd(bt, v, ri, e.layer_off, j, a, e.bias[j], &cst, &cer);
+      } else if (bt.l2x0) {  // l2 ball: A(0) x0 here, - eps ||A(0)||_2 in the final sum
+        const int64_t pb = (int64_t)ri.p * bt.d0 + j;
+        cst = fmaf(a, bt.l2x0[pb], cst);
+        cer = fmaf(a, a, cer);
+        if (v.xdense) v.xdense[(int64_t)row * v.ldx + j] = a;  // A(0) itself for the adjoint
       } else {
         const int64_t pb = (int64_t)ri.p * bt.d0 + j;
         const float tm = conc_term(a, bt.xlo[pb], bt.xhi[pb]);
@@ -137,11 +142,12 @@ __global__ __launch_bounds__(256) void convt_bwd(const float* __restrict__ lam, 
     const int r2 = sl.row0 + threadIdx.x;
     if (r2 < M) e.part[(int64_t)e.slot0 * M + r2] = tot;
   }
-  if (e.perr) {
+  float* const p2 = e.perr ? e.perr : e.psq;  // rounding-error bound, or the sum of A(0)^2 (l2 ball)
+  if (p2) {
     const float ter = row_sum(cer, pos, rede);
     if (threadIdx.x < sl.rb) {
       const int r2 = sl.row0 + threadIdx.x;
-      if (r2 < M) e.perr[(int64_t)e.slot0 * M + r2] = ter;
+      if (r2 < M) p2[(int64_t)e.slot0 * M + r2] = ter;
     }
   }
   if (MODE == kBwdConc && v.xpos) {
@@ -209,7 +215,8 @@ __global__ __launch_bounds__(256) void conv_fwd(const float* __restrict__ zin, i
 #pragma unroll
     for (int c = 0; c < CO; ++c) {
       const int j = c * pos + q;
-      const float zb = acc[c] + e.bias[j];
+      // l2 ball, first layer: W(1) x* + b(1) = (W(1) x0 + b(1)) - l2s (W(1) A(0))
+      const float zb = e.wx0 ? fmaf(-v.l2s[row], acc[c], e.wx0[(int64_t)ri.p * e.n + j]) : acc[c] + e.bias[j];
       if (v.sat) {  // the network itself at x*: every layer's output is kept
         const uint32_t rec = bt.status[(int64_t)ri.b * bt.nd + e.layer_off + j];
         e.out[(int64_t)row * e.ldo + j] = true_relu(rec, zb, v.sat + row);

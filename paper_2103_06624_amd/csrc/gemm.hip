@@ -191,7 +191,7 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt(const float* __restrict__ A,
           if (row >= M || col >= N) continue;
           if (MODE == kBwdConc) {
             const int64_t pb = (int64_t)ri.p * bt.d0 + col;
-            o.ech[q] = make_float2(bt.xlo[pb], bt.xhi[pb]);
+            o.ech[q] = bt.l2x0 ? make_float2(bt.l2x0[pb], 0.f) : make_float2(bt.xlo[pb], bt.xhi[pb]);
             continue;
           }
           const int64_t pc = (int64_t)ri.p * bt.nd + e.layer_off + col;
@@ -214,6 +214,9 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt(const float* __restrict__ A,
   // epilogue: lane holds rows 4*(lane/16)+r of each 16x16 block, column lane%16
   auto epilogue = [&](const Ops& o, floatx4 (&acc)[FM][FN]) {
     if (MODE == kBwdRelax || MODE == kBwdConc) {
+      // second per-row sum: the rounding-error bound (sound mode) or, when
+      // concretising over an l2 ball, the sum of A(0)^2 (the modes exclude each other)
+      float* const p2 = e.perr ? e.perr : e.psq;
       float cst[FM][4], cer[FM][4];
 #pragma unroll
       for (int i = 0; i < FM; ++i) {
@@ -238,6 +241,12 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt(const float* __restrict__ A,
                 e.out[(int64_t)row * e.ldo + col] = lam;
                 cer[i][r] = fmaf(fabsf(lam), o.esw[q], cer[i][r]);
               }
+            } else if (bt.l2x0) {  // l2 ball: A(0) x0 here, - eps ||A(0)||_2 in the final sum
+              if (ok) {
+                cst[i][r] = fmaf(a, o.ech[q].x, cst[i][r]);
+                cer[i][r] = fmaf(a, a, cer[i][r]);
+                if (v.xdense) v.xdense[(int64_t)row * v.ldx + col] = a;  // A(0) itself for the adjoint
+              }
             } else {
               if (ok) {
                 const float tm = conc_term(a, o.ech[q].x, o.ech[q].y);
@@ -258,7 +267,7 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt(const float* __restrict__ A,
             }
           }
           cst[i][r] = wave_sum16(cst[i][r]);
-          if (e.perr) cer[i][r] = wave_sum16(cer[i][r]);
+          if (p2) cer[i][r] = wave_sum16(cer[i][r]);
         }
       }
       // combine the two column halves (wn = 0, 1) of each row, one slot per tile
@@ -268,7 +277,7 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt(const float* __restrict__ A,
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             red[wn][wm * WM + i * 16 + rsub + r] = cst[i][r];
-            if (e.perr) rede[wn][wm * WM + i * 16 + rsub + r] = cer[i][r];
+            if (p2) rede[wn][wm * WM + i * 16 + rsub + r] = cer[i][r];
           }
       }
       __syncthreads();
@@ -276,7 +285,7 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt(const float* __restrict__ A,
         const int row = m0 + t;
         if (row < M) {
           e.part[(int64_t)(e.slot0 + tn) * M + row] = red[0][t] + red[1][t];
-          if (e.perr) e.perr[(int64_t)(e.slot0 + tn) * M + row] = rede[0][t] + rede[1][t];
+          if (p2) p2[(int64_t)(e.slot0 + tn) * M + row] = rede[0][t] + rede[1][t];
         }
       }
     } else if (MODE == kFwdTop) {
@@ -296,7 +305,8 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt(const float* __restrict__ A,
             const int col = n0 + wn * WN + j * 16 + csub;
             const int q = (i * 4 + r) * FN + j;
             if (rok && col < N) {
-              const float zb = acc[i][j][r] + o.ebias[j];
+              const float zb = e.wx0 ? fmaf(-v.l2s[row], acc[i][j][r], e.wx0[(int64_t)ri.p * N + col])
+                                     : acc[i][j][r] + o.ebias[j];
               const int64_t pc = (int64_t)ri.p * bt.nd + e.layer_off + col;
               float vn = 0.f;
               relax_fwd_value(bt, v, ri, o.rec[q], o.ech[q], o.east[q], o.ecf[q], pc, zb, true, o.emo[q], &vn);
@@ -340,7 +350,9 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt(const float* __restrict__ A,
             const int col = n0 + wn * WN + j * 16 + csub;
             if (col >= N) continue;
             const int q = (i * 4 + r) * FN + j;
-            const float zb = acc[i][j][r] + o.ebias[j];
+            // l2 ball, first layer: W(1) x* + b(1) = (W(1) x0 + b(1)) - l2s (W(1) A(0))
+            const float zb = e.wx0 ? fmaf(-v.l2s[row], acc[i][j][r], e.wx0[(int64_t)ri.p * N + col])
+                                   : acc[i][j][r] + o.ebias[j];
             if (v.sat) {  // the network itself at x*: every layer's output is kept
               e.out[(int64_t)row * e.ldo + col] = true_relu(o.rec[q], zb, v.sat + row);
               continue;

@@ -167,10 +167,18 @@ void launch_top(const TopArgs& a, hipStream_t s);
 // ub[row] = C_p W(L) z[row] + C_p b(L), z = zhat(L-1) of the network at x*
 void launch_top_dot(const TopArgs& a, const float* z, int ldz, float* ub, hipStream_t s);
 void launch_fill_i32(int* p, int v, int64_t n, hipStream_t s);
+// l2-ball concretisation data of the final sum
+struct L2Final {
+  const int* prop;    // [B] property of each subdomain
+  int m;              // rows per subdomain
+  const float* eps;   // [P] radius
+  float* l2s;         // [n_rows] out: eps / ||A(0)||_2, or null
+};
 // lb = sum of the used partial slots of each row; with perr (sound mode) minus
-// `scale` times the sum of the rounding-error partials, rounded outward
-void launch_finalize(const float* part, const float* perr, float scale, int n_slots, int n_used, int n_rows,
-                     float* lb, float* best, int first, hipStream_t s);
+// `scale` times the sum of the rounding-error partials, rounded outward; with
+// psq (l2 ball) minus eps_p sqrt(sum of the A(0)^2 partials)
+void launch_finalize(const float* part, const float* perr, float scale, const float* psq, const L2Final& l2,
+                     int n_slots, int n_used, int n_rows, float* lb, float* best, int first, hipStream_t s);
 void launch_adam(float* x, const float* g, float* m1, float* m2, int64_t n, float lr, float bc1, float bc2,
                  float lo, float hi, hipStream_t s);
 void launch_fill(float* p, float v, int64_t n, hipStream_t s);

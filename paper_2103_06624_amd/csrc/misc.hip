@@ -110,7 +110,9 @@ __global__ __launch_bounds__(256) void top_k(TopArgs a) {
       b2[e] = 0.f;
       if (a.conc) {
         const int64_t pb = (int64_t)ri.p * a.bt.d0 + j;
-        if (ok) {
+        if (ok && a.bt.l2x0) {
+          b1[e] = a.bt.l2x0[pb];
+        } else if (ok) {
           b1[e] = a.bt.xlo[pb];
           b2[e] = a.bt.xhi[pb];
         }
@@ -123,9 +125,14 @@ __global__ __launch_bounds__(256) void top_k(TopArgs a) {
 #pragma unroll
       for (int e = 0; e < E; ++e)
         if (j0 + 64 * e < a.n) {
-          const float tm = conc_term(av[e], b1[e], b2[e]);
-          cst += tm;
-          cer = fmaf(a.bt.sg, fabsf(tm), cer);
+          if (a.bt.l2x0) {  // l2 ball: A x0 here, - eps ||A||_2 in the final sum
+            cst = fmaf(av[e], b1[e], cst);
+            cer = fmaf(av[e], av[e], cer);
+          } else {
+            const float tm = conc_term(av[e], b1[e], b2[e]);
+            cst += tm;
+            cer = fmaf(a.bt.sg, fabsf(tm), cer);
+          }
         }
       continue;
     }
@@ -155,6 +162,9 @@ __global__ __launch_bounds__(256) void top_k(TopArgs a) {
   if (a.e.perr) {
     cer = wave_sum(cer);
     if (lane == 0) a.e.perr[(int64_t)a.e.slot0 * a.bt.n_rows + row] = cer + (a.err0 ? a.err0[ri.p * a.bt.m + ri.k] : 0.f);
+  } else if (a.e.psq) {  // zero unless the network has no ReLU layer
+    cer = wave_sum(cer);
+    if (lane == 0) a.e.psq[(int64_t)a.e.slot0 * a.bt.n_rows + row] = cer;
   }
 }
 
@@ -184,7 +194,9 @@ __global__ __launch_bounds__(256) void fill_i32_k(int* p, int v, int64_t n) {
 // four sums are then added in wave order.
 // Sound mode (perr set): the rounding-error partials are summed the same way,
 // scaled by `scale` for their own rounding, and the bound is lowered by them,
-// each step rounded outward.
+// each step rounded outward.  l2 ball (psq set): the partial sums of A(0)^2
+// give ||A(0)||_2 and the bound is lowered by eps_p ||A(0)||_2; l2s[row]
+// receives eps_p / ||A(0)||_2 (0 when A(0) = 0) for the adjoint's x*.
 __device__ __forceinline__ float slot_sum(const float* __restrict__ part, int n_used, int n_rows, int r, int g) {
   float s = 0.f;
   int t = g;
@@ -200,19 +212,25 @@ __device__ __forceinline__ float slot_sum(const float* __restrict__ part, int n_
 }
 
 __global__ __launch_bounds__(256) void finalize_k(const float* __restrict__ part, const float* __restrict__ perr,
-                                                  float scale, int n_used, int n_rows, float* lb, float* best,
-                                                  int first) {
+                                                  float scale, const float* __restrict__ psq, L2Final l2,
+                                                  int n_used, int n_rows, float* lb, float* best, int first) {
   __shared__ float red[4][64], rede[4][64];
   const int rl = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int r = blockIdx.x * 64 + rl;
+  const float* p2 = perr ? perr : psq;
   red[g][rl] = r < n_rows ? slot_sum(part, n_used, n_rows, r, g) : 0.f;
-  if (perr) rede[g][rl] = r < n_rows ? slot_sum(perr, n_used, n_rows, r, g) : 0.f;
+  if (p2) rede[g][rl] = r < n_rows ? slot_sum(p2, n_used, n_rows, r, g) : 0.f;
   __syncthreads();
   if (g == 0 && r < n_rows) {
     float tot = ((red[0][rl] + red[1][rl]) + red[2][rl]) + red[3][rl];
     if (perr) {
       const float err = nextafterf((((rede[0][rl] + rede[1][rl]) + rede[2][rl]) + rede[3][rl]) * scale, INFINITY);
       tot = nextafterf(tot - err, -INFINITY);
+    } else if (psq) {
+      const float nrm = sqrtf(((rede[0][rl] + rede[1][rl]) + rede[2][rl]) + rede[3][rl]);
+      const float eps = l2.eps[l2.prop[r / l2.m]];
+      tot = fmaf(-eps, nrm, tot);
+      if (l2.l2s) l2.l2s[r] = nrm > 0.f ? eps / nrm : 0.f;
     }
     if (lb) lb[r] = tot;
     if (best) best[r] = first ? tot : fmaxf(best[r], tot);
@@ -277,10 +295,10 @@ void launch_fill_i32(int* p, int v, int64_t n, hipStream_t s) {
 }
 
 void launch_top(const TopArgs& a, hipStream_t s) { launch_k(top_k, nblk(a.bt.n_rows, 4), 256, 0, s, a); }
-void launch_finalize(const float* part, const float* perr, float scale, int n_slots, int n_used, int n_rows,
-                     float* lb, float* best, int first, hipStream_t s) {
+void launch_finalize(const float* part, const float* perr, float scale, const float* psq, const L2Final& l2,
+                     int n_slots, int n_used, int n_rows, float* lb, float* best, int first, hipStream_t s) {
   (void)n_slots;
-  launch_k(finalize_k, nblk(n_rows, 64), 256, 0, s, part, perr, scale, n_used, n_rows, lb, best, first);
+  launch_k(finalize_k, nblk(n_rows, 64), 256, 0, s, part, perr, scale, psq, l2, n_used, n_rows, lb, best, first);
 }
 void launch_adam(float* x, const float* g, float* m1, float* m2, int64_t n, float lr, float bc1, float bc2, float lo,
                  float hi, hipStream_t s) {

@@ -51,3 +51,33 @@ def guarded_rel(a, ref):
     a = np.asarray(a, np.float64)
     ref = np.asarray(ref, np.float64)
     return np.abs(a - ref) / np.maximum(np.abs(ref), 1.0)
+
+
+@functools.lru_cache(maxsize=None)
+def l2_case(name, n_props=None, n_dom=None):
+    """The workload's properties over l2 balls: centre the generator's x0,
+    radius its box radius (the ball inscribed in the unclipped box).  Root
+    bounds are the oracle's over that enclosing box [x0 - eps, x0 + eps]
+    (so they hold over the ball), rounded outward to float32; subdomains are
+    drawn against them.  Returns (wl, lo, up, x0, eps, orc) with the oracle
+    already on the balls."""
+    wl = synth.make(name, n_props=n_props, n_dom=n_dom)
+    P = wl.n_props
+    x0 = np.asarray(wl.x0, np.float32)
+    eps = np.full(P, wl.eps, np.float32)
+    blo = x0.astype(np.float64) - eps[:, None].astype(np.float64)
+    bhi = x0.astype(np.float64) + eps[:, None].astype(np.float64)
+    net64 = bc.dense_net(wl.net.layers)
+    lo64, up64 = ob.root_bounds_all(net64, blo, bhi)
+    lo, up = bc.outward_f32(lo64, up64)
+    wl.x_lo = np.nextafter(blo.astype(np.float32), np.float32(-np.inf))
+    wl.x_hi = np.nextafter(bhi.astype(np.float32), np.float32(np.inf))
+    sp = synth.attach_splits(wl, lo, up)
+    orc = ob.OracleProblem(wl.net.layers, wl.x_lo, wl.x_hi, wl.C, lo, up, sp.dom_prop, sp.split_ptr, sp.layer,
+                           sp.neuron, sp.side, net64=net64)
+    orc.set_l2(x0, eps)
+    return wl, lo, up, x0, eps, orc
+
+
+def small_l2_case(name):
+    return l2_case(name, **SMALL[name])
