@@ -304,6 +304,33 @@ def main():
     sound = {"value": round(B / (ms_sound / 1e3), 1), "unit": "subdomain bounds/s", "ms_per_step": round(ms_sound, 4),
              "max_rel_margin": rel_margin, "min_margin": (lb_p - lb_s).min().item()}
 
+    # ---- l2-ball input sets: the same properties over the balls of radius
+    # eps around x0 (inscribed in the unclipped box, whose root bounds hold
+    # over them), same subdomain count; optimiser throughput
+    x0 = np.asarray(wl.x0, np.float32)
+    eps_l2 = np.full(wl.n_props, wl.eps, np.float32)
+    lo_b, up_b = api.root_bounds(wl.net.layers, np.nextafter(x0 - eps_l2[:, None], np.float32(-np.inf)),
+                                 np.nextafter(x0 + eps_l2[:, None], np.float32(np.inf)))
+    wl_b = synth.make(name)
+    sp_b = synth.attach_splits(wl_b, lo_b, up_b)
+    pb_b = api.BoundProblem.from_workload(wl_b, lo_b, up_b, sp_b)
+    if args.parts:
+        pb_b.set_parts(args.parts)
+    pb_b.set_input_l2(x0, eps_l2)
+    a_b, b_b = pb_b.alpha_init(), pb_b.zeros_beta()
+    opt_b = dict(iters=args.iters, lr_alpha=args.lr_alpha, lr_beta=args.lr_beta, decay=args.decay)
+    for _ in range(2):
+        pb_b.optimize(a_b.clone(), b_b.clone(), **opt_b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n_sound):
+        best_b, _ = pb_b.optimize(a_b.clone(), b_b.clone(), **opt_b)
+    torch.cuda.synchronize()
+    ms_l2 = (time.perf_counter() - t0) / n_sound * 1e3
+    l2_ball = {"value": round(pb_b.B / (ms_l2 / 1e3), 1), "unit": "subdomain bounds/s", "ms_per_step": round(ms_l2, 4),
+               "radius": float(wl.eps), "mean_bound": float(best_b.mean().item())}
+    pb_b.close()
+
     # ---- optimised intermediate bounds (each bound over its own alpha',
     # 20 Adam steps): time, how much they narrow the intervals, and what they
     # do to the bound of the batch at the default start
@@ -347,9 +374,8 @@ def main():
     fl_launch = next(s["flops"] / s["launches"] for s in stats if s["name"] == dom["name"])
     by_launch = next(s["bytes"] / s["launches"] for s in stats if s["name"] == dom["name"])
     if fl_launch > 0:
-        # the GEMMs run on the matrix cores; the conv kernels are FP32 FMAs on the
-        # vector ALUs (same FP32 peak: 256 CUs x 4 SIMDs x 64 lanes x 2 flops x 2.4 GHz)
-        bound = "mfma" if dom["name"].startswith(("gemm", "chain")) else "alu"
+        # the dense GEMMs and the conv layers' implicit GEMMs run on the matrix cores
+        bound = "mfma" if dom["name"].startswith(("gemm", "chain", "conv")) else "alu"
         roof = {"bound": bound, "achieved": round(dom["tflops"], 3), "peak": PEAK_FP32_MFMA_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(dom["tflops"] / PEAK_FP32_MFMA_TFLOPS, 4)}
     else:
@@ -359,7 +385,7 @@ def main():
     roof["traffic"] = traffic_for(dom["name"], name)
     roof["algorithmic_bytes_per_launch"] = by_launch
     roof["algorithmic_flops_per_launch"] = fl_launch
-    on_mfma = [s for s in stats if s["name"].startswith(("gemm", "chain"))]
+    on_mfma = [s for s in stats if s["name"].startswith(("gemm", "chain", "conv"))]
     gemm_fl = sum(s["flops"] for s in on_mfma)
     gemm_ms = sum(s["total_ms"] / s["reps"] for s in on_mfma)
     all_ms = sum(s["total_ms"] / s["reps"] for s in stats)
@@ -402,6 +428,7 @@ def main():
                        "ms_per_eval": round(ms_eval, 4)},
         "upper_bound": upper,
         "sound_mode": sound,
+        "l2_ball": l2_ball,
         "branch_and_bound": bab_res,
         "optimised_root_bounds": root_opt,
         "roofline": roof,

@@ -83,7 +83,7 @@ struct DevLayer {
   float* W = nullptr;      // dense [dout, ld_in]; conv OIHW
   float* Wt = nullptr;     // dense [din, ld_out]
   float* bias = nullptr;   // [dout], per neuron
-  int uniform = 0;         // conv: stride-parity classes hold whole waves
+  ConvPlan bwd{}, fwd{};   // conv: back-substitution and forward implicit GEMMs
 };
 
 }  // namespace
@@ -313,12 +313,9 @@ int check_layers(const cv_layer* layers, int n, std::vector<int>& dims, bool all
       if ((ly.in_h + 2 * ly.pad - ly.kernel) / ly.stride + 1 != ly.out_h ||
           (ly.in_w + 2 * ly.pad - ly.kernel) / ly.stride + 1 != ly.out_w)
         return fail(CV_ESHAPE, "layer %d: conv output size does not match", i + 1);
-      if (ly.stride > 2 || ly.in_h % ly.stride || ly.in_w % ly.stride)
-        return fail(CV_ESHAPE, "layer %d: stride must be 1 or 2 and divide the input plane", i + 1);
-      if ((ly.in_h * ly.in_w) % 64 || (ly.out_h * ly.out_w) % 64)
-        return fail(CV_ESHAPE, "layer %d: conv planes must hold a multiple of 64 positions", i + 1);
-      if (!conv_channels_supported(ly.in_c) || !conv_channels_supported(ly.out_c))
-        return fail(CV_ESHAPE, "layer %d: unsupported channel count", i + 1);
+      // the implicit GEMMs' N axes: stride^2 c_in columns (back-substitution), c_out (forward)
+      if (ly.stride > 8 || (int64_t)ly.stride * ly.stride * ly.in_c > 128 || ly.out_c > 128)
+        return fail(CV_ESHAPE, "layer %d: stride^2 * c_in and c_out must be at most 128", i + 1);
       if (i == n - 1 && !allow_conv_last) return fail(CV_ESHAPE, "the last layer must be dense");
     } else if (ly.type != CV_LAYER_DENSE) {
       return fail(CV_ESHAPE, "layer %d: unknown type %d", i + 1, ly.type);
@@ -334,6 +331,128 @@ bool finite_all(const float* p, int64_t n) {
   for (int64_t i = 0; i < n; ++i)
     if (!std::isfinite(p[i])) return false;
   return true;
+}
+
+// ---------------------------------------------------------------------------
+// conv layers as implicit GEMMs (ConvPlan; the kernels are in conv.hip)
+
+constexpr int kFar = -(1 << 20);  // an offset that puts any gather or output outside its plane
+
+struct HostPlan {
+  std::vector<int4> mt, kt, nt;
+  std::vector<float> wm;
+  ConvPlan p{};
+};
+
+// Pad the tables to whole tiles and lay out Wm (value wv(k, n) for k < K,
+// n < N) in MFMA operand order.
+template <class F>
+void plan_pad(HostPlan& o, int M, int K, int N, F wv) {
+  ConvPlan& p = o.p;
+  p.mpad = r16(M);
+  p.kpad = r16(K);  // the kernel takes four K steps of 4 per pass
+  const int tiles = (N + 15) / 16;
+  p.nt = tiles <= 1 ? 1 : tiles <= 2 ? 2 : tiles <= 4 ? 4 : 8;
+  o.mt.resize(p.mpad, make_int4(kFar, kFar, kFar, kFar));
+  o.kt.resize(p.kpad, make_int4(kFar, kFar, 0, 0));
+  o.nt.resize(p.nt * 16, make_int4(0, 0, -1, 0));
+  o.wm.assign((size_t)p.kpad * p.nt * 16, 0.f);
+  for (int ks = 0; ks < p.kpad / 4; ++ks)
+    for (int t = 0; t < p.nt; ++t)
+      for (int l = 0; l < 64; ++l) {
+        const int k = ks * 4 + l / 16, n = t * 16 + l % 16;
+        if (k < K && n < N) o.wm[((size_t)ks * p.nt + t) * 64 + l] = wv(k, n);
+      }
+}
+
+// Back-substitution through conv layer ly (transposed convolution), polyphase
+// form: GEMM rows (Y, X), columns (py, px, ci), K = (co, a, b).
+void plan_convt(const cv_layer& ly, HostPlan& o) {
+  const int s = ly.stride, k = ly.kernel, pad = ly.pad, ci = ly.in_c, hi = ly.in_h, wi = ly.in_w;
+  const int co = ly.out_c, ho = ly.out_h, wo = ly.out_w, am = (k + s - 1) / s;
+  std::vector<int> k0(s), T(s);
+  for (int c = 0; c < s; ++c) {
+    k0[c] = (c + pad) % s;
+    T[c] = (c + pad - k0[c]) / s;
+  }
+  auto range = [&](int n, int& lo, int& up) {
+    lo = INT32_MAX;
+    up = INT32_MIN;
+    for (int y = 0; y < n; ++y) {
+      const int Y = y / s + T[y % s];
+      lo = std::min(lo, Y);
+      up = std::max(up, Y);
+    }
+  };
+  int y0, y1, x0, x1;
+  range(hi, y0, y1);
+  range(wi, x0, x1);
+  const int nX = x1 - x0 + 1, M = (y1 - y0 + 1) * nX, K = co * am * am, N = s * s * ci;
+  plan_pad(o, M, K, N, [&](int kk, int n) {
+    const int c_o = kk / (am * am), a = (kk / am) % am, b = kk % am;
+    const int cls = n / ci, c = n % ci, py = cls / s, px = cls % s;
+    const int ky = k0[py] + s * a, kx = k0[px] + s * b;
+    return ky < k && kx < k ? ly.weight[(((size_t)c_o * ci + c) * k + ky) * k + kx] : 0.f;
+  });
+  for (int m = 0; m < M; ++m) {
+    const int Y = y0 + m / nX, X = x0 + m % nX;
+    o.mt[m] = make_int4(Y, X, Y, X);
+  }
+  for (int kk = 0; kk < K; ++kk)
+    o.kt[kk] = make_int4(-((kk / am) % am), -(kk % am), (kk / (am * am)) * ho * wo, 0);
+  for (int n = 0; n < N; ++n) {
+    const int cls = n / ci, c = n % ci, py = cls / s, px = cls % s;
+    o.nt[n] = make_int4(py - s * T[py], px - s * T[px], c * hi * wi, 0);
+  }
+  ConvPlan& p = o.p;
+  p.gh = ho;
+  p.gw = wo;
+  p.oh = hi;
+  p.ow = wi;
+  p.os = s;
+  p.din = co * ho * wo;
+  p.dout = ci * hi * wi;
+}
+
+// The forward convolution of ly: GEMM rows (oy, ox), K = (ci, ky, kx), N = co.
+void plan_conv(const cv_layer& ly, HostPlan& o) {
+  const int s = ly.stride, k = ly.kernel, pad = ly.pad, ci = ly.in_c, hi = ly.in_h, wi = ly.in_w;
+  const int co = ly.out_c, ho = ly.out_h, wo = ly.out_w;
+  const int M = ho * wo, K = ci * k * k;
+  plan_pad(o, M, K, co, [&](int kk, int n) { return ly.weight[(size_t)n * K + kk]; });
+  for (int m = 0; m < M; ++m) {
+    const int oy = m / wo, ox = m % wo;
+    o.mt[m] = make_int4(oy * s - pad, ox * s - pad, oy, ox);
+  }
+  for (int kk = 0; kk < K; ++kk) o.kt[kk] = make_int4((kk / k) % k, kk % k, (kk / (k * k)) * hi * wi, 0);
+  for (int n = 0; n < co; ++n) o.nt[n] = make_int4(0, 0, n * ho * wo, 0);
+  ConvPlan& p = o.p;
+  p.gh = hi;
+  p.gw = wi;
+  p.oh = ho;
+  p.ow = wo;
+  p.os = 1;
+  p.din = ci * hi * wi;
+  p.dout = co * ho * wo;
+}
+
+int upload_plan(cv_bound* h, HostPlan& o, int mode, ConvPlan& out) {
+  int4 *mt = nullptr, *kt = nullptr, *nt = nullptr;
+  float* wm = nullptr;
+  int rc;
+  if ((rc = h->mem.upload(&mt, o.mt.data(), o.mt.size(), nullptr)) ||
+      (rc = h->mem.upload(&kt, o.kt.data(), o.kt.size(), nullptr)) ||
+      (rc = h->mem.upload(&nt, o.nt.data(), o.nt.size(), nullptr)) ||
+      (rc = h->mem.upload(&wm, o.wm.data(), o.wm.size(), nullptr)))
+    return rc;
+  out = o.p;
+  out.mtab = mt;
+  out.ktab = kt;
+  out.ntab = nt;
+  out.wm = wm;
+  out.smem = conv_plan_smem(out);
+  out.grid = out.smem <= 65536 ? conv_plan_grid(mode, out) : 0;
+  return CV_OK;
 }
 
 // Build the layer copies on the device.
@@ -371,8 +490,13 @@ int upload_layers(cv_bound* h, const cv_layer* layers, int n, hipStream_t s) {
       if (rc) return rc;
       const int pos = ly.out_h * ly.out_w;
       for (int o = 0; o < d.dout; ++o) bias_full[o] = ly.bias[o / pos];
-      d.uniform = ((ly.in_h / ly.stride) * (ly.in_w / ly.stride)) % 64 == 0;
       if (!finite_all(ly.weight, (int64_t)nw)) return fail(CV_EINVAL, "layer %d: non-finite weight", i + 1);
+      HostPlan pb, pf;
+      plan_convt(ly, pb);
+      plan_conv(ly, pf);
+      if ((rc = upload_plan(h, pb, i == 0 ? kBwdConc : kBwdRelax, d.bwd)) ||
+          (rc = upload_plan(h, pf, i == 0 ? kFwdX : kFwd, d.fwd)))
+        return rc;
     }
     if (ly.type == CV_LAYER_DENSE && !finite_all(ly.weight, (int64_t)d.dout * d.din))
       return fail(CV_EINVAL, "layer %d: non-finite weight", i + 1);
@@ -585,12 +709,12 @@ int build(cv_bound* h, const cv_layer* layers, int n_layers, int P, const float*
     // faster at ~10^4 rows), cv_bound_autotune / cv_bound_set_plan choose
     if (!plan_chain(h)) h->chain_lo = 0;
   }
-  // conv kernels' LDS needs
+  // conv kernels' LDS needs: weight matrix, tables, an input and an output row
   for (int i = 0; i + 1 < n_layers; ++i) {
     const DevLayer& ly = h->layers[i];
     if (ly.type != CV_LAYER_CONV2D) continue;
-    if (convt_smem_bytes(ly.g, h->w64, i == 0) > 65536 || conv_smem_bytes(ly.g) > 65536)
-      return fail(CV_ESHAPE, "layer %d: conv rows do not fit in LDS", i + 1);
+    if (ly.bwd.smem > 65536 || ly.fwd.smem > 65536)
+      return fail(CV_ESHAPE, "layer %d: conv rows and weights do not fit in LDS", i + 1);
   }
   HIPCHK(hipStreamSynchronize(s));
   return CV_OK;
@@ -727,8 +851,9 @@ int prepare_sound(cv_bound* h, const cv_layer* layers, const float* x_lo, const 
   auto gam = [&](double n) { return n * up / (1.0 - n * up); };
   // longest addition chain: final sum over slots (and its four-way merge),
   // plus the longest in-kernel chain (GEMM tiles: a few; top layer: two per
-  // 64 neurons per lane; transposed convolutions: two per input channel per
-  // position a thread owns) and the reduction trees (at most 64 levels)
+  // 64 neurons per lane; transposed convolutions: two per 256 outputs of a
+  // row, bounded by two per input channel per 256 positions) and the
+  // reduction trees (at most 64 levels)
   int chain = 0;
   if (L >= 2) chain = std::max(chain, 2 * ((h->dims[L - 1] + 63) / 64));
   for (int i = 1; i < L; ++i) {
@@ -748,12 +873,11 @@ int prepare_sound(cv_bound* h, const cv_layer* layers, const float* x_lo, const 
       const cv_layer& ly = layers[i - 1];
       const int d = h->dims[i];
       const int per = ly.type == CV_LAYER_DENSE ? 1 : ly.out_h * ly.out_w;
-      // terms per output of the back-substitution product: all d_i neurons
-      // for a dense layer (matrix cores: u'); for a transposed convolution
-      // the taps of one stride-parity class, at most c_out ceil(k/s)^2
-      // (vector FMAs, one round-to-nearest each: u = u'/2)
+      // terms per output of the back-substitution product, all on the matrix
+      // cores (u'): all d_i neurons for a dense layer; for a transposed
+      // convolution the K axis of its polyphase GEMM, c_out ceil(k/s)^2
       const int ks = (ly.kernel + ly.stride - 1) / std::max(1, ly.stride);
-      const double gk = ly.type == CV_LAYER_DENSE ? gam(d) : gam(0.5 * ly.out_c * ks * ks);
+      const double gk = ly.type == CV_LAYER_DENSE ? gam(d) : gam((double)ly.out_c * ks * ks);
       std::vector<double> v(d, 0.0), hn(d);
       abs_weighted(ly, hm, v);
       for (int k = 0; k < d; ++k) {
@@ -966,7 +1090,7 @@ int enqueue_bwd(cv_bound* h, const float* alpha, const float* beta, bool grad, f
       if (pf) pf->end();
       slot += (N + kGemmCfgs[c].bn - 1) / kGemmCfgs[c].bn;
     } else {
-      ConvArgs a{h->act[cur], h->ldact, ly.W, ly.g, h->R, 0, ly.uniform, h->bt, v, e};
+      ConvArgs a{h->act[cur], h->ldact, ly.bwd, h->R, 0, h->bt, v, e};
       if (pf) pf->begin(std::string(mode == kBwdRelax ? "convt_bwd_relax_ci" : "convt_bwd_conc_ci") +
                             std::to_string(ly.g.ci),
                         2.0 * rows * conv_macs(ly.g), io);
@@ -1076,7 +1200,7 @@ int enqueue_fwd(cv_bound* h, const float* alpha, const float* beta, float* ga, f
       launch_gemm(c, e.top_out ? kFwdTop : mode, g, s);
       if (pf) pf->end();
     } else {
-      ConvArgs a{in, lda, ly.W, ly.g, h->R, last, ly.uniform, h->bt, v, e};
+      ConvArgs a{in, lda, ly.fwd, h->R, last, h->bt, v, e};
       if (pf) pf->begin(std::string(mode == kFwdX ? "conv_fwd_x_co" : "conv_fwd_co") + std::to_string(ly.g.co),
                         2.0 * rows * conv_macs(ly.g), io);
       if (launch_conv_fwd(mode, a, s)) return fail(CV_ESHAPE, "unsupported conv channels");
@@ -1524,7 +1648,7 @@ int enqueue_true_fwd(cv_bound* h, float* ub, int32_t* sat, hipStream_t s) {
       GemmArgs g{in, lda, ly.W, ly.ld_in, h->R, N, K, 0, h->bt, v, e};
       launch_gemm(c, mode, g, s);
     } else {
-      ConvArgs a{in, lda, ly.W, ly.g, h->R, 0, ly.uniform, h->bt, v, e};
+      ConvArgs a{in, lda, ly.fwd, h->R, 0, h->bt, v, e};
       if (launch_conv_fwd(mode, a, s)) return fail(CV_ESHAPE, "unsupported conv channels");
     }
   }

@@ -1,16 +1,28 @@
 // Back-substitution through convolution layers and the adjoint's forward
-// convolution (gfx950).
+// convolution, as implicit GEMMs on the matrix cores (gfx950, FP32 MFMA
+// 16x16x4).
 //
-// Back-substitution A(i-1) = Lambda(i) W(i) through a conv layer is the
-// transposed convolution of each row of Lambda(i) with the layer's kernel.
-// It is computed as an implicit GEMM per output position: for an output
-// (c_in, y, x) the K dimension runs over (c_out, valid taps), where for
-// stride s the valid taps are those with ky = (y + pad) mod s (+ s, ...), so
-// the positions are processed in stride-parity classes and every lane of a
-// wave shares the same taps and the same weights.  Each thread keeps all
-// C_in outputs of one position in registers, so an LDS read of Lambda feeds
-// C_in FMAs.  The adjoint's forward conv keeps all C_out outputs of one
-// position in registers likewise.
+// Each batch row is one GEMM D[m, n] = sum_k G[m, k] Wm[k, n] (ConvPlan):
+//  * transposed convolution, A(i-1) = Lambda(i) W(i) (Theorem 3.1 through a
+//    conv layer), in polyphase form.  With stride s, an output (y, x) =
+//    (s yy + py, s xx + px) of stride-parity class (py, px) takes the taps
+//    ky = ky0(py) + s a, kx = kx0(px) + s b, and the Lambda entries they
+//    meet sit at (Y - a, X - b) with Y = yy + T(py), X = xx + T(px).  The
+//    GEMM rows are indexed by (Y, X), so every class reads the same Lambda
+//    window: the s^2 classes and the c_in channels share the N axis
+//    (s^2 c_in columns), K runs over (c_out, a, b), and Wm[(co, a, b),
+//    (py, px, ci)] = W[co, ci, ky0(py) + s a, kx0(px) + s b] (0 past the
+//    kernel).
+//  * forward convolution (the adjoint's step, and the network itself for
+//    the upper bound): rows (oy, ox), K = (c_in, ky, kx) as im2col, N = c_out.
+// G is gathered from the row's input staged in LDS through per-row and
+// per-column offset tables; a tap outside the plane reads a zero slot, so
+// the zero padding is exact.  The results are scattered into an LDS copy of
+// the output row (each output position has exactly one (m, n)), and the
+// layer's epilogue (relaxation, concretisation, adjoint step) then walks the
+// row in natural order with coalesced global traffic.  Workgroups are
+// persistent over rows, so the weight matrix and tables are loaded into LDS
+// once per workgroup.
 #include "common.h"
 #include "internal.h"
 
@@ -18,277 +30,332 @@ namespace cvb {
 
 namespace {
 
-// Row slice of the block: RB rows per block, positions per row `pos`, 256 threads.
-struct Slice {
-  int rb;     // rows per block
-  int row0;   // first row of the block
-  int rl;     // this thread's row (local)
-  int q0;     // this thread's first position
-  int qstep;  // position stride
-};
+typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ Slice slice_of(int pos) {
-  Slice s;
-  s.rb = pos >= 256 ? 1 : 256 / pos;
-  s.row0 = blockIdx.x * s.rb;
-  if (s.rb == 1) {
-    s.rl = 0;
-    s.q0 = threadIdx.x;
-    s.qstep = 256;
-  } else {
-    s.rl = threadIdx.x / pos;
-    s.q0 = threadIdx.x - s.rl * pos;
-    s.qstep = pos;
-  }
-  return s;
-}
+constexpr int kPF = 4;  // per thread and row: input floats and output records loaded ahead
+constexpr int kEU = 4;  // outputs per thread whose second-level operands are gathered together
 
-// Sum `x` over the threads of each local row and return the total to thread 0
-// of that row (rows own whole waves since pos is a multiple of 64).
-__device__ __forceinline__ float row_sum(float x, int pos, float* red) {
+// Sum of x over the block (256 threads), returned to thread 0.
+__device__ __forceinline__ float block_sum(float x, float* red) {
   x = wave_sum(x);
-  const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) red[w] = x;
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
   __syncthreads();
-  float s = 0.f;
-  const int wpr = pos >= 256 ? 4 : pos / 64;  // waves per row
-  if (threadIdx.x < 4 && threadIdx.x < 256 / (wpr * 64)) {
-    for (int t = 0; t < wpr; ++t) s += red[threadIdx.x * wpr + t];
-  }
-  return s;
+  return threadIdx.x == 0 ? (red[0] + red[1]) + (red[2] + red[3]) : 0.f;
 }
 
-template <int CI, int MODE>
-__global__ __launch_bounds__(256) void convt_bwd(const float* __restrict__ lam, int ldl, const float* __restrict__ w,
-                                                 ConvGeom g, int M, int uniform, Batch bt, Vars v, Epi e) {
-  extern __shared__ float smem[];
-  __shared__ float red[4], rede[4];
-  const int pos = g.hi * g.wi;             // positions of the output plane
-  const int din = g.co * g.ho * g.wo;      // length of a Lambda row
-  const Slice sl = slice_of(pos);
-  float* lrow = smem;                                   // [rb][din]
-  const int w32 = bt.w64 * 2;
-  uint32_t* bits_all = reinterpret_cast<uint32_t*>(smem + sl.rb * din);  // [rb][2][w32] (conc mode)
-  for (int t = threadIdx.x; t < sl.rb * din; t += 256) {
-    const int rr = t / din, jj = t - rr * din;
-    const int row = sl.row0 + rr;
-    lrow[t] = row < M ? lam[(int64_t)row * ldl + jj] : 0.f;
+// First-level epilogue operands of outputs j = j0 + tid + 256 u of a row:
+// the status records (relaxation, adjoint), or the box / ball centre of the
+// row's property (concretisation).  Independent of the GEMM, so they are
+// loaded while it runs.
+template <int MODE>
+__device__ __forceinline__ void epi_first(const Batch& bt, const Epi& e, int row, int p, int j0, int dout,
+                                          uint32_t (&rec)[kPF], float (&b1)[kPF], float (&b2)[kPF]) {
+  const uint32_t* st = bt.status + (int64_t)(row / bt.m) * bt.nd + e.layer_off;
+#pragma unroll
+  for (int u = 0; u < kPF; ++u) {
+    const int jc = min(j0 + (int)threadIdx.x + 256 * u, dout - 1);
+    rec[u] = kInactive;
+    b1[u] = b2[u] = 0.f;
+    if (MODE == kBwdConc) {  // (b2 unused over an l2 ball)
+      const int64_t pb = (int64_t)p * bt.d0 + jc;
+      b1[u] = (bt.l2x0 ? bt.l2x0 : bt.xlo)[pb];
+      b2[u] = bt.xhi[pb];
+    } else {
+      rec[u] = st[jc];
+    }
   }
-  if (MODE == kBwdConc && v.xpos)
-    for (int t = threadIdx.x; t < sl.rb * 2 * w32; t += 256) bits_all[t] = 0u;
-  __syncthreads();
-  uint32_t* bits = bits_all + sl.rl * 2 * w32;
+}
 
-  const int row = sl.row0 + sl.rl;
-  const bool rok = row < M;
-  RowInfo ri;
-  if (rok) ri = row_info(bt, row);
-  const float* L = lrow + sl.rl * din;
-  const int s = g.s, k = g.k, pad = g.p;
-  const int hs = g.hi / s, ws = g.wi / s, cls_n = hs * ws;
-  float cst = 0.f, cer = 0.f;
-  for (int q = sl.q0; q < pos; q += sl.qstep) {
-    // position q in parity-class order
-    int cls = q / cls_n;
-    const int e0 = q - cls * cls_n;
-    const int yy = e0 / ws, xx = e0 - yy * ws;
-    if (uniform) cls = __builtin_amdgcn_readfirstlane(cls);
-    const int py = cls / s, px = cls - (cls / s) * s;
-    const int y = yy * s + py, x = xx * s + px;
-    const int ky0 = (py + pad) % s, kx0 = (px + pad) % s;
-    float acc[CI];
+// Input floats t = t0 + tid + 256 u of a row: the row of zin, or for a conv
+// first layer's adjoint step the box (x* then takes the sign planes too).
+template <int MODE>
+__device__ __forceinline__ void in_load(const float* zin, int ldi, const Batch& bt, int row, int t0, int din,
+                                        float (&s1)[kPF], float (&s2)[kPF]) {
+  const int p = MODE == kFwdX ? bt.prop[row / bt.m] : 0;
 #pragma unroll
-    for (int c = 0; c < CI; ++c) acc[c] = 0.f;
-    for (int co = 0; co < g.co; ++co) {
-      for (int ky = ky0; ky < k; ky += s) {
-        const int oy = (y + pad - ky) / s;
-        if (oy < 0 || oy >= g.ho) continue;
-        for (int kx = kx0; kx < k; kx += s) {
-          const int ox = (x + pad - kx) / s;
-          if (ox < 0 || ox >= g.wo) continue;
-          const float val = L[(co * g.ho + oy) * g.wo + ox];
-          const float* wp = w + ((int64_t)co * CI * k + ky) * k + kx;
+  for (int u = 0; u < kPF; ++u) {
+    const int tc = min(t0 + (int)threadIdx.x + 256 * u, din - 1);
+    if (MODE == kFwdX) {
+      s1[u] = bt.xlo[(int64_t)p * bt.d0 + tc];
+      s2[u] = bt.xhi[(int64_t)p * bt.d0 + tc];
+    } else {
+      s1[u] = zin[(int64_t)row * ldi + tc];
+      s2[u] = 0.f;
+    }
+  }
+}
+
+template <int MODE>
+__device__ __forceinline__ void in_store(float* zi, const Batch& bt, const Vars& v, int row, int t0, int din,
+                                         const float (&s1)[kPF], const float (&s2)[kPF]) {
+  if (MODE == kFwdX) {
+    uint64_t wp[kPF], wn[kPF];
 #pragma unroll
-          for (int c = 0; c < CI; ++c) acc[c] = fmaf(val, wp[(int64_t)c * k * k], acc[c]);
+    for (int u = 0; u < kPF; ++u) {
+      const int tc = min(t0 + (int)threadIdx.x + 256 * u, din - 1);
+      wp[u] = v.xpos[(int64_t)row * bt.w64 + (tc >> 6)];
+      wn[u] = v.xneg[(int64_t)row * bt.w64 + (tc >> 6)];
+    }
+#pragma unroll
+    for (int u = 0; u < kPF; ++u) {
+      const int t = t0 + (int)threadIdx.x + 256 * u;
+      if (t < din) zi[t] = xstar((wp[u] >> (t & 63)) & 1, (wn[u] >> (t & 63)) & 1, s1[u], s2[u]);
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < kPF; ++u) {
+      const int t = t0 + (int)threadIdx.x + 256 * u;
+      if (t < din) zi[t] = s1[u];
+    }
+  }
+}
+
+template <int MODE, int NT>
+__global__ __launch_bounds__(256) void conv_mm(const float* __restrict__ zin, int ldi, ConvPlan pl, int M, int last,
+                                               Batch bt, Vars v, Epi e) {
+  extern __shared__ float4 smem4[];
+  __shared__ float red[2][4];
+  constexpr bool kBwd = MODE == kBwdRelax || MODE == kBwdConc;
+  float* const wm = reinterpret_cast<float*>(smem4);
+  const int nwm = pl.kpad * NT * 16;  // floats
+  int4* const mt = reinterpret_cast<int4*>(wm + nwm);
+  int4* const kt = mt + pl.mpad;
+  int4* const ntb = kt + pl.kpad;
+  float* const zi = reinterpret_cast<float*>(ntb + NT * 16);
+  float* const zo = zi + ((pl.din + 4) & ~3);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+  for (int t = tid; t < nwm / 4; t += 256) smem4[t] = reinterpret_cast<const float4*>(pl.wm)[t];
+  for (int t = tid; t < pl.mpad; t += 256) mt[t] = pl.mtab[t];
+  for (int t = tid; t < pl.kpad; t += 256) kt[t] = pl.ktab[t];
+  for (int t = tid; t < NT * 16; t += 256) ntb[t] = pl.ntab[t];
+  if (tid == 0) zi[pl.din] = 0.f;  // the zero slot of out-of-plane taps
+
+  // the first row's input; later rows' inputs are loaded during the previous
+  // row's GEMM and stored after its epilogue
+  float s1[kPF], s2[kPF];
+  int row = blockIdx.x;
+  if (row < M)
+    for (int t0 = 0; t0 < pl.din; t0 += 256 * kPF) {
+      in_load<MODE>(zin, ldi, bt, row, t0, pl.din, s1, s2);
+      in_store<MODE>(zi, bt, v, row, t0, pl.din, s1, s2);
+    }
+  __syncthreads();
+
+  const int n_ks = pl.kpad >> 2, n_mt = pl.mpad >> 4;
+  const float* const wl = wm + lane;
+  for (; row < M; row += gridDim.x) {
+    const int nrow = row + gridDim.x;
+    const int p = bt.prop[row / bt.m];
+    uint32_t rec[kPF];
+    float b1[kPF], b2[kPF];
+    epi_first<MODE>(bt, e, row, p, 0, pl.dout, rec, b1, b2);
+    if (nrow < M) in_load<MODE>(zin, ldi, bt, nrow, 0, pl.din, s1, s2);
+
+    // ---- the GEMM: one 16-row tile of m per wave at a time, all N tiles
+    for (int mtile = wave; mtile < n_mt; mtile += 4) {
+      const int4 me = mt[mtile * 16 + (lane & 15)];
+      floatx4 acc[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+      // four K steps per pass (kpad is a multiple of 16): their table reads,
+      // gathers and weight reads are issued before the MFMAs that use them
+      for (int ks0 = 0; ks0 < n_ks; ks0 += 4) {
+        int4 ke[4];
+        float a[4], b[4][NT];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ke[q] = kt[(ks0 + q) * 4 + (lane >> 4)];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int t = 0; t < NT; ++t) b[q][t] = wl[((ks0 + q) * NT + t) * 64];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int yy = me.x + ke[q].x, xx = me.y + ke[q].y;
+          const bool ok = (unsigned)yy < (unsigned)pl.gh && (unsigned)xx < (unsigned)pl.gw;
+          a[q] = zi[ok ? ke[q].z + yy * pl.gw + xx : pl.din];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q], b[q][t], acc[t], 0, 0, 0);
+      }
+      // lane holds rows 4 (lane / 16) + r of the tile, column lane % 16
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int4 ne = ntb[t * 16 + (lane & 15)];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int4 mo = mt[mtile * 16 + 4 * (lane >> 4) + r];
+          const int y = pl.os * mo.z + ne.x, x = pl.os * mo.w + ne.y;
+          if (ne.z >= 0 && (unsigned)y < (unsigned)pl.oh && (unsigned)x < (unsigned)pl.ow)
+            zo[ne.z + y * pl.ow + x] = acc[t][r];
         }
       }
     }
-    if (!rok) continue;
-#pragma unroll
-    for (int c = 0; c < CI; ++c) {
-      const int j = c * pos + y * g.wi + x;
-      const float a = acc[c];
-      if (MODE == kBwdRelax) {
-        e.out[(int64_t)row * e.ldo + j] = relax_bwd(bt, v, ri, e.layer_off, j, a, e.bias[j], &cst, &cer);
-      } else if (bt.l2x0) {  // l2 ball: A(0) x0 here, - eps ||A(0)||_2 in the final sum
-        const int64_t pb = (int64_t)ri.p * bt.d0 + j;
-        cst = fmaf(a, bt.l2x0[pb], cst);
-        cer = fmaf(a, a, cer);
-        if (v.xdense) v.xdense[(int64_t)row * v.ldx + j] = a;  // A(0) itself for the adjoint
-      } else {
-        const int64_t pb = (int64_t)ri.p * bt.d0 + j;
-        const float tm = conc_term(a, bt.xlo[pb], bt.xhi[pb]);
-        cst += tm;
-        cer = fmaf(bt.sg, fabsf(tm), cer);
-        if (v.xpos) {
-          if (a > 0.f) atomicOr(&bits[j >> 5], 1u << (j & 31));
-          if (a < 0.f) atomicOr(&bits[w32 + (j >> 5)], 1u << (j & 31));
-        }
-      }
-    }
-  }
-  const float tot = row_sum(cst, pos, red);
-  if (threadIdx.x < sl.rb) {
-    const int r2 = sl.row0 + threadIdx.x;
-    if (r2 < M) e.part[(int64_t)e.slot0 * M + r2] = tot;
-  }
-  float* const p2 = e.perr ? e.perr : e.psq;  // rounding-error bound, or the sum of A(0)^2 (l2 ball)
-  if (p2) {
-    const float ter = row_sum(cer, pos, rede);
-    if (threadIdx.x < sl.rb) {
-      const int r2 = sl.row0 + threadIdx.x;
-      if (r2 < M) p2[(int64_t)e.slot0 * M + r2] = ter;
-    }
-  }
-  if (MODE == kBwdConc && v.xpos) {
     __syncthreads();
-    for (int t = threadIdx.x; t < sl.rb * w32; t += 256) {
-      const int rr = t / w32, wd = t - rr * w32;
-      const int r2 = sl.row0 + rr;
-      if (r2 < M) {
-        reinterpret_cast<uint32_t*>(v.xpos + (int64_t)r2 * bt.w64)[wd] = bits_all[rr * 2 * w32 + wd];
-        reinterpret_cast<uint32_t*>(v.xneg + (int64_t)r2 * bt.w64)[wd] = bits_all[rr * 2 * w32 + w32 + wd];
-      }
-    }
-  }
-}
 
-template <int CO, int MODE>
-__global__ __launch_bounds__(256) void conv_fwd(const float* __restrict__ zin, int ldi, const float* __restrict__ w,
-                                                ConvGeom g, int M, int last, Batch bt, Vars v, Epi e) {
-  extern __shared__ float smem[];
-  const int pos = g.ho * g.wo;
-  const int din = g.ci * g.hi * g.wi;
-  const Slice sl = slice_of(pos);
-  for (int t = threadIdx.x; t < sl.rb * din; t += 256) {
-    const int rr = t / din, jj = t - rr * din;
-    const int row = sl.row0 + rr;
-    float val = 0.f;
-    if (row < M) {
-      if (MODE == kFwdX) {
-        const int p = bt.prop[row / bt.m];
-        const uint64_t wp = v.xpos[(int64_t)row * bt.w64 + (jj >> 6)];
-        const uint64_t wn = v.xneg[(int64_t)row * bt.w64 + (jj >> 6)];
-        const int64_t pb = (int64_t)p * bt.d0 + jj;
-        val = xstar((wp >> (jj & 63)) & 1, (wn >> (jj & 63)) & 1, bt.xlo[pb], bt.xhi[pb]);
-      } else {
-        val = zin[(int64_t)row * ldi + jj];
-      }
-    }
-    smem[t] = val;
-  }
-  __syncthreads();
-  const int row = sl.row0 + sl.rl;
-  if (row >= M) return;
-  const RowInfo ri = row_info(bt, row);
-  const float* Z = smem + sl.rl * din;
-  const int s = g.s, k = g.k, pad = g.p;
-  for (int q = sl.q0; q < pos; q += sl.qstep) {
-    const int oy = q / g.wo, ox = q - oy * g.wo;
-    float acc[CO];
+    // ---- epilogue over the output row in natural order: first-level
+    // operands for 256 kPF outputs at a time (the first chunk's were loaded
+    // ahead), then kEU outputs per thread of second-level gathers
+    const RowInfo ri = row_info(bt, row);
+    const int64_t pc0 = (int64_t)p * bt.nd + e.layer_off;
+    float cst = 0.f, cer = 0.f;
+    for (int j0 = 0; j0 < pl.dout; j0 += 256 * kPF) {
+      if (j0 > 0) epi_first<MODE>(bt, e, row, p, j0, pl.dout, rec, b1, b2);
 #pragma unroll
-    for (int c = 0; c < CO; ++c) acc[c] = 0.f;
-    for (int ci = 0; ci < g.ci; ++ci) {
-      for (int ky = 0; ky < k; ++ky) {
-        const int iy = oy * s - pad + ky;
-        if (iy < 0 || iy >= g.hi) continue;
-        for (int kx = 0; kx < k; ++kx) {
-          const int ix = ox * s - pad + kx;
-          if (ix < 0 || ix >= g.wi) continue;
-          const float val = Z[(ci * g.hi + iy) * g.wi + ix];
-          const float* wp = w + ((int64_t)ci * k + ky) * k + kx;
+      for (int h = 0; h < kPF; h += kEU) {
+        float a[kEU], al[kEU], be[kEU], sw[kEU], bias[kEU];
+        float2 ch[kEU];
 #pragma unroll
-          for (int c = 0; c < CO; ++c) acc[c] = fmaf(val, wp[(int64_t)c * g.ci * k * k], acc[c]);
+        for (int u = 0; u < kEU; ++u) {
+          const int j = j0 + tid + 256 * (h + u);
+          const int jc = min(j, pl.dout - 1);
+          const uint32_t r = rec[h + u];
+          a[u] = zo[jc];
+          ch[u] = make_float2(0.f, 0.f);
+          al[u] = be[u] = sw[u] = bias[u] = 0.f;
+          if (MODE == kBwdConc) continue;
+          // l2 ball, first layer: W(1) x* + b(1) = (W(1) x0 + b(1)) - l2s (W(1) A(0))
+          bias[u] = !kBwd && e.wx0 ? e.wx0[(int64_t)p * e.n + jc] : e.bias[jc];
+          if (!kBwd && v.sat) continue;
+          if ((r & kKindMask) == kUnstable) ch[u] = bt.chord[pc0 + jc];
+          if (MODE == kBwdRelax) {
+            relax_vars(bt, v, ri, r, pc0 + jc, &al[u], &be[u]);
+            if (bt.sw) sw[u] = bt.sw[pc0 + jc];
+          } else if ((r & kKindMask) == kUnstable) {
+            const int64_t ai = ri.abase + (r & kCidxMask);
+            be[u] = v.acomp[ai];  // the stored A(i)_j
+            al[u] = v.alpha ? v.alpha[ai] : bt.adef[pc0 + jc];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kEU; ++u) {
+          const int j = j0 + tid + 256 * (h + u);
+          const bool ok = j < pl.dout;
+          const uint32_t r = rec[h + u];
+          if (MODE == kBwdRelax) {
+            if (!ok) continue;
+            if (v.acomp && (r & kKindMask) == kUnstable) v.acomp[ri.abase + (r & kCidxMask)] = a[u];
+            const float lam = relax_value(bt, v, ri, r, ch[u], relax_pick(r, al[u], be[u]), a[u], bias[u], &cst);
+            e.out[(int64_t)row * e.ldo + j] = lam;
+            cer = fmaf(fabsf(lam), sw[u], cer);
+          } else if (MODE == kBwdConc) {
+            if (bt.l2x0) {  // l2 ball: A(0) x0 here, - eps ||A(0)||_2 in the final sum
+              if (!ok) continue;
+              cst = fmaf(a[u], b1[h + u], cst);
+              cer = fmaf(a[u], a[u], cer);
+              if (v.xdense) v.xdense[(int64_t)row * v.ldx + j] = a[u];  // A(0) itself for the adjoint
+              continue;
+            }
+            if (ok) {
+              const float tm = conc_term(a[u], b1[h + u], b2[h + u]);
+              cst += tm;
+              cer = fmaf(bt.sg, fabsf(tm), cer);
+            }
+            if (v.xpos) {  // x* as sign planes: one 64-bit word per wave
+              const uint64_t bp = __ballot(ok && a[u] > 0.f), bn = __ballot(ok && a[u] < 0.f);
+              const int w0 = j0 + 256 * (h + u) + wave * 64;
+              if (lane == 0 && w0 < pl.dout) {
+                v.xpos[(int64_t)row * bt.w64 + (w0 >> 6)] = bp;
+                v.xneg[(int64_t)row * bt.w64 + (w0 >> 6)] = bn;
+              }
+            }
+          } else {
+            if (!ok) continue;
+            const float zb = e.wx0 ? fmaf(-v.l2s[row], a[u], bias[u]) : a[u] + bias[u];
+            if (v.sat) {  // the network itself at x*: every layer's output is kept
+              e.out[(int64_t)row * e.ldo + j] = true_relu(r, zb, v.sat + row);
+              continue;
+            }
+            const float zh = relax_fwd_value(bt, v, ri, r, ch[u], be[u], al[u], pc0 + j, zb);
+            if (!last) e.out[(int64_t)row * e.ldo + j] = zh;
+          }
         }
       }
     }
-#pragma unroll
-    for (int c = 0; c < CO; ++c) {
-      const int j = c * pos + q;
-      // l2 ball, first layer: W(1) x* + b(1) = (W(1) x0 + b(1)) - l2s (W(1) A(0))
-      const float zb = e.wx0 ? fmaf(-v.l2s[row], acc[c], e.wx0[(int64_t)ri.p * e.n + j]) : acc[c] + e.bias[j];
-      if (v.sat) {  // the network itself at x*: every layer's output is kept
-        const uint32_t rec = bt.status[(int64_t)ri.b * bt.nd + e.layer_off + j];
-        e.out[(int64_t)row * e.ldo + j] = true_relu(rec, zb, v.sat + row);
-        continue;
+    if (kBwd) {
+      const float tot = block_sum(cst, red[0]);
+      if (tid == 0) e.part[(int64_t)e.slot0 * M + row] = tot;
+      float* const p2 = e.perr ? e.perr : e.psq;  // rounding-error bound, or the sum of A(0)^2 (l2 ball)
+      if (p2) {
+        const float ter = block_sum(cer, red[1]);
+        if (tid == 0) p2[(int64_t)e.slot0 * M + row] = ter;
       }
-      const float zh = relax_fwd(bt, v, ri, e.layer_off, j, zb);
-      if (!last) e.out[(int64_t)row * e.ldo + j] = zh;
     }
+    // the next row's input (every wave is past this row's GEMM)
+    if (nrow < M) {
+      in_store<MODE>(zi, bt, v, nrow, 0, pl.din, s1, s2);
+      for (int t0 = 256 * kPF; t0 < pl.din; t0 += 256 * kPF) {
+        in_load<MODE>(zin, ldi, bt, nrow, t0, pl.din, s1, s2);
+        in_store<MODE>(zi, bt, v, nrow, t0, pl.din, s1, s2);
+      }
+    }
+    __syncthreads();
   }
 }
 
 template <int MODE>
-int convt_dispatch(const ConvArgs& a, hipStream_t st) {
-  const int pos = a.g.hi * a.g.wi;
-  const int rb = pos >= 256 ? 1 : 256 / pos;
-  const int din = a.g.co * a.g.ho * a.g.wo;
-  size_t sm = (size_t)rb * din * sizeof(float);
-  if (MODE == kBwdConc) sm += (size_t)rb * 4 * a.bt.w64 * sizeof(uint32_t);
-  const dim3 grid((a.M + rb - 1) / rb), block(256);
-#define CVB_CT(CI)                                                                                         \
-  case CI:                                                                                                 \
-    launch_k(convt_bwd<CI, MODE>, grid, block, sm, st, a.in, a.ldi, a.w, a.g, a.M, a.uniform, a.bt, a.v, a.e); \
-    return 0;
-  switch (a.g.ci) {
-    CVB_CT(1) CVB_CT(2) CVB_CT(3) CVB_CT(4) CVB_CT(8) CVB_CT(16) CVB_CT(32)
-    default:
-      return -1;
+const void* kernel_nt(int nt) {
+  switch (nt) {
+    case 1: return reinterpret_cast<const void*>(conv_mm<MODE, 1>);
+    case 2: return reinterpret_cast<const void*>(conv_mm<MODE, 2>);
+    case 4: return reinterpret_cast<const void*>(conv_mm<MODE, 4>);
+    case 8: return reinterpret_cast<const void*>(conv_mm<MODE, 8>);
+    default: return nullptr;
   }
-#undef CVB_CT
+}
+
+const void* kernel_for(int mode, int nt) {
+  switch (mode) {
+    case kBwdRelax: return kernel_nt<kBwdRelax>(nt);
+    case kBwdConc: return kernel_nt<kBwdConc>(nt);
+    case kFwdX: return kernel_nt<kFwdX>(nt);
+    default: return kernel_nt<kFwd>(nt);
+  }
 }
 
 template <int MODE>
-int conv_dispatch(const ConvArgs& a, hipStream_t st) {
-  const int pos = a.g.ho * a.g.wo;
-  const int rb = pos >= 256 ? 1 : 256 / pos;
-  const int din = a.g.ci * a.g.hi * a.g.wi;
-  const size_t sm = (size_t)rb * din * sizeof(float);
-  const dim3 grid((a.M + rb - 1) / rb), block(256);
-#define CVB_CF(CO)                                                                                      \
-  case CO:                                                                                              \
-    launch_k(conv_fwd<CO, MODE>, grid, block, sm, st, a.in, a.ldi, a.w, a.g, a.M, a.last, a.bt, a.v, a.e); \
+int dispatch(const ConvArgs& a, hipStream_t st) {
+  if (a.M <= 0) return 0;
+  const dim3 grid(std::min(a.M, std::max(1, a.pl.grid))), block(256);
+#define CVB_CM(NT)                                                                                            \
+  case NT:                                                                                                    \
+    launch_k(conv_mm<MODE, NT>, grid, block, a.pl.smem, st, a.in, a.ldi, a.pl, a.M, a.last, a.bt, a.v, a.e); \
     return 0;
-  switch (a.g.co) {
-    CVB_CF(1) CVB_CF(2) CVB_CF(3) CVB_CF(4) CVB_CF(8) CVB_CF(16) CVB_CF(32)
+  switch (a.pl.nt) {
+    CVB_CM(1) CVB_CM(2) CVB_CM(4) CVB_CM(8)
     default:
       return -1;
   }
-#undef CVB_CF
+#undef CVB_CM
 }
 
 }  // namespace
 
-bool conv_channels_supported(int c) { return c == 1 || c == 2 || c == 3 || c == 4 || c == 8 || c == 16 || c == 32; }
-
-size_t convt_smem_bytes(const ConvGeom& g, int w64, bool conc) {
-  const int pos = g.hi * g.wi;
-  const int rb = pos >= 256 ? 1 : 256 / pos;
-  return (size_t)rb * g.co * g.ho * g.wo * sizeof(float) + (conc ? (size_t)rb * 4 * w64 * sizeof(uint32_t) : 0);
+int conv_plan_smem(const ConvPlan& pl) {
+  return (pl.kpad * pl.nt * 16 + ((pl.din + 4) & ~3) + pl.dout) * (int)sizeof(float) +
+         (pl.mpad + pl.kpad + pl.nt * 16) * (int)sizeof(int4);
 }
 
-size_t conv_smem_bytes(const ConvGeom& g) {
-  const int pos = g.ho * g.wo;
-  const int rb = pos >= 256 ? 1 : 256 / pos;
-  return (size_t)rb * g.ci * g.hi * g.wi * sizeof(float);
+int conv_plan_grid(int mode, const ConvPlan& pl) {
+  const void* k = kernel_for(mode, pl.nt);
+  int dev = 0, cus = 0, per = 0;
+  if (!k || hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, 256, pl.smem) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return cus * per;
 }
 
 int launch_convt_bwd(int mode, const ConvArgs& a, hipStream_t s) {
-  return mode == kBwdConc ? convt_dispatch<kBwdConc>(a, s) : convt_dispatch<kBwdRelax>(a, s);
+  return mode == kBwdConc ? dispatch<kBwdConc>(a, s) : dispatch<kBwdRelax>(a, s);
 }
 
 int launch_conv_fwd(int mode, const ConvArgs& a, hipStream_t s) {
-  return mode == kFwdX ? conv_dispatch<kFwdX>(a, s) : conv_dispatch<kFwd>(a, s);
+  return mode == kFwdX ? dispatch<kFwdX>(a, s) : dispatch<kFwd>(a, s);
 }
 
 }  // namespace cvb

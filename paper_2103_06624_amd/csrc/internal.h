@@ -70,21 +70,37 @@ void launch_gemm(int cfg, int mode, const GemmArgs& g, hipStream_t s);
 struct ConvGeom {
   int ci, hi, wi, co, ho, wo, k, s, p;
 };
+// One direction of a conv layer as an implicit GEMM per batch row,
+// D[m, n] = sum_k G[m, k] Wm[k, n] (conv.hip).  G gathers the row's input
+// plane: element (m, k) is input[k.z + (m.x + k.x) * gw + (m.y + k.y)] when
+// (m.x + k.x, m.y + k.y) lies in the gh x gw plane, else 0.  D[m, n] is
+// output[n.z + (os * m.z + n.x) * ow + (os * m.w + n.y)] when that lies in
+// the oh x ow plane and n.z >= 0.  Device tables, built once per layer.
+struct ConvPlan {
+  const int4* mtab;  // [mpad] gather origin (x, y) and output origin (z, w) of GEMM row m
+  const int4* ktab;  // [kpad] gather offset (x, y) and channel base z of GEMM column k
+  const int4* ntab;  // [16 nt] output offset (x, y) and channel base z (-1: padding)
+  const float* wm;   // [kpad / 4][nt][64] Wm in MFMA 16x16x4 operand order
+  int mpad, kpad, nt;  // multiples of 16; nt: 16-column tiles (1, 2, 4 or 8)
+  int gh, gw;          // gathered plane
+  int oh, ow, os;      // output plane and its stride factor
+  int din, dout;       // staged input and output floats per row
+  int grid;            // persistent workgroups
+  int smem;            // dynamic LDS bytes
+};
 struct ConvArgs {
   const float* in;
   int ldi;
-  const float* w;  // OIHW
-  ConvGeom g;
+  ConvPlan pl;
   int M;
   int last;
-  int uniform;  // stride-parity classes hold whole waves
   Batch bt;
   Vars v;
   Epi e;
 };
-bool conv_channels_supported(int c);
-size_t convt_smem_bytes(const ConvGeom& g, int w64, bool conc);
-size_t conv_smem_bytes(const ConvGeom& g);
+// LDS bytes of a plan and the workgroups that run concurrently on the device
+int conv_plan_smem(const ConvPlan& pl);
+int conv_plan_grid(int mode, const ConvPlan& pl);
 int launch_convt_bwd(int mode, const ConvArgs& a, hipStream_t s);
 int launch_conv_fwd(int mode, const ConvArgs& a, hipStream_t s);
 
