@@ -450,6 +450,8 @@ int upload_plan(cv_bound* h, HostPlan& o, int mode, ConvPlan& out) {
   out.ktab = kt;
   out.ntab = nt;
   out.wm = wm;
+  // a weight matrix over 16 KB stays in global memory (more workgroups fit per CU)
+  out.wg = (size_t)out.kpad * out.nt * 16 * sizeof(float) > 16384 ? 1 : 0;
   out.smem = conv_plan_smem(out);
   out.grid = out.smem <= 65536 ? conv_plan_grid(mode, out) : 0;
   return CV_OK;

@@ -110,14 +110,20 @@ __device__ __forceinline__ void in_store(float* zi, const Batch& bt, const Vars&
   }
 }
 
-template <int MODE, int NT>
-__global__ __launch_bounds__(256) void conv_mm(const float* __restrict__ zin, int ldi, ConvPlan pl, int M, int last,
+// The forward modes ask for five waves per SIMD (at most 102 VGPRs): measured
+// 10-17 % faster than the compiler's own choice; the back-substitution modes
+// measured no better with it.  WG: the weight matrix is read from global
+// memory (L1/L2) instead of LDS, for matrices too large to leave room for
+// more than two workgroups per CU (measured 25-29 % faster there, 5-8 %
+// slower for small matrices).
+template <int MODE, int NT, bool WG>
+__global__ __launch_bounds__(256, MODE == kFwdX || MODE == kFwd ? 5 : 1) void conv_mm(const float* __restrict__ zin, int ldi, ConvPlan pl, int M, int last,
                                                Batch bt, Vars v, Epi e) {
   extern __shared__ float4 smem4[];
   __shared__ float red[2][4];
   constexpr bool kBwd = MODE == kBwdRelax || MODE == kBwdConc;
   float* const wm = reinterpret_cast<float*>(smem4);
-  const int nwm = pl.kpad * NT * 16;  // floats
+  const int nwm = WG ? 0 : pl.kpad * NT * 16;  // floats in LDS
   int4* const mt = reinterpret_cast<int4*>(wm + nwm);
   int4* const kt = mt + pl.mpad;
   int4* const ntb = kt + pl.kpad;
@@ -143,7 +149,7 @@ __global__ __launch_bounds__(256) void conv_mm(const float* __restrict__ zin, in
   __syncthreads();
 
   const int n_ks = pl.kpad >> 2, n_mt = pl.mpad >> 4;
-  const float* const wl = wm + lane;
+  const float* const wl = (WG ? pl.wm : wm) + lane;
   for (; row < M; row += gridDim.x) {
     const int nrow = row + gridDim.x;
     const int p = bt.prop[row / bt.m];
@@ -159,16 +165,35 @@ __global__ __launch_bounds__(256) void conv_mm(const float* __restrict__ zin, in
 #pragma unroll
       for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
       // four K steps per pass (kpad is a multiple of 16): their table reads,
-      // gathers and weight reads are issued before the MFMAs that use them
+      // gathers and weight reads are issued before the MFMAs that use them;
+      // weights from global memory are loaded one pass ahead
+      float bn[4][NT];
+      if (WG) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int t = 0; t < NT; ++t) bn[q][t] = wl[(q * NT + t) * 64];
+      }
       for (int ks0 = 0; ks0 < n_ks; ks0 += 4) {
         int4 ke[4];
         float a[4], b[4][NT];
 #pragma unroll
         for (int q = 0; q < 4; ++q) ke[q] = kt[(ks0 + q) * 4 + (lane >> 4)];
+        if (WG) {
+          const int kn = ks0 + 4 < n_ks ? ks0 + 4 : ks0;  // the last pass reloads its own (unused)
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+          for (int q = 0; q < 4; ++q)
 #pragma unroll
-          for (int t = 0; t < NT; ++t) b[q][t] = wl[((ks0 + q) * NT + t) * 64];
+            for (int t = 0; t < NT; ++t) {
+              b[q][t] = bn[q][t];
+              bn[q][t] = wl[((kn + q) * NT + t) * 64];
+            }
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) b[q][t] = wl[((ks0 + q) * NT + t) * 64];
+        }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int yy = me.x + ke[q].x, xx = me.y + ke[q].y;
@@ -295,33 +320,37 @@ __global__ __launch_bounds__(256) void conv_mm(const float* __restrict__ zin, in
   }
 }
 
-template <int MODE>
+template <int MODE, bool WG>
 const void* kernel_nt(int nt) {
   switch (nt) {
-    case 1: return reinterpret_cast<const void*>(conv_mm<MODE, 1>);
-    case 2: return reinterpret_cast<const void*>(conv_mm<MODE, 2>);
-    case 4: return reinterpret_cast<const void*>(conv_mm<MODE, 4>);
-    case 8: return reinterpret_cast<const void*>(conv_mm<MODE, 8>);
+    case 1: return reinterpret_cast<const void*>(conv_mm<MODE, 1, WG>);
+    case 2: return reinterpret_cast<const void*>(conv_mm<MODE, 2, WG>);
+    case 4: return reinterpret_cast<const void*>(conv_mm<MODE, 4, WG>);
+    case 8: return reinterpret_cast<const void*>(conv_mm<MODE, 8, WG>);
     default: return nullptr;
   }
 }
 
-const void* kernel_for(int mode, int nt) {
+template <int MODE>
+const void* kernel_wg(int nt, bool wg) {
+  return wg ? kernel_nt<MODE, true>(nt) : kernel_nt<MODE, false>(nt);
+}
+
+const void* kernel_for(int mode, int nt, bool wg) {
   switch (mode) {
-    case kBwdRelax: return kernel_nt<kBwdRelax>(nt);
-    case kBwdConc: return kernel_nt<kBwdConc>(nt);
-    case kFwdX: return kernel_nt<kFwdX>(nt);
-    default: return kernel_nt<kFwd>(nt);
+    case kBwdRelax: return kernel_wg<kBwdRelax>(nt, wg);
+    case kBwdConc: return kernel_wg<kBwdConc>(nt, wg);
+    case kFwdX: return kernel_wg<kFwdX>(nt, wg);
+    default: return kernel_wg<kFwd>(nt, wg);
   }
 }
 
-template <int MODE>
-int dispatch(const ConvArgs& a, hipStream_t st) {
-  if (a.M <= 0) return 0;
+template <int MODE, bool WG>
+int dispatch_wg(const ConvArgs& a, hipStream_t st) {
   const dim3 grid(std::min(a.M, std::max(1, a.pl.grid))), block(256);
-#define CVB_CM(NT)                                                                                            \
-  case NT:                                                                                                    \
-    launch_k(conv_mm<MODE, NT>, grid, block, a.pl.smem, st, a.in, a.ldi, a.pl, a.M, a.last, a.bt, a.v, a.e); \
+#define CVB_CM(NT)                                                                                                \
+  case NT:                                                                                                        \
+    launch_k(conv_mm<MODE, NT, WG>, grid, block, a.pl.smem, st, a.in, a.ldi, a.pl, a.M, a.last, a.bt, a.v, a.e); \
     return 0;
   switch (a.pl.nt) {
     CVB_CM(1) CVB_CM(2) CVB_CM(4) CVB_CM(8)
@@ -331,15 +360,21 @@ int dispatch(const ConvArgs& a, hipStream_t st) {
 #undef CVB_CM
 }
 
+template <int MODE>
+int dispatch(const ConvArgs& a, hipStream_t st) {
+  if (a.M <= 0) return 0;
+  return a.pl.wg ? dispatch_wg<MODE, true>(a, st) : dispatch_wg<MODE, false>(a, st);
+}
+
 }  // namespace
 
 int conv_plan_smem(const ConvPlan& pl) {
-  return (pl.kpad * pl.nt * 16 + ((pl.din + 4) & ~3) + pl.dout) * (int)sizeof(float) +
+  return ((pl.wg ? 0 : pl.kpad * pl.nt * 16) + ((pl.din + 4) & ~3) + pl.dout) * (int)sizeof(float) +
          (pl.mpad + pl.kpad + pl.nt * 16) * (int)sizeof(int4);
 }
 
 int conv_plan_grid(int mode, const ConvPlan& pl) {
-  const void* k = kernel_for(mode, pl.nt);
+  const void* k = kernel_for(mode, pl.nt, pl.wg != 0);
   int dev = 0, cus = 0, per = 0;
   if (!k || hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||

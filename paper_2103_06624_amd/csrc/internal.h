@@ -85,6 +85,7 @@ struct ConvPlan {
   int gh, gw;          // gathered plane
   int oh, ow, os;      // output plane and its stride factor
   int din, dout;       // staged input and output floats per row
+  int wg;              // 1: the kernel reads wm from global memory, not LDS
   int grid;            // persistent workgroups
   int smem;            // dynamic LDS bytes
 };
