@@ -366,10 +366,32 @@ void plan_pad(HostPlan& o, int M, int K, int N, F wv) {
 }
 
 // Back-substitution through conv layer ly (transposed convolution), polyphase
-// form: GEMM rows (Y, X), columns (py, px, ci), K = (co, a, b).
+// form: GEMM rows (Y, X), columns (py, px, ci), K = (co, a, b).  A stride-1
+// layer with c_in <= 8 folds output pairs x = 2 X + px into a row instead:
+// columns (px, ci), K = (co, a, b') with b' = kx - px in [-1, k).
 void plan_convt(const cv_layer& ly, HostPlan& o) {
   const int s = ly.stride, k = ly.kernel, pad = ly.pad, ci = ly.in_c, hi = ly.in_h, wi = ly.in_w;
   const int co = ly.out_c, ho = ly.out_h, wo = ly.out_w, am = (k + s - 1) / s;
+  ConvPlan& p = o.p;
+  p.gh = ho;
+  p.gw = wo;
+  p.oh = hi;
+  p.ow = wi;
+  p.din = co * ho * wo;
+  p.dout = ci * hi * wi;
+  if (s == 1 && ci <= 8) {
+    const int nX = (wi + 1) / 2, kb = k + 1, M = hi * nX, K = co * k * kb, N = 2 * ci;
+    plan_pad(o, M, K, N, [&](int kk, int n) {
+      const int c_o = kk / (k * kb), a = (kk / kb) % k, kx = kk % kb - 1 + n / ci;
+      return kx >= 0 && kx < k ? ly.weight[(((size_t)c_o * ci + n % ci) * k + a) * k + kx] : 0.f;
+    });
+    for (int m = 0; m < M; ++m) o.mt[m] = make_int4(m / nX + pad, 2 * (m % nX) + pad, m / nX + pad, m % nX);
+    for (int kk = 0; kk < K; ++kk) o.kt[kk] = make_int4(-((kk / kb) % k), 1 - kk % kb, (kk / (k * kb)) * ho * wo, 0);
+    for (int n = 0; n < N; ++n) o.nt[n] = make_int4(-pad, n / ci, (n % ci) * hi * wi, 0);
+    p.osy = 1;
+    p.osx = 2;
+    return;
+  }
   std::vector<int> k0(s), T(s);
   for (int c = 0; c < s; ++c) {
     k0[c] = (c + pad) % s;
@@ -404,20 +426,39 @@ void plan_convt(const cv_layer& ly, HostPlan& o) {
     const int cls = n / ci, c = n % ci, py = cls / s, px = cls % s;
     o.nt[n] = make_int4(py - s * T[py], px - s * T[px], c * hi * wi, 0);
   }
-  ConvPlan& p = o.p;
-  p.gh = ho;
-  p.gw = wo;
-  p.oh = hi;
-  p.ow = wi;
-  p.os = s;
-  p.din = co * ho * wo;
-  p.dout = ci * hi * wi;
+  p.osy = s;
+  p.osx = s;
 }
 
-// The forward convolution of ly: GEMM rows (oy, ox), K = (ci, ky, kx), N = co.
+// The forward convolution of ly: GEMM rows (oy, ox), K = (ci, ky, kx), N = co;
+// with c_out <= 8, output pairs ox = 2 X + px share a row: columns (px, co),
+// K = (ci, ky, kx') with kx' = kx + s px in [0, k + s).
 void plan_conv(const cv_layer& ly, HostPlan& o) {
   const int s = ly.stride, k = ly.kernel, pad = ly.pad, ci = ly.in_c, hi = ly.in_h, wi = ly.in_w;
   const int co = ly.out_c, ho = ly.out_h, wo = ly.out_w;
+  ConvPlan& p = o.p;
+  p.gh = hi;
+  p.gw = wi;
+  p.oh = ho;
+  p.ow = wo;
+  p.din = ci * hi * wi;
+  p.dout = co * ho * wo;
+  p.osy = 1;
+  if (co <= 8) {
+    const int nX = (wo + 1) / 2, kf = k + s, M = ho * nX, K = ci * k * kf;
+    plan_pad(o, M, K, 2 * co, [&](int kk, int n) {
+      const int c = kk / (k * kf), ky = (kk / kf) % k, kx = kk % kf - (n / co) * s;
+      return kx >= 0 && kx < k ? ly.weight[(((size_t)(n % co) * ci + c) * k + ky) * k + kx] : 0.f;
+    });
+    for (int m = 0; m < M; ++m) {
+      const int oy = m / nX, X = m % nX;
+      o.mt[m] = make_int4(oy * s - pad, 2 * X * s - pad, oy, X);
+    }
+    for (int kk = 0; kk < K; ++kk) o.kt[kk] = make_int4((kk / kf) % k, kk % kf, (kk / (k * kf)) * hi * wi, 0);
+    for (int n = 0; n < 2 * co; ++n) o.nt[n] = make_int4(0, n / co, (n % co) * ho * wo, 0);
+    p.osx = 2;
+    return;
+  }
   const int M = ho * wo, K = ci * k * k;
   plan_pad(o, M, K, co, [&](int kk, int n) { return ly.weight[(size_t)n * K + kk]; });
   for (int m = 0; m < M; ++m) {
@@ -426,14 +467,7 @@ void plan_conv(const cv_layer& ly, HostPlan& o) {
   }
   for (int kk = 0; kk < K; ++kk) o.kt[kk] = make_int4((kk / k) % k, kk % k, (kk / (k * k)) * hi * wi, 0);
   for (int n = 0; n < co; ++n) o.nt[n] = make_int4(0, 0, n * ho * wo, 0);
-  ConvPlan& p = o.p;
-  p.gh = hi;
-  p.gw = wi;
-  p.oh = ho;
-  p.ow = wo;
-  p.os = 1;
-  p.din = ci * hi * wi;
-  p.dout = co * ho * wo;
+  p.osx = 1;
 }
 
 int upload_plan(cv_bound* h, HostPlan& o, int mode, ConvPlan& out) {

@@ -15,6 +15,10 @@
 //    kernel).
 //  * forward convolution (the adjoint's step, and the network itself for
 //    the upper bound): rows (oy, ox), K = (c_in, ky, kx) as im2col, N = c_out.
+//  * with 8 or fewer columns, two horizontally adjacent outputs x = 2 X + px
+//    share a GEMM row and the N axis holds (px, channel): K widens to the
+//    k + s taps (k + 1 for a stride-1 transposed convolution) that the pair
+//    reads, and no MFMA column is left empty.
 // G is gathered from the row's input staged in LDS through per-row and
 // per-column offset tables; a tap outside the plane reads a zero slot, so
 // the zero padding is exact.  The results are scattered into an LDS copy of
@@ -212,7 +216,7 @@ __global__ __launch_bounds__(256, MODE == kFwdX || MODE == kFwd ? 5 : 1) void co
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int4 mo = mt[mtile * 16 + 4 * (lane >> 4) + r];
-          const int y = pl.os * mo.z + ne.x, x = pl.os * mo.w + ne.y;
+          const int y = pl.osy * mo.z + ne.x, x = pl.osx * mo.w + ne.y;
           if (ne.z >= 0 && (unsigned)y < (unsigned)pl.oh && (unsigned)x < (unsigned)pl.ow)
             zo[ne.z + y * pl.ow + x] = acc[t][r];
         }

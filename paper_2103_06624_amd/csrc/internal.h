@@ -74,7 +74,7 @@ struct ConvGeom {
 // D[m, n] = sum_k G[m, k] Wm[k, n] (conv.hip).  G gathers the row's input
 // plane: element (m, k) is input[k.z + (m.x + k.x) * gw + (m.y + k.y)] when
 // (m.x + k.x, m.y + k.y) lies in the gh x gw plane, else 0.  D[m, n] is
-// output[n.z + (os * m.z + n.x) * ow + (os * m.w + n.y)] when that lies in
+// output[n.z + (osy * m.z + n.x) * ow + (osx * m.w + n.y)] when that lies in
 // the oh x ow plane and n.z >= 0.  Device tables, built once per layer.
 struct ConvPlan {
   const int4* mtab;  // [mpad] gather origin (x, y) and output origin (z, w) of GEMM row m
@@ -83,7 +83,7 @@ struct ConvPlan {
   const float* wm;   // [kpad / 4][nt][64] Wm in MFMA 16x16x4 operand order
   int mpad, kpad, nt;  // multiples of 16; nt: 16-column tiles (1, 2, 4 or 8)
   int gh, gw;          // gathered plane
-  int oh, ow, os;      // output plane and its stride factor
+  int oh, ow, osy, osx;  // output plane and its stride factors
   int din, dout;       // staged input and output floats per row
   int wg;              // 1: the kernel reads wm from global memory, not LDS
   int grid;            // persistent workgroups
