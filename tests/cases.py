@@ -81,3 +81,48 @@ def l2_case(name, n_props=None, n_dom=None):
 
 def small_l2_case(name):
     return l2_case(name, **SMALL[name])
+
+
+def interval_bounds(net64, x_lo, x_hi):
+    """Pre-activation intervals of one property by interval arithmetic (valid
+    and looser than CROWN), float64, layer-major."""
+    c = (np.asarray(x_lo, np.float64) + np.asarray(x_hi, np.float64)) / 2
+    r = (np.asarray(x_hi, np.float64) - np.asarray(x_lo, np.float64)) / 2
+    los, ups = [], []
+    for W, b in net64[:-1]:
+        zc, zr = W @ c + b, np.abs(W) @ r
+        l, u = zc - zr, zc + zr
+        los.append(l)
+        ups.append(u)
+        hl, hu = np.maximum(l, 0), np.maximum(u, 0)
+        c, r = (hl + hu) / 2, (hu - hl) / 2
+    return np.concatenate(los), np.concatenate(ups)
+
+
+@functools.lru_cache(maxsize=None)
+def full_case_props(name, n_oracle_props=3, seed=0):
+    """The workload at full size.  The oracle's root bounds for a few
+    properties (the ones whose subdomains are compared), interval bounds for
+    the others (valid, looser; their subdomains are not compared).  A
+    subdomain's splits depend only on its own property's bounds, so the
+    compared subdomains are those the workload has with the oracle's bounds.
+    Returns (wl, lo, up, orc, props)."""
+    wl = synth.make(name)
+    P = wl.n_props
+    net64 = bc.dense_net(wl.net.layers)
+    rng = np.random.default_rng(seed)
+    props = tuple(sorted(rng.choice(P, size=min(n_oracle_props, P), replace=False).tolist()))
+    lo64, up64 = [], []
+    for p in range(P):
+        if p in props:
+            l, u = bc.root_bounds(net64, np.asarray(wl.x_lo[p], np.float64), np.asarray(wl.x_hi[p], np.float64))
+            l, u = np.concatenate(l), np.concatenate(u)
+        else:
+            l, u = interval_bounds(net64, wl.x_lo[p], wl.x_hi[p])
+        lo64.append(l)
+        up64.append(u)
+    lo, up = bc.outward_f32(np.stack(lo64), np.stack(up64))
+    sp = synth.attach_splits(wl, lo, up)
+    orc = ob.OracleProblem(wl.net.layers, wl.x_lo, wl.x_hi, wl.C, lo, up, sp.dom_prop, sp.split_ptr, sp.layer,
+                           sp.neuron, sp.side, net64=net64)
+    return wl, lo, up, orc, props

@@ -489,6 +489,34 @@ def test_full_size_sampled(name):
     assert max(e0) <= TOL and max(e1) <= TOL
 
 
+@pytest.mark.parametrize("name", ["cnn_base", "cnn_wide", "cnn_deep"])
+def test_full_size_sampled_cnn(name):
+    """The CNN workloads at full size, in the bench's launch configuration
+    (concurrent sub-batches): sampled subdomains of the properties that carry
+    the oracle's root bounds, checked one by one (plain evaluation at CROWN's
+    alpha, and the 20-step optimisation)."""
+    from paper_2103_06624_amd.api import BoundProblem
+    say("full size", name)
+    wl, lo, up, orc, props = cases.full_case_props(name)
+    pb = BoundProblem.from_workload(wl, lo, up)
+    a = pb.alpha_init()
+    b = pb.zeros_beta()
+    lb0 = pb.eval(a, b).cpu().numpy()
+    best, _ = pb.optimize(a, b)
+    best = best.cpu().numpy()
+    a0 = orc.default_alpha_flat()
+    z = np.zeros(orc.nnz * orc.m)
+    cand = [d for d in range(orc.B) if int(orc.dom_prop[d]) in props]
+    rng = np.random.default_rng(3)
+    e0, e1 = [], []
+    for d in sorted(rng.choice(cand, size=min(6, len(cand)), replace=False).tolist()):
+        e0.append(guarded_rel(lb0[d], orc.eval(d, a0, z)).max())
+        rbest, *_ = orc.optimize(d, a0, z)
+        e1.append(guarded_rel(best[d], rbest).max())
+    say(name, "rows", pb.n_rows, "full-size eval err", max(e0), "opt err", max(e1))
+    assert max(e0) <= TOL and max(e1) <= TOL
+
+
 @pytest.mark.parametrize("n_dom", [600, 1500, 2000])
 def test_chain_row_blocks(n_dom):
     """Batch sizes that give the fused chain 2 and 3 row blocks per workgroup,
