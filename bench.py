@@ -127,9 +127,13 @@ def bab_context(wl, lo, up, args):
     torch.cuda.synchronize()
     r = gb.bab(layers, wl.x_lo[p], wl.x_hi[p], C, lo[p], up[p], batch=args.bab_batch, max_rounds=args.bab_rounds,
                iters=args.iters, lr_alpha=args.lr_alpha, lr_beta=args.lr_beta, decay=args.decay)
+    # rounds that split a full batch (after the pool has grown to it)
+    full = [(n, s) for n, s in r["per_round"] if n >= 2 * args.bab_batch]
     return {"domains_per_s": round(r["domains"] / r["seconds"], 1), "domains": r["domains"], "rounds": r["rounds"],
             "batch": args.bab_batch, "seconds": round(r["seconds"], 3), "verdict": r["verdict"],
-            "lb": r["lb"], "ub": r["ub"]}
+            "lb": r["lb"], "ub": r["ub"],
+            "full_batch_rounds": len(full),
+            "full_batch_domains_per_s": round(sum(n for n, _ in full) / sum(s for _, s in full), 1) if full else None}
 
 
 def cpu_baseline(name, gpu_best, gpu_splits, gpu_lo, gpu_up, seconds, iters, lr_a, lr_b, decay):
@@ -198,7 +202,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--bab-rounds", type=int, default=12, help="branch-and-bound rounds timed as context")
+    ap.add_argument("--bab-rounds", type=int, default=16, help="branch-and-bound rounds timed as context")
     ap.add_argument("--bab-batch", type=int, default=1024, help="subdomains split per branch-and-bound round")
     ap.add_argument("--plan", default=None, help="dense-chain plan bwd,fwd (1,1 fused chains, 0,0 per-layer kernels); overrides the autotuner")
     ap.add_argument("--parts", type=int, default=0,

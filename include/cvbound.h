@@ -187,8 +187,10 @@ int cv_bound_upper(cv_bound *h, const float *alpha, const float *beta, float *lb
  *     moments kept internally; step0: steps already taken (0 for a fresh run);
  *   lb_best: device [n_rows] out, max over the iters+1 evaluated bounds;
  *   lb_last: device [n_rows] out (may be NULL), bound of the final iterate.
- * The whole loop is captured once in a HIP graph and replayed on later calls
- * with the same arguments. */
+ * The first call with a given set of arguments issues the loop's launches
+ * directly; the second captures the whole loop in a HIP graph, which later
+ * calls with the same arguments replay (a handle optimised once, as in a
+ * branch-and-bound round, pays no capture). */
 int cv_bound_optimize(cv_bound *h, int32_t iters, float lr_alpha, float lr_beta, float lr_decay,
                       float *alpha, float *beta, float *adam_state, int32_t step0,
                       float *lb_best, float *lb_last, void *stream);

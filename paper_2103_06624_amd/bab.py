@@ -54,7 +54,8 @@ def bab(layers, x_lo, x_hi, C, lo, up, batch=1024, max_rounds=64, max_pool=1 << 
     """x_lo, x_hi [d0]; C [m, dL]; lo, up [sum d_i] root bounds of this property.
     Returns a dict: verdict ('verified' | 'falsified' | 'unknown'), lb (the
     smallest lower bound over the leaves of the search tree), ub, rounds,
-    domains (subdomains bounded, the root included), seconds."""
+    domains (subdomains bounded, the root included), seconds, and per_round:
+    (children bounded, seconds) of each round."""
     t_start = time.perf_counter()
     x_lo = np.asarray(x_lo, np.float32)[None]
     x_hi = np.asarray(x_hi, np.float32)[None]
@@ -100,7 +101,9 @@ def bab(layers, x_lo, x_hi, C, lo, up, batch=1024, max_rounds=64, max_pool=1 << 
     f_ub = float(ub0[0])
     done_lb = np.inf if pool else float(lb0[0])
     rounds, domains, seq = 0, 1, 1
+    per_round = []
     while f_lb < 0 <= f_ub and pool and len(pool) < max_pool and rounds < max_rounds:
+        t_round = time.perf_counter()
         pool.sort(key=lambda t: (t[0], t[1]))
         picked, rest = [], []
         for t in pool:
@@ -124,6 +127,7 @@ def bab(layers, x_lo, x_hi, C, lo, up, batch=1024, max_rounds=64, max_pool=1 << 
             seq += 1
         f_lb = min(t[0] for t in pool) if pool else np.inf
         rounds += 1
+        per_round.append((len(children), time.perf_counter() - t_round))
     verdict = "falsified" if f_ub < 0 else ("verified" if f_lb >= 0 else "unknown")
     return {"verdict": verdict, "lb": min(f_lb, done_lb), "ub": f_ub, "rounds": rounds, "domains": domains,
-            "seconds": time.perf_counter() - t_start}
+            "seconds": time.perf_counter() - t_start, "per_round": per_round}

@@ -206,6 +206,7 @@ struct cv_bound {
   hipStream_t cap = nullptr;
   hipGraphExec_t gexec = nullptr;
   GraphKey gkey;
+  GraphKey gseen;  // arguments of the last call run without a graph
   Profiler* prof = nullptr;
 };
 
@@ -1324,8 +1325,9 @@ void drop_graph(cv_bound* h) {
   h->gkey.v.clear();
 }
 
-// The whole optimisation loop of one handle, captured once in a HIP graph
-// (keyed by the arguments) and replayed on `s`.
+// The whole optimisation loop of one handle: issued directly the first time
+// a set of arguments is seen, captured in a HIP graph (keyed by the
+// arguments) the second time and replayed on `s` from then on.
 int optimize_one(cv_bound* h, int iters, float lr_alpha, float lr_beta, float lr_decay, float* alpha, float* beta,
                  AdamPtrs ap, int step0, float* lb_best, float* lb_last, hipStream_t s) {
   int rc = ensure_opt(h);
@@ -1338,6 +1340,10 @@ int optimize_one(cv_bound* h, int iters, float lr_alpha, float lr_beta, float lr
   key.v = {(uintptr_t)alpha, (uintptr_t)beta, (uintptr_t)ap.ma, (uintptr_t)ap.va, (uintptr_t)ap.mb, (uintptr_t)ap.vb,
            (uintptr_t)lb_best, (uintptr_t)lb_last, (uintptr_t)iters, (uintptr_t)step0, fb[0], fb[1], fb[2]};
   if (!h->gexec || !(h->gkey == key)) {
+    if (!(h->gseen == key)) {  // first time: no capture
+      h->gseen = key;
+      return enqueue_opt(h, iters, lr_alpha, lr_beta, lr_decay, alpha, beta, ap, step0, lb_best, lb_last, s);
+    }
     drop_graph(h);
     if (!h->cap) HIPCHK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
     HIPCHK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
