@@ -2,9 +2,9 @@
 
 One property at a time.  The objective of a subdomain is min_k (C f(x))_k over
 its specification rows: the property holds when every row is >= 0.  The pool
-of unverified subdomains lives on the host (a subdomain is its list of split
-decisions); every round takes the `batch` subdomains with the lowest lower
-bounds (batch_pick_out), splits each on its next neuron into a z >= 0 and a
+of unverified subdomains lives on the host as arrays (a subdomain is its
+split decisions); every round takes the `batch` subdomains with the lowest
+lower bounds (batch_pick_out), splits each on its next neuron into a z >= 0 and a
 z < 0 child (batch_split) and bounds all children in one batch on the GPU:
 cv_bound_optimize from CROWN's default alpha and beta = 0, then cv_bound_upper
 at the final iterate for the network at the box minimiser x* (the upper
@@ -55,7 +55,11 @@ def bab(layers, x_lo, x_hi, C, lo, up, batch=1024, max_rounds=64, max_pool=1 << 
     Returns a dict: verdict ('verified' | 'falsified' | 'unknown'), lb (the
     smallest lower bound over the leaves of the search tree), ub, rounds,
     domains (subdomains bounded, the root included), seconds, and per_round:
-    (children bounded, seconds) of each round."""
+    (children bounded, seconds) of each round.
+
+    Every subdomain splits the neurons of the branching order in turn, so it
+    is its depth d (it has split order[0..d-1]) and the d sides it took; the
+    pool is held as arrays (lower bound, sequence number, depth, sides)."""
     t_start = time.perf_counter()
     x_lo = np.asarray(x_lo, np.float32)[None]
     x_hi = np.asarray(x_hi, np.float32)[None]
@@ -64,19 +68,20 @@ def bab(layers, x_lo, x_hi, C, lo, up, batch=1024, max_rounds=64, max_pool=1 << 
     up = np.asarray(up, np.float32)[None]
     relu_dims = [ly.d_out for ly in layers[:-1]]
     order = branch_order(lo[0], up[0], relu_dims)
+    o_lay = np.array([i for i, _ in order], np.int32)
+    o_neu = np.array([j for _, j in order], np.int32)
+    width = max(1, min(len(order), max_rounds))  # no subdomain is deeper than the rounds run
     opt = dict(iters=iters, lr_alpha=lr_alpha, lr_beta=lr_beta, decay=decay)
 
-    def solve(domains):
-        """(lower, upper) bound per subdomain, each a tuple of (layer, neuron, side)."""
-        ptr = np.zeros(len(domains) + 1, np.int64)
-        lay, neu, side = [], [], []
-        for b, dom in enumerate(domains):
-            for (i, j, s) in dom:
-                lay.append(i)
-                neu.append(j)
-                side.append(s)
-            ptr[b + 1] = len(lay)
-        pb = BoundProblem(layers, x_lo, x_hi, C, lo, up, np.zeros(len(domains), np.int32), ptr, lay, neu, side)
+    def solve(depth, sides):
+        """(lower, upper) bound per subdomain (depth [n], sides [n, width])."""
+        n = depth.shape[0]
+        ptr = np.zeros(n + 1, np.int64)
+        np.cumsum(depth, out=ptr[1:])
+        rep = np.repeat(np.arange(n), depth)
+        pos = np.arange(ptr[-1]) - ptr[rep]
+        pb = BoundProblem(layers, x_lo, x_hi, C, lo, up, np.zeros(n, np.int32), ptr, o_lay[pos], o_neu[pos],
+                          sides[rep, pos])
         try:
             if sound:
                 pb.set_sound(1)
@@ -88,46 +93,46 @@ def bab(layers, x_lo, x_hi, C, lo, up, batch=1024, max_rounds=64, max_pool=1 << 
         finally:
             pb.close()
 
-    def next_neuron(dom):
-        done = {(i, j) for (i, j, _) in dom}
-        for i, j in order:
-            if (i, j) not in done:
-                return i, j
-        return None
-
-    lb0, ub0 = solve([()])
-    pool = [(float(lb0[0]), 0, ())] if lb0[0] < 0 else []
-    f_lb = float(lb0[0]) if pool else np.inf
+    lb0, ub0 = solve(np.zeros(1, np.int32), np.zeros((1, width), np.int8))
+    # the pool: lower bound, sequence number (ties), depth, sides
+    p_lb = np.array([lb0[0]], np.float64) if lb0[0] < 0 else np.zeros(0)
+    p_seq = np.zeros(p_lb.shape[0], np.int64)
+    p_dep = np.zeros(p_lb.shape[0], np.int32)
+    p_sid = np.zeros((p_lb.shape[0], width), np.int8)
+    f_lb = float(lb0[0]) if p_lb.size else np.inf
     f_ub = float(ub0[0])
-    done_lb = np.inf if pool else float(lb0[0])
+    done_lb = np.inf if p_lb.size else float(lb0[0])
     rounds, domains, seq = 0, 1, 1
     per_round = []
-    while f_lb < 0 <= f_ub and pool and len(pool) < max_pool and rounds < max_rounds:
+    while f_lb < 0 <= f_ub and p_lb.size and p_lb.size < max_pool and rounds < max_rounds:
         t_round = time.perf_counter()
-        pool.sort(key=lambda t: (t[0], t[1]))
-        picked, rest = [], []
-        for t in pool:
-            (picked if len(picked) < batch and next_neuron(t[2]) is not None else rest).append(t)
-        if not picked:
+        srt = np.lexsort((p_seq, p_lb))  # lowest lower bound first, then the oldest
+        can = srt[p_dep[srt] < min(len(order), width)]
+        pick = can[:batch]
+        if pick.size == 0:
             break
-        pool = rest
-        children = []
-        for _, _, dom in picked:
-            i, j = next_neuron(dom)
-            children.append(dom + ((i, j, 1),))
-            children.append(dom + ((i, j, -1),))
-        lbs, ubs = solve(children)
-        domains += len(children)
+        keep = np.ones(p_lb.size, bool)
+        keep[pick] = False
+        # children: each picked subdomain splits order[depth], z >= 0 child first
+        nc = 2 * pick.size
+        c_dep = np.repeat(p_dep[pick] + 1, 2)
+        c_sid = np.repeat(p_sid[pick], 2, axis=0)
+        c_sid[np.arange(nc), c_dep - 1] = np.tile(np.array([1, -1], np.int8), pick.size)
+        lbs, ubs = solve(c_dep, c_sid)
+        domains += nc
         f_ub = min(f_ub, float(ubs.min()))
-        for dom, lb_c in zip(children, lbs):
-            if lb_c < 0:
-                pool.append((float(lb_c), seq, dom))
-            else:
-                done_lb = min(done_lb, float(lb_c))
-            seq += 1
-        f_lb = min(t[0] for t in pool) if pool else np.inf
+        c_seq = seq + np.arange(nc, dtype=np.int64)
+        seq += nc
+        open_ = lbs < 0
+        if (~open_).any():
+            done_lb = min(done_lb, float(lbs[~open_].min()))
+        p_lb = np.concatenate([p_lb[keep], lbs[open_].astype(np.float64)])
+        p_seq = np.concatenate([p_seq[keep], c_seq[open_]])
+        p_dep = np.concatenate([p_dep[keep], c_dep[open_]])
+        p_sid = np.concatenate([p_sid[keep], c_sid[open_]])
+        f_lb = float(p_lb.min()) if p_lb.size else np.inf
         rounds += 1
-        per_round.append((len(children), time.perf_counter() - t_round))
+        per_round.append((nc, time.perf_counter() - t_round))
     verdict = "falsified" if f_ub < 0 else ("verified" if f_lb >= 0 else "unknown")
     return {"verdict": verdict, "lb": min(f_lb, done_lb), "ub": f_ub, "rounds": rounds, "domains": domains,
             "seconds": time.perf_counter() - t_start, "per_round": per_round}
