@@ -266,7 +266,7 @@ int cv_bound_set_sound(cv_bound *h, int32_t on, void *stream);
  * Applies to the handle and its sub-batches, now and when later created.
  * Not combined with sound mode: CV_EINVAL while sound mode is on (and
  * cv_bound_set_sound(h, 1) fails while balls are set).  The fused dense
- * chain and the optimiser's fused top layer are not used over balls.
+ * chain is not used over balls.
  * Copies its arguments (synchronous on `stream`); the first call allocates
  * per-row buffers (CV_ENOMEM).  W(1) x0 + b(1) is formed on the host in
  * double and rounded once. */

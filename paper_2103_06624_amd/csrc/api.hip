@@ -1297,8 +1297,7 @@ int enqueue_opt(cv_bound* h, int iters, float lr_a, float lr_b, float decay, flo
   // the top layer's relaxation rides on the last adjoint GEMM from the
   // second iteration on (per-layer kernels, dense top layer, no sound margin)
   const int L = h->L;
-  const bool fuse =
-      L >= 2 && h->layers[L - 2].type == CV_LAYER_DENSE && !h->chain_b && !h->chain_f && !h->sound && !h->l2;
+  const bool fuse = L >= 2 && h->layers[L - 2].type == CV_LAYER_DENSE && !h->chain_b && !h->chain_f && !h->sound;
   for (int t = 0; t < iters; ++t) {
     if ((rc = enqueue_bwd(h, alpha, beta, true, nullptr, lb_best, t == 0, s, fuse && t > 0))) return rc;
     const int tt = step0 + t;

@@ -335,6 +335,7 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt(const float* __restrict__ A,
             c += e.cb[ri.p * e.cb_pstride + ri.k];
           }
           e.part[(int64_t)(e.slot0 + tn) * M + row] = c;
+          if (e.psq) e.psq[(int64_t)(e.slot0 + tn) * M + row] = 0.f;  // l2 ball: no A(0) terms here
         }
       }
     } else {
