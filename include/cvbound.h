@@ -120,9 +120,9 @@ int cv_bound_root_bounds_opt(const cv_layer *layers, int32_t n_layers, int32_t n
  * is not root-unstable for its property, the same neuron twice in one
  * subdomain, a side other than +-1, or when nnz reaches 2^29.  CV_ESHAPE when
  * shapes do not chain, the last layer is a convolution, or a convolution has
- * a stride other than 1 or 2 (dividing its input plane), an input or output
- * plane whose position count H*W is not a multiple of 64, a channel count
- * outside {1, 2, 3, 4, 8, 16, 32}, or rows too large for the on-chip tiles.
+ * a stride above 8, more than 128 columns in one of its implicit GEMMs
+ * (stride^2 * in_c for the back-substitution, out_c forward), or rows,
+ * tables and weights too large for a workgroup's 64 KB of LDS.
  * CV_EINVAL for non-finite inputs, x_lo > x_hi or a property index out of
  * range.  Validation happens before any device call.
  * Synchronous; copies everything it needs to the device. */

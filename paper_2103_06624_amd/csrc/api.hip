@@ -296,45 +296,6 @@ bool plan_chain(cv_bound* h) {
 }
 
 // ---------------------------------------------------------------------------
-// validation
-
-int check_layers(const cv_layer* layers, int n, std::vector<int>& dims, bool allow_conv_last = false) {
-  if (!layers || n < 1) return fail(CV_EINVAL, "need at least one layer");
-  dims.assign(n + 1, 0);
-  for (int i = 0; i < n; ++i) {
-    const cv_layer& ly = layers[i];
-    if (!ly.weight || !ly.bias) return fail(CV_EINVAL, "layer %d: null weight or bias", i + 1);
-    const int64_t din = (int64_t)ly.in_c * ly.in_h * ly.in_w;
-    const int64_t dout = (int64_t)ly.out_c * ly.out_h * ly.out_w;
-    if (ly.in_c <= 0 || ly.in_h <= 0 || ly.in_w <= 0 || ly.out_c <= 0 || ly.out_h <= 0 || ly.out_w <= 0 ||
-        din > (1 << 24) || dout > (1 << 24))
-      return fail(CV_ESHAPE, "layer %d: bad sizes", i + 1);
-    if (ly.type == CV_LAYER_CONV2D) {
-      if (ly.kernel <= 0 || ly.stride <= 0 || ly.pad < 0) return fail(CV_ESHAPE, "layer %d: bad conv geometry", i + 1);
-      if ((ly.in_h + 2 * ly.pad - ly.kernel) / ly.stride + 1 != ly.out_h ||
-          (ly.in_w + 2 * ly.pad - ly.kernel) / ly.stride + 1 != ly.out_w)
-        return fail(CV_ESHAPE, "layer %d: conv output size does not match", i + 1);
-      // the implicit GEMMs' N axes: stride^2 c_in columns (back-substitution), c_out (forward)
-      if (ly.stride > 8 || (int64_t)ly.stride * ly.stride * ly.in_c > 128 || ly.out_c > 128)
-        return fail(CV_ESHAPE, "layer %d: stride^2 * c_in and c_out must be at most 128", i + 1);
-      if (i == n - 1 && !allow_conv_last) return fail(CV_ESHAPE, "the last layer must be dense");
-    } else if (ly.type != CV_LAYER_DENSE) {
-      return fail(CV_ESHAPE, "layer %d: unknown type %d", i + 1, ly.type);
-    }
-    if (i == 0) dims[0] = (int)din;
-    else if (din != dims[i]) return fail(CV_ESHAPE, "layer %d: input size %lld does not match %d", i + 1, (long long)din, dims[i]);
-    dims[i + 1] = (int)dout;
-  }
-  return CV_OK;
-}
-
-bool finite_all(const float* p, int64_t n) {
-  for (int64_t i = 0; i < n; ++i)
-    if (!std::isfinite(p[i])) return false;
-  return true;
-}
-
-// ---------------------------------------------------------------------------
 // conv layers as implicit GEMMs (ConvPlan; the kernels are in conv.hip)
 
 constexpr int kFar = -(1 << 20);  // an offset that puts any gather or output outside its plane
@@ -471,6 +432,64 @@ void plan_conv(const cv_layer& ly, HostPlan& o) {
   p.osx = 1;
 }
 
+// Weight placement and LDS bytes of a built plan.
+void plan_finish(ConvPlan& p) {
+  // a weight matrix over 16 KB stays in global memory (more workgroups fit per CU)
+  p.wg = (size_t)p.kpad * p.nt * 16 * sizeof(float) > 16384 ? 1 : 0;
+  p.smem = conv_plan_smem(p);
+}
+
+// Whether both implicit GEMMs of conv layer ly fit the LDS a workgroup uses.
+bool conv_fits_lds(const cv_layer& ly) {
+  HostPlan pb, pf;
+  plan_convt(ly, pb);
+  plan_conv(ly, pf);
+  plan_finish(pb.p);
+  plan_finish(pf.p);
+  return pb.p.smem <= 65536 && pf.p.smem <= 65536;
+}
+
+// ---------------------------------------------------------------------------
+// validation
+
+int check_layers(const cv_layer* layers, int n, std::vector<int>& dims, bool allow_conv_last = false) {
+  if (!layers || n < 1) return fail(CV_EINVAL, "need at least one layer");
+  dims.assign(n + 1, 0);
+  for (int i = 0; i < n; ++i) {
+    const cv_layer& ly = layers[i];
+    if (!ly.weight || !ly.bias) return fail(CV_EINVAL, "layer %d: null weight or bias", i + 1);
+    const int64_t din = (int64_t)ly.in_c * ly.in_h * ly.in_w;
+    const int64_t dout = (int64_t)ly.out_c * ly.out_h * ly.out_w;
+    if (ly.in_c <= 0 || ly.in_h <= 0 || ly.in_w <= 0 || ly.out_c <= 0 || ly.out_h <= 0 || ly.out_w <= 0 ||
+        din > (1 << 24) || dout > (1 << 24))
+      return fail(CV_ESHAPE, "layer %d: bad sizes", i + 1);
+    if (ly.type == CV_LAYER_CONV2D) {
+      if (ly.kernel <= 0 || ly.stride <= 0 || ly.pad < 0) return fail(CV_ESHAPE, "layer %d: bad conv geometry", i + 1);
+      if ((ly.in_h + 2 * ly.pad - ly.kernel) / ly.stride + 1 != ly.out_h ||
+          (ly.in_w + 2 * ly.pad - ly.kernel) / ly.stride + 1 != ly.out_w)
+        return fail(CV_ESHAPE, "layer %d: conv output size does not match", i + 1);
+      // the implicit GEMMs' N axes: stride^2 c_in columns (back-substitution), c_out (forward)
+      if (ly.stride > 8 || (int64_t)ly.stride * ly.stride * ly.in_c > 128 || ly.out_c > 128)
+        return fail(CV_ESHAPE, "layer %d: stride^2 * c_in and c_out must be at most 128", i + 1);
+      if (i < n - 1 && !conv_fits_lds(ly))
+        return fail(CV_ESHAPE, "layer %d: conv rows and weights do not fit in LDS", i + 1);
+      if (i == n - 1 && !allow_conv_last) return fail(CV_ESHAPE, "the last layer must be dense");
+    } else if (ly.type != CV_LAYER_DENSE) {
+      return fail(CV_ESHAPE, "layer %d: unknown type %d", i + 1, ly.type);
+    }
+    if (i == 0) dims[0] = (int)din;
+    else if (din != dims[i]) return fail(CV_ESHAPE, "layer %d: input size %lld does not match %d", i + 1, (long long)din, dims[i]);
+    dims[i + 1] = (int)dout;
+  }
+  return CV_OK;
+}
+
+bool finite_all(const float* p, int64_t n) {
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
 int upload_plan(cv_bound* h, HostPlan& o, int mode, ConvPlan& out) {
   int4 *mt = nullptr, *kt = nullptr, *nt = nullptr;
   float* wm = nullptr;
@@ -485,10 +504,8 @@ int upload_plan(cv_bound* h, HostPlan& o, int mode, ConvPlan& out) {
   out.ktab = kt;
   out.ntab = nt;
   out.wm = wm;
-  // a weight matrix over 16 KB stays in global memory (more workgroups fit per CU)
-  out.wg = (size_t)out.kpad * out.nt * 16 * sizeof(float) > 16384 ? 1 : 0;
-  out.smem = conv_plan_smem(out);
-  out.grid = out.smem <= 65536 ? conv_plan_grid(mode, out) : 0;
+  plan_finish(out);
+  out.grid = conv_plan_grid(mode, out);
   return CV_OK;
 }
 
@@ -745,13 +762,6 @@ int build(cv_bound* h, const cv_layer* layers, int n_layers, int P, const float*
     // the chain is available; per-layer kernels stay the default (measured
     // faster at ~10^4 rows), cv_bound_autotune / cv_bound_set_plan choose
     if (!plan_chain(h)) h->chain_lo = 0;
-  }
-  // conv kernels' LDS needs: weight matrix, tables, an input and an output row
-  for (int i = 0; i + 1 < n_layers; ++i) {
-    const DevLayer& ly = h->layers[i];
-    if (ly.type != CV_LAYER_CONV2D) continue;
-    if (ly.bwd.smem > 65536 || ly.fwd.smem > 65536)
-      return fail(CV_ESHAPE, "layer %d: conv rows and weights do not fit in LDS", i + 1);
   }
   HIPCHK(hipStreamSynchronize(s));
   return CV_OK;

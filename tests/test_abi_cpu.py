@@ -98,3 +98,17 @@ def test_conv_last_layer_rejected():
     wl, lo, up = _tiny()
     rc, err = _init(wl, lo, up, [0], [0, 0], [], [], [], layers=net.layers)
     assert rc in (B.CV_ESHAPE,)
+
+
+@pytest.mark.parametrize("shape,msg", [
+    (((40, 16, 16), [(8, 4, 2, 1)]), "at most 128"),      # 4 * 40 back-substitution columns
+    (((64, 32, 32), [(64, 3, 1, 1)]), "fit in LDS"),       # a 64 x 32 x 32 row does not fit on chip
+])
+def test_conv_limits_rejected_before_any_device_call(shape, msg):
+    """The conv implicit GEMMs' limits are checked on the host, so init fails
+    cleanly (no device needed)."""
+    rng = np.random.default_rng(0)
+    net = synth.cnn(rng, shape[0], shape[1], [10])
+    wl, lo, up = _tiny()
+    rc, err = _init(wl, lo, up, [0], [0, 0], [], [], [], layers=net.layers)
+    assert rc == B.CV_ESHAPE and msg in err, (rc, err)
