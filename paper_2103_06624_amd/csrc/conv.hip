@@ -351,7 +351,8 @@ const void* kernel_for(int mode, int nt, bool wg) {
 
 template <int MODE, bool WG>
 int dispatch_wg(const ConvArgs& a, hipStream_t st) {
-  const dim3 grid(std::min(a.M, std::max(1, a.pl.grid))), block(256);
+  // the occupancy query's answer, or two workgroups per CU if it failed
+  const dim3 grid(std::min(a.M, a.pl.grid > 0 ? a.pl.grid : 512)), block(256);
 #define CVB_CM(NT)                                                                                                \
   case NT:                                                                                                        \
     launch_k(conv_mm<MODE, NT, WG>, grid, block, a.pl.smem, st, a.in, a.ldi, a.pl, a.M, a.last, a.bt, a.v, a.e); \
