@@ -250,8 +250,9 @@ int cv_bound_set_tiling(cv_bound *h, int32_t tiling);
  * the error of the merged specification C W(L); it is typically 1e-6 of the
  * bound's magnitude.  Gradients are those of the bound without the margin.
  * The fused dense chain is not used while sound mode is on (the per-layer
- * kernels carry the margin).  on: 0 or 1 (else CV_EINVAL).  The first switch
- * on computes the constants (host work, synchronous on `stream`). */
+ * kernels carry the margin).  on: 0 or 1 (else CV_EINVAL).  Switching on
+ * computes the constants for the current input sets, boxes or the balls of
+ * cv_bound_set_input_l2 (host work, synchronous on `stream`). */
 int cv_bound_set_sound(cv_bound *h, int32_t on, void *stream);
 
 /* l2-ball input sets (Sec. 2.1 allows any l_p ball; Theorem 3.1's last step
@@ -264,9 +265,10 @@ int cv_bound_set_sound(cv_bound *h, int32_t on, void *stream);
  *   x0: host [n_props][d0], finite; eps: host [n_props], finite and >= 0;
  *   x0 = NULL returns every property to its box (eps ignored).
  * Applies to the handle and its sub-batches, now and when later created.
- * Not combined with sound mode: CV_EINVAL while sound mode is on (and
- * cv_bound_set_sound(h, 1) fails while balls are set).  The fused dense
- * chain is not used over balls.
+ * With sound mode on, the margin is rebuilt for the balls (an input
+ * coordinate is bounded by |x0_j| + eps_p), and the bound is lowered by an
+ * upper bound on eps ||A(0)||_2 and by the rounding of the A(0) x0 sum
+ * (g ||A(0)||_2 ||x0||_2).  The fused dense chain is not used over balls.
  * Copies its arguments (synchronous on `stream`); the first call allocates
  * per-row buffers (CV_ENOMEM).  W(1) x0 + b(1) is formed on the host in
  * double and rounded once. */

@@ -168,6 +168,9 @@ struct cv_bound {
   // the A(0)^2 partials [n_slots, R] and eps / ||A(0)||_2 per row
   bool l2 = false;
   float *l2x0 = nullptr, *l2eps = nullptr, *wx0 = nullptr, *psq = nullptr, *l2s = nullptr;
+  std::vector<float> hl2x0, hl2eps;  // host copies (sound mode's weights are built from them)
+  float* x0n = nullptr;              // [P] ||x0_p||_2 rounded up (sound mode over balls)
+  float l2fac = 1.f;
   bool sound = false;
   float* sw = nullptr;    // [P, nd]
   float* perr = nullptr;  // [n_slots, R]
@@ -891,8 +894,12 @@ void affine_host(const cv_layer& ly, const float* x, std::vector<double>& out) {
 
 // Weights and constants of the margin for handle h from its host inputs
 // (layers, box [P, d0], root bounds [P, nd], C [P, m, dL] unless identity).
+// Over l2 balls (l2x0 [P, d0], l2eps [P] set) an input coordinate is bounded
+// by |x0_j| + eps_p instead of the box, and the per-property ||x0||_2 and the
+// norm's rounding factor are prepared for the final sum.
 int prepare_sound(cv_bound* h, const cv_layer* layers, const float* x_lo, const float* x_hi, const float* l,
-                  const float* u, const float* C, bool identity, hipStream_t s) {
+                  const float* u, const float* C, bool identity, hipStream_t s, const float* l2x0 = nullptr,
+                  const float* l2eps = nullptr) {
   const int L = h->L, P = h->P, m = h->m, nd = h->nd, d0 = h->d0;
   const double up = std::ldexp(1.0, -23);
   auto gam = [&](double n) { return n * up / (1.0 - n * up); };
@@ -914,7 +921,8 @@ int prepare_sound(cv_bound* h, const cv_layer* layers, const float* x_lo, const 
   for (int p = 0; p < P; ++p) {
     std::vector<double> hm(d0);
     for (int j = 0; j < d0; ++j)
-      hm[j] = std::max(std::fabs((double)x_lo[(size_t)p * d0 + j]), std::fabs((double)x_hi[(size_t)p * d0 + j]));
+      hm[j] = l2x0 ? std::fabs((double)l2x0[(size_t)p * d0 + j]) + (double)l2eps[p]
+                   : std::max(std::fabs((double)x_lo[(size_t)p * d0 + j]), std::fabs((double)x_hi[(size_t)p * d0 + j]));
     int off = 0;
     for (int i = 1; i < L; ++i) {
       const cv_layer& ly = layers[i - 1];
@@ -967,6 +975,19 @@ int prepare_sound(cv_bound* h, const cv_layer* layers, const float* x_lo, const 
   }
   HIPCHK(hipMemcpyAsync(h->sw, sw.data(), sw.size() * sizeof(float), hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(h->err0, e0.data(), e0.size() * sizeof(float), hipMemcpyHostToDevice, s));
+  if (l2x0) {
+    std::vector<float> x0n(P);
+    for (int p = 0; p < P; ++p) {
+      double t = 0.0;
+      for (int j = 0; j < d0; ++j) t += (double)l2x0[(size_t)p * d0 + j] * l2x0[(size_t)p * d0 + j];
+      x0n[p] = round_up_f(std::sqrt(t) * (1.0 + 1e-12));
+    }
+    if (!h->x0n && (rc = h->mem.alloc(&h->x0n, P))) return rc;
+    HIPCHK(hipMemcpyAsync(h->x0n, x0n.data(), sizeof(float) * P, hipMemcpyHostToDevice, s));
+    // sum of squares within gam(chain) relative, the square root and the
+    // product each within an ulp
+    h->l2fac = round_up_f((1.0 + gam(chain)) * (1.0 + 4.0 * up));
+  }
   HIPCHK(hipStreamSynchronize(s));
   h->sound_g = round_up_f(G);
   h->sound_scale = round_up_f(1.0 + 2.0 * gam(chain));
@@ -1148,7 +1169,7 @@ int enqueue_bwd(cv_bound* h, const float* alpha, const float* beta, bool grad, f
     cur ^= 1;
   }
   if (pf) pf->begin("finalize", 0, (double)h->R * (slot + 2) * 4.0);
-  const L2Final l2f{h->bt.prop, h->m, h->l2eps, h->l2s};
+  const L2Final l2f{h->bt.prop, h->m, h->l2eps, h->l2s, h->x0n, h->sound_g, h->l2fac};
   launch_finalize(h->part, h->sound ? h->perr : nullptr, h->sound_scale, h->l2 ? h->psq : nullptr, l2f, h->n_slots,
                   slot, h->R, lb, best, first, s);
   if (pf) pf->end();
@@ -1452,7 +1473,8 @@ int set_parts(cv_bound* h, int n) {
     const cv_bound::Inputs& in = *h->in;
     for (cv_bound* q : h->parts) {
       int rc = prepare_sound(q, in.layers.data(), in.xlo.data(), in.xhi.data(), in.l.data(), in.u.data(),
-                             in.C.data(), false, nullptr);
+                             in.C.data(), false, nullptr, h->l2 ? h->hl2x0.data() : nullptr,
+                             h->l2 ? h->hl2eps.data() : nullptr);
       if (rc) return rc;
       q->sound = true;
       q->bt.sw = q->sw;
@@ -1482,6 +1504,24 @@ int for_parts(cv_bound* h, hipStream_t s, F f) {
     if (rc) return rc;
     HIPCHK(hipEventRecord(h->pev[i], h->pstream[i]));
     HIPCHK(hipStreamWaitEvent(s, h->pev[i], 0));
+  }
+  return CV_OK;
+}
+
+// Sound mode on for h and its sub-batches, the margin's weights built for the
+// current input sets (boxes, or the balls set by cv_bound_set_input_l2).
+int rebuild_sound(cv_bound* h, hipStream_t s) {
+  const cv_bound::Inputs& in = *h->in;
+  std::vector<cv_bound*> all{h};
+  all.insert(all.end(), h->parts.begin(), h->parts.end());
+  for (cv_bound* q : all) {
+    int rc = prepare_sound(q, in.layers.data(), in.xlo.data(), in.xhi.data(), in.l.data(), in.u.data(), in.C.data(),
+                           false, s, h->l2 ? h->hl2x0.data() : nullptr, h->l2 ? h->hl2eps.data() : nullptr);
+    if (rc) return rc;
+    q->sound = true;
+    q->bt.sw = q->sw;
+    q->bt.sg = q->sound_g;
+    drop_graph(q);
   }
   return CV_OK;
 }
@@ -1934,20 +1974,12 @@ int cv_bound_set_tiling(cv_bound* h, int32_t tiling) {
 int cv_bound_set_sound(cv_bound* h, int32_t on, void* stream) {
   if (!h || !h->in) return fail(CV_EINVAL, "null handle");
   if (on != 0 && on != 1) return fail(CV_EINVAL, "sound must be 0 or 1");
-  if (on && h->l2) return fail(CV_EINVAL, "sound mode covers box input sets only");
-  // the sub-batch handles share the parent's network, boxes and root bounds
-  const cv_bound::Inputs& in = *h->in;
+  if (on) return rebuild_sound(h, (hipStream_t)stream);
   std::vector<cv_bound*> all{h};
   all.insert(all.end(), h->parts.begin(), h->parts.end());
   for (cv_bound* q : all) {
-    if (on && !q->sw) {
-      int rc = prepare_sound(q, in.layers.data(), in.xlo.data(), in.xhi.data(), in.l.data(), in.u.data(),
-                             in.C.data(), false, (hipStream_t)stream);
-      if (rc) return rc;
-    }
-    q->sound = on != 0;
-    q->bt.sw = q->sound ? q->sw : nullptr;
-    q->bt.sg = q->sound_g;
+    q->sound = false;
+    q->bt.sw = nullptr;
     drop_graph(q);
   }
   return CV_OK;
@@ -1965,10 +1997,9 @@ int cv_bound_set_input_l2(cv_bound* h, const float* x0, const float* eps, void* 
       q->bt.l2eps = nullptr;
       drop_graph(q);
     }
-    return CV_OK;
+    return h->sound ? rebuild_sound(h, s) : CV_OK;
   }
   if (!eps) return fail(CV_EINVAL, "null argument");
-  if (h->sound) return fail(CV_EINVAL, "sound mode covers box input sets only");
   const int P = h->P, d0 = h->d0, d1 = h->dims[1];
   for (int64_t i = 0; i < (int64_t)P * d0; ++i)
     if (!std::isfinite(x0[i])) return fail(CV_EINVAL, "x0 must be finite");
@@ -2008,7 +2039,9 @@ int cv_bound_set_input_l2(cv_bound* h, const float* x0, const float* eps, void* 
     q->bt.l2eps = h->l2eps;
     drop_graph(q);
   }
-  return CV_OK;
+  h->hl2x0.assign(x0, x0 + (size_t)P * d0);
+  h->hl2eps.assign(eps, eps + P);
+  return h->sound ? rebuild_sound(h, s) : CV_OK;
 }
 
 int cv_bound_profile(cv_bound* h, const float* alpha, const float* beta, int32_t reps, cv_kernel_stat* out,

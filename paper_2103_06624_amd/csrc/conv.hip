@@ -306,11 +306,15 @@ __global__ __launch_bounds__(256, MODE == kFwdX || MODE == kFwd ? 5 : 1) void co
     if (kBwd) {
       const float tot = block_sum(cst, red[0]);
       if (tid == 0) e.part[(int64_t)e.slot0 * M + row] = tot;
-      float* const p2 = e.perr ? e.perr : e.psq;  // rounding-error bound, or the sum of A(0)^2 (l2 ball)
+      // rounding-error bound, or the sum of A(0)^2 (l2 ball); with both modes
+      // on, the other array's slot gets 0
+      float* const p2 = MODE == kBwdConc && bt.l2x0 ? e.psq : (e.perr ? e.perr : e.psq);
+      float* const pz = e.perr && e.psq ? (p2 == e.perr ? e.psq : e.perr) : nullptr;
       if (p2) {
         const float ter = block_sum(cer, red[1]);
         if (tid == 0) p2[(int64_t)e.slot0 * M + row] = ter;
       }
+      if (pz && tid == 0) pz[(int64_t)e.slot0 * M + row] = 0.f;
     }
     // the next row's input (every wave is past this row's GEMM)
     if (nrow < M) {

@@ -215,8 +215,11 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt(const float* __restrict__ A,
   auto epilogue = [&](const Ops& o, floatx4 (&acc)[FM][FN]) {
     if (MODE == kBwdRelax || MODE == kBwdConc) {
       // second per-row sum: the rounding-error bound (sound mode) or, when
-      // concretising over an l2 ball, the sum of A(0)^2 (the modes exclude each other)
-      float* const p2 = e.perr ? e.perr : e.psq;
+      // concretising over an l2 ball, the sum of A(0)^2; with both modes on,
+      // the other array's slot gets 0 (the l2 concretisation's own rounding is
+      // bounded at the final sum)
+      float* const p2 = MODE == kBwdConc && bt.l2x0 ? e.psq : (e.perr ? e.perr : e.psq);
+      float* const pz = e.perr && e.psq ? (p2 == e.perr ? e.psq : e.perr) : nullptr;
       float cst[FM][4], cer[FM][4];
 #pragma unroll
       for (int i = 0; i < FM; ++i) {
@@ -286,6 +289,7 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt(const float* __restrict__ A,
         if (row < M) {
           e.part[(int64_t)(e.slot0 + tn) * M + row] = red[0][t] + red[1][t];
           if (p2) p2[(int64_t)(e.slot0 + tn) * M + row] = rede[0][t] + rede[1][t];
+          if (pz) pz[(int64_t)(e.slot0 + tn) * M + row] = 0.f;
         }
       }
     } else if (MODE == kFwdTop) {

@@ -190,6 +190,10 @@ struct L2Final {
   int m;              // rows per subdomain
   const float* eps;   // [P] radius
   float* l2s;         // [n_rows] out: eps / ||A(0)||_2, or null
+  // sound mode: ||x0_p||_2 rounded up [P], the concretisation sum's error
+  // factor g, and fac >= 1 bounding the rounding of the norm (unused otherwise)
+  const float* x0n;
+  float g, fac;
 };
 // lb = sum of the used partial slots of each row; with perr (sound mode) minus
 // `scale` times the sum of the rounding-error partials, rounded outward; with

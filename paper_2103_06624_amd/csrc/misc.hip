@@ -159,12 +159,16 @@ __global__ __launch_bounds__(256) void top_k(TopArgs a) {
   }
   cst = wave_sum(cst);
   if (lane == 0) a.e.part[(int64_t)a.e.slot0 * a.bt.n_rows + row] = cst + a.Cb[ri.p * a.cb_pstride + ri.k];
-  if (a.e.perr) {
+  if (a.e.perr || a.e.psq) {
+    // cer: the rounding-error bound, or over an l2 ball with no ReLU layer the
+    // sum of A^2 (then the error slot keeps only the specification's error)
+    const bool sq = a.conc && a.bt.l2x0;
     cer = wave_sum(cer);
-    if (lane == 0) a.e.perr[(int64_t)a.e.slot0 * a.bt.n_rows + row] = cer + (a.err0 ? a.err0[ri.p * a.bt.m + ri.k] : 0.f);
-  } else if (a.e.psq) {  // zero unless the network has no ReLU layer
-    cer = wave_sum(cer);
-    if (lane == 0) a.e.psq[(int64_t)a.e.slot0 * a.bt.n_rows + row] = cer;
+    if (lane == 0) {
+      const int64_t at = (int64_t)a.e.slot0 * a.bt.n_rows + row;
+      if (a.e.perr) a.e.perr[at] = (sq ? 0.f : cer) + (a.err0 ? a.err0[ri.p * a.bt.m + ri.k] : 0.f);
+      if (a.e.psq) a.e.psq[at] = sq ? cer : 0.f;
+    }
   }
 }
 
@@ -195,8 +199,9 @@ __global__ __launch_bounds__(256) void fill_i32_k(int* p, int v, int64_t n) {
 // Sound mode (perr set): the rounding-error partials are summed the same way,
 // scaled by `scale` for their own rounding, and the bound is lowered by them,
 // each step rounded outward.  l2 ball (psq set): the partial sums of A(0)^2
-// give ||A(0)||_2 and the bound is lowered by eps_p ||A(0)||_2; l2s[row]
-// receives eps_p / ||A(0)||_2 (0 when A(0) = 0) for the adjoint's x*.
+// give ||A(0)||_2 and the bound is lowered by eps_p ||A(0)||_2 (in sound mode
+// by an upper bound on it, plus the concretisation sum's own rounding);
+// l2s[row] receives eps_p / ||A(0)||_2 (0 when A(0) = 0) for the adjoint's x*.
 __device__ __forceinline__ float slot_sum(const float* __restrict__ part, int n_used, int n_rows, int r, int g) {
   float s = 0.f;
   int t = g;
@@ -214,24 +219,35 @@ __device__ __forceinline__ float slot_sum(const float* __restrict__ part, int n_
 __global__ __launch_bounds__(256) void finalize_k(const float* __restrict__ part, const float* __restrict__ perr,
                                                   float scale, const float* __restrict__ psq, L2Final l2,
                                                   int n_used, int n_rows, float* lb, float* best, int first) {
-  __shared__ float red[4][64], rede[4][64];
+  __shared__ float red[4][64], rede[4][64], redq[4][64];
   const int rl = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int r = blockIdx.x * 64 + rl;
-  const float* p2 = perr ? perr : psq;
   red[g][rl] = r < n_rows ? slot_sum(part, n_used, n_rows, r, g) : 0.f;
-  if (p2) rede[g][rl] = r < n_rows ? slot_sum(p2, n_used, n_rows, r, g) : 0.f;
+  if (perr) rede[g][rl] = r < n_rows ? slot_sum(perr, n_used, n_rows, r, g) : 0.f;
+  if (psq) redq[g][rl] = r < n_rows ? slot_sum(psq, n_used, n_rows, r, g) : 0.f;
   __syncthreads();
   if (g == 0 && r < n_rows) {
     float tot = ((red[0][rl] + red[1][rl]) + red[2][rl]) + red[3][rl];
-    if (perr) {
-      const float err = nextafterf((((rede[0][rl] + rede[1][rl]) + rede[2][rl]) + rede[3][rl]) * scale, INFINITY);
-      tot = nextafterf(tot - err, -INFINITY);
-    } else if (psq) {
-      const float nrm = sqrtf(((rede[0][rl] + rede[1][rl]) + rede[2][rl]) + rede[3][rl]);
-      const float eps = l2.eps[l2.prop[r / l2.m]];
-      tot = fmaf(-eps, nrm, tot);
+    float err = 0.f;
+    if (perr) err = nextafterf((((rede[0][rl] + rede[1][rl]) + rede[2][rl]) + rede[3][rl]) * scale, INFINITY);
+    if (psq) {
+      const int p = l2.prop[r / l2.m];
+      const float nrm = sqrtf(((redq[0][rl] + redq[1][rl]) + redq[2][rl]) + redq[3][rl]);
+      const float eps = l2.eps[p];
       if (l2.l2s) l2.l2s[r] = nrm > 0.f ? eps / nrm : 0.f;
+      if (perr) {
+        // sound: ||A(0)||_2 <= nrm * fac (the sum of squares and the square
+        // root rounded), and the float sum A(0) x0 is off by at most
+        // g sum |a x0| <= g ||A(0)||_2 ||x0||_2
+        const float nup = nextafterf(nrm * l2.fac, INFINITY);
+        const float m2 = nextafterf(nextafterf(eps * nup, INFINITY) + nextafterf(l2.g * nup * l2.x0n[p], INFINITY),
+                                    INFINITY);
+        err = nextafterf(err + m2, INFINITY);
+      } else {
+        tot = fmaf(-eps, nrm, tot);
+      }
     }
+    if (perr) tot = nextafterf(tot - err, -INFINITY);
     if (lb) lb[r] = tot;
     if (best) best[r] = first ? tot : fmaxf(best[r], tot);
   }
