@@ -238,3 +238,32 @@ def test_l2_sound_mode_is_below_the_exact_bound(name):
     assert np.array_equal(pb2.eval(dev(alpha), dev(beta)).cpu().numpy(), lb)
     pb.set_sound(0)
     assert np.array_equal(pb.eval(dev(alpha), dev(beta)).cpu().numpy(), lb_plain)
+
+
+def test_l2_zero_radius_is_the_point():
+    """Degenerate balls (eps = 0): the bound matches the oracle, and the upper
+    bound is the network at x0 itself on every row (x* = x0), checked against
+    an FP64 forward pass."""
+    wl, orc, pb, x0, eps = problem("mlp_small")
+    z = np.zeros_like(eps)
+    pb.set_input_l2(x0, z)
+    orc_z = cases.small_l2_case("mlp_small")[5]
+    alpha, beta = cases.random_vars(orc, seed=26)
+    saved = orc_z.l2
+    try:
+        orc_z.set_l2(x0, z)
+        lb, ub, sat = [t.cpu().numpy() for t in pb.upper(dev(alpha), dev(beta))]
+        ref = np.stack([orc_z.eval(b, alpha, beta) for b in range(orc_z.B)])
+        assert guarded_rel(lb, ref).max() <= TOL
+    finally:
+        orc_z.l2 = saved
+    for b in range(orc.B):
+        p = int(orc.dom_prop[b])
+        h = x0[p].astype(np.float64)
+        for i, (W, bias) in enumerate(orc.net64):
+            h = W @ h + bias
+            if i < len(orc.net64) - 1:
+                h = np.maximum(h, 0.0)
+        assert guarded_rel(ub[b], orc.C[p] @ h).max() <= TOL
+    s1 = sat.astype(bool)  # where x0 meets the subdomain's splits
+    assert (lb[s1] <= ub[s1] + TOL * np.maximum(1.0, np.abs(ub[s1]))).all()
