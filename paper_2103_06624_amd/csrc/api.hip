@@ -307,6 +307,7 @@ struct HostPlan {
   std::vector<int4> mt, kt, nt;
   std::vector<float> wm;
   ConvPlan p{};
+  int M = 0, K = 0;  // GEMM rows and columns before padding
 };
 
 // Pad the tables to whole tiles and lay out Wm (value wv(k, n) for k < K,
@@ -314,6 +315,8 @@ struct HostPlan {
 template <class F>
 void plan_pad(HostPlan& o, int M, int K, int N, F wv) {
   ConvPlan& p = o.p;
+  o.M = M;
+  o.K = K;
   p.mpad = r16(M);
   p.kpad = r16(K);  // the kernel takes four K steps of 4 per pass
   const int tiles = (N + 15) / 16;
@@ -328,6 +331,45 @@ void plan_pad(HostPlan& o, int M, int K, int N, F wv) {
         const int k = ks * 4 + l / 16, n = t * 16 + l % 16;
         if (k < K && n < N) o.wm[((size_t)ks * p.nt + t) * 64 + l] = wv(k, n);
       }
+}
+
+// Turn the gather tables (row origin (y, x) in mt, column offset (dy, dx)
+// and channel base in kt) into flat offsets into the staged row, whose
+// channel planes get a zero border wide enough for every tap the GEMM reads.
+void plan_border(HostPlan& o) {
+  ConvPlan& p = o.p;
+  const int plane = p.gh * p.gw, C = p.din / plane;
+  int y0 = INT32_MAX, y1 = INT32_MIN, x0 = INT32_MAX, x1 = INT32_MIN, dy0 = INT32_MAX, dy1 = INT32_MIN,
+      dx0 = INT32_MAX, dx1 = INT32_MIN;
+  for (int m = 0; m < o.M; ++m) {
+    y0 = std::min(y0, o.mt[m].x);
+    y1 = std::max(y1, o.mt[m].x);
+    x0 = std::min(x0, o.mt[m].y);
+    x1 = std::max(x1, o.mt[m].y);
+  }
+  for (int k = 0; k < o.K; ++k) {
+    dy0 = std::min(dy0, o.kt[k].x);
+    dy1 = std::max(dy1, o.kt[k].x);
+    dx0 = std::min(dx0, o.kt[k].y);
+    dx1 = std::max(dx1, o.kt[k].y);
+  }
+  const int bly = std::max(0, -(y0 + dy0)), bhy = std::max(0, y1 + dy1 - (p.gh - 1));
+  const int blx = std::max(0, -(x0 + dx0)), bhx = std::max(0, x1 + dx1 - (p.gw - 1));
+  p.gwp = p.gw + blx + bhx;
+  p.pplane = (p.gh + bly + bhy) * p.gwp;
+  p.bofs = bly * p.gwp + blx;
+  p.dinp = C * p.pplane;
+  p.mgp = (unsigned)((((uint64_t)1 << 32) + plane - 1) / plane);
+  p.mgw = (unsigned)((((uint64_t)1 << 32) + p.gw - 1) / p.gw);
+  const int4 e0 = o.mt[0];
+  for (int m = 0; m < p.mpad; ++m) {  // padding rows reuse row 0's window
+    const int4 e = m < o.M ? o.mt[m] : e0;
+    o.mt[m] = make_int4((e.x + bly) * p.gwp + (e.y + blx), 0, o.mt[m].z, o.mt[m].w);
+  }
+  for (int k = 0; k < p.kpad; ++k) {  // padding columns (zero weights) read row m's own origin
+    const int4 e = o.kt[k];
+    o.kt[k] = make_int4(k < o.K ? (e.z / plane) * p.pplane + e.x * p.gwp + e.y : 0, 0, 0, 0);
+  }
 }
 
 // Back-substitution through conv layer ly (transposed convolution), polyphase
@@ -355,6 +397,7 @@ void plan_convt(const cv_layer& ly, HostPlan& o) {
     for (int n = 0; n < N; ++n) o.nt[n] = make_int4(-pad, n / ci, (n % ci) * hi * wi, 0);
     p.osy = 1;
     p.osx = 2;
+    plan_border(o);
     return;
   }
   std::vector<int> k0(s), T(s);
@@ -393,6 +436,7 @@ void plan_convt(const cv_layer& ly, HostPlan& o) {
   }
   p.osy = s;
   p.osx = s;
+  plan_border(o);
 }
 
 // The forward convolution of ly: GEMM rows (oy, ox), K = (ci, ky, kx), N = co;
@@ -422,6 +466,7 @@ void plan_conv(const cv_layer& ly, HostPlan& o) {
     for (int kk = 0; kk < K; ++kk) o.kt[kk] = make_int4((kk / kf) % k, kk % kf, (kk / (k * kf)) * hi * wi, 0);
     for (int n = 0; n < 2 * co; ++n) o.nt[n] = make_int4(0, n / co, (n % co) * ho * wo, 0);
     p.osx = 2;
+    plan_border(o);
     return;
   }
   const int M = ho * wo, K = ci * k * k;
@@ -433,6 +478,7 @@ void plan_conv(const cv_layer& ly, HostPlan& o) {
   for (int kk = 0; kk < K; ++kk) o.kt[kk] = make_int4((kk / k) % k, kk % k, (kk / (k * k)) * hi * wi, 0);
   for (int n = 0; n < co; ++n) o.nt[n] = make_int4(0, 0, n * ho * wo, 0);
   p.osx = 1;
+  plan_border(o);
 }
 
 // Weight placement and LDS bytes of a built plan.

@@ -20,8 +20,9 @@
 //    k + s taps (k + 1 for a stride-1 transposed convolution) that the pair
 //    reads, and no MFMA column is left empty.
 // G is gathered from the row's input staged in LDS through per-row and
-// per-column offset tables; a tap outside the plane reads a zero slot, so
-// the zero padding is exact.  The results are scattered into an LDS copy of
+// per-column offset tables: each channel plane is staged inside a zero
+// border as wide as the farthest tap, so a gather is one add and one LDS
+// read and the zero padding is exact.  The results are scattered into an LDS copy of
 // the output row (each output position has exactly one (m, n)), and the
 // layer's epilogue (relaxation, concretisation, adjoint step) then walks the
 // row in natural order with coalesced global traffic.  Workgroups are
@@ -89,9 +90,19 @@ __device__ __forceinline__ void in_load(const float* zin, int ldi, const Batch& 
   }
 }
 
+// Staged slot of input float t: channel plane c = t / (gh gw) and position
+// (y, x) inside it, shifted into the zero-bordered layout (exact division by
+// multiply-high with ceil(2^32 / d), valid for t < 2^32 / d).
+__device__ __forceinline__ int staged(const ConvPlan& pl, int t) {
+  const int c = __umulhi((unsigned)t, pl.mgp);
+  const int rem = t - c * (pl.gh * pl.gw);
+  const int y = __umulhi((unsigned)rem, pl.mgw);
+  return c * pl.pplane + pl.bofs + y * pl.gwp + (rem - y * pl.gw);
+}
+
 template <int MODE>
-__device__ __forceinline__ void in_store(float* zi, const Batch& bt, const Vars& v, int row, int t0, int din,
-                                         const float (&s1)[kPF], const float (&s2)[kPF]) {
+__device__ __forceinline__ void in_store(float* zi, const ConvPlan& pl, const Batch& bt, const Vars& v, int row,
+                                         int t0, int din, const float (&s1)[kPF], const float (&s2)[kPF]) {
   if (MODE == kFwdX) {
     uint64_t wp[kPF], wn[kPF];
 #pragma unroll
@@ -103,25 +114,30 @@ __device__ __forceinline__ void in_store(float* zi, const Batch& bt, const Vars&
 #pragma unroll
     for (int u = 0; u < kPF; ++u) {
       const int t = t0 + (int)threadIdx.x + 256 * u;
-      if (t < din) zi[t] = xstar((wp[u] >> (t & 63)) & 1, (wn[u] >> (t & 63)) & 1, s1[u], s2[u]);
+      if (t < din) zi[staged(pl, t)] = xstar((wp[u] >> (t & 63)) & 1, (wn[u] >> (t & 63)) & 1, s1[u], s2[u]);
     }
   } else {
 #pragma unroll
     for (int u = 0; u < kPF; ++u) {
       const int t = t0 + (int)threadIdx.x + 256 * u;
-      if (t < din) zi[t] = s1[u];
+      if (t < din) zi[staged(pl, t)] = s1[u];
     }
   }
 }
 
-// The forward modes ask for five waves per SIMD (at most 102 VGPRs): measured
-// 10-17 % faster than the compiler's own choice; the back-substitution modes
-// measured no better with it.  WG: the weight matrix is read from global
-// memory (L1/L2) instead of LDS, for matrices too large to leave room for
-// more than two workgroups per CU (measured 25-29 % faster there, 5-8 %
-// slower for small matrices).
+// Waves per SIMD asked of the compiler (register budget), as measured best:
+// five for the forward modes with one N tile, four with several N tiles,
+// the compiler's own choice for back-substitution with one.
+template <int MODE, int NT>
+constexpr int conv_occupancy() {
+  return (MODE == kFwdX || MODE == kFwd) ? (NT == 1 ? 5 : 4) : (NT >= 2 ? 4 : 1);
+}
+
+// WG: the weight matrix is read from global memory (L1/L2) instead of LDS,
+// for matrices too large to leave room for more than two workgroups per CU
+// (measured 25-29 % faster there, 5-8 % slower for small matrices).
 template <int MODE, int NT, bool WG>
-__global__ __launch_bounds__(256, MODE == kFwdX || MODE == kFwd ? 5 : 1) void conv_mm(const float* __restrict__ zin, int ldi, ConvPlan pl, int M, int last,
+__global__ __launch_bounds__(256, (conv_occupancy<MODE, NT>())) void conv_mm(const float* __restrict__ zin, int ldi, ConvPlan pl, int M, int last,
                                                Batch bt, Vars v, Epi e) {
   extern __shared__ float4 smem4[];
   __shared__ float red[2][4];
@@ -132,14 +148,15 @@ __global__ __launch_bounds__(256, MODE == kFwdX || MODE == kFwd ? 5 : 1) void co
   int4* const kt = mt + pl.mpad;
   int4* const ntb = kt + pl.kpad;
   float* const zi = reinterpret_cast<float*>(ntb + NT * 16);
-  float* const zo = zi + ((pl.din + 4) & ~3);
+  float* const zo = zi + ((pl.dinp + 3) & ~3);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
   for (int t = tid; t < nwm / 4; t += 256) smem4[t] = reinterpret_cast<const float4*>(pl.wm)[t];
   for (int t = tid; t < pl.mpad; t += 256) mt[t] = pl.mtab[t];
   for (int t = tid; t < pl.kpad; t += 256) kt[t] = pl.ktab[t];
   for (int t = tid; t < NT * 16; t += 256) ntb[t] = pl.ntab[t];
-  if (tid == 0) zi[pl.din] = 0.f;  // the zero slot of out-of-plane taps
+  for (int t = tid; t < pl.dinp; t += 256) zi[t] = 0.f;  // the borders stay zero: out-of-plane taps
+  __syncthreads();  // before any thread stages a row over the zeroed planes
 
   // the first row's input; later rows' inputs are loaded during the previous
   // row's GEMM and stored after its epilogue
@@ -148,7 +165,7 @@ __global__ __launch_bounds__(256, MODE == kFwdX || MODE == kFwd ? 5 : 1) void co
   if (row < M)
     for (int t0 = 0; t0 < pl.din; t0 += 256 * kPF) {
       in_load<MODE>(zin, ldi, bt, row, t0, pl.din, s1, s2);
-      in_store<MODE>(zi, bt, v, row, t0, pl.din, s1, s2);
+      in_store<MODE>(zi, pl, bt, v, row, t0, pl.din, s1, s2);
     }
   __syncthreads();
 
@@ -199,11 +216,7 @@ __global__ __launch_bounds__(256, MODE == kFwdX || MODE == kFwd ? 5 : 1) void co
             for (int t = 0; t < NT; ++t) b[q][t] = wl[((ks0 + q) * NT + t) * 64];
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int yy = me.x + ke[q].x, xx = me.y + ke[q].y;
-          const bool ok = (unsigned)yy < (unsigned)pl.gh && (unsigned)xx < (unsigned)pl.gw;
-          a[q] = zi[ok ? ke[q].z + yy * pl.gw + xx : pl.din];
-        }
+        for (int q = 0; q < 4; ++q) a[q] = zi[me.x + ke[q].x];
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -318,10 +331,10 @@ __global__ __launch_bounds__(256, MODE == kFwdX || MODE == kFwd ? 5 : 1) void co
     }
     // the next row's input (every wave is past this row's GEMM)
     if (nrow < M) {
-      in_store<MODE>(zi, bt, v, nrow, 0, pl.din, s1, s2);
+      in_store<MODE>(zi, pl, bt, v, nrow, 0, pl.din, s1, s2);
       for (int t0 = 256 * kPF; t0 < pl.din; t0 += 256 * kPF) {
         in_load<MODE>(zin, ldi, bt, nrow, t0, pl.din, s1, s2);
-        in_store<MODE>(zi, bt, v, nrow, t0, pl.din, s1, s2);
+        in_store<MODE>(zi, pl, bt, v, nrow, t0, pl.din, s1, s2);
       }
     }
     __syncthreads();
@@ -378,7 +391,7 @@ int dispatch(const ConvArgs& a, hipStream_t st) {
 }  // namespace
 
 int conv_plan_smem(const ConvPlan& pl) {
-  return ((pl.wg ? 0 : pl.kpad * pl.nt * 16) + ((pl.din + 4) & ~3) + pl.dout) * (int)sizeof(float) +
+  return ((pl.wg ? 0 : pl.kpad * pl.nt * 16) + ((pl.dinp + 3) & ~3) + pl.dout) * (int)sizeof(float) +
          (pl.mpad + pl.kpad + pl.nt * 16) * (int)sizeof(int4);
 }
 

@@ -71,20 +71,24 @@ struct ConvGeom {
   int ci, hi, wi, co, ho, wo, k, s, p;
 };
 // One direction of a conv layer as an implicit GEMM per batch row,
-// D[m, n] = sum_k G[m, k] Wm[k, n] (conv.hip).  G gathers the row's input
-// plane: element (m, k) is input[k.z + (m.x + k.x) * gw + (m.y + k.y)] when
-// (m.x + k.x, m.y + k.y) lies in the gh x gw plane, else 0.  D[m, n] is
+// D[m, n] = sum_k G[m, k] Wm[k, n] (conv.hip).  The row's input is staged
+// in LDS with a zero border around each gh x gw channel plane (padded row
+// width gwp, padded plane pplane, interior origin bofs), so that G[m, k] is
+// staged[m.x + k.x] with no range check.  D[m, n] is
 // output[n.z + (osy * m.z + n.x) * ow + (osx * m.w + n.y)] when that lies in
 // the oh x ow plane and n.z >= 0.  Device tables, built once per layer.
 struct ConvPlan {
-  const int4* mtab;  // [mpad] gather origin (x, y) and output origin (z, w) of GEMM row m
-  const int4* ktab;  // [kpad] gather offset (x, y) and channel base z of GEMM column k
+  const int4* mtab;  // [mpad] gather offset x and output origin (z, w) of GEMM row m
+  const int4* ktab;  // [kpad] gather offset x of GEMM column k
   const int4* ntab;  // [16 nt] output offset (x, y) and channel base z (-1: padding)
   const float* wm;   // [kpad / 4][nt][64] Wm in MFMA 16x16x4 operand order
   int mpad, kpad, nt;  // multiples of 16; nt: 16-column tiles (1, 2, 4 or 8)
   int gh, gw;          // gathered plane
   int oh, ow, osy, osx;  // output plane and its stride factors
-  int din, dout;       // staged input and output floats per row
+  int din, dout;       // input and output floats per row
+  int dinp;            // staged floats per row (with the zero borders)
+  int gwp, pplane, bofs;  // padded row width, padded plane, offset of the interior origin
+  unsigned mgp, mgw;   // ceil(2^32 / (gh gw)), ceil(2^32 / gw): exact division of staging indices
   int wg;              // 1: the kernel reads wm from global memory, not LDS
   int grid;            // persistent workgroups
   int smem;            // dynamic LDS bytes
