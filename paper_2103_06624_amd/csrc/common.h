@@ -168,22 +168,18 @@ __device__ __forceinline__ RowInfo row_info(const Batch& bt, int r) {
 // acomp is set (the adjoint needs the branch and the value).
 __device__ __forceinline__ float relax_value(const Batch& bt, const Vars& v, const RowInfo& ri, uint32_t rec,
                                              float2 ch, float coef, float a, float bias, float* cst) {
+  // written as selects (no divergent branches); the same operations as the
+  // case analysis: active a, inactive 0, unstable alpha a (a >= 0) or the
+  // chord a u/(u-l) with a (-ul/(u-l)) into the constant, split a - beta
+  // (z >= 0: D = 1, S = -1) or beta (z < 0: D = 0, S = +1); coef is alpha
+  // for an unstable neuron and beta for a split one
   const uint32_t kind = rec & kKindMask;
-  float lam;
-  if (kind == kActive) {
-    lam = a;
-  } else if (kind == kInactive) {
-    lam = 0.f;
-  } else if (kind == kUnstable) {
-    if (a >= 0.f) {
-      lam = coef * a;  // coef = alpha
-    } else {
-      lam = a * ch.x;
-      *cst = fmaf(a, ch.y, *cst);
-    }
-  } else {
-    lam = (rec & kSidePos) ? a - coef : coef;  // coef = beta; D = 1, S = -1 / D = 0, S = +1
-  }
+  const bool uns = kind == kUnstable;
+  const bool neg = uns && !(a >= 0.f);
+  float lam = kind == kActive ? a : 0.f;
+  lam = uns ? (neg ? a * ch.x : coef * a) : lam;
+  lam = kind == kSplit ? ((rec & kSidePos) ? a - coef : coef) : lam;
+  *cst = neg ? fmaf(a, ch.y, *cst) : *cst;
   *cst = fmaf(lam, bias, *cst);
   return lam;
 }
