@@ -72,10 +72,12 @@ __device__ __forceinline__ void epi_first(const Batch& bt, const Epi& e, int row
 }
 
 // Input floats t = t0 + tid + 256 u of a row: the row of zin, or for a conv
-// first layer's adjoint step the box (x* then takes the sign planes too).
+// first layer's adjoint step the box and the 32-bit words of the sign planes
+// of A(0) that hold bit t (x* is formed when the row is staged).
 template <int MODE>
-__device__ __forceinline__ void in_load(const float* zin, int ldi, const Batch& bt, int row, int t0, int din,
-                                        float (&s1)[kPF], float (&s2)[kPF]) {
+__device__ __forceinline__ void in_load(const float* zin, int ldi, const Batch& bt, const Vars& v, int row, int t0,
+                                        int din, float (&s1)[kPF], float (&s2)[kPF], uint32_t (&w1)[kPF],
+                                        uint32_t (&w2)[kPF]) {
   const int p = MODE == kFwdX ? bt.prop[row / bt.m] : 0;
 #pragma unroll
   for (int u = 0; u < kPF; ++u) {
@@ -83,6 +85,9 @@ __device__ __forceinline__ void in_load(const float* zin, int ldi, const Batch& 
     if (MODE == kFwdX) {
       s1[u] = bt.xlo[(int64_t)p * bt.d0 + tc];
       s2[u] = bt.xhi[(int64_t)p * bt.d0 + tc];
+      // bit t of a plane's row: bit t % 32 of its 32-bit word t / 32
+      w1[u] = reinterpret_cast<const uint32_t*>(v.xpos)[(int64_t)row * 2 * bt.w64 + (tc >> 5)];
+      w2[u] = reinterpret_cast<const uint32_t*>(v.xneg)[(int64_t)row * 2 * bt.w64 + (tc >> 5)];
     } else {
       s1[u] = zin[(int64_t)row * ldi + tc];
       s2[u] = 0.f;
@@ -102,19 +107,13 @@ __device__ __forceinline__ int staged(const ConvPlan& pl, int t) {
 
 template <int MODE>
 __device__ __forceinline__ void in_store(float* zi, const ConvPlan& pl, const Batch& bt, const Vars& v, int row,
-                                         int t0, int din, const float (&s1)[kPF], const float (&s2)[kPF]) {
+                                         int t0, int din, const float (&s1)[kPF], const float (&s2)[kPF],
+                                         const uint32_t (&w1)[kPF], const uint32_t (&w2)[kPF]) {
   if (MODE == kFwdX) {
-    uint64_t wp[kPF], wn[kPF];
-#pragma unroll
-    for (int u = 0; u < kPF; ++u) {
-      const int tc = min(t0 + (int)threadIdx.x + 256 * u, din - 1);
-      wp[u] = v.xpos[(int64_t)row * bt.w64 + (tc >> 6)];
-      wn[u] = v.xneg[(int64_t)row * bt.w64 + (tc >> 6)];
-    }
 #pragma unroll
     for (int u = 0; u < kPF; ++u) {
       const int t = t0 + (int)threadIdx.x + 256 * u;
-      if (t < din) zi[staged(pl, t)] = xstar((wp[u] >> (t & 63)) & 1, (wn[u] >> (t & 63)) & 1, s1[u], s2[u]);
+      if (t < din) zi[staged(pl, t)] = xstar((w1[u] >> (t & 31)) & 1, (w2[u] >> (t & 31)) & 1, s1[u], s2[u]);
     }
   } else {
 #pragma unroll
@@ -126,11 +125,12 @@ __device__ __forceinline__ void in_store(float* zi, const ConvPlan& pl, const Ba
 }
 
 // Waves per SIMD asked of the compiler (register budget), as measured best:
-// five for the forward modes with one N tile, four with several N tiles,
-// the compiler's own choice for back-substitution with one.
+// four for the first layer's forward step (five spills its prefetched sign
+// words), five for the other forward steps with one N tile and four with
+// several, the compiler's own choice for back-substitution with one.
 template <int MODE, int NT>
 constexpr int conv_occupancy() {
-  return (MODE == kFwdX || MODE == kFwd) ? (NT == 1 ? 5 : 4) : (NT >= 2 ? 4 : 1);
+  return MODE == kFwdX ? 4 : MODE == kFwd ? (NT == 1 ? 5 : 4) : (NT >= 2 ? 4 : 1);
 }
 
 // WG: the weight matrix is read from global memory (L1/L2) instead of LDS,
@@ -161,11 +161,12 @@ __global__ __launch_bounds__(256, (conv_occupancy<MODE, NT>())) void conv_mm(con
   // the first row's input; later rows' inputs are loaded during the previous
   // row's GEMM and stored after its epilogue
   float s1[kPF], s2[kPF];
+  uint32_t w1[kPF], w2[kPF];
   int row = blockIdx.x;
   if (row < M)
     for (int t0 = 0; t0 < pl.din; t0 += 256 * kPF) {
-      in_load<MODE>(zin, ldi, bt, row, t0, pl.din, s1, s2);
-      in_store<MODE>(zi, pl, bt, v, row, t0, pl.din, s1, s2);
+      in_load<MODE>(zin, ldi, bt, v, row, t0, pl.din, s1, s2, w1, w2);
+      in_store<MODE>(zi, pl, bt, v, row, t0, pl.din, s1, s2, w1, w2);
     }
   __syncthreads();
 
@@ -177,7 +178,7 @@ __global__ __launch_bounds__(256, (conv_occupancy<MODE, NT>())) void conv_mm(con
     uint32_t rec[kPF];
     float b1[kPF], b2[kPF];
     epi_first<MODE>(bt, e, row, p, 0, pl.dout, rec, b1, b2);
-    if (nrow < M) in_load<MODE>(zin, ldi, bt, nrow, 0, pl.din, s1, s2);
+    if (nrow < M) in_load<MODE>(zin, ldi, bt, v, nrow, 0, pl.din, s1, s2, w1, w2);
 
     // ---- the GEMM: one 16-row tile of m per wave at a time, all N tiles
     for (int mtile = wave; mtile < n_mt; mtile += 4) {
@@ -244,7 +245,14 @@ __global__ __launch_bounds__(256, (conv_occupancy<MODE, NT>())) void conv_mm(con
     const int64_t pc0 = (int64_t)p * bt.nd + e.layer_off;
     float cst = 0.f, cer = 0.f;
     for (int j0 = 0; j0 < pl.dout; j0 += 256 * kPF) {
-      if (j0 > 0) epi_first<MODE>(bt, e, row, p, j0, pl.dout, rec, b1, b2);
+      // concretisation loads the next chunk's box one chunk ahead (measured
+      // faster there; slower for the modes with second-level gathers)
+      constexpr bool kAhead = MODE == kBwdConc;
+      uint32_t rn[kPF];
+      float bn1[kPF], bn2[kPF];
+      const bool more = j0 + 256 * kPF < pl.dout;
+      if (kAhead && more) epi_first<MODE>(bt, e, row, p, j0 + 256 * kPF, pl.dout, rn, bn1, bn2);
+      if (!kAhead && j0 > 0) epi_first<MODE>(bt, e, row, p, j0, pl.dout, rec, b1, b2);
 #pragma unroll
       for (int h = 0; h < kPF; h += kEU) {
         float a[kEU], al[kEU], be[kEU], sw[kEU], bias[kEU];
@@ -315,6 +323,14 @@ __global__ __launch_bounds__(256, (conv_occupancy<MODE, NT>())) void conv_mm(con
           }
         }
       }
+      if (kAhead && more) {
+#pragma unroll
+        for (int u = 0; u < kPF; ++u) {
+          rec[u] = rn[u];
+          b1[u] = bn1[u];
+          b2[u] = bn2[u];
+        }
+      }
     }
     if (kBwd) {
       const float tot = block_sum(cst, red[0]);
@@ -331,10 +347,10 @@ __global__ __launch_bounds__(256, (conv_occupancy<MODE, NT>())) void conv_mm(con
     }
     // the next row's input (every wave is past this row's GEMM)
     if (nrow < M) {
-      in_store<MODE>(zi, pl, bt, v, nrow, 0, pl.din, s1, s2);
+      in_store<MODE>(zi, pl, bt, v, nrow, 0, pl.din, s1, s2, w1, w2);
       for (int t0 = 256 * kPF; t0 < pl.din; t0 += 256 * kPF) {
-        in_load<MODE>(zin, ldi, bt, nrow, t0, pl.din, s1, s2);
-        in_store<MODE>(zi, pl, bt, v, nrow, t0, pl.din, s1, s2);
+        in_load<MODE>(zin, ldi, bt, v, nrow, t0, pl.din, s1, s2, w1, w2);
+        in_store<MODE>(zi, pl, bt, v, nrow, t0, pl.din, s1, s2, w1, w2);
       }
     }
     __syncthreads();
