@@ -315,6 +315,7 @@ def make(name: str, n_props: Optional[int] = None, n_dom: Optional[int] = None) 
         "cnn_wide": dict(seed=4),
         "cnn_deep": dict(seed=5),
         "tiny2d": dict(seed=11),
+        "cnn_odd": dict(seed=12),
     }
     if name not in specs:
         raise KeyError(name)
@@ -336,6 +337,9 @@ def make(name: str, n_props: Optional[int] = None, n_dom: Optional[int] = None) 
     elif name == "cnn_deep":
         net = cnn(wr, (3, 32, 32), [(8, 4, 2, 1), (8, 3, 1, 1), (8, 3, 1, 1), (8, 4, 2, 1)], [100, 10])
         P, per, depth = 64, None, (1, 16)
+    elif name == "cnn_odd":  # non-square planes, odd kernels and sizes that fill no tile or word evenly
+        net = cnn(wr, (3, 11, 13), [(5, 3, 2, 1), (7, 3, 1, 0)], [20, 10])
+        P, per, depth = 2, [10, 9], (1, 6)
     else:  # tiny2d: 2-D input, used by the brute-force pins
         net = mlp(wr, [2, 6, 6, 2])
         P, per, depth = 1, [4], (1, 3)

@@ -21,6 +21,7 @@ SMALL = {
     "cnn_base": dict(n_dom=24),
     "cnn_wide": dict(n_props=2, n_dom=22),
     "cnn_deep": dict(n_props=3, n_dom=21),
+    "cnn_odd": dict(),
 }
 
 

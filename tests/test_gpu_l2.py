@@ -43,7 +43,7 @@ def problem(name):
     return wl, orc, pb, x0, eps
 
 
-@pytest.mark.parametrize("name", ["mlp_small", "mlp_deep", "cnn_base", "cnn_deep"])
+@pytest.mark.parametrize("name", ["mlp_small", "mlp_deep", "cnn_base", "cnn_deep", "cnn_odd"])
 def test_l2_eval_parity(name):
     say("l2 eval parity", name)
     wl, orc, pb, _, _ = problem(name)
@@ -55,7 +55,7 @@ def test_l2_eval_parity(name):
     assert err.max() <= TOL
 
 
-@pytest.mark.parametrize("name", ["mlp_small", "cnn_base"])
+@pytest.mark.parametrize("name", ["mlp_small", "cnn_base", "cnn_odd"])
 def test_l2_grad_parity(name):
     """Bound and gradients at random (alpha, beta).  Rows are compared where
     no hidden-layer sign decision is within float32 reach of a kink (the

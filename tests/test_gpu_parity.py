@@ -338,7 +338,8 @@ def test_plan_rejects_bad_values():
 
 
 @pytest.mark.parametrize("name,plan", [("mlp_small", None), ("mlp_deep", None), ("cnn_base", None),
-                                       ("cnn_deep", None), ("mlp_deep", (0, 0)), ("cnn_deep", (0, 0))])
+                                       ("cnn_deep", None), ("cnn_odd", None), ("mlp_deep", (0, 0)),
+                                       ("cnn_deep", (0, 0))])
 def test_optimize_parity(name, plan):
     say("optimize parity", name, plan)
     wl, orc, pb = problem(name)
