@@ -112,3 +112,15 @@ def test_conv_limits_rejected_before_any_device_call(shape, msg):
     wl, lo, up = _tiny()
     rc, err = _init(wl, lo, up, [0], [0, 0], [], [], [], layers=net.layers)
     assert rc == B.CV_ESHAPE and msg in err, (rc, err)
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without the built library every entry point raises: the product path
+    has no CPU fallback."""
+    monkeypatch.setattr(B, "LIB_PATH", str(tmp_path / "libcvbound.so"))
+    monkeypatch.setattr(B, "_lib", None)
+    with pytest.raises(RuntimeError, match="is missing"):
+        B.lib()
+    for name in B.SIGNATURES:
+        with pytest.raises(RuntimeError, match="is missing"):
+            getattr(B, name)()
