@@ -388,8 +388,16 @@ def test_alpha_layout_matches_documentation():
     assert pb.n_alpha == orc.n_alpha and pb.n_beta == orc.nnz * orc.m
 
 
-def test_deterministic_and_graph_replay():
-    wl, orc, pb = problem("mlp_deep")
+@pytest.mark.parametrize("name,nparts", [("mlp_deep", None), ("mlp_deep", 2), ("cnn_odd", 3)])
+def test_deterministic_and_graph_replay(name, nparts):
+    """The optimiser's first call runs its loop directly, later calls replay
+    the captured graph(s) (one per concurrent sub-batch): every replay, with
+    eager work and synchronisations in between, equals the first call bit for
+    bit."""
+    say("graph replay", name, nparts)
+    wl, orc, pb = problem(name)
+    if nparts is not None:
+        pb.set_parts(nparts)
     alpha, beta = cases.random_vars(orc, seed=3)
     x1 = pb.eval(dev(alpha), dev(beta)).cpu().numpy()
     x2 = pb.eval(dev(alpha), dev(beta)).cpu().numpy()
