@@ -162,7 +162,12 @@ __global__ __launch_bounds__(256, (conv_occupancy<MODE, NT>())) void conv_mm(con
   // row's GEMM and stored after its epilogue
   float s1[kPF], s2[kPF];
   uint32_t w1[kPF], w2[kPF];
+  // XCD-aware row order: workgroups are dealt round-robin over the 8 XCDs, so
+  // the logical index (b mod 8) (G / 8) + b / 8 gives each XCD a contiguous
+  // block of rows at every step, and the spec rows of one subdomain
+  // (consecutive rows) share its status words in that XCD's L2
   int row = blockIdx.x;
+  if ((gridDim.x & 7) == 0) row = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
   if (row < M)
     for (int t0 = 0; t0 < pl.din; t0 += 256 * kPF) {
       in_load<MODE>(zin, ldi, bt, v, row, t0, pl.din, s1, s2, w1, w2);
