@@ -8,7 +8,7 @@ specification rows resident in HBM.  Inputs are synthetic (seeded generator
 shaped like the paper's verifiers); the network's intermediate bounds come
 from the library's own per-layer CROWN pass.
 
-Prints one JSON line.  `--gpus N` with N > 1 exits: this build runs on one GPU.
+Prints one JSON line.  `--gpus N` with N > 1 exits: the bound path runs on one GPU.
 """
 from __future__ import annotations
 
@@ -211,8 +211,9 @@ def main():
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (see the design notes for how "
-                                   "the batch would shard across GPUs)"}))
+        print(json.dumps({"error": "the bound path runs on one GPU; --gpus must be 1 (subdomains are "
+                                   "independent, so a batch shards across GPUs by subdomain ranges, "
+                                   "one process each; not built)"}))
         sys.exit(2)
 
     import numpy as np
