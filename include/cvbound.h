@@ -124,7 +124,9 @@ int cv_bound_root_bounds_opt(const cv_layer *layers, int32_t n_layers, int32_t n
  * (stride^2 * in_c for the back-substitution, out_c forward), or rows,
  * tables and weights too large for a workgroup's 64 KB of LDS.
  * CV_EINVAL for non-finite inputs, x_lo > x_hi or a property index out of
- * range.  Validation happens before any device call.
+ * range.  Validation happens before any device call.  n_dom = 0 is an empty
+ * batch: every later call on the handle returns CV_OK without device work,
+ * and its bound outputs may be NULL.
  * Synchronous; copies everything it needs to the device. */
 int cv_bound_init(cv_bound **out, const cv_layer *layers, int32_t n_layers,
                   int32_t n_props, const float *x_lo, const float *x_hi,

@@ -1803,14 +1803,15 @@ int enqueue_true_fwd(cv_bound* h, float* ub, int32_t* sat, hipStream_t s) {
 }
 
 int cv_bound_eval(cv_bound* h, const float* alpha, const float* beta, float* lb, void* stream) {
-  if (!h || !lb || (!alpha && h->n_alpha > 0) || (!beta && h->nnz > 0)) return fail(CV_EINVAL, "null argument");
+  if (!h || (!lb && h->R > 0) || (!alpha && h->n_alpha > 0) || (!beta && h->nnz > 0))
+    return fail(CV_EINVAL, "null argument");
   hipStream_t s = (hipStream_t)stream;
   return enqueue_bwd(h, alpha, beta, false, lb, nullptr, 0, s);
 }
 
 int cv_bound_grad(cv_bound* h, const float* alpha, const float* beta, float* lb, float* g_alpha, float* g_beta,
                   void* stream) {
-  if (!h || !lb || (!alpha && h->n_alpha > 0) || (!beta && h->nnz > 0) || (!g_alpha && h->n_alpha > 0) ||
+  if (!h || (!lb && h->R > 0) || (!alpha && h->n_alpha > 0) || (!beta && h->nnz > 0) || (!g_alpha && h->n_alpha > 0) ||
       (!g_beta && h->nnz > 0))
     return fail(CV_EINVAL, "null argument");
   int rc = ensure_grad(h);
@@ -1822,7 +1823,8 @@ int cv_bound_grad(cv_bound* h, const float* alpha, const float* beta, float* lb,
 
 int cv_bound_upper(cv_bound* h, const float* alpha, const float* beta, float* lb, float* ub, int32_t* sat,
                    void* stream) {
-  if (!h || !ub || !sat || (!alpha && h->n_alpha > 0) || (!beta && h->nnz > 0)) return fail(CV_EINVAL, "null argument");
+  if (!h || ((!ub || !sat) && h->R > 0) || (!alpha && h->n_alpha > 0) || (!beta && h->nnz > 0))
+    return fail(CV_EINVAL, "null argument");
   int rc = ensure_grad(h);
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
@@ -1840,7 +1842,8 @@ int cv_bound_upper(cv_bound* h, const float* alpha, const float* beta, float* lb
 
 int cv_bound_optimize(cv_bound* h, int32_t iters, float lr_alpha, float lr_beta, float lr_decay, float* alpha,
                       float* beta, float* adam_state, int32_t step0, float* lb_best, float* lb_last, void* stream) {
-  if (!h || !lb_best || (!alpha && h->n_alpha > 0) || (!beta && h->nnz > 0)) return fail(CV_EINVAL, "null argument");
+  if (!h || (!lb_best && h->R > 0) || (!alpha && h->n_alpha > 0) || (!beta && h->nnz > 0))
+    return fail(CV_EINVAL, "null argument");
   if (iters < 0 || step0 < 0 || !std::isfinite(lr_alpha) || !std::isfinite(lr_beta) || !std::isfinite(lr_decay))
     return fail(CV_EINVAL, "bad optimiser settings");
   hipStream_t s = (hipStream_t)stream;

@@ -476,6 +476,25 @@ def test_edge_cases_depth_and_tiny_batches():
         assert guarded_rel(lb, ref).max() <= TOL
 
 
+@pytest.mark.parametrize("name", ["mlp_small", "cnn_odd"])
+def test_empty_batch(name):
+    """No subdomains: every entry point returns at once with empty outputs."""
+    from paper_2103_06624_amd.api import BoundProblem
+    say("empty batch", name)
+    wl, lo, up, _, _, _ = cases.small_case(name)
+    pb = BoundProblem(wl.net.layers, wl.x_lo, wl.x_hi, wl.C, lo, up, np.zeros(0, np.int32), [0], [], [], [])
+    assert pb.n_alpha == 0 and pb.n_beta == 0
+    a, b = pb.alpha_init(), pb.zeros_beta()
+    assert pb.eval(a, b).numel() == 0
+    lb, ga, gb = pb.grad(a, b)
+    assert lb.numel() == 0 and ga.numel() == 0 and gb.numel() == 0
+    best, last = pb.optimize(a, b)
+    assert best.numel() == 0
+    out = pb.upper(a, b)
+    assert all(t.numel() == 0 for t in out)
+    torch.cuda.synchronize()
+
+
 @pytest.mark.parametrize("name", ["mlp_deep"])
 def test_full_size_sampled(name):
     """The benchmark's workload at full size; sampled subdomains checked one by one."""
