@@ -305,6 +305,27 @@ def test_adam_first_step_is_normalised_sign():
     assert np.allclose(th, [0.51, 0.49, 0.5], atol=1e-7)
 
 
+def test_adam_schedule_constant_gradient_trajectories():
+    """The 20-step schedule itself: decay exponent, both learning rates and
+    both projections (tests/golden/adam_schedule.json derives every value)."""
+    with open(os.path.join(HERE, "golden", "adam_schedule.json")) as f:
+        fx = json.load(f)
+    net = [(np.array(W, float), np.array(b, float)) for W, b in fx["net"]]
+    x_lo, x_hi = np.array(fx["x_lo"], float), np.array(fx["x_hi"], float)
+    lo = [np.array(v, float) for v in fx["l"]]
+    up = [np.array(v, float) for v in fx["u"]]
+    C = np.array(fx["C"], float)
+    for case in fx["cases"]:
+        split = [np.array(case["split"], np.int8)]
+        a0 = [np.array([[case["alpha0"]]])]
+        b0 = [np.array([[case["beta0"]]])]
+        cfg = bc.AdamConfig(iters=fx["iters"], lr_alpha=case["lr_alpha"], lr_beta=case["lr_beta"], decay=fx["decay"])
+        best, a, b, _ = bc.optimize(net, x_lo, x_hi, C, lo, up, split, a0, b0, cfg)
+        assert abs(a[0][0, 0] - case["alpha_final"]) <= 1e-12, (case["name"], a[0][0, 0])
+        assert abs(b[0][0, 0] - case["beta_final"]) <= 1e-12, (case["name"], b[0][0, 0])
+        assert abs(best[0] - case["best"]) <= 1e-11, (case["name"], best[0])
+
+
 def test_default_alpha_rule():
     assert list(bc.default_alpha(np.array([-1.0, -2.0, -1.0]), np.array([2.0, 1.0, 1.0]))) == [1.0, 0.0, 1.0]
 
