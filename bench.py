@@ -136,57 +136,138 @@ def bab_context(wl, lo, up, args):
             "full_batch_domains_per_s": round(sum(n for n, _ in full) / sum(s for _, s in full), 1) if full else None}
 
 
-def cpu_baseline(name, gpu_best, gpu_splits, gpu_lo, gpu_up, seconds, iters, lr_a, lr_b, decay):
-    """The FP64 oracle timed on this host on a bounded sample of the same
-    workload: per-subdomain 20-iteration optimisation (the same unit as the
-    GPU metric).  Also reports the GPU's relative error on the sample."""
+def cpu_baseline(name, wl, lo, up, sp, gpu, seconds, seconds_1t, iters, lr_a, lr_b, decay, n_sound=64):
+    """The FP64 oracle on this host, fed the very inputs the GPU path saw (the
+    workload, the GPU's own float32 root bounds and split sets):
+
+      * timing: the per-subdomain 20-iteration optimisation (the unit of the
+        GPU metric) on random subdomains, with the BLAS threads at all cores
+        for about `seconds`, then at one thread for about `seconds_1t`;
+      * rel_err: the GPU's optimised bounds against the oracle's on the timed
+        subdomains (the same algorithm in float32 and float64);
+      * soundness: at the GPU's own final iterate (alpha, beta) of the
+        optimisation, the count of rows whose float32 bound exceeds the
+        float64 bound at those variables, and the largest excess, in plain
+        float32 mode and in sound mode (each with its own root bounds)."""
     import numpy as np
-    from threadpoolctl import threadpool_info
+    from threadpoolctl import threadpool_info, threadpool_limits
 
     from oracle import batch as ob
     from oracle import beta_crown as bc
-    from paper_2103_06624_amd import synth
 
-    wl = synth.make(name)
-    net64 = bc.dense_net(wl.net.layers)
     t0 = time.perf_counter()
-    lo64, up64 = ob.root_bounds_all(net64, wl.x_lo, wl.x_hi)
-    t_root = time.perf_counter() - t0
-    lo, up = bc.outward_f32(lo64, up64)
-    sp = synth.attach_splits(wl, lo, up)
-    # compare subdomains whose split sets agree; neurons whose stability class
-    # differs between the float32 (GPU) and outward-rounded float64 root bounds
-    # have a bound within rounding of 0, where both relaxations coincide
-    flips = int(sum(np.sum(((lo[p] < 0) & (up[p] > 0)) != ((gpu_lo[p] < 0) & (gpu_up[p] > 0)))
-                    for p in range(lo.shape[0])))
+    net64 = bc.dense_net(wl.net.layers)
+    t_net = time.perf_counter() - t0
 
-    def same(d):
-        return sp.dom_prop[d] == gpu_splits.dom_prop[d] and sp.of(d) == gpu_splits.of(d)
-    orc = ob.OracleProblem(wl.net.layers, wl.x_lo, wl.x_hi, wl.C, lo, up, sp.dom_prop, sp.split_ptr, sp.layer,
-                           sp.neuron, sp.side, net64=net64)
+    def problem(lo_, up_, sp_):
+        return ob.OracleProblem(wl.net.layers, wl.x_lo, wl.x_hi, wl.C, lo_, up_, sp_.dom_prop, sp_.split_ptr,
+                                sp_.layer, sp_.neuron, sp_.side, net64=net64)
+
+    orc = problem(lo, up, sp)
     cfg = bc.AdamConfig(iters=iters, lr_alpha=lr_a, lr_beta=lr_b, decay=decay)
     a0 = orc.default_alpha_flat()
     z = np.zeros(orc.nnz * orc.m)
-    rng = np.random.default_rng(123)
-    order = rng.permutation(orc.B)
-    done, errs = 0, []
-    t0 = time.perf_counter()
-    while done < orc.B and time.perf_counter() - t0 < seconds:
-        d = int(order[done])
-        best, *_ = orc.optimize(d, a0, z, cfg)
-        if same(d):
-            errs.append(float(np.max(np.abs(gpu_best[d] - best) / np.maximum(np.abs(best), 1.0))))
-        done += 1
-    el = time.perf_counter() - t0
+    order = np.random.default_rng(123).permutation(orc.B)
+
+    def timed(budget):
+        # subdomains in one fixed random order, as many as fit the budget
+        done, errs = 0, []
+        t1 = time.perf_counter()
+        while done < orc.B and time.perf_counter() - t1 < budget:
+            d = int(order[done])
+            best, *_ = orc.optimize(d, a0, z, cfg)
+            errs.append(float(np.max(np.abs(gpu["best"][d] - best) / np.maximum(np.abs(best), 1.0))))
+            done += 1
+        return done, time.perf_counter() - t1, errs
+
+    done_all, el_all, errs = timed(seconds)
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    return {
-        "value": done / el,
+    with threadpool_limits(limits=1):
+        done_1, el_1, errs1 = timed(seconds_1t)
+    if len(errs1) > len(errs):
+        errs = errs1
+
+    def soundness(o, g):
+        """rows where the float32 bound lies above the float64 bound at the same variables"""
+        ds = order[:min(n_sound, o.B)]
+        ex = []
+        for d in ds:
+            d = int(d)
+            ref = o.eval(d, g["alpha"], g["beta"])
+            ex.append(np.asarray(g["last"][d], np.float64) - ref)
+            ex[-1] = np.stack([ex[-1], np.abs(ref)])
+        ex = np.concatenate(ex, axis=1)
+        exc = ex[0]
+        return {"rows": int(exc.size), "subdomains": int(len(ds)), "violations": int(np.sum(exc > 0)),
+                "max_excess": float(max(exc.max(), 0.0)),
+                "max_rel_excess": float(max((exc / np.maximum(ex[1], 1.0)).max(), 0.0)),
+                "max_rel_below": float(max((-exc / np.maximum(ex[1], 1.0)).max(), 0.0))}
+
+    snd = {"plain": soundness(orc, gpu)}
+    rel_sound = None
+    if gpu.get("sound") is not None:
+        gs = gpu["sound"]
+        orc_s = problem(gs["lo"], gs["up"], gs["splits"])
+        snd["sound_mode"] = soundness(orc_s, gs)
+        ers = []
+        a0s = orc_s.default_alpha_flat()
+        zs = np.zeros(orc_s.nnz * orc_s.m)
+        for d in order[:8]:
+            best, *_ = orc_s.optimize(int(d), a0s, zs, cfg)
+            ers.append(float(np.max(np.abs(gs["best"][int(d)] - best) / np.maximum(np.abs(best), 1.0))))
+        rel_sound = {"max": max(ers), "subdomains": len(ers)}
+    cb = {
+        "value": done_all / el_all,
         "unit": "subdomain bounds/s",
         "cores": int(threads),
         "kind": "oracle",
-        "sample": f"{done} of {orc.B} random subdomains ({orc.m} spec rows each), {iters}-iteration Adam, "
-                  f"float64 NumPy; root bounds ({t_root:.1f} s) not timed; host has {os.cpu_count()} CPUs",
-    }, ({"max": max(errs), "subdomains": len(errs), "root_stability_flips": flips} if errs else None)
+        "sample": f"{done_all} random subdomains of {orc.B} ({orc.m} spec rows each), {iters}-iteration Adam, "
+                  f"float64 NumPy on the GPU path's own root bounds and splits; {el_all:.1f} s with {threads} BLAS "
+                  f"threads; conv layers as dense matrices (built in {t_net:.1f} s, not timed); "
+                  f"host has {os.cpu_count()} CPUs",
+        "one_core": {"value": done_1 / el_1 if done_1 else None, "cores": 1,
+                     "sample": f"the first {done_1} of the same random subdomains, {el_1:.1f} s, BLAS limited to 1 thread"},
+    }
+    rel = {"max": max(errs), "subdomains": len(errs)} if errs else None
+    return cb, rel, snd, rel_sound
+
+
+def kernel_table(pb, a0, b0, reps):
+    """Per-kernel durations with HIP events on the launch stream (each launch
+    of one gradient pass and one plain evaluation issued 8 times back to back
+    between two events), algorithmic flops and bytes per launch."""
+    stats = pb.profile(a0, b0, reps=reps)
+    kern = []
+    for s in stats:
+        avg_ms = s["total_ms"] / (s["reps"] * s["launches"])
+        fl = s["flops"] / s["launches"]
+        by = s["bytes"] / s["launches"]
+        kern.append(dict(name=s["name"], launches_per_pass=s["launches"], avg_us=avg_ms * 1e3,
+                         tflops=(fl / (avg_ms * 1e-3) / 1e12) if fl else 0.0,
+                         gbs=by / (avg_ms * 1e-3) / 1e9, share=s["total_ms"], flops_per_launch=fl,
+                         bytes_per_launch=by))
+    tot = sum(k["share"] for k in kern)
+    for k in kern:
+        k["share"] = round(k["share"] / tot, 4)
+    return stats, kern
+
+
+def roofline(stats, kern, name):
+    dom = max(kern, key=lambda k: k["share"])
+    if dom["flops_per_launch"] > 0:
+        # the dense GEMMs and the conv layers' implicit GEMMs run on the matrix cores
+        bound = "mfma" if dom["name"].startswith(("gemm", "chain", "conv")) else "alu"
+        roof = {"bound": bound, "achieved": round(dom["tflops"], 3), "peak": PEAK_FP32_MFMA_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(dom["tflops"] / PEAK_FP32_MFMA_TFLOPS, 4)}
+    else:
+        roof = {"bound": "hbm", "achieved": round(dom["gbs"], 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(dom["gbs"] / PEAK_HBM_GBS, 4)}
+    roof["traffic"] = traffic_for(dom["name"], name)
+    roof["kernel"] = dom["name"]
+    roof["avg_us"] = round(dom["avg_us"], 3)
+    roof["algorithmic_bytes_per_launch"] = dom["bytes_per_launch"]
+    roof["algorithmic_flops_per_launch"] = dom["flops_per_launch"]
+    return roof
 
 
 def main():
@@ -194,26 +275,35 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="mlp_deep", choices=sorted(WORKLOAD_TEXT))
+    ap.add_argument("--workload", default="cnn_deep", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--iters", type=int, default=20)
     ap.add_argument("--lr-alpha", type=float, default=0.01)
     ap.add_argument("--lr-beta", type=float, default=0.05)
     ap.add_argument("--decay", type=float, default=0.98)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle timing budget at all host cores")
+    ap.add_argument("--cpu-seconds-1t", type=float, default=10.0, help="oracle timing budget at one thread")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-context", action="store_true",
+                    help="skip the context legs (upper bound, sound mode, l2 balls, optimised root bounds, "
+                         "branch and bound, library GEMM)")
+    ap.add_argument("--profile-only", action="store_true",
+                    help="build the batch, autotune, then run only the per-kernel timing pass (for rocprofv3)")
+    ap.add_argument("--profile-reps", type=int, default=5)
     ap.add_argument("--bab-rounds", type=int, default=16, help="branch-and-bound rounds timed as context")
     ap.add_argument("--bab-batch", type=int, default=1024, help="subdomains split per branch-and-bound round")
     ap.add_argument("--plan", default=None, help="dense-chain plan bwd,fwd (1,1 fused chains, 0,0 per-layer kernels); overrides the autotuner")
     ap.add_argument("--parts", type=int, default=0,
                     help="concurrent sub-batches of the optimiser (0: the library's default)")
+    ap.add_argument("--conv-variant", type=int, default=None,
+                    help="force one conv kernel variant on every conv layer (0-3; overrides the autotuner)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "the bound path runs on one GPU; --gpus must be 1 (subdomains are "
-                                   "independent, so a batch shards across GPUs by subdomain ranges, "
-                                   "one process each; not built)"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1 (subdomains are "
+                                   "independent, so a batch would shard across GPUs by subdomain ranges, "
+                                   "one process each; that is not built)"}))
         sys.exit(2)
 
     import numpy as np
@@ -234,13 +324,41 @@ def main():
     if args.parts:
         pb.set_parts(args.parts)
     if not args.no_autotune:
+        log("[bench] autotune")
         pb.autotune()
     if args.plan:
         cb, cf = (int(x) for x in args.plan.split(","))
         pb.set_plan(cb, cf)
-
+    if args.conv_variant is not None:
+        pb.set_conv_variant(args.conv_variant)
+    variant_names = ["row-major/LDS weights", "row-major/global weights", "subdomain-major/LDS weights",
+                     "subdomain-major/global weights"]
+    conv_plan = {f"layer{i + 1}": {"back_substitution": variant_names[pb.conv_variant(i + 1, 0)],
+                                   "adjoint": variant_names[pb.conv_variant(i + 1, 1)]}
+                 for i, ly in enumerate(wl.net.layers) if ly.kind == synth.CONV}
     a0 = pb.alpha_init()
     b0 = pb.zeros_beta()
+
+    def calib_copy():
+        if args.calib_copy_mib:
+            n = args.calib_copy_mib * (1 << 20) // 4
+            x = torch.ones(n, device="cuda")
+            y = torch.empty_like(x)
+            for _ in range(3):
+                y.copy_(x)
+            torch.cuda.synchronize()
+
+    if args.profile_only:
+        log(f"[bench] profile pass only ({args.profile_reps} reps)")
+        stats, kern = kernel_table(pb, a0, b0, args.profile_reps)
+        torch.cuda.synchronize()
+        calib_copy()
+        print(json.dumps({"workload": name, "profile_reps": args.profile_reps, "conv_plan": conv_plan,
+                          "roofline": roofline(stats, kern, name),
+                          "kernels": [{k: (round(v, 3) if isinstance(v, float) else v) for k, v in kk.items()}
+                                      for kk in kern]}), flush=True)
+        return
+
     alpha, beta = a0.clone(), b0.clone()
     best = torch.empty(pb.n_rows, device="cuda")
     last = torch.empty(pb.n_rows, device="cuda")
@@ -261,6 +379,7 @@ def main():
     el = time.perf_counter() - t0
     ms_step = el / args.steps * 1e3
     value = B / (ms_step / 1e3)
+    log(f"[bench] {ms_step:.3f} ms per step, {value:.1f} subdomain bounds/s")
 
     # ---- plain evaluation of the same batch
     lb = torch.empty(pb.n_rows, device="cuda")
@@ -274,144 +393,148 @@ def main():
     torch.cuda.synchronize()
     ms_eval = (time.perf_counter() - t0) / n_eval * 1e3
 
-    # ---- the primal side on the same batch: bound, x*, the network at x*
-    # and the split check (cv_bound_upper), at the default start
-    for _ in range(3):
-        _, ub, sat = pb.upper(a0, b0)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(n_eval):
-        _, ub, sat = pb.upper(a0, b0)
-    torch.cuda.synchronize()
-    ms_upper = (time.perf_counter() - t0) / n_eval * 1e3
-    upper = {"value": round(B / (ms_upper / 1e3), 1), "unit": "subdomain (lower, upper) bound pairs/s",
-             "ms_per_call": round(ms_upper, 4), "rows_meeting_splits": int(sat.sum().item()),
-             "rows_below_zero": int((ub < 0).sum().item())}
+    # ---- a clean 20-iteration run from the default start: the bounds and the
+    # final iterate the oracle leg checks
+    alpha.copy_(a0)
+    beta.copy_(b0)
+    pb.optimize(alpha, beta, **opt)
+    gpu = {"best": best.view(B, m).cpu().numpy().astype(np.float64),
+           "last": last.view(B, m).cpu().numpy().astype(np.float64),
+           "alpha": alpha.cpu().numpy(), "beta": beta.cpu().numpy(), "sound": None}
 
-    # ---- sound mode (rigorous float32 rounding margin) on the same batch:
-    # optimiser throughput and the margin against the plain float32 bound
-    pb.set_sound(1)
-    for _ in range(2):
-        alpha.copy_(a0)
-        beta.copy_(b0)
-        pb.optimize(alpha, beta, **opt)
-    torch.cuda.synchronize()
+    ctx = {}
     n_sound = max(3, args.steps // 4)
-    t0 = time.perf_counter()
-    for _ in range(n_sound):
-        pb.optimize(alpha, beta, **opt)
-    torch.cuda.synchronize()
-    ms_sound = (time.perf_counter() - t0) / n_sound * 1e3
-    lb_s = pb.eval(a0, b0)
-    pb.set_sound(0)
-    lb_p = pb.eval(a0, b0)
-    rel_margin = ((lb_p - lb_s) / lb_p.abs().clamp(min=1.0)).max().item()
-    sound = {"value": round(B / (ms_sound / 1e3), 1), "unit": "subdomain bounds/s", "ms_per_step": round(ms_sound, 4),
-             "max_rel_margin": rel_margin, "min_margin": (lb_p - lb_s).min().item()}
+    if not args.no_context:
+        # ---- the primal side on the same batch: bound, x*, the network at x*
+        # and the split check (cv_bound_upper), at the default start
+        log("[bench] upper bound")
+        for _ in range(3):
+            _, ub, sat = pb.upper(a0, b0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n_eval):
+            _, ub, sat = pb.upper(a0, b0)
+        torch.cuda.synchronize()
+        ms_upper = (time.perf_counter() - t0) / n_eval * 1e3
+        ctx["upper_bound"] = {"value": round(B / (ms_upper / 1e3), 1),
+                              "unit": "subdomain (lower, upper) bound pairs/s", "ms_per_call": round(ms_upper, 4),
+                              "rows_meeting_splits": int(sat.sum().item()),
+                              "rows_below_zero": int((ub < 0).sum().item())}
 
-    # ---- l2-ball input sets: the same properties over the balls of radius
-    # eps around x0 (inscribed in the unclipped box, whose root bounds hold
-    # over them), same subdomain count; optimiser throughput
-    x0 = np.asarray(wl.x0, np.float32)
-    eps_l2 = np.full(wl.n_props, wl.eps, np.float32)
-    lo_b, up_b = api.root_bounds(wl.net.layers, np.nextafter(x0 - eps_l2[:, None], np.float32(-np.inf)),
-                                 np.nextafter(x0 + eps_l2[:, None], np.float32(np.inf)))
-    wl_b = synth.make(name)
-    sp_b = synth.attach_splits(wl_b, lo_b, up_b)
-    pb_b = api.BoundProblem.from_workload(wl_b, lo_b, up_b, sp_b)
-    if args.parts:
-        pb_b.set_parts(args.parts)
-    pb_b.set_input_l2(x0, eps_l2)
-    a_b, b_b = pb_b.alpha_init(), pb_b.zeros_beta()
-    opt_b = dict(iters=args.iters, lr_alpha=args.lr_alpha, lr_beta=args.lr_beta, decay=args.decay)
-    for _ in range(2):
-        pb_b.optimize(a_b.clone(), b_b.clone(), **opt_b)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(n_sound):
-        best_b, _ = pb_b.optimize(a_b.clone(), b_b.clone(), **opt_b)
-    torch.cuda.synchronize()
-    ms_l2 = (time.perf_counter() - t0) / n_sound * 1e3
-    l2_ball = {"value": round(pb_b.B / (ms_l2 / 1e3), 1), "unit": "subdomain bounds/s", "ms_per_step": round(ms_l2, 4),
-               "radius": float(wl.eps), "mean_bound": float(best_b.mean().item())}
-    pb_b.close()
+        # ---- sound mode end to end: the sound root bounds (every bound moved
+        # outward by its rigorous float32 margin), subdomains drawn against
+        # them, and the margin on every reported bound; optimiser throughput,
+        # the margin against the plain float32 bound of the same problem, and
+        # the final iterate for the oracle's soundness count
+        log("[bench] sound mode")
+        lo_s, up_s = api.root_bounds(wl.net.layers, wl.x_lo, wl.x_hi, sound=True)
+        wl_s = synth.make(name)
+        sp_s = synth.attach_splits(wl_s, lo_s, up_s)
+        pb_s = api.BoundProblem.from_workload(wl_s, lo_s, up_s, sp_s)
+        if args.parts:
+            pb_s.set_parts(args.parts)
+        pb_s.set_sound(1)
+        a_s0, b_s0 = pb_s.alpha_init(), pb_s.zeros_beta()
+        a_s, b_s = a_s0.clone(), b_s0.clone()
+        best_s = torch.empty(pb_s.n_rows, device="cuda")
+        last_s = torch.empty(pb_s.n_rows, device="cuda")
+        opt_s = dict(opt, lb_best=best_s, lb_last=last_s)
+        for _ in range(2):
+            pb_s.optimize(a_s, b_s, **opt_s)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n_sound):
+            pb_s.optimize(a_s, b_s, **opt_s)
+        torch.cuda.synchronize()
+        ms_sound = (time.perf_counter() - t0) / n_sound * 1e3
+        a_s.copy_(a_s0)
+        b_s.copy_(b_s0)
+        pb_s.optimize(a_s, b_s, **opt_s)
+        gpu["sound"] = {"best": best_s.view(B, m).cpu().numpy().astype(np.float64),
+                        "last": last_s.view(B, m).cpu().numpy().astype(np.float64),
+                        "alpha": a_s.cpu().numpy(), "beta": b_s.cpu().numpy(), "lo": lo_s, "up": up_s,
+                        "splits": sp_s}
+        lb_s = pb_s.eval(a_s0, b_s0)
+        pb_s.set_sound(0)
+        lb_p = pb_s.eval(a_s0, b_s0)
+        rel_margin = ((lb_p - lb_s) / lb_p.abs().clamp(min=1.0)).max().item()
+        ctx["sound_mode"] = {"value": round(pb_s.B / (ms_sound / 1e3), 1), "unit": "subdomain bounds/s",
+                             "ms_per_step": round(ms_sound, 4), "root_bounds": "sound (outward by the margin)",
+                             "max_rel_margin": rel_margin, "min_margin": (lb_p - lb_s).min().item()}
+        pb_s.close()
 
-    # ---- optimised intermediate bounds (each bound over its own alpha',
-    # 20 Adam steps): time, how much they narrow the intervals, and what they
-    # do to the bound of the batch at the default start
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    lo_o, up_o = api.root_bounds(wl.net.layers, wl.x_lo, wl.x_hi, opt_iters=args.iters, lr_alpha=0.1,
-                                 decay=args.decay)
-    t_ropt = time.perf_counter() - t0
-    w_c, w_o = (up - lo), (up_o - lo_o)
-    # the same generator keys: only subdomains that split a neuron the tighter bounds made stable change
-    wl_o = synth.make(name)
-    sp_o = synth.attach_splits(wl_o, lo_o, up_o)
-    pb_o = api.BoundProblem.from_workload(wl_o, lo_o, up_o, sp_o)
-    lb_o = pb_o.eval(pb_o.alpha_init(), pb_o.zeros_beta())
-    lb_c = pb.eval(a0, b0)
-    root_opt = {"seconds": round(t_ropt, 3), "mean_width_ratio": float(np.mean(w_o / np.maximum(w_c, 1e-12))),
-                "rows_improved": int((lb_o > lb_c).sum().item()), "mean_bound_gain": float((lb_o - lb_c).mean().item())}
-    pb_o.close()
+        # ---- l2-ball input sets: the same properties over the balls of radius
+        # eps around x0 (inscribed in the unclipped box, whose root bounds hold
+        # over them), same subdomain count; optimiser throughput
+        log("[bench] l2 balls")
+        x0 = np.asarray(wl.x0, np.float32)
+        eps_l2 = np.full(wl.n_props, wl.eps, np.float32)
+        lo_b, up_b = api.root_bounds(wl.net.layers, np.nextafter(x0 - eps_l2[:, None], np.float32(-np.inf)),
+                                     np.nextafter(x0 + eps_l2[:, None], np.float32(np.inf)))
+        wl_b = synth.make(name)
+        sp_b = synth.attach_splits(wl_b, lo_b, up_b)
+        pb_b = api.BoundProblem.from_workload(wl_b, lo_b, up_b, sp_b)
+        if args.parts:
+            pb_b.set_parts(args.parts)
+        pb_b.set_input_l2(x0, eps_l2)
+        a_b, b_b = pb_b.alpha_init(), pb_b.zeros_beta()
+        opt_b = dict(iters=args.iters, lr_alpha=args.lr_alpha, lr_beta=args.lr_beta, decay=args.decay)
+        for _ in range(2):
+            pb_b.optimize(a_b.clone(), b_b.clone(), **opt_b)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n_sound):
+            best_b, _ = pb_b.optimize(a_b.clone(), b_b.clone(), **opt_b)
+        torch.cuda.synchronize()
+        ms_l2 = (time.perf_counter() - t0) / n_sound * 1e3
+        ctx["l2_ball"] = {"value": round(pb_b.B / (ms_l2 / 1e3), 1), "unit": "subdomain bounds/s",
+                          "ms_per_step": round(ms_l2, 4), "radius": float(wl.eps),
+                          "mean_bound": float(best_b.mean().item())}
+        pb_b.close()
 
-    # ---- branch and bound (Alg. 1) on property 0 of the workload, each row's
-    # objective offset to the middle of its root [lower, upper] bound (an
-    # extra constant output carries the offsets), so that the search has to
-    # branch; a fixed number of rounds of `batch` splits each
-    bab_res = bab_context(wl, lo, up, args)
+        # ---- optimised intermediate bounds (each bound over its own alpha',
+        # 20 Adam steps): time, how much they narrow the intervals, and what
+        # they do to the bound of the batch at the default start
+        log("[bench] optimised root bounds")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lo_o, up_o = api.root_bounds(wl.net.layers, wl.x_lo, wl.x_hi, opt_iters=args.iters, lr_alpha=0.1,
+                                     decay=args.decay)
+        t_ropt = time.perf_counter() - t0
+        w_c, w_o = (up - lo), (up_o - lo_o)
+        # the same generator keys: only subdomains that split a neuron the
+        # tighter bounds made stable change
+        wl_o = synth.make(name)
+        sp_o = synth.attach_splits(wl_o, lo_o, up_o)
+        pb_o = api.BoundProblem.from_workload(wl_o, lo_o, up_o, sp_o)
+        lb_o = pb_o.eval(pb_o.alpha_init(), pb_o.zeros_beta())
+        lb_c = pb.eval(a0, b0)
+        ctx["optimised_root_bounds"] = {"seconds": round(t_ropt, 3),
+                                        "mean_width_ratio": float(np.mean(w_o / np.maximum(w_c, 1e-12))),
+                                        "rows_improved": int((lb_o > lb_c).sum().item()),
+                                        "mean_bound_gain": float((lb_o - lb_c).mean().item())}
+        pb_o.close()
+
+        # ---- branch and bound (Alg. 1) on property 0 of the workload, each
+        # row's objective offset to the middle of its root [lower, upper]
+        # bound (an extra constant output carries the offsets), so that the
+        # search has to branch; a fixed number of rounds of `batch` splits each
+        log("[bench] branch and bound")
+        ctx["branch_and_bound"] = bab_context(wl, lo, up, args)
+
+        # ---- context: the vendor library's plain FP32 GEMM (no epilogue) at
+        # the back-substitution shapes of the dense layers, same rows
+        ctx["library_fp32_gemm"] = library_gemm_context(wl, pb.n_rows)
 
     # ---- per-kernel durations with HIP events on the launch stream
     log("[bench] per-kernel event timing")
-    stats = pb.profile(a0, b0, reps=5)
-    kern = []
-    for s in stats:
-        avg_ms = s["total_ms"] / (s["reps"] * s["launches"])
-        fl = s["flops"] / s["launches"]
-        by = s["bytes"] / s["launches"]
-        kern.append(dict(name=s["name"], launches_per_pass=s["launches"], avg_us=avg_ms * 1e3,
-                         tflops=(fl / (avg_ms * 1e-3) / 1e12) if fl else 0.0,
-                         gbs=by / (avg_ms * 1e-3) / 1e9, share=s["total_ms"]))
-    tot = sum(k["share"] for k in kern)
-    for k in kern:
-        k["share"] = round(k["share"] / tot, 4)
-    dom = max(kern, key=lambda k: k["share"])
-    fl_launch = next(s["flops"] / s["launches"] for s in stats if s["name"] == dom["name"])
-    by_launch = next(s["bytes"] / s["launches"] for s in stats if s["name"] == dom["name"])
-    if fl_launch > 0:
-        # the dense GEMMs and the conv layers' implicit GEMMs run on the matrix cores
-        bound = "mfma" if dom["name"].startswith(("gemm", "chain", "conv")) else "alu"
-        roof = {"bound": bound, "achieved": round(dom["tflops"], 3), "peak": PEAK_FP32_MFMA_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(dom["tflops"] / PEAK_FP32_MFMA_TFLOPS, 4)}
-    else:
-        roof = {"bound": "hbm", "achieved": round(dom["gbs"], 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(dom["gbs"] / PEAK_HBM_GBS, 4)}
-    roof["kernel"] = dom["name"]
-    roof["traffic"] = traffic_for(dom["name"], name)
-    roof["algorithmic_bytes_per_launch"] = by_launch
-    roof["algorithmic_flops_per_launch"] = fl_launch
+    stats, kern = kernel_table(pb, a0, b0, args.profile_reps)
+    roof = roofline(stats, kern, name)
     on_mfma = [s for s in stats if s["name"].startswith(("gemm", "chain", "conv"))]
     gemm_fl = sum(s["flops"] for s in on_mfma)
     gemm_ms = sum(s["total_ms"] / s["reps"] for s in on_mfma)
     all_ms = sum(s["total_ms"] / s["reps"] for s in stats)
-
-    # ---- context: the vendor library's plain FP32 GEMM (no epilogue) at the
-    # back-substitution shapes of the dense layers, same rows
-    lib = library_gemm_context(wl, pb.n_rows)
-
-    # ---- a clean 20-iteration run from the default start (for the error check)
-    alpha.copy_(a0)
-    beta.copy_(b0)
-    pb.optimize(alpha, beta, **opt)
-    gpu_best = best.view(B, m).cpu().numpy().astype(np.float64)
-
-    if args.calib_copy_mib:
-        n = args.calib_copy_mib * (1 << 20) // 4
-        x = torch.ones(n, device="cuda")
-        y = torch.empty_like(x)
-        for _ in range(3):
-            y.copy_(x)
-        torch.cuda.synchronize()
+    calib_copy()
 
     line = {
         "metric": "subdomain bounds/sec (20-iter alpha/beta opt) vs plain eval; rel err vs FP64",
@@ -431,24 +554,23 @@ def main():
                    "lr_decay": args.decay, "root_bounds": "per-layer CROWN on the GPU"},
         "plain_eval": {"value": round(B / (ms_eval / 1e3), 1), "unit": "subdomain bounds/s",
                        "ms_per_eval": round(ms_eval, 4)},
-        "upper_bound": upper,
-        "sound_mode": sound,
-        "l2_ball": l2_ball,
-        "branch_and_bound": bab_res,
-        "optimised_root_bounds": root_opt,
         "roofline": roof,
+        "conv_plan": conv_plan,
         "mfma_kernels_tflops": round(gemm_fl / (gemm_ms * 1e-3) / 1e12, 3) if gemm_ms else None,
         "mfma_kernels_time_share": round(gemm_ms / all_ms, 4) if all_ms else None,
-        "kernels": [{k: (round(v, 3) if isinstance(v, float) else v) for k, v in kk.items()} for kk in kern],
-        "library_fp32_gemm": lib,
-        "root_bounds_s": round(t_root, 3),
     }
+    line.update(ctx)
+    line["kernels"] = [{k: (round(v, 3) if isinstance(v, float) else v) for k, v in kk.items()} for kk in kern]
+    line["root_bounds_s"] = round(t_root, 3)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
-        cb, rel = cpu_baseline(name, gpu_best, sp, lo, up, args.cpu_seconds, args.iters, args.lr_alpha, args.lr_beta,
-                               args.decay)
+        cb, rel, snd, rel_sound = cpu_baseline(name, wl, lo, up, sp, gpu, args.cpu_seconds, args.cpu_seconds_1t,
+                                               args.iters, args.lr_alpha, args.lr_beta, args.decay)
         line["cpu_baseline"] = cb
         line["rel_err_vs_fp64"] = rel
+        line["soundness"] = snd
+        if rel_sound is not None:
+            line["rel_err_vs_fp64_sound_mode"] = rel_sound
     print(json.dumps(line), flush=True)
 
 

@@ -198,9 +198,11 @@ int cv_bound_optimize(cv_bound *h, int32_t iters, float lr_alpha, float lr_beta,
                       float *lb_best, float *lb_last, void *stream);
 
 /* Time the candidate tile shapes of every layer's kernels on this handle's
- * shapes and keep the fastest (process-wide cache keyed by shape).
- * Synchronous.  Results do not depend on the choice beyond float32 rounding
- * of the summation order. */
+ * shapes and keep the fastest (process-wide cache keyed by shape): the GEMM
+ * tilings of the dense layers, the kernel variants of the conv layers
+ * (cv_bound_set_conv_variant), per layer and direction, and the fused dense
+ * chain against per-layer kernels.  Synchronous.  Results do not depend on
+ * the choice beyond float32 rounding of the summation order. */
 int cv_bound_autotune(cv_bound *h, void *stream);
 
 /* Execution plan of the dense layers at the top of the network, for the
@@ -238,6 +240,31 @@ int cv_bound_set_parts(cv_bound *h, int32_t nparts);
  * -1..cv_bound_num_tilings()-1. */
 int32_t cv_bound_num_tilings(void);
 int cv_bound_set_tiling(cv_bound *h, int32_t tiling);
+
+/* Kernel variants of the conv layers (back-substitution through a conv
+ * layer as a transposed convolution, Theorem 3.1's A(i-1) = Lambda(i) W(i),
+ * and the adjoint's forward convolution), all computing the same result up
+ * to float32 summation order:
+ *   0  row-major: each workgroup takes one batch row at a time, the weight
+ *      matrix held in LDS;
+ *   1  row-major, the weights read from global memory (L1/L2);
+ *   2  subdomain-major: each workgroup takes the specification rows of one
+ *      subdomain in turn and keeps the subdomain's status records and its
+ *      property's chords (or box) in registers across them, weights in LDS;
+ *   3  subdomain-major, weights from global memory.
+ * cv_bound_num_conv_variants: how many there are.
+ * cv_bound_set_conv_variant: force `variant` on every conv layer of h (and of
+ * its sub-batches) in both directions where it can run that layer (where it
+ * cannot, the layer keeps its default), or -1 to return to the tuned choice
+ * per layer shape (cv_bound_autotune's, else the default: subdomain-major
+ * where an instantiation holds the layer's rows, weights in LDS up to 16 KB).
+ * CV_EINVAL outside -1..cv_bound_num_conv_variants()-1.
+ * cv_bound_conv_variant: the variant conv layer `layer` (1..L) runs in
+ * direction dir (0 back-substitution, 1 adjoint), or -1 for a dense layer or
+ * bad arguments.  Host only. */
+int32_t cv_bound_num_conv_variants(void);
+int cv_bound_set_conv_variant(cv_bound *h, int32_t variant);
+int cv_bound_conv_variant(const cv_bound *h, int32_t layer, int32_t dir);
 
 /* Sound mode (off by default): every bound this handle reports (eval, grad,
  * upper, optimize) is lowered by a rigorous bound on its float32 rounding

@@ -177,6 +177,18 @@ class BoundProblem:
         """Force one GEMM tiling on every dense layer (-1: the tuned choice)."""
         B.check(B.cv_bound_set_tiling(self.h, tiling))
 
+    @staticmethod
+    def num_conv_variants():
+        return int(B.cv_bound_num_conv_variants())
+
+    def set_conv_variant(self, variant):
+        """Force one conv kernel variant on every conv layer (-1: the tuned choice)."""
+        B.check(B.cv_bound_set_conv_variant(self.h, variant))
+
+    def conv_variant(self, layer, direction):
+        """Variant conv layer `layer` (1..L) runs: direction 0 back-substitution, 1 adjoint."""
+        return int(B.cv_bound_conv_variant(self.h, layer, direction))
+
     def set_sound(self, on):
         """Lower every reported bound by a rigorous float32 rounding-error margin."""
         B.check(B.cv_bound_set_sound(self.h, int(on), _stream()))

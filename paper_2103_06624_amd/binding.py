@@ -64,6 +64,9 @@ SIGNATURES = {
     "cv_bound_set_parts": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "cv_bound_num_tilings": (ctypes.c_int32, []),
     "cv_bound_set_tiling": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "cv_bound_num_conv_variants": (ctypes.c_int32, []),
+    "cv_bound_set_conv_variant": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "cv_bound_conv_variant": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32]),
     "cv_bound_set_sound": (ctypes.c_int, [_vp, ctypes.c_int32, _vp]),
     "cv_bound_set_input_l2": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "cv_bound_profile": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32, ctypes.POINTER(cv_kernel_stat),
@@ -119,6 +122,9 @@ cv_bound_set_plan = _fn("cv_bound_set_plan")
 cv_bound_set_parts = _fn("cv_bound_set_parts")
 cv_bound_num_tilings = _fn("cv_bound_num_tilings")
 cv_bound_set_tiling = _fn("cv_bound_set_tiling")
+cv_bound_num_conv_variants = _fn("cv_bound_num_conv_variants")
+cv_bound_set_conv_variant = _fn("cv_bound_set_conv_variant")
+cv_bound_conv_variant = _fn("cv_bound_conv_variant")
 cv_bound_set_sound = _fn("cv_bound_set_sound")
 cv_bound_set_input_l2 = _fn("cv_bound_set_input_l2")
 cv_bound_profile = _fn("cv_bound_profile")

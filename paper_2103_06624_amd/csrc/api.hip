@@ -84,6 +84,7 @@ struct DevLayer {
   float* Wt = nullptr;     // dense [din, ld_out]
   float* bias = nullptr;   // [dout], per neuron
   ConvPlan bwd{}, fwd{};   // conv: back-substitution and forward implicit GEMMs
+  ConvPlan bwd_def{}, fwd_def{};  // the same as first built (before any variant choice)
 };
 
 }  // namespace
@@ -256,6 +257,42 @@ void assign_tiles(cv_bound* h, int tiling) {
     h->cfg[i - 1] =
         tiling >= 0 ? tiling : cfg_for(h, i - 1 >= 1 ? kBwdRelax : kBwdConc, h->R, N_b, K_b, gemm_default_cfg(h->R, N_b));
     h->cfg[n_layers + i - 1] = tiling >= 0 ? tiling : cfg_for(h, kFwd, h->R, K_b, N_b, gemm_default_cfg(h->R, K_b));
+  }
+}
+
+// Conv kernel variants (conv_plan_variant) per layer shape and direction,
+// chosen by cv_bound_autotune: (mode, rows, c_in, h_in, w_in, c_out, k, s, p).
+typedef std::tuple<int, int, int, int, int, int, int, int, int> ConvKey;
+std::map<ConvKey, int> g_conv_tune;
+
+ConvKey conv_key(int mode, int rows, const ConvGeom& g) {
+  return ConvKey{mode, rows, g.ci, g.hi, g.wi, g.co, g.k, g.s, g.p};
+}
+
+int conv_mode(int layer_index, bool bwd, bool first_dense) {
+  (void)first_dense;
+  return bwd ? (layer_index == 0 ? kBwdConc : kBwdRelax) : (layer_index == 0 ? kFwdX : kFwd);
+}
+
+// Kernel variant of every conv layer in both directions: `forced` >= 0 forces
+// that variant where it can run (elsewhere the default), -1 takes the tuned
+// choice for each layer shape, else the default plan.
+void assign_conv_variants(cv_bound* h, int forced) {
+  for (int i = 0; i < h->L; ++i) {
+    DevLayer& d = h->layers[i];
+    if (d.type != CV_LAYER_CONV2D) continue;
+    for (int dir = 0; dir < 2; ++dir) {
+      ConvPlan& pl = dir == 0 ? d.bwd : d.fwd;
+      pl = dir == 0 ? d.bwd_def : d.fwd_def;
+      const int mode = conv_mode(i, dir == 0, false);
+      int v = forced;
+      if (v < 0) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_conv_tune.find(conv_key(mode, h->R, d.g));
+        v = it == g_conv_tune.end() ? -1 : it->second;
+      }
+      if (v >= 0) (void)conv_plan_variant(mode, pl, v);
+    }
   }
 }
 
@@ -555,6 +592,7 @@ int upload_plan(cv_bound* h, HostPlan& o, int mode, ConvPlan& out) {
   out.wm = wm;
   plan_finish(out);
   out.grid = conv_plan_grid(mode, out);
+  conv_plan_sd(mode, out);
   return CV_OK;
 }
 
@@ -600,6 +638,8 @@ int upload_layers(cv_bound* h, const cv_layer* layers, int n, hipStream_t s) {
       if ((rc = upload_plan(h, pb, i == 0 ? kBwdConc : kBwdRelax, d.bwd)) ||
           (rc = upload_plan(h, pf, i == 0 ? kFwdX : kFwd, d.fwd)))
         return rc;
+      d.bwd_def = d.bwd;
+      d.fwd_def = d.fwd;
     }
     if (ly.type == CV_LAYER_DENSE && !finite_all(ly.weight, (int64_t)d.dout * d.din))
       return fail(CV_EINVAL, "layer %d: non-finite weight", i + 1);
@@ -798,6 +838,7 @@ int build(cv_bound* h, const cv_layer* layers, int n_layers, int P, const float*
   }
   if ((rc = M.alloc(&h->part, (size_t)std::max(1, h->R) * h->n_slots))) return rc;
   assign_tiles(h, -1);
+  assign_conv_variants(h, -1);
   // dense layers fused by the chain kernels (LDS-resident widths up to kChainWidth)
   h->chain_lo = 0;
   h->chain_b = h->chain_f = 0;
@@ -1059,6 +1100,11 @@ Epi make_epi(const cv_bound* h) {
   return e;
 }
 
+// profile name of a conv layer: channels, kernel and stride ("8-16k4s2")
+std::string conv_tag(const ConvGeom& g) {
+  return std::to_string(g.ci) + "-" + std::to_string(g.co) + "k" + std::to_string(g.k) + "s" + std::to_string(g.s);
+}
+
 // conv MACs of one row (taps inside the input only)
 double conv_macs(const ConvGeom& g) {
   double taps = 0;
@@ -1205,8 +1251,7 @@ int enqueue_bwd(cv_bound* h, const float* alpha, const float* beta, bool grad, f
       slot += (N + kGemmCfgs[c].bn - 1) / kGemmCfgs[c].bn;
     } else {
       ConvArgs a{h->act[cur], h->ldact, ly.bwd, h->R, 0, h->bt, v, e};
-      if (pf) pf->begin(std::string(mode == kBwdRelax ? "convt_bwd_relax_ci" : "convt_bwd_conc_ci") +
-                            std::to_string(ly.g.ci),
+      if (pf) pf->begin(std::string(mode == kBwdRelax ? "convt_bwd_relax_" : "convt_bwd_conc_") + conv_tag(ly.g),
                         2.0 * rows * conv_macs(ly.g), io);
       if (launch_convt_bwd(mode, a, s)) return fail(CV_ESHAPE, "unsupported conv channels");
       if (pf) pf->end();
@@ -1315,7 +1360,7 @@ int enqueue_fwd(cv_bound* h, const float* alpha, const float* beta, float* ga, f
       if (pf) pf->end();
     } else {
       ConvArgs a{in, lda, ly.fwd, h->R, last, h->bt, v, e};
-      if (pf) pf->begin(std::string(mode == kFwdX ? "conv_fwd_x_co" : "conv_fwd_co") + std::to_string(ly.g.co),
+      if (pf) pf->begin(std::string(mode == kFwdX ? "conv_fwd_x_" : "conv_fwd_") + conv_tag(ly.g),
                         2.0 * rows * conv_macs(ly.g), io);
       if (launch_conv_fwd(mode, a, s)) return fail(CV_ESHAPE, "unsupported conv channels");
       if (pf) pf->end();
@@ -1830,8 +1875,18 @@ int cv_bound_upper(cv_bound* h, const float* alpha, const float* beta, float* lb
   hipStream_t s = (hipStream_t)stream;
   if (h->R == 0) return CV_OK;
   if (h->L == 1) {  // no ReLU layer: the bound is exact and attained at x*
-    if ((rc = enqueue_bwd(h, alpha, beta, false, ub, nullptr, 0, s))) return rc;
-    if (lb) HIPCHK(hipMemcpyAsync(lb, ub, sizeof(float) * h->R, hipMemcpyDeviceToDevice, s));
+    // ub is the network's value at x*, never lowered by the sound margin;
+    // in sound mode lb is the lowered bound of a second pass
+    const bool snd = h->sound;
+    const Batch saved = h->bt;
+    h->sound = false;
+    h->bt.sw = nullptr;
+    rc = enqueue_bwd(h, alpha, beta, false, ub, nullptr, 0, s);
+    h->sound = snd;
+    h->bt = saved;
+    if (rc) return rc;
+    if (lb && snd && (rc = enqueue_bwd(h, alpha, beta, false, lb, nullptr, 0, s))) return rc;
+    if (lb && !snd) HIPCHK(hipMemcpyAsync(lb, ub, sizeof(float) * h->R, hipMemcpyDeviceToDevice, s));
     launch_fill_i32(sat, 1, h->R, s);
     HIPCHK(hipGetLastError());
     return CV_OK;
@@ -1950,6 +2005,67 @@ int cv_bound_autotune(cv_bound* h, void* stream) {
       g_tune[{mode, h->R, N, K}] = best;
     }
   }
+  // conv layers: each kernel variant timed per layer and direction on this
+  // batch (the same operands as a gradient pass)
+  for (int dir = 0; dir < 2; ++dir) {
+    for (int i = 1; i < L; ++i) {
+      DevLayer& ly = h->layers[i - 1];
+      if (ly.type != CV_LAYER_CONV2D) continue;
+      const int mode = conv_mode(i - 1, dir == 0, false);
+      Epi e = make_epi(h);
+      Vars v{};
+      v.alpha = nullptr;
+      v.beta = h->g_beta;
+      v.acomp = h->acomp;
+      v.galpha = h->g_alpha;
+      v.gbeta = h->g_beta;
+      v.xpos = h->xpos;
+      v.xneg = h->xneg;
+      const float* in = h->act[0];
+      int last = 0;
+      if (dir == 0) {
+        if (mode == kBwdRelax) {
+          e.layer_off = h->offs[i - 2];
+          e.bias = h->layers[i - 2].bias;
+          e.out = h->act[1];
+        }
+        e.slot0 = 1;
+        e.n = h->dims[i - 1];
+      } else {
+        e.layer_off = h->offs[i - 1];
+        e.bias = ly.bias;
+        e.n = h->dims[i];
+        e.out = h->act[1];
+        last = i == L - 1;
+      }
+      const ConvPlan def = dir == 0 ? ly.bwd_def : ly.fwd_def;
+      float best_ms = 1e30f;
+      int best = -1;
+      for (int var = 0; var < kNumConvVariants; ++var) {
+        ConvPlan pl = def;
+        if (conv_plan_variant(mode, pl, var)) continue;
+        ConvArgs a{in, h->ldact, pl, h->R, last, h->bt, v, e};
+        auto run = [&]() { return dir == 0 ? launch_convt_bwd(mode, a, s) : launch_conv_fwd(mode, a, s); };
+        for (int w = 0; w < 2; ++w)
+          if (run()) return fail(CV_ESHAPE, "unsupported conv channels");
+        HIPCHK(hipEventRecord(e0, s));
+        for (int w = 0; w < 5; ++w) run();
+        HIPCHK(hipEventRecord(e1, s));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = var;
+        }
+      }
+      if (best >= 0) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_conv_tune[conv_key(mode, h->R, ly.g)] = best;
+      }
+    }
+  }
+  assign_conv_variants(h, -1);
   // whole passes: fused dense chain or per-layer kernels
   if (h->chain_lo) {
     const int saved_b = h->chain_b, saved_f = h->chain_f;
@@ -2007,6 +2123,29 @@ int cv_bound_set_plan(cv_bound* h, int32_t chain_bwd, int32_t chain_fwd) {
 }
 
 int32_t cv_bound_num_tilings(void) { return kNumGemmCfgs; }
+
+int32_t cv_bound_num_conv_variants(void) { return kNumConvVariants; }
+
+int cv_bound_set_conv_variant(cv_bound* h, int32_t variant) {
+  if (!h) return fail(CV_EINVAL, "null handle");
+  if (variant < -1 || variant >= kNumConvVariants)
+    return fail(CV_EINVAL, "conv variant must be -1 or in [0, %d)", kNumConvVariants);
+  assign_conv_variants(h, variant);
+  drop_graph(h);
+  for (cv_bound* q : h->parts) {
+    assign_conv_variants(q, variant);
+    drop_graph(q);
+  }
+  return CV_OK;
+}
+
+int cv_bound_conv_variant(const cv_bound* h, int32_t layer, int32_t dir) {
+  if (!h || layer < 1 || layer > h->L || (dir != 0 && dir != 1)) return -1;
+  const DevLayer& d = h->layers[layer - 1];
+  if (d.type != CV_LAYER_CONV2D) return -1;
+  const ConvPlan& pl = dir == 0 ? d.bwd : d.fwd;
+  return (pl.sd ? 2 : 0) + (pl.wg ? 1 : 0);
+}
 
 int cv_bound_set_tiling(cv_bound* h, int32_t tiling) {
   if (!h) return fail(CV_EINVAL, "null handle");

@@ -74,13 +74,13 @@ __device__ __forceinline__ void epi_first(const Batch& bt, const Epi& e, int row
 // Input floats t = t0 + tid + 256 u of a row: the row of zin, or for a conv
 // first layer's adjoint step the box and the 32-bit words of the sign planes
 // of A(0) that hold bit t (x* is formed when the row is staged).
-template <int MODE>
+template <int MODE, int N>
 __device__ __forceinline__ void in_load(const float* zin, int ldi, const Batch& bt, const Vars& v, int row, int t0,
-                                        int din, float (&s1)[kPF], float (&s2)[kPF], uint32_t (&w1)[kPF],
-                                        uint32_t (&w2)[kPF]) {
+                                        int din, float (&s1)[N], float (&s2)[N], uint32_t (&w1)[N],
+                                        uint32_t (&w2)[N]) {
   const int p = MODE == kFwdX ? bt.prop[row / bt.m] : 0;
 #pragma unroll
-  for (int u = 0; u < kPF; ++u) {
+  for (int u = 0; u < N; ++u) {
     const int tc = min(t0 + (int)threadIdx.x + 256 * u, din - 1);
     if (MODE == kFwdX) {
       s1[u] = bt.xlo[(int64_t)p * bt.d0 + tc];
@@ -105,21 +105,84 @@ __device__ __forceinline__ int staged(const ConvPlan& pl, int t) {
   return c * pl.pplane + pl.bofs + y * pl.gwp + (rem - y * pl.gw);
 }
 
-template <int MODE>
+template <int MODE, int N>
 __device__ __forceinline__ void in_store(float* zi, const ConvPlan& pl, const Batch& bt, const Vars& v, int row,
-                                         int t0, int din, const float (&s1)[kPF], const float (&s2)[kPF],
-                                         const uint32_t (&w1)[kPF], const uint32_t (&w2)[kPF]) {
+                                         int t0, int din, const float (&s1)[N], const float (&s2)[N],
+                                         const uint32_t (&w1)[N], const uint32_t (&w2)[N]) {
   if (MODE == kFwdX) {
 #pragma unroll
-    for (int u = 0; u < kPF; ++u) {
+    for (int u = 0; u < N; ++u) {
       const int t = t0 + (int)threadIdx.x + 256 * u;
       if (t < din) zi[staged(pl, t)] = xstar((w1[u] >> (t & 31)) & 1, (w2[u] >> (t & 31)) & 1, s1[u], s2[u]);
     }
   } else {
 #pragma unroll
-    for (int u = 0; u < kPF; ++u) {
+    for (int u = 0; u < N; ++u) {
       const int t = t0 + (int)threadIdx.x + 256 * u;
       if (t < din) zi[staged(pl, t)] = s1[u];
+    }
+  }
+}
+
+// The implicit GEMM of one batch row, D = G Wm, from the row staged in zi into
+// its LDS output row zo: each wave takes 16-row tiles of m, all N tiles.
+template <int NT, bool WG>
+__device__ __forceinline__ void conv_gemm_row(const ConvPlan& pl, const float* zi, float* zo, const float* wl,
+                                              const int4* mt, const int4* kt, const int4* ntb, int n_ks, int n_mt,
+                                              int lane, int wave) {
+  for (int mtile = wave; mtile < n_mt; mtile += 4) {
+    const int4 me = mt[mtile * 16 + (lane & 15)];
+    floatx4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    // four K steps per pass (kpad is a multiple of 16): their table reads,
+    // gathers and weight reads are issued before the MFMAs that use them;
+    // weights from global memory are loaded one pass ahead
+    float bn[4][NT];
+    if (WG) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) bn[q][t] = wl[(q * NT + t) * 64];
+    }
+    for (int ks0 = 0; ks0 < n_ks; ks0 += 4) {
+      int4 ke[4];
+      float a[4], b[4][NT];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) ke[q] = kt[(ks0 + q) * 4 + (lane >> 4)];
+      if (WG) {
+        const int kn = ks0 + 4 < n_ks ? ks0 + 4 : ks0;  // the last pass reloads its own (unused)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int t = 0; t < NT; ++t) {
+            b[q][t] = bn[q][t];
+            bn[q][t] = wl[((kn + q) * NT + t) * 64];
+          }
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int t = 0; t < NT; ++t) b[q][t] = wl[((ks0 + q) * NT + t) * 64];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a[q] = zi[me.x + ke[q].x];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q], b[q][t], acc[t], 0, 0, 0);
+    }
+    // lane holds rows 4 (lane / 16) + r of the tile, column lane % 16
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int4 ne = ntb[t * 16 + (lane & 15)];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int4 mo = mt[mtile * 16 + 4 * (lane >> 4) + r];
+        const int y = pl.osy * mo.z + ne.x, x = pl.osx * mo.w + ne.y;
+        if (ne.z >= 0 && (unsigned)y < (unsigned)pl.oh && (unsigned)x < (unsigned)pl.ow)
+          zo[ne.z + y * pl.ow + x] = acc[t][r];
+      }
     }
   }
 }
@@ -186,61 +249,7 @@ __global__ __launch_bounds__(256, (conv_occupancy<MODE, NT>())) void conv_mm(con
     if (nrow < M) in_load<MODE>(zin, ldi, bt, v, nrow, 0, pl.din, s1, s2, w1, w2);
 
     // ---- the GEMM: one 16-row tile of m per wave at a time, all N tiles
-    for (int mtile = wave; mtile < n_mt; mtile += 4) {
-      const int4 me = mt[mtile * 16 + (lane & 15)];
-      floatx4 acc[NT];
-#pragma unroll
-      for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
-      // four K steps per pass (kpad is a multiple of 16): their table reads,
-      // gathers and weight reads are issued before the MFMAs that use them;
-      // weights from global memory are loaded one pass ahead
-      float bn[4][NT];
-      if (WG) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-          for (int t = 0; t < NT; ++t) bn[q][t] = wl[(q * NT + t) * 64];
-      }
-      for (int ks0 = 0; ks0 < n_ks; ks0 += 4) {
-        int4 ke[4];
-        float a[4], b[4][NT];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) ke[q] = kt[(ks0 + q) * 4 + (lane >> 4)];
-        if (WG) {
-          const int kn = ks0 + 4 < n_ks ? ks0 + 4 : ks0;  // the last pass reloads its own (unused)
-#pragma unroll
-          for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int t = 0; t < NT; ++t) {
-              b[q][t] = bn[q][t];
-              bn[q][t] = wl[((kn + q) * NT + t) * 64];
-            }
-        } else {
-#pragma unroll
-          for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int t = 0; t < NT; ++t) b[q][t] = wl[((ks0 + q) * NT + t) * 64];
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) a[q] = zi[me.x + ke[q].x];
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-          for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q], b[q][t], acc[t], 0, 0, 0);
-      }
-      // lane holds rows 4 (lane / 16) + r of the tile, column lane % 16
-#pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const int4 ne = ntb[t * 16 + (lane & 15)];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int4 mo = mt[mtile * 16 + 4 * (lane >> 4) + r];
-          const int y = pl.osy * mo.z + ne.x, x = pl.osx * mo.w + ne.y;
-          if (ne.z >= 0 && (unsigned)y < (unsigned)pl.oh && (unsigned)x < (unsigned)pl.ow)
-            zo[ne.z + y * pl.ow + x] = acc[t][r];
-        }
-      }
-    }
+    conv_gemm_row<NT, WG>(pl, zi, zo, wl, mt, kt, ntb, n_ks, n_mt, lane, wave);
     __syncthreads();
 
     // ---- epilogue over the output row in natural order: first-level
@@ -362,6 +371,236 @@ __global__ __launch_bounds__(256, (conv_occupancy<MODE, NT>())) void conv_mm(con
   }
 }
 
+// ---------------------------------------------------------------------------
+// Subdomain-major variant.  A workgroup takes work units of up to `mu`
+// consecutive specification rows of one subdomain (all m rows when m is
+// small).  The rows of a unit share the subdomain's status records and its
+// property's chords, biases and box, so those are loaded once per unit into
+// registers (NJ outputs per thread: dout <= 256 NJ), and the layer's bias
+// into LDS once per workgroup; each row's own variables (alpha or beta, the
+// stored A and the Adam moments) are loaded one row ahead, and the next row's
+// input (its first 256 NI floats; any rest after the epilogue) is loaded while
+// the current row's GEMM runs.  The epilogue then finds its operands in
+// registers and LDS: no dependent gather is left on a row's critical path.
+
+// Per-unit operands of outputs j = tid + 256 u: the status record and the
+// chord; for concretisation the box (or the ball's centre) in ch.
+template <int MODE, int NJ>
+__device__ __forceinline__ void sd_load(const Batch& bt, const Epi& e, int b, int p, int dout, uint32_t (&rec)[NJ],
+                                        float2 (&ch)[NJ]) {
+#pragma unroll
+  for (int u = 0; u < NJ; ++u) {
+    const int jc = min((int)threadIdx.x + 256 * u, dout - 1);
+    rec[u] = kInactive;
+    if (MODE == kBwdConc) {
+      const int64_t pb = (int64_t)p * bt.d0 + jc;
+      ch[u] = make_float2((bt.l2x0 ? bt.l2x0 : bt.xlo)[pb], bt.xhi[pb]);
+    } else {
+      rec[u] = bt.status[(int64_t)b * bt.nd + e.layer_off + jc];
+      ch[u] = bt.chord[(int64_t)p * bt.nd + e.layer_off + jc];  // defined (zero) for stable neurons too
+    }
+  }
+}
+
+// Per-row variables of outputs j = tid + 256 u.  Back-substitution: x1 = the
+// neuron's alpha (unstable) or beta (split), one load from a selected
+// address.  Adjoint: x1 = the stored A(i)_j and x2 = alpha of an unstable
+// neuron; with the fused Adam step also its moments (x3, x4).
+template <int MODE, int NJ>
+__device__ __forceinline__ void sd_row_vars(const Batch& bt, const Vars& v, const Epi& e, const RowInfo& ri,
+                                            int dout, const uint32_t (&rec)[NJ], float (&x1)[NJ], float (&x2)[NJ],
+                                            float (&x3)[NJ], float (&x4)[NJ]) {
+  const int64_t pc0 = (int64_t)ri.p * bt.nd + e.layer_off;
+#pragma unroll
+  for (int u = 0; u < NJ; ++u) {
+    const int j = (int)threadIdx.x + 256 * u;
+    const uint32_t r = rec[u];
+    const uint32_t kind = r & kKindMask;
+    const bool ok = j < dout;
+    x1[u] = x2[u] = x3[u] = x4[u] = 0.f;
+    if (MODE == kBwdRelax) {
+      const float* src = nullptr;
+      if (ok && kind == kUnstable) src = v.alpha ? v.alpha + ri.abase + (r & kCidxMask) : bt.adef + pc0 + j;
+      if (ok && kind == kSplit) src = v.beta + (int64_t)(r & kSplitMask) * bt.m + ri.k;
+      if (src) x1[u] = *src;
+    } else if (MODE == kFwd || MODE == kFwdX) {
+      if (ok && kind == kUnstable && !v.sat) {
+        const int64_t ai = ri.abase + (r & kCidxMask);
+        x1[u] = v.acomp[ai];
+        x2[u] = v.alpha ? v.alpha[ai] : bt.adef[pc0 + j];
+        if (v.adam) {
+          x3[u] = v.ma[ai];
+          x4[u] = v.va[ai];
+        }
+      }
+    }
+  }
+}
+
+// occupancy (waves per SIMD) of the subdomain-major kernels
+template <int MODE, int NJ>
+constexpr int conv_sd_occupancy() {
+  return 3;
+}
+
+template <int MODE, int NT, bool WG, int NJ, int NI>
+__global__ __launch_bounds__(256, (conv_sd_occupancy<MODE, NJ>())) void conv_sd(
+    const float* __restrict__ zin, int ldi, ConvPlan pl, int M, int last, Batch bt, Vars v, Epi e, int mu) {
+  extern __shared__ float4 smem4[];
+  __shared__ float red[2][4][2];
+  constexpr bool kBwd = MODE == kBwdRelax || MODE == kBwdConc;
+  const int m = bt.m;
+  const int upb = (m + mu - 1) / mu;  // units per subdomain
+  const int n_units = (M / m) * upb;
+  if ((int)blockIdx.x >= n_units) return;
+  float* const wm = reinterpret_cast<float*>(smem4);
+  const int nwm = WG ? 0 : pl.kpad * NT * 16;  // floats in LDS
+  int4* const mt = reinterpret_cast<int4*>(wm + nwm);
+  int4* const kt = mt + pl.mpad;
+  int4* const ntb = kt + pl.kpad;
+  float* const zi = reinterpret_cast<float*>(ntb + NT * 16);
+  float* const zo = zi + ((pl.dinp + 3) & ~3);
+  float* const bsh = zo + pl.dout;  // the output layer's bias per neuron (not for concretisation)
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+  for (int t = tid; t < nwm / 4; t += 256) smem4[t] = reinterpret_cast<const float4*>(pl.wm)[t];
+  for (int t = tid; t < pl.mpad; t += 256) mt[t] = pl.mtab[t];
+  for (int t = tid; t < pl.kpad; t += 256) kt[t] = pl.ktab[t];
+  for (int t = tid; t < NT * 16; t += 256) ntb[t] = pl.ntab[t];
+  for (int t = tid; t < pl.dinp; t += 256) zi[t] = 0.f;  // the borders stay zero: out-of-plane taps
+  if (MODE != kBwdConc)
+    for (int t = tid; t < pl.dout; t += 256) bsh[t] = e.bias[t];
+  __syncthreads();  // before any thread stages a row over the zeroed planes
+
+  int unit = blockIdx.x;
+  int b = unit / upb;
+  int r1 = b * m + min((unit - b * upb) * mu + mu, m);
+  int row = b * m + (unit - b * upb) * mu;
+  float s1[NI], s2[NI];
+  uint32_t w1[NI], w2[NI];
+  for (int t0 = 0; t0 < pl.din; t0 += 256 * NI) {
+    in_load<MODE>(zin, ldi, bt, v, row, t0, pl.din, s1, s2, w1, w2);
+    in_store<MODE>(zi, pl, bt, v, row, t0, pl.din, s1, s2, w1, w2);
+  }
+  uint32_t rec[NJ];
+  float2 ch[NJ];
+  float x1[NJ], x2[NJ], x3[NJ], x4[NJ];
+  int p = bt.prop[b];
+  sd_load<MODE>(bt, e, b, p, pl.dout, rec, ch);
+  RowInfo ri = row_info(bt, row);
+  sd_row_vars<MODE>(bt, v, e, ri, pl.dout, rec, x1, x2, x3, x4);
+  __syncthreads();
+
+  const int n_ks = pl.kpad >> 2, n_mt = pl.mpad >> 4;
+  const float* const wl = (WG ? pl.wm : wm) + lane;
+  for (int par = 0;; par ^= 1) {
+    // the next row: the unit's next, or the first of this workgroup's next unit
+    int nrow = row + 1, nunit = unit;
+    if (nrow >= r1) {
+      nunit = unit + gridDim.x;
+      const int nb = nunit / upb;
+      nrow = nunit < n_units ? nb * m + (nunit - nb * upb) * mu : -1;
+    }
+    if (nrow >= 0) in_load<MODE>(zin, ldi, bt, v, nrow, 0, pl.din, s1, s2, w1, w2);
+
+    conv_gemm_row<NT, WG>(pl, zi, zo, wl, mt, kt, ntb, n_ks, n_mt, lane, wave);
+    __syncthreads();
+    // every wave is past this row's GEMM: zi takes the next row (the rest of
+    // a long input row after the epilogue)
+    if (nrow >= 0) in_store<MODE>(zi, pl, bt, v, nrow, 0, pl.din, s1, s2, w1, w2);
+
+    // ---- epilogue: every operand is in registers
+    const int64_t pc0 = (int64_t)p * bt.nd + e.layer_off;
+    float cst = 0.f, cer = 0.f;
+#pragma unroll
+    for (int u = 0; u < NJ; ++u) {
+      const int j = tid + 256 * u;
+      const bool ok = j < pl.dout;
+      const float a = zo[min(j, pl.dout - 1)];
+      const uint32_t r = rec[u];
+      if (MODE == kBwdRelax) {
+        if (!ok) continue;
+        if (v.acomp && (r & kKindMask) == kUnstable) v.acomp[ri.abase + (r & kCidxMask)] = a;
+        const float lam = relax_value(bt, v, ri, r, ch[u], x1[u], a, bsh[j], &cst);
+        e.out[(int64_t)row * e.ldo + j] = lam;
+        if (bt.sw) cer = fmaf(fabsf(lam), bt.sw[pc0 + j], cer);
+      } else if (MODE == kBwdConc) {
+        if (bt.l2x0) {  // l2 ball: A(0) x0 here, - eps ||A(0)||_2 in the final sum
+          if (!ok) continue;
+          cst = fmaf(a, ch[u].x, cst);
+          cer = fmaf(a, a, cer);
+          if (v.xdense) v.xdense[(int64_t)row * v.ldx + j] = a;  // A(0) itself for the adjoint
+          continue;
+        }
+        if (ok) {
+          const float tm = conc_term(a, ch[u].x, ch[u].y);
+          cst += tm;
+          cer = fmaf(bt.sg, fabsf(tm), cer);
+        }
+        if (v.xpos) {  // x* as sign planes: one 64-bit word per wave
+          const uint64_t bp = __ballot(ok && a > 0.f), bn = __ballot(ok && a < 0.f);
+          const int w0 = 256 * u + wave * 64;
+          if (lane == 0 && w0 < pl.dout) {
+            v.xpos[(int64_t)row * bt.w64 + (w0 >> 6)] = bp;
+            v.xneg[(int64_t)row * bt.w64 + (w0 >> 6)] = bn;
+          }
+        }
+      } else {
+        if (!ok) continue;
+        // l2 ball, first layer: W(1) x* + b(1) = (W(1) x0 + b(1)) - l2s (W(1) A(0))
+        const float zb = e.wx0 ? fmaf(-v.l2s[row], a, e.wx0[(int64_t)p * e.n + j]) : a + bsh[j];
+        if (v.sat) {  // the network itself at x*: every layer's output is kept
+          e.out[(int64_t)row * e.ldo + j] = true_relu(r, zb, v.sat + row);
+          continue;
+        }
+        const float zh = relax_fwd_value(bt, v, ri, r, ch[u], x1[u], x2[u], pc0 + j, zb, v.adam != 0,
+                                         make_float2(x3[u], x4[u]));
+        if (!last) e.out[(int64_t)row * e.ldo + j] = zh;
+      }
+    }
+    if (kBwd) {
+      cst = wave_sum(cst);
+      cer = wave_sum(cer);
+      if (lane == 0) {
+        red[par][wave][0] = cst;
+        red[par][wave][1] = cer;
+      }
+    }
+    const int done_row = row;
+    if (nrow >= 0)
+      for (int t0 = 256 * NI; t0 < pl.din; t0 += 256 * NI) {
+        in_load<MODE>(zin, ldi, bt, v, nrow, t0, pl.din, s1, s2, w1, w2);
+        in_store<MODE>(zi, pl, bt, v, nrow, t0, pl.din, s1, s2, w1, w2);
+      }
+    // the next row's operands: for a new unit its status records and chords
+    // first, then the row's own variables
+    if (nrow >= 0) {
+      if (nunit != unit) {
+        unit = nunit;
+        b = unit / upb;
+        r1 = b * m + min((unit - b * upb) * mu + mu, m);
+        p = bt.prop[b];
+        sd_load<MODE>(bt, e, b, p, pl.dout, rec, ch);
+      }
+      row = nrow;
+      ri = row_info(bt, row);
+      sd_row_vars<MODE>(bt, v, e, ri, pl.dout, rec, x1, x2, x3, x4);
+    }
+    __syncthreads();
+    if (kBwd && tid == 0) {
+      const float tot = (red[par][0][0] + red[par][1][0]) + (red[par][2][0] + red[par][3][0]);
+      e.part[(int64_t)e.slot0 * M + done_row] = tot;
+      // rounding-error bound, or the sum of A(0)^2 (l2 ball); with both modes
+      // on, the other array's slot gets 0
+      float* const p2 = MODE == kBwdConc && bt.l2x0 ? e.psq : (e.perr ? e.perr : e.psq);
+      float* const pz = e.perr && e.psq ? (p2 == e.perr ? e.psq : e.perr) : nullptr;
+      if (p2) p2[(int64_t)e.slot0 * M + done_row] = (red[par][0][1] + red[par][1][1]) + (red[par][2][1] + red[par][3][1]);
+      if (pz) pz[(int64_t)e.slot0 * M + done_row] = 0.f;
+    }
+    if (nrow < 0) break;
+  }
+}
+
 template <int MODE, bool WG>
 const void* kernel_nt(int nt) {
   switch (nt) {
@@ -403,9 +642,81 @@ int dispatch_wg(const ConvArgs& a, hipStream_t st) {
 #undef CVB_CM
 }
 
+// (NJ, NI) pairs of the subdomain-major kernel instantiated per mode (the
+// layer shapes of the CIFAR-sized networks and small test networks)
+#define CVB_SD_BWD_RELAX(X) X(4, 4) X(4, 8) X(8, 4) X(8, 8)
+#define CVB_SD_BWD_CONC(X) X(4, 4) X(4, 8) X(12, 4) X(12, 8)
+#define CVB_SD_FWD_X(X) X(4, 4) X(8, 4)
+#define CVB_SD_FWD(X) X(4, 4) X(4, 8) X(8, 4) X(8, 8)
+
+template <int MODE, int NT, bool WG>
+const void* sd_kernel(int nj, int ni) {
+#define CVB_SDK(J, I) \
+  if (nj == J && ni == I) return reinterpret_cast<const void*>(conv_sd<MODE, NT, WG, J, I>);
+  if constexpr (MODE == kBwdRelax) {
+    CVB_SD_BWD_RELAX(CVB_SDK)
+  } else if constexpr (MODE == kBwdConc) {
+    CVB_SD_BWD_CONC(CVB_SDK)
+  } else if constexpr (MODE == kFwdX) {
+    CVB_SD_FWD_X(CVB_SDK)
+  } else {
+    CVB_SD_FWD(CVB_SDK)
+  }
+#undef CVB_SDK
+  return nullptr;
+}
+
+template <int MODE>
+const void* sd_kernel_for(int nt, bool wg, int nj, int ni) {
+  if (nt == 1) return wg ? sd_kernel<MODE, 1, true>(nj, ni) : sd_kernel<MODE, 1, false>(nj, ni);
+  if (nt == 2) return wg ? sd_kernel<MODE, 2, true>(nj, ni) : sd_kernel<MODE, 2, false>(nj, ni);
+  return nullptr;
+}
+
+const void* sd_kernel_mode(int mode, int nt, bool wg, int nj, int ni) {
+  switch (mode) {
+    case kBwdRelax: return sd_kernel_for<kBwdRelax>(nt, wg, nj, ni);
+    case kBwdConc: return sd_kernel_for<kBwdConc>(nt, wg, nj, ni);
+    case kFwdX: return sd_kernel_for<kFwdX>(nt, wg, nj, ni);
+    default: return sd_kernel_for<kFwd>(nt, wg, nj, ni);
+  }
+}
+
+// Work-unit size: all of a subdomain's rows when there are few (the
+// verification specs), else 16 (the identity specs of the root bounds).
+inline int sd_unit_rows(int m) { return m <= 32 ? m : 16; }
+
+template <int MODE, int NT, bool WG>
+int launch_sd(const ConvArgs& a, hipStream_t st) {
+  const int mu = sd_unit_rows(a.bt.m);
+  const int n_units = (a.M / a.bt.m) * ((a.bt.m + mu - 1) / mu);
+  const dim3 grid(std::min(n_units, a.pl.grid_sd > 0 ? a.pl.grid_sd : 512)), block(256);
+#define CVB_SDL(J, I)                                                                                            \
+  if (a.pl.nj == J && a.pl.ni == I) {                                                                           \
+    launch_k(conv_sd<MODE, NT, WG, J, I>, grid, block, a.pl.smem_sd, st, a.in, a.ldi, a.pl, a.M, a.last, a.bt, a.v, \
+             a.e, mu);                                                                                          \
+    return 0;                                                                                                   \
+  }
+  if constexpr (MODE == kBwdRelax) {
+    CVB_SD_BWD_RELAX(CVB_SDL)
+  } else if constexpr (MODE == kBwdConc) {
+    CVB_SD_BWD_CONC(CVB_SDL)
+  } else if constexpr (MODE == kFwdX) {
+    CVB_SD_FWD_X(CVB_SDL)
+  } else {
+    CVB_SD_FWD(CVB_SDL)
+  }
+#undef CVB_SDL
+  return -1;
+}
+
 template <int MODE>
 int dispatch(const ConvArgs& a, hipStream_t st) {
   if (a.M <= 0) return 0;
+  if (a.pl.sd && a.pl.nj > 0 && (a.pl.nt == 1 || a.pl.nt == 2)) {
+    if (a.pl.nt == 1) return a.pl.wg ? launch_sd<MODE, 1, true>(a, st) : launch_sd<MODE, 1, false>(a, st);
+    return a.pl.wg ? launch_sd<MODE, 2, true>(a, st) : launch_sd<MODE, 2, false>(a, st);
+  }
   return a.pl.wg ? dispatch_wg<MODE, true>(a, st) : dispatch_wg<MODE, false>(a, st);
 }
 
@@ -426,6 +737,52 @@ int conv_plan_grid(int mode, const ConvPlan& pl) {
     return 0;
   }
   return cus * per;
+}
+
+int conv_plan_variant(int mode, ConvPlan& pl, int variant) {
+  // 0/1: row-major kernel, 2/3: subdomain-major; odd: weights read from
+  // global memory instead of LDS
+  const int wg = variant & 1, sd = variant >> 1;
+  ConvPlan q = pl;
+  q.wg = wg;
+  q.smem = conv_plan_smem(q);
+  q.grid = conv_plan_grid(mode, q);
+  conv_plan_sd(mode, q);
+  if (q.smem > 65536 || (sd && (!q.nj || q.smem_sd > 65536 || q.grid_sd <= 0)) || (!sd && q.grid <= 0)) return -1;
+  q.sd = sd;
+  pl = q;
+  return 0;
+}
+
+void conv_plan_sd(int mode, ConvPlan& pl) {
+  // the smallest instantiated register sizes that hold the row's outputs and inputs
+  pl.nj = pl.ni = 0;
+  pl.grid_sd = 0;
+  pl.sd = 0;
+  // (the input prefetch depth ni need not cover the row: the rest is staged
+  // after the epilogue)
+  int nj = 0, ni = 0;
+  for (int c : {4, 8, 12, 16}) {
+    if (nj || pl.dout > 256 * c) continue;
+    for (int i : {4, 8, 12, 16})
+      if (sd_kernel_mode(mode, pl.nt, pl.wg != 0, c, i) && (!ni || pl.din > 256 * ni)) {
+        nj = c;
+        ni = i;
+      }
+  }
+  if (!nj) return;
+  pl.nj = nj;
+  pl.ni = ni;
+  const void* k = sd_kernel_mode(mode, pl.nt, pl.wg != 0, nj, ni);
+  pl.smem_sd = pl.smem + (mode == kBwdConc ? 0 : pl.dout * (int)sizeof(float));
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, 256, pl.smem_sd) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  pl.grid_sd = cus * per;
+  pl.sd = pl.grid_sd > 0 ? 1 : 0;
 }
 
 int launch_convt_bwd(int mode, const ConvArgs& a, hipStream_t s) {

@@ -92,6 +92,13 @@ struct ConvPlan {
   int wg;              // 1: the kernel reads wm from global memory, not LDS
   int grid;            // persistent workgroups
   int smem;            // dynamic LDS bytes
+  // subdomain-major kernel (conv_sd): outputs and inputs per thread held in
+  // registers (0: no instantiation holds this layer), its persistent
+  // workgroups, and whether launches use it (else the row-major conv_mm)
+  int nj, ni;
+  int grid_sd;
+  int smem_sd;  // its dynamic LDS bytes (the plan's and the layer's bias per neuron)
+  int sd;
 };
 struct ConvArgs {
   const float* in;
@@ -106,6 +113,15 @@ struct ConvArgs {
 // LDS bytes of a plan and the workgroups that run concurrently on the device
 int conv_plan_smem(const ConvPlan& pl);
 int conv_plan_grid(int mode, const ConvPlan& pl);
+// register sizes of the subdomain-major kernel for a plan (nj = ni = 0 when
+// no instantiation holds it) and its concurrent workgroups
+void conv_plan_sd(int mode, ConvPlan& pl);
+// Kernel variant of a conv plan: 0 row-major with the weights in LDS, 1
+// row-major reading them from global memory, 2 and 3 the subdomain-major
+// kernel likewise.  Rebuilds the LDS size and grids; -1 (plan unchanged)
+// when the variant cannot run this layer.
+constexpr int kNumConvVariants = 4;
+int conv_plan_variant(int mode, ConvPlan& pl, int variant);
 int launch_convt_bwd(int mode, const ConvArgs& a, hipStream_t s);
 int launch_conv_fwd(int mode, const ConvArgs& a, hipStream_t s);
 

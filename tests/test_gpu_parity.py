@@ -317,6 +317,44 @@ def test_every_tiling(name):
     assert guarded_rel(lb, lb_ref).max() <= TOL
 
 
+@pytest.mark.parametrize("name", ["cnn_base", "cnn_wide", "cnn_deep", "cnn_odd"])
+def test_every_conv_variant(name):
+    """Every conv kernel variant (row-major or subdomain-major, weights in LDS
+    or global memory) on every conv layer in both directions: bounds,
+    gradients and a 5-step optimisation against the oracle, and the tuned
+    choice afterwards."""
+    from paper_2103_06624_amd.api import BoundProblem
+    wl, orc, pb = problem(name)
+    alpha, beta = cases.random_vars(orc, seed=19)
+    ref = oracle_grads(orc, alpha, beta)
+    lb_ref = np.stack([r[0] for r in ref])
+    a0 = orc.default_alpha_flat()
+    z0 = np.zeros(orc.nnz * orc.m)
+    from oracle.beta_crown import AdamConfig
+    opt_ref = np.stack([orc.optimize(d, a0, z0, AdamConfig(iters=5))[0] for d in range(orc.B)])
+    n = BoundProblem.num_conv_variants()
+    assert n == 4
+    conv_layers = [i + 1 for i, ly in enumerate(wl.net.layers) if ly.kind == 1]
+    for var in range(n):
+        pb.set_conv_variant(var)
+        ran = [(pb.conv_variant(i, 0), pb.conv_variant(i, 1)) for i in conv_layers]
+        say("conv variant", name, var, "layers run", ran)
+        lb = pb.eval(dev(alpha), dev(beta)).cpu().numpy()
+        assert guarded_rel(lb, lb_ref).max() <= TOL, var
+        check_grad(name, orc, pb, alpha, beta, ref)
+        best, _ = pb.optimize(dev(a0), dev(z0), iters=5)
+        assert guarded_rel(best.cpu().numpy(), opt_ref).max() <= TOL, var
+    pb.autotune()
+    ran = [(pb.conv_variant(i, 0), pb.conv_variant(i, 1)) for i in conv_layers]
+    say("tuned", name, ran)
+    assert all(0 <= v < n for pair in ran for v in pair)
+    lb = pb.eval(dev(alpha), dev(beta)).cpu().numpy()
+    assert guarded_rel(lb, lb_ref).max() <= TOL
+    pb.set_conv_variant(-1)
+    with pytest.raises(Exception):
+        pb.set_conv_variant(n)
+
+
 def test_tiling_rejects_bad_values():
     from paper_2103_06624_amd.api import BoundProblem
     from paper_2103_06624_amd.binding import CvError
@@ -524,6 +562,43 @@ def test_point_box_gives_the_network_value(name):
         ref = np.asarray(wl.C[dp[d]], np.float64) @ (W @ z + bias)
         assert guarded_rel(lb[d], ref).max() <= TOL
         assert guarded_rel(best[d], ref).max() <= TOL
+
+
+def test_no_relu_layer_upper_bound_in_sound_mode():
+    """A network with no ReLU layer: the bound is the exact box minimum of
+    C (W x + b), attained at x*.  In sound mode only lb is lowered by the
+    rounding margin; ub stays the network's value at x* (an upper bound of
+    the minimum), identical to plain mode's."""
+    from oracle import beta_crown as bc
+    from paper_2103_06624_amd import synth
+    from paper_2103_06624_amd.api import BoundProblem
+    say("no ReLU layer, sound mode upper bound")
+    rng = np.random.default_rng(5)
+    d0, d1, P, m = 37, 6, 2, 5
+    W = rng.standard_normal((d1, d0)).astype(np.float32)
+    bias = rng.standard_normal(d1).astype(np.float32)
+    layers = [synth.Layer(synth.DENSE, W, bias, (d0, 1, 1), (d1, 1, 1))]
+    x0 = rng.uniform(0, 1, (P, d0)).astype(np.float32)
+    x_lo, x_hi = x0 - 0.1, x0 + 0.1
+    C = rng.standard_normal((P, m, d1)).astype(np.float32)
+    empty = np.zeros((P, 0), np.float32)
+    dp = np.array([0, 1, 1], np.int32)
+    pb = BoundProblem(layers, x_lo, x_hi, C, empty, empty, dp, np.zeros(4, np.int64), [], [], [])
+    a, b = pb.alpha_init(), pb.zeros_beta()
+    lb_p, ub_p, sat_p = (t.cpu().numpy() for t in pb.upper(a, b))
+    pb.set_sound(1)
+    lb_s, ub_s, sat_s = (t.cpu().numpy() for t in pb.upper(a, b))
+    net64 = bc.dense_net(layers)
+    for d in range(3):
+        p = dp[d]
+        ref = bc.bound(net64, x_lo[p].astype(np.float64), x_hi[p].astype(np.float64), C[p].astype(np.float64),
+                       [], [], [], [], [])
+        assert (lb_s[d] <= ref).all(), (lb_s[d], ref)
+        assert guarded_rel(lb_s[d], ref).max() <= SOUND_TOL
+        assert guarded_rel(ub_s[d], ref).max() <= TOL
+    assert np.array_equal(ub_s, ub_p) and (sat_s == 1).all() and (sat_p == 1).all()
+    assert (lb_s <= lb_p).all() and np.array_equal(lb_p, ub_p)
+    pb.close()
 
 
 @pytest.mark.parametrize("name", ["mlp_deep"])
