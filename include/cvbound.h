@@ -159,6 +159,25 @@ int cv_bound_eval(cv_bound *h, const float *alpha, const float *beta, float *lb,
 int cv_bound_grad(cv_bound *h, const float *alpha, const float *beta, float *lb,
                   float *g_alpha, float *g_beta, void *stream);
 
+/* cv_bound_grad for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation.
+ * Same arguments, results and stream semantics as cv_bound_grad, but no call
+ * allocates: where cv_bound_grad uses (and on its first call allocates) the
+ * handle's workspace -- the two activation buffers, the per-row partial
+ * sums, the stored A at unstable neurons, the box minimiser x* and the
+ * sound-mode / l2-ball partials -- this call carves them from one static
+ * device array of 32 MiB per GPU (its address resolved at cv_bound_init;
+ * the array lives until the process ends).  CV_ENOMEM, with the bytes
+ * needed in cv_last_error(), when the batch needs more than the array holds
+ * (about R (2 w + 2 d0/8 + 1 + slots) + 4 n_alpha bytes for R = n_dom * m
+ * rows of width w, plus 4 R d0 for a dense first layer).  Every piece is
+ * written before it is read, so nothing carries over between calls, but all
+ * calls on one GPU share the array: calls that overlap in time on the same
+ * GPU (two streams, two threads, two handles) race and must be serialised
+ * by the caller. */
+int cv_bound_grad_noalloc(cv_bound *h, const float *alpha, const float *beta, float *lb,
+                          float *g_alpha, float *g_beta, void *stream);
+
 /* The primal side of the branch-and-bound step (Alg. 1 and its footnote; the
  * appendix on infeasible subdomains): for each row, the box minimiser x* of
  * the final linear function of the bound at (alpha, beta) (Eq.

@@ -137,6 +137,13 @@ class BoundProblem:
         B.check(B.cv_bound_grad(self.h, _dptr(alpha), _dptr(beta), _dptr(lb), _dptr(ga), _dptr(gb), _stream()))
         return lb.view(self.B, self.m), ga, gb
 
+    def grad_noalloc(self, alpha, beta, lb, g_alpha, g_beta):
+        """cv_bound_grad into caller-provided outputs, with the library's
+        static workspace instead of the handle's (no device allocation)."""
+        B.check(B.cv_bound_grad_noalloc(self.h, _dptr(alpha), _dptr(beta), _dptr(lb), _dptr(g_alpha), _dptr(g_beta),
+                                        _stream()))
+        return lb.view(self.B, self.m), g_alpha, g_beta
+
     def upper(self, alpha, beta, with_lb=True):
         """(lb, ub, sat) [B, m]: the bound, the network at each row's box
         minimiser x*, and whether x* meets the subdomain's splits."""

@@ -56,6 +56,7 @@ SIGNATURES = {
     "cv_bound_alpha_init": (ctypes.c_int, [_vp, _vp, _vp]),
     "cv_bound_eval": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "cv_bound_grad": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "cv_bound_grad_noalloc": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "cv_bound_upper": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "cv_bound_optimize": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_float, ctypes.c_float, ctypes.c_float, _vp,
                                          _vp, _vp, ctypes.c_int32, _vp, _vp, _vp]),
@@ -115,6 +116,7 @@ cv_bound_alpha_offset = _fn("cv_bound_alpha_offset")
 cv_bound_alpha_init = _fn("cv_bound_alpha_init")
 cv_bound_eval = _fn("cv_bound_eval")
 cv_bound_grad = _fn("cv_bound_grad")
+cv_bound_grad_noalloc = _fn("cv_bound_grad_noalloc")
 cv_bound_upper = _fn("cv_bound_upper")
 cv_bound_optimize = _fn("cv_bound_optimize")
 cv_bound_autotune = _fn("cv_bound_autotune")

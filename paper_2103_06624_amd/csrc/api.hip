@@ -138,6 +138,7 @@ struct GraphKey {
 
 struct cv_bound {
   DevMem mem;
+  int dev = 0;  // the device the handle was built on
   int L = 0;  // layers (ReLU after 1..L-1)
   std::vector<DevLayer> layers;
   std::vector<int> dims;  // d_0..d_L
@@ -1525,6 +1526,7 @@ int set_parts(cv_bound* h, int n) {
       free_parts(h);
       return rc;
     }
+    q->dev = h->dev;
     q->chain_b = h->chain_b ? (q->chain_lo ? 1 : 0) : 0;
     q->chain_f = h->chain_f ? (q->chain_lo && q->chain_lo + 1 <= q->L - 1 ? 1 : 0) : 0;
     h->parts.push_back(q.release());
@@ -1669,6 +1671,110 @@ void keep_inputs(cv_bound* h, const cv_layer* layers, int n_layers, int P, const
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Workspace of cv_bound_grad_noalloc: one static device array per GPU, held
+// until the process ends.  Its host-side name is not a device address: host
+// code uses only the address hipGetSymbolAddress returns for the current
+// device, resolved once per device at cv_bound_init.
+
+constexpr size_t kScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int resolve_scratch(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(CV_EDEVICE, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return CV_OK;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) {
+    (void)hipGetLastError();
+    return fail(CV_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+  }
+  g_scratch_ptr[dev] = p;
+  return CV_OK;
+}
+
+// The gradient pass with every workspace buffer carved from the static array
+// (256-byte aligned pieces): the two activation buffers, the partial slots,
+// the stored A at unstable neurons, x* (sign planes and/or dense rows) and
+// the sound-mode / l2-ball partials.  Every piece is written by the pass
+// before it is read, so nothing needs clearing.  The handle's own buffers are
+// swapped out for the launches and restored afterwards (kernel arguments are
+// taken at launch).
+int grad_noalloc(cv_bound* h, const float* alpha, const float* beta, float* lb, float* g_alpha, float* g_beta,
+                 hipStream_t s) {
+  void* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    base = (h->dev >= 0 && h->dev < kMaxDevices) ? g_scratch_ptr[h->dev] : nullptr;
+  }
+  if (!base) return fail(CV_EDEVICE, "static workspace not resolved for device %d", h->dev);
+  const size_t R = (size_t)std::max(1, h->R);
+  const bool dense1 = h->layers[0].type == CV_LAYER_DENSE;
+  const int ldx = r4(h->d0);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off += (bytes + 255) & ~(size_t)255;
+    return at;
+  };
+  const size_t o_act0 = h->L >= 2 ? take(R * h->ldact * sizeof(float)) : 0;
+  const size_t o_act1 = h->L >= 2 ? take(R * h->ldact * sizeof(float)) : 0;
+  const size_t o_part = take(R * h->n_slots * sizeof(float));
+  const size_t o_acomp = take((size_t)std::max<int64_t>(1, h->n_alpha) * sizeof(float));
+  const size_t o_xpos = take(R * h->w64 * sizeof(uint64_t));
+  const size_t o_xneg = take(R * h->w64 * sizeof(uint64_t));
+  const bool need_xd = dense1 || h->l2;
+  const size_t o_xd = need_xd ? take(R * ldx * sizeof(float)) : 0;
+  const size_t o_perr = h->sound ? take(R * h->n_slots * sizeof(float)) : 0;
+  const size_t o_psq = h->l2 ? take(R * h->n_slots * sizeof(float)) : 0;
+  const size_t o_l2s = h->l2 ? take(R * sizeof(float)) : 0;
+  if (off > kScratchBytes)
+    return fail(CV_ENOMEM, "cv_bound_grad_noalloc: this batch needs %zu bytes of workspace, the static array holds %zu",
+                off, kScratchBytes);
+  unsigned char* b = static_cast<unsigned char*>(base);
+  struct Saved {
+    float *act0, *act1, *part, *acomp, *xdense, *perr, *psq, *l2s;
+    uint64_t *xpos, *xneg;
+    int ldx;
+  } sv{h->act[0], h->act[1], h->part, h->acomp, h->xdense, h->perr, h->psq, h->l2s, h->xpos, h->xneg, h->ldx};
+  if (h->L >= 2) {
+    h->act[0] = reinterpret_cast<float*>(b + o_act0);
+    h->act[1] = reinterpret_cast<float*>(b + o_act1);
+  }
+  h->part = reinterpret_cast<float*>(b + o_part);
+  h->acomp = reinterpret_cast<float*>(b + o_acomp);
+  h->xpos = reinterpret_cast<uint64_t*>(b + o_xpos);
+  h->xneg = reinterpret_cast<uint64_t*>(b + o_xneg);
+  if (need_xd) {
+    h->xdense = reinterpret_cast<float*>(b + o_xd);
+    h->ldx = ldx;
+  }
+  if (h->sound) h->perr = reinterpret_cast<float*>(b + o_perr);
+  if (h->l2) {
+    h->psq = reinterpret_cast<float*>(b + o_psq);
+    h->l2s = reinterpret_cast<float*>(b + o_l2s);
+  }
+  int rc = enqueue_bwd(h, alpha, beta, true, lb, nullptr, 0, s);
+  if (!rc) rc = enqueue_fwd(h, alpha, beta, g_alpha, g_beta, nullptr, s);
+  h->act[0] = sv.act0;
+  h->act[1] = sv.act1;
+  h->part = sv.part;
+  h->acomp = sv.acomp;
+  h->xdense = sv.xdense;
+  h->perr = sv.perr;
+  h->psq = sv.psq;
+  h->l2s = sv.l2s;
+  h->xpos = sv.xpos;
+  h->xneg = sv.xneg;
+  h->ldx = sv.ldx;
+  return rc;
+}
+
 // ===========================================================================
 // ABI
 
@@ -1770,6 +1876,9 @@ int cv_bound_init(cv_bound** out, const cv_layer* layers, int32_t n_layers, int3
   int rc = build(h.get(), layers, n_layers, n_props, x_lo, x_hi, m, sp, l, u, n_dom, dom_prop, split_ptr,
                  split_layer, split_neuron, split_side, (hipStream_t)stream);
   if (rc) return rc;
+  // the device of this handle, and the address of its static workspace there
+  HIPCHK(hipGetDevice(&h->dev));
+  if ((rc = resolve_scratch(h->dev))) return rc;
   keep_inputs(h.get(), layers, n_layers, n_props, x_lo, x_hi, m, C, l, u, n_dom, dom_prop, split_ptr, split_layer,
               split_neuron, split_side);
   // large batches: two concurrent halves in the optimiser (their kernels
@@ -1864,6 +1973,15 @@ int cv_bound_grad(cv_bound* h, const float* alpha, const float* beta, float* lb,
   hipStream_t s = (hipStream_t)stream;
   if ((rc = enqueue_bwd(h, alpha, beta, true, lb, nullptr, 0, s))) return rc;
   return enqueue_fwd(h, alpha, beta, g_alpha, g_beta, nullptr, s);
+}
+
+int cv_bound_grad_noalloc(cv_bound* h, const float* alpha, const float* beta, float* lb, float* g_alpha,
+                          float* g_beta, void* stream) {
+  if (!h || (!lb && h->R > 0) || (!alpha && h->n_alpha > 0) || (!beta && h->nnz > 0) || (!g_alpha && h->n_alpha > 0) ||
+      (!g_beta && h->nnz > 0))
+    return fail(CV_EINVAL, "null argument");
+  if (h->R == 0) return CV_OK;
+  return grad_noalloc(h, alpha, beta, lb, g_alpha, g_beta, (hipStream_t)stream);
 }
 
 int cv_bound_upper(cv_bound* h, const float* alpha, const float* beta, float* lb, float* ub, int32_t* sat,
