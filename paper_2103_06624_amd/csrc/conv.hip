@@ -38,6 +38,9 @@ namespace {
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kPF = 4;  // per thread and row: input floats and output records loaded ahead
+// s_waitcnt immediate for vmcnt(0) with the other counters left free (gfx9
+// encoding: vmcnt bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8)
+constexpr int kWaitVm0 = 0x0F70;
 constexpr int kEU = 4;  // outputs per thread whose second-level operands are gathered together
 
 // Sum of x over the block (256 threads), returned to thread 0.
@@ -74,14 +77,14 @@ __device__ __forceinline__ void epi_first(const Batch& bt, const Epi& e, int row
 // Input floats t = t0 + tid + 256 u of a row: the row of zin, or for a conv
 // first layer's adjoint step the box and the 32-bit words of the sign planes
 // of A(0) that hold bit t (x* is formed when the row is staged).
-template <int MODE, int N>
+template <int MODE, int N, int TB = 256>
 __device__ __forceinline__ void in_load(const float* zin, int ldi, const Batch& bt, const Vars& v, int row, int t0,
                                         int din, float (&s1)[N], float (&s2)[N], uint32_t (&w1)[N],
                                         uint32_t (&w2)[N]) {
   const int p = MODE == kFwdX ? bt.prop[row / bt.m] : 0;
 #pragma unroll
   for (int u = 0; u < N; ++u) {
-    const int tc = min(t0 + (int)threadIdx.x + 256 * u, din - 1);
+    const int tc = min(t0 + (int)threadIdx.x + TB * u, din - 1);
     if (MODE == kFwdX) {
       s1[u] = bt.xlo[(int64_t)p * bt.d0 + tc];
       s2[u] = bt.xhi[(int64_t)p * bt.d0 + tc];
@@ -105,20 +108,20 @@ __device__ __forceinline__ int staged(const ConvPlan& pl, int t) {
   return c * pl.pplane + pl.bofs + y * pl.gwp + (rem - y * pl.gw);
 }
 
-template <int MODE, int N>
+template <int MODE, int N, int TB = 256>
 __device__ __forceinline__ void in_store(float* zi, const ConvPlan& pl, const Batch& bt, const Vars& v, int row,
                                          int t0, int din, const float (&s1)[N], const float (&s2)[N],
                                          const uint32_t (&w1)[N], const uint32_t (&w2)[N]) {
   if (MODE == kFwdX) {
 #pragma unroll
     for (int u = 0; u < N; ++u) {
-      const int t = t0 + (int)threadIdx.x + 256 * u;
+      const int t = t0 + (int)threadIdx.x + TB * u;
       if (t < din) zi[staged(pl, t)] = xstar((w1[u] >> (t & 31)) & 1, (w2[u] >> (t & 31)) & 1, s1[u], s2[u]);
     }
   } else {
 #pragma unroll
     for (int u = 0; u < N; ++u) {
-      const int t = t0 + (int)threadIdx.x + 256 * u;
+      const int t = t0 + (int)threadIdx.x + TB * u;
       if (t < din) zi[staged(pl, t)] = s1[u];
     }
   }
@@ -126,11 +129,15 @@ __device__ __forceinline__ void in_store(float* zi, const ConvPlan& pl, const Ba
 
 // The implicit GEMM of one batch row, D = G Wm, from the row staged in zi into
 // its LDS output row zo: each wave takes 16-row tiles of m, all N tiles.
-template <int NT, bool WG>
+// With sct set, the output slot of every accumulator element comes from a
+// table built once per workgroup (sct[(mtile NT + t) 64 + lane] holds the
+// four rows' slots; slots outside the plane point at a spare slot past the
+// row), so the scatter is four unconditional LDS stores.
+template <int NT, bool WG, int NW = 4>
 __device__ __forceinline__ void conv_gemm_row(const ConvPlan& pl, const float* zi, float* zo, const float* wl,
                                               const int4* mt, const int4* kt, const int4* ntb, int n_ks, int n_mt,
-                                              int lane, int wave) {
-  for (int mtile = wave; mtile < n_mt; mtile += 4) {
+                                              int lane, int wave, const int4* sct = nullptr) {
+  for (int mtile = wave; mtile < n_mt; mtile += NW) {
     const int4 me = mt[mtile * 16 + (lane & 15)];
     floatx4 acc[NT];
 #pragma unroll
@@ -173,6 +180,17 @@ __device__ __forceinline__ void conv_gemm_row(const ConvPlan& pl, const float* z
         for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q], b[q][t], acc[t], 0, 0, 0);
     }
     // lane holds rows 4 (lane / 16) + r of the tile, column lane % 16
+    if (sct) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int4 ad = sct[(mtile * NT + t) * 64 + lane];
+        zo[ad.x] = acc[t][0];
+        zo[ad.y] = acc[t][1];
+        zo[ad.z] = acc[t][2];
+        zo[ad.w] = acc[t][3];
+      }
+      continue;
+    }
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       const int4 ne = ntb[t * 16 + (lane & 15)];
@@ -184,6 +202,18 @@ __device__ __forceinline__ void conv_gemm_row(const ConvPlan& pl, const float* z
           zo[ne.z + y * pl.ow + x] = acc[t][r];
       }
     }
+  }
+}
+
+// in_store with the staged slots of inputs t = tid + TB u precomputed (so)
+template <int MODE, int N, int TB>
+__device__ __forceinline__ void in_store_at(float* zi, const int (&so)[N], int din, const float (&s1)[N],
+                                            const float (&s2)[N], const uint32_t (&w1)[N], const uint32_t (&w2)[N]) {
+#pragma unroll
+  for (int u = 0; u < N; ++u) {
+    const int t = (int)threadIdx.x + TB * u;
+    if (t >= din) continue;
+    zi[so[u]] = MODE == kFwdX ? xstar((w1[u] >> (t & 31)) & 1, (w2[u] >> (t & 31)) & 1, s1[u], s2[u]) : s1[u];
   }
 }
 
@@ -376,21 +406,24 @@ __global__ __launch_bounds__(256, (conv_occupancy<MODE, NT>())) void conv_mm(con
 // consecutive specification rows of one subdomain (all m rows when m is
 // small).  The rows of a unit share the subdomain's status records and its
 // property's chords, biases and box, so those are loaded once per unit into
-// registers (NJ outputs per thread: dout <= 256 NJ), and the layer's bias
+// registers (NJ outputs per thread: dout <= 512 NJ), and the layer's bias
 // into LDS once per workgroup; each row's own variables (alpha or beta, the
 // stored A and the Adam moments) are loaded one row ahead, and the next row's
-// input (its first 256 NI floats; any rest after the epilogue) is loaded while
+// input (its first 512 NI floats; any rest after the epilogue) is loaded while
 // the current row's GEMM runs.  The epilogue then finds its operands in
 // registers and LDS: no dependent gather is left on a row's critical path.
 
-// Per-unit operands of outputs j = tid + 256 u: the status record and the
+constexpr int kSdThreads = 512;  // threads per workgroup of the subdomain-major kernel
+constexpr int kSdWaves = kSdThreads / 64;
+
+// Per-unit operands of outputs j = tid + 512 u: the status record and the
 // chord; for concretisation the box (or the ball's centre) in ch.
 template <int MODE, int NJ>
 __device__ __forceinline__ void sd_load(const Batch& bt, const Epi& e, int b, int p, int dout, uint32_t (&rec)[NJ],
                                         float2 (&ch)[NJ]) {
 #pragma unroll
   for (int u = 0; u < NJ; ++u) {
-    const int jc = min((int)threadIdx.x + 256 * u, dout - 1);
+    const int jc = min((int)threadIdx.x + kSdThreads * u, dout - 1);
     rec[u] = kInactive;
     if (MODE == kBwdConc) {
       const int64_t pb = (int64_t)p * bt.d0 + jc;
@@ -402,7 +435,7 @@ __device__ __forceinline__ void sd_load(const Batch& bt, const Epi& e, int b, in
   }
 }
 
-// Per-row variables of outputs j = tid + 256 u.  Back-substitution: x1 = the
+// Per-row variables of outputs j = tid + 512 u.  Back-substitution: x1 = the
 // neuron's alpha (unstable) or beta (split), one load from a selected
 // address.  Adjoint: x1 = the stored A(i)_j and x2 = alpha of an unstable
 // neuron; with the fused Adam step also its moments (x3, x4).
@@ -413,7 +446,7 @@ __device__ __forceinline__ void sd_row_vars(const Batch& bt, const Vars& v, cons
   const int64_t pc0 = (int64_t)ri.p * bt.nd + e.layer_off;
 #pragma unroll
   for (int u = 0; u < NJ; ++u) {
-    const int j = (int)threadIdx.x + 256 * u;
+    const int j = (int)threadIdx.x + kSdThreads * u;
     const uint32_t r = rec[u];
     const uint32_t kind = r & kKindMask;
     const bool ok = j < dout;
@@ -438,16 +471,18 @@ __device__ __forceinline__ void sd_row_vars(const Batch& bt, const Vars& v, cons
 }
 
 // occupancy (waves per SIMD) of the subdomain-major kernels
-template <int MODE, int NJ>
+template <int MODE, int NJ, int NI>
 constexpr int conv_sd_occupancy() {
-  return 3;
+  // the adjoint holds four variables per output (stored A, alpha, Adam
+  // moments) and the first layer's the sign-plane words of its input
+  return NJ >= 8 || NJ + NI >= 12 ? 3 : 4;
 }
 
 template <int MODE, int NT, bool WG, int NJ, int NI>
-__global__ __launch_bounds__(256, (conv_sd_occupancy<MODE, NJ>())) void conv_sd(
+__global__ __launch_bounds__(kSdThreads, (conv_sd_occupancy<MODE, NJ, NI>())) void conv_sd(
     const float* __restrict__ zin, int ldi, ConvPlan pl, int M, int last, Batch bt, Vars v, Epi e, int mu) {
   extern __shared__ float4 smem4[];
-  __shared__ float red[2][4][2];
+  __shared__ float red[2][kSdWaves][2];
   constexpr bool kBwd = MODE == kBwdRelax || MODE == kBwdConc;
   const int m = bt.m;
   const int upb = (m + mu - 1) / mu;  // units per subdomain
@@ -459,145 +494,180 @@ __global__ __launch_bounds__(256, (conv_sd_occupancy<MODE, NJ>())) void conv_sd(
   int4* const kt = mt + pl.mpad;
   int4* const ntb = kt + pl.kpad;
   float* const zi = reinterpret_cast<float*>(ntb + NT * 16);
-  float* const zo = zi + ((pl.dinp + 3) & ~3);
-  float* const bsh = zo + pl.dout;  // the output layer's bias per neuron (not for concretisation)
+  float* const zo = zi + ((pl.dinp + 3) & ~3);  // the output row, then a spare slot (padding: at most 7 floats)
+  int4* const sct = reinterpret_cast<int4*>(zo + ((pl.dout + 4 + 3) & ~3));  // scatter slots [n_mt NT 64]
+  const int n_mt = pl.mpad >> 4;
+  float* const bsh = reinterpret_cast<float*>(sct + n_mt * NT * 64);  // bias per neuron (not for concretisation)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
-  for (int t = tid; t < nwm / 4; t += 256) smem4[t] = reinterpret_cast<const float4*>(pl.wm)[t];
-  for (int t = tid; t < pl.mpad; t += 256) mt[t] = pl.mtab[t];
-  for (int t = tid; t < pl.kpad; t += 256) kt[t] = pl.ktab[t];
-  for (int t = tid; t < NT * 16; t += 256) ntb[t] = pl.ntab[t];
-  for (int t = tid; t < pl.dinp; t += 256) zi[t] = 0.f;  // the borders stay zero: out-of-plane taps
+  for (int t = tid; t < nwm / 4; t += kSdThreads) smem4[t] = reinterpret_cast<const float4*>(pl.wm)[t];
+  for (int t = tid; t < pl.mpad; t += kSdThreads) mt[t] = pl.mtab[t];
+  for (int t = tid; t < pl.kpad; t += kSdThreads) kt[t] = pl.ktab[t];
+  for (int t = tid; t < NT * 16; t += kSdThreads) ntb[t] = pl.ntab[t];
+  for (int t = tid; t < pl.dinp; t += kSdThreads) zi[t] = 0.f;  // the borders stay zero: out-of-plane taps
   if (MODE != kBwdConc)
-    for (int t = tid; t < pl.dout; t += 256) bsh[t] = e.bias[t];
+    for (int t = tid; t < pl.dout; t += kSdThreads) bsh[t] = e.bias[t];
   __syncthreads();  // before any thread stages a row over the zeroed planes
-
-  int unit = blockIdx.x;
-  int b = unit / upb;
-  int r1 = b * m + min((unit - b * upb) * mu + mu, m);
-  int row = b * m + (unit - b * upb) * mu;
-  float s1[NI], s2[NI];
-  uint32_t w1[NI], w2[NI];
-  for (int t0 = 0; t0 < pl.din; t0 += 256 * NI) {
-    in_load<MODE>(zin, ldi, bt, v, row, t0, pl.din, s1, s2, w1, w2);
-    in_store<MODE>(zi, pl, bt, v, row, t0, pl.din, s1, s2, w1, w2);
-  }
-  uint32_t rec[NJ];
-  float2 ch[NJ];
-  float x1[NJ], x2[NJ], x3[NJ], x4[NJ];
-  int p = bt.prop[b];
-  sd_load<MODE>(bt, e, b, p, pl.dout, rec, ch);
-  RowInfo ri = row_info(bt, row);
-  sd_row_vars<MODE>(bt, v, e, ri, pl.dout, rec, x1, x2, x3, x4);
-  __syncthreads();
-
-  const int n_ks = pl.kpad >> 2, n_mt = pl.mpad >> 4;
-  const float* const wl = (WG ? pl.wm : wm) + lane;
-  for (int par = 0;; par ^= 1) {
-    // the next row: the unit's next, or the first of this workgroup's next unit
-    int nrow = row + 1, nunit = unit;
-    if (nrow >= r1) {
-      nunit = unit + gridDim.x;
-      const int nb = nunit / upb;
-      nrow = nunit < n_units ? nb * m + (nunit - nb * upb) * mu : -1;
-    }
-    if (nrow >= 0) in_load<MODE>(zin, ldi, bt, v, nrow, 0, pl.din, s1, s2, w1, w2);
-
-    conv_gemm_row<NT, WG>(pl, zi, zo, wl, mt, kt, ntb, n_ks, n_mt, lane, wave);
-    __syncthreads();
-    // every wave is past this row's GEMM: zi takes the next row (the rest of
-    // a long input row after the epilogue)
-    if (nrow >= 0) in_store<MODE>(zi, pl, bt, v, nrow, 0, pl.din, s1, s2, w1, w2);
-
-    // ---- epilogue: every operand is in registers
-    const int64_t pc0 = (int64_t)p * bt.nd + e.layer_off;
-    float cst = 0.f, cer = 0.f;
+  // the scatter slot of every accumulator element (the same for every row);
+  // element r of lane l in tile (mtile, t) is output (m = 16 mtile + 4 (l / 16)
+  // + r, n = 16 t + l % 16); outputs outside the plane go to the spare slot
+  for (int i = tid; i < n_mt * NT * 64; i += kSdThreads) {
+    const int mtile = i / (NT * 64), t = (i / 64) % NT, ln = i % 64;
+    const int4 ne = ntb[t * 16 + (ln & 15)];
+    int ad[4];
 #pragma unroll
-    for (int u = 0; u < NJ; ++u) {
-      const int j = tid + 256 * u;
-      const bool ok = j < pl.dout;
-      const float a = zo[min(j, pl.dout - 1)];
-      const uint32_t r = rec[u];
-      if (MODE == kBwdRelax) {
-        if (!ok) continue;
-        if (v.acomp && (r & kKindMask) == kUnstable) v.acomp[ri.abase + (r & kCidxMask)] = a;
-        const float lam = relax_value(bt, v, ri, r, ch[u], x1[u], a, bsh[j], &cst);
-        e.out[(int64_t)row * e.ldo + j] = lam;
-        if (bt.sw) cer = fmaf(fabsf(lam), bt.sw[pc0 + j], cer);
-      } else if (MODE == kBwdConc) {
-        if (bt.l2x0) {  // l2 ball: A(0) x0 here, - eps ||A(0)||_2 in the final sum
+    for (int r = 0; r < 4; ++r) {
+      const int4 mo = mt[mtile * 16 + 4 * (ln >> 4) + r];
+      const int y = pl.osy * mo.z + ne.x, x = pl.osx * mo.w + ne.y;
+      const bool ok = ne.z >= 0 && (unsigned)y < (unsigned)pl.oh && (unsigned)x < (unsigned)pl.ow;
+      ad[r] = ok ? ne.z + y * pl.ow + x : pl.dout;
+    }
+    sct[i] = make_int4(ad[0], ad[1], ad[2], ad[3]);
+  }
+  // the staged slots of this thread's first NI kSdThreads inputs (the same for every row)
+  int so[NI];
+#pragma unroll
+  for (int u = 0; u < NI; ++u) so[u] = staged(pl, min(tid + kSdThreads * u, pl.din - 1));
+
+  // the first row of this workgroup's first unit: staged before the loop;
+  // later units' first rows are staged by the previous row, like any next row
+  {
+    const int b0 = blockIdx.x / upb;
+    const int row0 = b0 * m + ((int)blockIdx.x - b0 * upb) * mu;
+    float s1[NI], s2[NI];
+    uint32_t w1[NI], w2[NI];
+    for (int t0 = 0; t0 < pl.din; t0 += kSdThreads * NI) {
+      in_load<MODE, NI, kSdThreads>(zin, ldi, bt, v, row0, t0, pl.din, s1, s2, w1, w2);
+      in_store<MODE, NI, kSdThreads>(zi, pl, bt, v, row0, t0, pl.din, s1, s2, w1, w2);
+    }
+  }
+  const int n_ks = pl.kpad >> 2;
+  const float* const wl = (WG ? pl.wm : wm) + lane;
+  int par = 0;
+  for (int unit = blockIdx.x; unit < n_units; unit += gridDim.x) {
+    const int b = unit / upb;
+    const int r0 = b * m + (unit - b * upb) * mu;
+    const int r1 = b * m + min((unit - b * upb) * mu + mu, m);
+    const int p = bt.prop[b];
+    // a row's first alpha entry is its subdomain's plus k times the
+    // property's unstable count (the layout of rbase): no per-row load
+    const int64_t ab0 = bt.aoff[b];
+    const int uc = bt.ucount[p];
+    const int64_t pc0 = (int64_t)p * bt.nd + e.layer_off;
+    uint32_t rec[NJ];
+    float2 ch[NJ];
+    float x1[NJ], x2[NJ], x3[NJ], x4[NJ];
+    sd_load<MODE>(bt, e, b, p, pl.dout, rec, ch);
+    RowInfo ri{b, r0 - b * m, p, ab0 + (int64_t)(r0 - b * m) * uc};
+    sd_row_vars<MODE>(bt, v, e, ri, pl.dout, rec, x1, x2, x3, x4);
+    // the next unit's first row (staged during this unit's last row)
+    const int nunit = unit + gridDim.x;
+    const int nb = nunit / upb;
+    const int nfirst = nunit < n_units ? nb * m + (nunit - nb * upb) * mu : -1;
+    __syncthreads();  // the unit's first row is staged
+
+    for (int row = r0; row < r1; ++row, par ^= 1) {
+      const int nrow = row + 1 < r1 ? row + 1 : nfirst;
+      float s1[NI], s2[NI];
+      uint32_t w1[NI], w2[NI];
+      if (nrow >= 0) in_load<MODE, NI, kSdThreads>(zin, ldi, bt, v, nrow, 0, pl.din, s1, s2, w1, w2);
+
+      conv_gemm_row<NT, WG, kSdWaves>(pl, zi, zo, wl, mt, kt, ntb, n_ks, n_mt, lane, wave, sct);
+      __syncthreads();
+      // every wave is past this row's GEMM: zi takes the next row (the rest
+      // of a long input row after the epilogue)
+      if (nrow >= 0) in_store_at<MODE, NI, kSdThreads>(zi, so, pl.din, s1, s2, w1, w2);
+
+      // ---- epilogue: every operand is in registers.  One wait for every
+      // outstanding load here (the row's variables and the staged input have
+      // long arrived): the compiler then knows they are ready and issues no
+      // wait between the epilogue's stores, which would otherwise each wait
+      // for the store before it (stores count against the same counter)
+      __builtin_amdgcn_s_waitcnt(kWaitVm0);
+      float cst = 0.f, cer = 0.f;
+#pragma unroll
+      for (int u = 0; u < NJ; ++u) {
+        const int j = tid + kSdThreads * u;
+        const bool ok = j < pl.dout;
+        const float a = zo[min(j, pl.dout - 1)];
+        const uint32_t r = rec[u];
+        if (MODE == kBwdRelax) {
           if (!ok) continue;
-          cst = fmaf(a, ch[u].x, cst);
-          cer = fmaf(a, a, cer);
-          if (v.xdense) v.xdense[(int64_t)row * v.ldx + j] = a;  // A(0) itself for the adjoint
-          continue;
-        }
-        if (ok) {
-          const float tm = conc_term(a, ch[u].x, ch[u].y);
-          cst += tm;
-          cer = fmaf(bt.sg, fabsf(tm), cer);
-        }
-        if (v.xpos) {  // x* as sign planes: one 64-bit word per wave
-          const uint64_t bp = __ballot(ok && a > 0.f), bn = __ballot(ok && a < 0.f);
-          const int w0 = 256 * u + wave * 64;
-          if (lane == 0 && w0 < pl.dout) {
-            v.xpos[(int64_t)row * bt.w64 + (w0 >> 6)] = bp;
-            v.xneg[(int64_t)row * bt.w64 + (w0 >> 6)] = bn;
+          if (v.acomp && (r & kKindMask) == kUnstable) v.acomp[ri.abase + (r & kCidxMask)] = a;
+          const float lam = relax_value(bt, v, ri, r, ch[u], x1[u], a, bsh[j], &cst);
+          e.out[(int64_t)row * e.ldo + j] = lam;
+          if (bt.sw) cer = fmaf(fabsf(lam), bt.sw[pc0 + j], cer);
+        } else if (MODE == kBwdConc) {
+          if (bt.l2x0) {  // l2 ball: A(0) x0 here, - eps ||A(0)||_2 in the final sum
+            if (!ok) continue;
+            cst = fmaf(a, ch[u].x, cst);
+            cer = fmaf(a, a, cer);
+            if (v.xdense) v.xdense[(int64_t)row * v.ldx + j] = a;  // A(0) itself for the adjoint
+            continue;
           }
+          if (ok) {
+            const float tm = conc_term(a, ch[u].x, ch[u].y);
+            cst += tm;
+            cer = fmaf(bt.sg, fabsf(tm), cer);
+          }
+          if (v.xpos) {  // x* as sign planes: one 64-bit word per wave
+            const uint64_t bp = __ballot(ok && a > 0.f), bn = __ballot(ok && a < 0.f);
+            const int w0 = kSdThreads * u + wave * 64;
+            if (lane == 0 && w0 < pl.dout) {
+              v.xpos[(int64_t)row * bt.w64 + (w0 >> 6)] = bp;
+              v.xneg[(int64_t)row * bt.w64 + (w0 >> 6)] = bn;
+            }
+          }
+        } else {
+          if (!ok) continue;
+          // l2 ball, first layer: W(1) x* + b(1) = (W(1) x0 + b(1)) - l2s (W(1) A(0))
+          const float zb = e.wx0 ? fmaf(-v.l2s[row], a, e.wx0[(int64_t)p * e.n + j]) : a + bsh[j];
+          if (v.sat) {  // the network itself at x*: every layer's output is kept
+            e.out[(int64_t)row * e.ldo + j] = true_relu(r, zb, v.sat + row);
+            continue;
+          }
+          const float zh = relax_fwd_value(bt, v, ri, r, ch[u], x1[u], x2[u], pc0 + j, zb, v.adam != 0,
+                                           make_float2(x3[u], x4[u]));
+          if (!last) e.out[(int64_t)row * e.ldo + j] = zh;
         }
-      } else {
-        if (!ok) continue;
-        // l2 ball, first layer: W(1) x* + b(1) = (W(1) x0 + b(1)) - l2s (W(1) A(0))
-        const float zb = e.wx0 ? fmaf(-v.l2s[row], a, e.wx0[(int64_t)p * e.n + j]) : a + bsh[j];
-        if (v.sat) {  // the network itself at x*: every layer's output is kept
-          e.out[(int64_t)row * e.ldo + j] = true_relu(r, zb, v.sat + row);
-          continue;
+      }
+      if (kBwd) {
+        cst = wave_sum(cst);
+        cer = wave_sum(cer);
+        if (lane == 0) {
+          red[par][wave][0] = cst;
+          red[par][wave][1] = cer;
         }
-        const float zh = relax_fwd_value(bt, v, ri, r, ch[u], x1[u], x2[u], pc0 + j, zb, v.adam != 0,
-                                         make_float2(x3[u], x4[u]));
-        if (!last) e.out[(int64_t)row * e.ldo + j] = zh;
+      }
+      if (nrow >= 0)
+        for (int t0 = kSdThreads * NI; t0 < pl.din; t0 += kSdThreads * NI) {
+          in_load<MODE, NI, kSdThreads>(zin, ldi, bt, v, nrow, t0, pl.din, s1, s2, w1, w2);
+          in_store<MODE, NI, kSdThreads>(zi, pl, bt, v, nrow, t0, pl.din, s1, s2, w1, w2);
+        }
+      // the next row's own variables (the unit's status records and chords
+      // stay); the next unit's are loaded at its start
+      if (row + 1 < r1) {
+        ri.k += 1;
+        ri.abase += uc;
+        sd_row_vars<MODE>(bt, v, e, ri, pl.dout, rec, x1, x2, x3, x4);
+      }
+      __syncthreads();
+      if (kBwd && tid == 0) {
+        float tot = 0.f, ter = 0.f;
+#pragma unroll
+        for (int w = 0; w < kSdWaves; ++w) {
+          tot += red[par][w][0];
+          ter += red[par][w][1];
+        }
+        e.part[(int64_t)e.slot0 * M + row] = tot;
+        // rounding-error bound, or the sum of A(0)^2 (l2 ball); with both
+        // modes on, the other array's slot gets 0
+        float* const p2 = MODE == kBwdConc && bt.l2x0 ? e.psq : (e.perr ? e.perr : e.psq);
+        float* const pz = e.perr && e.psq ? (p2 == e.perr ? e.psq : e.perr) : nullptr;
+        if (p2) p2[(int64_t)e.slot0 * M + row] = ter;
+        if (pz) pz[(int64_t)e.slot0 * M + row] = 0.f;
       }
     }
-    if (kBwd) {
-      cst = wave_sum(cst);
-      cer = wave_sum(cer);
-      if (lane == 0) {
-        red[par][wave][0] = cst;
-        red[par][wave][1] = cer;
-      }
-    }
-    const int done_row = row;
-    if (nrow >= 0)
-      for (int t0 = 256 * NI; t0 < pl.din; t0 += 256 * NI) {
-        in_load<MODE>(zin, ldi, bt, v, nrow, t0, pl.din, s1, s2, w1, w2);
-        in_store<MODE>(zi, pl, bt, v, nrow, t0, pl.din, s1, s2, w1, w2);
-      }
-    // the next row's operands: for a new unit its status records and chords
-    // first, then the row's own variables
-    if (nrow >= 0) {
-      if (nunit != unit) {
-        unit = nunit;
-        b = unit / upb;
-        r1 = b * m + min((unit - b * upb) * mu + mu, m);
-        p = bt.prop[b];
-        sd_load<MODE>(bt, e, b, p, pl.dout, rec, ch);
-      }
-      row = nrow;
-      ri = row_info(bt, row);
-      sd_row_vars<MODE>(bt, v, e, ri, pl.dout, rec, x1, x2, x3, x4);
-    }
-    __syncthreads();
-    if (kBwd && tid == 0) {
-      const float tot = (red[par][0][0] + red[par][1][0]) + (red[par][2][0] + red[par][3][0]);
-      e.part[(int64_t)e.slot0 * M + done_row] = tot;
-      // rounding-error bound, or the sum of A(0)^2 (l2 ball); with both modes
-      // on, the other array's slot gets 0
-      float* const p2 = MODE == kBwdConc && bt.l2x0 ? e.psq : (e.perr ? e.perr : e.psq);
-      float* const pz = e.perr && e.psq ? (p2 == e.perr ? e.psq : e.perr) : nullptr;
-      if (p2) p2[(int64_t)e.slot0 * M + done_row] = (red[par][0][1] + red[par][1][1]) + (red[par][2][1] + red[par][3][1]);
-      if (pz) pz[(int64_t)e.slot0 * M + done_row] = 0.f;
-    }
-    if (nrow < 0) break;
   }
 }
 
@@ -644,10 +714,10 @@ int dispatch_wg(const ConvArgs& a, hipStream_t st) {
 
 // (NJ, NI) pairs of the subdomain-major kernel instantiated per mode (the
 // layer shapes of the CIFAR-sized networks and small test networks)
-#define CVB_SD_BWD_RELAX(X) X(4, 4) X(4, 8) X(8, 4) X(8, 8)
-#define CVB_SD_BWD_CONC(X) X(4, 4) X(4, 8) X(12, 4) X(12, 8)
-#define CVB_SD_FWD_X(X) X(4, 4) X(8, 4)
-#define CVB_SD_FWD(X) X(4, 4) X(4, 8) X(8, 4) X(8, 8)
+#define CVB_SD_BWD_RELAX(X) X(2, 2) X(2, 4) X(4, 2) X(4, 4) X(8, 4)
+#define CVB_SD_BWD_CONC(X) X(2, 2) X(2, 4) X(6, 4) X(6, 8)
+#define CVB_SD_FWD_X(X) X(2, 2) X(4, 4) X(8, 4)
+#define CVB_SD_FWD(X) X(2, 2) X(2, 4) X(4, 4) X(4, 8)
 
 template <int MODE, int NT, bool WG>
 const void* sd_kernel(int nj, int ni) {
@@ -690,7 +760,7 @@ template <int MODE, int NT, bool WG>
 int launch_sd(const ConvArgs& a, hipStream_t st) {
   const int mu = sd_unit_rows(a.bt.m);
   const int n_units = (a.M / a.bt.m) * ((a.bt.m + mu - 1) / mu);
-  const dim3 grid(std::min(n_units, a.pl.grid_sd > 0 ? a.pl.grid_sd : 512)), block(256);
+  const dim3 grid(std::min(n_units, a.pl.grid_sd > 0 ? a.pl.grid_sd : 256)), block(kSdThreads);
 #define CVB_SDL(J, I)                                                                                            \
   if (a.pl.nj == J && a.pl.ni == I) {                                                                           \
     launch_k(conv_sd<MODE, NT, WG, J, I>, grid, block, a.pl.smem_sd, st, a.in, a.ldi, a.pl, a.M, a.last, a.bt, a.v, \
@@ -762,10 +832,10 @@ void conv_plan_sd(int mode, ConvPlan& pl) {
   // (the input prefetch depth ni need not cover the row: the rest is staged
   // after the epilogue)
   int nj = 0, ni = 0;
-  for (int c : {4, 8, 12, 16}) {
-    if (nj || pl.dout > 256 * c) continue;
-    for (int i : {4, 8, 12, 16})
-      if (sd_kernel_mode(mode, pl.nt, pl.wg != 0, c, i) && (!ni || pl.din > 256 * ni)) {
+  for (int c : {2, 4, 6, 8}) {
+    if (nj || pl.dout > kSdThreads * c) continue;
+    for (int i : {2, 4, 6, 8})
+      if (sd_kernel_mode(mode, pl.nt, pl.wg != 0, c, i) && (!ni || pl.din > kSdThreads * ni)) {
         nj = c;
         ni = i;
       }
@@ -774,10 +844,12 @@ void conv_plan_sd(int mode, ConvPlan& pl) {
   pl.nj = nj;
   pl.ni = ni;
   const void* k = sd_kernel_mode(mode, pl.nt, pl.wg != 0, nj, ni);
-  pl.smem_sd = pl.smem + (mode == kBwdConc ? 0 : pl.dout * (int)sizeof(float));
+  // the plan's LDS, the spare output slot (padded), the scatter table and the bias
+  pl.smem_sd = pl.smem + 32 + (pl.mpad >> 4) * pl.nt * 64 * (int)sizeof(int4) +
+               (mode == kBwdConc ? 0 : pl.dout * (int)sizeof(float));
   int dev = 0, cus = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, 256, pl.smem_sd) != hipSuccess) {
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, kSdThreads, pl.smem_sd) != hipSuccess) {
     (void)hipGetLastError();
     return;
   }
