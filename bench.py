@@ -459,7 +459,7 @@ def main():
         lb_p = pb_s.eval(a_s0, b_s0)
         rel_margin = ((lb_p - lb_s) / lb_p.abs().clamp(min=1.0)).max().item()
         ctx["sound_mode"] = {"value": round(pb_s.B / (ms_sound / 1e3), 1), "unit": "subdomain bounds/s",
-                             "ms_per_step": round(ms_sound, 4), "root_bounds": "sound (outward by the margin)",
+                             "ms_per_step": round(ms_sound, 4), "root_bounds": "sound (float64 with its rounding margin, rounded outward)",
                              "max_rel_margin": rel_margin, "min_margin": (lb_p - lb_s).min().item()}
         pb_s.close()
 

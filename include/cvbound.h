@@ -81,10 +81,10 @@ int cv_bound_root_bounds(const cv_layer *layers, int32_t n_layers, int32_t n_pro
                          const float *x_lo, const float *x_hi,
                          float *l_out, float *u_out, void *stream);
 
-/* The same bounds made sound: each is moved outward by a rigorous bound on
- * its float32 rounding error (the margin of cv_bound_set_sound, with each
- * layer's bounds built on the previous layers' sound bounds), so l_out and
- * u_out enclose every pre-activation the network takes on the box.  Same
+/* The same bounds made sound: each is evaluated as in sound mode (float64
+ * with a rigorous rounding margin, rounded outward to float; each layer's
+ * bounds built on the previous layers' sound bounds), so l_out and u_out
+ * enclose every pre-activation the network takes on the box.  Same
  * arguments and behaviour as cv_bound_root_bounds. */
 int cv_bound_root_bounds_sound(const cv_layer *layers, int32_t n_layers, int32_t n_props,
                                const float *x_lo, const float *x_hi,
@@ -111,7 +111,10 @@ int cv_bound_root_bounds_opt(const cv_layer *layers, int32_t n_layers, int32_t n
  *     of Sec. 2.1, possibly clipped).
  *   m, C: host [n_props][m][d_L] specification rows, merged into the last
  *     layer (Sec. 2.1).
- *   l, u: host [n_props][sum_{i<L} d_i] intermediate bounds, layer-major.
+ *   l, u: host [n_props][sum_{i<L} d_i] intermediate bounds, layer-major;
+ *     both NULL: computed here by per-layer CROWN on the GPU, exactly as
+ *     cv_bound_root_bounds (float32, not outward-rounded; for sound mode
+ *     pass cv_bound_root_bounds_sound's bounds instead).
  *   n_dom, dom_prop: host [n_dom] property of each subdomain.
  *   split_ptr: host [n_dom+1] CSR offsets; split_layer (1..L-1),
  *     split_neuron, split_side (+1: z >= 0, i.e. Z+, S = -1; -1: z < 0,
@@ -286,21 +289,26 @@ int cv_bound_set_conv_variant(cv_bound *h, int32_t variant);
 int cv_bound_conv_variant(const cv_bound *h, int32_t layer, int32_t dir);
 
 /* Sound mode (off by default): every bound this handle reports (eval, grad,
- * upper, optimize) is lowered by a rigorous bound on its float32 rounding
- * error, so that it lies below the value the same relaxation (same alpha,
- * beta and sign decisions) gives in exact arithmetic, hence below the true
- * minimum (Theorem 3.1's bound is sound for any alpha in [0,1], beta >= 0).
- * The margin per row is sum over the neurons of the row's Lambda weighted by
- * per-neuron constants computed once in double from |W|, the root bounds and
- * the box (matrix-product error g(d_i) sum |Lambda||W| max|input|, the
- * rounding of Lambda, of the float32 chord and of every addition into the
- * constant and the concretisation; g(n) = n u'/(1 - n u'), u' = 2^-23), plus
- * the error of the merged specification C W(L); it is typically 1e-6 of the
- * bound's magnitude.  Gradients are those of the bound without the margin.
- * The fused dense chain is not used while sound mode is on (the per-layer
- * kernels carry the margin).  on: 0 or 1 (else CV_EINVAL).  Switching on
- * computes the constants for the current input sets, boxes or the balls of
- * cv_bound_set_input_l2 (host work, synchronous on `stream`). */
+ * upper, optimize) is rigorous: it lies below the value the same relaxation
+ * (same alpha, beta and sign decisions) gives in exact arithmetic, hence
+ * below the true minimum (Theorem 3.1's bound is sound for any alpha in
+ * [0,1], beta >= 0).  The bound is evaluated in float64 -- the specification
+ * merged into the last layer, every back-substitution product, the
+ * relaxation (chords formed in double from the root bounds), the constants
+ * and the concretisation -- and lowered by a rigorous bound on its float64
+ * rounding (per-row sum of |Lambda_k| times per-neuron weights computed once
+ * on the host: g(d_i) sum |W| max|input|, the rounding of Lambda and of the
+ * chord, every addition into the constant and the concretisation, the
+ * merged specification; g(n) = n u/(1 - n u), u = 2^-52), then rounded down
+ * to float: typically within one float ulp of the exact bound.
+ * cv_bound_optimize runs its iterations with the plain float32 kernels,
+ * records each row's best iterate (its float32 bound and its variables),
+ * and reports lb_best = the larger of the float64 sound bounds of that
+ * iterate and of the final one, lb_last = the final iterate's.  Gradients
+ * are those of the bound itself.  on: 0 or 1 (else CV_EINVAL).  Switching
+ * on computes the weights for the current input sets, boxes or the balls of
+ * cv_bound_set_input_l2 (host work, synchronous on `stream`) and allocates
+ * the float64 buffers; CV_ESHAPE if a ReLU layer is wider than 8192. */
 int cv_bound_set_sound(cv_bound *h, int32_t on, void *stream);
 
 /* l2-ball input sets (Sec. 2.1 allows any l_p ball; Theorem 3.1's last step

@@ -231,20 +231,24 @@ class BoundProblem:
 
 
 class BetaCrownBound(torch.autograd.Function):
-    """lb = g(alpha, beta) per row [B, m]; backward returns the grad_lb-weighted
-    d lb / d(alpha, beta) (each variable belongs to exactly one row)."""
+    """lb = g(alpha, beta) per row [B, m].  forward is cv_bound_eval (the bound
+    alone); backward is cv_bound_grad at the saved variables, scaled by the
+    incoming per-row gradient (each variable belongs to exactly one row), so a
+    forward with no backward pays for the bound only."""
 
     @staticmethod
     def forward(ctx, alpha, beta, problem):
-        lb, ga, gb = problem.grad(alpha.detach().contiguous(), beta.detach().contiguous())
+        a, b = alpha.detach().contiguous(), beta.detach().contiguous()
+        lb = problem.eval(a, b)
         ctx.problem = problem
-        ctx.save_for_backward(ga, gb)
+        ctx.save_for_backward(a, b)
         return lb.clone()
 
     @staticmethod
     def backward(ctx, grad_lb):
-        ga, gb = ctx.saved_tensors
+        a, b = ctx.saved_tensors
         pb = ctx.problem
+        _, ga, gb = pb.grad(a, b)
         g = grad_lb.reshape(-1).contiguous()
         ra, rb = pb.row_maps()
         return ga * g[ra], gb * g[rb], None

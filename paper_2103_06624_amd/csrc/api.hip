@@ -178,6 +178,18 @@ struct cv_bound {
   float* perr = nullptr;  // [n_slots, R]
   float* err0 = nullptr;  // [P, m]
   float sound_g = 0.f, sound_scale = 1.f;
+  // the float64 evaluation of sound mode: root bounds and specification kept
+  // on the device, margin weights of the float64 analysis, row buffers
+  float *dl = nullptr, *du = nullptr, *dC = nullptr;
+  float* sw64 = nullptr;    // [P, nd]
+  float* err064 = nullptr;  // [P, m]
+  double sg64 = 0.0, scale64 = 1.0, ball64 = 0.0;
+  double* act64[2] = {nullptr, nullptr};
+  double *part64 = nullptr, *perr64 = nullptr, *psq64 = nullptr;  // [L, R]
+  // the optimiser in sound mode: each row's best float32 bound so far, the
+  // variables of that iterate, and which rows the last evaluation improved
+  float *gbest = nullptr, *abest = nullptr, *bbest = nullptr;
+  int* improved = nullptr;
   int* ulist = nullptr;
   int64_t* uoff = nullptr;
   // gradient / optimisation buffers (allocated on first use)
@@ -774,6 +786,8 @@ int build(cv_bound* h, const cv_layer* layers, int n_layers, int P, const float*
       (rc = M.alloc(&d_status, (size_t)B * nd)) || (rc = M.upload(&h->ulist, ulist.data(), ulist.size(), s)) ||
       (rc = M.upload(&h->uoff, uoff.data(), P + 1, s)))
     return rc;
+  h->dl = d_l;
+  h->du = d_u;
   launch_prep_chord(d_l, d_u, d_chord, d_adef, (int64_t)P * nd, s);
   launch_status_fill(d_status, d_kind, d_prop, B, nd, s);
   launch_status_split(d_status, d_split_dom, d_split_col, d_side, h->nnz, nd, s);
@@ -789,6 +803,7 @@ int build(cv_bound* h, const cv_layer* layers, int n_layers, int P, const float*
   bt.aoff = d_aoff;
   bt.rbase = d_rbase;
   bt.ucount = d_ucount;
+  bt.sptr = d_sptr;
   bt.status = d_status;
   bt.cidx = d_cidx;
   bt.chord = d_chord;
@@ -815,6 +830,7 @@ int build(cv_bound* h, const cv_layer* layers, int n_layers, int P, const float*
     if ((rc = M.upload(&dC, spec.C, (size_t)P * m * last.dout, s)) ||
         (rc = M.alloc(&h->CW, (size_t)P * m * h->ldcw)) || (rc = M.alloc(&h->Cb, (size_t)P * m)))
       return rc;
+    h->dC = dC;
     launch_spec_merge(dC, last.W, last.ld_in, last.bias, P, m, last.dout, dprev, h->CW, h->ldcw, h->Cb, s);
     h->cw_pstride = (int64_t)m * h->ldcw;
     h->cb_pstride = m;
@@ -985,10 +1001,25 @@ void affine_host(const cv_layer& ly, const float* x, std::vector<double>& out) {
 // Over l2 balls (l2x0 [P, d0], l2eps [P] set) an input coordinate is bounded
 // by |x0_j| + eps_p instead of the box, and the per-property ||x0||_2 and the
 // norm's rounding factor are prepared for the final sum.
+// One rounding-error analysis (the terms above) for unit roundoff up (2^-23
+// for the float32 kernels, 2^-52 for the float64 evaluation) and the longest
+// addition chain of the kernels' sums.
+struct SoundWeights {
+  std::vector<float> sw, e0;
+  double G = 0, gchain = 0;
+};
+
+void sound_weights(const cv_bound* h, const cv_layer* layers, const float* x_lo, const float* x_hi, const float* l,
+                   const float* u, const float* C, bool identity, const float* l2x0, const float* l2eps, double up,
+                   int chain, SoundWeights& out);
+
 int prepare_sound(cv_bound* h, const cv_layer* layers, const float* x_lo, const float* x_hi, const float* l,
                   const float* u, const float* C, bool identity, hipStream_t s, const float* l2x0 = nullptr,
                   const float* l2eps = nullptr) {
-  const int L = h->L, P = h->P, m = h->m, nd = h->nd, d0 = h->d0;
+  const int L = h->L, P = h->P, nd = h->nd, d0 = h->d0;
+  // the float64 evaluation keeps one row of Lambda in a workgroup's 64 KB of LDS
+  for (int i = 1; i < L; ++i)
+    if (h->dims[i] > 8192) return fail(CV_ESHAPE, "sound mode: layer %d is wider than 8192 neurons", i);
   const double up = std::ldexp(1.0, -23);
   auto gam = [&](double n) { return n * up / (1.0 - n * up); };
   // longest addition chain: final sum over slots (and its four-way merge),
@@ -1004,7 +1035,68 @@ int prepare_sound(cv_bound* h, const cv_layer* layers, const float* x_lo, const 
       chain = std::max(chain, 2 * ly.in_c * ((ly.in_h * ly.in_w + 255) / 256));
   }
   chain += h->n_slots + 64;
+  SoundWeights w32, w64;
+  sound_weights(h, layers, x_lo, x_hi, l, u, C, identity, l2x0, l2eps, up, chain, w32);
+  // float64 kernels: per-thread chains over a layer's outputs (at most the
+  // widest layer), block trees (8 levels), the final sum over L slots
+  int chain64 = 64 + L;
+  for (int i = 0; i <= L; ++i) chain64 = std::max(chain64, h->dims[i] + 64 + L);
+  const double up64 = std::ldexp(1.0, -52);
+  sound_weights(h, layers, x_lo, x_hi, l, u, C, identity, l2x0, l2eps, up64, chain64, w64);
+  int rc;
+  if (!h->sw) {
+    if ((rc = h->mem.alloc(&h->sw, w32.sw.size())) || (rc = h->mem.alloc(&h->err0, w32.e0.size())) ||
+        (rc = h->mem.alloc(&h->perr, (size_t)std::max(1, h->R) * h->n_slots)) ||
+        (rc = h->mem.alloc(&h->sw64, w64.sw.size())) || (rc = h->mem.alloc(&h->err064, w64.e0.size())) ||
+        (rc = h->mem.alloc(&h->act64[0], (size_t)std::max(1, h->R) * h->ldact)) ||
+        (rc = h->mem.alloc(&h->act64[1], (size_t)std::max(1, h->R) * h->ldact)) ||
+        (rc = h->mem.alloc(&h->part64, (size_t)std::max(1, h->R) * L)) ||
+        (rc = h->mem.alloc(&h->perr64, (size_t)std::max(1, h->R) * L)) ||
+        (rc = h->mem.alloc(&h->psq64, (size_t)std::max(1, h->R) * L)) ||
+        (rc = h->mem.alloc(&h->gbest, (size_t)std::max(1, h->R))) ||
+        (rc = h->mem.alloc(&h->improved, (size_t)std::max(1, h->R))) ||
+        (rc = h->mem.alloc(&h->abest, (size_t)std::max<int64_t>(1, h->n_alpha))) ||
+        (rc = h->mem.alloc(&h->bbest, (size_t)std::max<int64_t>(1, h->nnz * h->m))))
+      return rc;
+  }
+  HIPCHK(hipMemcpyAsync(h->sw, w32.sw.data(), w32.sw.size() * sizeof(float), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(h->err0, w32.e0.data(), w32.e0.size() * sizeof(float), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(h->sw64, w64.sw.data(), w64.sw.size() * sizeof(float), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(h->err064, w64.e0.data(), w64.e0.size() * sizeof(float), hipMemcpyHostToDevice, s));
+  const double G = w32.G;
+  h->sg64 = w64.G;
+  h->scale64 = 1.0 + 2.0 * w64.gchain;
+  // ||A(0)||_2: d0 squares summed, a square root; A(0) x0: d0 products summed
+  h->ball64 = (d0 + 64) * up64 / (1.0 - (d0 + 64) * up64) + 4.0 * up64;
+  (void)nd;
+  (void)P;
+  if (l2x0) {
+    std::vector<float> x0n(P);
+    for (int p = 0; p < P; ++p) {
+      double t = 0.0;
+      for (int j = 0; j < d0; ++j) t += (double)l2x0[(size_t)p * d0 + j] * l2x0[(size_t)p * d0 + j];
+      x0n[p] = round_up_f(std::sqrt(t) * (1.0 + 1e-12));
+    }
+    if (!h->x0n && (rc = h->mem.alloc(&h->x0n, P))) return rc;
+    HIPCHK(hipMemcpyAsync(h->x0n, x0n.data(), sizeof(float) * P, hipMemcpyHostToDevice, s));
+    // sum of squares within gam(chain) relative, the square root and the
+    // product each within an ulp
+    h->l2fac = round_up_f((1.0 + gam(chain)) * (1.0 + 4.0 * up));
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  h->sound_g = round_up_f(G);
+  h->sound_scale = round_up_f(1.0 + 2.0 * gam(chain));
+  return CV_OK;
+}
+
+void sound_weights(const cv_bound* h, const cv_layer* layers, const float* x_lo, const float* x_hi, const float* l,
+                   const float* u, const float* C, bool identity, const float* l2x0, const float* l2eps, double up,
+                   int chain, SoundWeights& out) {
+  const int L = h->L, P = h->P, m = h->m, nd = h->nd, d0 = h->d0;
+  auto gam = [&](double n) { return n * up / (1.0 - n * up); };
   const double G = gam(chain) + up;
+  out.G = G;
+  out.gchain = gam(chain);
   std::vector<float> sw((size_t)P * std::max(nd, 1), 0.f), e0((size_t)P * m, 0.f);
   for (int p = 0; p < P; ++p) {
     std::vector<double> hm(d0);
@@ -1055,31 +1147,8 @@ int prepare_sound(cv_bound* h, const cv_layer* layers, const float* x_lo, const 
       }
     }
   }
-  int rc;
-  if (!h->sw) {
-    if ((rc = h->mem.alloc(&h->sw, sw.size())) || (rc = h->mem.alloc(&h->err0, e0.size())) ||
-        (rc = h->mem.alloc(&h->perr, (size_t)std::max(1, h->R) * h->n_slots)))
-      return rc;
-  }
-  HIPCHK(hipMemcpyAsync(h->sw, sw.data(), sw.size() * sizeof(float), hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(h->err0, e0.data(), e0.size() * sizeof(float), hipMemcpyHostToDevice, s));
-  if (l2x0) {
-    std::vector<float> x0n(P);
-    for (int p = 0; p < P; ++p) {
-      double t = 0.0;
-      for (int j = 0; j < d0; ++j) t += (double)l2x0[(size_t)p * d0 + j] * l2x0[(size_t)p * d0 + j];
-      x0n[p] = round_up_f(std::sqrt(t) * (1.0 + 1e-12));
-    }
-    if (!h->x0n && (rc = h->mem.alloc(&h->x0n, P))) return rc;
-    HIPCHK(hipMemcpyAsync(h->x0n, x0n.data(), sizeof(float) * P, hipMemcpyHostToDevice, s));
-    // sum of squares within gam(chain) relative, the square root and the
-    // product each within an ulp
-    h->l2fac = round_up_f((1.0 + gam(chain)) * (1.0 + 4.0 * up));
-  }
-  HIPCHK(hipStreamSynchronize(s));
-  h->sound_g = round_up_f(G);
-  h->sound_scale = round_up_f(1.0 + 2.0 * gam(chain));
-  return CV_OK;
+  out.sw.swap(sw);
+  out.e0.swap(e0);
 }
 
 // ---------------------------------------------------------------------------
@@ -1137,7 +1206,7 @@ double chain_flops(const cv_bound* h) {
 // skip_top: the top layer was relaxed by the previous adjoint pass (fused
 // into its last GEMM): start from its Lambda(L-1) and partial slots.
 int enqueue_bwd(cv_bound* h, const float* alpha, const float* beta, bool grad, float* lb, float* best, int first,
-                hipStream_t s, bool skip_top = false) {
+                hipStream_t s, bool skip_top = false, int* improved = nullptr) {
   const int L = h->L;
   Vars v{};
   v.alpha = alpha;
@@ -1156,7 +1225,7 @@ int enqueue_bwd(cv_bound* h, const float* alpha, const float* beta, bool grad, f
   if (skip_top) {
     cur = h->ftop_buf;
     slot = h->ftop_slots;
-  } else if (h->chain_b && !h->sound && !h->l2) {
+  } else if (h->chain_b && !h->sound && !h->l2 && !improved) {
     const int lo = h->chain_lo;
     ChainArgs ca{};
     ca.nl = L - lo;
@@ -1263,8 +1332,88 @@ int enqueue_bwd(cv_bound* h, const float* alpha, const float* beta, bool grad, f
   if (pf) pf->begin("finalize", 0, (double)h->R * (slot + 2) * 4.0);
   const L2Final l2f{h->bt.prop, h->m, h->l2eps, h->l2s, h->x0n, h->sound_g, h->l2fac};
   launch_finalize(h->part, h->sound ? h->perr : nullptr, h->sound_scale, h->l2 ? h->psq : nullptr, l2f, h->n_slots,
-                  slot, h->R, lb, best, first, s);
+                  slot, h->R, lb, best, first, s, improved);
   if (pf) pf->end();
+  HIPCHK(hipGetLastError());
+  return CV_OK;
+}
+
+// Sound mode's evaluation in float64 (sound64.hip): every back-substitution
+// step, relaxation and concretisation in double with its rigorous float64
+// margin; lb = the bound minus the margin rounded down to float (best: the
+// running maximum, first = 1 starts it).  Needs the buffers of set_sound.
+int enqueue_bwd64(cv_bound* h, const float* alpha, const float* beta, float* lb, float* best, int first,
+                  hipStream_t s) {
+  const int L = h->L;
+  if (h->R == 0) return CV_OK;
+  if (!h->sw64 || !h->act64[0]) return fail(CV_EINVAL, "sound mode is off");
+  Pass64 q{};
+  q.bt = h->bt;
+  q.l = h->dl;
+  q.u = h->du;
+  q.alpha = alpha;
+  q.beta = beta;
+  q.sw = h->sw64;
+  q.sg = h->sg64;
+  q.part = h->part64;
+  q.perr = h->perr64;
+  q.psq = h->l2 ? h->psq64 : nullptr;
+  Top64 t{};
+  const DevLayer& last = h->layers[L - 1];
+  if (h->dC) {
+    t.C = h->dC;
+    t.dL = h->dims[L];
+    t.WL = last.W;
+    t.ldw = last.ld_in;
+    t.bL = last.bias;
+  } else {
+    t.CW = h->CW;
+    t.cw_pstride = h->cw_pstride;
+    t.ldcw = h->ldcw;
+    t.Cb = h->Cb;
+    t.cb_pstride = h->cb_pstride;
+  }
+  t.n = h->dims[L - 1];
+  t.conc = L == 1;
+  t.err0 = h->err064;
+  if (L >= 2) {
+    t.layer_off = h->offs[L - 2];
+    t.bias = h->layers[L - 2].bias;
+    t.out = h->act64[0];
+    t.ldo = h->ldact;
+  }
+  launch_top64(q, t, s);
+  int cur = 0;
+  for (int i = L - 1; i >= 1; --i) {
+    const DevLayer& ly = h->layers[i - 1];
+    Lay64 y{};
+    y.in = h->act64[cur];
+    y.ldi = h->ldact;
+    y.K = h->dims[i];
+    y.N = h->dims[i - 1];
+    y.W = ly.W;
+    y.ldw = ly.ld_in;
+    y.conc = i == 1;
+    y.slot = L - i;
+    if (i >= 2) {
+      y.layer_off = h->offs[i - 2];
+      y.bias = h->layers[i - 2].bias;
+      y.out = h->act64[cur ^ 1];
+      y.ldo = h->ldact;
+    }
+    if (ly.type == CV_LAYER_DENSE) launch_dense64(q, y, s);
+    else launch_conv64(q, y, ly.g, s);
+    cur ^= 1;
+  }
+  Fin64 f{};
+  f.n_used = L;
+  f.scale = h->scale64;
+  f.ball = h->ball64;
+  f.x0n = h->x0n;
+  f.lb = lb;
+  f.best = best;
+  f.first = first;
+  launch_finalize64(q, f, s);
   HIPCHK(hipGetLastError());
   return CV_OK;
 }
@@ -1417,12 +1566,34 @@ int enqueue_opt(cv_bound* h, int iters, float lr_a, float lr_b, float decay, flo
     ap.vb = h->adam + 2 * h->n_alpha + nb;
   }
   int rc;
+  // sound mode: the iterations run the plain float32 kernels, and each row's
+  // best iterate is recorded (its float32 bound and its variables); the
+  // reported bounds are then the float64 evaluations of that iterate and of
+  // the final one (below)
+  const bool snd = h->sound;
+  const float* sw_saved = h->bt.sw;
+  if (snd) {
+    h->sound = false;
+    h->bt.sw = nullptr;
+  }
+  float* const track = snd ? h->gbest : lb_best;
+  int* const impr = snd ? h->improved : nullptr;
   // the top layer's relaxation rides on the last adjoint GEMM from the
   // second iteration on (per-layer kernels, dense top layer, no sound margin)
   const int L = h->L;
   const bool fuse = L >= 2 && h->layers[L - 2].type == CV_LAYER_DENSE && !h->chain_b && !h->chain_f && !h->sound;
+  auto restore = [&]() {
+    if (snd) {
+      h->sound = true;
+      h->bt.sw = sw_saved;
+    }
+  };
   for (int t = 0; t < iters; ++t) {
-    if ((rc = enqueue_bwd(h, alpha, beta, true, nullptr, lb_best, t == 0, s, fuse && t > 0))) return rc;
+    if ((rc = enqueue_bwd(h, alpha, beta, true, nullptr, track, t == 0, s, fuse && t > 0, impr))) {
+      restore();
+      return rc;
+    }
+    if (snd) launch_keep_best(alpha, beta, h->abest, h->bbest, impr, h->bt, s);
     const int tt = step0 + t;
     AdamStep ad;
     ad.bc1 = (float)(1.0 - std::pow(0.9, tt + 1));
@@ -1434,9 +1605,20 @@ int enqueue_opt(cv_bound* h, int iters, float lr_a, float lr_b, float decay, flo
     ad.va = ap.va;
     ad.mb = ap.mb;
     ad.vb = ap.vb;
-    if ((rc = enqueue_fwd(h, alpha, beta, nullptr, nullptr, &ad, s, fuse))) return rc;
+    if ((rc = enqueue_fwd(h, alpha, beta, nullptr, nullptr, &ad, s, fuse))) {
+      restore();
+      return rc;
+    }
   }
-  if ((rc = enqueue_bwd(h, alpha, beta, false, lb_last, lb_best, iters == 0, s, fuse && iters > 0))) return rc;
+  rc = enqueue_bwd(h, alpha, beta, false, lb_last, track, iters == 0, s, fuse && iters > 0, impr);
+  if (!rc && snd) launch_keep_best(alpha, beta, h->abest, h->bbest, impr, h->bt, s);
+  restore();
+  if (rc) return rc;
+  // sound mode: the best and the final iterates in float64 (each with its
+  // rigorous float64 margin, rounded down): lb_best = the larger of the two
+  if (snd && ((rc = enqueue_bwd64(h, h->abest, h->bbest, nullptr, lb_best, 1, s)) ||
+              (rc = enqueue_bwd64(h, alpha, beta, lb_last, lb_best, 0, s))))
+    return rc;
   HIPCHK(hipGetLastError());
   return CV_OK;
 }
@@ -1761,6 +1943,9 @@ int grad_noalloc(cv_bound* h, const float* alpha, const float* beta, float* lb, 
   }
   int rc = enqueue_bwd(h, alpha, beta, true, lb, nullptr, 0, s);
   if (!rc) rc = enqueue_fwd(h, alpha, beta, g_alpha, g_beta, nullptr, s);
+  // sound mode: the float64 bound (its buffers were allocated when sound
+  // mode was switched on)
+  if (!rc && h->sound) rc = enqueue_bwd64(h, alpha, beta, lb, nullptr, 0, s);
   h->act[0] = sv.act0;
   h->act[1] = sv.act1;
   h->part = sv.part;
@@ -1834,7 +2019,8 @@ int root_bounds(const cv_layer* layers, int32_t n_layers, int32_t n_props, const
       launch_alpha_default(alpha, hb.ulist, hb.uoff, hb.bt, s);
       if ((rc = enqueue_opt(&hb, iters, lr_alpha, 0.f, decay, alpha, nullptr, AdamPtrs{}, 0, dlb, dlast, s)))
         return rc;
-    } else if ((rc = enqueue_bwd(&hb, nullptr, nullptr, false, dlb, nullptr, 0, s))) {
+    } else if ((rc = sound ? enqueue_bwd64(&hb, nullptr, nullptr, dlb, nullptr, 0, s)
+                           : enqueue_bwd(&hb, nullptr, nullptr, false, dlb, nullptr, 0, s))) {
       return rc;
     }
     std::vector<float> lb(hb.R);
@@ -1870,6 +2056,24 @@ int cv_bound_init(cv_bound** out, const cv_layer* layers, int32_t n_layers, int3
   if (!C) return fail(CV_EINVAL, "null specification");
   if (split_ptr && n_dom > 0 && split_ptr[n_dom] > 0 && (!split_layer || !split_neuron || !split_side))
     return fail(CV_EINVAL, "null split arrays");
+  // no intermediate bounds given: per-layer CROWN on the GPU (as
+  // cv_bound_root_bounds), computed once here for every property
+  std::vector<float> lroot, uroot;
+  if (!l || !u) {
+    std::vector<int> dims;
+    int rc0 = check_layers(layers, n_layers, dims);
+    if (rc0) return rc0;
+    if (n_props <= 0 || !x_lo || !x_hi) return fail(CV_EINVAL, "bad arguments");
+    int nd = 0;
+    for (int i = 1; i < n_layers; ++i) nd += dims[i];
+    lroot.assign((size_t)n_props * std::max(nd, 1), 0.f);
+    uroot.assign((size_t)n_props * std::max(nd, 1), 0.f);
+    if (nd > 0 && (rc0 = root_bounds(layers, n_layers, n_props, x_lo, x_hi, lroot.data(), uroot.data(), false,
+                                     stream)))
+      return rc0;
+    l = lroot.data();
+    u = uroot.data();
+  }
   std::unique_ptr<cv_bound> h(new cv_bound());
   Spec sp;
   sp.C = C;
@@ -1960,6 +2164,7 @@ int cv_bound_eval(cv_bound* h, const float* alpha, const float* beta, float* lb,
   if (!h || (!lb && h->R > 0) || (!alpha && h->n_alpha > 0) || (!beta && h->nnz > 0))
     return fail(CV_EINVAL, "null argument");
   hipStream_t s = (hipStream_t)stream;
+  if (h->sound) return enqueue_bwd64(h, alpha, beta, lb, nullptr, 0, s);
   return enqueue_bwd(h, alpha, beta, false, lb, nullptr, 0, s);
 }
 
@@ -1972,7 +2177,8 @@ int cv_bound_grad(cv_bound* h, const float* alpha, const float* beta, float* lb,
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
   if ((rc = enqueue_bwd(h, alpha, beta, true, lb, nullptr, 0, s))) return rc;
-  return enqueue_fwd(h, alpha, beta, g_alpha, g_beta, nullptr, s);
+  if ((rc = enqueue_fwd(h, alpha, beta, g_alpha, g_beta, nullptr, s))) return rc;
+  return h->sound ? enqueue_bwd64(h, alpha, beta, lb, nullptr, 0, s) : CV_OK;
 }
 
 int cv_bound_grad_noalloc(cv_bound* h, const float* alpha, const float* beta, float* lb, float* g_alpha,
@@ -2003,14 +2209,15 @@ int cv_bound_upper(cv_bound* h, const float* alpha, const float* beta, float* lb
     h->sound = snd;
     h->bt = saved;
     if (rc) return rc;
-    if (lb && snd && (rc = enqueue_bwd(h, alpha, beta, false, lb, nullptr, 0, s))) return rc;
+    if (lb && snd && (rc = enqueue_bwd64(h, alpha, beta, lb, nullptr, 0, s))) return rc;
     if (lb && !snd) HIPCHK(hipMemcpyAsync(lb, ub, sizeof(float) * h->R, hipMemcpyDeviceToDevice, s));
     launch_fill_i32(sat, 1, h->R, s);
     HIPCHK(hipGetLastError());
     return CV_OK;
   }
   if ((rc = enqueue_bwd(h, alpha, beta, true, lb, nullptr, 0, s))) return rc;
-  return enqueue_true_fwd(h, ub, sat, s);
+  if ((rc = enqueue_true_fwd(h, ub, sat, s))) return rc;
+  return h->sound && lb ? enqueue_bwd64(h, alpha, beta, lb, nullptr, 0, s) : CV_OK;
 }
 
 int cv_bound_optimize(cv_bound* h, int32_t iters, float lr_alpha, float lr_beta, float lr_decay, float* alpha,

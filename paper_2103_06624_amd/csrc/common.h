@@ -35,6 +35,7 @@ struct Batch {
   const int64_t* aoff;      // [B] first alpha entry of each subdomain
   const int64_t* rbase;     // [n_rows] first alpha entry of each row
   const int* ucount;        // [P] root-unstable neurons per property
+  const int64_t* sptr;      // [B+1] CSR offsets of each subdomain's splits
   const uint32_t* status;   // [B, nd] status records
   const int* cidx;          // [P, nd] index in the property's unstable list or -1
   const float2* chord;      // [P, nd] (u/(u-l), -u l/(u-l)) for unstable neurons

@@ -783,9 +783,14 @@ int launch_sd(const ConvArgs& a, hipStream_t st) {
 template <int MODE>
 int dispatch(const ConvArgs& a, hipStream_t st) {
   if (a.M <= 0) return 0;
+  // the subdomain-major kernel where an instantiation of this mode holds the
+  // plan (a plan built for one mode may be launched in another: over an l2
+  // ball the first layer's adjoint reads A(0) rows instead of sign planes),
+  // else the row-major one
   if (a.pl.sd && a.pl.nj > 0 && (a.pl.nt == 1 || a.pl.nt == 2)) {
-    if (a.pl.nt == 1) return a.pl.wg ? launch_sd<MODE, 1, true>(a, st) : launch_sd<MODE, 1, false>(a, st);
-    return a.pl.wg ? launch_sd<MODE, 2, true>(a, st) : launch_sd<MODE, 2, false>(a, st);
+    const int r = a.pl.nt == 1 ? (a.pl.wg ? launch_sd<MODE, 1, true>(a, st) : launch_sd<MODE, 1, false>(a, st))
+                               : (a.pl.wg ? launch_sd<MODE, 2, true>(a, st) : launch_sd<MODE, 2, false>(a, st));
+    if (r == 0) return 0;
   }
   return a.pl.wg ? dispatch_wg<MODE, true>(a, st) : dispatch_wg<MODE, false>(a, st);
 }

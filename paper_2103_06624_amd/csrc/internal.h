@@ -177,6 +177,67 @@ void chain_prepare(int lds_bytes);
 void launch_chain_bwd(const ChainArgs& a, hipStream_t s);
 void launch_chain_fwd(const ChainArgs& a, hipStream_t s);
 
+// sound64.hip: the sound-mode evaluation in float64
+struct Pass64 {
+  Batch bt;
+  const float* l;      // [P, nd] root bounds (the chords are formed from them in double)
+  const float* u;
+  const float* alpha;  // [n_alpha] or null (default slopes)
+  const float* beta;   // [nnz, m]
+  const float* sw;     // [P, nd] weight of |Lambda_k| in the float64 rounding-error bound
+  double sg;           // weight of each concretisation term
+  double* part;        // [slots, R] partial constants
+  double* perr;        // [slots, R] partial rounding-error bounds
+  double* psq;         // [slots, R] partial sums of A(0)^2 (l2 ball), or null
+};
+struct Top64 {
+  // general specification: C_p [m, dL] times the last (dense) layer W(L),
+  // b(L), formed in double; or (C null) the exact float rows CW = +-W(L)
+  const float* C;
+  int dL;
+  const float* WL;
+  int ldw;
+  const float* bL;
+  const float* CW;
+  int64_t cw_pstride;
+  int ldcw;
+  const float* Cb;
+  int64_t cb_pstride;
+  int n;            // width of layer L-1
+  int layer_off;
+  const float* bias;  // bias of layer L-1 per neuron
+  double* out;
+  int ldo;
+  int conc;         // no ReLU layer: concretise directly
+  const float* err0;  // [P, m] rounding-error bound of forming C W(L) and C b(L)
+};
+struct Lay64 {
+  const double* in;  // Lambda(i) rows
+  int ldi;
+  int K, N;          // d_i, d_(i-1)
+  const float* W;    // dense [d_i, ldw]; conv OIHW
+  int ldw;
+  int conc;          // 1: into the input (concretise)
+  int layer_off;     // layer i-1 in the nd axis (relaxation)
+  const float* bias; // bias of layer i-1 per neuron
+  double* out;
+  int ldo;
+  int slot;
+};
+struct Fin64 {
+  int n_used;
+  double scale;      // >= 1: the summation of the error partials
+  double ball;       // relative rounding of ||A(0)||_2 and of the A(0) x0 sum (l2 ball)
+  const float* x0n;  // [P] ||x0||_2 rounded up (l2 ball)
+  float* lb;
+  float* best;
+  int first;
+};
+void launch_top64(const Pass64& q, const Top64& t, hipStream_t s);
+void launch_dense64(const Pass64& q, const Lay64& y, hipStream_t s);
+void launch_conv64(const Pass64& q, const Lay64& y, const ConvGeom& g, hipStream_t s);
+void launch_finalize64(const Pass64& q, const Fin64& f, hipStream_t s);
+
 // misc.hip
 void launch_prep_chord(const float* l, const float* u, float2* chord, float* adef, int64_t n, hipStream_t s);
 void launch_status_fill(uint32_t* status, const uint32_t* root_kind, const int* prop, int B, int nd,
@@ -218,8 +279,14 @@ struct L2Final {
 // lb = sum of the used partial slots of each row; with perr (sound mode) minus
 // `scale` times the sum of the rounding-error partials, rounded outward; with
 // psq (l2 ball) minus eps_p sqrt(sum of the A(0)^2 partials)
+// improved (optional, with best): improved[row] = 1 where this bound raised
+// best[row] (or first), else 0
 void launch_finalize(const float* part, const float* perr, float scale, const float* psq, const L2Final& l2,
-                     int n_slots, int n_used, int n_rows, float* lb, float* best, int first, hipStream_t s);
+                     int n_slots, int n_used, int n_rows, float* lb, float* best, int first, hipStream_t s,
+                     int* improved = nullptr);
+// copy the variables of the rows flagged in improved into abest / bbest
+void launch_keep_best(const float* alpha, const float* beta, float* abest, float* bbest, const int* improved,
+                      const Batch& bt, hipStream_t s);
 void launch_adam(float* x, const float* g, float* m1, float* m2, int64_t n, float lr, float bc1, float bc2,
                  float lo, float hi, hipStream_t s);
 void launch_fill(float* p, float v, int64_t n, hipStream_t s);

@@ -218,7 +218,8 @@ __device__ __forceinline__ float slot_sum(const float* __restrict__ part, int n_
 
 __global__ __launch_bounds__(256) void finalize_k(const float* __restrict__ part, const float* __restrict__ perr,
                                                   float scale, const float* __restrict__ psq, L2Final l2,
-                                                  int n_used, int n_rows, float* lb, float* best, int first) {
+                                                  int n_used, int n_rows, float* lb, float* best, int first,
+                                                  int* improved) {
   __shared__ float red[4][64], rede[4][64], redq[4][64];
   const int rl = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int r = blockIdx.x * 64 + rl;
@@ -249,8 +250,27 @@ __global__ __launch_bounds__(256) void finalize_k(const float* __restrict__ part
     }
     if (perr) tot = nextafterf(tot - err, -INFINITY);
     if (lb) lb[r] = tot;
-    if (best) best[r] = first ? tot : fmaxf(best[r], tot);
+    if (best) {
+      const bool up = first || tot > best[r];
+      if (up) best[r] = tot;
+      if (improved) improved[r] = up ? 1 : 0;
+    }
   }
+}
+
+// The variables of every row whose bound improved (improved[row]): alpha's
+// [U_p] block of the row and beta's entries of the row (one per split of its
+// subdomain, stride m), copied to abest / bbest.  One block per row.
+__global__ __launch_bounds__(256) void keep_best_k(const float* __restrict__ alpha, const float* __restrict__ beta,
+                                                   float* abest, float* bbest, const int* __restrict__ improved,
+                                                   Batch bt) {
+  const int row = blockIdx.x;
+  if (!improved[row]) return;
+  const RowInfo ri = row_info(bt, row);
+  const int U = bt.ucount[ri.p];
+  for (int t = threadIdx.x; t < U; t += 256) abest[ri.abase + t] = alpha[ri.abase + t];
+  const int64_t s0 = bt.sptr[ri.b], s1 = bt.sptr[ri.b + 1];
+  for (int64_t t = s0 + threadIdx.x; t < s1; t += 256) bbest[t * bt.m + ri.k] = beta[t * bt.m + ri.k];
 }
 
 // Projected Adam ascent step (Kingma & Ba, beta1 0.9, beta2 0.999, eps 1e-8).
@@ -312,9 +332,15 @@ void launch_fill_i32(int* p, int v, int64_t n, hipStream_t s) {
 
 void launch_top(const TopArgs& a, hipStream_t s) { launch_k(top_k, nblk(a.bt.n_rows, 4), 256, 0, s, a); }
 void launch_finalize(const float* part, const float* perr, float scale, const float* psq, const L2Final& l2,
-                     int n_slots, int n_used, int n_rows, float* lb, float* best, int first, hipStream_t s) {
+                     int n_slots, int n_used, int n_rows, float* lb, float* best, int first, hipStream_t s,
+                     int* improved) {
   (void)n_slots;
-  launch_k(finalize_k, nblk(n_rows, 64), 256, 0, s, part, perr, scale, psq, l2, n_used, n_rows, lb, best, first);
+  launch_k(finalize_k, nblk(n_rows, 64), 256, 0, s, part, perr, scale, psq, l2, n_used, n_rows, lb, best, first,
+           improved);
+}
+void launch_keep_best(const float* alpha, const float* beta, float* abest, float* bbest, const int* improved,
+                      const Batch& bt, hipStream_t s) {
+  if (bt.n_rows > 0) launch_k(keep_best_k, (unsigned)bt.n_rows, 256, 0, s, alpha, beta, abest, bbest, improved, bt);
 }
 void launch_adam(float* x, const float* g, float* m1, float* m2, int64_t n, float lr, float bc1, float bc2, float lo,
                  float hi, hipStream_t s) {
