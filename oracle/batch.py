@@ -53,15 +53,15 @@ class OracleProblem:
         self.unstable = [np.nonzero((self.lo[p] < 0) & (self.up[p] > 0))[0] for p in range(self.lo.shape[0])]
         sizes = np.array([self.m * self.unstable[int(p)].shape[0] for p in self.dom_prop], np.int64)
         self.alpha_off = np.concatenate([[0], np.cumsum(sizes)])
-        self.l2 = None  # (x0 [P, d0], eps [P]) when the input set is an l2 ball per property
+        self.l2 = None  # (x0 [P, d0], eps [P], p) when the input set is an l_p ball per property
 
-    def set_l2(self, x0, eps):
-        """Input set of property p: the l2 ball of radius eps[p] around x0[p]
-        (None: back to the box)."""
-        self.l2 = None if x0 is None else (np.asarray(x0, np.float64), np.asarray(eps, np.float64))
+    def set_l2(self, x0, eps, p=2.0):
+        """Input set of property k: the l_p ball (default l2) of radius eps[k]
+        around x0[k] (x0 None: back to the box)."""
+        self.l2 = None if x0 is None else (np.asarray(x0, np.float64), np.asarray(eps, np.float64), float(p))
 
     def _ball(self, p):
-        return None if self.l2 is None else (self.l2[0][p], float(self.l2[1][p]))
+        return None if self.l2 is None else (self.l2[0][p], float(self.l2[1][p]), self.l2[2])
 
     @property
     def n_alpha(self):

@@ -132,24 +132,40 @@ def split_sign(split):
 # the bound at fixed (alpha, beta)
 
 
+def ball_parts(ball):
+    """(x0, eps, q) of an l_p ball given as (x0, eps) (p = 2) or (x0, eps, p),
+    1 < p < inf; q = p / (p - 1) is the dual exponent (1/p + 1/q = 1)."""
+    if len(ball) == 2:
+        x0, eps = ball
+        p = 2.0
+    else:
+        x0, eps, p = ball
+    return x0, eps, p / (p - 1.0)
+
+
 def concretise(A0, x_lo, x_hi, ball=None):
     """min over the input set of A0 x, row by row (Eq. beta_crown_lp): over
-    the box, sum_j min(A0_j x_lo_j, A0_j x_hi_j); over the l2 ball
-    ball = (x0, eps), A0 x0 - eps ||A0||_2 (Hoelder, q = p = 2)."""
+    the box, sum_j min(A0_j x_lo_j, A0_j x_hi_j); over the l_p ball
+    ||x - x0||_p <= eps, A0 x0 - eps ||A0||_q (Hoelder's inequality with the
+    dual exponent q; q = 2 for the l2 ball)."""
     if ball is None:
         return np.minimum(A0 * x_lo, A0 * x_hi).sum(axis=1)
-    x0, eps = ball
-    return A0 @ x0 - eps * np.linalg.norm(A0, axis=1)
+    x0, eps, q = ball_parts(ball)
+    return A0 @ x0 - eps * np.linalg.norm(A0, ord=q, axis=1)
 
 
 def minimiser(A0, x_lo, x_hi, ball=None):
     """x* of min A0 x over the input set, row by row: `box_minimiser`, or on
-    the l2 ball x0 - eps A0 / ||A0||_2 (x0 where A0 = 0)."""
+    the l_p ball x0 - eps sign(A0) |A0|^(q-1) / ||A0||_q^(q-1), the point of
+    equality in Hoelder's inequality (x0 where A0 = 0); for p = 2 this is
+    x0 - eps A0 / ||A0||_2."""
     if ball is None:
         return box_minimiser(A0, x_lo, x_hi)
-    x0, eps = ball
-    nrm = np.linalg.norm(A0, axis=1, keepdims=True)
-    return x0[None, :] - eps * np.divide(A0, nrm, out=np.zeros_like(A0), where=nrm > 0)
+    x0, eps, q = ball_parts(ball)
+    nrm = np.linalg.norm(A0, ord=q, axis=1, keepdims=True)
+    dirn = np.sign(A0) * np.abs(A0) ** (q - 1.0)
+    scale = nrm ** (q - 1.0)
+    return x0[None, :] - eps * np.divide(dirn, scale, out=np.zeros_like(A0), where=scale > 0)
 
 
 def bound(net64, x_lo, x_hi, C, lo, up, split, alpha, beta, keep=False, ball=None):
@@ -161,7 +177,8 @@ def bound(net64, x_lo, x_hi, C, lo, up, split, alpha, beta, keep=False, ball=Non
       lo/up [d_i] pre-activation bounds, split [d_i] in {+1, -1, 0},
       alpha [m, d_i] in [0, 1], beta [m, d_i] >= 0 (read only where split).
     Returns g [m] (and the per-layer trace used by the adjoint when keep).
-    ball = (x0, eps): the input set is the l2 ball instead of the box.
+    ball = (x0, eps) or (x0, eps, p): the input set is the l2 (or l_p) ball
+    instead of the box.
 
     Recursion (Eq. definition_A with the spec merged into the last layer):
       A(L-1) = C W(L),  c = C b(L);

@@ -536,3 +536,120 @@ def test_l2_ball_gradient_matches_central_differences(seed):
                     assert abs(fd - grads[i][r, j]) <= 1e-6 + 1e-5 * abs(fd), (which, i, r, j, fd, grads[i][r, j])
                     checked += 1
     assert checked >= 10
+
+
+# ---------------------------------------------------------------------------
+# general l_p-ball input sets (Eq. beta_crown_lp with the dual exponent q)
+
+LP_PS = (1.5, 3.0, 6.0)
+
+
+@pytest.mark.parametrize("p", LP_PS)
+@pytest.mark.parametrize("seed", range(3))
+def test_lp_ball_matches_dual_form_and_hoelder_equality(seed, p):
+    """The bound over the l_p ball equals Theorem 3.2's dual form with the
+    q-norm of nu-hat(0) (1/p + 1/q = 1); x* lies on the ball's surface
+    (||x* - x0||_p = eps) and attains Hoelder's equality for the linear part;
+    ub is the network at that x* (independent forward)."""
+    rng, net, x0, eps, x_lo, x_hi, lo, up, C = tiny_case(seed + 1700, widths=(4, 6, 5, 4, 2), m=2)
+    split = random_split(rng, lo, up, k=2)
+    alpha, beta = random_vars(rng, lo, 2, split, beta_scale=2.0)
+    q = p / (p - 1.0)
+    ball = (x0, eps, p)
+    g, A0, _ = bc.bound(net, x_lo, x_hi, C, lo, up, split, alpha, beta, keep=True, ball=ball)
+    _, ub, _, _ = bc.upper_bound(net, x_lo, x_hi, C, lo, up, split, alpha, beta, ball)
+    xs = bc.minimiser(A0, x_lo, x_hi, ball)
+    for r in range(2):
+        gd, _, nh0 = pinlib.dual_nu_bound(net, x0, eps, C[r], lo, up, split, [a[r] for a in alpha],
+                                          [b[r] for b in beta], with_input=True, q=q)
+        assert abs(gd - g[r]) <= 1e-10 * max(1, abs(g[r]))
+        coef = -nh0
+        assert abs(np.sum(np.abs(xs[r] - x0) ** p) ** (1 / p) - eps) <= 1e-12
+        assert abs(coef @ xs[r] - (coef @ x0 - eps * np.sum(np.abs(coef) ** q) ** (1 / q))) \
+            <= 1e-10 * max(1.0, abs(coef @ x0))
+        _, logits = pinlib.forward_all(net, xs[r][None, :])
+        assert abs(ub[r] - C[r] @ logits[0]) <= 1e-10 * max(1, abs(ub[r]))
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_lp_ball_bound_orders_with_the_ball_and_reduces_to_l2_and_box(seed):
+    """At fixed variables the l_p balls of one radius are nested (p < r gives
+    the smaller ball), so the bound falls as p grows: l_1.5 >= l_2 >= l_3 >=
+    l_6 >= box (the box is the l_inf ball).  p = 2 reproduces the l2 form
+    exactly, and p = 1000 is within d^(1/p) - 1 of the box's eps-term."""
+    rng, net, x0, eps, x_lo, x_hi, lo, up, C = tiny_case(seed + 1800, widths=(5, 7, 6, 3), m=3)
+    split = random_split(rng, lo, up, k=2)
+    alpha, beta = random_vars(rng, lo, 3, split, beta_scale=1.0)
+    gs = [bc.bound(net, x_lo, x_hi, C, lo, up, split, alpha, beta, ball=(x0, eps, p)) for p in (1.5, 2.0, 3.0, 6.0)]
+    g_box, A0, _ = bc.bound(net, x_lo, x_hi, C, lo, up, split, alpha, beta, keep=True)
+    for a, b in zip(gs, gs[1:] + [g_box]):
+        assert np.all(a >= b - 1e-12)
+    g_l2 = bc.bound(net, x_lo, x_hi, C, lo, up, split, alpha, beta, ball=(x0, eps))
+    assert np.array_equal(gs[1], g_l2)
+    g_big = bc.bound(net, x_lo, x_hi, C, lo, up, split, alpha, beta, ball=(x0, eps, 1000.0))
+    gap = eps * np.abs(A0).sum(axis=1) * (x0.shape[0] ** (1 / 1000.0) - 1)
+    assert np.all(g_big >= g_box - 1e-12) and np.all(g_big - g_box <= gap + 1e-12)
+
+
+@pytest.mark.parametrize("p", (1.5, 3.0))
+@pytest.mark.parametrize("seed", range(3))
+def test_lp_ball_bound_sound_on_the_ball(seed, p):
+    """Below the network's minimum over a dense sampling of the 2-D l_p ball
+    (direction times radius, each direction scaled to unit p-norm) restricted
+    to the split half-spaces."""
+    rng, net, x0, eps, x_lo, x_hi, lo, up, C = tiny_case(seed + 1900, widths=(2, 6, 6, 2), m=2)
+    th = np.linspace(0, 2 * np.pi, 721)[:-1]
+    d = np.stack([np.cos(th), np.sin(th)], 1)
+    d /= (np.abs(d) ** p).sum(axis=1, keepdims=True) ** (1 / p)
+    rad = np.linspace(0, 1, 301) ** 0.5
+    X = (x0[None, None, :] + eps * rad[:, None, None] * d[None]).reshape(-1, 2)
+    for trial in range(3):
+        split = random_split(rng, lo, up, k=trial)
+        alpha, beta = random_vars(rng, lo, 2, split, beta_scale=2.0)
+        g = bc.bound(net, x_lo, x_hi, C, lo, up, split, alpha, beta, ball=(x0, eps, p))
+        zs, logits = pinlib.forward_all(net, X)
+        ok = np.ones(X.shape[0], bool)
+        for z, s in zip(zs, split):
+            ok &= np.all((z[:, s > 0] >= 0), axis=1) & np.all((z[:, s < 0] <= 0), axis=1)
+        if ok.any():
+            fmin = (logits[ok] @ C.T).min(axis=0)
+            assert np.all(g <= fmin + 1e-9), (g, fmin)
+
+
+@pytest.mark.parametrize("p", (1.5, 3.0))
+def test_lp_ball_gradient_matches_central_differences(p):
+    rng, net, x0, eps, x_lo, x_hi, lo, up, C = tiny_case(2000 + int(p * 10), widths=(5, 8, 7, 3), m=2)
+    split = random_split(rng, lo, up, k=2)
+    alpha, beta = random_vars(rng, lo, 2, split, beta_scale=0.5)
+    alpha = [np.clip(a, 0.05, 0.95) for a in alpha]
+    beta = [np.where(s != 0, b + 0.1, 0.0) for b, s in zip(beta, split)]
+    ball = (x0, eps, p)
+    g, ga, gb = bc.bound_and_grad(net, x_lo, x_hi, C, lo, up, split, alpha, beta, ball)
+    h = 1e-5
+
+    def pattern(a, b):
+        _, A0, tr = bc.bound(net, x_lo, x_hi, C, lo, up, split, a, b, keep=True, ball=ball)
+        return [np.sign(t[0]) for t in tr]
+
+    base = pattern(alpha, beta)
+    checked = 0
+    for which, vars_, grads in (("a", alpha, ga), ("b", beta, gb)):
+        for i in range(len(vars_)):
+            for r in range(2):
+                for j in range(vars_[i].shape[1]):
+                    uns = lo[i][j] < 0 < up[i][j] and split[i][j] == 0
+                    if (which == "a" and not uns) or (which == "b" and split[i][j] == 0):
+                        continue
+                    pp, qq = [v.copy() for v in vars_], [v.copy() for v in vars_]
+                    pp[i][r, j] += h
+                    qq[i][r, j] -= h
+                    args_p = (pp, beta) if which == "a" else (alpha, pp)
+                    args_q = (qq, beta) if which == "a" else (alpha, qq)
+                    if any(np.any(x != y) or np.any(x != z) for x, y, z in
+                           zip(base, pattern(*args_p), pattern(*args_q))):
+                        continue
+                    fd = (bc.bound(net, x_lo, x_hi, C, lo, up, split, *args_p, ball=ball)[r] -
+                          bc.bound(net, x_lo, x_hi, C, lo, up, split, *args_q, ball=ball)[r]) / (2 * h)
+                    assert abs(fd - grads[i][r, j]) <= 1e-6 + 1e-5 * abs(fd), (which, i, r, j, fd, grads[i][r, j])
+                    checked += 1
+    assert checked >= 10
