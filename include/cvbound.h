@@ -330,6 +330,21 @@ int cv_bound_set_sound(cv_bound *h, int32_t on, void *stream);
  * double and rounded once. */
 int cv_bound_set_input_l2(cv_bound *h, const float *x0, const float *eps, void *stream);
 
+/* l_p-ball input sets for any p in [4/3, inf) (Sec. 2.1's l_p balls; Eq.
+ * beta_crown_lp concretises with the dual norm, 1/p + 1/q = 1): property
+ * k's input set becomes {x : ||x - x0_k||_p <= eps_k}.  The bound's last
+ * step is A(0) x0 - eps ||A(0)||_q, and the adjoint and cv_bound_upper use
+ * the minimiser x* = x0 - eps sign(A(0)) |A(0)|^(q-1) / ||A(0)||_q^(q-1)
+ * (x0 where A(0) = 0), the equality case of Hoelder's inequality.
+ * p = 2 is exactly cv_bound_set_input_l2; the box (p = inf) is the handle's
+ * x_lo, x_hi (x0 = NULL returns to it).  q <= 4 (p >= 4/3) keeps the float32
+ * powers |A(0)|^q in range for entries of magnitude about 1e-9 .. 1e9; the
+ * powers are formed as 2^(q log2|a|).  Arguments, allocation, sub-batches
+ * and the caller's duty for root bounds as for cv_bound_set_input_l2.
+ * CV_EINVAL for p < 4/3 or not finite, and for p != 2 while sound mode is
+ * on (cv_bound_set_sound likewise refuses to switch on over such balls). */
+int cv_bound_set_input_lp(cv_bound *h, const float *x0, const float *eps, float p, void *stream);
+
 /* Per-kernel timing of one gradient pass plus one plain evaluation, issued
  * eagerly on `stream`, repeated `reps` times.  Each kernel launch of a pass
  * is issued 8 times back to back (same arguments) between two HIP events on

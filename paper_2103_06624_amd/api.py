@@ -210,6 +210,16 @@ class BoundProblem:
         eps = np.ascontiguousarray(np.broadcast_to(np.asarray(eps, np.float32), (x0.shape[0],)))
         B.check(B.cv_bound_set_input_l2(self.h, _ptr(x0), _ptr(eps), _stream()))
 
+    def set_input_lp(self, x0, eps, p):
+        """Input sets {x : ||x - x0_k||_p <= eps_k} per property, p in [4/3, inf)
+        (x0 [P, d0], eps [P], host arrays); x0=None returns to the boxes."""
+        if x0 is None:
+            B.check(B.cv_bound_set_input_lp(self.h, None, None, 2.0, _stream()))
+            return
+        x0 = np.ascontiguousarray(x0, dtype=np.float32)
+        eps = np.ascontiguousarray(np.broadcast_to(np.asarray(eps, np.float32), (x0.shape[0],)))
+        B.check(B.cv_bound_set_input_lp(self.h, _ptr(x0), _ptr(eps), float(p), _stream()))
+
     def set_parts(self, nparts):
         """Concurrent sub-batches (streams) of optimize(); 1 disables the split."""
         B.check(B.cv_bound_set_parts(self.h, nparts))

@@ -70,6 +70,7 @@ SIGNATURES = {
     "cv_bound_conv_variant": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32]),
     "cv_bound_set_sound": (ctypes.c_int, [_vp, ctypes.c_int32, _vp]),
     "cv_bound_set_input_l2": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "cv_bound_set_input_lp": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_float, _vp]),
     "cv_bound_profile": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32, ctypes.POINTER(cv_kernel_stat),
                                         ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _vp]),
     "cv_bound_destroy": (None, [_vp]),
@@ -129,6 +130,7 @@ cv_bound_set_conv_variant = _fn("cv_bound_set_conv_variant")
 cv_bound_conv_variant = _fn("cv_bound_conv_variant")
 cv_bound_set_sound = _fn("cv_bound_set_sound")
 cv_bound_set_input_l2 = _fn("cv_bound_set_input_l2")
+cv_bound_set_input_lp = _fn("cv_bound_set_input_lp")
 cv_bound_profile = _fn("cv_bound_profile")
 cv_bound_destroy = _fn("cv_bound_destroy")
 cv_last_error = _fn("cv_last_error")

@@ -173,6 +173,7 @@ struct cv_bound {
   std::vector<float> hl2x0, hl2eps;  // host copies (sound mode's weights are built from them)
   float* x0n = nullptr;              // [P] ||x0_p||_2 rounded up (sound mode over balls)
   float l2fac = 1.f;
+  float lpq = 2.f;  // dual exponent q of the balls (2: l2)
   bool sound = false;
   float* sw = nullptr;    // [P, nd]
   float* perr = nullptr;  // [n_slots, R]
@@ -1330,7 +1331,7 @@ int enqueue_bwd(cv_bound* h, const float* alpha, const float* beta, bool grad, f
     cur ^= 1;
   }
   if (pf) pf->begin("finalize", 0, (double)h->R * (slot + 2) * 4.0);
-  const L2Final l2f{h->bt.prop, h->m, h->l2eps, h->l2s, h->x0n, h->sound_g, h->l2fac};
+  const L2Final l2f{h->bt.prop, h->m, h->l2eps, h->l2s, h->x0n, h->sound_g, h->l2fac, h->lpq};
   launch_finalize(h->part, h->sound ? h->perr : nullptr, h->sound_scale, h->l2 ? h->psq : nullptr, l2f, h->n_slots,
                   slot, h->R, lb, best, first, s, improved);
   if (pf) pf->end();
@@ -1740,8 +1741,10 @@ int set_parts(cv_bound* h, int n) {
       q->l2eps = h->l2eps;
       q->wx0 = h->wx0;
       q->l2 = true;
+      q->lpq = h->lpq;
       q->bt.l2x0 = h->l2x0;
       q->bt.l2eps = h->l2eps;
+      q->bt.lpq = h->lpq;
     }
   }
   if (h->sound) {
@@ -2487,6 +2490,7 @@ int cv_bound_set_tiling(cv_bound* h, int32_t tiling) {
 int cv_bound_set_sound(cv_bound* h, int32_t on, void* stream) {
   if (!h || !h->in) return fail(CV_EINVAL, "null handle");
   if (on != 0 && on != 1) return fail(CV_EINVAL, "sound must be 0 or 1");
+  if (on && h->l2 && h->lpq != 2.f) return fail(CV_EINVAL, "sound mode supports boxes and l2 balls only");
   if (on) return rebuild_sound(h, (hipStream_t)stream);
   std::vector<cv_bound*> all{h};
   all.insert(all.end(), h->parts.begin(), h->parts.end());
@@ -2498,7 +2502,7 @@ int cv_bound_set_sound(cv_bound* h, int32_t on, void* stream) {
   return CV_OK;
 }
 
-int cv_bound_set_input_l2(cv_bound* h, const float* x0, const float* eps, void* stream) {
+int cv_bound_set_input_lp(cv_bound* h, const float* x0, const float* eps, float p_norm, void* stream) {
   if (!h || !h->in) return fail(CV_EINVAL, "null handle");
   hipStream_t s = (hipStream_t)stream;
   std::vector<cv_bound*> all{h};
@@ -2506,6 +2510,7 @@ int cv_bound_set_input_l2(cv_bound* h, const float* x0, const float* eps, void* 
   if (!x0) {  // back to the box
     for (cv_bound* q : all) {
       q->l2 = false;
+      q->lpq = 2.f;
       q->bt.l2x0 = nullptr;
       q->bt.l2eps = nullptr;
       drop_graph(q);
@@ -2513,6 +2518,10 @@ int cv_bound_set_input_l2(cv_bound* h, const float* x0, const float* eps, void* 
     return h->sound ? rebuild_sound(h, s) : CV_OK;
   }
   if (!eps) return fail(CV_EINVAL, "null argument");
+  // q = p / (p - 1) <= 4 keeps the float32 q-th powers of A(0) in range
+  if (!(p_norm >= 4.f / 3.f) || !std::isfinite(p_norm)) return fail(CV_EINVAL, "p must be finite and >= 4/3");
+  const float lpq = p_norm == 2.f ? 2.f : (float)((double)p_norm / ((double)p_norm - 1.0));
+  if (h->sound && lpq != 2.f) return fail(CV_EINVAL, "sound mode supports boxes and l2 balls only");
   const int P = h->P, d0 = h->d0, d1 = h->dims[1];
   for (int64_t i = 0; i < (int64_t)P * d0; ++i)
     if (!std::isfinite(x0[i])) return fail(CV_EINVAL, "x0 must be finite");
@@ -2548,13 +2557,19 @@ int cv_bound_set_input_l2(cv_bound* h, const float* x0, const float* eps, void* 
     q->l2eps = h->l2eps;
     q->wx0 = h->wx0;
     q->l2 = true;
+    q->lpq = lpq;
     q->bt.l2x0 = h->l2x0;
     q->bt.l2eps = h->l2eps;
+    q->bt.lpq = lpq;
     drop_graph(q);
   }
   h->hl2x0.assign(x0, x0 + (size_t)P * d0);
   h->hl2eps.assign(eps, eps + P);
   return h->sound ? rebuild_sound(h, s) : CV_OK;
+}
+
+int cv_bound_set_input_l2(cv_bound* h, const float* x0, const float* eps, void* stream) {
+  return cv_bound_set_input_lp(h, x0, eps, 2.f, stream);
 }
 
 int cv_bound_profile(cv_bound* h, const float* alpha, const float* beta, int32_t reps, cv_kernel_stat* out,

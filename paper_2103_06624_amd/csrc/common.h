@@ -51,6 +51,9 @@ struct Batch {
   // each property's ball (the q = 2 form of Eq. beta_crown_lp)
   const float* l2x0;        // [P, d0]
   const float* l2eps;       // [P]
+  // dual exponent q = p/(p-1) of the l_p ball (2 for the l2 ball); read only
+  // with l2x0 set
+  float lpq;
 };
 
 // Variables of one pass.
@@ -225,6 +228,23 @@ __device__ __forceinline__ float relax_bwd(const Batch& bt, const Vars& v, const
 // Box minimiser contribution min(a xl, a xu) (Eq. beta_crown_lp for a box).
 __device__ __forceinline__ float conc_term(float a, float xl, float xu) {
   return fminf(a * xl, a * xu);
+}
+
+// One entry a of A(0) over an l_p ball (Eq. beta_crown_lp with the dual
+// exponent q): adds |a|^q to the row's q-norm sum and returns
+// sign(a) |a|^(q-1), the direction of the minimiser
+// x* = x0 - eps sign(A(0)) |A(0)|^(q-1) / ||A(0)||_q^(q-1) (Hoelder's
+// equality case).  q = 2: a*a (fused) and a itself.  Otherwise the power is
+// formed as 2^((q-1) log2 |a|).
+__device__ __forceinline__ float lp_entry(float a, float q, float* sum) {
+  if (q == 2.f) {
+    *sum = fmaf(a, a, *sum);
+    return a;
+  }
+  const float aa = fabsf(a);
+  const float t = aa > 0.f ? exp2f((q - 1.f) * log2f(aa)) : 0.f;
+  *sum = fmaf(aa, t, *sum);
+  return copysignf(t, a);
 }
 
 // x* of the box minimum: xl where A(0) > 0, xu where < 0, the centre at 0.

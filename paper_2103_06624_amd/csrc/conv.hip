@@ -335,11 +335,11 @@ __global__ __launch_bounds__(256, (conv_occupancy<MODE, NT>())) void conv_mm(con
             e.out[(int64_t)row * e.ldo + j] = lam;
             cer = fmaf(fabsf(lam), sw[u], cer);
           } else if (MODE == kBwdConc) {
-            if (bt.l2x0) {  // l2 ball: A(0) x0 here, - eps ||A(0)||_2 in the final sum
+            if (bt.l2x0) {  // l_p ball: A(0) x0 here, - eps ||A(0)||_q in the final sum
               if (!ok) continue;
               cst = fmaf(a[u], b1[h + u], cst);
-              cer = fmaf(a[u], a[u], cer);
-              if (v.xdense) v.xdense[(int64_t)row * v.ldx + j] = a[u];  // A(0) itself for the adjoint
+              const float xd = lp_entry(a[u], bt.lpq, &cer);
+              if (v.xdense) v.xdense[(int64_t)row * v.ldx + j] = xd;  // x*'s direction for the adjoint
               continue;
             }
             if (ok) {
@@ -598,11 +598,11 @@ __global__ __launch_bounds__(kSdThreads, (conv_sd_occupancy<MODE, NJ, NI>())) vo
           e.out[(int64_t)row * e.ldo + j] = lam;
           if (bt.sw) cer = fmaf(fabsf(lam), bt.sw[pc0 + j], cer);
         } else if (MODE == kBwdConc) {
-          if (bt.l2x0) {  // l2 ball: A(0) x0 here, - eps ||A(0)||_2 in the final sum
+          if (bt.l2x0) {  // l_p ball: A(0) x0 here, - eps ||A(0)||_q in the final sum
             if (!ok) continue;
             cst = fmaf(a, ch[u].x, cst);
-            cer = fmaf(a, a, cer);
-            if (v.xdense) v.xdense[(int64_t)row * v.ldx + j] = a;  // A(0) itself for the adjoint
+            const float xd = lp_entry(a, bt.lpq, &cer);
+            if (v.xdense) v.xdense[(int64_t)row * v.ldx + j] = xd;  // x*'s direction for the adjoint
             continue;
           }
           if (ok) {

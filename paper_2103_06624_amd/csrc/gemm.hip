@@ -244,11 +244,11 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt(const float* __restrict__ A,
                 e.out[(int64_t)row * e.ldo + col] = lam;
                 cer[i][r] = fmaf(fabsf(lam), o.esw[q], cer[i][r]);
               }
-            } else if (bt.l2x0) {  // l2 ball: A(0) x0 here, - eps ||A(0)||_2 in the final sum
+            } else if (bt.l2x0) {  // l_p ball: A(0) x0 here, - eps ||A(0)||_q in the final sum
               if (ok) {
                 cst[i][r] = fmaf(a, o.ech[q].x, cst[i][r]);
-                cer[i][r] = fmaf(a, a, cer[i][r]);
-                if (v.xdense) v.xdense[(int64_t)row * v.ldx + col] = a;  // A(0) itself for the adjoint
+                const float xd = lp_entry(a, bt.lpq, &cer[i][r]);
+                if (v.xdense) v.xdense[(int64_t)row * v.ldx + col] = xd;  // x*'s direction for the adjoint
               }
             } else {
               if (ok) {

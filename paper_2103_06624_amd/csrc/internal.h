@@ -265,20 +265,21 @@ void launch_top(const TopArgs& a, hipStream_t s);
 // ub[row] = C_p W(L) z[row] + C_p b(L), z = zhat(L-1) of the network at x*
 void launch_top_dot(const TopArgs& a, const float* z, int ldz, float* ub, hipStream_t s);
 void launch_fill_i32(int* p, int v, int64_t n, hipStream_t s);
-// l2-ball concretisation data of the final sum
+// l_p-ball concretisation data of the final sum
 struct L2Final {
   const int* prop;    // [B] property of each subdomain
   int m;              // rows per subdomain
   const float* eps;   // [P] radius
-  float* l2s;         // [n_rows] out: eps / ||A(0)||_2, or null
+  float* l2s;         // [n_rows] out: eps / ||A(0)||_q^(q-1), or null
   // sound mode: ||x0_p||_2 rounded up [P], the concretisation sum's error
   // factor g, and fac >= 1 bounding the rounding of the norm (unused otherwise)
   const float* x0n;
   float g, fac;
+  float q;  // dual exponent of the ball (2: l2; sound mode only with 2)
 };
 // lb = sum of the used partial slots of each row; with perr (sound mode) minus
 // `scale` times the sum of the rounding-error partials, rounded outward; with
-// psq (l2 ball) minus eps_p sqrt(sum of the A(0)^2 partials)
+// psq (l_p ball) minus eps_p (sum of the |A(0)|^q partials)^(1/q)
 // improved (optional, with best): improved[row] = 1 where this bound raised
 // best[row] (or first), else 0
 void launch_finalize(const float* part, const float* perr, float scale, const float* psq, const L2Final& l2,

@@ -125,9 +125,9 @@ __global__ __launch_bounds__(256) void top_k(TopArgs a) {
 #pragma unroll
       for (int e = 0; e < E; ++e)
         if (j0 + 64 * e < a.n) {
-          if (a.bt.l2x0) {  // l2 ball: A x0 here, - eps ||A||_2 in the final sum
+          if (a.bt.l2x0) {  // l_p ball: A x0 here, - eps ||A||_q in the final sum
             cst = fmaf(av[e], b1[e], cst);
-            cer = fmaf(av[e], av[e], cer);
+            lp_entry(av[e], a.bt.lpq, &cer);
           } else {
             const float tm = conc_term(av[e], b1[e], b2[e]);
             cst += tm;
@@ -160,8 +160,9 @@ __global__ __launch_bounds__(256) void top_k(TopArgs a) {
   cst = wave_sum(cst);
   if (lane == 0) a.e.part[(int64_t)a.e.slot0 * a.bt.n_rows + row] = cst + a.Cb[ri.p * a.cb_pstride + ri.k];
   if (a.e.perr || a.e.psq) {
-    // cer: the rounding-error bound, or over an l2 ball with no ReLU layer the
-    // sum of A^2 (then the error slot keeps only the specification's error)
+    // cer: the rounding-error bound, or over an l_p ball with no ReLU layer
+    // the sum of |A|^q (then the error slot keeps only the specification's
+    // error)
     const bool sq = a.conc && a.bt.l2x0;
     cer = wave_sum(cer);
     if (lane == 0) {
@@ -198,10 +199,11 @@ __global__ __launch_bounds__(256) void fill_i32_k(int* p, int v, int64_t n) {
 // four sums are then added in wave order.
 // Sound mode (perr set): the rounding-error partials are summed the same way,
 // scaled by `scale` for their own rounding, and the bound is lowered by them,
-// each step rounded outward.  l2 ball (psq set): the partial sums of A(0)^2
-// give ||A(0)||_2 and the bound is lowered by eps_p ||A(0)||_2 (in sound mode
-// by an upper bound on it, plus the concretisation sum's own rounding);
-// l2s[row] receives eps_p / ||A(0)||_2 (0 when A(0) = 0) for the adjoint's x*.
+// each step rounded outward.  l_p ball (psq set): the partial sums of
+// |A(0)|^q give ||A(0)||_q and the bound is lowered by eps_p ||A(0)||_q (in
+// sound mode, l2 only, by an upper bound on it, plus the concretisation sum's
+// own rounding); l2s[row] receives eps_p / ||A(0)||_q^(q-1) (0 when A(0) = 0),
+// the scale of the adjoint's x* = x0 - l2s sign(A(0)) |A(0)|^(q-1).
 __device__ __forceinline__ float slot_sum(const float* __restrict__ part, int n_used, int n_rows, int r, int g) {
   float s = 0.f;
   int t = g;
@@ -233,9 +235,17 @@ __global__ __launch_bounds__(256) void finalize_k(const float* __restrict__ part
     if (perr) err = nextafterf((((rede[0][rl] + rede[1][rl]) + rede[2][rl]) + rede[3][rl]) * scale, INFINITY);
     if (psq) {
       const int p = l2.prop[r / l2.m];
-      const float nrm = sqrtf(((redq[0][rl] + redq[1][rl]) + redq[2][rl]) + redq[3][rl]);
+      const float sq = ((redq[0][rl] + redq[1][rl]) + redq[2][rl]) + redq[3][rl];
       const float eps = l2.eps[p];
-      if (l2.l2s) l2.l2s[r] = nrm > 0.f ? eps / nrm : 0.f;
+      float nrm;
+      if (l2.q == 2.f) {
+        nrm = sqrtf(sq);
+        if (l2.l2s) l2.l2s[r] = nrm > 0.f ? eps / nrm : 0.f;
+      } else {
+        // ||A||_q = S^(1/q); the adjoint's scale eps / ||A||_q^(q-1) = eps ||A||_q / S
+        nrm = sq > 0.f ? exp2f(log2f(sq) / l2.q) : 0.f;
+        if (l2.l2s) l2.l2s[r] = sq > 0.f ? eps * (nrm / sq) : 0.f;
+      }
       if (perr) {
         // sound: ||A(0)||_2 <= nrm * fac (the sum of squares and the square
         // root rounded), and the float sum A(0) x0 is off by at most

@@ -6,6 +6,7 @@ library so both see the same unstable sets.
 """
 from __future__ import annotations
 
+import copy
 import functools
 
 import numpy as np
@@ -82,6 +83,16 @@ def l2_case(name, n_props=None, n_dom=None):
 
 def small_l2_case(name):
     return l2_case(name, **SMALL[name])
+
+
+def small_lp_case(name, p):
+    """small_l2_case's centres and radii as l_p balls.  For any p >= 1 the
+    l_p ball of radius eps lies in the box [x0 - eps, x0 + eps], so the same
+    root bounds hold over it.  The oracle is a copy set to the l_p balls."""
+    wl, lo, up, x0, eps, orc = small_l2_case(name)
+    orc = copy.copy(orc)
+    orc.set_l2(x0, eps, p)
+    return wl, lo, up, x0, eps, orc
 
 
 def interval_bounds(net64, x_lo, x_hi):
