@@ -52,9 +52,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_for(kernel, workload):
+def traffic_for(kernel, workload, conv_plan):
     """HBM traffic per launch from committed rocprofv3 counter runs, if they
-    were taken on the current kernel sources; else None."""
+    were taken on the current kernel sources under the same conv plan; else
+    None."""
     path = os.path.join(ROOT, "profiles", "traffic.txt")
     if not os.path.exists(path):
         return None
@@ -63,7 +64,184 @@ def traffic_for(kernel, workload):
     ent = rec.get(workload, {}).get(kernel)
     if not ent or ent.get("source_hash") != kernel_source_hash():
         return None
+    if rec.get("_about", {}).get(f"conv_plan_{workload}") != conv_plan:
+        return None
     return ent.get("bytes_per_launch")
+
+
+# ---- rocprofv3 counter runs -> per-kernel figures (host only) --------------
+# The counter runs profile `bench.py --profile-only`, whose last work is the
+# per-kernel timing pass: every launch of one gradient pass and one plain
+# evaluation issued 8 times back to back.  Its dispatches are therefore the
+# last 8 x (launches per pass) x reps of the run, in pass order, and are named
+# here from the pass's own kernel list (first appearances in pass order).
+
+
+def counter_dispatches(d):
+    """Dispatches of a rocprofv3 --pmc CSV run under directory d, in dispatch
+    order: {kernel, grid, counters {name: value}}."""
+    import csv
+    import glob
+    files = sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True))
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {d}")
+    disp = {}
+    for f in files:
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                k = (int(r.get("Process_Id") or 0), int(r["Dispatch_Id"]))
+                e = disp.setdefault(k, {"kernel": r["Kernel_Name"], "grid": int(r["Grid_Size"]), "c": {}})
+                e["c"][r["Counter_Name"]] = e["c"].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    return [disp[k] for k in sorted(disp)]
+
+
+def last_json_line(path):
+    with open(path) as f:
+        lines = [ln for ln in f.read().splitlines() if ln.startswith("{")]
+    return json.loads(lines[-1])
+
+
+def name_profile_pass(disp, prof):
+    """{kernel name of the timing pass: [its dispatches]} from a counter run of
+    `bench.py --profile-only` whose printed line is prof."""
+    kern = prof["kernels"]
+    reps = prof["profile_reps"]
+    n = 8 * reps * sum(k["launches_per_pass"] for k in kern)
+    tail = disp[-n:]
+    if len(tail) != n:
+        raise SystemExit("counter run holds fewer dispatches than the timing pass")
+    names = iter([k["name"] for k in kern])
+    key_name, out = {}, {}
+    for i in range(0, n, 8):
+        grp = tail[i:i + 8]
+        key = (grp[0]["kernel"], grp[0]["grid"])
+        if any((g["kernel"], g["grid"]) != key for g in grp):
+            raise SystemExit(f"dispatch group at {i} is not 8 launches of one kernel")
+        if key not in key_name:
+            key_name[key] = next(names)
+        out.setdefault(key_name[key], []).extend(grp)
+    for k in kern:
+        got = len(out.get(k["name"], ()))
+        if got != 8 * reps * k["launches_per_pass"]:
+            raise SystemExit(f"{k['name']}: {got} dispatches, expected {8 * reps * k['launches_per_pass']}")
+    return out
+
+
+def copy_factor(d, counter, mib):
+    """Known bytes of one mib-MiB device copy / what `counter` (KiB) reads for
+    it: the mean over the calibration run's last 3 dispatches (the copies)."""
+    disp = counter_dispatches(d)[-3:]
+    if len({x["kernel"] for x in disp}) != 1:
+        raise SystemExit("calibration run does not end with 3 copies of one kernel")
+    kib = sum(x["c"][counter] for x in disp) / 3
+    return (mib << 20) / (kib * 1024.0)
+
+
+def ingest_traffic(args):
+    """Write the workload's entry of profiles/traffic.txt from a FETCH_SIZE
+    and a WRITE_SIZE counter run of --profile-only and the two counters'
+    readings of a plain copy (--calib-only)."""
+    fetch_dir, write_dir, cal_f, cal_w, prof_path = args.ingest_traffic
+    prof = last_json_line(prof_path)
+    ff = copy_factor(cal_f, "FETCH_SIZE", args.calib_copy_mib)
+    fw = copy_factor(cal_w, "WRITE_SIZE", args.calib_copy_mib)
+    fetch = name_profile_pass(counter_dispatches(fetch_dir), prof)
+    write = name_profile_pass(counter_dispatches(write_dir), prof)
+    path = os.path.join(ROOT, "profiles", "traffic.txt")
+    rec = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            rec = json.load(f)
+    h = kernel_source_hash()
+    ent = {}
+    for name in fetch:
+        fb = sum(x["c"]["FETCH_SIZE"] for x in fetch[name]) / len(fetch[name]) * 1024 * ff
+        wb = sum(x["c"]["WRITE_SIZE"] for x in write[name]) / len(write[name]) * 1024 * fw
+        ent[name] = {"bytes_per_launch": int(fb + wb), "fetch_bytes": int(fb), "write_bytes": int(wb),
+                     "dispatches": len(fetch[name]), "source_hash": h}
+    rec["_about"] = {k: v for k, v in rec.get("_about", {}).items() if not k.startswith(("what", "commands"))}
+    rec["_about"]["what"] = (
+        "HBM bytes per launch per kernel = mean FETCH_SIZE x fetch factor + mean WRITE_SIZE x write factor "
+        "(KiB per dispatch, over the kernel's dispatches in bench.py --profile-only's per-kernel timing pass, "
+        "every launch issued 8 times back to back); factors = known bytes of a plain device copy "
+        "(bench.py --calib-only, 256 MiB) / what the same counter reads for it.  Valid for the kernel sources "
+        "of source_hash (sha256 of paper_2103_06624_amd/csrc/* except the host-side api.hip, first 16 hex "
+        "digits) and the conv plan conv_plan_<workload> the counter runs' autotuner chose.")
+    rec["_about"]["commands"] = [
+        "cd /tmp && export TMPDIR=/tmp && timeout -s KILL 300 rocprofv3 --pmc FETCH_SIZE --output-format csv "
+        "-d $REPO/gpurun_out/pmc_fetch -o run -- python3 $REPO/bench.py --workload <W> --profile-only "
+        "--profile-reps 1 > $REPO/gpurun_out/pmc_fetch.out",
+        "(the same with --pmc WRITE_SIZE into pmc_write)",
+        "timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE --output-format csv -d $REPO/gpurun_out/cal_fetch -o run "
+        "-- python3 $REPO/bench.py --calib-only --calib-copy-mib 256 (and WRITE_SIZE into cal_write)",
+        "python3 bench.py --ingest-traffic gpurun_out/pmc_fetch gpurun_out/pmc_write gpurun_out/cal_fetch "
+        "gpurun_out/cal_write gpurun_out/pmc_fetch.out"]
+    rec["_about"][f"factors_{prof['workload']}"] = {"fetch": round(ff, 4), "write": round(fw, 4)}
+    rec["_about"][f"conv_plan_{prof['workload']}"] = prof["conv_plan"]
+    rec[prof["workload"]] = ent
+    # entries taken on other kernel sources are stale: drop them
+    for w in [w for w in rec if not w.startswith("_")]:
+        rec[w] = {k: v for k, v in rec[w].items() if v.get("source_hash") == h}
+        if not rec[w]:
+            del rec[w]
+    for k in [k for k in rec["_about"] if k.startswith(("factors_", "conv_plan_"))]:
+        if k.split("_", 1)[1].replace("plan_", "", 1) not in rec:
+            del rec["_about"][k]
+    with open(path, "w") as f:
+        json.dump(rec, f, indent=1, sort_keys=True)
+        f.write("\n")
+    algo = {k["name"]: k["bytes_per_launch"] for k in prof["kernels"]}
+    for name, e in sorted(ent.items(), key=lambda kv: -kv[1]["bytes_per_launch"]):
+        print(f"{name:32s} HBM {e['bytes_per_launch'] / 1e6:10.1f} MB/launch  algorithmic "
+              f"{algo.get(name, 0) / 1e6:10.1f} MB  ratio {e['bytes_per_launch'] / max(algo.get(name, 1), 1):6.2f}")
+
+
+def counters_summary(args):
+    """Per-kernel counter figures of the timing pass (markdown table) from
+    counter runs of --profile-only: MFMA busy = SQ_VALU_MFMA_BUSY_CYCLES /
+    (GRBM_GUI_ACTIVE / 8 XCDs x 1024 SIMDs), instructions per dispatch."""
+    prof = last_json_line(args.counters_summary[0])
+    merged = {}
+    for d in args.counters_summary[1:]:
+        for name, lst in name_profile_pass(counter_dispatches(d), prof).items():
+            m = merged.setdefault(name, {})
+            for c in {c for x in lst for c in x["c"]}:
+                m[c] = sum(x["c"].get(c, 0.0) for x in lst) / len(lst)
+    us = {k["name"]: k["avg_us"] for k in prof["kernels"]}
+    tf = {k["name"]: k["tflops"] for k in prof["kernels"]}
+    print("| kernel | avg us (HIP events) | TFLOP/s | MFMA busy | VALU insts/disp (M) | MFMA insts/disp (M) | "
+          "LDS insts/disp (M) | LDS bank conflict / LDS active |")
+    print("|---|---|---|---|---|---|---|---|")
+    for name, m in merged.items():
+        gr = m.get("GRBM_GUI_ACTIVE", 0.0) / 8
+        busy = m["SQ_VALU_MFMA_BUSY_CYCLES"] / (gr * 1024) if gr and "SQ_VALU_MFMA_BUSY_CYCLES" in m else None
+        bank = (m["SQ_LDS_BANK_CONFLICT"] / m["SQ_LDS_IDX_ACTIVE"]
+                if m.get("SQ_LDS_IDX_ACTIVE") and "SQ_LDS_BANK_CONFLICT" in m else None)
+        f = lambda c: f"{m[c] / 1e6:.2f}" if c in m else "-"
+        print(f"| {name} | {us.get(name, 0):.1f} | {tf.get(name, 0):.1f} | "
+              f"{'-' if busy is None else f'{busy:.3f}'} | {f('SQ_INSTS_VALU')} | {f('SQ_INSTS_MFMA')} | "
+              f"{f('SQ_INSTS_LDS')} | {'-' if bank is None else f'{bank:.3f}'} |")
+
+
+def trace_summary(args):
+    """Per-kernel durations of the timing pass from a rocprofv3
+    --kernel-trace database of --profile-only (the `kernels` view), beside the
+    pass's own HIP-event averages (markdown)."""
+    import sqlite3
+    prof = last_json_line(args.trace_summary[0])
+    con = sqlite3.connect(args.trace_summary[1])
+    disp = [{"kernel": n, "grid": gx * gy * gz, "us": d / 1e3}
+            for n, gx, gy, gz, d in con.execute(
+                "select name, grid_x, grid_y, grid_z, duration from kernels order by dispatch_id")]
+    named = name_profile_pass(disp, prof)
+    ev = {k["name"]: k for k in prof["kernels"]}
+    print("| kernel | symbol | dispatches | rocprofv3 avg us | HIP-event avg us | rocprof / events |")
+    print("|---|---|---|---|---|---|")
+    for name, lst in named.items():
+        a = sum(x["us"] for x in lst) / len(lst)
+        sym = lst[0]["kernel"].replace("void ", "").replace("cvb::(anonymous namespace)::", "").split("(")[0]
+        print(f"| {name} | `{sym}` | {len(lst)} | {a:.1f} | {ev[name]['avg_us']:.1f} | "
+              f"{a / ev[name]['avg_us']:.3f} |")
 
 
 def library_gemm_context(wl, rows):
@@ -252,7 +430,7 @@ def kernel_table(pb, a0, b0, reps):
     return stats, kern
 
 
-def roofline(stats, kern, name):
+def roofline(stats, kern, name, conv_plan):
     dom = max(kern, key=lambda k: k["share"])
     if dom["flops_per_launch"] > 0:
         # the dense GEMMs and the conv layers' implicit GEMMs run on the matrix cores
@@ -262,7 +440,7 @@ def roofline(stats, kern, name):
     else:
         roof = {"bound": "hbm", "achieved": round(dom["gbs"], 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(dom["gbs"] / PEAK_HBM_GBS, 4)}
-    roof["traffic"] = traffic_for(dom["name"], name)
+    roof["traffic"] = traffic_for(dom["name"], name, conv_plan)
     roof["kernel"] = dom["name"]
     roof["avg_us"] = round(dom["avg_us"], 3)
     roof["algorithmic_bytes_per_launch"] = dom["bytes_per_launch"]
@@ -297,9 +475,25 @@ def main():
                     help="concurrent sub-batches of the optimiser (0: the library's default)")
     ap.add_argument("--conv-variant", type=int, default=None,
                     help="force one conv kernel variant on every conv layer (0-3; overrides the autotuner)")
-    ap.add_argument("--calib-copy-mib", type=int, default=0,
-                    help="also run a plain device copy of this size (counter calibration)")
+    ap.add_argument("--calib-copy-mib", type=int, default=256,
+                    help="size of the plain device copy of --calib-only (counter calibration)")
+    ap.add_argument("--calib-only", action="store_true",
+                    help="only the plain device copy of --calib-copy-mib MiB (a counter run's calibration)")
+    ap.add_argument("--ingest-traffic", nargs=5, metavar=("FETCH_DIR", "WRITE_DIR", "CAL_FETCH_DIR",
+                                                          "CAL_WRITE_DIR", "PROFILE_OUT"),
+                    help="host only: write profiles/traffic.txt's entry from counter runs of --profile-only")
+    ap.add_argument("--counters-summary", nargs="+", metavar="PATH",
+                    help="host only: PROFILE_OUT then counter-run directories of --profile-only; "
+                         "prints a markdown table per kernel")
+    ap.add_argument("--trace-summary", nargs=2, metavar=("PROFILE_OUT", "RESULTS_DB"),
+                    help="host only: the timing pass's kernel durations from a rocprofv3 --kernel-trace database")
     args = ap.parse_args()
+    if args.trace_summary:
+        return trace_summary(args)
+    if args.ingest_traffic:
+        return ingest_traffic(args)
+    if args.counters_summary:
+        return counters_summary(args)
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1 (subdomains are "
                                    "independent, so a batch would shard across GPUs by subdomain ranges, "
@@ -312,6 +506,15 @@ def main():
     from paper_2103_06624_amd import api, synth
 
     torch.cuda.set_device(0)
+    if args.calib_only:
+        n = args.calib_copy_mib * (1 << 20) // 4
+        x = torch.ones(n, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration_copy_mib": args.calib_copy_mib}))
+        return
     name = args.workload
     log(f"[bench] workload {name}: building inputs")
     wl = synth.make(name)
@@ -339,22 +542,12 @@ def main():
     a0 = pb.alpha_init()
     b0 = pb.zeros_beta()
 
-    def calib_copy():
-        if args.calib_copy_mib:
-            n = args.calib_copy_mib * (1 << 20) // 4
-            x = torch.ones(n, device="cuda")
-            y = torch.empty_like(x)
-            for _ in range(3):
-                y.copy_(x)
-            torch.cuda.synchronize()
-
     if args.profile_only:
         log(f"[bench] profile pass only ({args.profile_reps} reps)")
         stats, kern = kernel_table(pb, a0, b0, args.profile_reps)
         torch.cuda.synchronize()
-        calib_copy()
         print(json.dumps({"workload": name, "profile_reps": args.profile_reps, "conv_plan": conv_plan,
-                          "roofline": roofline(stats, kern, name),
+                          "roofline": roofline(stats, kern, name, conv_plan),
                           "kernels": [{k: (round(v, 3) if isinstance(v, float) else v) for k, v in kk.items()}
                                       for kk in kern]}), flush=True)
         return
@@ -529,12 +722,11 @@ def main():
     # ---- per-kernel durations with HIP events on the launch stream
     log("[bench] per-kernel event timing")
     stats, kern = kernel_table(pb, a0, b0, args.profile_reps)
-    roof = roofline(stats, kern, name)
+    roof = roofline(stats, kern, name, conv_plan)
     on_mfma = [s for s in stats if s["name"].startswith(("gemm", "chain", "conv"))]
     gemm_fl = sum(s["flops"] for s in on_mfma)
     gemm_ms = sum(s["total_ms"] / s["reps"] for s in on_mfma)
     all_ms = sum(s["total_ms"] / s["reps"] for s in stats)
-    calib_copy()
 
     line = {
         "metric": "subdomain bounds/sec (20-iter alpha/beta opt) vs plain eval; rel err vs FP64",
