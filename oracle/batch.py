@@ -16,6 +16,7 @@ from __future__ import annotations
 import numpy as np
 
 from . import beta_crown as bc
+from . import joint as jt
 
 
 def root_bounds_all(net64, x_lo, x_hi):
@@ -144,3 +145,16 @@ class OracleProblem:
                                      self.alpha_to_layers(b, alpha_flat), self.beta_to_layers(b, beta_flat), cfg,
                                      self._ball(p))
         return best, self.alpha_from_layers(b, a), self.beta_from_layers(b, bt), g
+
+    def joint_optimize(self, b, alpha_flat, beta_flat, cfg=None):
+        """Eq. (opt_non_convex) for subdomain b (oracle.joint.joint_optimize):
+        (best g [m], final alpha block, final beta [depth_b, m], final g,
+        lo, up of the final iterate, each [sum d_i] layer-major)."""
+        if self.l2 is not None:
+            raise ValueError("joint optimisation is over boxes")
+        p, lo, up, split = self.domain(b)
+        best, a, bt, g, l_j, u_j = jt.joint_optimize(self.net64, self.x_lo[p], self.x_hi[p], self.C[p], lo, up, split,
+                                                     self.alpha_to_layers(b, alpha_flat),
+                                                     self.beta_to_layers(b, beta_flat), cfg)
+        return (best, self.alpha_from_layers(b, a), self.beta_from_layers(b, bt), g, np.concatenate(l_j),
+                np.concatenate(u_j))
