@@ -238,6 +238,55 @@ int cv_bound_autotune(cv_bound *h, void *stream);
  * up to float32 summation order. */
 int cv_bound_set_plan(cv_bound *h, int32_t chain_bwd, int32_t chain_fwd);
 
+/* Joint optimisation of intermediate-layer bounds (Sec. 3.3, Eq.
+ * opt_non_convex).  As cv_bound_optimize, except that every subdomain's
+ * pre-activation bounds of ReLU layers 2..L-1 are recomputed in each
+ * iteration: layer i's are Theorem 3.1's bounds of z(i) (and of -z(i)) on the
+ * sub-network of layers 1..i under the subdomain's splits below layer i, with
+ * variables alpha', beta' of their own, shared by all neurons of layer i per
+ * bound side (per subdomain: one alpha' entry per root-unstable neuron below
+ * layer i, one beta' per split below it).  The tighter of the computed and
+ * the root bound feeds the relaxation of the layers above (the gradient
+ * follows the computed one unless it is looser than the root's by more than
+ * 1e-4 max(1, |root|), so a tie carries it);
+ * layer 1's bounds stay the root's (exact over the box).  All variables
+ * ascend sum g together by projected Adam -- the gradient reaches alpha',
+ * beta' through the bounds -- with lr_alpha for alpha and alpha', lr_beta for
+ * beta and beta', lr * lr_decay^t at iteration t; alpha' starts at CROWN's
+ * slope of the root bounds, beta' at 0, every Adam moment at 0.  A split
+ * decides its neuron's relaxation whatever the bounds say (they contradict it
+ * only for an empty subdomain).
+ *   alpha, beta: device, in: the final objective's start (layouts as for
+ *     cv_bound_optimize), out: its final iterate;
+ *   lb_best: device [B][m], the best bound of the iters + 1 evaluated iterates;
+ *   lb_last: device [B][m] or NULL, the final iterate's bound;
+ *   l_out, u_out: device [B][sum d_i] or NULL, each subdomain's bounds of the
+ *     final iterate (layer-major).
+ * Boxes and plain float32 only: CV_EINVAL with sound mode on or l_p balls set.
+ * The first call builds, per intermediate layer i, a pass of 2 d_i rows per
+ * subdomain with per-row copies of its variables (device memory grows with
+ * B x sum_i 2 d_i x the unstable neurons below layer i; CV_ENOMEM when it
+ * does not fit), kept until cv_bound_destroy.  Eager on `stream` (no graph);
+ * cv_bound_set_parts does not apply. */
+int cv_bound_optimize_joint(cv_bound *h, int32_t iters, float lr_alpha, float lr_beta, float lr_decay,
+                            float *alpha, float *beta, float *lb_best, float *lb_last, float *l_out,
+                            float *u_out, void *stream);
+
+/* The shared variables of intermediate layer `layer` (2..L-1) after the last
+ * cv_bound_optimize_joint: alpha' and beta' of its final iterate and their
+ * gradients of that call's last iteration (zeros when it ran no iteration).
+ * Layouts, per subdomain in order: alpha' [2][uc_b] -- lower-bound side, then
+ * upper-bound side; uc_b = root-unstable neurons of b's property in layers
+ * 1..layer-1, in layer-major index order (the order of the handle's alpha
+ * blocks) -- and beta' [nnz_layer][2]: the subdomain's splits on layers below
+ * `layer`, in their CSR order, each with (lower side, upper side).
+ * cv_bound_joint_sizes gives the two lengths.  Outputs are device buffers;
+ * any may be NULL; stream-ordered copies.  CV_EINVAL before the first
+ * cv_bound_optimize_joint or for a layer outside 2..L-1. */
+int cv_bound_joint_sizes(const cv_bound *h, int32_t layer, int64_t *n_alpha_p, int64_t *n_beta_p);
+int cv_bound_joint_vars(cv_bound *h, int32_t layer, float *alpha_p, float *beta_p, float *g_alpha_p,
+                        float *g_beta_p, void *stream);
+
 /* Concurrent sub-batches of cv_bound_optimize: the subdomains are split into
  * nparts contiguous ranges of nearly equal size, each optimised by its own
  * captured graph on its own stream, forked from and joined back into the

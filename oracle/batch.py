@@ -158,3 +158,81 @@ class OracleProblem:
                                                      self.beta_to_layers(b, beta_flat), cfg)
         return (best, self.alpha_from_layers(b, a), self.beta_from_layers(b, bt), g, np.concatenate(l_j),
                 np.concatenate(u_j))
+
+    # ---- joint optimisation: the library's shared alpha' / beta' layouts ---
+    def joint_layout(self, b, i):
+        """Entries of subdomain b in the shared variables of layer i: the
+        root-unstable neurons of its property below layer i (nd-axis index,
+        layer-major) and its splits below layer i (CSR entries, in order)."""
+        u = self.unstable[int(self.dom_prop[b])]
+        us = u[u < self.offs[i - 1]]
+        ts = [t for t in range(self.ptr[b], self.ptr[b + 1]) if int(self.s_layer[t]) < i]
+        return us, ts
+
+    def joint_offsets(self, i):
+        """Start of each subdomain's block in layer i's shared alpha' and beta'."""
+        oa, ob = [0], [0]
+        for b in range(self.B):
+            us, ts = self.joint_layout(b, i)
+            oa.append(oa[-1] + 2 * len(us))
+            ob.append(ob[-1] + 2 * len(ts))
+        return oa, ob
+
+    def joint_vars(self, b, flat):
+        """oracle.joint.JointVars of subdomain b from the library's shared
+        arrays flat = {layer i: (alpha' [sum 2 uc], beta' [nnz_i * 2])}."""
+        ap, bp = {}, {}
+        for i, (ash, bsh) in flat.items():
+            oa, ob = self.joint_offsets(i)
+            us, ts = self.joint_layout(b, i)
+            a = np.asarray(ash[oa[b]:oa[b + 1]], np.float64).reshape(2, len(us))
+            bb = np.asarray(bsh[ob[b]:ob[b + 1]], np.float64).reshape(len(ts), 2)
+            ap[i], bp[i] = [], []
+            for side in (0, 1):
+                dense = np.zeros(self.offs[i - 1])
+                dense[us] = a[side]
+                ap[i].append([jt._t(dense[self.offs[k]:self.offs[k + 1]]) for k in range(i - 1)])
+                dense = np.zeros(self.offs[i - 1])
+                for n, t in enumerate(ts):
+                    dense[self.offs[int(self.s_layer[t]) - 1] + int(self.s_neuron[t])] = bb[n, side]
+                bp[i].append([jt._t(dense[self.offs[k]:self.offs[k + 1]]) for k in range(i - 1)])
+        return jt.JointVars(ap, bp)
+
+    def joint_eval(self, b, alpha_flat, beta_flat, jv, grad=False):
+        """(g [m], lo, up [sum d_i]) of Eq. (opt_non_convex)'s bound for
+        subdomain b at the final objective's alpha, beta (library layouts)
+        and the intermediate variables jv; with grad, also d(sum g)/d(jv) in
+        the library's shared layouts {layer i: (g alpha' block, g beta' block)}."""
+        p, lo, up, split = self.domain(b)
+        leaves = jv.leaves()
+        if grad:
+            for x in leaves:
+                x.requires_grad_(True)
+        g, l_j, u_j = jt.joint_bound(self.net64, self.x_lo[p], self.x_hi[p], self.C[p], lo, up, split,
+                                     [jt._t(a) for a in self.alpha_to_layers(b, alpha_flat)],
+                                     [jt._t(x) for x in self.beta_to_layers(b, beta_flat)], jv)
+        out = (g.detach().numpy().copy(), np.concatenate([x.detach().numpy() for x in l_j]),
+               np.concatenate([x.detach().numpy() for x in u_j]))
+        if not grad:
+            return out
+        gr = jt.torch.autograd.grad(g.sum(), leaves, allow_unused=True)
+        gmap = {id(x): (jt.torch.zeros_like(x) if y is None else y) for x, y in zip(leaves, gr)}
+        gflat = {}
+        for i in jv.ap:
+            us, ts = self.joint_layout(b, i)
+            ga = np.zeros((2, len(us)))
+            gb = np.zeros((len(ts), 2))
+            for side in (0, 1):
+                dense = np.concatenate([gmap[id(x)].numpy() for x in jv.ap[i][side]])
+                ga[side] = dense[us]
+                dense = np.concatenate([gmap[id(x)].numpy() for x in jv.bp[i][side]])
+                for n, t in enumerate(ts):
+                    gb[n, side] = dense[self.offs[int(self.s_layer[t]) - 1] + int(self.s_neuron[t])]
+            gflat[i] = (ga.reshape(-1), gb.reshape(-1))
+        return out + (gflat,)
+
+    def joint_start(self, b):
+        """oracle.joint.init_vars for subdomain b (alpha' at CROWN's slopes of
+        its property's root bounds, beta' = 0)."""
+        p, lo, up, _ = self.domain(b)
+        return jt.init_vars(self.net64, lo, up)

@@ -18,8 +18,10 @@ Readings where the paper is silent (each listed in the design notes):
     function), with no variables;
   * a subdomain's bound of layer i is the larger (l) / smaller (u) of the
     root bound and the jointly computed one -- both are sound for the
-    subdomain, a subset of the root's input set -- so the gradient reaches
-    alpha', beta' only where the computed bound is the tighter;
+    subdomain, a subset of the root's input set; the gradient reaches alpha',
+    beta' through the computed bound unless it is looser than the root bound
+    by more than a relative 1e-4 (`clip_lower`: at the start, with no splits,
+    the two tie exactly, and either is a valid subgradient choice);
   * a split neuron's relaxation follows its split (z >= 0: identity, z < 0:
     zero) whatever its bounds say; they can contradict the split only when
     the subdomain is empty;
@@ -106,6 +108,19 @@ def init_vars(net64, lo_root, up_root):
     return JointVars(ap, bp)
 
 
+TIE = 1e-4  # relative width of a tie between a computed bound and the root bound
+
+
+def clip_lower(new, root):
+    """The larger of a computed lower bound and the root one, as used; its
+    gradient follows the computed bound unless that is looser than the root
+    bound by more than TIE max(1, |root|) (at a tie either bound is a valid
+    choice of subgradient; this one keeps the computed bound's variables
+    moving, and the margin makes the choice the same in any precision)."""
+    use = new >= root - TIE * torch.clamp(root.abs(), min=1.0)
+    return torch.where(use, new + (torch.maximum(new, root) - new).detach(), root)
+
+
 def joint_bound(net64, x_lo, x_hi, C, lo_root, up_root, split, alpha, beta, jv):
     """(g [m], lo, up): the final bound with every intermediate bound of
     layers 2..L-1 computed from jv, as torch tensors (differentiable in
@@ -124,11 +139,8 @@ def joint_bound(net64, x_lo, x_hi, C, lo_root, up_root, split, alpha, beta, jv):
             a_rows = [a.expand(d, -1) for a in jv.ap[i][side]]
             b_rows = [bb.expand(d, -1) for bb in jv.bp[i][side]]
             rows.append(bound_t(net[:i], xl, xu, Ci, lo, up, sp[:i - 1], a_rows, b_rows))
-        # the tighter of the root bound and the computed one; the gradient
-        # follows the computed bound only where it is strictly tighter
-        lr_, ur_ = _t(lo_root[i - 1]), _t(up_root[i - 1])
-        lo.append(torch.where(rows[0] > lr_, rows[0], lr_))
-        up.append(torch.where(-rows[1] < ur_, -rows[1], ur_))
+        lo.append(clip_lower(rows[0], _t(lo_root[i - 1])))
+        up.append(-clip_lower(rows[1], -_t(up_root[i - 1])))
     g = bound_t(net, xl, xu, _t(C), lo, up, sp, alpha, beta)
     return g, lo, up
 

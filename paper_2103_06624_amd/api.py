@@ -80,6 +80,7 @@ class BoundProblem:
         split_neuron = np.ascontiguousarray(split_neuron, np.int32)
         split_side = np.ascontiguousarray(split_side, np.int8)
         self.P, self.m = C.shape[0], C.shape[1]
+        self.nd = sum(ly.d_out for ly in layers[:-1])
         self.B = dom_prop.shape[0]
         self._ucount = ((lo < 0) & (up > 0)).sum(axis=1).astype(np.int64)
         self._dom_prop = dom_prop
@@ -162,6 +163,31 @@ class BoundProblem:
         B.check(B.cv_bound_optimize(self.h, iters, lr_alpha, lr_beta, decay, _dptr(alpha), _dptr(beta),
                                     _dptr(adam_state), step0, _dptr(best), _dptr(last), _stream()))
         return best.view(self.B, self.m), last.view(self.B, self.m)
+
+    def optimize_joint(self, alpha, beta, iters=20, lr_alpha=0.01, lr_beta=0.05, decay=0.98, bounds=False):
+        """In-place projected Adam on alpha, beta jointly with every subdomain's
+        intermediate bounds (cv_bound_optimize_joint); returns (best, last)
+        bounds [B, m], and with bounds=True also the final iterate's
+        intermediate bounds (l, u) [B, sum d_i]."""
+        best = self._f(self.n_rows)
+        last = self._f(self.n_rows)
+        lo = self._f(self.B * self.nd) if bounds else None
+        up = self._f(self.B * self.nd) if bounds else None
+        B.check(B.cv_bound_optimize_joint(self.h, iters, lr_alpha, lr_beta, decay, _dptr(alpha), _dptr(beta),
+                                          _dptr(best), _dptr(last), _dptr(lo), _dptr(up), _stream()))
+        out = (best.view(self.B, self.m), last.view(self.B, self.m))
+        if bounds:
+            out += (lo.view(self.B, self.nd), up.view(self.B, self.nd))
+        return out
+
+    def joint_vars(self, layer):
+        """(alpha', beta', their gradients) of intermediate layer `layer` after
+        the last optimize_joint (cv_bound_joint_vars layouts), device tensors."""
+        na, nb = ctypes.c_int64(), ctypes.c_int64()
+        B.check(B.cv_bound_joint_sizes(self.h, layer, ctypes.byref(na), ctypes.byref(nb)))
+        out = [self._f(na.value), self._f(nb.value), self._f(na.value), self._f(nb.value)]
+        B.check(B.cv_bound_joint_vars(self.h, layer, *[_dptr(t) for t in out], _stream()))
+        return tuple(out)
 
     def row_maps(self):
         """(row of each alpha entry, row of each beta entry) as device index tensors."""

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcvbound.so")
-SOURCES = ["gemm.hip", "chain.hip", "conv.hip", "misc.hip", "sound64.hip", "api.hip"]
+SOURCES = ["gemm.hip", "chain.hip", "conv.hip", "misc.hip", "sound64.hip", "joint.hip", "api.hip"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-I", os.path.join(HERE, "..", "include")]
 

@@ -202,6 +202,11 @@ struct cv_bound {
   float* g_alpha = nullptr;
   float* g_beta = nullptr;
   float* adam = nullptr;  // [2 n_alpha + 2 n_beta]
+  // joint optimisation of intermediate bounds: the adjoint's zbar at
+  // upper-chord neurons (passes of the joint state only), and that state
+  float* zchord = nullptr;
+  struct Joint;
+  Joint* joint = nullptr;
   // tile choice per ReLU-layer kernel: [0..L-1] back-substitution of layer i+1,
   // [L..2L-1] adjoint forward of layer i+1
   std::vector<int> cfg;
@@ -1458,6 +1463,7 @@ int enqueue_fwd(cv_bound* h, const float* alpha, const float* beta, float* ga, f
   v.gbeta = gb;
   v.xpos = h->xpos;
   v.xneg = h->xneg;
+  v.zchord = h->zchord;
   if (ad) {
     v.adam = 1;
     v.lr_a = ad->lr_a;
@@ -1804,8 +1810,11 @@ int rebuild_sound(cv_bound* h, hipStream_t s) {
   return CV_OK;
 }
 
+void free_joint(cv_bound* h);
+
 void destroy_handle(cv_bound* h) {
   if (!h) return;
+  free_joint(h);
   free_parts(h);
   drop_graph(h);
   if (h->cap) (void)hipStreamDestroy(h->cap);
@@ -2044,6 +2053,249 @@ int root_bounds(const cv_layer* layers, int32_t n_layers, int32_t n_props, const
   return CV_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Joint optimisation of intermediate bounds (Sec. 3.3, Eq. opt_non_convex).
+// Every subdomain's bounds of ReLU layers 2..L-1 are recomputed in each
+// iteration as beta-CROWN bounds of the sub-network ending at that layer
+// (specification [I; -I]), with variables alpha', beta' shared by the layer's
+// neurons per bound side; they replace the root bounds where tighter and feed
+// the relaxation of the final objective.  The gradient of sum g reaches
+// alpha', beta' through the bounds: d g / d l, d u at each unstable neuron
+// (launch_joint_cot) weighs the rows of the layer's pass, whose per-row
+// gradients are summed onto the shared variables (launch_joint_reduce), and
+// the pass's own bounds' gradient flows on to the layers below it.
+// Each pass is a handle of its own with one "property" per subdomain, so its
+// relaxation tables (status, chord) are per subdomain and are refreshed from
+// the current bounds before it runs.
+
+}  // namespace
+
+struct JointLayer {
+  cv_bound* h = nullptr;  // layers 1..i, specification [I; -I], the splits below layer i
+  int i = 0, d = 0, off = 0;
+  int64_t nnz = 0, n_ash = 0;
+  float *arow = nullptr, *brow = nullptr, *garow = nullptr, *gbrow = nullptr;  // per-row copies
+  float *ash = nullptr, *bsh = nullptr, *gash = nullptr, *gbsh = nullptr;      // shared [sum_b 2 uc_b], [nnz][2]
+  float *ma = nullptr, *va = nullptr, *mb = nullptr, *vb = nullptr;            // Adam moments of ash, bsh
+  float *lb = nullptr, *w = nullptr;                                           // [B][2d] row bounds, weights
+  uint32_t* st0 = nullptr;  // status words at the root bounds
+};
+
+struct cv_bound::Joint {
+  cv_bound* hm = nullptr;  // the final objective, one property per subdomain
+  uint32_t* st0m = nullptr;
+  std::vector<JointLayer> lay;
+  DevMem mem;
+  float *lroot = nullptr, *uroot = nullptr, *lcur = nullptr, *ucur = nullptr, *dL = nullptr, *dU = nullptr;
+  uint8_t *ml = nullptr, *mu = nullptr;
+  float *ga = nullptr, *gb = nullptr, *ma = nullptr, *va = nullptr, *mb = nullptr, *vb = nullptr;
+  float* lb = nullptr;  // [R] bounds of the current iterate
+  ~Joint() {
+    destroy_handle(hm);
+    for (JointLayer& q : lay) destroy_handle(q.h);
+  }
+};
+
+namespace {
+
+void free_joint(cv_bound* h) {
+  delete h->joint;
+  h->joint = nullptr;
+}
+
+// The joint state of h, built from its kept init arguments on first use.
+int make_joint(cv_bound* h, hipStream_t s) {
+  if (h->joint) return CV_OK;
+  const cv_bound::Inputs& in = *h->in;
+  const int B = h->B, nd = h->nd, L = h->L, m = h->m, d0 = h->d0, dL = h->dims[L];
+  if (in.l.empty()) return fail(CV_EINVAL, "joint optimisation needs the handle's root bounds");
+  std::unique_ptr<cv_bound::Joint> J(new cv_bound::Joint());
+  // one property per subdomain: its box, specification and root bounds
+  std::vector<float> xlo((size_t)B * d0), xhi((size_t)B * d0), C((size_t)B * m * dL), lr((size_t)B * nd),
+      ur((size_t)B * nd);
+  std::vector<int32_t> ident(B);
+  for (int b = 0; b < B; ++b) {
+    const int p = in.prop[b];
+    ident[b] = b;
+    std::copy(in.xlo.begin() + (size_t)p * d0, in.xlo.begin() + (size_t)(p + 1) * d0, xlo.begin() + (size_t)b * d0);
+    std::copy(in.xhi.begin() + (size_t)p * d0, in.xhi.begin() + (size_t)(p + 1) * d0, xhi.begin() + (size_t)b * d0);
+    std::copy(in.C.begin() + (size_t)p * m * dL, in.C.begin() + (size_t)(p + 1) * m * dL, C.begin() + (size_t)b * m * dL);
+    std::copy(in.l.begin() + (size_t)p * nd, in.l.begin() + (size_t)(p + 1) * nd, lr.begin() + (size_t)b * nd);
+    std::copy(in.u.begin() + (size_t)p * nd, in.u.begin() + (size_t)(p + 1) * nd, ur.begin() + (size_t)b * nd);
+  }
+  int rc;
+  J->hm = new cv_bound();
+  Spec sp;
+  sp.C = C.data();
+  if ((rc = build(J->hm, in.layers.data(), L, B, xlo.data(), xhi.data(), m, sp, lr.data(), ur.data(), B,
+                  ident.data(), in.sptr.data(), in.slayer.data(), in.sneuron.data(), in.sside.data(), s)))
+    return rc;
+  if (J->hm->n_alpha != h->n_alpha || J->hm->nnz != h->nnz) return fail(CV_EINVAL, "joint layout mismatch");
+  cv_bound* hm = J->hm;
+  DevMem& M = J->mem;
+  const size_t bnd = (size_t)std::max(1, B * nd);
+  if ((rc = ensure_grad(hm)) || (rc = hm->mem.alloc(&hm->zchord, hm->n_alpha)) ||
+      (rc = M.upload(&J->lroot, lr.data(), lr.size(), s)) || (rc = M.upload(&J->uroot, ur.data(), ur.size(), s)) ||
+      (rc = M.alloc(&J->lcur, bnd)) || (rc = M.alloc(&J->ucur, bnd)) || (rc = M.alloc(&J->dL, bnd)) ||
+      (rc = M.alloc(&J->dU, bnd)) || (rc = M.alloc(&J->ml, bnd)) || (rc = M.alloc(&J->mu, bnd)) ||
+      (rc = M.alloc(&J->ga, h->n_alpha)) || (rc = M.alloc(&J->gb, h->nnz * m)) ||
+      (rc = M.alloc(&J->ma, h->n_alpha)) || (rc = M.alloc(&J->va, h->n_alpha)) ||
+      (rc = M.alloc(&J->mb, h->nnz * m)) || (rc = M.alloc(&J->vb, h->nnz * m)) ||
+      (rc = M.alloc(&J->lb, std::max(1, h->R))) || (rc = M.alloc(&J->st0m, (size_t)std::max(1, B * nd))))
+    return rc;
+  HIPCHK(hipMemcpyAsync(J->st0m, hm->bt.status, sizeof(uint32_t) * B * nd, hipMemcpyDeviceToDevice, s));
+  // the pass of each intermediate layer i = 2..L-1
+  for (int i = 2; i <= L - 1; ++i) {
+    JointLayer q;
+    q.i = i;
+    q.d = h->dims[i];
+    q.off = h->offs[i - 1];
+    const int ndx = q.off;  // ReLU layers 1..i-1
+    std::vector<float> lsub((size_t)B * ndx), usub((size_t)B * ndx);
+    for (int b = 0; b < B; ++b)
+      for (int c = 0; c < ndx; ++c) {
+        lsub[(size_t)b * ndx + c] = lr[(size_t)b * nd + c];
+        usub[(size_t)b * ndx + c] = ur[(size_t)b * nd + c];
+      }
+    std::vector<int64_t> ptr(B + 1, 0);
+    std::vector<int32_t> sl, sn;
+    std::vector<int8_t> ss;
+    for (int b = 0; b < B; ++b) {
+      for (int64_t t = in.sptr[b]; t < in.sptr[b + 1]; ++t)
+        if (in.slayer[t] < i) {
+          sl.push_back(in.slayer[t]);
+          sn.push_back(in.sneuron[t]);
+          ss.push_back(in.sside[t]);
+        }
+      ptr[b + 1] = (int64_t)sl.size();
+    }
+    q.nnz = ptr[B];
+    sl.push_back(0);
+    sn.push_back(0);
+    ss.push_back(1);
+    q.h = new cv_bound();
+    J->lay.push_back(q);  // owned by J from here on
+    JointLayer& Q = J->lay.back();
+    Spec si;
+    si.identity = true;
+    if ((rc = build(Q.h, in.layers.data(), i, B, xlo.data(), xhi.data(), 2 * Q.d, si, lsub.data(), usub.data(), B,
+                    ident.data(), ptr.data(), sl.data(), sn.data(), ss.data(), s)))
+      return rc;
+    cv_bound* x = Q.h;
+    Q.n_ash = x->n_alpha / Q.d;  // 2 uc_b per subdomain
+    const int64_t nb = Q.nnz * 2 * Q.d;
+    if ((rc = ensure_grad(x)) || (rc = x->mem.alloc(&x->zchord, x->n_alpha)) ||
+        (rc = M.alloc(&Q.arow, x->n_alpha)) || (rc = M.alloc(&Q.brow, nb)) || (rc = M.alloc(&Q.garow, x->n_alpha)) ||
+        (rc = M.alloc(&Q.gbrow, nb)) || (rc = M.alloc(&Q.ash, Q.n_ash)) || (rc = M.alloc(&Q.bsh, Q.nnz * 2)) ||
+        (rc = M.alloc(&Q.gash, Q.n_ash)) || (rc = M.alloc(&Q.gbsh, Q.nnz * 2)) || (rc = M.alloc(&Q.ma, Q.n_ash)) ||
+        (rc = M.alloc(&Q.va, Q.n_ash)) || (rc = M.alloc(&Q.mb, Q.nnz * 2)) || (rc = M.alloc(&Q.vb, Q.nnz * 2)) ||
+        (rc = M.alloc(&Q.lb, std::max(1, x->R))) || (rc = M.alloc(&Q.w, std::max(1, x->R))) ||
+        (rc = M.alloc(&Q.st0, (size_t)std::max(1, B * ndx))))
+      return rc;
+    HIPCHK(hipMemcpyAsync(Q.st0, x->bt.status, sizeof(uint32_t) * B * ndx, hipMemcpyDeviceToDevice, s));
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  h->joint = J.release();
+  return CV_OK;
+}
+
+// Status / chords of pass x (its first nd_x columns) from the current bounds.
+void joint_refresh(cv_bound::Joint* J, cv_bound* x, const uint32_t* st0, int nd, hipStream_t s) {
+  launch_joint_refresh(const_cast<uint32_t*>(x->bt.status), st0, const_cast<float2*>(x->bt.chord), J->lcur, J->ucur,
+                       x->B, x->nd, nd, s);
+}
+
+// One forward phase: every intermediate layer's bounds from the shared
+// variables (with the per-row gradients of each pass when grad), then the
+// final objective's bounds into lb (its gradients into J->ga, J->gb when grad).
+int joint_forward(cv_bound* h, const float* alpha, const float* beta, bool grad, float* lb, float* best, int first,
+                  hipStream_t s) {
+  cv_bound::Joint* J = h->joint;
+  const int B = h->B, nd = h->nd;
+  int rc;
+  for (JointLayer& q : J->lay) {
+    cv_bound* x = q.h;
+    joint_refresh(J, x, q.st0, nd, s);
+    launch_joint_bcast(q.arow, q.ash, q.brow, q.bsh, x->bt, q.d, q.nnz, s);
+    if ((rc = enqueue_bwd(x, q.arow, q.brow, grad, q.lb, nullptr, 0, s))) return rc;
+    if (grad) {
+      launch_fill(q.garow, 0.f, x->n_alpha, s);  // entries of neurons made stable are not written
+      if ((rc = enqueue_fwd(x, q.arow, q.brow, q.garow, q.gbrow, nullptr, s))) return rc;
+    }
+    launch_joint_clip(q.lb, q.d, q.off, J->lroot, J->uroot, J->lcur, J->ucur, J->ml, J->mu, B, nd, s);
+  }
+  cv_bound* hm = J->hm;
+  joint_refresh(J, hm, J->st0m, nd, s);
+  if ((rc = enqueue_bwd(hm, alpha, beta, grad, lb, best, first, s))) return rc;
+  if (grad) {
+    launch_fill(J->ga, 0.f, h->n_alpha, s);
+    if ((rc = enqueue_fwd(hm, alpha, beta, J->ga, J->gb, nullptr, s))) return rc;
+  }
+  HIPCHK(hipGetLastError());
+  return CV_OK;
+}
+
+// The reverse phase: d(sum g)/d(l, u) from the final objective's pass, then
+// layer by layer from the top: row weights, shared gradients, and the pass's
+// own contribution to the bounds' gradients of the layers below it.
+void joint_reverse(cv_bound* h, hipStream_t s) {
+  cv_bound::Joint* J = h->joint;
+  const int B = h->B, nd = h->nd, col0 = h->L > 2 ? h->dims[1] : nd;
+  cv_bound* hm = J->hm;
+  launch_fill(J->dL, 0.f, (int64_t)B * nd, s);
+  launch_fill(J->dU, 0.f, (int64_t)B * nd, s);
+  launch_joint_cot(J->dL, J->dU, hm->bt.status, hm->acomp, hm->zchord, nullptr, J->lcur, J->ucur, hm->bt, col0, nd,
+                   nd, B, s);
+  for (int t = (int)J->lay.size() - 1; t >= 0; --t) {
+    JointLayer& q = J->lay[t];
+    cv_bound* x = q.h;
+    launch_joint_weights(q.w, J->dL, J->dU, J->ml, J->mu, B, q.d, q.off, nd, s);
+    launch_joint_reduce(q.gash, q.garow, q.gbsh, q.gbrow, q.w, x->bt, B, q.d, q.nnz, s);
+    launch_joint_cot(J->dL, J->dU, x->bt.status, x->acomp, x->zchord, q.w, J->lcur, J->ucur, x->bt, col0, x->nd, nd,
+                     B, s);
+  }
+}
+
+int optimize_joint(cv_bound* h, int iters, float lr_a, float lr_b, float decay, float* alpha, float* beta,
+                   float* lb_best, float* lb_last, float* l_out, float* u_out, hipStream_t s) {
+  int rc = make_joint(h, s);
+  if (rc) return rc;
+  cv_bound::Joint* J = h->joint;
+  const int B = h->B, nd = h->nd;
+  const int64_t nb = h->nnz * h->m;
+  // fresh start of the intermediate variables and of every Adam moment
+  HIPCHK(hipMemcpyAsync(J->lcur, J->lroot, sizeof(float) * B * nd, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemcpyAsync(J->ucur, J->uroot, sizeof(float) * B * nd, hipMemcpyDeviceToDevice, s));
+  for (JointLayer& q : J->lay) {
+    launch_joint_alpha_init(q.ash, q.h->ulist, q.h->uoff, q.h->bt, B, q.d, s);
+    launch_fill(q.bsh, 0.f, q.nnz * 2, s);
+    launch_fill(q.gash, 0.f, q.n_ash, s);
+    launch_fill(q.gbsh, 0.f, q.nnz * 2, s);
+    for (float* z : {q.ma, q.va}) launch_fill(z, 0.f, q.n_ash, s);
+    for (float* z : {q.mb, q.vb}) launch_fill(z, 0.f, q.nnz * 2, s);
+  }
+  for (float* z : {J->ma, J->va}) launch_fill(z, 0.f, h->n_alpha, s);
+  for (float* z : {J->mb, J->vb}) launch_fill(z, 0.f, nb, s);
+  for (int t = 0; t < iters; ++t) {
+    if ((rc = joint_forward(h, alpha, beta, true, J->lb, lb_best, t == 0, s))) return rc;
+    joint_reverse(h, s);
+    const float bc1 = (float)(1.0 - std::pow(0.9, t + 1)), bc2 = (float)(1.0 - std::pow(0.999, t + 1));
+    const float la = (float)(lr_a * std::pow((double)decay, t)), lb = (float)(lr_b * std::pow((double)decay, t));
+    launch_adam(alpha, J->ga, J->ma, J->va, h->n_alpha, la, bc1, bc2, 0.f, 1.f, s);
+    launch_adam(beta, J->gb, J->mb, J->vb, nb, lb, bc1, bc2, 0.f, INFINITY, s);
+    for (JointLayer& q : J->lay) {
+      launch_adam(q.ash, q.gash, q.ma, q.va, q.n_ash, la, bc1, bc2, 0.f, 1.f, s);
+      launch_adam(q.bsh, q.gbsh, q.mb, q.vb, q.nnz * 2, lb, bc1, bc2, 0.f, INFINITY, s);
+    }
+  }
+  // the final iterate, evaluated once more
+  if ((rc = joint_forward(h, alpha, beta, false, lb_last ? lb_last : J->lb, lb_best, iters == 0, s))) return rc;
+  if (l_out) HIPCHK(hipMemcpyAsync(l_out, J->lcur, sizeof(float) * B * nd, hipMemcpyDeviceToDevice, s));
+  if (u_out) HIPCHK(hipMemcpyAsync(u_out, J->ucur, sizeof(float) * B * nd, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipGetLastError());
+  return CV_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -2246,6 +2498,45 @@ int cv_bound_optimize(cv_bound* h, int32_t iters, float lr_alpha, float lr_beta,
     return optimize_one(q, iters, lr_alpha, lr_beta, lr_decay, alpha ? alpha + o.a0 : nullptr,
                         beta ? beta + o.s0 : nullptr, pq, step0, lb_best + o.r0, lb_last ? lb_last + o.r0 : nullptr, t);
   });
+}
+
+int cv_bound_optimize_joint(cv_bound* h, int32_t iters, float lr_alpha, float lr_beta, float lr_decay, float* alpha,
+                            float* beta, float* lb_best, float* lb_last, float* l_out, float* u_out, void* stream) {
+  if (!h || !h->in || (!lb_best && h->R > 0) || (!alpha && h->n_alpha > 0) || (!beta && h->nnz > 0))
+    return fail(CV_EINVAL, "null argument");
+  if (iters < 0 || !std::isfinite(lr_alpha) || !std::isfinite(lr_beta) || !std::isfinite(lr_decay))
+    return fail(CV_EINVAL, "bad optimiser settings");
+  if (h->sound) return fail(CV_EINVAL, "joint optimisation runs in plain float32 (sound mode is on)");
+  if (h->l2) return fail(CV_EINVAL, "joint optimisation is over boxes (l_p balls are set)");
+  if (h->R == 0) return CV_OK;
+  return optimize_joint(h, iters, lr_alpha, lr_beta, lr_decay, alpha, beta, lb_best, lb_last, l_out, u_out,
+                        (hipStream_t)stream);
+}
+
+int cv_bound_joint_sizes(const cv_bound* h, int32_t layer, int64_t* n_alpha_p, int64_t* n_beta_p) {
+  if (!h) return fail(CV_EINVAL, "null handle");
+  if (!h->joint) return fail(CV_EINVAL, "no joint state (cv_bound_optimize_joint has not run)");
+  if (layer < 2 || layer > h->L - 1) return fail(CV_EINVAL, "layer must be 2..L-1");
+  const JointLayer& q = h->joint->lay[layer - 2];
+  if (n_alpha_p) *n_alpha_p = q.n_ash;
+  if (n_beta_p) *n_beta_p = q.nnz * 2;
+  return CV_OK;
+}
+
+int cv_bound_joint_vars(cv_bound* h, int32_t layer, float* alpha_p, float* beta_p, float* g_alpha_p, float* g_beta_p,
+                        void* stream) {
+  int64_t na = 0, nb = 0;
+  int rc = cv_bound_joint_sizes(h, layer, &na, &nb);
+  if (rc) return rc;
+  const JointLayer& q = h->joint->lay[layer - 2];
+  hipStream_t s = (hipStream_t)stream;
+  const std::pair<float*, const float*> cp[] = {{alpha_p, q.ash}, {g_alpha_p, q.gash}};
+  for (const auto& c : cp)
+    if (c.first && na) HIPCHK(hipMemcpyAsync(c.first, c.second, sizeof(float) * na, hipMemcpyDeviceToDevice, s));
+  const std::pair<float*, const float*> cb[] = {{beta_p, q.bsh}, {g_beta_p, q.gbsh}};
+  for (const auto& c : cb)
+    if (c.first && nb) HIPCHK(hipMemcpyAsync(c.first, c.second, sizeof(float) * nb, hipMemcpyDeviceToDevice, s));
+  return CV_OK;
 }
 
 int cv_bound_set_parts(cv_bound* h, int32_t nparts) {

@@ -69,6 +69,10 @@ struct Vars {
   int ldx;
   // l2-ball adjoint: eps / ||A(0)||_2 of each row (x* = x0 - l2s A(0)), or null
   const float* l2s;
+  // joint optimisation of intermediate bounds: where an unstable neuron's
+  // stored A is negative (upper chord), the adjoint's zbar there, in the
+  // neuron's alpha slot (the gradient of the bound in l and u needs it), or null
+  float* zchord;
   // The network's own forward pass at x* (upper bound) instead of the
   // adjoint's relaxed one: when set, the forward kernels apply the exact ReLU
   // and clear sat[row] where a pre-activation breaks a split of the row's
@@ -277,6 +281,7 @@ __device__ __forceinline__ float relax_fwd_value(const Batch& bt, const Vars& v,
     } else {
       g = 0.f;
       zh = fmaf(ch.x, zb, ch.y);
+      if (v.zchord) v.zchord[ai] = zb;
     }
     float an = al;
     if (v.adam && mom_ahead) an = adam_step(v.alpha_w, v.ma, v.va, ai, g, v.lr_a, v.bc1, v.bc2, 0.f, 1.f, al, mom.x, mom.y);

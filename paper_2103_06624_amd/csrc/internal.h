@@ -285,6 +285,38 @@ struct L2Final {
 void launch_finalize(const float* part, const float* perr, float scale, const float* psq, const L2Final& l2,
                      int n_slots, int n_used, int n_rows, float* lb, float* best, int first, hipStream_t s,
                      int* improved = nullptr);
+// joint optimisation of intermediate bounds (Sec. 3.3, Eq. opt_non_convex);
+// current bounds lcur / ucur and root bounds are [B][nd] (one row per subdomain)
+// status / chord of columns [0, nd_x) of a handle (row stride nd_x) from the
+// current bounds; status0 holds the handle's words at the root bounds
+void launch_joint_refresh(uint32_t* status, const uint32_t* status0, float2* chord, const float* lcur,
+                          const float* ucur, int B, int nd_x, int nd, hipStream_t s);
+// shared alpha' [B][2][uc_b] at CROWN's slope of each subdomain's root bounds
+void launch_joint_alpha_init(float* ash, const int* ulist, const int64_t* uoff, const Batch& bt, int B, int d,
+                             hipStream_t s);
+// layer (off, d) bounds from an intermediate pass's rows [B][2d] (lower
+// bounds of z, then of -z), clipped by the root bounds; ml / mu = 1 where the
+// gradient follows the computed bound (not looser than the root's by more
+// than a relative 1e-4)
+void launch_joint_clip(const float* lb, int d, int off, const float* lroot, const float* uroot, float* lcur,
+                       float* ucur, uint8_t* ml, uint8_t* mu, int B, int nd, hipStream_t s);
+// shared alpha' [B][2][uc_b] / beta' [nnz][2] copied to every row of their
+// side (rows k >= d hold the upper bounds) in the pass's own layouts
+void launch_joint_bcast(float* arow, const float* ash, float* brow, const float* bsh, const Batch& bt, int d,
+                        int64_t nnz, hipStream_t s);
+// shared gradients = per side, sum over its rows of w[row] x the row's gradient
+void launch_joint_reduce(float* gash, const float* garow, float* gbsh, const float* gbrow, const float* w,
+                         const Batch& bt, int B, int d, int64_t nnz, hipStream_t s);
+// dL, dU [B][nd] += d(sum_rows w g)/dl, /du at the unstable neurons of columns
+// [col0, nd_x) of a handle (w null: every row weighs 1), from its stored A
+// (acomp) and the adjoint's zbar at upper-chord neurons (zchord)
+void launch_joint_cot(float* dL, float* dU, const uint32_t* status, const float* acomp, const float* zchord,
+                      const float* w, const float* lcur, const float* ucur, const Batch& bt, int col0, int nd_x,
+                      int nd, int B, hipStream_t s);
+// row weights of layer (off, d)'s pass: dL where ml (lower rows), -dU where mu
+// (upper rows), else 0
+void launch_joint_weights(float* w, const float* dL, const float* dU, const uint8_t* ml, const uint8_t* mu, int B,
+                          int d, int off, int nd, hipStream_t s);
 // copy the variables of the rows flagged in improved into abest / bbest
 void launch_keep_best(const float* alpha, const float* beta, float* abest, float* bbest, const int* improved,
                       const Batch& bt, hipStream_t s);

@@ -239,3 +239,34 @@ def test_a_split_decides_its_neuron_even_against_its_bounds():
                        [torch.tensor([3.0], dtype=torch.float64)], [torch.tensor([-1])],
                        [torch.tensor([[0.5]], dtype=torch.float64)], [torch.tensor([[b]], dtype=torch.float64)])
         assert abs(float(g[0]) - b) <= 1e-15
+
+
+def test_shared_layouts_round_trip():
+    """The batch driver's mapping of the library's shared alpha' / beta'
+    layouts: writing each subdomain's starting variables into the flat
+    arrays and reading them back gives the same bound, bounds and gradient
+    as the starting variables themselves (mlp_deep, splits on several
+    layers)."""
+    from tests import cases
+    wl, lo, up, lo64, up64, orc = cases.small_case("mlp_deep")
+    a0 = orc.default_alpha_flat()
+    z = np.zeros(orc.nnz * orc.m)
+    L = len(orc.net64)
+    flat = {}
+    for i in range(2, L):
+        oa, ob = orc.joint_offsets(i)
+        ash, bsh = np.zeros(oa[-1]), np.zeros(ob[-1])
+        for b in range(orc.B):
+            us, ts = orc.joint_layout(b, i)
+            p = int(orc.dom_prop[b])
+            dflt = bc.default_alpha(orc.lo[p][us], orc.up[p][us])
+            ash[oa[b]:oa[b + 1]] = np.concatenate([dflt, dflt])
+        flat[i] = (ash, bsh)
+    for b in (0, 7, 31):
+        g1, l1, u1, gr1 = orc.joint_eval(b, a0, z, orc.joint_vars(b, flat), grad=True)
+        g2, l2, u2, gr2 = orc.joint_eval(b, a0, z, orc.joint_start(b), grad=True)
+        assert np.array_equal(g1, g2) and np.array_equal(l1, l2) and np.array_equal(u1, u2)
+        for i in gr1:
+            assert np.array_equal(gr1[i][0], gr2[i][0]) and np.array_equal(gr1[i][1], gr2[i][1])
+            assert gr1[i][0].shape[0] == 2 * orc.joint_layout(b, i)[0].shape[0]
+        assert any(np.abs(gr1[i][0]).max(initial=0) > 0 for i in gr1)
