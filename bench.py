@@ -314,6 +314,45 @@ def bab_context(wl, lo, up, args):
             "full_batch_domains_per_s": round(sum(n for n, _ in full) / sum(s for _, s in full), 1) if full else None}
 
 
+def joint_context(wl, lo, up, args):
+    """Joint optimisation of intermediate bounds (Eq. opt_non_convex) at the
+    root of every property (one unsplit subdomain each): seconds and bounds
+    of 20 joint iterations beside the plain optimiser's on the same
+    subdomains, and how much the intermediate bounds narrowed."""
+    import numpy as np
+    import torch
+
+    from paper_2103_06624_amd.api import BoundProblem
+
+    P = wl.n_props
+    pb = BoundProblem(wl.net.layers, wl.x_lo, wl.x_hi, wl.C, lo, up, np.arange(P, dtype=np.int32),
+                      np.zeros(P + 1, np.int64), [], [], [])
+    opt = dict(iters=args.iters, lr_alpha=args.lr_alpha, lr_beta=args.lr_beta, decay=args.decay)
+    a, b = pb.alpha_init(), pb.zeros_beta()
+    pb.optimize_joint(a.clone(), b.clone(), **opt)  # builds the passes
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    best_j, _, lo_j, up_j = pb.optimize_joint(a.clone(), b.clone(), bounds=True, **opt)
+    torch.cuda.synchronize()
+    t_j = time.perf_counter() - t0
+    pb.optimize(a.clone(), b.clone(), **opt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    best_p, _ = pb.optimize(a.clone(), b.clone(), **opt)
+    torch.cuda.synchronize()
+    t_p = time.perf_counter() - t0
+    gain = (best_j - best_p).cpu().numpy()
+    d1 = wl.net.layers[0].d_out
+    w_root = (up - lo)[:, d1:]
+    w_j = (up_j - lo_j).cpu().numpy()[:, d1:]
+    pb.close()
+    return {"subdomains": P, "spec_rows": int(wl.C.shape[1]), "seconds": round(t_j, 4),
+            "plain_seconds": round(t_p, 4), "mean_bound_joint": float(best_j.mean().item()),
+            "mean_bound_plain": float(best_p.mean().item()), "mean_gain": float(gain.mean()),
+            "rows_improved": int((gain > 0).sum()), "rows": int(gain.size),
+            "intermediate_width_ratio": float(np.mean(w_j / np.maximum(w_root, 1e-12)))}
+
+
 def cpu_baseline(name, wl, lo, up, sp, gpu, seconds, seconds_1t, iters, lr_a, lr_b, decay, n_sound=64):
     """The FP64 oracle on this host, fed the very inputs the GPU path saw (the
     workload, the GPU's own float32 root bounds and split sets):
@@ -707,6 +746,10 @@ def main():
                                         "rows_improved": int((lb_o > lb_c).sum().item()),
                                         "mean_bound_gain": float((lb_o - lb_c).mean().item())}
         pb_o.close()
+
+        # ---- joint optimisation of intermediate bounds at every property's root
+        log("[bench] joint optimisation of intermediate bounds")
+        ctx["joint_intermediate_bounds"] = joint_context(wl, lo, up, args)
 
         # ---- branch and bound (Alg. 1) on property 0 of the workload, each
         # row's objective offset to the middle of its root [lower, upper]

@@ -265,6 +265,9 @@ __device__ __forceinline__ float xstar(bool pos, bool neg, float xl, float xu) {
 // read ahead by the caller together with al (its current value).  var_new,
 // when set, receives the neuron's variable after this step (alpha of an
 // unstable neuron, beta of a split one).
+// kZchord = false compiles the zchord store out (kernels that never run in a
+// pass of the joint optimisation, where registers are tight).
+template <bool kZchord = true>
 __device__ __forceinline__ float relax_fwd_value(const Batch& bt, const Vars& v, const RowInfo& ri, uint32_t rec,
                                                  float2 ch, float a_st, float al, int64_t pc, float zb,
                                                  bool mom_ahead = false, float2 mom = float2{0.f, 0.f},
@@ -281,7 +284,7 @@ __device__ __forceinline__ float relax_fwd_value(const Batch& bt, const Vars& v,
     } else {
       g = 0.f;
       zh = fmaf(ch.x, zb, ch.y);
-      if (v.zchord) v.zchord[ai] = zb;
+      if (kZchord && v.zchord) v.zchord[ai] = zb;
     }
     float an = al;
     if (v.adam && mom_ahead) an = adam_step(v.alpha_w, v.ma, v.va, ai, g, v.lr_a, v.bc1, v.bc2, 0.f, 1.f, al, mom.x, mom.y);

@@ -626,8 +626,8 @@ __global__ __launch_bounds__(kSdThreads, (conv_sd_occupancy<MODE, NJ, NI>())) vo
             e.out[(int64_t)row * e.ldo + j] = true_relu(r, zb, v.sat + row);
             continue;
           }
-          const float zh = relax_fwd_value(bt, v, ri, r, ch[u], x1[u], x2[u], pc0 + j, zb, v.adam != 0,
-                                           make_float2(x3[u], x4[u]));
+          const float zh = relax_fwd_value<false>(bt, v, ri, r, ch[u], x1[u], x2[u], pc0 + j, zb, v.adam != 0,
+                                                  make_float2(x3[u], x4[u]));
           if (!last) e.out[(int64_t)row * e.ldo + j] = zh;
         }
       }
@@ -787,7 +787,10 @@ int dispatch(const ConvArgs& a, hipStream_t st) {
   // plan (a plan built for one mode may be launched in another: over an l2
   // ball the first layer's adjoint reads A(0) rows instead of sign planes),
   // else the row-major one
-  if (a.pl.sd && a.pl.nj > 0 && (a.pl.nt == 1 || a.pl.nt == 2)) {
+  // (a pass that stores the adjoint's zbar at upper-chord neurons takes the
+  // row-major kernel: the subdomain-major one compiles that store out)
+  const bool sd_ok = !(MODE >= kFwdX && a.v.zchord);
+  if (sd_ok && a.pl.sd && a.pl.nj > 0 && (a.pl.nt == 1 || a.pl.nt == 2)) {
     const int r = a.pl.nt == 1 ? (a.pl.wg ? launch_sd<MODE, 1, true>(a, st) : launch_sd<MODE, 1, false>(a, st))
                                : (a.pl.wg ? launch_sd<MODE, 2, true>(a, st) : launch_sd<MODE, 2, false>(a, st));
     if (r == 0) return 0;
