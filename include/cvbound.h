@@ -238,6 +238,24 @@ int cv_bound_autotune(cv_bound *h, void *stream);
  * up to float32 summation order. */
 int cv_bound_set_plan(cv_bound *h, int32_t chain_bwd, int32_t chain_fwd);
 
+/* A new batch of subdomains for the handle (Alg. 1: each round bounds the
+ * children of the subdomains it split), over the same network, properties,
+ * specifications, root bounds, input sets and modes (sound mode, l_p balls,
+ * forced tilings and conv variants, the sub-batch count set by
+ * cv_bound_set_parts).  Arguments as cv_bound_init's n_dom .. split_side
+ * (host pointers, copied; the same validation: CV_ESPLIT / CV_EINVAL leave
+ * the handle's previous batch in place).  Batch-sized device buffers are
+ * reused when the new batch is no larger than one the handle has held, else
+ * reallocated with a quarter to spare (CV_ENOMEM then leaves the handle
+ * without a batch: update it again or destroy it).  The alpha and beta
+ * layouts follow the new batch (query cv_bound_sizes); the optimiser's graph
+ * and any joint-optimisation state are dropped (a later
+ * cv_bound_optimize_joint rebuilds it).  Synchronous on `stream` (it waits
+ * for the device before it frees buffers). */
+int cv_bound_update(cv_bound *h, int32_t n_dom, const int32_t *dom_prop, const int64_t *split_ptr,
+                    const int32_t *split_layer, const int32_t *split_neuron, const int8_t *split_side,
+                    void *stream);
+
 /* Joint optimisation of intermediate-layer bounds (Sec. 3.3, Eq.
  * opt_non_convex).  As cv_bound_optimize, except that every subdomain's
  * pre-activation bounds of ReLU layers 2..L-1 are recomputed in each

@@ -95,6 +95,25 @@ class BoundProblem:
         B.check(B.cv_bound_sizes(h, ctypes.byref(na), ctypes.byref(nb), ctypes.byref(nr)))
         self.n_alpha, self.n_beta, self.n_rows = na.value, nb.value, nr.value
 
+    def update(self, dom_prop, split_ptr, split_layer, split_neuron, split_side):
+        """A new batch of subdomains on this handle (cv_bound_update): same
+        network, properties, specifications and root bounds; the alpha / beta
+        layouts and sizes follow the new batch."""
+        dom_prop = np.ascontiguousarray(dom_prop, np.int32)
+        split_ptr = np.ascontiguousarray(split_ptr, np.int64)
+        split_layer = np.ascontiguousarray(split_layer, np.int32)
+        split_neuron = np.ascontiguousarray(split_neuron, np.int32)
+        split_side = np.ascontiguousarray(split_side, np.int8)
+        B.check(B.cv_bound_update(self.h, dom_prop.shape[0], _ptr(dom_prop), _ptr(split_ptr), _ptr(split_layer),
+                                  _ptr(split_neuron), _ptr(split_side), _stream()))
+        self.B = dom_prop.shape[0]
+        self._dom_prop = dom_prop
+        self._split_ptr = split_ptr
+        self._maps = None
+        na, nb, nr = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        B.check(B.cv_bound_sizes(self.h, ctypes.byref(na), ctypes.byref(nb), ctypes.byref(nr)))
+        self.n_alpha, self.n_beta, self.n_rows = na.value, nb.value, nr.value
+
     @classmethod
     def from_workload(cls, wl, lo, up, splits=None):
         sp = splits if splits is not None else wl.splits

@@ -65,6 +65,7 @@ SIGNATURES = {
     "cv_bound_joint_sizes": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
                                             ctypes.POINTER(ctypes.c_int64)]),
     "cv_bound_joint_vars": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp]),
+    "cv_bound_update": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp]),
     "cv_bound_autotune": (ctypes.c_int, [_vp, _vp]),
     "cv_bound_set_plan": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32]),
     "cv_bound_set_parts": (ctypes.c_int, [_vp, ctypes.c_int32]),
@@ -139,6 +140,7 @@ cv_bound_set_input_lp = _fn("cv_bound_set_input_lp")
 cv_bound_optimize_joint = _fn("cv_bound_optimize_joint")
 cv_bound_joint_sizes = _fn("cv_bound_joint_sizes")
 cv_bound_joint_vars = _fn("cv_bound_joint_vars")
+cv_bound_update = _fn("cv_bound_update")
 cv_bound_profile = _fn("cv_bound_profile")
 cv_bound_destroy = _fn("cv_bound_destroy")
 cv_last_error = _fn("cv_last_error")

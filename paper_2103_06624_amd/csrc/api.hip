@@ -49,8 +49,10 @@ inline int r32(int d) { return (d + 31) & ~31; }
 
 struct DevMem {
   std::vector<void*> ptrs;
-  ~DevMem() {
+  ~DevMem() { clear(); }
+  void clear() {
     for (void* p : ptrs) (void)hipFree(p);
+    ptrs.clear();
   }
   template <typename T>
   int alloc(T** out, size_t count) {
@@ -138,6 +140,14 @@ struct GraphKey {
 
 struct cv_bound {
   DevMem mem;
+  // buffers whose size depends on the subdomain batch (rows, alpha entries,
+  // splits), sized by capacities that only grow: cv_bound_update reuses them
+  // for any batch no larger than one the handle has held
+  DevMem bm;
+  struct Cap {
+    int B = 0;
+    int64_t R = 0, na = 0, nnz = 0;
+  } bcap;
   int dev = 0;  // the device the handle was built on
   int L = 0;  // layers (ReLU after 1..L-1)
   std::vector<DevLayer> layers;
@@ -153,6 +163,16 @@ struct cv_bound {
   std::vector<int> h_cidx;  // [P, nd]
   std::vector<int> h_ucount;
   std::vector<double> unst_rows_per_layer;  // sum over rows of unstable neurons per ReLU layer
+  // root classes per property (kind | index in the unstable list) [P, nd], and
+  // the unstable count per property and ReLU layer: what a new batch's splits
+  // are checked against and its tables built from
+  std::vector<uint32_t> h_kind;
+  std::vector<std::vector<int>> h_ucount_layer;
+  uint32_t* d_kind = nullptr;
+  int *d_split_dom = nullptr, *d_split_col = nullptr;
+  int8_t* d_side = nullptr;
+  int forced_tiling = -1, forced_conv = -1;  // cv_bound_set_tiling / cv_bound_set_conv_variant
+  int parts_req = 0;  // cv_bound_set_parts (0: two sub-batches from kPartsMinRows rows on)
   // device arrays
   Batch bt{};
   float* CW = nullptr;
@@ -675,6 +695,164 @@ struct Spec {
   bool identity = false;
 };
 
+// Every buffer of the batch pool dropped (their contents are per batch).
+void release_batch(cv_bound* h) {
+  h->bm.clear();
+  h->act[0] = h->act[1] = nullptr;
+  h->act64[0] = h->act64[1] = nullptr;
+  for (float** p : {&h->part, &h->acomp, &h->xdense, &h->g_alpha, &h->g_beta, &h->adam, &h->perr, &h->gbest,
+                    &h->abest, &h->bbest, &h->psq, &h->l2s, &h->zchord})
+    *p = nullptr;
+  for (double** p : {&h->part64, &h->perr64, &h->psq64}) *p = nullptr;
+  h->xpos = h->xneg = nullptr;
+  h->improved = nullptr;
+  h->d_split_dom = h->d_split_col = nullptr;
+  h->d_side = nullptr;
+  h->bt.prop = nullptr;
+  h->bt.aoff = h->bt.rbase = h->bt.sptr = nullptr;
+  h->bt.status = nullptr;
+  h->bcap = cv_bound::Cap{};
+}
+
+// A subdomain batch checked on the host (Sec. 3.4: independent subdomains
+// bounded together): splits against each property's root-unstable neurons,
+// and the tables the device needs.  Touches no device state.
+struct BatchPlan {
+  int B = 0;
+  int64_t R = 0, nnz = 0, n_alpha = 0;
+  const int32_t* dom_prop = nullptr;
+  const int64_t* split_ptr = nullptr;
+  const int8_t* split_side = nullptr;
+  std::vector<int> split_dom, split_col;
+  std::vector<int64_t> aoff;
+  std::vector<double> unst;
+};
+
+int check_batch(const cv_bound* h, int B, const int32_t* dom_prop, const int64_t* split_ptr,
+                const int32_t* split_layer, const int32_t* split_neuron, const int8_t* split_side, BatchPlan& bp) {
+  const int P = h->P, nd = h->nd, m = h->m, n_layers = h->L;
+  if (B < 0) return fail(CV_EINVAL, "n_dom must be >= 0");
+  if (!split_ptr || (!dom_prop && B > 0)) return fail(CV_EINVAL, "null input pointer");
+  const int64_t R = (int64_t)B * m;
+  if (R > (1ll << 30)) return fail(CV_EINVAL, "too many rows (%lld)", (long long)R);
+  if (split_ptr[0] != 0) return fail(CV_ESPLIT, "split_ptr[0] must be 0");
+  const int64_t nnz = B > 0 ? split_ptr[B] : 0;
+  if (nnz > 0 && (!split_layer || !split_neuron || !split_side)) return fail(CV_EINVAL, "null split arrays");
+  bp.split_dom.assign(nnz, 0);
+  bp.split_col.assign(nnz, 0);
+  bp.aoff.assign(B + 1, 0);
+  bp.unst.assign(std::max(1, n_layers - 1), 0.0);
+  std::vector<int> seen(nd, -1);
+  for (int b = 0; b < B; ++b) {
+    const int p = dom_prop[b];
+    if (p < 0 || p >= P) return fail(CV_EINVAL, "subdomain %d: property %d out of range", b, p);
+    bp.aoff[b + 1] = bp.aoff[b] + (int64_t)m * h->h_ucount[p];
+    for (int li = 0; li + 1 < n_layers; ++li) bp.unst[li] += (double)m * h->h_ucount_layer[p][li];
+    const int64_t s0 = split_ptr[b], s1 = split_ptr[b + 1];
+    if (s1 < s0) return fail(CV_ESPLIT, "subdomain %d: split_ptr decreases", b);
+    if (s1 >= kMaxSplits) return fail(CV_ESPLIT, "more than %lld splits in total", (long long)kMaxSplits - 1);
+    for (int64_t t = s0; t < s1; ++t) {
+      const int ly = split_layer[t], nr = split_neuron[t];
+      if (ly < 1 || ly >= n_layers) return fail(CV_ESPLIT, "split %lld: layer %d out of range", (long long)t, ly);
+      if (nr < 0 || nr >= h->dims[ly]) return fail(CV_ESPLIT, "split %lld: neuron %d out of range", (long long)t, nr);
+      if (split_side[t] != 1 && split_side[t] != -1)
+        return fail(CV_ESPLIT, "split %lld: side must be +1 or -1", (long long)t);
+      const int col = h->offs[ly - 1] + nr;
+      if ((h->h_kind[(size_t)p * nd + col] & kKindMask) != kUnstable)
+        return fail(CV_ESPLIT, "split %lld: neuron (%d,%d) is not root-unstable", (long long)t, ly, nr);
+      if (seen[col] == b) return fail(CV_ESPLIT, "subdomain %d splits neuron (%d,%d) twice", b, ly, nr);
+      seen[col] = b;
+      bp.split_dom[t] = b;
+      bp.split_col[t] = col;
+    }
+  }
+  bp.B = B;
+  bp.R = R;
+  bp.nnz = nnz;
+  bp.n_alpha = bp.aoff[B];
+  bp.dom_prop = dom_prop;
+  bp.split_ptr = split_ptr;
+  bp.split_side = split_side;
+  return CV_OK;
+}
+
+// The checked batch made h's (the caller's arrays must still be live): row and
+// alpha tables, CSR split arrays, status words.  Batch-sized buffers live in
+// h->bm; when the batch needs more than the pool holds the pool is
+// reallocated, sized for this batch (grow: with a quarter to spare, for
+// batches that grow round by round), else reused.
+int set_batch(cv_bound* h, const BatchPlan& bp, bool grow, hipStream_t s) {
+  const int nd = h->nd, m = h->m, n_layers = h->L;
+  const int B = bp.B;
+  const int64_t R = bp.R, nnz = bp.nnz;
+  const int32_t* dom_prop = bp.dom_prop;
+  const int64_t* split_ptr = bp.split_ptr;
+  const int8_t* split_side = bp.split_side;
+  const std::vector<int64_t>& aoff = bp.aoff;
+  const std::vector<int>& split_dom = bp.split_dom;
+  const std::vector<int>& split_col = bp.split_col;
+  // ---- commit
+  h->B = B;
+  h->R = (int)R;
+  h->nnz = nnz;
+  h->h_prop.assign(dom_prop, dom_prop + B);
+  h->h_aoff = aoff;
+  h->n_alpha = bp.n_alpha;
+  h->unst_rows_per_layer = bp.unst;
+  cv_bound::Cap& c = h->bcap;
+  if (B > c.B || R > c.R || h->n_alpha > c.na || nnz > c.nnz || !h->bt.status) {
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipDeviceSynchronize());  // every stream of the handle is done with the old buffers
+    release_batch(h);
+    auto sz = [&](int64_t n) { return grow ? n + n / 4 : n; };
+    c.B = (int)sz(B);
+    c.R = sz(R);
+    c.na = sz(h->n_alpha);
+    c.nnz = sz(nnz);
+    DevMem& M = h->bm;
+    int rc;
+    int *d_prop;
+    int64_t *d_aoff, *d_sptr, *d_rbase;
+    uint32_t* d_status;
+    if ((rc = M.alloc(&d_prop, c.B)) || (rc = M.alloc(&d_aoff, c.B + 1)) || (rc = M.alloc(&d_sptr, c.B + 1)) ||
+        (rc = M.alloc(&d_rbase, c.R)) || (rc = M.alloc(&h->d_split_dom, c.nnz)) ||
+        (rc = M.alloc(&h->d_split_col, c.nnz)) || (rc = M.alloc(&h->d_side, c.nnz)) ||
+        (rc = M.alloc(&d_status, (size_t)c.B * nd)) || (rc = M.alloc(&h->part, (size_t)std::max<int64_t>(1, c.R) * h->n_slots)))
+      return rc;
+    if (n_layers >= 2 && ((rc = M.alloc(&h->act[0], (size_t)c.R * h->ldact)) ||
+                          (rc = M.alloc(&h->act[1], (size_t)c.R * h->ldact))))
+      return rc;
+    h->bt.prop = d_prop;
+    h->bt.aoff = d_aoff;
+    h->bt.sptr = d_sptr;
+    h->bt.rbase = d_rbase;
+    h->bt.status = d_status;
+  }
+  std::vector<int64_t> rbase((size_t)R);
+  for (int b = 0; b < B; ++b)
+    for (int k = 0; k < m; ++k) rbase[(size_t)b * m + k] = aoff[b] + (int64_t)k * h->h_ucount[dom_prop[b]];
+  // blocking copies: the host arrays may be the caller's temporaries
+  auto up = [&](void* dst, const void* src, size_t bytes) -> int {
+    if (bytes) HIPCHK(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
+    return CV_OK;
+  };
+  int rc;
+  if ((rc = up(const_cast<int*>(h->bt.prop), dom_prop, sizeof(int) * B)) ||
+      (rc = up(const_cast<int64_t*>(h->bt.aoff), aoff.data(), sizeof(int64_t) * (B + 1))) ||
+      (rc = up(const_cast<int64_t*>(h->bt.sptr), split_ptr, sizeof(int64_t) * (B + 1))) ||
+      (rc = up(const_cast<int64_t*>(h->bt.rbase), rbase.data(), sizeof(int64_t) * R)) ||
+      (rc = up(h->d_split_dom, split_dom.data(), sizeof(int) * nnz)) ||
+      (rc = up(h->d_split_col, split_col.data(), sizeof(int) * nnz)) ||
+      (rc = up(h->d_side, split_side, sizeof(int8_t) * nnz)))
+    return rc;
+  uint32_t* status = const_cast<uint32_t*>(h->bt.status);
+  launch_status_fill(status, h->d_kind, h->bt.prop, B, nd, s);
+  launch_status_split(status, h->d_split_dom, h->d_split_col, h->d_side, nnz, nd, s);
+  HIPCHK(hipGetLastError());
+  h->bt.n_rows = h->R;
+  return CV_OK;
+}
+
 int build(cv_bound* h, const cv_layer* layers, int n_layers, int P, const float* x_lo, const float* x_hi, int m,
           Spec spec, const float* l, const float* u, int B, const int32_t* dom_prop, const int64_t* split_ptr,
           const int32_t* split_layer, const int32_t* split_neuron, const int8_t* split_side, hipStream_t s) {
@@ -686,10 +864,6 @@ int build(cv_bound* h, const cv_layer* layers, int n_layers, int P, const float*
   h->L = n_layers;
   h->P = P;
   h->m = m;
-  h->B = B;
-  const int64_t R = (int64_t)B * m;
-  if (R > (1ll << 30)) return fail(CV_EINVAL, "too many rows (%lld)", (long long)R);
-  h->R = (int)R;
   h->d0 = h->dims[0];
   h->w64 = (h->d0 + 63) / 64;
   h->offs.assign(std::max(1, n_layers), 0);
@@ -709,12 +883,12 @@ int build(cv_bound* h, const cv_layer* layers, int n_layers, int P, const float*
   if (spec.C && !finite_all(spec.C, (int64_t)P * m * h->dims[n_layers])) return fail(CV_EINVAL, "non-finite C");
 
   // ---- per-property neuron classes (Eq. definition_D: l >= 0 active, u <= 0 inactive)
-  std::vector<uint32_t> kind((size_t)P * nd);
+  h->h_kind.assign((size_t)P * nd, 0u);
   h->h_cidx.assign((size_t)P * nd, -1);
   h->h_ucount.assign(P, 0);
   std::vector<int> ulist;
   std::vector<int64_t> uoff(P + 1, 0);
-  std::vector<std::vector<int>> ucount_layer(P, std::vector<int>(std::max(1, n_layers - 1), 0));
+  h->h_ucount_layer.assign(P, std::vector<int>(std::max(1, n_layers - 1), 0));
   for (int p = 0; p < P; ++p) {
     uoff[p] = (int64_t)ulist.size();
     for (int j = 0; j < nd; ++j) {
@@ -725,92 +899,42 @@ int build(cv_bound* h, const cv_layer* layers, int n_layers, int P, const float*
         h->h_cidx[(size_t)p * nd + j] = h->h_ucount[p]++;
         ulist.push_back(j);
         int li = (int)(std::upper_bound(h->offs.begin(), h->offs.begin() + (n_layers - 1), j) - h->offs.begin()) - 1;
-        ucount_layer[p][li]++;
+        h->h_ucount_layer[p][li]++;
       }
-      kind[(size_t)p * nd + j] = k;
+      h->h_kind[(size_t)p * nd + j] = k;
     }
   }
   uoff[P] = (int64_t)ulist.size();
+  // the subdomains and their splits, checked before any device work
+  BatchPlan bp;
+  if ((rc = check_batch(h, B, dom_prop, split_ptr, split_layer, split_neuron, split_side, bp))) return rc;
 
-  // ---- subdomains and splits
-  if (split_ptr[0] != 0) return fail(CV_ESPLIT, "split_ptr[0] must be 0");
-  h->nnz = B > 0 ? split_ptr[B] : 0;
-  std::vector<int> split_dom(h->nnz), split_col(h->nnz);
-  h->h_prop.assign(dom_prop, dom_prop + B);
-  h->h_aoff.assign(B + 1, 0);
-  h->unst_rows_per_layer.assign(std::max(1, n_layers - 1), 0.0);
-  std::vector<int> seen(nd, -1);
-  for (int b = 0; b < B; ++b) {
-    const int p = dom_prop[b];
-    if (p < 0 || p >= P) return fail(CV_EINVAL, "subdomain %d: property %d out of range", b, p);
-    h->h_aoff[b + 1] = h->h_aoff[b] + (int64_t)m * h->h_ucount[p];
-    for (int li = 0; li + 1 < n_layers; ++li) h->unst_rows_per_layer[li] += (double)m * ucount_layer[p][li];
-    const int64_t s0 = split_ptr[b], s1 = split_ptr[b + 1];
-    if (s1 < s0) return fail(CV_ESPLIT, "subdomain %d: split_ptr decreases", b);
-    if (s1 >= kMaxSplits) return fail(CV_ESPLIT, "more than %lld splits in total", (long long)kMaxSplits - 1);
-    for (int64_t t = s0; t < s1; ++t) {
-      const int ly = split_layer[t], nr = split_neuron[t];
-      if (ly < 1 || ly >= n_layers) return fail(CV_ESPLIT, "split %lld: layer %d out of range", (long long)t, ly);
-      if (nr < 0 || nr >= h->dims[ly]) return fail(CV_ESPLIT, "split %lld: neuron %d out of range", (long long)t, nr);
-      if (split_side[t] != 1 && split_side[t] != -1)
-        return fail(CV_ESPLIT, "split %lld: side must be +1 or -1", (long long)t);
-      const int col = h->offs[ly - 1] + nr;
-      if ((kind[(size_t)p * nd + col] & kKindMask) != kUnstable)
-        return fail(CV_ESPLIT, "split %lld: neuron (%d,%d) is not root-unstable", (long long)t, ly, nr);
-      if (seen[col] == b) return fail(CV_ESPLIT, "subdomain %d splits neuron (%d,%d) twice", b, ly, nr);
-      seen[col] = b;
-      split_dom[t] = b;
-      split_col[t] = col;
-    }
-  }
-  h->n_alpha = h->h_aoff[B];
-
-  // ---- device copies
+  // ---- device copies of the network and of the per-property tables
   rc = upload_layers(h, layers, n_layers, s);
   if (rc) return rc;
   DevMem& M = h->mem;
-  int *d_prop, *d_ucount, *d_cidx, *d_split_dom, *d_split_col;
-  int64_t *d_aoff, *d_sptr, *d_rbase;
-  uint32_t *d_kind, *d_status;
-  std::vector<int64_t> rbase((size_t)B * m);
-  for (int b = 0; b < B; ++b)
-    for (int k = 0; k < m; ++k) rbase[(size_t)b * m + k] = h->h_aoff[b] + (int64_t)k * h->h_ucount[h->h_prop[b]];
-  int8_t* d_side;
+  int *d_ucount, *d_cidx;
   float *d_l, *d_u, *d_xlo, *d_xhi, *d_adef;
   float2* d_chord;
-  if ((rc = M.upload(&d_prop, h->h_prop.data(), B, s)) || (rc = M.upload(&d_aoff, h->h_aoff.data(), B + 1, s)) ||
-      (rc = M.upload(&d_rbase, rbase.data(), rbase.size(), s)) ||
-      (rc = M.upload(&d_ucount, h->h_ucount.data(), P, s)) || (rc = M.upload(&d_sptr, split_ptr, B + 1, s)) ||
+  if ((rc = M.upload(&d_ucount, h->h_ucount.data(), P, s)) ||
       (rc = M.upload(&d_cidx, h->h_cidx.data(), (size_t)P * nd, s)) ||
-      (rc = M.upload(&d_kind, kind.data(), (size_t)P * nd, s)) ||
-      (rc = M.upload(&d_split_dom, split_dom.data(), h->nnz, s)) ||
-      (rc = M.upload(&d_split_col, split_col.data(), h->nnz, s)) ||
-      (rc = M.upload(&d_side, split_side ? split_side : (const int8_t*)nullptr, split_side ? h->nnz : 0, s)) ||
+      (rc = M.upload(&h->d_kind, h->h_kind.data(), (size_t)P * nd, s)) ||
       (rc = M.upload(&d_l, l, l ? (size_t)P * nd : 0, s)) || (rc = M.upload(&d_u, u, u ? (size_t)P * nd : 0, s)) ||
       (rc = M.upload(&d_xlo, x_lo, (size_t)P * h->d0, s)) || (rc = M.upload(&d_xhi, x_hi, (size_t)P * h->d0, s)) ||
       (rc = M.alloc(&d_adef, (size_t)P * nd)) || (rc = M.alloc(&d_chord, (size_t)P * nd)) ||
-      (rc = M.alloc(&d_status, (size_t)B * nd)) || (rc = M.upload(&h->ulist, ulist.data(), ulist.size(), s)) ||
-      (rc = M.upload(&h->uoff, uoff.data(), P + 1, s)))
+      (rc = M.upload(&h->ulist, ulist.data(), ulist.size(), s)) || (rc = M.upload(&h->uoff, uoff.data(), P + 1, s)))
     return rc;
   h->dl = d_l;
   h->du = d_u;
   launch_prep_chord(d_l, d_u, d_chord, d_adef, (int64_t)P * nd, s);
-  launch_status_fill(d_status, d_kind, d_prop, B, nd, s);
-  launch_status_split(d_status, d_split_dom, d_split_col, d_side, h->nnz, nd, s);
   HIPCHK(hipGetLastError());
 
   Batch& bt = h->bt;
   bt.m = m;
-  bt.n_rows = h->R;
   bt.nd = nd;
   bt.d0 = h->d0;
   bt.w64 = h->w64;
-  bt.prop = d_prop;
-  bt.aoff = d_aoff;
-  bt.rbase = d_rbase;
   bt.ucount = d_ucount;
-  bt.sptr = d_sptr;
-  bt.status = d_status;
   bt.cidx = d_cidx;
   bt.chord = d_chord;
   bt.adef = d_adef;
@@ -855,11 +979,8 @@ int build(cv_bound* h, const cv_layer* layers, int n_layers, int P, const float*
     const DevLayer& ly = h->layers[i - 1];
     h->n_slots += ly.type == CV_LAYER_DENSE ? (h->dims[i - 1] + 31) / 32 : 1;
   }
-  if (n_layers >= 2) {
-    if ((rc = M.alloc(&h->act[0], (size_t)h->R * h->ldact)) || (rc = M.alloc(&h->act[1], (size_t)h->R * h->ldact)))
-      return rc;
-  }
-  if ((rc = M.alloc(&h->part, (size_t)std::max(1, h->R) * h->n_slots))) return rc;
+  // ---- the subdomains: splits checked, row tables, status words, buffers
+  if ((rc = set_batch(h, bp, false, s))) return rc;
   assign_tiles(h, -1);
   assign_conv_variants(h, -1);
   // dense layers fused by the chain kernels (LDS-resident widths up to kChainWidth)
@@ -880,16 +1001,18 @@ int build(cv_bound* h, const cv_layer* layers, int n_layers, int P, const float*
   return CV_OK;
 }
 
+// (batch-sized buffers come from the batch pool at its capacities)
 int ensure_grad(cv_bound* h) {
   if (h->acomp) return CV_OK;
   int rc;
-  if ((rc = h->mem.alloc(&h->acomp, h->n_alpha)) || (rc = h->mem.alloc(&h->xpos, (size_t)h->R * h->w64)) ||
-      (rc = h->mem.alloc(&h->xneg, (size_t)h->R * h->w64)))
+  const cv_bound::Cap& c = h->bcap;
+  if ((rc = h->bm.alloc(&h->acomp, c.na)) || (rc = h->bm.alloc(&h->xpos, (size_t)c.R * h->w64)) ||
+      (rc = h->bm.alloc(&h->xneg, (size_t)c.R * h->w64)))
     return rc;
   if (h->layers[0].type == CV_LAYER_DENSE && !h->xdense) {
     // the first adjoint step reads x* as a plain GEMM operand
     h->ldx = r4(h->d0);
-    if ((rc = h->mem.alloc(&h->xdense, (size_t)h->R * h->ldx))) return rc;
+    if ((rc = h->bm.alloc(&h->xdense, (size_t)c.R * h->ldx))) return rc;
   }
   return CV_OK;
 }
@@ -898,10 +1021,26 @@ int ensure_opt(cv_bound* h) {
   int rc = ensure_grad(h);
   if (rc) return rc;
   if (h->g_alpha) return CV_OK;
-  const int64_t nb = h->nnz * h->m;
-  if ((rc = h->mem.alloc(&h->g_alpha, h->n_alpha)) || (rc = h->mem.alloc(&h->g_beta, nb)) ||
-      (rc = h->mem.alloc(&h->adam, 2 * h->n_alpha + 2 * nb)))
+  const cv_bound::Cap& c = h->bcap;
+  const int64_t nb = c.nnz * h->m;
+  if ((rc = h->bm.alloc(&h->g_alpha, c.na)) || (rc = h->bm.alloc(&h->g_beta, nb)) ||
+      (rc = h->bm.alloc(&h->adam, 2 * c.na + 2 * nb)))
     return rc;
+  return CV_OK;
+}
+
+// The l_p-ball buffers of a handle: per-row |A(0)|^q partials and minimiser
+// scales, and the minimiser's direction kept densely.
+int ensure_ball(cv_bound* q) {
+  int rc;
+  const cv_bound::Cap& c = q->bcap;
+  if (!q->psq && ((rc = q->bm.alloc(&q->psq, (size_t)q->n_slots * std::max<int64_t>(1, c.R))) ||
+                  (rc = q->bm.alloc(&q->l2s, std::max<int64_t>(1, c.R)))))
+    return rc;
+  if (!q->xdense) {
+    q->ldx = r4(q->d0);
+    if ((rc = q->bm.alloc(&q->xdense, (size_t)std::max<int64_t>(1, c.R) * q->ldx))) return rc;
+  }
   return CV_OK;
 }
 
@@ -1019,6 +1158,25 @@ void sound_weights(const cv_bound* h, const cv_layer* layers, const float* x_lo,
                    const float* u, const float* C, bool identity, const float* l2x0, const float* l2eps, double up,
                    int chain, SoundWeights& out);
 
+// Sound mode's batch-sized buffers (float64 rows and partials, the optimiser's
+// best-iterate copies), from the batch pool at its capacities.
+int ensure_sound_batch(cv_bound* h) {
+  if (h->perr) return CV_OK;
+  const cv_bound::Cap& c = h->bcap;
+  const int64_t R1 = std::max<int64_t>(1, c.R);
+  const int L = h->L;
+  int rc;
+  if ((rc = h->bm.alloc(&h->perr, (size_t)R1 * h->n_slots)) ||
+      (rc = h->bm.alloc(&h->act64[0], (size_t)R1 * h->ldact)) ||
+      (rc = h->bm.alloc(&h->act64[1], (size_t)R1 * h->ldact)) || (rc = h->bm.alloc(&h->part64, (size_t)R1 * L)) ||
+      (rc = h->bm.alloc(&h->perr64, (size_t)R1 * L)) || (rc = h->bm.alloc(&h->psq64, (size_t)R1 * L)) ||
+      (rc = h->bm.alloc(&h->gbest, (size_t)R1)) || (rc = h->bm.alloc(&h->improved, (size_t)R1)) ||
+      (rc = h->bm.alloc(&h->abest, (size_t)std::max<int64_t>(1, c.na))) ||
+      (rc = h->bm.alloc(&h->bbest, (size_t)std::max<int64_t>(1, c.nnz * h->m))))
+    return rc;
+  return CV_OK;
+}
+
 int prepare_sound(cv_bound* h, const cv_layer* layers, const float* x_lo, const float* x_hi, const float* l,
                   const float* u, const float* C, bool identity, hipStream_t s, const float* l2x0 = nullptr,
                   const float* l2eps = nullptr) {
@@ -1052,19 +1210,10 @@ int prepare_sound(cv_bound* h, const cv_layer* layers, const float* x_lo, const 
   int rc;
   if (!h->sw) {
     if ((rc = h->mem.alloc(&h->sw, w32.sw.size())) || (rc = h->mem.alloc(&h->err0, w32.e0.size())) ||
-        (rc = h->mem.alloc(&h->perr, (size_t)std::max(1, h->R) * h->n_slots)) ||
-        (rc = h->mem.alloc(&h->sw64, w64.sw.size())) || (rc = h->mem.alloc(&h->err064, w64.e0.size())) ||
-        (rc = h->mem.alloc(&h->act64[0], (size_t)std::max(1, h->R) * h->ldact)) ||
-        (rc = h->mem.alloc(&h->act64[1], (size_t)std::max(1, h->R) * h->ldact)) ||
-        (rc = h->mem.alloc(&h->part64, (size_t)std::max(1, h->R) * L)) ||
-        (rc = h->mem.alloc(&h->perr64, (size_t)std::max(1, h->R) * L)) ||
-        (rc = h->mem.alloc(&h->psq64, (size_t)std::max(1, h->R) * L)) ||
-        (rc = h->mem.alloc(&h->gbest, (size_t)std::max(1, h->R))) ||
-        (rc = h->mem.alloc(&h->improved, (size_t)std::max(1, h->R))) ||
-        (rc = h->mem.alloc(&h->abest, (size_t)std::max<int64_t>(1, h->n_alpha))) ||
-        (rc = h->mem.alloc(&h->bbest, (size_t)std::max<int64_t>(1, h->nnz * h->m))))
+        (rc = h->mem.alloc(&h->sw64, w64.sw.size())) || (rc = h->mem.alloc(&h->err064, w64.e0.size())))
       return rc;
   }
+  if ((rc = ensure_sound_batch(h))) return rc;
   HIPCHK(hipMemcpyAsync(h->sw, w32.sw.data(), w32.sw.size() * sizeof(float), hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(h->err0, w32.e0.data(), w32.e0.size() * sizeof(float), hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(h->sw64, w64.sw.data(), w64.sw.size() * sizeof(float), hipMemcpyHostToDevice, s));
@@ -1701,7 +1850,7 @@ int set_parts(cv_bound* h, int n) {
   for (int i = 0; i <= n; ++i) h->part_dom[i] = (int)((int64_t)h->B * i / n);
   for (int i = 0; i < n; ++i) {
     const int b0 = h->part_dom[i], b1 = h->part_dom[i + 1];
-    const int64_t s0 = in.sptr[b0], s1 = in.sptr[b1];
+    const int64_t s0 = in.sptr[b0];
     std::vector<int64_t> ptr(b1 - b0 + 1);
     for (int b = b0; b <= b1; ++b) ptr[b - b0] = in.sptr[b] - s0;
     std::unique_ptr<cv_bound> q(new cv_bound());
@@ -1716,6 +1865,10 @@ int set_parts(cv_bound* h, int n) {
       return rc;
     }
     q->dev = h->dev;
+    q->forced_tiling = h->forced_tiling;
+    q->forced_conv = h->forced_conv;
+    if (h->forced_tiling >= 0) assign_tiles(q.get(), h->forced_tiling);
+    if (h->forced_conv >= 0) assign_conv_variants(q.get(), h->forced_conv);
     q->chain_b = h->chain_b ? (q->chain_lo ? 1 : 0) : 0;
     q->chain_f = h->chain_f ? (q->chain_lo && q->chain_lo + 1 <= q->L - 1 ? 1 : 0) : 0;
     h->parts.push_back(q.release());
@@ -1738,11 +1891,7 @@ int set_parts(cv_bound* h, int n) {
   if (h->l2) {
     for (cv_bound* q : h->parts) {
       int rc;
-      if ((rc = q->mem.alloc(&q->psq, (size_t)q->n_slots * std::max(1, q->R))) ||
-          (rc = q->mem.alloc(&q->l2s, std::max(1, q->R))))
-        return rc;
-      q->ldx = r4(q->d0);
-      if ((rc = q->mem.alloc(&q->xdense, (size_t)std::max(1, q->R) * q->ldx))) return rc;
+      if ((rc = ensure_ball(q))) return rc;
       q->l2x0 = h->l2x0;
       q->l2eps = h->l2eps;
       q->wx0 = h->wx0;
@@ -1764,6 +1913,74 @@ int set_parts(cv_bound* h, int n) {
       q->bt.sw = q->sw;
       q->bt.sg = q->sound_g;
     }
+  }
+  return CV_OK;
+}
+
+void free_joint(cv_bound* h);
+
+// h re-targeted to a new batch (set_batch), with everything chosen per batch
+// redone: tile and conv-variant choices (they are keyed by the row count),
+// the chain geometry, sound-mode and ball buffers; the optimiser graph and any
+// joint state are dropped.
+int update_batch(cv_bound* h, int B, const int32_t* dom_prop, const int64_t* split_ptr, const int32_t* split_layer,
+                 const int32_t* split_neuron, const int8_t* split_side, hipStream_t s) {
+  BatchPlan bp;
+  int rc = check_batch(h, B, dom_prop, split_ptr, split_layer, split_neuron, split_side, bp);
+  if (rc) return rc;
+  // work still queued on any stream (the sub-batches' own ones included) may
+  // read the tables about to be rewritten
+  HIPCHK(hipDeviceSynchronize());
+  if ((rc = set_batch(h, bp, true, s))) return rc;
+  drop_graph(h);
+  h->gseen = GraphKey{};
+  free_joint(h);
+  assign_tiles(h, h->forced_tiling);
+  assign_conv_variants(h, h->forced_conv);
+  if (h->chain_lo && !plan_chain(h)) {
+    h->chain_lo = 0;
+    h->chain_b = h->chain_f = 0;
+  }
+  if (h->sound && (rc = ensure_sound_batch(h))) return rc;
+  if (h->l2 && (rc = ensure_ball(h))) return rc;
+  return CV_OK;
+}
+
+// A new batch for h and its sub-batches (Alg. 1's rounds), keeping the
+// network, properties, specifications, root bounds, input sets and modes.
+int update_domains(cv_bound* h, int B, const int32_t* dom_prop, const int64_t* split_ptr, const int32_t* split_layer,
+                   const int32_t* split_neuron, const int8_t* split_side, hipStream_t s) {
+  int rc = update_batch(h, B, dom_prop, split_ptr, split_layer, split_neuron, split_side, s);
+  if (rc) return rc;
+  cv_bound::Inputs& in = *h->in;
+  const int64_t nnz = B > 0 ? split_ptr[B] : 0;
+  in.prop.assign(dom_prop, dom_prop + B);
+  in.sptr.assign(split_ptr, split_ptr + B + 1);
+  in.slayer.assign(split_layer, split_layer + nnz);
+  in.sneuron.assign(split_neuron, split_neuron + nnz);
+  in.sside.assign(split_side, split_side + nnz);
+  in.slayer.push_back(0);  // sliced pointers stay valid for empty slices
+  in.sneuron.push_back(0);
+  in.sside.push_back(1);
+  int n = h->parts_req > 0 ? h->parts_req : (h->R >= kPartsMinRows ? 2 : 1);
+  n = std::min(n, std::max(1, B));
+  if (n <= 1) {
+    free_parts(h);
+    return CV_OK;
+  }
+  if ((int)h->parts.size() != n) {
+    free_parts(h);
+    return set_parts(h, n);
+  }
+  for (int i = 0; i <= n; ++i) h->part_dom[i] = (int)((int64_t)B * i / n);
+  for (int i = 0; i < n; ++i) {
+    const int b0 = h->part_dom[i], b1 = h->part_dom[i + 1];
+    const int64_t s0 = in.sptr[b0];
+    std::vector<int64_t> ptr(b1 - b0 + 1);
+    for (int b = b0; b <= b1; ++b) ptr[b - b0] = in.sptr[b] - s0;
+    if ((rc = update_batch(h->parts[i], b1 - b0, in.prop.data() + b0, ptr.data(), in.slayer.data() + s0,
+                           in.sneuron.data() + s0, in.sside.data() + s0, s)))
+      return rc;
   }
   return CV_OK;
 }
@@ -2542,7 +2759,14 @@ int cv_bound_joint_vars(cv_bound* h, int32_t layer, float* alpha_p, float* beta_
 int cv_bound_set_parts(cv_bound* h, int32_t nparts) {
   if (!h) return fail(CV_EINVAL, "null handle");
   if (nparts < 1 || nparts > kMaxParts) return fail(CV_EINVAL, "nparts must be 1..%d", kMaxParts);
+  h->parts_req = nparts;
   return set_parts(h, std::min<int>(nparts, std::max(1, h->B)));
+}
+
+int cv_bound_update(cv_bound* h, int32_t n_dom, const int32_t* dom_prop, const int64_t* split_ptr,
+                    const int32_t* split_layer, const int32_t* split_neuron, const int8_t* split_side, void* stream) {
+  if (!h || !h->in) return fail(CV_EINVAL, "null handle");
+  return update_domains(h, n_dom, dom_prop, split_ptr, split_layer, split_neuron, split_side, (hipStream_t)stream);
 }
 
 int cv_bound_autotune(cv_bound* h, void* stream) {
@@ -2749,9 +2973,11 @@ int cv_bound_set_conv_variant(cv_bound* h, int32_t variant) {
   if (!h) return fail(CV_EINVAL, "null handle");
   if (variant < -1 || variant >= kNumConvVariants)
     return fail(CV_EINVAL, "conv variant must be -1 or in [0, %d)", kNumConvVariants);
+  h->forced_conv = variant;
   assign_conv_variants(h, variant);
   drop_graph(h);
   for (cv_bound* q : h->parts) {
+    q->forced_conv = variant;
     assign_conv_variants(q, variant);
     drop_graph(q);
   }
@@ -2769,9 +2995,11 @@ int cv_bound_conv_variant(const cv_bound* h, int32_t layer, int32_t dir) {
 int cv_bound_set_tiling(cv_bound* h, int32_t tiling) {
   if (!h) return fail(CV_EINVAL, "null handle");
   if (tiling < -1 || tiling >= kNumGemmCfgs) return fail(CV_EINVAL, "tiling must be -1 or in [0, %d)", kNumGemmCfgs);
+  h->forced_tiling = tiling;
   assign_tiles(h, tiling);
   drop_graph(h);
   for (cv_bound* q : h->parts) {
+    q->forced_tiling = tiling;
     assign_tiles(q, tiling);
     drop_graph(q);
   }
@@ -2837,13 +3065,7 @@ int cv_bound_set_input_lp(cv_bound* h, const float* x0, const float* eps, float 
   // the sub-batches read the parent's centre, radius and W(1) x0 + b(1); each
   // handle keeps its own per-row sums and scales, and x* (A(0)) densely
   for (cv_bound* q : all) {
-    if (!q->psq && ((rc = q->mem.alloc(&q->psq, (size_t)q->n_slots * std::max(1, q->R))) ||
-                    (rc = q->mem.alloc(&q->l2s, std::max(1, q->R)))))
-      return rc;
-    if (!q->xdense) {
-      q->ldx = r4(q->d0);
-      if ((rc = q->mem.alloc(&q->xdense, (size_t)std::max(1, q->R) * q->ldx))) return rc;
-    }
+    if ((rc = ensure_ball(q))) return rc;
     q->l2x0 = h->l2x0;
     q->l2eps = h->l2eps;
     q->wx0 = h->wx0;
