@@ -304,14 +304,18 @@ def bab_context(wl, lo, up, args):
     C = np.hstack([wl.C[p], -t[:, None]]).astype(np.float32)
     torch.cuda.synchronize()
     r = gb.bab(layers, wl.x_lo[p], wl.x_hi[p], C, lo[p], up[p], batch=args.bab_batch, max_rounds=args.bab_rounds,
-               iters=args.iters, lr_alpha=args.lr_alpha, lr_beta=args.lr_beta, decay=args.decay)
-    # rounds that split a full batch (after the pool has grown to it)
-    full = [(n, s) for n, s in r["per_round"] if n >= 2 * args.bab_batch]
+               iters=args.iters, lr_alpha=args.lr_alpha, lr_beta=args.lr_beta, decay=args.decay, warm=args.bab_warm)
+    # rounds that split a full batch (after the pool has grown to it), and the
+    # optimiser's own rate over the same rounds (the rest of a round: the
+    # handle's re-targeting, the upper bound, the pool on the host)
+    full = [(n, s, o) for n, s, o in r["per_round"] if n >= 2 * args.bab_batch]
+    fb = sum(n for n, _, _ in full)
     return {"domains_per_s": round(r["domains"] / r["seconds"], 1), "domains": r["domains"], "rounds": r["rounds"],
             "batch": args.bab_batch, "seconds": round(r["seconds"], 3), "verdict": r["verdict"],
-            "lb": r["lb"], "ub": r["ub"],
+            "lb": r["lb"], "ub": r["ub"], "warm_start": bool(args.bab_warm),
             "full_batch_rounds": len(full),
-            "full_batch_domains_per_s": round(sum(n for n, _ in full) / sum(s for _, s in full), 1) if full else None}
+            "full_batch_domains_per_s": round(fb / sum(s for _, s, _ in full), 1) if full else None,
+            "full_batch_optimizer_domains_per_s": round(fb / sum(o for _, _, o in full), 1) if full else None}
 
 
 def joint_context(wl, lo, up, args):
@@ -509,6 +513,7 @@ def main():
     ap.add_argument("--profile-reps", type=int, default=5)
     ap.add_argument("--bab-rounds", type=int, default=16, help="branch-and-bound rounds timed as context")
     ap.add_argument("--bab-batch", type=int, default=1024, help="subdomains split per branch-and-bound round")
+    ap.add_argument("--bab-warm", action="store_true", help="warm-start branch-and-bound children from their parents")
     ap.add_argument("--plan", default=None, help="dense-chain plan bwd,fwd (1,1 fused chains, 0,0 per-layer kernels); overrides the autotuner")
     ap.add_argument("--parts", type=int, default=0,
                     help="concurrent sub-batches of the optimiser (0: the library's default)")

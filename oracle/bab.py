@@ -12,9 +12,16 @@ network at the box minimiser of the final iterate as its upper bound
 (Domain_Filter) and returns the rest to the pool.  The global lower bound is
 the pool's smallest, the global upper bound the smallest upper bound seen.
 It stops when the property is proved (empty pool), a counter-example is found
-(upper bound < 0), no pooled subdomain can be split further, the pool exceeds
-`max_pool`, or after `max_rounds` rounds.  Intermediate bounds stay those of
-the root, split neurons taking l >= 0 / u <= 0 (App. B.1 remark).
+(upper bound < 0), the global upper and lower bounds are within `delta` of
+each other (Alg. 1's f-bar - f-underbar <= delta), no pooled subdomain can be
+split further, the pool exceeds `max_pool`, or after `max_rounds` rounds.
+Intermediate bounds stay those of the root, split neurons taking l >= 0 /
+u <= 0 (App. B.1 remark).
+
+Children's starting point: CROWN's default alpha and beta = 0, or with
+warm=True their parent's final alpha and beta (the new split's beta at 0,
+the Adam moments fresh) -- the paper does not say where a child's
+optimisation starts; any start gives a sound bound.
 
 Branching rule: the paper names BaBSR and FSB only by citation, so a simple
 rule of this project is used, the same in the library's driver: neurons in
@@ -40,7 +47,7 @@ def branch_order(lo, up):
     return [(i, j) for _, i, j in items]
 
 
-def bab(net64, x_lo, x_hi, C, lo, up, batch=8, max_rounds=64, max_pool=4096, cfg=None):
+def bab(net64, x_lo, x_hi, C, lo, up, batch=8, max_rounds=64, max_pool=4096, cfg=None, warm=False, delta=0.0):
     """Returns a dict: verdict ('verified' | 'falsified' | 'unknown'), lb (the
     smallest lower bound over the leaves of the search tree, a lower bound of
     the minimum), ub (the smallest upper bound seen), rounds, domains
@@ -48,13 +55,14 @@ def bab(net64, x_lo, x_hi, C, lo, up, batch=8, max_rounds=64, max_pool=4096, cfg
     cfg = cfg or bc.AdamConfig()
     m = C.shape[0]
     order = branch_order(lo, up)
+    a_root = [np.tile(bc.default_alpha(l, u), (m, 1)) for l, u in zip(lo, up)]
+    b_root = [np.zeros((m, l.shape[0])) for l in lo]
 
-    def solve(split):
-        a0 = [np.tile(bc.default_alpha(l, u), (m, 1)) for l, u in zip(lo, up)]
-        b0 = [np.zeros((m, l.shape[0])) for l in lo]
+    def solve(split, start):
+        a0, b0 = start if warm and start is not None else (a_root, b_root)
         best, a, b, _ = bc.optimize(net64, x_lo, x_hi, C, lo, up, split, a0, b0, cfg)
         _, ub, _, _ = bc.upper_bound(net64, x_lo, x_hi, C, lo, up, split, a, b)
-        return float(best.min()), float(ub.min())
+        return float(best.min()), float(ub.min()), (a, b)
 
     def next_neuron(split):
         for i, j in order:
@@ -63,13 +71,13 @@ def bab(net64, x_lo, x_hi, C, lo, up, batch=8, max_rounds=64, max_pool=4096, cfg
         return None
 
     root = [np.zeros(l.shape[0], np.int8) for l in lo]
-    lb, ub = solve(root)
-    pool = [(lb, 0, root)] if lb < 0 else []  # (lower bound, insertion number, split)
+    lb, ub, var = solve(root, None)
+    pool = [(lb, 0, root, var)] if lb < 0 else []  # (lower bound, insertion number, split, final alpha / beta)
     f_lb = lb if pool else np.inf
     f_ub = ub
     done_lb = np.inf if pool else lb  # smallest lower bound among the dropped (proved) leaves
     rounds, domains, seq = 0, 1, 1
-    while f_lb < 0 <= f_ub and pool and len(pool) < max_pool and rounds < max_rounds:
+    while f_lb < 0 <= f_ub and f_ub - f_lb > delta and pool and len(pool) < max_pool and rounds < max_rounds:
         pool.sort(key=lambda t: (t[0], t[1]))
         picked, rest = [], []
         for t in pool:
@@ -77,16 +85,16 @@ def bab(net64, x_lo, x_hi, C, lo, up, batch=8, max_rounds=64, max_pool=4096, cfg
         if not picked:
             break
         pool = rest
-        for _, _, split in picked:
+        for _, _, split, var in picked:
             i, j = next_neuron(split)
             for side in (1, -1):
                 child = [s.copy() for s in split]
                 child[i][j] = side
-                lb_c, ub_c = solve(child)
+                lb_c, ub_c, var_c = solve(child, var)
                 domains += 1
                 f_ub = min(f_ub, ub_c)
                 if lb_c < 0:
-                    pool.append((lb_c, seq, child))
+                    pool.append((lb_c, seq, child, var_c))
                 else:
                     done_lb = min(done_lb, lb_c)
                 seq += 1

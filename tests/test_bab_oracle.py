@@ -86,3 +86,50 @@ def test_library_branch_order_matches_oracle():
     o = ob.branch_order(lo, up)
     g = gb.branch_order(np.concatenate(lo), np.concatenate(up), [7, 5])
     assert g == [(i + 1, j) for i, j in o]
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_warm_started_bab_keeps_the_guarantees(seed):
+    """Children started from their parent's final alpha, beta: still sound
+    both ways and complete on the proving side (any start gives a sound bound,
+    and a fully split subdomain's bound is exact)."""
+    net, x_lo, x_hi, lo, up = tiny_net(seed + 500)
+    C = np.ones((1, 1))
+    fstar, n_uns = exact_min(net, C, x_lo, x_hi, lo, up)
+    if n_uns > 9 or n_uns < 2:
+        pytest.skip("enumeration size")
+    cfg = bc.AdamConfig(iters=60, lr_alpha=0.1, lr_beta=0.2)
+    for t in (fstar - 0.05 * max(1.0, abs(fstar)), fstar + 0.05 * max(1.0, abs(fstar))):
+        r = ob.bab(shifted(net, t), x_lo, x_hi, C, lo, up, batch=4, max_rounds=400, cfg=cfg, warm=True)
+        target = fstar - t
+        assert r["lb"] <= target + 1e-9 and r["ub"] >= target - 1e-9, (r, target)
+        if target > 0:
+            assert r["verdict"] == "verified", (r, target)
+        else:
+            assert r["verdict"] in ("falsified", "unknown"), (r, target)
+
+
+def test_delta_exit_stops_once_the_bounds_meet():
+    """Alg. 1's f-bar - f-underbar <= delta exit: a delta wider than the
+    root's gap stops before any round; a moderate one stops as soon as the
+    gap closes to it (the search without delta runs on), and the reported
+    bounds still bracket the exact minimum."""
+    for seed in range(500, 520):
+        net, x_lo, x_hi, lo, up = tiny_net(seed)
+        C = np.ones((1, 1))
+        fstar, n_uns = exact_min(net, C, x_lo, x_hi, lo, up)
+        if 3 <= n_uns <= 9:
+            break
+    cfg = bc.AdamConfig(iters=60, lr_alpha=0.1, lr_beta=0.2)
+    t = fstar - 0.05 * max(1.0, abs(fstar))  # a true property: the search proves it
+    net_t = shifted(net, t)
+    full = ob.bab(net_t, x_lo, x_hi, C, lo, up, batch=1, max_rounds=400, cfg=cfg)
+    wide = ob.bab(net_t, x_lo, x_hi, C, lo, up, batch=1, max_rounds=400, cfg=cfg, delta=1e6)
+    assert wide["rounds"] == 0 and wide["verdict"] == "unknown"
+    assert wide["lb"] <= fstar - t <= wide["ub"] + 1e-9
+    gap0 = wide["ub"] - wide["lb"]
+    mid = ob.bab(net_t, x_lo, x_hi, C, lo, up, batch=1, max_rounds=400, cfg=cfg, delta=0.5 * gap0)
+    assert mid["lb"] <= fstar - t + 1e-9
+    assert mid["rounds"] <= full["rounds"]
+    if mid["verdict"] == "unknown":
+        assert mid["ub"] - mid["lb"] <= 0.5 * gap0 + 1e-12
