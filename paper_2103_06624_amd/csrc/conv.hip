@@ -435,6 +435,71 @@ __device__ __forceinline__ void sd_load(const Batch& bt, const Epi& e, int b, in
   }
 }
 
+// An opaque copy (in the adjoint modes) of a value the subdomain-major
+// kernels keep across a subdomain's rows: tests on it are then made where they
+// are used, in the row loop, instead of being hoisted out of it as per-lane
+// masks (a 64-bit scalar pair each, several per output unit, which spill).
+// Measured: the adjoint kernels 2-4 % faster; the back-substitution ones 1-6 %
+// slower (there the recomputed tests cost more than the spills), so they keep
+// the hoisted form.
+template <int MODE, class T>
+__device__ __forceinline__ T per_row(T x) {
+  if (MODE == kFwd || MODE == kFwdX) asm volatile("" : "+v"(x));
+  return x;
+}
+
+// Back-substitution with relaxation, per output unit of a subdomain: the
+// relaxation's case analysis (Lemma 2.1 with the split term) as numbers, so
+// that the epilogue is straight arithmetic on them:
+//   Lambda = a (ca + (a >= 0 ? ux x : su)) + sg x,  constant += min(a, 0) ci,
+// with x the unit's variable (alpha of an unstable neuron, beta of a split
+// one): active ca = 1; unstable ux = 1 and the chord's slope su and intercept
+// ci; split z >= 0: ca = 1, sg = -1; split z < 0: sg = +1; every other
+// coefficient 0.  Each case gives the operations, and the roundings, of the
+// case analysis.  The variable of row k is vsrc[k vstr] (alpha: the row's
+// block moves by the property's unstable count; beta: by one); a unit with
+// no variable reads a finite dummy (its default slope), which every
+// coefficient it meets is 0 for.  cix: the unstable index (the stored A's
+// slot), else -1.
+struct RelaxCoef {
+  float ca, ux, sg, su, ci;
+  int cix, vstr;
+  const float* vsrc;
+};
+
+template <int NJ>
+__device__ __forceinline__ void sd_relax_coef(const Batch& bt, const Vars& v, const Epi& e, int b, int p, int dout,
+                                              int64_t ab0, int uc, RelaxCoef (&cf)[NJ]) {
+#pragma unroll
+  for (int u = 0; u < NJ; ++u) {
+    const int jc = min((int)threadIdx.x + kSdThreads * u, dout - 1);
+    const uint32_t r = bt.status[(int64_t)b * bt.nd + e.layer_off + jc];
+    const int64_t pc = (int64_t)p * bt.nd + e.layer_off + jc;
+    const uint32_t kind = r & kKindMask;
+    const bool pos = (r & kSidePos) != 0;
+    RelaxCoef c{0.f, 0.f, 0.f, 0.f, 0.f, -1, 0, bt.adef + pc};
+    if (kind == kActive) c.ca = 1.f;
+    if (kind == kUnstable) {
+      const float2 ch = bt.chord[pc];
+      c.ux = 1.f;
+      c.su = ch.x;
+      c.ci = ch.y;
+      c.cix = (int)(r & kCidxMask);
+      if (v.alpha) {
+        c.vsrc = v.alpha + ab0 + c.cix;
+        c.vstr = uc;
+      }
+    }
+    if (kind == kSplit) {
+      c.ca = pos ? 1.f : 0.f;
+      c.sg = pos ? -1.f : 1.f;
+      c.vsrc = v.beta + (int64_t)(r & kSplitMask) * bt.m;
+      c.vstr = 1;
+    }
+    cf[u] = c;
+  }
+}
+
 // Per-row variables of outputs j = tid + 512 u.  Back-substitution: x1 = the
 // neuron's alpha (unstable) or beta (split), one load from a selected
 // address.  Adjoint: x1 = the stored A(i)_j and x2 = alpha of an unstable
@@ -446,8 +511,8 @@ __device__ __forceinline__ void sd_row_vars(const Batch& bt, const Vars& v, cons
   const int64_t pc0 = (int64_t)ri.p * bt.nd + e.layer_off;
 #pragma unroll
   for (int u = 0; u < NJ; ++u) {
-    const int j = (int)threadIdx.x + kSdThreads * u;
-    const uint32_t r = rec[u];
+    const int j = per_row<MODE>((int)threadIdx.x + kSdThreads * u);
+    const uint32_t r = per_row<MODE>(rec[u]);
     const uint32_t kind = r & kKindMask;
     const bool ok = j < dout;
     x1[u] = x2[u] = x3[u] = x4[u] = 0.f;
@@ -557,9 +622,16 @@ __global__ __launch_bounds__(kSdThreads, (conv_sd_occupancy<MODE, NJ, NI>())) vo
     uint32_t rec[NJ];
     float2 ch[NJ];
     float x1[NJ], x2[NJ], x3[NJ], x4[NJ];
-    sd_load<MODE>(bt, e, b, p, pl.dout, rec, ch);
+    RelaxCoef cf[MODE == kBwdRelax ? NJ : 1];
     RowInfo ri{b, r0 - b * m, p, ab0 + (int64_t)(r0 - b * m) * uc};
-    sd_row_vars<MODE>(bt, v, e, ri, pl.dout, rec, x1, x2, x3, x4);
+    if constexpr (MODE == kBwdRelax) {
+      sd_relax_coef<NJ>(bt, v, e, b, p, pl.dout, ab0, uc, cf);
+#pragma unroll
+      for (int u = 0; u < NJ; ++u) x1[u] = cf[u].vsrc[(int64_t)ri.k * cf[u].vstr];
+    } else {
+      sd_load<MODE>(bt, e, b, p, pl.dout, rec, ch);
+      sd_row_vars<MODE>(bt, v, e, ri, pl.dout, rec, x1, x2, x3, x4);
+    }
     // the next unit's first row (staged during this unit's last row)
     const int nunit = unit + gridDim.x;
     const int nb = nunit / upb;
@@ -587,14 +659,19 @@ __global__ __launch_bounds__(kSdThreads, (conv_sd_occupancy<MODE, NJ, NI>())) vo
       float cst = 0.f, cer = 0.f;
 #pragma unroll
       for (int u = 0; u < NJ; ++u) {
-        const int j = tid + kSdThreads * u;
+        const int j = per_row<MODE>(tid + kSdThreads * u);
         const bool ok = j < pl.dout;
         const float a = zo[min(j, pl.dout - 1)];
-        const uint32_t r = rec[u];
-        if (MODE == kBwdRelax) {
+        const uint32_t r = per_row<MODE>(rec[u]);
+        if constexpr (MODE == kBwdRelax) {
           if (!ok) continue;
-          if (v.acomp && (r & kKindMask) == kUnstable) v.acomp[ri.abase + (r & kCidxMask)] = a;
-          const float lam = relax_value(bt, v, ri, r, ch[u], x1[u], a, bsh[j], &cst);
+          const RelaxCoef& c = cf[u];
+          if (v.acomp && c.cix >= 0) v.acomp[ri.abase + c.cix] = a;
+          const float x = x1[u];
+          const float t = a >= 0.f ? c.ux * x : c.su;
+          const float lam = fmaf(a, c.ca + t, c.sg * x);
+          cst = fmaf(fminf(a, 0.f), c.ci, cst);
+          cst = fmaf(lam, bsh[j], cst);
           e.out[(int64_t)row * e.ldo + j] = lam;
           if (bt.sw) cer = fmaf(fabsf(lam), bt.sw[pc0 + j], cer);
         } else if (MODE == kBwdConc) {
@@ -649,7 +726,12 @@ __global__ __launch_bounds__(kSdThreads, (conv_sd_occupancy<MODE, NJ, NI>())) vo
       if (row + 1 < r1) {
         ri.k += 1;
         ri.abase += uc;
-        sd_row_vars<MODE>(bt, v, e, ri, pl.dout, rec, x1, x2, x3, x4);
+        if constexpr (MODE == kBwdRelax) {
+#pragma unroll
+          for (int u = 0; u < NJ; ++u) x1[u] = cf[u].vsrc[(int64_t)ri.k * cf[u].vstr];
+        } else {
+          sd_row_vars<MODE>(bt, v, e, ri, pl.dout, rec, x1, x2, x3, x4);
+        }
       }
       __syncthreads();
       if (kBwd && tid == 0) {
