@@ -500,38 +500,141 @@ __device__ __forceinline__ void sd_relax_coef(const Batch& bt, const Vars& v, co
   }
 }
 
-// Per-row variables of outputs j = tid + 512 u.  Back-substitution: x1 = the
-// neuron's alpha (unstable) or beta (split), one load from a selected
-// address.  Adjoint: x1 = the stored A(i)_j and x2 = alpha of an unstable
-// neuron; with the fused Adam step also its moments (x3, x4).
+// Adjoint (the forward sweep from x*), per output unit of a subdomain: the
+// relaxation's case analysis as numbers, like the back-substitution's.  With
+// a the GEMM's output, zb = rm a + kb (kb the bias, or W(1) x0 + b(1) on an l2
+// ball's first layer, where rm = -l2s of the row; rm = 1 otherwise), x1 the
+// stored A(i)_j of an unstable neuron (0 elsewhere) and x2 its alpha
+// (elsewhere the constant slope: 1 active or split z >= 0, 0 inactive or
+// split z < 0):
+//   zhat = x1 >= 0 ? zb x2 : su zb + ci,
+// and an unstable neuron's alpha gradient is x1 >= 0 ? zb x1 : 0 -- the
+// operations and roundings of the case analysis, the sign of a zero aside.
+// cix: an unstable neuron's alpha slot; -2 - (its alpha slot) for a split
+// neuron, whose record bits (side, split index) are bsp; -1 otherwise.  x1
+// and x2 keep their constants over the unit's rows except at unstable
+// neurons, whose A, alpha (and Adam moments x3, x4) each row loads.
+struct AdjCoef {
+  float su, ci;
+  int cix;
+  uint32_t bsp;
+};
+
+template <int NJ>
+__device__ __forceinline__ void sd_adj_coef(const Batch& bt, const Vars& v, const Epi& e, int b, int p, int dout,
+                                            AdjCoef (&cf)[NJ], float (&x1)[NJ], float (&x2)[NJ], float (&x3)[NJ],
+                                            float (&x4)[NJ]) {
+#pragma unroll
+  for (int u = 0; u < NJ; ++u) {
+    const int j = (int)threadIdx.x + kSdThreads * u;
+    const int jc = min(j, dout - 1);
+    const uint32_t r = bt.status[(int64_t)b * bt.nd + e.layer_off + jc];
+    const int64_t pc = (int64_t)p * bt.nd + e.layer_off + jc;
+    const uint32_t kind = j < dout ? r & kKindMask : kInactive;
+    AdjCoef c{0.f, 0.f, -1, 0u};
+    float ca = kind == kActive ? 1.f : 0.f;
+    if (kind == kUnstable) {
+      const float2 ch = bt.chord[pc];
+      c.su = ch.x;
+      c.ci = ch.y;
+      c.cix = (int)(r & kCidxMask);
+      ca = bt.adef[pc];  // the default alpha, for passes given none
+    }
+    if (kind == kSplit) {
+      ca = (r & kSidePos) ? 1.f : 0.f;
+      c.cix = -2 - bt.cidx[pc];
+      c.bsp = r & (kSidePos | kSplitMask);
+    }
+    cf[u] = c;
+    x1[u] = 0.f;
+    x2[u] = ca;
+    x3[u] = x4[u] = 0.f;
+  }
+}
+
 template <int MODE, int NJ>
-__device__ __forceinline__ void sd_row_vars(const Batch& bt, const Vars& v, const Epi& e, const RowInfo& ri,
-                                            int dout, const uint32_t (&rec)[NJ], float (&x1)[NJ], float (&x2)[NJ],
-                                            float (&x3)[NJ], float (&x4)[NJ]) {
-  const int64_t pc0 = (int64_t)ri.p * bt.nd + e.layer_off;
+__device__ __forceinline__ void sd_adj_row_vars(const Vars& v, const RowInfo& ri, const AdjCoef (&cf)[NJ],
+                                                float (&x1)[NJ], float (&x2)[NJ], float (&x3)[NJ], float (&x4)[NJ]) {
+  if (v.sat) return;
+  const float* const ac = v.acomp + ri.abase;
+#pragma unroll
+  for (int u = 0; u < NJ; ++u) {
+    const int ci = per_row<MODE>(cf[u].cix);
+    if (ci >= 0) {
+      // (unsigned offsets from the row's uniform base: scalar-base addressing)
+      const uint32_t o = (uint32_t)ci;
+      x1[u] = ac[o];
+      if (v.alpha) x2[u] = (v.alpha + ri.abase)[o];
+      if (v.adam) {
+        x3[u] = (v.ma + ri.abase)[o];
+        x4[u] = (v.va + ri.abase)[o];
+      }
+    }
+  }
+}
+
+// A split neuron's variables (cix <= -2): beta's gradient is -zb on the
+// z >= 0 side and zb on the z < 0 side; its alpha slot gets gradient 0 (with
+// Adam: a step on its moments alone).
+__device__ __forceinline__ void adj_split(const Batch& bt, const Vars& v, const RowInfo& ri, int cix, uint32_t bsp,
+                                          float zb) {
+  const int64_t bi = (int64_t)(bsp & kSplitMask) * bt.m + ri.k;
+  const int64_t ai = ri.abase + (-2 - cix);
+  const float gb = (bsp & kSidePos) ? -zb : zb;
+  if (v.adam) {
+    adam_apply(v.beta_w, v.mb, v.vb, bi, gb, v.lr_b, v.bc1, v.bc2, 0.f, INFINITY);
+    adam_apply(v.alpha_w, v.ma, v.va, ai, 0.f, v.lr_a, v.bc1, v.bc2, 0.f, 1.f);
+  } else {
+    v.gbeta[bi] = gb;
+    v.galpha[ai] = 0.f;
+  }
+}
+
+// The adjoint's epilogue of one row (the relaxed network; orow: the row of
+// the next layer's input, or null after the last layer).
+template <int MODE, bool kAdam, int NJ>
+__device__ __forceinline__ void sd_adj_epi(const Batch& bt, const Vars& v, const RowInfo& ri, const float* zo,
+                                           int dout, float rm, const float* kb, float* orow, const AdjCoef (&cf)[NJ],
+                                           const float (&x1)[NJ], const float (&x2)[NJ], const float (&x3)[NJ],
+                                           const float (&x4)[NJ]) {
 #pragma unroll
   for (int u = 0; u < NJ; ++u) {
     const int j = per_row<MODE>((int)threadIdx.x + kSdThreads * u);
-    const uint32_t r = per_row<MODE>(rec[u]);
-    const uint32_t kind = r & kKindMask;
-    const bool ok = j < dout;
-    x1[u] = x2[u] = x3[u] = x4[u] = 0.f;
-    if (MODE == kBwdRelax) {
-      const float* src = nullptr;
-      if (ok && kind == kUnstable) src = v.alpha ? v.alpha + ri.abase + (r & kCidxMask) : bt.adef + pc0 + j;
-      if (ok && kind == kSplit) src = v.beta + (int64_t)(r & kSplitMask) * bt.m + ri.k;
-      if (src) x1[u] = *src;
-    } else if (MODE == kFwd || MODE == kFwdX) {
-      if (ok && kind == kUnstable && !v.sat) {
-        const int64_t ai = ri.abase + (r & kCidxMask);
-        x1[u] = v.acomp[ai];
-        x2[u] = v.alpha ? v.alpha[ai] : bt.adef[pc0 + j];
-        if (v.adam) {
-          x3[u] = v.ma[ai];
-          x4[u] = v.va[ai];
-        }
-      }
+    if (j >= dout) continue;
+    const AdjCoef& c = cf[u];
+    const float zb = fmaf(rm, zo[j], kb[j]);
+    const bool ge = x1[u] >= 0.f;
+    const float zh = ge ? zb * x2[u] : fmaf(c.su, zb, c.ci);
+    if (orow) orow[(uint32_t)j] = zh;
+    const int ci = per_row<MODE>(c.cix);
+    if (ci >= 0) {
+      const float g = ge ? zb * x1[u] : 0.f;
+      const uint32_t o = (uint32_t)ci;
+      if (kAdam)
+        adam_step(v.alpha_w + ri.abase, v.ma + ri.abase, v.va + ri.abase, o, g, v.lr_a, v.bc1, v.bc2, 0.f, 1.f,
+                  x2[u], x3[u], x4[u]);
+      else
+        (v.galpha + ri.abase)[o] = g;
+    } else if (ci < -1) {
+      adj_split(bt, v, ri, ci, per_row<MODE>(c.bsp), zb);  // its addresses: computed here, not held
     }
+  }
+}
+
+// The network itself at x* (upper bound): the exact ReLU, every layer's
+// output kept; a pre-activation that breaks a split of the row's subdomain
+// clears sat[row].
+template <int MODE, int NJ>
+__device__ __forceinline__ void sd_adj_sat(const Vars& v, const float* zo, int dout, float rm, const float* kb,
+                                           float* orow, int row, const AdjCoef (&cf)[NJ]) {
+#pragma unroll
+  for (int u = 0; u < NJ; ++u) {
+    const int j = per_row<MODE>((int)threadIdx.x + kSdThreads * u);
+    if (j >= dout) continue;
+    const AdjCoef& c = cf[u];
+    const float zb = fmaf(rm, zo[j], kb[j]);
+    if (c.cix < -1 && ((c.bsp & kSidePos) ? zb < 0.f : zb > 0.f)) v.sat[row] = 0;
+    orow[j] = fmaxf(zb, 0.f);
   }
 }
 
@@ -623,14 +726,21 @@ __global__ __launch_bounds__(kSdThreads, (conv_sd_occupancy<MODE, NJ, NI>())) vo
     float2 ch[NJ];
     float x1[NJ], x2[NJ], x3[NJ], x4[NJ];
     RelaxCoef cf[MODE == kBwdRelax ? NJ : 1];
+    AdjCoef af[kBwd ? 1 : NJ];
     RowInfo ri{b, r0 - b * m, p, ab0 + (int64_t)(r0 - b * m) * uc};
     if constexpr (MODE == kBwdRelax) {
       sd_relax_coef<NJ>(bt, v, e, b, p, pl.dout, ab0, uc, cf);
 #pragma unroll
       for (int u = 0; u < NJ; ++u) x1[u] = cf[u].vsrc[(int64_t)ri.k * cf[u].vstr];
-    } else {
+    } else if constexpr (MODE == kBwdConc) {
       sd_load<MODE>(bt, e, b, p, pl.dout, rec, ch);
-      sd_row_vars<MODE>(bt, v, e, ri, pl.dout, rec, x1, x2, x3, x4);
+    } else {
+      sd_adj_coef<NJ>(bt, v, e, b, p, pl.dout, af, x1, x2, x3, x4);
+      sd_adj_row_vars<MODE, NJ>(v, ri, af, x1, x2, x3, x4);
+      // an l2 ball's first layer: the property's W(1) x0 + b(1) takes the
+      // bias's place (every wave is past the previous unit's last epilogue)
+      if (e.wx0)
+        for (int t = tid; t < pl.dout; t += kSdThreads) bsh[t] = e.wx0[(int64_t)p * e.n + t];
     }
     // the next unit's first row (staged during this unit's last row)
     const int nunit = unit + gridDim.x;
@@ -657,12 +767,23 @@ __global__ __launch_bounds__(kSdThreads, (conv_sd_occupancy<MODE, NJ, NI>())) vo
       // for the store before it (stores count against the same counter)
       __builtin_amdgcn_s_waitcnt(kWaitVm0);
       float cst = 0.f, cer = 0.f;
+      if constexpr (!kBwd) {
+        // the uniform switches are taken once per row, outside the unit loop
+        const float rm = e.wx0 ? -v.l2s[row] : 1.f;
+        const float* const kb = bsh;
+        float* const orow = e.out + (int64_t)row * e.ldo;
+        if (v.sat)
+          sd_adj_sat<MODE, NJ>(v, zo, pl.dout, rm, kb, orow, row, af);
+        else if (v.adam)
+          sd_adj_epi<MODE, true, NJ>(bt, v, ri, zo, pl.dout, rm, kb, last ? nullptr : orow, af, x1, x2, x3, x4);
+        else
+          sd_adj_epi<MODE, false, NJ>(bt, v, ri, zo, pl.dout, rm, kb, last ? nullptr : orow, af, x1, x2, x3, x4);
+      }
 #pragma unroll
-      for (int u = 0; u < NJ; ++u) {
+      for (int u = 0; u < (kBwd ? NJ : 0); ++u) {
         const int j = per_row<MODE>(tid + kSdThreads * u);
         const bool ok = j < pl.dout;
         const float a = zo[min(j, pl.dout - 1)];
-        const uint32_t r = per_row<MODE>(rec[u]);
         if constexpr (MODE == kBwdRelax) {
           if (!ok) continue;
           const RelaxCoef& c = cf[u];
@@ -695,17 +816,6 @@ __global__ __launch_bounds__(kSdThreads, (conv_sd_occupancy<MODE, NJ, NI>())) vo
               v.xneg[(int64_t)row * bt.w64 + (w0 >> 6)] = bn;
             }
           }
-        } else {
-          if (!ok) continue;
-          // l2 ball, first layer: W(1) x* + b(1) = (W(1) x0 + b(1)) - l2s (W(1) A(0))
-          const float zb = e.wx0 ? fmaf(-v.l2s[row], a, e.wx0[(int64_t)p * e.n + j]) : a + bsh[j];
-          if (v.sat) {  // the network itself at x*: every layer's output is kept
-            e.out[(int64_t)row * e.ldo + j] = true_relu(r, zb, v.sat + row);
-            continue;
-          }
-          const float zh = relax_fwd_value<false>(bt, v, ri, r, ch[u], x1[u], x2[u], pc0 + j, zb, v.adam != 0,
-                                                  make_float2(x3[u], x4[u]));
-          if (!last) e.out[(int64_t)row * e.ldo + j] = zh;
         }
       }
       if (kBwd) {
@@ -729,8 +839,8 @@ __global__ __launch_bounds__(kSdThreads, (conv_sd_occupancy<MODE, NJ, NI>())) vo
         if constexpr (MODE == kBwdRelax) {
 #pragma unroll
           for (int u = 0; u < NJ; ++u) x1[u] = cf[u].vsrc[(int64_t)ri.k * cf[u].vstr];
-        } else {
-          sd_row_vars<MODE>(bt, v, e, ri, pl.dout, rec, x1, x2, x3, x4);
+        } else if constexpr (!kBwd) {
+          sd_adj_row_vars<MODE, NJ>(v, ri, af, x1, x2, x3, x4);
         }
       }
       __syncthreads();
