@@ -467,23 +467,33 @@ struct RelaxCoef {
   const float* vsrc;
 };
 
+// (the records and chords of all units are loaded first, unconditionally --
+// the chords are defined at every neuron -- so that they are in flight
+// together: one memory round trip per unit of rows, not two per output)
 template <int NJ>
 __device__ __forceinline__ void sd_relax_coef(const Batch& bt, const Vars& v, const Epi& e, int b, int p, int dout,
                                               int64_t ab0, int uc, RelaxCoef (&cf)[NJ]) {
+  uint32_t rr[NJ];
+  float2 chv[NJ];
 #pragma unroll
   for (int u = 0; u < NJ; ++u) {
     const int jc = min((int)threadIdx.x + kSdThreads * u, dout - 1);
-    const uint32_t r = bt.status[(int64_t)b * bt.nd + e.layer_off + jc];
+    rr[u] = bt.status[(int64_t)b * bt.nd + e.layer_off + jc];
+    chv[u] = bt.chord[(int64_t)p * bt.nd + e.layer_off + jc];
+  }
+#pragma unroll
+  for (int u = 0; u < NJ; ++u) {
+    const int jc = min((int)threadIdx.x + kSdThreads * u, dout - 1);
     const int64_t pc = (int64_t)p * bt.nd + e.layer_off + jc;
+    const uint32_t r = rr[u];
     const uint32_t kind = r & kKindMask;
     const bool pos = (r & kSidePos) != 0;
     RelaxCoef c{0.f, 0.f, 0.f, 0.f, 0.f, -1, 0, bt.adef + pc};
     if (kind == kActive) c.ca = 1.f;
     if (kind == kUnstable) {
-      const float2 ch = bt.chord[pc];
       c.ux = 1.f;
-      c.su = ch.x;
-      c.ci = ch.y;
+      c.su = chv[u].x;
+      c.ci = chv[u].y;
       c.cix = (int)(r & kCidxMask);
       if (v.alpha) {
         c.vsrc = v.alpha + ab0 + c.cix;
@@ -524,25 +534,35 @@ template <int NJ>
 __device__ __forceinline__ void sd_adj_coef(const Batch& bt, const Vars& v, const Epi& e, int b, int p, int dout,
                                             AdjCoef (&cf)[NJ], float (&x1)[NJ], float (&x2)[NJ], float (&x3)[NJ],
                                             float (&x4)[NJ]) {
+  // (all loads first, as for the back-substitution)
+  uint32_t rr[NJ];
+  float2 chv[NJ];
+  float ad[NJ];
+  int cx[NJ];
 #pragma unroll
   for (int u = 0; u < NJ; ++u) {
-    const int j = (int)threadIdx.x + kSdThreads * u;
-    const int jc = min(j, dout - 1);
-    const uint32_t r = bt.status[(int64_t)b * bt.nd + e.layer_off + jc];
+    const int jc = min((int)threadIdx.x + kSdThreads * u, dout - 1);
     const int64_t pc = (int64_t)p * bt.nd + e.layer_off + jc;
-    const uint32_t kind = j < dout ? r & kKindMask : kInactive;
+    rr[u] = bt.status[(int64_t)b * bt.nd + e.layer_off + jc];
+    chv[u] = bt.chord[pc];
+    ad[u] = bt.adef[pc];
+    cx[u] = bt.cidx[pc];
+  }
+#pragma unroll
+  for (int u = 0; u < NJ; ++u) {
+    const uint32_t r = rr[u];
+    const uint32_t kind = (int)threadIdx.x + kSdThreads * u < dout ? r & kKindMask : kInactive;
     AdjCoef c{0.f, 0.f, -1, 0u};
     float ca = kind == kActive ? 1.f : 0.f;
     if (kind == kUnstable) {
-      const float2 ch = bt.chord[pc];
-      c.su = ch.x;
-      c.ci = ch.y;
+      c.su = chv[u].x;
+      c.ci = chv[u].y;
       c.cix = (int)(r & kCidxMask);
-      ca = bt.adef[pc];  // the default alpha, for passes given none
+      ca = ad[u];  // the default alpha, for passes given none
     }
     if (kind == kSplit) {
       ca = (r & kSidePos) ? 1.f : 0.f;
-      c.cix = -2 - bt.cidx[pc];
+      c.cix = -2 - cx[u];
       c.bsp = r & (kSidePos | kSplitMask);
     }
     cf[u] = c;
