@@ -448,6 +448,22 @@ void plan_border(HostPlan& o) {
   }
 }
 
+// Column n of a paired plan (two horizontally adjacent outputs x = 2 X + px
+// per GEMM row, c channels): its (px, channel).  With 8 channels the columns
+// go in groups of four, px alternating between groups -- (px 0, ch 0-3),
+// (px 1, ch 0-3), (px 0, ch 4-7), (px 1, ch 4-7) -- so the 32 lanes that
+// store two neighbouring column groups of a transposed MFMA tile write the
+// two parities of a position: even and odd LDS banks.
+inline void pair_col(int n, int c, int& px, int& ch) {
+  if (c == 8) {
+    px = (n >> 2) & 1;
+    ch = (n & 3) | ((n >> 3) << 2);
+  } else {
+    px = n / c;
+    ch = n % c;
+  }
+}
+
 // Back-substitution through conv layer ly (transposed convolution), polyphase
 // form: GEMM rows (Y, X), columns (py, px, ci), K = (co, a, b).  A stride-1
 // layer with c_in <= 8 folds output pairs x = 2 X + px into a row instead:
@@ -465,12 +481,18 @@ void plan_convt(const cv_layer& ly, HostPlan& o) {
   if (s == 1 && ci <= 8) {
     const int nX = (wi + 1) / 2, kb = k + 1, M = hi * nX, K = co * k * kb, N = 2 * ci;
     plan_pad(o, M, K, N, [&](int kk, int n) {
-      const int c_o = kk / (k * kb), a = (kk / kb) % k, kx = kk % kb - 1 + n / ci;
-      return kx >= 0 && kx < k ? ly.weight[(((size_t)c_o * ci + n % ci) * k + a) * k + kx] : 0.f;
+      int px, c;
+      pair_col(n, ci, px, c);
+      const int c_o = kk / (k * kb), a = (kk / kb) % k, kx = kk % kb - 1 + px;
+      return kx >= 0 && kx < k ? ly.weight[(((size_t)c_o * ci + c) * k + a) * k + kx] : 0.f;
     });
     for (int m = 0; m < M; ++m) o.mt[m] = make_int4(m / nX + pad, 2 * (m % nX) + pad, m / nX + pad, m % nX);
     for (int kk = 0; kk < K; ++kk) o.kt[kk] = make_int4(-((kk / kb) % k), 1 - kk % kb, (kk / (k * kb)) * ho * wo, 0);
-    for (int n = 0; n < N; ++n) o.nt[n] = make_int4(-pad, n / ci, (n % ci) * hi * wi, 0);
+    for (int n = 0; n < N; ++n) {
+      int px, c;
+      pair_col(n, ci, px, c);
+      o.nt[n] = make_int4(-pad, px, c * hi * wi, 0);
+    }
     p.osy = 1;
     p.osx = 2;
     plan_border(o);
@@ -532,15 +554,21 @@ void plan_conv(const cv_layer& ly, HostPlan& o) {
   if (co <= 8) {
     const int nX = (wo + 1) / 2, kf = k + s, M = ho * nX, K = ci * k * kf;
     plan_pad(o, M, K, 2 * co, [&](int kk, int n) {
-      const int c = kk / (k * kf), ky = (kk / kf) % k, kx = kk % kf - (n / co) * s;
-      return kx >= 0 && kx < k ? ly.weight[(((size_t)(n % co) * ci + c) * k + ky) * k + kx] : 0.f;
+      int px, c_o;
+      pair_col(n, co, px, c_o);
+      const int c = kk / (k * kf), ky = (kk / kf) % k, kx = kk % kf - px * s;
+      return kx >= 0 && kx < k ? ly.weight[(((size_t)c_o * ci + c) * k + ky) * k + kx] : 0.f;
     });
     for (int m = 0; m < M; ++m) {
       const int oy = m / nX, X = m % nX;
       o.mt[m] = make_int4(oy * s - pad, 2 * X * s - pad, oy, X);
     }
     for (int kk = 0; kk < K; ++kk) o.kt[kk] = make_int4((kk / kf) % k, kk % kf, (kk / (k * kf)) * hi * wi, 0);
-    for (int n = 0; n < 2 * co; ++n) o.nt[n] = make_int4(0, n / co, (n % co) * ho * wo, 0);
+    for (int n = 0; n < 2 * co; ++n) {
+      int px, c_o;
+      pair_col(n, co, px, c_o);
+      o.nt[n] = make_int4(0, px, c_o * ho * wo, 0);
+    }
     p.osx = 2;
     plan_border(o);
     return;

@@ -131,9 +131,14 @@ __device__ __forceinline__ void in_store(float* zi, const ConvPlan& pl, const Ba
 // its LDS output row zo: each wave takes 16-row tiles of m, all N tiles.
 // With sct set, the output slot of every accumulator element comes from a
 // table built once per workgroup (sct[(mtile NT + t) 64 + lane] holds the
-// four rows' slots; slots outside the plane point at a spare slot past the
-// row), so the scatter is four unconditional LDS stores.
-template <int NT, bool WG, int NW = 4>
+// four slots of the lane; slots outside the plane point at a spare slot past
+// the row), so the scatter is four unconditional LDS stores.  TR computes the
+// transposed tile (the MFMA's operands swapped): a lane then holds one
+// output position and four columns, and a store of the 16 lanes that share
+// a column writes 16 neighbouring positions of one channel plane -- distinct
+// LDS banks, where the 16 columns (channels a plane apart) of one position
+// would all meet in one or two banks.
+template <int NT, bool WG, int NW = 4, bool TR = false>
 __device__ __forceinline__ void conv_gemm_row(const ConvPlan& pl, const float* zi, float* zo, const float* wl,
                                               const int4* mt, const int4* kt, const int4* ntb, int n_ks, int n_mt,
                                               int lane, int wave, const int4* sct = nullptr) {
@@ -177,9 +182,12 @@ __device__ __forceinline__ void conv_gemm_row(const ConvPlan& pl, const float* z
 #pragma unroll
       for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q], b[q][t], acc[t], 0, 0, 0);
+        for (int t = 0; t < NT; ++t)
+          acc[t] = TR ? __builtin_amdgcn_mfma_f32_16x16x4f32(b[q][t], a[q], acc[t], 0, 0, 0)
+                      : __builtin_amdgcn_mfma_f32_16x16x4f32(a[q], b[q][t], acc[t], 0, 0, 0);
     }
-    // lane holds rows 4 (lane / 16) + r of the tile, column lane % 16
+    // lane holds rows 4 (lane / 16) + r of the tile, column lane % 16 (TR:
+    // row lane % 16, columns 4 (lane / 16) + r)
     if (sct) {
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
@@ -697,15 +705,16 @@ __global__ __launch_bounds__(kSdThreads, (conv_sd_occupancy<MODE, NJ, NI>())) vo
     for (int t = tid; t < pl.dout; t += kSdThreads) bsh[t] = e.bias[t];
   __syncthreads();  // before any thread stages a row over the zeroed planes
   // the scatter slot of every accumulator element (the same for every row);
-  // element r of lane l in tile (mtile, t) is output (m = 16 mtile + 4 (l / 16)
-  // + r, n = 16 t + l % 16); outputs outside the plane go to the spare slot
+  // element r of lane l in tile (mtile, t) is output (m = 16 mtile + l % 16,
+  // n = 16 t + 4 (l / 16) + r) (the transposed tile); outputs outside the
+  // plane go to the spare slot
   for (int i = tid; i < n_mt * NT * 64; i += kSdThreads) {
     const int mtile = i / (NT * 64), t = (i / 64) % NT, ln = i % 64;
-    const int4 ne = ntb[t * 16 + (ln & 15)];
+    const int4 mo = mt[mtile * 16 + (ln & 15)];
     int ad[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int4 mo = mt[mtile * 16 + 4 * (ln >> 4) + r];
+      const int4 ne = ntb[t * 16 + 4 * (ln >> 4) + r];
       const int y = pl.osy * mo.z + ne.x, x = pl.osx * mo.w + ne.y;
       const bool ok = ne.z >= 0 && (unsigned)y < (unsigned)pl.oh && (unsigned)x < (unsigned)pl.ow;
       ad[r] = ok ? ne.z + y * pl.ow + x : pl.dout;
@@ -774,7 +783,7 @@ __global__ __launch_bounds__(kSdThreads, (conv_sd_occupancy<MODE, NJ, NI>())) vo
       uint32_t w1[NI], w2[NI];
       if (nrow >= 0) in_load<MODE, NI, kSdThreads>(zin, ldi, bt, v, nrow, 0, pl.din, s1, s2, w1, w2);
 
-      conv_gemm_row<NT, WG, kSdWaves>(pl, zi, zo, wl, mt, kt, ntb, n_ks, n_mt, lane, wave, sct);
+      conv_gemm_row<NT, WG, kSdWaves, true>(pl, zi, zo, wl, mt, kt, ntb, n_ks, n_mt, lane, wave, sct);
       __syncthreads();
       // every wave is past this row's GEMM: zi takes the next row (the rest
       // of a long input row after the epilogue)
