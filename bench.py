@@ -110,16 +110,30 @@ def name_profile_pass(disp, prof):
     tail = disp[-n:]
     if len(tail) != n:
         raise SystemExit("counter run holds fewer dispatches than the timing pass")
-    names = iter([k["name"] for k in kern])
-    key_name, out = {}, {}
-    for i in range(0, n, 8):
+    # a group of 8 takes the name its (symbol, grid) had before while that
+    # name has launches left in the current pass, else the next name not yet
+    # seen (two names may share a symbol and grid)
+    order = [k["name"] for k in kern]
+    per_pass = {k["name"]: k["launches_per_pass"] for k in kern}
+    groups_per_rep = sum(per_pass.values())
+    key_names, out, seen, left = {}, {}, [], {}
+    for gi, i in enumerate(range(0, n, 8)):
+        if gi % groups_per_rep == 0:
+            left = dict(per_pass)
         grp = tail[i:i + 8]
         key = (grp[0]["kernel"], grp[0]["grid"])
         if any((g["kernel"], g["grid"]) != key for g in grp):
             raise SystemExit(f"dispatch group at {i} is not 8 launches of one kernel")
-        if key not in key_name:
-            key_name[key] = next(names)
-        out.setdefault(key_name[key], []).extend(grp)
+        name = next((nm for nm in key_names.get(key, []) if left[nm] > 0), None)
+        if name is None:
+            fresh = [nm for nm in order if nm not in seen]
+            if not fresh:
+                raise SystemExit(f"dispatch group at {i}: no kernel name left for {key}")
+            name = fresh[0]
+            seen.append(name)
+            key_names.setdefault(key, []).append(name)
+        left[name] -= 1
+        out.setdefault(name, []).extend(grp)
     for k in kern:
         got = len(out.get(k["name"], ()))
         if got != 8 * reps * k["launches_per_pass"]:
