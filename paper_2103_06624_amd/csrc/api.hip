@@ -381,6 +381,7 @@ constexpr int kFar = -(1 << 20);  // an offset that puts any gather or output ou
 
 struct HostPlan {
   std::vector<int4> mt, kt, nt;
+  std::vector<int> ku;  // the uniform per-step part of kt (empty: kt does not split)
   std::vector<float> wm;
   ConvPlan p{};
   int M = 0, K = 0;  // GEMM rows and columns before padding
@@ -407,6 +408,32 @@ void plan_pad(HostPlan& o, int M, int K, int N, F wv) {
         const int k = ks * 4 + l / 16, n = t * 16 + l % 16;
         if (k < K && n < N) o.wm[((size_t)ks * p.nt + t) * 64 + l] = wv(k, n);
       }
+}
+
+// The split kt[4 s + q] = ku[s] + v(q) of the column offsets (v(q) = kt[q] -
+// kt[0], ku[s] = kt[4 s]), when every real column obeys it and every padding
+// column's tap, so placed, stays inside the staged row for every GEMM row
+// (a padding column has zero weights, so any tap in range will do); else
+// ku stays empty and the kernels read kt.
+void plan_uniform(HostPlan& o) {
+  const ConvPlan& p = o.p;
+  o.ku.clear();
+  if (o.K < 4) return;
+  int v[4], m0 = INT32_MAX, m1 = INT32_MIN;
+  for (int q = 0; q < 4; ++q) v[q] = o.kt[q].x - o.kt[0].x;
+  for (int m = 0; m < p.mpad; ++m) {
+    m0 = std::min(m0, o.mt[m].x);
+    m1 = std::max(m1, o.mt[m].x);
+  }
+  std::vector<int> ku(p.kpad / 4);
+  for (int s = 0; s < p.kpad / 4; ++s) {
+    ku[s] = 4 * s < o.K ? o.kt[4 * s].x : ku[0];
+    for (int q = 0; q < 4; ++q) {
+      const int kk = 4 * s + q, off = ku[s] + v[q];
+      if (kk < o.K ? o.kt[kk].x != off : (m0 + off < 0 || m1 + off >= p.dinp)) return;
+    }
+  }
+  o.ku = ku;
 }
 
 // Turn the gather tables (row origin (y, x) in mt, column offset (dy, dx)
@@ -446,6 +473,7 @@ void plan_border(HostPlan& o) {
     const int4 e = o.kt[k];
     o.kt[k] = make_int4(k < o.K ? (e.z / plane) * p.pplane + e.x * p.gwp + e.y : 0, 0, 0, 0);
   }
+  plan_uniform(o);
 }
 
 // Column n of a paired plan (two horizontally adjacent outputs x = 2 X + px
@@ -553,17 +581,37 @@ void plan_conv(const cv_layer& ly, HostPlan& o) {
   p.osy = 1;
   if (co <= 8) {
     const int nX = (wo + 1) / 2, kf = k + s, M = ho * nX, K = ci * k * kf;
+    // K index kk -> (c, ky, kx'); with k a multiple of 4 the order is (kx', c,
+    // ky), ky innermost, so that the column offsets split into a per-step and
+    // a per-lane part (plan_uniform); otherwise (c, ky, kx')
+    const bool ky_in = k % 4 == 0;
+    auto kdec = [&](int kk, int& c, int& ky, int& kx) {
+      if (ky_in) {
+        ky = kk % k;
+        c = (kk / k) % ci;
+        kx = kk / (k * ci);
+      } else {
+        c = kk / (k * kf);
+        ky = (kk / kf) % k;
+        kx = kk % kf;
+      }
+    };
     plan_pad(o, M, K, 2 * co, [&](int kk, int n) {
-      int px, c_o;
+      int px, c_o, c, ky, kxf;
       pair_col(n, co, px, c_o);
-      const int c = kk / (k * kf), ky = (kk / kf) % k, kx = kk % kf - px * s;
+      kdec(kk, c, ky, kxf);
+      const int kx = kxf - px * s;
       return kx >= 0 && kx < k ? ly.weight[(((size_t)c_o * ci + c) * k + ky) * k + kx] : 0.f;
     });
     for (int m = 0; m < M; ++m) {
       const int oy = m / nX, X = m % nX;
       o.mt[m] = make_int4(oy * s - pad, 2 * X * s - pad, oy, X);
     }
-    for (int kk = 0; kk < K; ++kk) o.kt[kk] = make_int4((kk / kf) % k, kk % kf, (kk / (k * kf)) * hi * wi, 0);
+    for (int kk = 0; kk < K; ++kk) {
+      int c, ky, kxf;
+      kdec(kk, c, ky, kxf);
+      o.kt[kk] = make_int4(ky, kxf, c * hi * wi, 0);
+    }
     for (int n = 0; n < 2 * co; ++n) {
       int px, c_o;
       pair_col(n, co, px, c_o);
@@ -645,17 +693,20 @@ bool finite_all(const float* p, int64_t n) {
 
 int upload_plan(cv_bound* h, HostPlan& o, int mode, ConvPlan& out) {
   int4 *mt = nullptr, *kt = nullptr, *nt = nullptr;
+  int* ku = nullptr;
   float* wm = nullptr;
   int rc;
   if ((rc = h->mem.upload(&mt, o.mt.data(), o.mt.size(), nullptr)) ||
       (rc = h->mem.upload(&kt, o.kt.data(), o.kt.size(), nullptr)) ||
       (rc = h->mem.upload(&nt, o.nt.data(), o.nt.size(), nullptr)) ||
+      (!o.ku.empty() && (rc = h->mem.upload(&ku, o.ku.data(), o.ku.size(), nullptr))) ||
       (rc = h->mem.upload(&wm, o.wm.data(), o.wm.size(), nullptr)))
     return rc;
   out = o.p;
   out.mtab = mt;
   out.ktab = kt;
   out.ntab = nt;
+  out.kuni = ku;
   out.wm = wm;
   plan_finish(out);
   out.grid = conv_plan_grid(mode, out);

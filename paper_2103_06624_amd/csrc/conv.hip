@@ -142,14 +142,22 @@ template <int NT, bool WG, int NW = 4, bool TR = false>
 __device__ __forceinline__ void conv_gemm_row(const ConvPlan& pl, const float* zi, float* zo, const float* wl,
                                               const int4* mt, const int4* kt, const int4* ntb, int n_ks, int n_mt,
                                               int lane, int wave, const int4* sct = nullptr) {
+  // the split column offsets (ConvPlan::kuni), read through the constant
+  // address space so that the uniform per-step part comes by scalar loads
+  typedef const int __attribute__((address_space(4)))* cint_ptr;
+  const cint_ptr ku = (cint_ptr)pl.kuni;
+  const bool uni = pl.kuni != nullptr;
+  const int kv = uni ? kt[lane >> 4].x - ku[0] : 0;  // the lane's part
   for (int mtile = wave; mtile < n_mt; mtile += NW) {
     const int4 me = mt[mtile * 16 + (lane & 15)];
     floatx4 acc[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
-    // four K steps per pass (kpad is a multiple of 16): their table reads,
-    // gathers and weight reads are issued before the MFMAs that use them;
-    // weights from global memory are loaded one pass ahead
+    // four K steps per pass (kpad is a multiple of 16): their gathers and
+    // weight reads are issued before the MFMAs that use them; weights from
+    // global memory are loaded one pass ahead.  A gather's offset is either
+    // the lane's row origin plus kuni[step] + kv (no table read on its path)
+    // or the table's entry.
     float bn[4][NT];
     if (WG) {
 #pragma unroll
@@ -157,11 +165,8 @@ __device__ __forceinline__ void conv_gemm_row(const ConvPlan& pl, const float* z
 #pragma unroll
         for (int t = 0; t < NT; ++t) bn[q][t] = wl[(q * NT + t) * 64];
     }
-    for (int ks0 = 0; ks0 < n_ks; ks0 += 4) {
-      int4 ke[4];
-      float a[4], b[4][NT];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) ke[q] = kt[(ks0 + q) * 4 + (lane >> 4)];
+    auto pass = [&](int ks0, const float(&a)[4]) {
+      float b[4][NT];
       if (WG) {
         const int kn = ks0 + 4 < n_ks ? ks0 + 4 : ks0;  // the last pass reloads its own (unused)
 #pragma unroll
@@ -178,13 +183,36 @@ __device__ __forceinline__ void conv_gemm_row(const ConvPlan& pl, const float* z
           for (int t = 0; t < NT; ++t) b[q][t] = wl[((ks0 + q) * NT + t) * 64];
       }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) a[q] = zi[me.x + ke[q].x];
-#pragma unroll
       for (int q = 0; q < 4; ++q)
 #pragma unroll
         for (int t = 0; t < NT; ++t)
           acc[t] = TR ? __builtin_amdgcn_mfma_f32_16x16x4f32(b[q][t], a[q], acc[t], 0, 0, 0)
                       : __builtin_amdgcn_mfma_f32_16x16x4f32(a[q], b[q][t], acc[t], 0, 0, 0);
+    };
+    if (uni) {
+      const float* const zr = zi + me.x + kv;
+      for (int ks0 = 0; ks0 < n_ks; ks0 += 4) {
+        float a[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a[q] = zr[ku[ks0 + q]];
+        pass(ks0, a);
+        if (!WG) {
+          // every LDS read of the pass (four gathers, the weights) issued
+          // before its four MFMAs: one LDS latency per pass, not one per MFMA
+          __builtin_amdgcn_sched_group_barrier(0x100, 4 + 2 * NT, 0);
+          __builtin_amdgcn_sched_group_barrier(0x008, 4 * NT, 0);
+        }
+      }
+    } else {
+      for (int ks0 = 0; ks0 < n_ks; ks0 += 4) {
+        int4 ke[4];
+        float a[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ke[q] = kt[(ks0 + q) * 4 + (lane >> 4)];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a[q] = zi[me.x + ke[q].x];
+        pass(ks0, a);
+      }
     }
     // lane holds rows 4 (lane / 16) + r of the tile, column lane % 16 (TR:
     // row lane % 16, columns 4 (lane / 16) + r)

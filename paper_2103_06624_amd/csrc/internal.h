@@ -81,6 +81,11 @@ struct ConvPlan {
   const int4* mtab;  // [mpad] gather offset x and output origin (z, w) of GEMM row m
   const int4* ktab;  // [kpad] gather offset x of GEMM column k
   const int4* ntab;  // [16 nt] output offset (x, y) and channel base z (-1: padding)
+  // [kpad / 4] or null: when the column offsets split as ktab[4 s + q].x =
+  // kuni[s] + v(q) (a per-step part uniform across the wave and a per-lane
+  // part; in-range taps for the padding columns), the GEMM gathers through
+  // kuni, read by scalar loads, and v, instead of reading ktab every step
+  const int* kuni;
   const float* wm;   // [kpad / 4][nt][64] Wm in MFMA 16x16x4 operand order
   int mpad, kpad, nt;  // multiples of 16; nt: 16-column tiles (1, 2, 4 or 8)
   int gh, gw;          // gathered plane
