@@ -138,82 +138,95 @@ __device__ __forceinline__ void in_store(float* zi, const ConvPlan& pl, const Ba
 // a column writes 16 neighbouring positions of one channel plane -- distinct
 // LDS banks, where the 16 columns (channels a plane apart) of one position
 // would all meet in one or two banks.
+// One 16-row tile of m (row origin mex of the lane's row) over the K steps
+// [ks_lo, ks_hi) (multiples of 4), accumulated into acc: four K steps per
+// pass, their gathers and weight reads issued before the MFMAs that use them;
+// weights from global memory are loaded one pass ahead.  A gather's offset is
+// either the lane's row origin plus kuni[step] + kv (uni: no table read on
+// its path; kuni read through the constant address space, so by scalar
+// loads) or the table's entry.
+template <int NT, bool WG, bool TR>
+__device__ __forceinline__ void conv_gemm_tile(const ConvPlan& pl, const float* zi, const float* wl, int mex,
+                                               const int4* kt, bool uni, int kv, int ks_lo, int ks_hi, int lane,
+                                               floatx4 (&acc)[NT]) {
+  typedef const int __attribute__((address_space(4)))* cint_ptr;
+  const cint_ptr ku = (cint_ptr)pl.kuni;
+  float bn[4][NT];
+  if (WG) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) bn[q][t] = wl[((ks_lo + q) * NT + t) * 64];
+  }
+  auto pass = [&](int ks0, const float(&a)[4]) {
+    float b[4][NT];
+    if (WG) {
+      const int kn = ks0 + 4 < ks_hi ? ks0 + 4 : ks0;  // the last pass reloads its own (unused)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          b[q][t] = bn[q][t];
+          bn[q][t] = wl[((kn + q) * NT + t) * 64];
+        }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) b[q][t] = wl[((ks0 + q) * NT + t) * 64];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+        acc[t] = TR ? __builtin_amdgcn_mfma_f32_16x16x4f32(b[q][t], a[q], acc[t], 0, 0, 0)
+                    : __builtin_amdgcn_mfma_f32_16x16x4f32(a[q], b[q][t], acc[t], 0, 0, 0);
+  };
+  if (uni) {
+    const float* const zr = zi + mex + kv;
+    for (int ks0 = ks_lo; ks0 < ks_hi; ks0 += 4) {
+      float a[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a[q] = zr[ku[ks0 + q]];
+      pass(ks0, a);
+      if (!WG) {
+        // every LDS read of the pass (four gathers, the weights) issued
+        // before its four MFMAs: one LDS latency per pass, not one per MFMA
+        __builtin_amdgcn_sched_group_barrier(0x100, 4 + 2 * NT, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, 4 * NT, 0);
+      }
+    }
+  } else {
+    for (int ks0 = ks_lo; ks0 < ks_hi; ks0 += 4) {
+      int4 ke[4];
+      float a[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) ke[q] = kt[(ks0 + q) * 4 + (lane >> 4)];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a[q] = zi[mex + ke[q].x];
+      pass(ks0, a);
+    }
+  }
+}
+
+// The lane's part kv of the split column offsets (ConvPlan::kuni), 0 without.
+__device__ __forceinline__ int conv_kv(const ConvPlan& pl, const int4* kt, int lane) {
+  typedef const int __attribute__((address_space(4)))* cint_ptr;
+  return pl.kuni ? kt[lane >> 4].x - ((cint_ptr)pl.kuni)[0] : 0;
+}
+
 template <int NT, bool WG, int NW = 4, bool TR = false>
 __device__ __forceinline__ void conv_gemm_row(const ConvPlan& pl, const float* zi, float* zo, const float* wl,
                                               const int4* mt, const int4* kt, const int4* ntb, int n_ks, int n_mt,
                                               int lane, int wave, const int4* sct = nullptr) {
-  // the split column offsets (ConvPlan::kuni), read through the constant
-  // address space so that the uniform per-step part comes by scalar loads
-  typedef const int __attribute__((address_space(4)))* cint_ptr;
-  const cint_ptr ku = (cint_ptr)pl.kuni;
   const bool uni = pl.kuni != nullptr;
-  const int kv = uni ? kt[lane >> 4].x - ku[0] : 0;  // the lane's part
+  const int kv = conv_kv(pl, kt, lane);
   for (int mtile = wave; mtile < n_mt; mtile += NW) {
     const int4 me = mt[mtile * 16 + (lane & 15)];
     floatx4 acc[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
-    // four K steps per pass (kpad is a multiple of 16): their gathers and
-    // weight reads are issued before the MFMAs that use them; weights from
-    // global memory are loaded one pass ahead.  A gather's offset is either
-    // the lane's row origin plus kuni[step] + kv (no table read on its path)
-    // or the table's entry.
-    float bn[4][NT];
-    if (WG) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int t = 0; t < NT; ++t) bn[q][t] = wl[(q * NT + t) * 64];
-    }
-    auto pass = [&](int ks0, const float(&a)[4]) {
-      float b[4][NT];
-      if (WG) {
-        const int kn = ks0 + 4 < n_ks ? ks0 + 4 : ks0;  // the last pass reloads its own (unused)
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-          for (int t = 0; t < NT; ++t) {
-            b[q][t] = bn[q][t];
-            bn[q][t] = wl[((kn + q) * NT + t) * 64];
-          }
-      } else {
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-          for (int t = 0; t < NT; ++t) b[q][t] = wl[((ks0 + q) * NT + t) * 64];
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int t = 0; t < NT; ++t)
-          acc[t] = TR ? __builtin_amdgcn_mfma_f32_16x16x4f32(b[q][t], a[q], acc[t], 0, 0, 0)
-                      : __builtin_amdgcn_mfma_f32_16x16x4f32(a[q], b[q][t], acc[t], 0, 0, 0);
-    };
-    if (uni) {
-      const float* const zr = zi + me.x + kv;
-      for (int ks0 = 0; ks0 < n_ks; ks0 += 4) {
-        float a[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) a[q] = zr[ku[ks0 + q]];
-        pass(ks0, a);
-        if (!WG) {
-          // every LDS read of the pass (four gathers, the weights) issued
-          // before its four MFMAs: one LDS latency per pass, not one per MFMA
-          __builtin_amdgcn_sched_group_barrier(0x100, 4 + 2 * NT, 0);
-          __builtin_amdgcn_sched_group_barrier(0x008, 4 * NT, 0);
-        }
-      }
-    } else {
-      for (int ks0 = 0; ks0 < n_ks; ks0 += 4) {
-        int4 ke[4];
-        float a[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) ke[q] = kt[(ks0 + q) * 4 + (lane >> 4)];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) a[q] = zi[me.x + ke[q].x];
-        pass(ks0, a);
-      }
-    }
+    conv_gemm_tile<NT, WG, TR>(pl, zi, wl, me.x, kt, uni, kv, 0, n_ks, lane, acc);
     // lane holds rows 4 (lane / 16) + r of the tile, column lane % 16 (TR:
     // row lane % 16, columns 4 (lane / 16) + r)
     if (sct) {
@@ -722,7 +735,17 @@ __global__ __launch_bounds__(kSdThreads, (conv_sd_occupancy<MODE, NJ, NI>())) vo
   int4* const sct = reinterpret_cast<int4*>(zo + ((pl.dout + 4 + 3) & ~3));  // scatter slots [n_mt NT 64]
   const int n_mt = pl.mpad >> 4;
   float* const bsh = reinterpret_cast<float*>(sct + n_mt * NT * 64);  // bias per neuron (not for concretisation)
+  // partial tiles of a split K (below): [kSdWaves][NT][64] floatx4
+  floatx4* const kpart = reinterpret_cast<floatx4*>(bsh + (MODE != kBwdConc ? (pl.dout + 3) & ~3 : 0));
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // With fewer 16-row tiles than waves (a small output plane with a long K),
+  // each tile's K passes are split over ksp waves (a power of two, a pass at
+  // least each) whose partial tiles are summed in LDS before the scatter.
+  // (compiled in for the narrow output instantiations only, NJ <= 2: the
+  // wide ones have planes of many tiles, and its registers would cost them)
+  int ksp = 1;
+  if (NJ <= 2)
+    while (2 * ksp * n_mt <= kSdWaves && 2 * ksp <= (pl.kpad >> 4)) ksp *= 2;
 
   for (int t = tid; t < nwm / 4; t += kSdThreads) smem4[t] = reinterpret_cast<const float4*>(pl.wm)[t];
   for (int t = tid; t < pl.mpad; t += kSdThreads) mt[t] = pl.mtab[t];
@@ -749,6 +772,8 @@ __global__ __launch_bounds__(kSdThreads, (conv_sd_occupancy<MODE, NJ, NI>())) vo
     }
     sct[i] = make_int4(ad[0], ad[1], ad[2], ad[3]);
   }
+  const bool uni = pl.kuni != nullptr;
+  const int kv = conv_kv(pl, kt, lane);
   // the staged slots of this thread's first NI kSdThreads inputs (the same for every row)
   int so[NI];
 #pragma unroll
@@ -811,7 +836,35 @@ __global__ __launch_bounds__(kSdThreads, (conv_sd_occupancy<MODE, NJ, NI>())) vo
       uint32_t w1[NI], w2[NI];
       if (nrow >= 0) in_load<MODE, NI, kSdThreads>(zin, ldi, bt, v, nrow, 0, pl.din, s1, s2, w1, w2);
 
-      conv_gemm_row<NT, WG, kSdWaves, true>(pl, zi, zo, wl, mt, kt, ntb, n_ks, n_mt, lane, wave, sct);
+      if (NJ > 2 || ksp == 1) {
+        conv_gemm_row<NT, WG, kSdWaves, true>(pl, zi, zo, wl, mt, kt, ntb, n_ks, n_mt, lane, wave, sct);
+      } else {
+        const int mtile = wave % n_mt, c = wave / n_mt;
+        if (c < ksp) {
+          const int np = n_ks >> 2;
+          floatx4 acc[NT];
+#pragma unroll
+          for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+          conv_gemm_tile<NT, WG, true>(pl, zi, wl, mt[mtile * 16 + (lane & 15)].x, kt, uni, kv, (c * np / ksp) * 4,
+                                       ((c + 1) * np / ksp) * 4, lane, acc);
+#pragma unroll
+          for (int t = 0; t < NT; ++t) kpart[(wave * NT + t) * 64 + lane] = acc[t];
+        }
+        __syncthreads();  // every partial tile is in LDS
+        if (wave < n_mt) {  // the tile's sum (chunks in order), scattered
+          floatx4 acc[NT];
+#pragma unroll
+          for (int t = 0; t < NT; ++t) {
+            acc[t] = kpart[(wave * NT + t) * 64 + lane];
+            for (int cc = 1; cc < ksp; ++cc) acc[t] += kpart[((cc * n_mt + wave) * NT + t) * 64 + lane];
+            const int4 ad = sct[(wave * NT + t) * 64 + lane];
+            zo[ad.x] = acc[t][0];
+            zo[ad.y] = acc[t][1];
+            zo[ad.z] = acc[t][2];
+            zo[ad.w] = acc[t][3];
+          }
+        }
+      }
       __syncthreads();
       // every wave is past this row's GEMM: zi takes the next row (the rest
       // of a long input row after the epilogue)
@@ -1103,7 +1156,8 @@ void conv_plan_sd(int mode, ConvPlan& pl) {
   const void* k = sd_kernel_mode(mode, pl.nt, pl.wg != 0, nj, ni);
   // the plan's LDS, the spare output slot (padded), the scatter table and the bias
   pl.smem_sd = pl.smem + 32 + (pl.mpad >> 4) * pl.nt * 64 * (int)sizeof(int4) +
-               (mode == kBwdConc ? 0 : pl.dout * (int)sizeof(float));
+               (mode == kBwdConc ? 0 : ((pl.dout + 3) & ~3) * (int)sizeof(float)) +
+               ((pl.mpad >> 4) < kSdWaves && pl.kpad >= 32 ? kSdWaves * pl.nt * 64 * 16 : 0);  // split-K partial tiles
   int dev = 0, cus = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
       hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, kSdThreads, pl.smem_sd) != hipSuccess) {
