@@ -74,28 +74,56 @@ __device__ __forceinline__ void epi_first(const Batch& bt, const Epi& e, int row
   }
 }
 
-// Input floats t = t0 + tid + 256 u of a row: the row of zin, or for a conv
-// first layer's adjoint step the box and the 32-bit words of the sign planes
-// of A(0) that hold bit t (x* is formed when the row is staged).
+// Input floats t = t0 + tid + TB u of a row: the row of zin, or for a conv
+// first layer's adjoint step (row property p) the box and the sign planes of
+// A(0) (x* is formed when the row is staged).  The box is read through a row
+// pointer uniform across the workgroup (p taken to a scalar register).  The
+// N inputs of a lane need bit (lane % 32) of 2N 32-bit words of each plane
+// per wave (inputs u: words (t0 + TB u) / 32 + 2 wave + {0, 1}): lane 2u + h
+// loads word h of input u into g1 (plane A(0) > 0) and g2 (A(0) < 0), and
+// the lanes fetch theirs from it when the row is staged (sign_bits).
 template <int MODE, int N, int TB = 256>
-__device__ __forceinline__ void in_load(const float* zin, int ldi, const Batch& bt, const Vars& v, int row, int t0,
-                                        int din, float (&s1)[N], float (&s2)[N], uint32_t (&w1)[N],
-                                        uint32_t (&w2)[N]) {
-  const int p = MODE == kFwdX ? bt.prop[row / bt.m] : 0;
+__device__ __forceinline__ void in_load(const float* zin, int ldi, const Batch& bt, const Vars& v, int row, int p,
+                                        int t0, int din, float (&s1)[N], float (&s2)[N], uint32_t& g1,
+                                        uint32_t& g2) {
+  static_assert(2 * N <= 64, "one word per lane");
+  if constexpr (MODE == kFwdX) {
+    const int pu = __builtin_amdgcn_readfirstlane(p);
+    const float* const xl = bt.xlo + (int64_t)pu * bt.d0;
+    const float* const xu = bt.xhi + (int64_t)pu * bt.d0;
 #pragma unroll
-  for (int u = 0; u < N; ++u) {
-    const int tc = min(t0 + (int)threadIdx.x + TB * u, din - 1);
-    if (MODE == kFwdX) {
-      s1[u] = bt.xlo[(int64_t)p * bt.d0 + tc];
-      s2[u] = bt.xhi[(int64_t)p * bt.d0 + tc];
-      // bit t of a plane's row: bit t % 32 of its 32-bit word t / 32
-      w1[u] = reinterpret_cast<const uint32_t*>(v.xpos)[(int64_t)row * 2 * bt.w64 + (tc >> 5)];
-      w2[u] = reinterpret_cast<const uint32_t*>(v.xneg)[(int64_t)row * 2 * bt.w64 + (tc >> 5)];
-    } else {
+    for (int u = 0; u < N; ++u) {
+      const int tc = min(t0 + (int)threadIdx.x + TB * u, din - 1);
+      s1[u] = xl[tc];
+      s2[u] = xu[tc];
+    }
+    const int lane = (int)threadIdx.x & 63, l = min(lane, 2 * N - 1);
+    const int wi = min(((t0 + TB * (l >> 1)) >> 5) + 2 * ((int)threadIdx.x >> 6) + (l & 1), 2 * bt.w64 - 1);
+    g1 = reinterpret_cast<const uint32_t*>(v.xpos + (int64_t)row * bt.w64)[wi];
+    g2 = reinterpret_cast<const uint32_t*>(v.xneg + (int64_t)row * bt.w64)[wi];
+  } else {
+#pragma unroll
+    for (int u = 0; u < N; ++u) {
+      const int tc = min(t0 + (int)threadIdx.x + TB * u, din - 1);
       s1[u] = zin[(int64_t)row * ldi + tc];
       s2[u] = 0.f;
     }
+    g1 = g2 = 0;
   }
+}
+
+// x* at input u of the lane from the words in_load left in g1, g2 (every
+// lane of the wave takes part: a cross-lane read)
+__device__ __forceinline__ float xstar_from(int u, uint32_t g1, uint32_t g2, float xl, float xu) {
+  const int lane = (int)threadIdx.x & 63, src = 2 * u + (lane >> 5);
+  const uint32_t a = (uint32_t)__shfl((int)g1, src), b = (uint32_t)__shfl((int)g2, src);
+  return xstar((a >> (lane & 31)) & 1, (b >> (lane & 31)) & 1, xl, xu);
+}
+
+// the property of a row, where the first layer's adjoint step stages x*
+template <int MODE>
+__device__ __forceinline__ int row_prop(const Batch& bt, int row) {
+  return MODE == kFwdX ? bt.prop[row / bt.m] : 0;
 }
 
 // Staged slot of input float t: channel plane c = t / (gh gw) and position
@@ -111,12 +139,13 @@ __device__ __forceinline__ int staged(const ConvPlan& pl, int t) {
 template <int MODE, int N, int TB = 256>
 __device__ __forceinline__ void in_store(float* zi, const ConvPlan& pl, const Batch& bt, const Vars& v, int row,
                                          int t0, int din, const float (&s1)[N], const float (&s2)[N],
-                                         const uint32_t (&w1)[N], const uint32_t (&w2)[N]) {
+                                         uint32_t g1, uint32_t g2) {
   if (MODE == kFwdX) {
 #pragma unroll
     for (int u = 0; u < N; ++u) {
       const int t = t0 + (int)threadIdx.x + TB * u;
-      if (t < din) zi[staged(pl, t)] = xstar((w1[u] >> (t & 31)) & 1, (w2[u] >> (t & 31)) & 1, s1[u], s2[u]);
+      const float x = xstar_from(u, g1, g2, s1[u], s2[u]);
+      if (t < din) zi[staged(pl, t)] = x;
     }
   } else {
 #pragma unroll
@@ -257,12 +286,12 @@ __device__ __forceinline__ void conv_gemm_row(const ConvPlan& pl, const float* z
 // in_store with the staged slots of inputs t = tid + TB u precomputed (so)
 template <int MODE, int N, int TB>
 __device__ __forceinline__ void in_store_at(float* zi, const int (&so)[N], int din, const float (&s1)[N],
-                                            const float (&s2)[N], const uint32_t (&w1)[N], const uint32_t (&w2)[N]) {
+                                            const float (&s2)[N], uint32_t g1, uint32_t g2) {
 #pragma unroll
   for (int u = 0; u < N; ++u) {
     const int t = (int)threadIdx.x + TB * u;
-    if (t >= din) continue;
-    zi[so[u]] = MODE == kFwdX ? xstar((w1[u] >> (t & 31)) & 1, (w2[u] >> (t & 31)) & 1, s1[u], s2[u]) : s1[u];
+    const float x = MODE == kFwdX ? xstar_from(u, g1, g2, s1[u], s2[u]) : s1[u];
+    if (t < din) zi[so[u]] = x;
   }
 }
 
@@ -303,7 +332,7 @@ __global__ __launch_bounds__(256, (conv_occupancy<MODE, NT>())) void conv_mm(con
   // the first row's input; later rows' inputs are loaded during the previous
   // row's GEMM and stored after its epilogue
   float s1[kPF], s2[kPF];
-  uint32_t w1[kPF], w2[kPF];
+  uint32_t g1, g2;
   // XCD-aware row order: workgroups are dealt round-robin over the 8 XCDs, so
   // the logical index (b mod 8) (G / 8) + b / 8 gives each XCD a contiguous
   // block of rows at every step, and the spec rows of one subdomain
@@ -312,8 +341,8 @@ __global__ __launch_bounds__(256, (conv_occupancy<MODE, NT>())) void conv_mm(con
   if ((gridDim.x & 7) == 0) row = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
   if (row < M)
     for (int t0 = 0; t0 < pl.din; t0 += 256 * kPF) {
-      in_load<MODE>(zin, ldi, bt, v, row, t0, pl.din, s1, s2, w1, w2);
-      in_store<MODE>(zi, pl, bt, v, row, t0, pl.din, s1, s2, w1, w2);
+      in_load<MODE>(zin, ldi, bt, v, row, row_prop<MODE>(bt, row), t0, pl.din, s1, s2, g1, g2);
+      in_store<MODE>(zi, pl, bt, v, row, t0, pl.din, s1, s2, g1, g2);
     }
   __syncthreads();
 
@@ -322,10 +351,11 @@ __global__ __launch_bounds__(256, (conv_occupancy<MODE, NT>())) void conv_mm(con
   for (; row < M; row += gridDim.x) {
     const int nrow = row + gridDim.x;
     const int p = bt.prop[row / bt.m];
+    const int np = nrow < M ? row_prop<MODE>(bt, nrow) : 0;
     uint32_t rec[kPF];
     float b1[kPF], b2[kPF];
     epi_first<MODE>(bt, e, row, p, 0, pl.dout, rec, b1, b2);
-    if (nrow < M) in_load<MODE>(zin, ldi, bt, v, nrow, 0, pl.din, s1, s2, w1, w2);
+    if (nrow < M) in_load<MODE>(zin, ldi, bt, v, nrow, np, 0, pl.din, s1, s2, g1, g2);
 
     // ---- the GEMM: one 16-row tile of m per wave at a time, all N tiles
     conv_gemm_row<NT, WG>(pl, zi, zo, wl, mt, kt, ntb, n_ks, n_mt, lane, wave);
@@ -440,10 +470,10 @@ __global__ __launch_bounds__(256, (conv_occupancy<MODE, NT>())) void conv_mm(con
     }
     // the next row's input (every wave is past this row's GEMM)
     if (nrow < M) {
-      in_store<MODE>(zi, pl, bt, v, nrow, 0, pl.din, s1, s2, w1, w2);
+      in_store<MODE>(zi, pl, bt, v, nrow, 0, pl.din, s1, s2, g1, g2);
       for (int t0 = 256 * kPF; t0 < pl.din; t0 += 256 * kPF) {
-        in_load<MODE>(zin, ldi, bt, v, nrow, t0, pl.din, s1, s2, w1, w2);
-        in_store<MODE>(zi, pl, bt, v, nrow, t0, pl.din, s1, s2, w1, w2);
+        in_load<MODE>(zin, ldi, bt, v, nrow, np, t0, pl.din, s1, s2, g1, g2);
+        in_store<MODE>(zi, pl, bt, v, nrow, t0, pl.din, s1, s2, g1, g2);
       }
     }
     __syncthreads();
@@ -707,6 +737,63 @@ __device__ __forceinline__ void sd_adj_sat(const Vars& v, const float* zo, int d
   }
 }
 
+// The first layer's adjoint step in the subdomain-major kernel stages x* for
+// the whole input row right after the GEMM: the lanes' words of the two sign
+// planes for every 512-input chunk of the row (at most 32 chunks) come in one
+// load per plane (lane 2u + h: word h of chunk u, as in_load), the box of the
+// first NI chunks in registers, and that of the rest (the tail) from LDS, each
+// thread holding the entries it stages itself (no barrier), rewritten when the
+// next unit's first row is staged (the property may change there only).
+__device__ __forceinline__ void sdx_words(const Batch& bt, const Vars& v, int row, uint32_t& g1, uint32_t& g2) {
+  const int lane = (int)threadIdx.x & 63;
+  const int wi = min(16 * (lane >> 1) + 2 * ((int)threadIdx.x >> 6) + (lane & 1), 2 * bt.w64 - 1);
+  g1 = reinterpret_cast<const uint32_t*>(v.xpos + (int64_t)row * bt.w64)[wi];
+  g2 = reinterpret_cast<const uint32_t*>(v.xneg + (int64_t)row * bt.w64)[wi];
+}
+
+template <int NI>
+__device__ __forceinline__ void sdx_box(const Batch& bt, int p, int din, float (&s1)[NI], float (&s2)[NI]) {
+  const int pu = __builtin_amdgcn_readfirstlane(p);
+  const float* const xl = bt.xlo + (int64_t)pu * bt.d0;
+  const float* const xu = bt.xhi + (int64_t)pu * bt.d0;
+#pragma unroll
+  for (int u = 0; u < NI; ++u) {
+    const int tc = min((int)threadIdx.x + kSdThreads * u, din - 1);
+    s1[u] = xl[tc];
+    s2[u] = xu[tc];
+  }
+}
+
+// the tail of property p's box into bxt ([2][din - kSdThreads NI]); din > kSdThreads NI
+template <int NI>
+__device__ __forceinline__ void sdx_tail_box(const Batch& bt, int p, int din, float* bxt) {
+  const int base = kSdThreads * NI, nt = din - base;
+  const int pu = __builtin_amdgcn_readfirstlane(p);
+  const float* const xl = bt.xlo + (int64_t)pu * bt.d0 + base;
+  const float* const xu = bt.xhi + (int64_t)pu * bt.d0 + base;
+  for (int t = (int)threadIdx.x; t < nt; t += kSdThreads) {
+    bxt[t] = xl[t];
+    bxt[nt + t] = xu[t];
+  }
+}
+
+template <int NI>
+__device__ __forceinline__ void sdx_stage(float* zi, const ConvPlan& pl, int din, const float (&s1)[NI],
+                                          const float (&s2)[NI], uint32_t g1, uint32_t g2, const float* bxt) {
+#pragma unroll
+  for (int u = 0; u < NI; ++u) {
+    const int t = (int)threadIdx.x + kSdThreads * u;
+    const float x = xstar_from(u, g1, g2, s1[u], s2[u]);
+    if (t < din) zi[staged(pl, t)] = x;
+  }
+  const int base = kSdThreads * NI, nt = din - base;
+  for (int u = NI; kSdThreads * u < din; ++u) {
+    const int t = (int)threadIdx.x + kSdThreads * u, i = min(t - base, nt - 1);
+    const float x = xstar_from(u, g1, g2, bxt[i], bxt[nt + i]);
+    if (t < din) zi[staged(pl, t)] = x;
+  }
+}
+
 // occupancy (waves per SIMD) of the subdomain-major kernels
 template <int MODE, int NJ, int NI>
 constexpr int conv_sd_occupancy() {
@@ -737,6 +824,8 @@ __global__ __launch_bounds__(kSdThreads, (conv_sd_occupancy<MODE, NJ, NI>())) vo
   float* const bsh = reinterpret_cast<float*>(sct + n_mt * NT * 64);  // bias per neuron (not for concretisation)
   // partial tiles of a split K (below): [kSdWaves][NT][64] floatx4
   floatx4* const kpart = reinterpret_cast<floatx4*>(bsh + (MODE != kBwdConc ? (pl.dout + 3) & ~3 : 0));
+  // the first layer's adjoint step: the tail of the box (sdx_tail_box)
+  float* const bxt = reinterpret_cast<float*>(kpart + (n_mt < kSdWaves && pl.kpad >= 32 ? kSdWaves * NT * 64 : 0));
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   // With fewer 16-row tiles than waves (a small output plane with a long K),
   // each tile's K passes are split over ksp waves (a power of two, a pass at
@@ -777,7 +866,7 @@ __global__ __launch_bounds__(kSdThreads, (conv_sd_occupancy<MODE, NJ, NI>())) vo
   // the staged slots of this thread's first NI kSdThreads inputs (the same for every row)
   int so[NI];
 #pragma unroll
-  for (int u = 0; u < NI; ++u) so[u] = staged(pl, min(tid + kSdThreads * u, pl.din - 1));
+  for (int u = 0; u < NI; ++u) so[u] = MODE == kFwdX ? 0 : staged(pl, min(tid + kSdThreads * u, pl.din - 1));
 
   // the first row of this workgroup's first unit: staged before the loop;
   // later units' first rows are staged by the previous row, like any next row
@@ -785,10 +874,18 @@ __global__ __launch_bounds__(kSdThreads, (conv_sd_occupancy<MODE, NJ, NI>())) vo
     const int b0 = blockIdx.x / upb;
     const int row0 = b0 * m + ((int)blockIdx.x - b0 * upb) * mu;
     float s1[NI], s2[NI];
-    uint32_t w1[NI], w2[NI];
-    for (int t0 = 0; t0 < pl.din; t0 += kSdThreads * NI) {
-      in_load<MODE, NI, kSdThreads>(zin, ldi, bt, v, row0, t0, pl.din, s1, s2, w1, w2);
-      in_store<MODE, NI, kSdThreads>(zi, pl, bt, v, row0, t0, pl.din, s1, s2, w1, w2);
+    uint32_t g1, g2;
+    if constexpr (MODE == kFwdX) {
+      const int p0 = bt.prop[b0];
+      if (pl.din > kSdThreads * NI) sdx_tail_box<NI>(bt, p0, pl.din, bxt);
+      sdx_box<NI>(bt, p0, pl.din, s1, s2);
+      sdx_words(bt, v, row0, g1, g2);
+      sdx_stage<NI>(zi, pl, pl.din, s1, s2, g1, g2, bxt);
+    } else {
+      for (int t0 = 0; t0 < pl.din; t0 += kSdThreads * NI) {
+        in_load<MODE, NI, kSdThreads>(zin, ldi, bt, v, row0, 0, t0, pl.din, s1, s2, g1, g2);
+        in_store<MODE, NI, kSdThreads>(zi, pl, bt, v, row0, t0, pl.din, s1, s2, g1, g2);
+      }
     }
   }
   const int n_ks = pl.kpad >> 2;
@@ -828,13 +925,21 @@ __global__ __launch_bounds__(kSdThreads, (conv_sd_occupancy<MODE, NJ, NI>())) vo
     const int nunit = unit + gridDim.x;
     const int nb = nunit / upb;
     const int nfirst = nunit < n_units ? nb * m + (nunit - nb * upb) * mu : -1;
+    const int nprop = MODE == kFwdX && nunit < n_units ? bt.prop[nb] : 0;  // its property
     __syncthreads();  // the unit's first row is staged
 
     for (int row = r0; row < r1; ++row, par ^= 1) {
       const int nrow = row + 1 < r1 ? row + 1 : nfirst;
       float s1[NI], s2[NI];
-      uint32_t w1[NI], w2[NI];
-      if (nrow >= 0) in_load<MODE, NI, kSdThreads>(zin, ldi, bt, v, nrow, 0, pl.din, s1, s2, w1, w2);
+      uint32_t g1, g2;
+      if (nrow >= 0) {
+        if constexpr (MODE == kFwdX) {
+          sdx_box<NI>(bt, row + 1 < r1 ? p : nprop, pl.din, s1, s2);
+          sdx_words(bt, v, nrow, g1, g2);
+        } else {
+          in_load<MODE, NI, kSdThreads>(zin, ldi, bt, v, nrow, 0, 0, pl.din, s1, s2, g1, g2);
+        }
+      }
 
       if (NJ > 2 || ksp == 1) {
         conv_gemm_row<NT, WG, kSdWaves, true>(pl, zi, zo, wl, mt, kt, ntb, n_ks, n_mt, lane, wave, sct);
@@ -868,7 +973,15 @@ __global__ __launch_bounds__(kSdThreads, (conv_sd_occupancy<MODE, NJ, NI>())) vo
       __syncthreads();
       // every wave is past this row's GEMM: zi takes the next row (the rest
       // of a long input row after the epilogue)
-      if (nrow >= 0) in_store_at<MODE, NI, kSdThreads>(zi, so, pl.din, s1, s2, w1, w2);
+      if (nrow >= 0) {
+        if constexpr (MODE == kFwdX) {
+          // (the next unit's first row: its property's tail of the box first)
+          if (row + 1 == r1 && pl.din > kSdThreads * NI) sdx_tail_box<NI>(bt, nprop, pl.din, bxt);
+          sdx_stage<NI>(zi, pl, pl.din, s1, s2, g1, g2, bxt);
+        } else {
+          in_store_at<MODE, NI, kSdThreads>(zi, so, pl.din, s1, s2, g1, g2);
+        }
+      }
 
       // ---- epilogue: every operand is in registers.  One wait for every
       // outstanding load here (the row's variables and the staged input have
@@ -936,10 +1049,10 @@ __global__ __launch_bounds__(kSdThreads, (conv_sd_occupancy<MODE, NJ, NI>())) vo
           red[par][wave][1] = cer;
         }
       }
-      if (nrow >= 0)
+      if (MODE != kFwdX && nrow >= 0)
         for (int t0 = kSdThreads * NI; t0 < pl.din; t0 += kSdThreads * NI) {
-          in_load<MODE, NI, kSdThreads>(zin, ldi, bt, v, nrow, t0, pl.din, s1, s2, w1, w2);
-          in_store<MODE, NI, kSdThreads>(zi, pl, bt, v, nrow, t0, pl.din, s1, s2, w1, w2);
+          in_load<MODE, NI, kSdThreads>(zin, ldi, bt, v, nrow, 0, t0, pl.din, s1, s2, g1, g2);
+          in_store<MODE, NI, kSdThreads>(zi, pl, bt, v, nrow, t0, pl.din, s1, s2, g1, g2);
         }
       // the next row's own variables (the unit's status records and chords
       // stay); the next unit's are loaded at its start
@@ -1151,13 +1264,16 @@ void conv_plan_sd(int mode, ConvPlan& pl) {
       }
   }
   if (!nj) return;
+  // the first layer's adjoint step reads the sign words of at most 32 chunks of kSdThreads inputs
+  if (mode == kFwdX && pl.din > 32 * kSdThreads) return;
   pl.nj = nj;
   pl.ni = ni;
   const void* k = sd_kernel_mode(mode, pl.nt, pl.wg != 0, nj, ni);
   // the plan's LDS, the spare output slot (padded), the scatter table and the bias
   pl.smem_sd = pl.smem + 32 + (pl.mpad >> 4) * pl.nt * 64 * (int)sizeof(int4) +
                (mode == kBwdConc ? 0 : ((pl.dout + 3) & ~3) * (int)sizeof(float)) +
-               ((pl.mpad >> 4) < kSdWaves && pl.kpad >= 32 ? kSdWaves * pl.nt * 64 * 16 : 0);  // split-K partial tiles
+               ((pl.mpad >> 4) < kSdWaves && pl.kpad >= 32 ? kSdWaves * pl.nt * 64 * 16 : 0) +  // split-K partial tiles
+               (mode == kFwdX ? 2 * std::max(0, pl.din - kSdThreads * ni) * (int)sizeof(float) : 0);  // box tail
   int dev = 0, cus = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
       hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, kSdThreads, pl.smem_sd) != hipSuccess) {
