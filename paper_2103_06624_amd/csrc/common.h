@@ -328,18 +328,34 @@ __device__ __forceinline__ float relax_fwd(const Batch& bt, const Vars& v, const
   return relax_fwd_value(bt, v, ri, rec, ch, a_st, al, pc, zb);
 }
 
+// Butterfly sums by DPP moves within rows of 16 lanes (no LDS round trip).
+// Each step adds the values of lanes l and l ^ o; once the lanes of a quad
+// (of a half row) hold equal values, the half-row (row) mirror pairs every
+// lane with one of the partner group, so the additions, and with them the
+// roundings, are those of the xor butterfly (float addition commutes).
+template <int kCtrl>
+__device__ __forceinline__ float dpp_step(float x) {
+  return x + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), kCtrl, 0xF, 0xF, true));
+}
+
 __device__ __forceinline__ float wave_sum16(float x) {
-  // sum over the 16 lanes that share lane/16 (xor within 16-lane groups)
-  x += __shfl_xor(x, 1, 64);
-  x += __shfl_xor(x, 2, 64);
-  x += __shfl_xor(x, 4, 64);
-  x += __shfl_xor(x, 8, 64);
+  // sum over the 16 lanes that share lane/16 (xor 1, 2, 4, 8)
+  x = dpp_step<0xB1>(x);   // quad_perm [1, 0, 3, 2]: lane ^ 1
+  x = dpp_step<0x4E>(x);   // quad_perm [2, 3, 0, 1]: lane ^ 2
+  x = dpp_step<0x141>(x);  // row_half_mirror: the other quad of the half row
+  x = dpp_step<0x140>(x);  // row_mirror: the other half of the row
   return x;
 }
 
 __device__ __forceinline__ float wave_sum(float x) {
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-  return x;
+  // the row sums, then xor 16 and xor 32 across rows as
+  // (r0 + r1) + (r2 + r3) in every lane
+  x = wave_sum16(x);
+  const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 0));
+  const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 16));
+  const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 32));
+  const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 48));
+  return (r0 + r1) + (r2 + r3);
 }
 
 }  // namespace cvb
