@@ -213,16 +213,24 @@ def ingest_traffic(args):
 def counters_summary(args):
     """Per-kernel counter figures of the timing pass (markdown table) from
     counter runs of --profile-only: MFMA busy = SQ_VALU_MFMA_BUSY_CYCLES /
-    (GRBM_GUI_ACTIVE / 8 XCDs x 1024 SIMDs), instructions per dispatch."""
-    prof = last_json_line(args.counters_summary[0])
-    merged = {}
-    for d in args.counters_summary[1:]:
+    (GRBM_GUI_ACTIVE / 8 XCDs x 1024 SIMDs), instructions per dispatch.
+    Arguments: a run's printed output, then its counter directories; or
+    (output, directory) pairs, one per run, where the runs' autotuners may
+    have chosen different plans (a kernel is then summarised from the runs
+    that hold it)."""
+    a = args.counters_summary
+    paired = len(a) % 2 == 0 and all(os.path.isfile(x) for x in a[0::2]) and all(os.path.isdir(x) for x in a[1::2])
+    runs = [(a[i], a[i + 1]) for i in range(0, len(a), 2)] if paired else [(a[0], d) for d in a[1:]]
+    merged, us, tf = {}, {}, {}
+    for out, d in runs:
+        prof = last_json_line(out)
+        for k in prof["kernels"]:
+            us.setdefault(k["name"], k["avg_us"])
+            tf.setdefault(k["name"], k["tflops"])
         for name, lst in name_profile_pass(counter_dispatches(d), prof).items():
             m = merged.setdefault(name, {})
             for c in {c for x in lst for c in x["c"]}:
                 m[c] = sum(x["c"].get(c, 0.0) for x in lst) / len(lst)
-    us = {k["name"]: k["avg_us"] for k in prof["kernels"]}
-    tf = {k["name"]: k["tflops"] for k in prof["kernels"]}
     print("| kernel | avg us (HIP events) | TFLOP/s | MFMA busy | VALU insts/disp (M) | MFMA insts/disp (M) | "
           "LDS insts/disp (M) | LDS bank conflict / LDS active |")
     print("|---|---|---|---|---|---|---|---|")
