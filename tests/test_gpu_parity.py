@@ -282,7 +282,7 @@ def test_sound_root_bounds_enclose_sampled_preactivations():
                 off += d
 
 
-@pytest.mark.parametrize("name", ["mlp_small", "cnn_base"])
+@pytest.mark.parametrize("name", ["mlp_small", "cnn_base", "cnn_odd", "mlp_deep"])
 def test_optimised_root_bounds_parity(name):
     """Intermediate bounds each maximised over its own alpha' (10 Adam steps):
     against the oracle's, at least as tight as the library's CROWN bounds, and
@@ -483,8 +483,11 @@ def test_deterministic_and_graph_replay(name, nparts):
         assert np.array_equal(best2.cpu().numpy(), r1[0]) and np.array_equal(a.cpu().numpy(), r1[1])
 
 
-def test_autotune_keeps_parity():
-    wl, orc, pb = problem("mlp_deep")
+@pytest.mark.parametrize("name", ["mlp_deep", "cnn_base", "cnn_odd"])
+def test_autotune_keeps_parity(name):
+    """After the autotuner's choice of dense tilings and plans and (on a CNN)
+    of the conv kernel variant per layer and direction."""
+    wl, orc, pb = problem(name)
     pb.autotune()
     alpha, beta = cases.random_vars(orc, seed=4)
     lb = pb.eval(dev(alpha), dev(beta)).cpu().numpy()
