@@ -170,6 +170,8 @@ struct cv_bound {
   std::vector<std::vector<int>> h_ucount_layer;
   uint32_t* d_kind = nullptr;
   int *d_split_dom = nullptr, *d_split_col = nullptr;
+  uint8_t* d_defer = nullptr;  // [nd] 1 on the columns of conv layers (their split steps run after the adjoint)
+  bool has_conv = false;
   int8_t* d_side = nullptr;
   int forced_tiling = -1, forced_conv = -1;  // cv_bound_set_tiling / cv_bound_set_conv_variant
   int parts_req = 0;  // cv_bound_set_parts (0: two sub-batches from kPartsMinRows rows on)
@@ -992,6 +994,15 @@ int build(cv_bound* h, const cv_layer* layers, int n_layers, int P, const float*
   rc = upload_layers(h, layers, n_layers, s);
   if (rc) return rc;
   DevMem& M = h->mem;
+  {
+    std::vector<uint8_t> defer(std::max(1, nd), 0);
+    for (int i = 1; i < n_layers; ++i)
+      if (layers[i - 1].type == CV_LAYER_CONV2D) {
+        h->has_conv = true;
+        std::fill(defer.begin() + h->offs[i - 1], defer.begin() + h->offs[i - 1] + h->dims[i], (uint8_t)1);
+      }
+    if ((rc = M.upload(&h->d_defer, defer.data(), defer.size(), s))) return rc;
+  }
   int *d_ucount, *d_cidx;
   float *d_l, *d_u, *d_xlo, *d_xhi, *d_adef;
   float2* d_chord;
@@ -1745,6 +1756,9 @@ int enqueue_fwd(cv_bound* h, const float* alpha, const float* beta, float* ga, f
       if (pf) pf->end();
     } else {
       ConvArgs a{in, lda, ly.fwd, h->R, last, h->bt, v, e};
+      // with Adam, the split neurons' steps wait for split_adam_k after the
+      // pass: their reads would otherwise stall the epilogue
+      if (v.adam && h->g_beta) a.v.gsplit = h->g_beta;
       if (pf) pf->begin(std::string(mode == kFwdX ? "conv_fwd_x_" : "conv_fwd_") + conv_tag(ly.g),
                         2.0 * rows * conv_macs(ly.g), io);
       if (launch_conv_fwd(mode, a, s)) return fail(CV_ESHAPE, "unsupported conv channels");
@@ -1778,6 +1792,13 @@ int enqueue_fwd(cv_bound* h, const float* alpha, const float* beta, float* ga, f
                       rows * h->dims[lo - 1] * 4.0 + (double)h->B * (h->nd - h->offs[lo - 1]) * 2.0 +
                           unst * 4.0 * (ad ? 7 : 3));
     launch_chain_fwd(ca, s);
+    if (pf) pf->end();
+  }
+  if (v.adam && h->g_beta && h->has_conv && h->nnz > 0) {
+    Vars w = v;
+    w.gsplit = h->g_beta;
+    if (pf) pf->begin("split_adam", 0.0, (double)h->nnz * h->m * 4.0 * 10);
+    launch_split_adam(h->bt, w, h->d_split_dom, h->d_split_col, h->d_defer, h->nnz, s);
     if (pf) pf->end();
   }
   HIPCHK(hipGetLastError());

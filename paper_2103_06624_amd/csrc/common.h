@@ -90,6 +90,11 @@ struct Vars {
   float* va;
   float* mb;
   float* vb;
+  // With adam set, a conv layer's adjoint may leave its split neurons' steps
+  // to split_adam_k after the pass (their variables' reads would otherwise
+  // wait inside the epilogue): it writes each split neuron's beta gradient
+  // here ([nnz, m]) and touches neither variable.
+  float* gsplit;
 };
 
 // One projected Adam ascent step on entry i (Kingma & Ba: beta1 0.9, beta2
@@ -302,7 +307,9 @@ __device__ __forceinline__ float relax_fwd_value(const Batch& bt, const Vars& v,
   // a split neuron is root-unstable, so it owns an alpha entry: its gradient is 0
   const int64_t ai = ri.abase + bt.cidx[pc];
   const float gb = pos ? -zb : zb;
-  if (v.adam) {
+  if (v.gsplit) {  // (no var_new: the passes that defer never ask for it)
+    v.gsplit[bi] = gb;
+  } else if (v.adam) {
     const float bn = adam_apply(v.beta_w, v.mb, v.vb, bi, gb, v.lr_b, v.bc1, v.bc2, 0.f, INFINITY);
     adam_apply(v.alpha_w, v.ma, v.va, ai, 0.f, v.lr_a, v.bc1, v.bc2, 0.f, 1.f);
     if (var_new) *var_new = bn;

@@ -680,7 +680,9 @@ __device__ __forceinline__ void adj_split(const Batch& bt, const Vars& v, const 
   const int64_t bi = (int64_t)(bsp & kSplitMask) * bt.m + ri.k;
   const int64_t ai = ri.abase + (-2 - cix);
   const float gb = (bsp & kSidePos) ? -zb : zb;
-  if (v.adam) {
+  if (v.gsplit) {  // the steps: split_adam_k, after the pass
+    v.gsplit[bi] = gb;
+  } else if (v.adam) {
     adam_apply(v.beta_w, v.mb, v.vb, bi, gb, v.lr_b, v.bc1, v.bc2, 0.f, INFINITY);
     adam_apply(v.alpha_w, v.ma, v.va, ai, 0.f, v.lr_a, v.bc1, v.bc2, 0.f, 1.f);
   } else {

@@ -325,6 +325,10 @@ void launch_joint_weights(float* w, const float* dL, const float* dU, const uint
 // copy the variables of the rows flagged in improved into abest / bbest
 void launch_keep_best(const float* alpha, const float* beta, float* abest, float* bbest, const int* improved,
                       const Batch& bt, hipStream_t s);
+// the split neurons' Adam steps a conv layer's adjoint deferred (Vars::gsplit):
+// every split t in a column flagged in defer [nd], every spec row
+void launch_split_adam(const Batch& bt, const Vars& v, const int* split_dom, const int* split_col,
+                       const uint8_t* defer, int64_t nnz, hipStream_t s);
 void launch_adam(float* x, const float* g, float* m1, float* m2, int64_t n, float lr, float bc1, float bc2,
                  float lo, float hi, hipStream_t s);
 void launch_fill(float* p, float v, int64_t n, hipStream_t s);

@@ -291,6 +291,26 @@ __global__ void adam_k(float* x, const float* __restrict__ g, float* m1, float* 
   adam_apply(x, m1, m2, i, g[i], lr, bc1, bc2, lo, hi);
 }
 
+// The steps a conv layer's adjoint left to after the pass (Vars::gsplit):
+// for split t of a layer whose columns are flagged in defer and spec row k,
+// the Adam step of beta[t, k] on its staged gradient and the zero-gradient
+// step of the split neuron's alpha entry in that row -- the fused epilogue's
+// steps, in the same arithmetic.
+__global__ void split_adam_k(Batch bt, Vars v, const int* __restrict__ split_dom, const int* __restrict__ split_col,
+                             const uint8_t* __restrict__ defer, int64_t nnz) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nnz * bt.m) return;
+  const int64_t t = i / bt.m;
+  const int k = (int)(i - t * bt.m);
+  const int col = split_col[t];
+  if (!defer[col]) return;
+  const int b = split_dom[t];
+  const int p = bt.prop[b];
+  const int64_t ai = bt.rbase[(int64_t)b * bt.m + k] + bt.cidx[(int64_t)p * bt.nd + col];
+  adam_apply(v.beta_w, v.mb, v.vb, i, v.gsplit[i], v.lr_b, v.bc1, v.bc2, 0.f, INFINITY);
+  adam_apply(v.alpha_w, v.ma, v.va, ai, 0.f, v.lr_a, v.bc1, v.bc2, 0.f, 1.f);
+}
+
 __global__ void fill_k(float* p, float v, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -352,6 +372,13 @@ void launch_keep_best(const float* alpha, const float* beta, float* abest, float
                       const Batch& bt, hipStream_t s) {
   if (bt.n_rows > 0) launch_k(keep_best_k, (unsigned)bt.n_rows, 256, 0, s, alpha, beta, abest, bbest, improved, bt);
 }
+void launch_split_adam(const Batch& bt, const Vars& v, const int* split_dom, const int* split_col,
+                       const uint8_t* defer, int64_t nnz, hipStream_t s) {
+  const int64_t n = nnz * bt.m;
+  if (n <= 0) return;
+  split_adam_k<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(bt, v, split_dom, split_col, defer, nnz);
+}
+
 void launch_adam(float* x, const float* g, float* m1, float* m2, int64_t n, float lr, float bc1, float bc2, float lo,
                  float hi, hipStream_t s) {
   if (n > 0) adam_k<<<nblk(n, 256), 256, 0, s>>>(x, g, m1, m2, n, lr, bc1, bc2, lo, hi);
