@@ -97,8 +97,6 @@ struct Vars {
   float* gsplit;
 };
 
-// One projected Adam ascent step on entry i (Kingma & Ba: beta1 0.9, beta2
-// 0.999, eps 1e-8; bc1 = 1 - 0.9^t, bc2 = 1 - 0.999^t), clamped to [lo, hi].
 // The exact ReLU of the network at x* (the primal side of Alg. 1): clears
 // *sat_row when zb breaks the split of a split neuron (z >= 0 for a z >= 0
 // split, z <= 0 for a z < 0 split: the strict side closed, as in the LP).
@@ -111,16 +109,16 @@ __device__ __forceinline__ float true_relu(uint32_t rec, float zb, int* sat_row)
   return fmaxf(zb, 0.f);
 }
 
-// adam_step takes the entry's current value and moments as arguments (read
-// ahead by the caller); adam_apply reads them itself.
-__device__ __forceinline__ float adam_step(float* x, float* m1, float* m2, int64_t i, float g, float lr, float bc1,
-                                           float bc2, float lo, float hi, float xv, float m1v, float m2v) {
+// One projected Adam ascent step (Kingma & Ba: beta1 0.9, beta2 0.999, eps
+// 1e-8; bc1 = 1 - 0.9^t, bc2 = 1 - 0.999^t), clamped to [lo, hi], from an
+// entry's value xv, moments m1v, m2v and gradient g: the new moments in a, b
+// and the new value returned.
+__device__ __forceinline__ float adam_values(float g, float lr, float bc1, float bc2, float lo, float hi, float xv,
+                                             float m1v, float m2v, float& a, float& b) {
   // fmaf keeps the products with the moments next to g: a product of a moment
   // alone would be hoisted to where the moment is read ahead, stalling there
-  const float a = fmaf(0.9f, m1v, 0.1f * g);
-  const float b = fmaf(0.999f, m2v, 0.001f * g * g);
-  m1[i] = a;
-  m2[i] = b;
+  a = fmaf(0.9f, m1v, 0.1f * g);
+  b = fmaf(0.999f, m2v, 0.001f * g * g);
   // bias corrections as reciprocals (uniform across the launch); the square
   // root and the reciprocal are the hardware's single instructions (each
   // within 1 ulp; the correctly rounded library forms cost some 25 more
@@ -128,7 +126,18 @@ __device__ __forceinline__ float adam_step(float* x, float* m1, float* m2, int64
   // lr (a / bc1) / (sqrt(b / bc2) + 1e-8)
   const float den = __builtin_amdgcn_sqrtf(b * (1.f / bc2)) + 1e-8f;
   const float step = lr * a * (1.f / bc1) * __builtin_amdgcn_rcpf(den);
-  const float xn = fminf(fmaxf(xv + step, lo), hi);
+  return fminf(fmaxf(xv + step, lo), hi);
+}
+
+// The step on entry i of x (moments m1, m2): adam_step takes the entry's
+// current value and moments as arguments (read ahead by the caller);
+// adam_apply reads them itself.
+__device__ __forceinline__ float adam_step(float* x, float* m1, float* m2, int64_t i, float g, float lr, float bc1,
+                                           float bc2, float lo, float hi, float xv, float m1v, float m2v) {
+  float a, b;
+  const float xn = adam_values(g, lr, bc1, bc2, lo, hi, xv, m1v, m2v, a, b);
+  m1[i] = a;
+  m2[i] = b;
   x[i] = xn;
   return xn;
 }

@@ -81,7 +81,7 @@ __device__ __forceinline__ void epi_first(const Batch& bt, const Epi& e, int row
 // N inputs of a lane need bit (lane % 32) of 2N 32-bit words of each plane
 // per wave (inputs u: words (t0 + TB u) / 32 + 2 wave + {0, 1}): lane 2u + h
 // loads word h of input u into g1 (plane A(0) > 0) and g2 (A(0) < 0), and
-// the lanes fetch theirs from it when the row is staged (sign_bits).
+// the lanes fetch theirs from it when the row is staged (xstar_from).
 template <int MODE, int N, int TB = 256>
 __device__ __forceinline__ void in_load(const float* zin, int ldi, const Batch& bt, const Vars& v, int row, int p,
                                         int t0, int din, float (&s1)[N], float (&s2)[N], uint32_t& g1,

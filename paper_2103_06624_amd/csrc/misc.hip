@@ -308,7 +308,15 @@ __global__ void split_adam_k(Batch bt, Vars v, const int* __restrict__ split_dom
   const int p = bt.prop[b];
   const int64_t ai = bt.rbase[(int64_t)b * bt.m + k] + bt.cidx[(int64_t)p * bt.nd + col];
   adam_apply(v.beta_w, v.mb, v.vb, i, v.gsplit[i], v.lr_b, v.bc1, v.bc2, 0.f, INFINITY);
-  adam_apply(v.alpha_w, v.ma, v.va, ai, 0.f, v.lr_a, v.bc1, v.bc2, 0.f, 1.f);
+  // the alpha entry's zero-gradient step often leaves it and its moments as
+  // they were (moments at zero): only what changed is stored (scattered
+  // entries, one per row and split)
+  const float xv = v.alpha_w[ai], m1v = v.ma[ai], m2v = v.va[ai];
+  float m1n, m2n;
+  const float xn = adam_values(0.f, v.lr_a, v.bc1, v.bc2, 0.f, 1.f, xv, m1v, m2v, m1n, m2n);
+  if (__float_as_uint(m1n) != __float_as_uint(m1v)) v.ma[ai] = m1n;
+  if (__float_as_uint(m2n) != __float_as_uint(m2v)) v.va[ai] = m2n;
+  if (__float_as_uint(xn) != __float_as_uint(xv)) v.alpha_w[ai] = xn;
 }
 
 __global__ void fill_k(float* p, float v, int64_t n) {
