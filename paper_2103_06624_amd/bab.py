@@ -31,7 +31,9 @@ intercept -l u / (u - l) of their upper chord, ties by layer then index; a
 subdomain splits the first neuron of that order it has not split yet.
 
 sound=True runs the bounds in sound mode (cv_bound_set_sound): every lower
-bound is then rigorous in float32, so a 'verified' verdict is a proof.
+bound is then evaluated in float64 with a rigorous rounding margin and
+rounded down to float, so a 'verified' verdict is a proof (given sound root
+bounds, e.g. api.root_bounds(..., sound=True)).
 """
 from __future__ import annotations
 
