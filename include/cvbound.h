@@ -97,7 +97,8 @@ int cv_bound_root_bounds_sound(const cv_layer *layers, int32_t n_layers, int32_t
  * CROWN's default (learning rate lr_alpha, decay lr_decay per step), keeping
  * the best iterate; each layer is built on the optimised bounds of the layers
  * below.  Each bound is therefore at least as tight as CROWN's.  sound = 1
- * applies the rigorous float32 margin (cv_bound_set_sound) to every bound.
+ * reports every bound as sound mode does (cv_bound_set_sound: float64 with a
+ * rigorous rounding margin, rounded outward to float).
  * iters = 0 is cv_bound_root_bounds (sound = 0) or _sound (sound = 1).
  * CV_EINVAL on iters < 0, sound outside 0/1 or non-finite rates. */
 int cv_bound_root_bounds_opt(const cv_layer *layers, int32_t n_layers, int32_t n_props,

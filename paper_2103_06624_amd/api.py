@@ -47,7 +47,8 @@ def make_layers(layers):
 
 def root_bounds(layers, x_lo, x_hi, sound=False, opt_iters=0, lr_alpha=0.1, decay=0.98):
     """Per-layer CROWN intermediate bounds on the GPU: (l, u) float32 [P, sum d_i];
-    sound: moved outward by the rigorous float32 rounding margin; opt_iters > 0:
+    sound: evaluated in float64 with a rigorous rounding margin and rounded
+    outward (sound mode); opt_iters > 0:
     each bound maximised over its own alpha' by that many Adam steps."""
     arr, keep = make_layers(layers)
     x_lo = np.ascontiguousarray(x_lo, np.float32)

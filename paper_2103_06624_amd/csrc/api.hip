@@ -2295,7 +2295,8 @@ int grad_noalloc(cv_bound* h, const float* alpha, const float* beta, float* lb, 
 namespace {
 
 // Root bounds of every ReLU layer, one sub-network at a time (layers 1..i,
-// specification [I; -I] on layer i); sound: with the rigorous float32 margin.
+// specification [I; -I] on layer i); sound: evaluated as sound mode does (float64
+// with a rigorous rounding margin, rounded outward).
 int root_bounds(const cv_layer* layers, int32_t n_layers, int32_t n_props, const float* x_lo, const float* x_hi,
                 float* l_out, float* u_out, bool sound, void* stream, int iters = 0, float lr_alpha = 0.f,
                 float decay = 1.f) {
@@ -2330,7 +2331,7 @@ int root_bounds(const cv_layer* layers, int32_t n_layers, int32_t n_props, const
     rc = build(&hb, sub.data(), i, n_props, x_lo, x_hi, 2 * d, sp, lsub.data(), usub.data(), n_props, prop.data(),
                sptr.data(), nullptr, nullptr, nullptr, s);
     if (rc) return rc;
-    if (sound) {  // the bounds are lowered (l) and raised (u) by the rigorous float32 margin
+    if (sound) {  // the bounds come from the float64 pass with its margin, rounded outward
       if ((rc = prepare_sound(&hb, sub.data(), x_lo, x_hi, lsub.data(), usub.data(), nullptr, true, s))) return rc;
       hb.sound = true;
       hb.bt.sw = hb.sw;
