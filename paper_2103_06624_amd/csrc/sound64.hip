@@ -154,30 +154,34 @@ __global__ __launch_bounds__(256) void dense64_k(Pass64 q, Lay64 y) {
 // position (ci, iy, ix), A(i-1) = sum over (co, ky, kx) with oy = (iy + pad -
 // ky) / stride and ox likewise whole and inside the output plane of
 // Lambda(i)[co, oy, ox] W[co, ci, ky, kx], in double.
-__global__ __launch_bounds__(256) void conv64_k(Pass64 q, Lay64 y, ConvGeom g) {
+// The weights are staged in LDS after the row when they fit (w_lds), else
+// read from global memory; the same values and order either way.
+__global__ __launch_bounds__(256) void conv64_k(Pass64 q, Lay64 y, ConvGeom g, int w_lds) {
   extern __shared__ double lam_s[];
   __shared__ double red[4];
   const int row = blockIdx.x;
   const RowInfo ri = row_info(q.bt, row);
+  float* const w_s = reinterpret_cast<float*>(lam_s + y.K);
+  const float* const W = w_lds ? w_s : y.W;
   for (int k = threadIdx.x; k < y.K; k += 256) lam_s[k] = y.in[(int64_t)row * y.ldi + k];
+  if (w_lds)
+    for (int t = threadIdx.x; t < g.co * g.ci * g.k * g.k; t += 256) w_s[t] = y.W[t];
   __syncthreads();
   double cst = 0.0, err = 0.0, sq = 0.0;
   for (int j = threadIdx.x; j < y.N; j += 256) {
     const int ci = j / (g.hi * g.wi), rem = j - ci * g.hi * g.wi;
     const int iy = rem / g.wi, ix = rem - iy * g.wi;
     double a = 0.0;
-    for (int ky = 0; ky < g.k; ++ky) {
-      const int ty = iy + g.p - ky;
-      if (ty < 0 || ty % g.s) continue;
-      const int oy = ty / g.s;
+    // the taps with iy + p - ky a non-negative multiple of the stride, in
+    // ascending ky (then kx, then co): ky = ry, ry + s, ... and oy = oy0, oy0 - 1, ...
+    const int ry = (iy + g.p) % g.s, rx = (ix + g.p) % g.s;
+    const int oy0 = (iy + g.p - ry) / g.s, ox0 = (ix + g.p - rx) / g.s;
+    for (int ky = ry, oy = oy0; ky < g.k && oy >= 0; ky += g.s, --oy) {
       if (oy >= g.ho) continue;
-      for (int kx = 0; kx < g.k; ++kx) {
-        const int tx = ix + g.p - kx;
-        if (tx < 0 || tx % g.s) continue;
-        const int ox = tx / g.s;
+      for (int kx = rx, ox = ox0; kx < g.k && ox >= 0; kx += g.s, --ox) {
         if (ox >= g.wo) continue;
         for (int co = 0; co < g.co; ++co)
-          a += lam_s[(co * g.ho + oy) * g.wo + ox] * (double)y.W[(((int64_t)co * g.ci + ci) * g.k + ky) * g.k + kx];
+          a += lam_s[(co * g.ho + oy) * g.wo + ox] * (double)W[((co * g.ci + ci) * g.k + ky) * g.k + kx];
       }
     }
     if (y.conc) {
@@ -242,7 +246,10 @@ void launch_dense64(const Pass64& q, const Lay64& y, hipStream_t s) {
 }
 
 void launch_conv64(const Pass64& q, const Lay64& y, const ConvGeom& g, hipStream_t s) {
-  if (q.bt.n_rows > 0) launch_k(conv64_k, (unsigned)q.bt.n_rows, 256, (uint32_t)(y.K * sizeof(double)), s, q, y, g);
+  if (q.bt.n_rows <= 0) return;
+  const size_t row_b = (size_t)y.K * sizeof(double), w_b = (size_t)g.co * g.ci * g.k * g.k * sizeof(float);
+  const int w_lds = row_b + w_b <= 48 * 1024 ? 1 : 0;
+  launch_k(conv64_k, (unsigned)q.bt.n_rows, 256, (uint32_t)(row_b + (w_lds ? w_b : 0)), s, q, y, g, w_lds);
 }
 
 void launch_finalize64(const Pass64& q, const Fin64& f, hipStream_t s) {
