@@ -12,9 +12,9 @@
 // float: the reported bound lies below the exact bound of the same relaxation
 // by that margin (about 1e-13 of the terms' magnitudes) plus one float ulp.
 //
-// One workgroup per batch row for the convolution layers and up to four rows
-// per workgroup for the dense ones (the rows' inputs in LDS), one wave per
-// row for the top layer.  These kernels run once per evaluation in sound
+// One workgroup per batch row for the dense and convolution layers (four
+// rows per workgroup for dense layers on large batches; the rows' inputs in
+// LDS), one wave per row for the top layer.  These kernels run once per evaluation in sound
 // mode, not in the optimiser's loop.
 #include "common.h"
 #include "internal.h"
@@ -222,12 +222,39 @@ __global__ __launch_bounds__(256) void top64_k(Pass64 q, Top64 t) {
 }
 
 // Back-substitution through dense layer i: A(i-1)_j = sum_k Lambda(i)_k W(i)_kj
-// in double, then the relaxation of layer i-1 (or the concretisation).  Up
-// to kDenseRows consecutive rows per workgroup (rpb, all of them in LDS), so
-// that each weight read serves every one of them; each row's sums keep the
-// one-row order.
+// in double, then the relaxation of layer i-1 (or the concretisation).
+__global__ __launch_bounds__(256) void dense64_k(Pass64 q, Lay64 y) {
+  extern __shared__ double lam_s[];
+  __shared__ double red[4];
+  const int row = blockIdx.x;
+  const RowInfo ri = row_info(q.bt, row);
+  for (int k = threadIdx.x; k < y.K; k += 256) lam_s[k] = y.in[(int64_t)row * y.ldi + k];
+  __syncthreads();
+  double cst = 0.0, err = 0.0, sq = 0.0;
+  for (int j = threadIdx.x; j < y.N; j += 256) {
+    double a = 0.0;
+    for (int k = 0; k < y.K; ++k) a += lam_s[k] * (double)y.W[(int64_t)k * y.ldw + j];
+    if (y.conc) {
+      conc64(q, ri.p, j, a, cst, err, sq);
+    } else {
+      const int64_t pc = (int64_t)ri.p * q.bt.nd + y.layer_off + j;
+      const uint32_t rec = q.bt.status[(int64_t)ri.b * q.bt.nd + y.layer_off + j];
+      y.out[(int64_t)row * y.ldo + j] = relax64(q, ri, rec, pc, a, (double)y.bias[j], cst, err);
+    }
+  }
+  const double c = block_sum_d(cst, red), e = block_sum_d(err, red), s2 = block_sum_d(sq, red);
+  if (threadIdx.x == 0) {
+    q.part[(int64_t)y.slot * q.bt.n_rows + row] = c;
+    q.perr[(int64_t)y.slot * q.bt.n_rows + row] = e;
+    if (q.psq) q.psq[(int64_t)y.slot * q.bt.n_rows + row] = s2;
+  }
+}
+
+// The same for kDenseRows consecutive rows per workgroup (rpb, all of them
+// in LDS), so that each weight read serves every one of them, on large
+// batches; each row's sums keep the one-row order.
 constexpr int kDenseRows = 4;
-__global__ __launch_bounds__(256) void dense64_k(Pass64 q, Lay64 y, int rpb) {
+__global__ __launch_bounds__(256) void dense64_rows_k(Pass64 q, Lay64 y, int rpb) {
   extern __shared__ double lam_s[];
   __shared__ double red[4];
   const int row0 = blockIdx.x * rpb;
@@ -472,10 +499,14 @@ void launch_top64(const Pass64& q, const Top64& t, hipStream_t s) {
 
 void launch_dense64(const Pass64& q, const Lay64& y, hipStream_t s) {
   if (q.bt.n_rows <= 0) return;
-  // several rows per workgroup while they fit in 64 KB of LDS (K <= 8192 rows always do one)
-  const int rpb = std::max(1, std::min(kDenseRows, (int)(64 * 1024 / (std::max(y.K, 1) * sizeof(double)))));
-  launch_k(dense64_k, (unsigned)((q.bt.n_rows + rpb - 1) / rpb), 256, (uint32_t)(rpb * y.K * sizeof(double)), s, q, y,
-           rpb);
+  // several rows per workgroup on batches that still give 4096+ workgroups,
+  // while the rows fit in 64 KB of LDS; else one (K <= 8192 always fits)
+  const int rpb = std::min(kDenseRows, (int)(64 * 1024 / (std::max(y.K, 1) * sizeof(double))));
+  if (q.bt.n_rows >= 4096 * kDenseRows && rpb == kDenseRows)
+    launch_k(dense64_rows_k, (unsigned)((q.bt.n_rows + rpb - 1) / rpb), 256, (uint32_t)(rpb * y.K * sizeof(double)),
+             s, q, y, rpb);
+  else
+    launch_k(dense64_k, (unsigned)q.bt.n_rows, 256, (uint32_t)(y.K * sizeof(double)), s, q, y);
 }
 
 void launch_conv64(const Pass64& q, const Lay64& y, const ConvGeom& g, hipStream_t s) {
