@@ -19,6 +19,7 @@
 #include "common.h"
 #include "internal.h"
 
+#include <type_traits>
 #include <utility>
 
 namespace cvb {
@@ -104,22 +105,28 @@ __device__ __forceinline__ void epi64(const Pass64& q, const RowInfo& ri, const 
         }
       }
     }
+    // local copies, all three written back, so that neither branch updates
+    // its sum through memory
+    double c = cst, e = err, s2 = sq;
     if (q.bt.l2x0) {
 #pragma unroll
       for (int u = 0; u < kC; ++u) {
         if (j0 + 256 * u >= y.N) continue;
-        cst += a[u] * (double)x0[u];
-        sq += a[u] * a[u];
+        c += a[u] * (double)x0[u];
+        s2 += a[u] * a[u];
       }
     } else {
 #pragma unroll
       for (int u = 0; u < kC; ++u) {
         if (j0 + 256 * u >= y.N) continue;
         const double tm = fmin(a[u] * (double)x0[u], a[u] * (double)x1[u]);
-        cst += tm;
-        err += q.sg * fabs(tm);
+        c += tm;
+        e += q.sg * fabs(tm);
       }
     }
+    cst = c;
+    err = e;
+    sq = s2;
     return;
   }
   uint32_t rec[kC];
@@ -400,15 +407,60 @@ __device__ __forceinline__ void conv64_row_pos(const Pass64& q, const Lay64& y, 
   }
 }
 
+// The outputs of one row for a 3-channel input of 1024 positions (32x32):
+// N = 3072, so a thread's outputs j0 + 256 u (u < 12, one pass) sit at four
+// positions j0 + 256 g, each in all three channels (u = g + 4 c).  Each
+// Lambda value read from LDS serves the three channels of its position; wt
+// holds the weights as [co][ky][kx][3].  Each output's sum keeps the order of
+// tap_sum64, and the epilogue takes the outputs in ascending j as before.
+__device__ __forceinline__ void conv64_row_rgb(const Pass64& q, const Lay64& y, const ConvGeom& g,
+                                               const RowInfo& ri, int row, const double* lam_s, const float* wt,
+                                               double& cst, double& err, double& sq) {
+  constexpr int P = 4, C = 3, kC = P * C;
+  const int j0 = threadIdx.x;
+  double a[kC];
+#pragma unroll
+  for (int u = 0; u < kC; ++u) a[u] = 0.0;
+  // one position (a compile-time gi, so that a stays in registers)
+  auto position = [&](auto gic) {
+    constexpr int gi = decltype(gic)::value;
+    const int pos = j0 + 256 * gi;
+    const int iy = pos / g.wi, ix = pos - iy * g.wi;
+    const int ry = (iy + g.p) % g.s, rx = (ix + g.p) % g.s;
+    const int oy0 = (iy + g.p - ry) / g.s, ox0 = (ix + g.p - rx) / g.s;
+    for (int ky = ry, oy = oy0; ky < g.k && oy >= 0; ky += g.s, --oy) {
+      if (oy >= g.ho) continue;
+      for (int kx = rx, ox = ox0; kx < g.k && ox >= 0; kx += g.s, --ox) {
+        if (ox >= g.wo) continue;
+        const float* wp = wt + (ky * g.k + kx) * C;
+#pragma unroll 2
+        for (int co = 0; co < g.co; ++co) {
+          const double l = lam_s[(co * g.ho + oy) * g.wo + ox];
+          const float* w = wp + co * g.k * g.k * C;
+#pragma unroll
+          for (int c = 0; c < C; ++c) a[gi + P * c] += l * (double)w[c];
+        }
+      }
+    }
+  };
+  position(std::integral_constant<int, 0>{});
+  position(std::integral_constant<int, 1>{});
+  position(std::integral_constant<int, 2>{});
+  position(std::integral_constant<int, 3>{});
+  epi64<kC>(q, ri, y, row, j0, a, cst, err, sq);
+}
+
 // Back-substitution through conv layer i (transposed convolution): for input
 // position (ci, iy, ix), A(i-1) = sum over (co, ky, kx) with oy = (iy + pad -
 // ky) / stride and ox likewise whole and inside the output plane of
 // Lambda(i)[co, oy, ox] W[co, ci, ky, kx], in double.
 // The weights are staged in LDS after the row when they fit (w_lds: as
 // stored, or in the position-blocked layout of conv64_row_pos when the plane
-// size divides 256), else read from global memory; the same values and the
-// same order of every sum in all three cases.
-__global__ __launch_bounds__(256) void conv64_k(Pass64 q, Lay64 y, ConvGeom g, int w_lds) {
+// size divides 256, or of conv64_row_rgb for a 3x32x32 input), else read
+// from global memory; the same values and the same order of every sum in
+// every case.
+template <int w_lds>
+__global__ __launch_bounds__(256) void conv64_k(Pass64 q, Lay64 y, ConvGeom g) {
   extern __shared__ double lam_s[];
   __shared__ double red[4];
   const int row = blockIdx.x;
@@ -426,11 +478,12 @@ __global__ __launch_bounds__(256) void conv64_k(Pass64 q, Lay64 y, ConvGeom g, i
       if (k0 + 256 * u < y.K) lam_s[k0 + 256 * u] = v[u];
   }
   // w_lds: 1 the weights as stored, 2 the position-blocked layout of
-  // conv64_row_pos with dci = 256 / (hi wi) and cip channels, 0 global memory
-  const int dci = w_lds == 2 ? 256 / (g.hi * g.wi) : 0, cip = g.ci + dci * kC64;
-  if (w_lds == 1) {
+  // conv64_row_pos with dci = 256 / (hi wi) and cip channels, 3 that layout
+  // with cip = 3 for conv64_row_rgb, 0 global memory
+  const int dci = w_lds == 2 ? 256 / (g.hi * g.wi) : 0, cip = w_lds == 3 ? 3 : g.ci + dci * kC64;
+  if constexpr (w_lds == 1) {
     for (int t = threadIdx.x; t < g.co * g.ci * g.k * g.k; t += 256) w_s[t] = y.W[t];
-  } else if (w_lds == 2) {
+  } else if constexpr (w_lds >= 2) {
     for (int t = threadIdx.x; t < g.co * g.k * g.k * cip; t += 256) {
       const int c = t % cip, r = t / cip, kx = r % g.k, r2 = r / g.k, ky = r2 % g.k, co = r2 / g.k;
       w_s[t] = c < g.ci ? y.W[((co * g.ci + c) * g.k + ky) * g.k + kx] : 0.f;
@@ -438,12 +491,14 @@ __global__ __launch_bounds__(256) void conv64_k(Pass64 q, Lay64 y, ConvGeom g, i
   }
   __syncthreads();
   double cst = 0.0, err = 0.0, sq = 0.0;
-  if (w_lds == 2) {
+  if constexpr (w_lds == 3) {
+    conv64_row_rgb(q, y, g, ri, row, lam_s, w_s, cst, err, sq);
+  } else if constexpr (w_lds == 2) {
     if (dci == 1) conv64_row_pos<kC64, 1>(q, y, g, ri, row, lam_s, w_s, cip, cst, err, sq);
     else if (dci == 2) conv64_row_pos<kC64, 2>(q, y, g, ri, row, lam_s, w_s, cip, cst, err, sq);
     else if (dci == 4) conv64_row_pos<kC64, 4>(q, y, g, ri, row, lam_s, w_s, cip, cst, err, sq);
     else conv64_row_pos<kC64, 8>(q, y, g, ri, row, lam_s, w_s, cip, cst, err, sq);
-  } else if (w_lds == 1) {
+  } else if constexpr (w_lds == 1) {
     conv64_row<kC64>(q, y, g, ri, row, lam_s, w_s, cst, err, sq);
   } else {
     conv64_row<kC64>(q, y, g, ri, row, lam_s, y.W, cst, err, sq);
@@ -516,14 +571,21 @@ void launch_conv64(const Pass64& q, const Lay64& y, const ConvGeom& g, hipStream
   const size_t wt_b = (size_t)g.co * g.k * g.k * (g.ci + (hw > 0 ? 256 / hw : 0) * kC64) * sizeof(float);
   int w_lds = 0;
   size_t lds = row_b;
-  if (hw >= 32 && 256 % hw == 0 && y.N == g.ci * hw && row_b + wt_b <= 48 * 1024) {
+  if (hw == 1024 && g.ci == 3 && y.N == 3 * 1024 && row_b + w_b <= 48 * 1024) {
+    w_lds = 3;  // the [co][ky][kx][3] layout holds the same number of weights
+    lds += w_b;
+  } else if (hw >= 32 && 256 % hw == 0 && y.N == g.ci * hw && row_b + wt_b <= 48 * 1024) {
     w_lds = 2;
     lds += wt_b;
   } else if (row_b + w_b <= 48 * 1024) {
     w_lds = 1;
     lds += w_b;
   }
-  launch_k(conv64_k, (unsigned)q.bt.n_rows, 256, (uint32_t)lds, s, q, y, g, w_lds);
+  const unsigned nb = (unsigned)q.bt.n_rows;
+  if (w_lds == 3) launch_k(conv64_k<3>, nb, 256, (uint32_t)lds, s, q, y, g);
+  else if (w_lds == 2) launch_k(conv64_k<2>, nb, 256, (uint32_t)lds, s, q, y, g);
+  else if (w_lds == 1) launch_k(conv64_k<1>, nb, 256, (uint32_t)lds, s, q, y, g);
+  else launch_k(conv64_k<0>, nb, 256, (uint32_t)lds, s, q, y, g);
 }
 
 void launch_finalize64(const Pass64& q, const Fin64& f, hipStream_t s) {
